@@ -1,0 +1,217 @@
+/*
+ * lsmg — level-set multigrid for the sulfation model on MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  The method is that of Coco, Semplice and Serra
+ * Capizzano (arXiv 1902.07029): a Crank-Nicolson step (section 3.1) of the
+ * sulfation model (section 2, eq. maineq) on a uniform Cartesian grid masked by
+ * a level set (section 3.2), finite differences on inside nodes and ghost-point
+ * boundary rows (section 3.3), Newton-Raphson (section 3.4) whose linear systems
+ * are solved by a multigrid V-cycle (section 3.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns lsmg_status; 0 is success, negative values are
+ *   errors and lsmg_last_error() gives a thread-local message.  Nothing else
+ *   is reported through exceptions or aborts.
+ * - Pointers marked "device" are GPU global-memory addresses owned by the
+ *   caller (for example torch tensors' data_ptr()).  The library never frees
+ *   them and never keeps them beyond the call.  Pointers marked "host" are
+ *   ordinary CPU memory.
+ * - The library owns every internal buffer of a hierarchy and of a state.
+ * - All GPU work of a hierarchy is enqueued on the HIP stream given to
+ *   lsmg_build_hierarchy (NULL = the null stream).  Entry points that return
+ *   a scalar through a host pointer synchronise that stream before returning;
+ *   the others only enqueue.
+ * - Grids: dim = 2 or 3, n nodes per axis on the box [lo, hi]^dim, spacing
+ *   h = (hi - lo) / (n - 1) on every axis (Delta x = Delta y [= Delta z] as in
+ *   section 3.3).  Grid arrays are n^dim doubles, x fastest.
+ * - Compact vectors of level l: 2 * Na doubles, Na = Ni + Ng active nodes,
+ *   the s-block then the c-block (section 3.3, "all s variables before the c
+ *   ones"); active nodes are ordered as the inside nodes in lexicographic grid
+ *   order followed by the ghost nodes in lexicographic grid order (the map M of
+ *   eq. maprij).  Level 0 is the finest grid.
+ */
+#ifndef LSMG_H
+#define LSMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LSMG_OK = 0,
+    LSMG_EINVAL = -1,      /* bad argument, size or call order */
+    LSMG_EGEOM = -2,       /* geometry the method cannot discretise (see lsmg_build_hierarchy) */
+    LSMG_ENOCONV = -3,     /* Newton did not reach the tolerance in newton_max iterations */
+    LSMG_ENONFINITE = -4,  /* a NaN or infinity appeared in a residual, update or coarse factor */
+    LSMG_EOOM = -5,        /* device allocation failed */
+    LSMG_EHIP = -6,        /* a HIP runtime call failed */
+    LSMG_ENOTIMPL = -7
+} lsmg_status;
+
+typedef struct {
+    int dim;        /* 2 or 3 */
+    int n;          /* nodes per axis; (n - 1) = (coarsest_n - 1) * 2^k */
+    double lo, hi;  /* box [lo, hi]^dim */
+} lsmg_grid;
+
+typedef struct {
+    /* model, section 2 and eq. (dataeq): reaction rates a/m_c and a/m_s,
+     * diffusion d, porosity phi(c) = alpha c + beta */
+    double a, d, m_s, m_c, alpha, beta;
+    /* ghost-row relaxation parameter tau^s of eq. (RelGhost), 0 < tau_s < 1 (eq. CFLcond) */
+    double tau_s;
+    int nu1, nu2;          /* pre- and post-smoothing steps of the V-cycle */
+    int ghost_sweeps;      /* ghost relaxations per smoothing step (>= 1) */
+    int band_steps;        /* layers of the boundary-defect extension (section 3.5.2) */
+    int ghost_c_new;       /* 1: the ghost c-row relaxation uses the new delta s */
+    int coarsest_n;        /* nodes per axis of the coarsest grid (>= 3) */
+    int precision;         /* 0: FP64 V-cycle; 1: FP32 V-cycle inside FP64 iterative refinement */
+    double newton_tol;     /* stop when min(|F|_inf, |dW|_inf / |W|_inf) < newton_tol (section 3.4) */
+    int newton_max;
+    double lin_rtol;       /* linear solve stops when |J dW - F|_inf <= lin_rtol |F|_inf */
+    int cycles_max;        /* V-cycles per linear solve at most */
+} lsmg_params;
+
+typedef struct lsmg_hierarchy lsmg_hierarchy;
+typedef struct lsmg_state lsmg_state;
+
+typedef struct {
+    int newton_iters;   /* Newton iterations of the step */
+    int vcycles;        /* V-cycles executed (one per refinement step in mixed precision) */
+    double res_inf;     /* |F(W^{n+1})|_inf at exit */
+    double rho_last;    /* last convergence factor |r_q|_inf / |r_{q-1}|_inf (section 4.2) */
+    double rho_geo;     /* geometric mean of all convergence factors of the step */
+    double dw_rel;      /* last |dW|_inf / |W|_inf */
+} lsmg_step_stats;
+
+/* Default parameters: the model data of eq. (dataeq), tau_s = 0.9 (section
+ * 3.5.1), V(2,2), 5 ghost sweeps, 3 band layers, ghost_c_new = 1, coarsest 5,
+ * FP64, newton_tol 1e-10, newton_max 20, lin_rtol 1e-3, cycles_max 30. */
+void lsmg_default_params(lsmg_params *p);
+
+/* Build the grid hierarchy of one domain (sections 3.2-3.3, 3.5).
+ * d_levelset: device, n^dim doubles, the level set phi at the nodes (inside
+ *   where phi < 0, eq. ghostdef); read during the call only.
+ * Per level (phi injected to every coarser grid): node classification
+ * (inside / ghost / inactive), the compact ordering, ghost geometry (normal by
+ * central differences, eq. nij; upwind stencil ST; boundary point B by
+ * bisection; the biquadratic/triquadratic weights of eq. JssD with a lower-
+ * order fallback where ST reaches an inactive node) and the tables of the
+ * boundary-aware restriction.
+ * stream: a hipStream_t (NULL for the null stream); every later call of this
+ *   hierarchy runs on it.
+ * Errors: LSMG_EINVAL (bad grid or parameters), LSMG_EGEOM (an inside node on
+ *   the box edge, or a finest-level ghost whose boundary point falls outside
+ *   its stencil), LSMG_EOOM, LSMG_EHIP.  *out is NULL on error. */
+lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid,
+                                 const lsmg_params *params, void *stream, lsmg_hierarchy **out);
+void lsmg_destroy_hierarchy(lsmg_hierarchy *h);
+
+/* Replace the solver parameters (the model constants and the grid are fixed at build). */
+lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params);
+
+/* Number of levels (host out). */
+lsmg_status lsmg_num_levels(const lsmg_hierarchy *h, int *nlev);
+
+/* Level facts (host outs): nodes per axis, spacing, inside, ghost and
+ * boundary-band node counts. */
+lsmg_status lsmg_level_info(const lsmg_hierarchy *h, int level, int *n, double *hh,
+                            int *n_inside, int *n_ghost, int *n_band);
+
+/* Compact-to-grid map of a level: d_out device, Na int64 lexicographic grid indices. */
+lsmg_status lsmg_compact_to_grid(lsmg_hierarchy *h, int level, int64_t *d_out);
+
+/* Ghost table of a level (all device, Ng rows; nst = 3^dim):
+ * d_st: Ng*nst int32 compact indices of the stencil ST (k = (k_x, k_y[, k_z]) in
+ *   {0,1,2}^dim, x fastest, node G - h (m_x k_x, ...)), -1 where inactive;
+ * d_w: Ng*nst weights of the boundary row (eq. JssD); d_B: Ng*dim boundary
+ * points; d_normal: Ng*dim unit normals; d_order: Ng int32 (2 quadratic,
+ * 1 linear, 0 constant); d_bfallback: Ng int32 (1 when B came from the
+ * first-order projection instead of bisection).  Any pointer may be NULL. */
+lsmg_status lsmg_ghost_table(lsmg_hierarchy *h, int level, int32_t *d_st, double *d_w, double *d_B,
+                             double *d_normal, int32_t *d_order, int32_t *d_bfallback);
+
+/* ---- one Crank-Nicolson step ---------------------------------------------- */
+
+/* A state holds W = (s, c) on the finest active nodes (FP64, device). */
+lsmg_status lsmg_state_create(lsmg_hierarchy *h, lsmg_state **out);
+void lsmg_state_destroy(lsmg_state *st);
+/* d_W: device compact vector of level 0 (2 Na doubles). */
+lsmg_status lsmg_state_set(lsmg_state *st, const double *d_W);
+lsmg_status lsmg_state_get(const lsmg_state *st, double *d_W);
+/* Grid form: d_s, d_c device n^dim doubles; set reads active nodes only,
+ * get writes NaN at inactive nodes. */
+lsmg_status lsmg_state_set_grid(lsmg_state *st, const double *d_s, const double *d_c);
+lsmg_status lsmg_state_get_grid(const lsmg_state *st, double *d_s, double *d_c);
+
+/* Advance st from t_n to t_{n+1} = t_n + dt (sections 3.1, 3.3, 3.4): Newton on
+ * F(W) = 0 from W^{(n+1,0)} = W^n, each linear system J dW = F solved by
+ * V-cycles from dW = 0, W <- W - dW, stop when
+ * min(|F|_inf, |dW|_inf / |W|_inf) < newton_tol after at least one iteration.
+ * d_sb: device, Ng boundary values s_b(B_g, t_{n+1}) in ghost order, or NULL to
+ *   use sb_const for every ghost.
+ * d_fn, d_fnp1: device compact vectors [f1 | f2] of the source terms of
+ *   section 4.1 at t_n and t_{n+1}, or both NULL.
+ * stats: host, may be NULL.  Synchronises the stream.
+ * The state is replaced only on LSMG_OK; on LSMG_ENOCONV or LSMG_ENONFINITE it
+ * still holds W^n. */
+lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, const double *d_sb,
+                                double sb_const, const double *d_fn, const double *d_fnp1,
+                                lsmg_step_stats *stats);
+
+/* ---- components of the step, on compact device vectors -------------------- */
+
+/* Newton residual F(W) (eqs. FDs, FDc, and the boundary row s~(B) - s_b on
+ * ghosts) for the step from W^n = d_Wn with time step dt; d_F out; res_inf
+ * (host, may be NULL) receives |F|_inf and synchronises. */
+lsmg_status lsmg_residual(lsmg_hierarchy *h, const double *d_W, const double *d_Wn, double dt,
+                          const double *d_sb, double sb_const, const double *d_fn,
+                          const double *d_fnp1, double *d_F, double *res_inf);
+
+/* Fix the linearisation point of the Jacobian on every level: W on the
+ * finest level, injected to the coarser ones; builds and factors the coarsest
+ * operator.  Required before the calls below. */
+lsmg_status lsmg_set_linearization(lsmg_hierarchy *h, const double *d_W, double dt);
+
+/* Linearisation point of a level (compact, device out). */
+lsmg_status lsmg_level_state(lsmg_hierarchy *h, int level, double *d_W);
+
+/* y = J x on a level (section 3.4 Jacobian rows). */
+lsmg_status lsmg_apply_J(lsmg_hierarchy *h, int level, const double *d_x, double *d_y);
+
+/* nsweeps smoothing steps (section 3.5.1): red-black collective Gauss-Seidel
+ * on inside nodes, then ghost_sweeps ghost relaxations (eq. RelGhost). */
+lsmg_status lsmg_smooth(lsmg_hierarchy *h, int level, const double *d_rhs, double *d_x, int nsweeps);
+
+/* Defect r = rhs - J x (section 3.5.2); res_inf as in lsmg_residual. */
+lsmg_status lsmg_defect(lsmg_hierarchy *h, int level, const double *d_rhs, const double *d_x,
+                        double *d_r, double *res_inf);
+
+/* Boundary-aware restriction of a defect of level `level` to the right-hand
+ * side of level+1 (section 3.5.2, Fig. Neigh, with the ghost-defect band
+ * extension). */
+lsmg_status lsmg_restrict(lsmg_hierarchy *h, int level, const double *d_r, double *d_rhs_coarse);
+
+/* x += bilinear/trilinear prolongation of the coarse correction of level+1
+ * (section 3.5.3). */
+lsmg_status lsmg_prolong_add(lsmg_hierarchy *h, int level, const double *d_e_coarse, double *d_x);
+
+/* Direct solve on the coarsest level (dense LU with partial pivoting, FP64). */
+lsmg_status lsmg_coarse_solve(lsmg_hierarchy *h, const double *d_rhs, double *d_x);
+
+/* One V(nu1, nu2) cycle on `level` with initial guess d_x (in/out);
+ * res_inf (host, may be NULL) receives |rhs - J x|_inf after the cycle. */
+lsmg_status lsmg_vcycle(lsmg_hierarchy *h, int level, const double *d_rhs, double *d_x, double *res_inf);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char *lsmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSMG_H */

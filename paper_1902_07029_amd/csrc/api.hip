@@ -1,0 +1,1037 @@
+// C ABI of the lsmg library: hierarchy construction, the Newton / Crank-Nicolson
+// driver (section 3.4), the V-cycle driver (section 3.5) and the component entry
+// points used by the parity tests.  All device work is enqueued on the
+// hierarchy's stream; host decisions (cycle and Newton stopping) read max-norms
+// back through pinned memory.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lsmg.h"
+#include "lsmg_dev.hpp"
+#include "lsmg_host.hpp"
+
+using namespace lsmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+lsmg_status fail(lsmg_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(x)                                                                                      \
+    do {                                                                                               \
+        hipError_t e_ = (x);                                                                           \
+        if (e_ != hipSuccess) return fail(LSMG_EHIP, "%s failed: %s", #x, hipGetErrorString(e_));      \
+    } while (0)
+
+#define LSMGCHK(x)                        \
+    do {                                  \
+        lsmg_status s_ = (x);             \
+        if (s_ != LSMG_OK) return s_;     \
+    } while (0)
+
+struct Level {
+    int n = 0, Wp = 0;
+    long long rows = 0, cs = 0, ssize = 0;
+    double h = 0.0;
+    int ni = 0, ng = 0, na = 0, nb = 0, bmax = 0;
+    uint8_t *type = nullptr, *ext = nullptr;
+    int *cmap = nullptr, *c2s = nullptr;
+    int64_t *c2g = nullptr;
+    double *s = nullptr, *c = nullptr, *rhs_s = nullptr, *rhs_c = nullptr, *x_s = nullptr, *x_c = nullptr,
+           *r_s = nullptr, *r_c = nullptr;
+    int *g_idx = nullptr, *g_st = nullptr, *g_stc = nullptr, *g_order = nullptr, *g_bfall = nullptr;
+    double *g_w = nullptr, *g_B = nullptr, *g_nrm = nullptr, *g_tmp = nullptr, *g_old = nullptr;
+    int *b_idx = nullptr, *b_cnt = nullptr, *b_src = nullptr;
+    double *b_wt = nullptr;
+    float *s32 = nullptr, *c32 = nullptr, *rhs_s32 = nullptr, *rhs_c32 = nullptr, *x_s32 = nullptr, *x_c32 = nullptr,
+          *r_s32 = nullptr, *r_c32 = nullptr, *g_w32 = nullptr, *g_tmp32 = nullptr, *g_old32 = nullptr,
+          *b_wt32 = nullptr;
+    int4 *items = nullptr;              // [seg colour 0 | seg colour 1 | ghost chunks | band chunks]
+    int nseg[2] = {0, 0}, nghc = 0, nbandc = 0;
+    const int4 *w_seg(int colour) const { return items + (colour ? nseg[0] : 0); }
+    const int4 *w_act() const { return items; }
+    int nw_act() const { return nseg[0] + nseg[1] + nghc; }
+    const int4 *w_gh() const { return items + nseg[0] + nseg[1]; }
+    const int4 *w_band() const { return items + nseg[0] + nseg[1] + nghc; }
+};
+
+}  // namespace
+
+struct lsmg_hierarchy {
+    int dim = 2, nst = 9, nlev = 0;
+    double lo = -1.0, hi = 1.0;
+    lsmg_params p{};
+    hipStream_t stream = nullptr;
+    std::vector<Level> L;
+    std::vector<LevelDesc<double>> hd64;
+    std::vector<LevelDesc<float>> hd32;
+    LevelDesc<double> *d64 = nullptr;
+    LevelDesc<float> *d32 = nullptr;
+    bool have32 = false;
+    double dt = 0.0;
+    bool lin_set = false;
+    double *bs = nullptr, *bc = nullptr, *tmp_s = nullptr, *tmp_c = nullptr;
+    double *lu = nullptr;
+    int *piv = nullptr, *lu_status = nullptr;
+    int luN = 0;
+    unsigned long long *d_norms = nullptr, *h_norms = nullptr;
+    int *h_status = nullptr;
+    std::vector<void *> allocs;
+    ~lsmg_hierarchy()
+    {
+        for (void *p : allocs) (void)hipFree(p);
+        if (h_norms) (void)hipHostFree(h_norms);
+        if (h_status) (void)hipHostFree(h_status);
+    }
+    template <typename T>
+    lsmg_status alloc(T **ptr, long long count)
+    {
+        *ptr = nullptr;
+        if (count <= 0) count = 1;
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess)
+            return fail(LSMG_EOOM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
+        allocs.push_back(p);
+        *ptr = (T *)p;
+        return LSMG_OK;
+    }
+    template <typename T>
+    lsmg_status zalloc(T **ptr, long long count)
+    {
+        LSMGCHK(alloc(ptr, count));
+        HIPCHK(hipMemsetAsync(*ptr, 0, sizeof(T) * (size_t)(count > 0 ? count : 1), stream));
+        return LSMG_OK;
+    }
+};
+
+struct lsmg_state {
+    lsmg_hierarchy *h = nullptr;
+    double *s = nullptr, *c = nullptr;
+    ~lsmg_state()
+    {
+        (void)hipFree(s);
+        (void)hipFree(c);
+    }
+};
+
+namespace {
+
+int ipow(int b, int e)
+{
+    int r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+lsmg_status check_params(const lsmg_params *p)
+{
+    if (!p) return fail(LSMG_EINVAL, "params is NULL");
+    if (!(p->tau_s > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->ghost_sweeps < 1 || p->band_steps < 0 ||
+        p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
+        !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1))
+        return fail(LSMG_EINVAL, "invalid solver parameters");
+    return LSMG_OK;
+}
+
+void fill_desc_scalars(lsmg_hierarchy *H)
+{
+    const lsmg_params &p = H->p;
+    for (int l = 0; l < H->nlev; ++l) {
+        const Level &Lv = H->L[l];
+        LevelDesc<double> &D = H->hd64[l];
+        D.kap = p.d / (4.0 * Lv.h * Lv.h);
+        D.d_half_h2 = p.d / (2.0 * Lv.h * Lv.h);
+        D.alpha = p.alpha;
+        D.beta = p.beta;
+        D.dt_inv = H->dt > 0.0 ? 1.0 / H->dt : 0.0;
+        D.ks_half = 0.5 * (p.a / p.m_c);
+        D.kc_half = 0.5 * (p.a / p.m_s);
+        D.tau_s = p.tau_s;
+        D.ghost_c_new = p.ghost_c_new;
+        if (H->have32) {
+            LevelDesc<float> &E = H->hd32[l];
+            E.kap = (float)D.kap;
+            E.d_half_h2 = (float)D.d_half_h2;
+            E.alpha = (float)D.alpha;
+            E.beta = (float)D.beta;
+            E.dt_inv = (float)D.dt_inv;
+            E.ks_half = (float)D.ks_half;
+            E.kc_half = (float)D.kc_half;
+            E.tau_s = (float)D.tau_s;
+            E.ghost_c_new = D.ghost_c_new;
+        }
+    }
+}
+
+lsmg_status push_desc(lsmg_hierarchy *H)
+{
+    fill_desc_scalars(H);
+    HIPCHK(hipMemcpyAsync(H->d64, H->hd64.data(), sizeof(LevelDesc<double>) * H->nlev, hipMemcpyHostToDevice,
+                          H->stream));
+    if (H->have32)
+        HIPCHK(hipMemcpyAsync(H->d32, H->hd32.data(), sizeof(LevelDesc<float>) * H->nlev, hipMemcpyHostToDevice,
+                              H->stream));
+    // the host copies must stay unchanged until the copies ran
+    HIPCHK(hipStreamSynchronize(H->stream));
+    return LSMG_OK;
+}
+
+lsmg_status set_dt(lsmg_hierarchy *H, double dt)
+{
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LSMG_EINVAL, "dt must be positive and finite");
+    if (dt != H->dt) {
+        H->dt = dt;
+        LSMGCHK(push_desc(H));
+    }
+    return LSMG_OK;
+}
+
+lsmg_status read_norms(lsmg_hierarchy *H, int count)
+{
+    HIPCHK(hipMemcpyAsync(H->h_norms, H->d_norms, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost,
+                          H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    return LSMG_OK;
+}
+
+double norm_value(const lsmg_hierarchy *H, int slot)
+{
+    double v;
+    std::memcpy(&v, &H->h_norms[slot], sizeof(double));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+template <typename T>
+const LevelDesc<T> *descs(const lsmg_hierarchy *H);
+template <>
+const LevelDesc<double> *descs<double>(const lsmg_hierarchy *H) { return H->d64; }
+template <>
+const LevelDesc<float> *descs<float>(const lsmg_hierarchy *H) { return H->d32; }
+
+template <typename T>
+void smooth_level(lsmg_hierarchy *H, int l)
+{
+    const Level &Lv = H->L[l];
+    const LevelDesc<T> *d = descs<T>(H);
+    launch_smooth_colour<T>(H->dim, d, Lv.w_seg(0), Lv.nseg[0], 0, H->stream);
+    launch_smooth_colour<T>(H->dim, d, Lv.w_seg(1), Lv.nseg[1], 1, H->stream);
+    for (int g = 0; g < H->p.ghost_sweeps; ++g) launch_ghost<T>(H->dim, d, Lv.w_gh(), Lv.nghc, H->stream);
+}
+
+template <typename T>
+void vcycle_rec(lsmg_hierarchy *H, int l)
+{
+    const Level &Lv = H->L[l];
+    const LevelDesc<T> *d = descs<T>(H);
+    if (l == H->nlev - 1) {
+        launch_coarse_solve<T>(d, l, 2 * Lv.na, Lv.c2s, H->lu, H->piv, H->stream);
+        return;
+    }
+    for (int i = 0; i < H->p.nu1; ++i) smooth_level<T>(H, l);
+    launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), nullptr, H->stream);
+    launch_band<T>(d, Lv.w_band(), Lv.nbandc, H->stream);
+    const Level &C = H->L[l + 1];
+    launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), H->stream);
+    vcycle_rec<T>(H, l + 1);
+    launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), H->stream);
+    for (int i = 0; i < H->p.nu2; ++i) smooth_level<T>(H, l);
+}
+
+// linearisation on every level from level 0's (s, c); factors the coarsest operator
+lsmg_status linearize(lsmg_hierarchy *H)
+{
+    for (int l = 1; l < H->nlev; ++l) {
+        const Level &C = H->L[l];
+        launch_inject<double>(H->dim, H->d64, C.w_act(), C.nw_act(), H->stream);
+    }
+    if (H->have32)
+        for (int l = 0; l < H->nlev; ++l) {
+            const Level &Lv = H->L[l];
+            launch_to_f32(H->dim, H->d64, H->d32, Lv.w_act(), Lv.nw_act(), 0, H->stream);
+        }
+    const Level &Lc = H->L[H->nlev - 1];
+    launch_coarse_factor(H->dim, H->d64, H->nlev - 1, Lc.c2s, H->lu, H->piv, H->lu_status, H->stream);
+    H->lin_set = true;
+    return LSMG_OK;
+}
+
+lsmg_status check_factor(lsmg_hierarchy *H)
+{
+    HIPCHK(hipMemcpyAsync(H->h_status, H->lu_status, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    if (*H->h_status != 0) return fail(LSMG_ENONFINITE, "coarsest operator is singular or not finite");
+    return LSMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy construction
+// ---------------------------------------------------------------------------
+lsmg_status build_level_arrays(lsmg_hierarchy *H, int l, const double *phi, uint8_t *fin, uint8_t *fgh,
+                               int64_t *scratch, int nscratch, int *err)
+{
+    Level &Lv = H->L[l];
+    const int dim = H->dim;
+    const long long nn = (long long)Lv.n * Lv.n * (dim == 3 ? Lv.n : 1);
+    LSMGCHK(H->zalloc(&Lv.type, Lv.ssize));
+    LSMGCHK(H->zalloc(&Lv.ext, Lv.ssize));
+    LSMGCHK(H->alloc(&Lv.cmap, Lv.ssize));
+    launch_fill<int>(Lv.cmap, Lv.ssize, -1, H->stream);
+    launch_classify(dim, phi, Lv.n, Lv.Wp, Lv.cs, Lv.type, fin, fgh, err, H->stream);
+    const int ni = compact_flags(fin, nn, nullptr, scratch, nscratch, H->stream);
+    const int ng = compact_flags(fgh, nn, nullptr, scratch, nscratch, H->stream);
+    if (ni < 0 || ng < 0) return fail(LSMG_EHIP, "compaction failed on level %d", l);
+    Lv.ni = ni;
+    Lv.ng = ng;
+    Lv.na = ni + ng;
+    LSMGCHK(H->alloc(&Lv.c2g, Lv.na));
+    LSMGCHK(H->alloc(&Lv.c2s, Lv.na));
+    if (ni > 0) compact_flags(fin, nn, Lv.c2g, scratch, nscratch, H->stream);
+    if (ng > 0) compact_flags(fgh, nn, Lv.c2g + ni, scratch, nscratch, H->stream);
+    launch_c2s(dim, Lv.c2g, Lv.na, Lv.n, Lv.Wp, Lv.cs, Lv.c2s, Lv.cmap, H->stream);
+    // ghost geometry
+    const int nst = H->nst;
+    LSMGCHK(H->alloc(&Lv.g_idx, ng));
+    LSMGCHK(H->alloc(&Lv.g_st, (long long)ng * nst));
+    LSMGCHK(H->alloc(&Lv.g_stc, (long long)ng * nst));
+    LSMGCHK(H->alloc(&Lv.g_w, (long long)ng * nst));
+    LSMGCHK(H->alloc(&Lv.g_B, (long long)ng * dim));
+    LSMGCHK(H->alloc(&Lv.g_nrm, (long long)ng * dim));
+    LSMGCHK(H->alloc(&Lv.g_order, ng));
+    LSMGCHK(H->alloc(&Lv.g_bfall, ng));
+    LSMGCHK(H->zalloc(&Lv.g_tmp, ng));
+    LSMGCHK(H->zalloc(&Lv.g_old, ng));
+    launch_ghost_geometry(dim, l, phi, Lv.type, Lv.c2g + ni, Lv.cmap, ng, Lv.n, Lv.Wp, Lv.cs, H->lo, Lv.h, Lv.g_idx,
+                          Lv.g_st, Lv.g_stc, Lv.g_w, Lv.g_B, Lv.g_nrm, Lv.g_order, Lv.g_bfall, err, H->stream);
+    launch_ghost_ext(ng, Lv.g_idx, Lv.ext, H->stream);
+    // vectors
+    LSMGCHK(H->zalloc(&Lv.s, Lv.ssize));
+    LSMGCHK(H->zalloc(&Lv.c, Lv.ssize));
+    LSMGCHK(H->zalloc(&Lv.rhs_s, Lv.ssize));
+    LSMGCHK(H->zalloc(&Lv.rhs_c, Lv.ssize));
+    LSMGCHK(H->zalloc(&Lv.x_s, Lv.ssize));
+    LSMGCHK(H->zalloc(&Lv.x_c, Lv.ssize));
+    LSMGCHK(H->zalloc(&Lv.r_s, Lv.ssize));
+    LSMGCHK(H->zalloc(&Lv.r_c, Lv.ssize));
+    return LSMG_OK;
+}
+
+lsmg_status build_band(lsmg_hierarchy *H, int l, const double *phi, uint8_t *flag, int64_t *scratch, int nscratch)
+{
+    Level &F = H->L[l];
+    const Level &C = H->L[l + 1];
+    const int dim = H->dim;
+    const long long nn = (long long)F.n * F.n * (dim == 3 ? F.n : 1);
+    HIPCHK(hipMemsetAsync(flag, 0, (size_t)nn, H->stream));
+    launch_band_mark(dim, C.c2g + C.ni, C.ng, C.n, F.type, F.n, F.Wp, F.cs, flag, H->stream);
+    const int nb = compact_flags(flag, nn, nullptr, scratch, nscratch, H->stream);
+    if (nb < 0) return fail(LSMG_EHIP, "band compaction failed on level %d", l);
+    F.nb = nb;
+    F.bmax = ipow(dim, H->p.band_steps);
+    if (nb == 0) return LSMG_OK;
+    int64_t *band = nullptr;
+    int *bandid = nullptr, *up_s = nullptr, *up_b = nullptr, *blayer = nullptr;
+    double *up_w = nullptr;
+    HIPCHK(hipMalloc(&band, sizeof(int64_t) * nb));
+    HIPCHK(hipMalloc(&bandid, sizeof(int) * nn));
+    HIPCHK(hipMalloc(&up_s, sizeof(int) * nb * dim));
+    HIPCHK(hipMalloc(&up_b, sizeof(int) * nb * dim));
+    HIPCHK(hipMalloc(&up_w, sizeof(double) * nb * dim));
+    HIPCHK(hipMalloc(&blayer, sizeof(int) * nb));
+    compact_flags(flag, nn, band, scratch, nscratch, H->stream);
+    launch_fill<int>(bandid, nn, -1, H->stream);
+    launch_fill_bandid(band, nb, bandid, H->stream);
+    LSMGCHK(H->alloc(&F.b_idx, nb));
+    LSMGCHK(H->zalloc(&F.b_cnt, nb));
+    LSMGCHK(H->zalloc(&F.b_src, (long long)nb * (F.bmax > 0 ? F.bmax : 1)));
+    LSMGCHK(H->zalloc(&F.b_wt, (long long)nb * (F.bmax > 0 ? F.bmax : 1)));
+    HIPCHK(hipMemsetAsync(blayer, 0, sizeof(int) * nb, H->stream));
+    launch_band_geometry(dim, phi, band, nb, F.type, bandid, F.n, F.Wp, F.cs, F.h, up_s, up_b, up_w, F.b_idx,
+                         H->stream);
+    for (int layer = 1; layer <= H->p.band_steps; ++layer)
+        launch_band_layer(dim, layer, nb, F.bmax, up_s, up_b, up_w, blayer, F.b_cnt, F.b_src, F.b_wt, H->stream);
+    launch_band_ext(nb, F.b_idx, blayer, F.ext, H->stream);
+    HIPCHK(hipStreamSynchronize(H->stream));
+    (void)hipFree(band);
+    (void)hipFree(bandid);
+    (void)hipFree(up_s);
+    (void)hipFree(up_b);
+    (void)hipFree(up_w);
+    (void)hipFree(blayer);
+    return LSMG_OK;
+}
+
+lsmg_status build_items(lsmg_hierarchy *H, int l)
+{
+    Level &Lv = H->L[l];
+    int4 *seg[2] = {nullptr, nullptr};
+    int cnt[2] = {0, 0};
+    build_segments(H->dim, Lv.type, Lv.n, Lv.Wp, Lv.rows, Lv.cs, l, seg, cnt, H->stream);
+    if (Lv.ni > 0 && cnt[0] + cnt[1] == 0) return fail(LSMG_EHIP, "segment construction failed on level %d", l);
+    Lv.nseg[0] = cnt[0];
+    Lv.nseg[1] = cnt[1];
+    Lv.nghc = (Lv.ng + kWave - 1) / kWave;
+    Lv.nbandc = (Lv.nb + kWave - 1) / kWave;
+    const int total = cnt[0] + cnt[1] + Lv.nghc + Lv.nbandc;
+    LSMGCHK(H->alloc(&Lv.items, total));
+    if (cnt[0] + cnt[1] > 0)
+        HIPCHK(hipMemcpyAsync(Lv.items, seg[0], sizeof(int4) * (cnt[0] + cnt[1]), hipMemcpyDeviceToDevice, H->stream));
+    std::vector<int4> hv;
+    for (int c = 0; c < Lv.nghc; ++c) {
+        const int e = (c + 1) * kWave < Lv.ng ? (c + 1) * kWave : Lv.ng;
+        hv.push_back(make_int4((l << 2) | 2, 0, c * kWave, e));
+    }
+    for (int c = 0; c < Lv.nbandc; ++c) {
+        const int e = (c + 1) * kWave < Lv.nb ? (c + 1) * kWave : Lv.nb;
+        hv.push_back(make_int4((l << 2) | 3, 0, c * kWave, e));
+    }
+    if (!hv.empty())
+        HIPCHK(hipMemcpyAsync(Lv.items + cnt[0] + cnt[1], hv.data(), sizeof(int4) * hv.size(), hipMemcpyHostToDevice,
+                              H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    if (seg[0]) (void)hipFree(seg[0]);
+    return LSMG_OK;
+}
+
+lsmg_status build_f32(lsmg_hierarchy *H)
+{
+    for (int l = 0; l < H->nlev; ++l) {
+        Level &Lv = H->L[l];
+        LSMGCHK(H->zalloc(&Lv.s32, Lv.ssize));
+        LSMGCHK(H->zalloc(&Lv.c32, Lv.ssize));
+        LSMGCHK(H->zalloc(&Lv.rhs_s32, Lv.ssize));
+        LSMGCHK(H->zalloc(&Lv.rhs_c32, Lv.ssize));
+        LSMGCHK(H->zalloc(&Lv.x_s32, Lv.ssize));
+        LSMGCHK(H->zalloc(&Lv.x_c32, Lv.ssize));
+        LSMGCHK(H->zalloc(&Lv.r_s32, Lv.ssize));
+        LSMGCHK(H->zalloc(&Lv.r_c32, Lv.ssize));
+        LSMGCHK(H->alloc(&Lv.g_w32, (long long)Lv.ng * H->nst));
+        LSMGCHK(H->zalloc(&Lv.g_tmp32, Lv.ng));
+        LSMGCHK(H->zalloc(&Lv.g_old32, Lv.ng));
+        launch_convert<float, double>(Lv.g_w32, Lv.g_w, (long long)Lv.ng * H->nst, H->stream);
+        LSMGCHK(H->zalloc(&Lv.b_wt32, (long long)Lv.nb * (Lv.bmax > 0 ? Lv.bmax : 1)));
+        if (Lv.nb > 0) launch_convert<float, double>(Lv.b_wt32, Lv.b_wt, (long long)Lv.nb * Lv.bmax, H->stream);
+    }
+    H->have32 = true;
+    return LSMG_OK;
+}
+
+void make_descs(lsmg_hierarchy *H)
+{
+    H->hd64.assign(H->nlev, LevelDesc<double>{});
+    H->hd32.assign(H->nlev, LevelDesc<float>{});
+    for (int l = 0; l < H->nlev; ++l) {
+        const Level &Lv = H->L[l];
+        LevelDesc<double> &D = H->hd64[l];
+        D.dim = H->dim; D.n = Lv.n; D.Wp = Lv.Wp; D.nst = H->nst;
+        D.ni = Lv.ni; D.ng = Lv.ng; D.na = Lv.na; D.nb = Lv.nb; D.bmax = Lv.bmax; D.level = l;
+        D.rows = Lv.rows; D.cs = Lv.cs; D.lo = H->lo; D.h = Lv.h;
+        D.type = Lv.type; D.ext = Lv.ext; D.cmap = Lv.cmap;
+        D.s = Lv.s; D.c = Lv.c; D.rhs_s = Lv.rhs_s; D.rhs_c = Lv.rhs_c; D.x_s = Lv.x_s; D.x_c = Lv.x_c;
+        D.r_s = Lv.r_s; D.r_c = Lv.r_c;
+        D.g_idx = Lv.g_idx; D.g_st = Lv.g_st; D.g_w = Lv.g_w; D.g_tmp = Lv.g_tmp; D.g_old = Lv.g_old;
+        D.b_idx = Lv.b_idx; D.b_cnt = Lv.b_cnt; D.b_src = Lv.b_src; D.b_wt = Lv.b_wt;
+        LevelDesc<float> &E = H->hd32[l];
+        E.dim = D.dim; E.n = D.n; E.Wp = D.Wp; E.nst = D.nst;
+        E.ni = D.ni; E.ng = D.ng; E.na = D.na; E.nb = D.nb; E.bmax = D.bmax; E.level = l;
+        E.rows = D.rows; E.cs = D.cs; E.lo = D.lo; E.h = D.h;
+        E.type = D.type; E.ext = D.ext; E.cmap = D.cmap;
+        E.s = Lv.s32; E.c = Lv.c32; E.rhs_s = Lv.rhs_s32; E.rhs_c = Lv.rhs_c32; E.x_s = Lv.x_s32; E.x_c = Lv.x_c32;
+        E.r_s = Lv.r_s32; E.r_c = Lv.r_c32;
+        E.g_idx = D.g_idx; E.g_st = D.g_st; E.g_w = Lv.g_w32; E.g_tmp = Lv.g_tmp32; E.g_old = Lv.g_old32;
+        E.b_idx = D.b_idx; E.b_cnt = D.b_cnt; E.b_src = D.b_src; E.b_wt = Lv.b_wt32;
+    }
+}
+
+lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
+{
+    const int dim = g->dim;
+    H->dim = dim;
+    H->nst = dim == 2 ? 9 : 27;
+    H->lo = g->lo;
+    H->hi = g->hi;
+    int nlev = 1, nl = g->n;
+    while (nl > H->p.coarsest_n) {
+        if ((nl - 1) % 2) return fail(LSMG_EINVAL, "n - 1 must be (coarsest_n - 1) * 2^k");
+        nl = (nl - 1) / 2 + 1;
+        ++nlev;
+        if (nlev > 16) return fail(LSMG_EINVAL, "too many levels");
+    }
+    if (nl != H->p.coarsest_n) return fail(LSMG_EINVAL, "n - 1 must be (coarsest_n - 1) * 2^k");
+    H->nlev = nlev;
+    H->L.assign(nlev, Level{});
+    nl = g->n;
+    for (int l = 0; l < nlev; ++l) {
+        Level &Lv = H->L[l];
+        Lv.n = nl;
+        Lv.h = (g->hi - g->lo) / (nl - 1);
+        Lv.Wp = ((nl + 1) / 2 + 15) / 16 * 16;
+        Lv.rows = dim == 2 ? nl : (long long)nl * nl;
+        Lv.cs = Lv.rows * Lv.Wp;
+        Lv.ssize = 2 * Lv.cs;
+        if (Lv.ssize > 0x7fffffffLL) return fail(LSMG_EINVAL, "grid too large for 32-bit storage indices");
+        nl = (nl - 1) / 2 + 1;
+    }
+    const long long nn0 = (long long)g->n * g->n * (dim == 3 ? g->n : 1);
+    // temporaries
+    std::vector<double *> phis(nlev, nullptr);
+    uint8_t *fin = nullptr, *fgh = nullptr;
+    int64_t *scratch = nullptr;
+    int *err = nullptr;
+    const long long nscr = compact_scratch_size(nn0) + 1;
+    lsmg_status st = LSMG_OK;
+    auto cleanup = [&]() {
+        for (double *p : phis) (void)hipFree(p);
+        (void)hipFree(fin);
+        (void)hipFree(fgh);
+        (void)hipFree(scratch);
+        (void)hipFree(err);
+    };
+    if (hipMalloc(&fin, nn0) != hipSuccess || hipMalloc(&fgh, nn0) != hipSuccess ||
+        hipMalloc(&scratch, sizeof(int64_t) * nscr) != hipSuccess || hipMalloc(&err, sizeof(int)) != hipSuccess) {
+        cleanup();
+        return fail(LSMG_EOOM, "build temporaries");
+    }
+    (void)hipMemsetAsync(err, 0, sizeof(int), H->stream);
+    for (int l = 0; l < nlev && st == LSMG_OK; ++l) {
+        const Level &Lv = H->L[l];
+        const long long nn = (long long)Lv.n * Lv.n * (dim == 3 ? Lv.n : 1);
+        if (hipMalloc(&phis[l], sizeof(double) * nn) != hipSuccess) {
+            st = fail(LSMG_EOOM, "level-set copy");
+            break;
+        }
+        if (l == 0)
+            (void)hipMemcpyAsync(phis[0], d_phi, sizeof(double) * nn, hipMemcpyDeviceToDevice, H->stream);
+        else
+            launch_inject_phi(dim, phis[l - 1], H->L[l - 1].n, phis[l], Lv.n, H->stream);
+        st = build_level_arrays(H, l, phis[l], fin, fgh, scratch, (int)nscr, err);
+    }
+    for (int l = 0; l + 1 < nlev && st == LSMG_OK; ++l) st = build_band(H, l, phis[l], fin, scratch, (int)nscr);
+    int herr = 0;
+    if (st == LSMG_OK) {
+        (void)hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, H->stream);
+        if (hipStreamSynchronize(H->stream) != hipSuccess) st = fail(LSMG_EHIP, "build synchronisation failed");
+    }
+    cleanup();
+    if (st != LSMG_OK) return st;
+    if (herr & 1) return fail(LSMG_EGEOM, "an inside node lies on the box edge");
+    if (herr & 2) return fail(LSMG_EGEOM, "a finest-level ghost's boundary point lies outside its stencil");
+    for (int l = 0; l < nlev; ++l) LSMGCHK(build_items(H, l));
+    // Newton work arrays, coarsest LU, norms
+    const Level &L0 = H->L[0];
+    LSMGCHK(H->zalloc(&H->bs, L0.ssize));
+    LSMGCHK(H->zalloc(&H->bc, L0.ssize));
+    LSMGCHK(H->zalloc(&H->tmp_s, L0.ssize));
+    LSMGCHK(H->zalloc(&H->tmp_c, L0.ssize));
+    H->luN = 2 * H->L[nlev - 1].na;
+    LSMGCHK(H->alloc(&H->lu, (long long)H->luN * H->luN));
+    LSMGCHK(H->alloc(&H->piv, H->luN));
+    LSMGCHK(H->zalloc(&H->lu_status, 1));
+    LSMGCHK(H->zalloc(&H->d_norms, 16));
+    HIPCHK(hipHostMalloc(&H->h_norms, sizeof(unsigned long long) * 16, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&H->h_status, sizeof(int), hipHostMallocDefault));
+    if (H->p.precision == 1) LSMGCHK(build_f32(H));
+    LSMGCHK(H->alloc(&H->d64, nlev));
+    LSMGCHK(H->alloc(&H->d32, nlev));
+    make_descs(H);
+    LSMGCHK(push_desc(H));
+    return LSMG_OK;
+}
+
+lsmg_status level_ok(const lsmg_hierarchy *H, int level)
+{
+    if (!H) return fail(LSMG_EINVAL, "hierarchy is NULL");
+    if (level < 0 || level >= H->nlev) return fail(LSMG_EINVAL, "level %d out of range", level);
+    return LSMG_OK;
+}
+
+// compact (device) -> split arrays of a level
+template <typename T>
+void scatter(lsmg_hierarchy *H, int l, const double *v, T *a, T *b)
+{
+    const Level &Lv = H->L[l];
+    launch_scatter_compact<T>(Lv.c2s, Lv.na, v, a, b, H->stream);
+}
+
+template <typename T>
+void gather(lsmg_hierarchy *H, int l, const T *a, const T *b, double *v)
+{
+    const Level &Lv = H->L[l];
+    launch_gather_compact<T>(Lv.c2s, Lv.na, a, b, v, H->stream);
+}
+
+void zero_active_x(lsmg_hierarchy *H, int l)
+{
+    const Level &Lv = H->L[l];
+    launch_fill<double>(Lv.x_s, Lv.ssize, 0.0, H->stream);
+    launch_fill<double>(Lv.x_c, Lv.ssize, 0.0, H->stream);
+}
+
+// linear solve J dW = F on level 0 (rhs already in rhs_s / rhs_c) by V-cycles from zero;
+// nF = |F|_inf.  Returns cycles run; rho statistics accumulate into the outs.
+lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_last, double *logsum, int *nrho)
+{
+    const Level &L0 = H->L[0];
+    zero_active_x(H, 0);
+    double rprev = nF;
+    const bool mixed = H->p.precision == 1;
+    if (mixed) {
+        // r = F - J 0 in FP64
+        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), nullptr, H->stream);
+    }
+    for (int q = 0; q < H->p.cycles_max; ++q) {
+        if (rprev <= H->p.lin_rtol * nF) break;
+        launch_zero_u64(H->d_norms + 1, 1, H->stream);
+        if (!mixed) {
+            vcycle_rec<double>(H, 0);
+        } else {
+            launch_to_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), 1, H->stream);
+            vcycle_rec<float>(H, 0);
+            launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), H->stream);
+        }
+        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), H->d_norms + 1, H->stream);
+        LSMGCHK(read_norms(H, 2));
+        const double rq = norm_value(H, 1);
+        ++*cycles;
+        *rho_last = rprev > 0.0 ? rq / rprev : 0.0;
+        if (*rho_last > 0.0) *logsum += std::log(*rho_last);
+        ++*nrho;
+        rprev = rq;
+        if (!std::isfinite(rq)) break;
+    }
+    return LSMG_OK;
+}
+
+StepArgsHost step_args(lsmg_hierarchy *H, const double *sn, const double *cn, const double *sb, double sb_const,
+                       const double *fn, const double *fnp1)
+{
+    StepArgsHost a;
+    a.sn = sn;
+    a.cn = cn;
+    a.bs = H->bs;
+    a.bc = H->bc;
+    a.fn = (fn && fnp1) ? fn : nullptr;
+    a.fnp1 = (fn && fnp1) ? fnp1 : nullptr;
+    a.sb = sb;
+    a.sb_const = sb_const;
+    return a;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void lsmg_default_params(lsmg_params *p)
+{
+    if (!p) return;
+    p->a = 1.0e4;
+    p->d = 0.1;
+    p->m_s = 64.06;
+    p->m_c = 100.09;
+    p->alpha = 0.01;
+    p->beta = 0.1;
+    p->tau_s = 0.9;
+    p->nu1 = 2;
+    p->nu2 = 2;
+    p->ghost_sweeps = 5;
+    p->band_steps = 3;
+    p->ghost_c_new = 1;
+    p->coarsest_n = 5;
+    p->precision = 0;
+    p->newton_tol = 1e-10;
+    p->newton_max = 20;
+    p->lin_rtol = 1e-3;
+    p->cycles_max = 30;
+}
+
+const char *lsmg_last_error(void) { return g_err.c_str(); }
+
+lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid, const lsmg_params *params,
+                                 void *stream, lsmg_hierarchy **out)
+{
+    if (!out) return fail(LSMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d_levelset || !grid) return fail(LSMG_EINVAL, "levelset or grid is NULL");
+    if (grid->dim != 2 && grid->dim != 3) return fail(LSMG_EINVAL, "dim must be 2 or 3");
+    if (grid->n < 3 || !(grid->hi > grid->lo)) return fail(LSMG_EINVAL, "bad grid");
+    LSMGCHK(check_params(params));
+    lsmg_hierarchy *H = new (std::nothrow) lsmg_hierarchy();
+    if (!H) return fail(LSMG_EOOM, "host allocation");
+    H->p = *params;
+    H->stream = (hipStream_t)stream;
+    lsmg_status st = build(H, d_levelset, grid);
+    if (st != LSMG_OK) {
+        (void)hipStreamSynchronize(H->stream);
+        delete H;
+        return st;
+    }
+    *out = H;
+    return LSMG_OK;
+}
+
+void lsmg_destroy_hierarchy(lsmg_hierarchy *h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
+{
+    if (!h) return fail(LSMG_EINVAL, "hierarchy is NULL");
+    LSMGCHK(check_params(params));
+    if (params->coarsest_n != h->p.coarsest_n || params->band_steps != h->p.band_steps)
+        return fail(LSMG_EINVAL, "coarsest_n and band_steps are fixed at build");
+    if (params->precision == 1 && !h->have32) {
+        h->p.precision = 1;
+        LSMGCHK(build_f32(h));
+        make_descs(h);
+    }
+    h->p = *params;
+    return push_desc(h);
+}
+
+lsmg_status lsmg_num_levels(const lsmg_hierarchy *h, int *nlev)
+{
+    if (!h || !nlev) return fail(LSMG_EINVAL, "NULL argument");
+    *nlev = h->nlev;
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_level_info(const lsmg_hierarchy *h, int level, int *n, double *hh, int *n_inside, int *n_ghost,
+                            int *n_band)
+{
+    LSMGCHK(level_ok(h, level));
+    const Level &Lv = h->L[level];
+    if (n) *n = Lv.n;
+    if (hh) *hh = Lv.h;
+    if (n_inside) *n_inside = Lv.ni;
+    if (n_ghost) *n_ghost = Lv.ng;
+    if (n_band) *n_band = Lv.nb;
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_compact_to_grid(lsmg_hierarchy *h, int level, int64_t *d_out)
+{
+    LSMGCHK(level_ok(h, level));
+    if (!d_out) return fail(LSMG_EINVAL, "d_out is NULL");
+    const Level &Lv = h->L[level];
+    HIPCHK(hipMemcpyAsync(d_out, Lv.c2g, sizeof(int64_t) * Lv.na, hipMemcpyDeviceToDevice, h->stream));
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_ghost_table(lsmg_hierarchy *h, int level, int32_t *d_st, double *d_w, double *d_B, double *d_normal,
+                             int32_t *d_order, int32_t *d_bfallback)
+{
+    LSMGCHK(level_ok(h, level));
+    const Level &Lv = h->L[level];
+    const size_t ng = Lv.ng, nst = h->nst, dim = h->dim;
+    if (ng == 0) return LSMG_OK;
+    // stored structure-of-arrays (k * ng + q); returned row-major (q * nst + k)
+    if (d_st || d_w) {
+        std::vector<int> st(ng * nst), stT(ng * nst);
+        std::vector<double> w(ng * nst), wT(ng * nst);
+        HIPCHK(hipMemcpyAsync(st.data(), Lv.g_stc, sizeof(int) * ng * nst, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(w.data(), Lv.g_w, sizeof(double) * ng * nst, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (size_t q = 0; q < ng; ++q)
+            for (size_t k = 0; k < nst; ++k) {
+                stT[q * nst + k] = st[k * ng + q];
+                wT[q * nst + k] = w[k * ng + q];
+            }
+        if (d_st) HIPCHK(hipMemcpyAsync(d_st, stT.data(), sizeof(int) * ng * nst, hipMemcpyHostToDevice, h->stream));
+        if (d_w) HIPCHK(hipMemcpyAsync(d_w, wT.data(), sizeof(double) * ng * nst, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    if (d_B) HIPCHK(hipMemcpyAsync(d_B, Lv.g_B, sizeof(double) * ng * dim, hipMemcpyDeviceToDevice, h->stream));
+    if (d_normal)
+        HIPCHK(hipMemcpyAsync(d_normal, Lv.g_nrm, sizeof(double) * ng * dim, hipMemcpyDeviceToDevice, h->stream));
+    if (d_order) HIPCHK(hipMemcpyAsync(d_order, Lv.g_order, sizeof(int) * ng, hipMemcpyDeviceToDevice, h->stream));
+    if (d_bfallback)
+        HIPCHK(hipMemcpyAsync(d_bfallback, Lv.g_bfall, sizeof(int) * ng, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_state_create(lsmg_hierarchy *h, lsmg_state **out)
+{
+    if (!h || !out) return fail(LSMG_EINVAL, "NULL argument");
+    *out = nullptr;
+    lsmg_state *st = new (std::nothrow) lsmg_state();
+    if (!st) return fail(LSMG_EOOM, "host allocation");
+    st->h = h;
+    const Level &L0 = h->L[0];
+    if (hipMalloc(&st->s, sizeof(double) * L0.ssize) != hipSuccess ||
+        hipMalloc(&st->c, sizeof(double) * L0.ssize) != hipSuccess) {
+        delete st;
+        return fail(LSMG_EOOM, "state allocation");
+    }
+    if (hipMemsetAsync(st->s, 0, sizeof(double) * L0.ssize, h->stream) != hipSuccess ||
+        hipMemsetAsync(st->c, 0, sizeof(double) * L0.ssize, h->stream) != hipSuccess) {
+        delete st;
+        return fail(LSMG_EHIP, "state clear");
+    }
+    *out = st;
+    return LSMG_OK;
+}
+
+void lsmg_state_destroy(lsmg_state *st)
+{
+    if (!st) return;
+    (void)hipStreamSynchronize(st->h->stream);
+    delete st;
+}
+
+lsmg_status lsmg_state_set(lsmg_state *st, const double *d_W)
+{
+    if (!st || !d_W) return fail(LSMG_EINVAL, "NULL argument");
+    scatter<double>(st->h, 0, d_W, st->s, st->c);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_state_get(const lsmg_state *st, double *d_W)
+{
+    if (!st || !d_W) return fail(LSMG_EINVAL, "NULL argument");
+    gather<double>(st->h, 0, st->s, st->c, d_W);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_state_set_grid(lsmg_state *st, const double *d_s, const double *d_c)
+{
+    if (!st || !d_s || !d_c) return fail(LSMG_EINVAL, "NULL argument");
+    const Level &L0 = st->h->L[0];
+    launch_grid_to_split(L0.c2g, L0.na, d_s, d_c, L0.c2s, st->s, st->c, st->h->stream);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_state_get_grid(const lsmg_state *st, double *d_s, double *d_c)
+{
+    if (!st || !d_s || !d_c) return fail(LSMG_EINVAL, "NULL argument");
+    const lsmg_hierarchy *h = st->h;
+    const Level &L0 = h->L[0];
+    const long long nn = (long long)L0.n * L0.n * (h->dim == 3 ? L0.n : 1);
+    launch_fill<double>(d_s, nn, NAN, h->stream);
+    launch_fill<double>(d_c, nn, NAN, h->stream);
+    launch_compact_to_grid(L0.c2g, L0.na, st->s, st->c, L0.c2s, d_s, d_c, h->stream);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, const double *d_sb, double sb_const,
+                                const double *d_fn, const double *d_fnp1, lsmg_step_stats *stats)
+{
+    if (!h || !st || st->h != h) return fail(LSMG_EINVAL, "bad hierarchy or state");
+    LSMGCHK(set_dt(h, dt));
+    const Level &L0 = h->L[0];
+    hipStream_t s = h->stream;
+    // W^{(n+1,0)} = W^n
+    HIPCHK(hipMemcpyAsync(L0.s, st->s, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(L0.c, st->c, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
+    const StepArgsHost A = step_args(h, st->s, st->c, d_sb, sb_const, d_fn, d_fnp1);
+    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, s);
+    launch_zero_u64(h->d_norms, 4, s);
+    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->d_norms, s);
+    LSMGCHK(read_norms(h, 1));
+    double nF = norm_value(h, 0);
+    lsmg_status rc = LSMG_ENOCONV;
+    int cycles = 0, nrho = 0, it;
+    double rho_last = 0.0, logsum = 0.0, dwrel = 0.0;
+    for (it = 1; it <= h->p.newton_max; ++it) {
+        if (!std::isfinite(nF)) {
+            rc = fail(LSMG_ENONFINITE, "residual is not finite");
+            break;
+        }
+        LSMGCHK(linearize(h));
+        LSMGCHK(check_factor(h));
+        LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho));
+        launch_zero_u64(h->d_norms, 4, s);
+        launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), h->d_norms + 2, h->d_norms + 3, s);
+        launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->d_norms, s);
+        LSMGCHK(read_norms(h, 4));
+        nF = norm_value(h, 0);
+        const double nD = norm_value(h, 2), nW = norm_value(h, 3);
+        dwrel = nW > 0.0 ? nD / nW : nD;
+        if (!std::isfinite(nF) || !std::isfinite(dwrel)) {
+            rc = fail(LSMG_ENONFINITE, "Newton iterate is not finite");
+            break;
+        }
+        if ((nF < dwrel ? nF : dwrel) < h->p.newton_tol) {
+            rc = LSMG_OK;
+            break;
+        }
+    }
+    if (rc == LSMG_ENOCONV) fail(LSMG_ENOCONV, "Newton did not converge in %d iterations", h->p.newton_max);
+    if (stats) {
+        stats->newton_iters = it > h->p.newton_max ? h->p.newton_max : it;
+        stats->vcycles = cycles;
+        stats->res_inf = nF;
+        stats->rho_last = rho_last;
+        stats->rho_geo = nrho > 0 ? std::exp(logsum / nrho) : 0.0;
+        stats->dw_rel = dwrel;
+    }
+    if (rc == LSMG_OK) {
+        HIPCHK(hipMemcpyAsync(st->s, L0.s, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(st->c, L0.c, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    h->lin_set = false;
+    return rc;
+}
+
+lsmg_status lsmg_residual(lsmg_hierarchy *h, const double *d_W, const double *d_Wn, double dt, const double *d_sb,
+                          double sb_const, const double *d_fn, const double *d_fnp1, double *d_F, double *res_inf)
+{
+    if (!h || !d_W || !d_Wn || !d_F) return fail(LSMG_EINVAL, "NULL argument");
+    LSMGCHK(set_dt(h, dt));
+    const Level &L0 = h->L[0];
+    scatter<double>(h, 0, d_W, L0.s, L0.c);
+    scatter<double>(h, 0, d_Wn, h->tmp_s, h->tmp_c);
+    const StepArgsHost A = step_args(h, h->tmp_s, h->tmp_c, d_sb, sb_const, d_fn, d_fnp1);
+    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->stream);
+    launch_zero_u64(h->d_norms, 1, h->stream);
+    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->d_norms, h->stream);
+    gather<double>(h, 0, L0.rhs_s, L0.rhs_c, d_F);
+    h->lin_set = false;
+    if (res_inf) {
+        LSMGCHK(read_norms(h, 1));
+        *res_inf = norm_value(h, 0);
+    }
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_set_linearization(lsmg_hierarchy *h, const double *d_W, double dt)
+{
+    if (!h || !d_W) return fail(LSMG_EINVAL, "NULL argument");
+    LSMGCHK(set_dt(h, dt));
+    const Level &L0 = h->L[0];
+    scatter<double>(h, 0, d_W, L0.s, L0.c);
+    LSMGCHK(linearize(h));
+    return check_factor(h);
+}
+
+lsmg_status lsmg_level_state(lsmg_hierarchy *h, int level, double *d_W)
+{
+    LSMGCHK(level_ok(h, level));
+    if (!d_W) return fail(LSMG_EINVAL, "NULL argument");
+    gather<double>(h, level, h->L[level].s, h->L[level].c, d_W);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_apply_J(lsmg_hierarchy *h, int level, const double *d_x, double *d_y)
+{
+    LSMGCHK(level_ok(h, level));
+    if (!h->lin_set) return fail(LSMG_EINVAL, "no linearisation point set");
+    const Level &Lv = h->L[level];
+    scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
+    launch_apply_J<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), h->stream);
+    gather<double>(h, level, Lv.r_s, Lv.r_c, d_y);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_smooth(lsmg_hierarchy *h, int level, const double *d_rhs, double *d_x, int nsweeps)
+{
+    LSMGCHK(level_ok(h, level));
+    if (!h->lin_set) return fail(LSMG_EINVAL, "no linearisation point set");
+    const Level &Lv = h->L[level];
+    scatter<double>(h, level, d_rhs, Lv.rhs_s, Lv.rhs_c);
+    scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
+    for (int i = 0; i < nsweeps; ++i) smooth_level<double>(h, level);
+    gather<double>(h, level, Lv.x_s, Lv.x_c, d_x);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_defect(lsmg_hierarchy *h, int level, const double *d_rhs, const double *d_x, double *d_r,
+                        double *res_inf)
+{
+    LSMGCHK(level_ok(h, level));
+    if (!h->lin_set) return fail(LSMG_EINVAL, "no linearisation point set");
+    const Level &Lv = h->L[level];
+    scatter<double>(h, level, d_rhs, Lv.rhs_s, Lv.rhs_c);
+    scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
+    launch_zero_u64(h->d_norms + 1, 1, h->stream);
+    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), h->d_norms + 1, h->stream);
+    if (d_r) gather<double>(h, level, Lv.r_s, Lv.r_c, d_r);
+    if (res_inf) {
+        LSMGCHK(read_norms(h, 2));
+        *res_inf = norm_value(h, 1);
+    }
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_restrict(lsmg_hierarchy *h, int level, const double *d_r, double *d_rhs_coarse)
+{
+    LSMGCHK(level_ok(h, level));
+    if (level + 1 >= h->nlev) return fail(LSMG_EINVAL, "no coarser level");
+    const Level &F = h->L[level], &C = h->L[level + 1];
+    launch_fill<double>(F.r_s, F.ssize, 0.0, h->stream);
+    launch_fill<double>(F.r_c, F.ssize, 0.0, h->stream);
+    scatter<double>(h, level, d_r, F.r_s, F.r_c);
+    launch_band<double>(h->d64, F.w_band(), F.nbandc, h->stream);
+    launch_restrict<double>(h->dim, h->d64, C.w_act(), C.nw_act(), h->stream);
+    gather<double>(h, level + 1, C.rhs_s, C.rhs_c, d_rhs_coarse);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_prolong_add(lsmg_hierarchy *h, int level, const double *d_e_coarse, double *d_x)
+{
+    LSMGCHK(level_ok(h, level));
+    if (level + 1 >= h->nlev) return fail(LSMG_EINVAL, "no coarser level");
+    const Level &F = h->L[level], &C = h->L[level + 1];
+    scatter<double>(h, level + 1, d_e_coarse, C.x_s, C.x_c);
+    scatter<double>(h, level, d_x, F.x_s, F.x_c);
+    launch_prolong<double>(h->dim, h->d64, F.w_act(), F.nw_act(), h->stream);
+    gather<double>(h, level, F.x_s, F.x_c, d_x);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_coarse_solve(lsmg_hierarchy *h, const double *d_rhs, double *d_x)
+{
+    if (!h || !d_rhs || !d_x) return fail(LSMG_EINVAL, "NULL argument");
+    if (!h->lin_set) return fail(LSMG_EINVAL, "no linearisation point set");
+    const int lc = h->nlev - 1;
+    const Level &Lc = h->L[lc];
+    scatter<double>(h, lc, d_rhs, Lc.rhs_s, Lc.rhs_c);
+    launch_coarse_solve<double>(h->d64, lc, 2 * Lc.na, Lc.c2s, h->lu, h->piv, h->stream);
+    gather<double>(h, lc, Lc.x_s, Lc.x_c, d_x);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_vcycle(lsmg_hierarchy *h, int level, const double *d_rhs, double *d_x, double *res_inf)
+{
+    LSMGCHK(level_ok(h, level));
+    if (!h->lin_set) return fail(LSMG_EINVAL, "no linearisation point set");
+    const Level &Lv = h->L[level];
+    scatter<double>(h, level, d_rhs, Lv.rhs_s, Lv.rhs_c);
+    scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
+    vcycle_rec<double>(h, level);
+    launch_zero_u64(h->d_norms + 1, 1, h->stream);
+    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), h->d_norms + 1, h->stream);
+    gather<double>(h, level, Lv.x_s, Lv.x_c, d_x);
+    if (res_inf) {
+        LSMGCHK(read_norms(h, 2));
+        *res_inf = norm_value(h, 1);
+    }
+    return LSMG_OK;
+}
+
+}  // extern "C"

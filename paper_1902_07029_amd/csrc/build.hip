@@ -1,0 +1,633 @@
+// Hierarchy build kernels: node classification and compaction (section 3.3,
+// eq. ghostdef, map M of eq. maprij), inside-row work segments, ghost geometry
+// (eq. nij, the upwind stencil ST, the boundary point B by bisection and the
+// weights of eq. JssD) and the tables of the boundary-defect extension used by
+// the restriction (section 3.5.2).
+//
+// This file is compiled with -ffp-contract=off: the geometry is a discrete
+// definition (which stencil nodes carry an exactly-zero weight, which side of
+// the level set a bisection midpoint falls on), so it is evaluated with plain
+// IEEE double operations in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "lsmg_dev.hpp"
+#include "lsmg_host.hpp"
+
+namespace lsmg {
+
+// ---------------------------------------------------------------------------
+// level set on the coarser grids: injection phi_c(I) = phi_f(2 I)
+// ---------------------------------------------------------------------------
+__global__ void k_inject_phi(int dim, const double *__restrict__ pf, int nf, double *__restrict__ pc, int nc)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long nn = (long long)nc * nc * (dim == 3 ? nc : 1);
+    if (g >= nn) return;
+    const int i = (int)(g % nc), j = (int)((g / nc) % nc), k = dim == 3 ? (int)(g / ((long long)nc * nc)) : 0;
+    const long long gf = (long long)(2 * i) + (long long)nf * ((long long)(2 * j) + (long long)nf * (2 * k));
+    pc[g] = pf[gf];
+}
+
+// ---------------------------------------------------------------------------
+// classification: inside where phi < 0; ghost where not inside and an axis
+// neighbour is inside; an inside node on the box edge is a geometry error
+// ---------------------------------------------------------------------------
+__global__ void k_classify(int dim, const double *__restrict__ phi, int n, int Wp, long long cs,
+                           uint8_t *__restrict__ type, uint8_t *__restrict__ fin, uint8_t *__restrict__ fgh,
+                           int *__restrict__ err)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nn = (long long)n * n * (dim == 3 ? n : 1);
+    if (g >= nn) return;
+    int id[3] = {(int)(g % n), (int)((g / n) % n), dim == 3 ? (int)(g / ((long long)n * n)) : 0};
+    const bool inside = phi[g] < 0.0;
+    bool ghost = false;
+    if (inside) {
+        for (int a = 0; a < dim; ++a)
+            if (id[a] == 0 || id[a] == n - 1) atomicOr(err, 1);
+    } else {
+        long long st = 1;
+        for (int a = 0; a < dim; ++a) {
+            if (id[a] > 0 && phi[g - st] < 0.0) ghost = true;
+            if (id[a] < n - 1 && phi[g + st] < 0.0) ghost = true;
+            st *= n;
+        }
+    }
+    const uint8_t t = inside ? kIn : (ghost ? kGhost : kOut);
+    type[sidx(n, Wp, cs, id[0], id[1], id[2])] = t;
+    fin[g] = inside;
+    fgh[g] = ghost;
+}
+
+// ---------------------------------------------------------------------------
+// ordered stream compaction of a byte flag array
+// ---------------------------------------------------------------------------
+constexpr int kTileThreads = 256, kTilePer = 16, kTile = kTileThreads * kTilePer;
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_count(const uint8_t *__restrict__ f, long long N,
+                                                             int64_t *__restrict__ counts)
+{
+    const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kTilePer;
+    int c = 0;
+    for (int e = 0; e < kTilePer; ++e)
+        if (base + e < N) c += f[base + e] != 0;
+    __shared__ int sh[kTileThreads];
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = kTileThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = sh[0];
+}
+
+// exclusive scan of M int64 values in place by one 1024-thread workgroup; total in a[M]
+__global__ __launch_bounds__(1024) void k_scan_single(int64_t *__restrict__ a, long long M)
+{
+    __shared__ int64_t sh[1024];
+    const int t = threadIdx.x;
+    const long long chunk = (M + 1023) / 1024;
+    const long long b = t * chunk, e = b + chunk < M ? b + chunk : M;
+    int64_t s = 0;
+    for (long long i = b; i < e; ++i) s += a[i];
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t > 0 ? sh[t - 1] : 0;
+    for (long long i = b; i < e; ++i) {
+        const int64_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (t == 1023) a[M] = sh[1023];
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_emit(const uint8_t *__restrict__ f, long long N,
+                                                            const int64_t *__restrict__ offs, int64_t *__restrict__ out)
+{
+    const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kTilePer;
+    int c = 0;
+    for (int e = 0; e < kTilePer; ++e)
+        if (base + e < N) c += f[base + e] != 0;
+    __shared__ int sh[kTileThreads];
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < kTileThreads; off <<= 1) {
+        int v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    long long pos = offs[blockIdx.x] + (threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0);
+    for (int e = 0; e < kTilePer; ++e)
+        if (base + e < N && f[base + e]) out[pos++] = base + e;
+}
+
+long long compact_scratch_size(long long N) { return (N + kTile - 1) / kTile + 1; }
+
+int compact_flags(const uint8_t *flags, long long N, int64_t *out, int64_t *scratch, int nscratch, hipStream_t s)
+{
+    const long long nt = (N + kTile - 1) / kTile;
+    if (nt + 1 > nscratch || N <= 0) return N <= 0 ? 0 : -1;
+    k_tile_count<<<(unsigned)nt, kTileThreads, 0, s>>>(flags, N, scratch);
+    k_scan_single<<<1, 1024, 0, s>>>(scratch, nt);
+    if (out) k_tile_emit<<<(unsigned)nt, kTileThreads, 0, s>>>(flags, N, scratch, out);
+    int64_t total = 0;
+    if (hipMemcpyAsync(&total, scratch + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    return (int)total;
+}
+
+// compact index -> storage index, and storage -> compact
+__global__ void k_c2s(int dim, const int64_t *__restrict__ c2g, int na, int n, int Wp, long long cs,
+                      int *__restrict__ c2s, int *__restrict__ cmap)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= na) return;
+    const long long g = c2g[r];
+    const int i = (int)(g % n), j = (int)((g / n) % n), k = dim == 3 ? (int)(g / ((long long)n * n)) : 0;
+    const long long q = sidx(n, Wp, cs, i, j, k);
+    c2s[r] = (int)q;
+    cmap[q] = r;
+}
+
+// ---------------------------------------------------------------------------
+// work segments of inside nodes: per (colour, row) the range [pmin, pmax] of
+// inside positions cut into pieces of at most 64
+// ---------------------------------------------------------------------------
+__global__ void k_seg_count(const uint8_t *__restrict__ type, long long rows, int Wp, long long cs,
+                            int64_t *__restrict__ cnt, int *__restrict__ pmin)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * rows) return;
+    const long long colour = t / rows, row = t - colour * rows;
+    const uint8_t *rp = type + colour * cs + row * Wp;
+    int lo = -1, hi = -1;
+    for (int p = 0; p < Wp; ++p)
+        if (rp[p] == kIn) {
+            if (lo < 0) lo = p;
+            hi = p;
+        }
+    cnt[t] = lo < 0 ? 0 : (hi - lo + kWave) / kWave;
+    pmin[t] = lo;
+    if (lo >= 0) pmin[t + 2 * rows] = hi;
+}
+
+__global__ void k_seg_emit(long long rows, const int64_t *__restrict__ offs, const int *__restrict__ pmin, int desc,
+                           int4 *__restrict__ items)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * rows) return;
+    const long long colour = t / rows, row = t - colour * rows;
+    const int lo = pmin[t];
+    if (lo < 0) return;
+    const int hi = pmin[t + 2 * rows];
+    long long o = offs[t];
+    for (int p = lo; p <= hi; p += kWave) {
+        const int e = p + kWave <= hi + 1 ? p + kWave : hi + 1;
+        items[o++] = make_int4((desc << 2) | (int)colour, (int)row, p, e);
+    }
+}
+
+void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows, long long cs, int desc,
+                    int4 **out_items, int *out_count, hipStream_t s)
+{
+    (void)dim;
+    (void)n;
+    int64_t *cnt = nullptr;
+    int *pmin = nullptr;
+    out_items[0] = out_items[1] = nullptr;
+    out_count[0] = out_count[1] = 0;
+    if (hipMalloc(&cnt, sizeof(int64_t) * (2 * rows + 1)) != hipSuccess) return;
+    if (hipMalloc(&pmin, sizeof(int) * 4 * rows) != hipSuccess) { (void)hipFree(cnt); return; }
+    const unsigned nb = (unsigned)((2 * rows + 255) / 256);
+    k_seg_count<<<nb, 256, 0, s>>>(type, rows, Wp, cs, cnt, pmin);
+    // per-colour totals come from the exclusive scan at rows and 2 rows
+    k_scan_single<<<1, 1024, 0, s>>>(cnt, 2 * rows);
+    int64_t h[2] = {0, 0};
+    (void)hipMemcpyAsync(&h[0], cnt + rows, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&h[1], cnt + 2 * rows, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    const long long total = h[1];
+    int4 *items = nullptr;
+    if (total > 0 && hipMalloc(&items, sizeof(int4) * total) == hipSuccess) {
+        k_seg_emit<<<nb, 256, 0, s>>>(rows, cnt, pmin, desc, items);
+        (void)hipStreamSynchronize(s);
+        out_items[0] = items;
+        out_items[1] = items + h[0];
+        out_count[0] = (int)h[0];
+        out_count[1] = (int)(total - h[0]);
+    }
+    (void)hipFree(cnt);
+    (void)hipFree(pmin);
+}
+
+// ---------------------------------------------------------------------------
+// ghost geometry (section 3.3): normal by central differences (one-sided at
+// the box edge), upwind stencil ST, boundary point B by full-precision
+// bisection of the biquadratic (triquadratic) interpolant of phi on the
+// segment P = G - 2 h n -> G, the tensor weights of eq. (JssD) and the order
+// fallback (quadratic -> linear -> constant) where a nonzero weight falls on
+// an inactive or out-of-box node.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double lag2(int k, double t)
+{
+    if (k == 0) return t * (1.0 + t) / 2.0;
+    if (k == 1) return (1.0 - t) * (1.0 + t);
+    return t * (t - 1.0) / 2.0;
+}
+
+__device__ __forceinline__ double lag1(int k, double t)
+{
+    if (k == 0) return t;
+    if (k == 1) return 1.0 - t;
+    return 0.0;
+}
+
+template <int DIM>
+__device__ double phi_interp(const double *phi, const long long *stl, const int *gi, const int *m, const double *X,
+                             double lo, double h)
+{
+    constexpr int NST = DIM == 2 ? 9 : 27;
+    double t[3];
+    for (int a = 0; a < DIM; ++a) t[a] = (double)m[a] * (X[a] - (lo + (double)(gi[a] - m[a]) * h)) / h;
+    double v = 0.0;
+    for (int k = 0; k < NST; ++k) {
+        int kk = k;
+        double wk = 1.0;
+        for (int a = 0; a < DIM; ++a) {
+            wk *= lag2(kk % 3, t[a]);
+            kk /= 3;
+        }
+        v += wk * phi[stl[k]];
+    }
+    return v;
+}
+
+template <int DIM>
+__global__ void k_ghost_geometry(int level, const double *__restrict__ phi, const uint8_t *__restrict__ type,
+                                 const int64_t *__restrict__ c2g_gh, const int *__restrict__ cmap, int ng, int n,
+                                 int Wp, long long cs, double lo, double h, int *__restrict__ g_idx,
+                                 int *__restrict__ g_st, int *__restrict__ g_stc, double *__restrict__ g_w,
+                                 double *__restrict__ g_B, double *__restrict__ g_nrm, int *__restrict__ g_order,
+                                 int *__restrict__ g_bfall, int *__restrict__ err)
+{
+    constexpr int NST = DIM == 2 ? 9 : 27;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ng) return;
+    const long long g = c2g_gh[q];
+    int gi[3] = {(int)(g % n), (int)((g / n) % n), DIM == 3 ? (int)(g / ((long long)n * n)) : 0};
+    double G[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < DIM; ++a) G[a] = lo + (double)gi[a] * h;
+    // normal
+    double nt[3] = {0.0, 0.0, 0.0}, nrm[3] = {0.0, 0.0, 0.0};
+    long long sa = 1;
+    for (int a = 0; a < DIM; ++a) {
+        if (gi[a] > 0 && gi[a] < n - 1) nt[a] = (phi[g + sa] - phi[g - sa]) / (2.0 * h);
+        else if (gi[a] == 0) nt[a] = (phi[g + sa] - phi[g]) / h;
+        else nt[a] = (phi[g] - phi[g - sa]) / h;
+        sa *= n;
+    }
+    double len2 = 0.0;
+    for (int a = 0; a < DIM; ++a) len2 += nt[a] * nt[a];
+    const double len = sqrt(len2);
+    int m[3] = {1, 1, 1};
+    if (len > 0.0)
+        for (int a = 0; a < DIM; ++a) nrm[a] = nt[a] / len;
+    for (int a = 0; a < DIM; ++a) m[a] = nrm[a] >= 0.0 ? 1 : -1;
+    // upwind stencil
+    long long stl[NST];
+    long long sts[NST];
+    bool oob[NST];
+    bool any_oob = false;
+    const long long gs = sidx(n, Wp, cs, gi[0], gi[1], gi[2]);
+    for (int k = 0; k < NST; ++k) {
+        int kk = k, id[3] = {0, 0, 0};
+        bool o = false;
+        for (int a = 0; a < DIM; ++a) {
+            id[a] = gi[a] - m[a] * (kk % 3);
+            kk /= 3;
+            if (id[a] < 0 || id[a] >= n) o = true;
+        }
+        oob[k] = o;
+        any_oob |= o;
+        stl[k] = o ? g : (long long)id[0] + (long long)n * ((long long)id[1] + (long long)n * id[2]);
+        sts[k] = o ? gs : sidx(n, Wp, cs, id[0], id[1], id[2]);
+    }
+    // boundary point
+    double Bp[3] = {G[0], G[1], G[2]};
+    int bfall = 0;
+    if (len > 0.0 && any_oob) {
+        bfall = 1;
+        for (int a = 0; a < DIM; ++a) Bp[a] = G[a] - phi[g] * nt[a] / len2;
+    } else if (len > 0.0) {
+        double P[3] = {0.0, 0.0, 0.0}, X[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < DIM; ++a) P[a] = G[a] - 2.0 * h * nrm[a];
+        const double f0 = phi_interp<DIM>(phi, stl, gi, m, P, lo, h);
+        if (f0 < 0.0) {
+            double alo = 0.0, ahi = 1.0;
+            for (int it = 0; it < 200; ++it) {
+                const double am = 0.5 * (alo + ahi);
+                if (am <= alo || am >= ahi) break;
+                for (int a = 0; a < DIM; ++a) X[a] = P[a] + am * (G[a] - P[a]);
+                if (phi_interp<DIM>(phi, stl, gi, m, X, lo, h) < 0.0) alo = am;
+                else ahi = am;
+            }
+            for (int a = 0; a < DIM; ++a) Bp[a] = P[a] + ahi * (G[a] - P[a]);
+        } else {
+            bfall = 1;
+            for (int a = 0; a < DIM; ++a) Bp[a] = G[a] - phi[g] * nt[a] / len2;
+        }
+    }
+    double th[3] = {1.0, 1.0, 1.0};
+    for (int a = 0; a < DIM; ++a) th[a] = (double)m[a] * (Bp[a] - (lo + (double)(gi[a] - m[a]) * h)) / h;
+    bool bad = false;
+    for (int a = 0; a < DIM; ++a)
+        if (!(th[a] >= -1.0 && th[a] <= 2.0)) bad = true;
+    if (bad && level == 0) atomicOr(err, 2);
+    double w[NST];
+    int order = 2;
+    if (!bad) {
+        for (int k = 0; k < NST; ++k) {
+            int kk = k;
+            double wk = 1.0;
+            for (int a = 0; a < DIM; ++a) {
+                wk *= lag2(kk % 3, th[a]);
+                kk /= 3;
+            }
+            w[k] = wk;
+        }
+        for (int k = 0; k < NST; ++k)
+            if (w[k] != 0.0 && (oob[k] || type[sts[k]] == kOut)) order = 1;
+        if (order == 1) {
+            for (int k = 0; k < NST; ++k) {
+                int kk = k;
+                double wk = 1.0;
+                for (int a = 0; a < DIM; ++a) {
+                    wk *= lag1(kk % 3, th[a]);
+                    kk /= 3;
+                }
+                w[k] = wk;
+            }
+            for (int k = 0; k < NST; ++k)
+                if (w[k] != 0.0 && (oob[k] || type[sts[k]] == kOut)) order = 0;
+        }
+    } else {
+        order = 0;
+    }
+    if (order == 0)
+        for (int k = 0; k < NST; ++k) w[k] = k == 0 ? 1.0 : 0.0;
+    g_idx[q] = (int)gs;
+    for (int k = 0; k < NST; ++k) {
+        // zero-weight entries point at the ghost itself, which is always active
+        const long long tgt = w[k] != 0.0 ? sts[k] : gs;
+        g_st[k * ng + q] = (int)tgt;
+        g_stc[k * ng + q] = cmap[sts[k]];
+        g_w[k * ng + q] = w[k];
+    }
+    for (int a = 0; a < DIM; ++a) {
+        g_B[q * DIM + a] = Bp[a];
+        g_nrm[q * DIM + a] = nrm[a];
+    }
+    g_order[q] = order;
+    g_bfall[q] = bfall;
+}
+
+// ---------------------------------------------------------------------------
+// boundary band: inactive fine nodes in the 3^d neighbourhood of the fine
+// centre 2I of every coarse ghost I
+// ---------------------------------------------------------------------------
+__global__ void k_band_mark(int dim, const int64_t *__restrict__ c2g_cg, int ngc, int nc,
+                            const uint8_t *__restrict__ ftype, int nf, int fWp, long long fcs,
+                            uint8_t *__restrict__ flag)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ngc) return;
+    const long long g = c2g_cg[q];
+    const int ci[3] = {(int)(g % nc), (int)((g / nc) % nc), dim == 3 ? (int)(g / ((long long)nc * nc)) : 0};
+    const int nst = dim == 3 ? 27 : 9;
+    for (int k = 0; k < nst; ++k) {
+        int kk = k, id[3] = {0, 0, 0};
+        bool in = true;
+        for (int a = 0; a < dim; ++a) {
+            id[a] = 2 * ci[a] + kk % 3 - 1;
+            kk /= 3;
+            if (id[a] < 0 || id[a] >= nf) in = false;
+        }
+        if (!in) continue;
+        if (ftype[sidx(nf, fWp, fcs, id[0], id[1], id[2])] == kOut)
+            flag[(long long)id[0] + (long long)nf * ((long long)id[1] + (long long)nf * id[2])] = 1;
+    }
+}
+
+__global__ void k_fill_bandid(const int64_t *__restrict__ band, int nb, int *__restrict__ bandid)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) bandid[band[b]] = b;
+}
+
+// upwind neighbours q - m_a e_a of each band node that are ghosts or band nodes,
+// with weights |n_a| of the central-difference normal at the band node
+__global__ void k_band_geometry(int dim, const double *__restrict__ phi, const int64_t *__restrict__ band, int nb,
+                                const uint8_t *__restrict__ type, const int *__restrict__ bandid, int n, int Wp,
+                                long long cs, double h, int *__restrict__ up_s, int *__restrict__ up_b,
+                                double *__restrict__ up_w, int *__restrict__ b_idx)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const long long g = band[b];
+    const int gi[3] = {(int)(g % n), (int)((g / n) % n), dim == 3 ? (int)(g / ((long long)n * n)) : 0};
+    double nt[3] = {0.0, 0.0, 0.0};
+    long long sa = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (gi[a] > 0 && gi[a] < n - 1) nt[a] = (phi[g + sa] - phi[g - sa]) / (2.0 * h);
+        else if (gi[a] == 0) nt[a] = (phi[g + sa] - phi[g]) / h;
+        else nt[a] = (phi[g] - phi[g - sa]) / h;
+        sa *= n;
+    }
+    double len2 = 0.0;
+    for (int a = 0; a < dim; ++a) len2 += nt[a] * nt[a];
+    const double len = sqrt(len2);
+    b_idx[b] = (int)sidx(n, Wp, cs, gi[0], gi[1], gi[2]);
+    sa = 1;
+    for (int a = 0; a < dim; ++a) {
+        const double na = len > 0.0 ? nt[a] / len : 0.0;
+        const int ma = na >= 0.0 ? 1 : -1;
+        int up[3] = {gi[0], gi[1], gi[2]};
+        up[a] -= ma;
+        up_s[a * nb + b] = -1;
+        up_b[a * nb + b] = -1;
+        up_w[a * nb + b] = 0.0;
+        if (up[a] >= 0 && up[a] < n) {
+            const long long gu = g - ma * sa;
+            const long long su = sidx(n, Wp, cs, up[0], up[1], up[2]);
+            const int bid = bandid[gu];
+            if (type[su] == kGhost || bid >= 0) {
+                up_s[a * nb + b] = (int)su;
+                up_b[a * nb + b] = type[su] == kGhost ? -1 : bid;
+                up_w[a * nb + b] = fabs(na);
+            }
+        }
+        sa *= n;
+    }
+}
+
+// one layer of the extension: an unassigned band node with assigned upwind
+// neighbours (ghosts, or band nodes of earlier layers) becomes the normalised
+// |n_a|-weighted combination of them, composed down to ghost sources
+__global__ void k_band_layer(int dim, int layer, int nb, int maxc, const int *__restrict__ up_s,
+                             const int *__restrict__ up_b, const double *__restrict__ up_w, int *__restrict__ blayer,
+                             int *__restrict__ b_cnt, int *__restrict__ b_src, double *__restrict__ b_wt)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb || blayer[b] != 0) return;
+    bool asg[3] = {false, false, false};
+    double ws = 0.0;
+    int cnt = 0;
+    for (int a = 0; a < dim; ++a) {
+        const int su = up_s[a * nb + b];
+        if (su < 0) continue;
+        const int bb = up_b[a * nb + b];
+        bool ok = bb < 0;
+        if (!ok) {
+            const int lb = blayer[bb];
+            ok = lb > 0 && lb < layer;
+        }
+        if (!ok) continue;
+        asg[a] = true;
+        ws += up_w[a * nb + b];
+        ++cnt;
+    }
+    if (cnt == 0) return;
+    int e = 0;
+    for (int a = 0; a < dim; ++a) {
+        if (!asg[a]) continue;
+        const double wa = ws > 0.0 ? up_w[a * nb + b] / ws : 1.0 / cnt;
+        const int bb = up_b[a * nb + b];
+        if (bb < 0) {
+            if (e < maxc) {
+                b_src[e * nb + b] = up_s[a * nb + b];
+                b_wt[e * nb + b] = wa;
+                ++e;
+            }
+        } else {
+            const int cb = b_cnt[bb];
+            for (int j = 0; j < cb && e < maxc; ++j) {
+                b_src[e * nb + b] = b_src[j * nb + bb];
+                b_wt[e * nb + b] = wa * b_wt[j * nb + bb];
+                ++e;
+            }
+        }
+    }
+    b_cnt[b] = e;
+    blayer[b] = layer;
+}
+
+__global__ void k_band_ext(int nb, const int *__restrict__ b_idx, const int *__restrict__ blayer, uint8_t *ext)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb && blayer[b] > 0) ext[b_idx[b]] = 1;
+}
+
+__global__ void k_ghost_ext(int ng, const int *__restrict__ g_idx, uint8_t *ext)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < ng) ext[g_idx[q]] = 1;
+}
+
+template <typename D, typename S>
+__global__ void k_convert(D *__restrict__ dst, const S *__restrict__ src, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (D)src[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+void launch_inject_phi(int dim, const double *pf, int nf, double *pc, int nc, hipStream_t s)
+{
+    const long long nn = (long long)nc * nc * (dim == 3 ? nc : 1);
+    k_inject_phi<<<blocks(nn), 256, 0, s>>>(dim, pf, nf, pc, nc);
+}
+
+void launch_classify(int dim, const double *phi, int n, int Wp, long long cs, uint8_t *type, uint8_t *fin,
+                     uint8_t *fgh, int *err, hipStream_t s)
+{
+    const long long nn = (long long)n * n * (dim == 3 ? n : 1);
+    k_classify<<<blocks(nn), 256, 0, s>>>(dim, phi, n, Wp, cs, type, fin, fgh, err);
+}
+
+void launch_c2s(int dim, const int64_t *c2g, int na, int n, int Wp, long long cs, int *c2s, int *cmap, hipStream_t s)
+{
+    if (na > 0) k_c2s<<<blocks(na), 256, 0, s>>>(dim, c2g, na, n, Wp, cs, c2s, cmap);
+}
+
+void launch_ghost_geometry(int dim, int level, const double *phi, const uint8_t *type, const int64_t *c2g_gh,
+                           const int *cmap, int ng, int n, int Wp, long long cs, double lo, double h, int *g_idx,
+                           int *g_st, int *g_stc, double *g_w, double *g_B, double *g_nrm, int *g_order, int *g_bfall,
+                           int *err, hipStream_t s)
+{
+    if (ng <= 0) return;
+    if (dim == 2)
+        k_ghost_geometry<2><<<blocks(ng, 64), 64, 0, s>>>(level, phi, type, c2g_gh, cmap, ng, n, Wp, cs, lo, h, g_idx,
+                                                          g_st, g_stc, g_w, g_B, g_nrm, g_order, g_bfall, err);
+    else
+        k_ghost_geometry<3><<<blocks(ng, 64), 64, 0, s>>>(level, phi, type, c2g_gh, cmap, ng, n, Wp, cs, lo, h, g_idx,
+                                                          g_st, g_stc, g_w, g_B, g_nrm, g_order, g_bfall, err);
+}
+
+void launch_band_mark(int dim, const int64_t *c2g_cg, int ngc, int nc, const uint8_t *ftype, int nf, int fWp,
+                      long long fcs, uint8_t *flag, hipStream_t s)
+{
+    if (ngc > 0) k_band_mark<<<blocks(ngc), 256, 0, s>>>(dim, c2g_cg, ngc, nc, ftype, nf, fWp, fcs, flag);
+}
+
+void launch_fill_bandid(const int64_t *band, int nb, int *bandid, hipStream_t s)
+{
+    if (nb > 0) k_fill_bandid<<<blocks(nb), 256, 0, s>>>(band, nb, bandid);
+}
+
+void launch_band_geometry(int dim, const double *phi, const int64_t *band, int nb, const uint8_t *type,
+                          const int *bandid, int n, int Wp, long long cs, double h, int *up_s, int *up_b,
+                          double *up_w, int *b_idx, hipStream_t s)
+{
+    if (nb > 0)
+        k_band_geometry<<<blocks(nb), 256, 0, s>>>(dim, phi, band, nb, type, bandid, n, Wp, cs, h, up_s, up_b, up_w,
+                                                   b_idx);
+}
+
+void launch_band_layer(int dim, int layer, int nb, int maxc, const int *up_s, const int *up_b, const double *up_w,
+                       int *blayer, int *b_cnt, int *b_src, double *b_wt, hipStream_t s)
+{
+    if (nb > 0)
+        k_band_layer<<<blocks(nb), 256, 0, s>>>(dim, layer, nb, maxc, up_s, up_b, up_w, blayer, b_cnt, b_src, b_wt);
+}
+
+void launch_band_ext(int nb, const int *b_idx, const int *blayer, uint8_t *ext, hipStream_t s)
+{
+    if (nb > 0) k_band_ext<<<blocks(nb), 256, 0, s>>>(nb, b_idx, blayer, ext);
+}
+
+void launch_ghost_ext(int ng, const int *g_idx, uint8_t *ext, hipStream_t s)
+{
+    if (ng > 0) k_ghost_ext<<<blocks(ng), 256, 0, s>>>(ng, g_idx, ext);
+}
+
+template <typename D, typename S>
+void launch_convert(D *dst, const S *src, long long n, hipStream_t s)
+{
+    if (n > 0) k_convert<D, S><<<blocks(n), 256, 0, s>>>(dst, src, n);
+}
+template void launch_convert<float, double>(float *, const double *, long long, hipStream_t);
+
+}  // namespace lsmg

@@ -1,0 +1,128 @@
+// Internal device-side definitions of the lsmg GPU library (gfx950).
+//
+// Storage of a level: every per-node array is a full grid held in red/black
+// split form.  Node (i, j[, k]) has colour c = (i + j + k) & 1, row
+// r = j + n k and position p = i >> 1; its storage index is
+//     c * cs + r * Wp + p,   cs = rows * Wp,  rows = n^(dim-1),
+// with Wp >= (n + 1) / 2 rounded up to 16 doubles (128 bytes).  A red or black
+// half-sweep therefore reads and writes contiguous memory, and the four (six)
+// axis neighbours of a node are the other colour in the same row (x) or at the
+// same position in the rows above and below (y, z).
+//
+// Work is described by lists of int4 work items, one 64-lane wavefront per
+// item: x = (descriptor index << 2) | kind, then
+//   kind 0 / 1: inside nodes of colour 0 / 1 in row y, positions [z, w);
+//   kind 2: ghosts [z, w) of the level's ghost list;
+//   kind 3: band nodes [z, w) of the level's boundary band.
+// Descriptors of one hierarchy are contiguous by level (finest first), so the
+// next coarser level of descriptor d is d + 1 and the next finer is d - 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsmg {
+
+constexpr int kWave = 64;
+constexpr int kItemsPerBlock = 4;          // 256-thread workgroups, one item per wavefront
+constexpr int kBlock = kWave * kItemsPerBlock;
+constexpr int kMaxBandEntries2 = 8;        // 2^band_steps with band_steps <= 3 (2-D)
+constexpr int kMaxBandEntries3 = 27;       // 3^band_steps (3-D)
+
+enum : uint8_t { kOut = 0, kIn = 1, kGhost = 2 };
+
+template <typename T>
+struct LevelDesc {
+    int dim, n, Wp, nst;
+    int ni, ng, na, nb, bmax;
+    int level, pad0;
+    long long rows, cs;
+    double lo, h;
+    // model and solver scalars in the working precision
+    T kap;       // d / (4 h^2)
+    T alpha, beta, dt_inv, ks_half, kc_half, tau_s;
+    T d_half_h2; // d / (2 h^2)
+    int ghost_c_new, pad1;
+    // per-node arrays (split layout)
+    const uint8_t *type;     // kOut / kIn / kGhost
+    const uint8_t *ext;      // 1 for ghosts and band nodes reached by the extension
+    const int *cmap;         // storage -> compact index, -1 if inactive
+    T *s, *c;                // linearisation point
+    T *rhs_s, *rhs_c;
+    T *x_s, *x_c;
+    T *r_s, *r_c;
+    // ghost table (structure of arrays, entry k of ghost q at k * ng + q)
+    const int *g_idx;        // storage index of ghost q
+    const int *g_st;         // storage index of stencil node k
+    const T *g_w;            // boundary-row weight of stencil node k
+    T *g_tmp, *g_old;        // Jacobi buffers
+    // band of inactive nodes used by the boundary-defect restriction
+    const int *b_idx;        // storage index of band node b
+    const int *b_cnt;        // number of ghost sources
+    const int *b_src;        // entry j at j * nb + b: storage index of a ghost
+    const T *b_wt;           // its weight
+};
+
+__device__ __forceinline__ int item_desc(int4 w) { return w.x >> 2; }
+__device__ __forceinline__ int item_kind(int4 w) { return w.x & 3; }
+
+// grid coordinates of the node at (colour, row, position)
+template <int DIM>
+__device__ __forceinline__ void node_coords(int n, int colour, long long row, int p, int &i, int &j, int &k)
+{
+    if (DIM == 2) {
+        j = (int)row;
+        k = 0;
+    } else {
+        j = (int)(row % n);
+        k = (int)(row / n);
+    }
+    i = 2 * p + ((colour + j + k) & 1);
+}
+
+__device__ __forceinline__ long long sidx(int n, int Wp, long long cs, int i, int j, int k)
+{
+    const int colour = (i + j + k) & 1;
+    return colour * cs + ((long long)j + (long long)n * k) * Wp + (i >> 1);
+}
+
+// storage indices of the axis neighbours of node (i, row) with colour `colour`,
+// ordered x-, x+, y-, y+[, z-, z+]
+template <int DIM>
+__device__ __forceinline__ void neighbours(int n, int Wp, long long cs, int colour, long long row, int i, int p,
+                                           long long *nb)
+{
+    const long long ob = (colour ^ 1) * cs + row * Wp;
+    nb[0] = ob + ((i - 1) >> 1);
+    nb[1] = ob + ((i + 1) >> 1);
+    nb[2] = ob - Wp + p;
+    nb[3] = ob + Wp + p;
+    if (DIM == 3) {
+        nb[4] = ob - (long long)n * Wp + p;
+        nb[5] = ob + (long long)n * Wp + p;
+    }
+}
+
+// max of non-negative doubles as ordered bit patterns; NaN (any payload, sign
+// cleared) orders above +inf, so the maximum propagates NaN
+__device__ __forceinline__ unsigned long long abs_bits(double v)
+{
+    return (unsigned long long)__double_as_longlong(v) & 0x7fffffffffffffffull;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void norm_accumulate(unsigned long long *slot, unsigned long long bits)
+{
+    bits = wave_max_u64(bits);
+    if ((threadIdx.x & (kWave - 1)) == 0 && bits != 0ull) atomicMax(slot, bits);
+}
+
+}  // namespace lsmg

@@ -1,0 +1,87 @@
+// Host-side launchers of the lsmg kernels (implemented in kernels.hip and
+// build.hip) and the structures the C ABI layer shares with them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lsmg_dev.hpp"
+
+namespace lsmg {
+
+struct StepArgsHost {
+    const double *sn, *cn;
+    double *bs, *bc;
+    const double *fn, *fnp1;
+    const double *sb;
+    double sb_const;
+};
+
+// ---- V-cycle and Newton kernels (kernels.hip) ----
+template <typename T> void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int colour, hipStream_t s);
+template <typename T> void launch_ghost(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
+template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, unsigned long long *slot, hipStream_t s);
+template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
+template <typename T> void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
+template <typename T> void launch_restrict(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
+template <typename T> void launch_prolong(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
+template <typename T> void launch_inject(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
+void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const StepArgsHost &a, hipStream_t s);
+void launch_residual(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const StepArgsHost &a,
+                     unsigned long long *slot, hipStream_t s);
+void launch_newton_update(int dim, const LevelDesc<double> *d, const int4 *w, int nw, unsigned long long *ndw,
+                          unsigned long long *nw_slot, hipStream_t s);
+void launch_to_f32(int dim, const LevelDesc<double> *d64, const LevelDesc<float> *d32, const int4 *w, int nw, int what,
+                   hipStream_t s);
+void launch_add_f32(int dim, const LevelDesc<double> *d64, const LevelDesc<float> *d32, const int4 *w, int nw,
+                    hipStream_t s);
+template <typename T> void launch_gather_compact(const int *c2s, int na, const T *a, const T *b, double *out, hipStream_t s);
+template <typename T> void launch_scatter_compact(const int *c2s, int na, const double *v, T *a, T *b, hipStream_t s);
+template <typename T> void launch_fill(T *p, long long n, T v, hipStream_t s);
+void launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+void launch_compact_to_grid(const int64_t *c2g, int na, const double *a, const double *b, const int *c2s, double *gs,
+                            double *gc, hipStream_t s);
+void launch_grid_to_split(const int64_t *c2g, int na, const double *gs, const double *gc, const int *c2s, double *a,
+                          double *b, hipStream_t s);
+void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, const int *c2s, double *A, int *piv, int *status,
+                          hipStream_t s);
+template <typename T> void launch_coarse_solve(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *A,
+                                               const int *piv, hipStream_t s);
+
+// ---- hierarchy build (build.hip) ----
+struct BuildLevel {
+    int n, Wp;
+    long long rows, cs;
+    double lo, h;
+    const double *phi;   // level set on this level, n^dim, lexicographic
+    uint8_t *type;       // split layout (out)
+    uint8_t *ext;        // split layout (out)
+};
+
+void launch_inject_phi(int dim, const double *phi_f, int nf, double *phi_c, int nc, hipStream_t s);
+void launch_classify(int dim, const double *phi, int n, int Wp, long long cs, uint8_t *type_split, uint8_t *flag_in,
+                     uint8_t *flag_gh, int *err, hipStream_t s);
+// stream compaction of a byte flag array in index order; returns the count (synchronises)
+int compact_flags(const uint8_t *flags, long long N, int64_t *out, int64_t *scratch_counts, int nscratch, hipStream_t s);
+long long compact_scratch_size(long long N);
+void launch_c2s(int dim, const int64_t *c2g, int na, int n, int Wp, long long cs, int *c2s, int *cmap, hipStream_t s);
+// inside-segment work items of a level: returns the item count per colour (synchronises)
+void build_segments(int dim, const uint8_t *type_split, int n, int Wp, long long rows, long long cs, int desc,
+                    int4 **out_items, int *out_count, hipStream_t s);
+void launch_ghost_geometry(int dim, int level, const double *phi, const uint8_t *type_split, const int64_t *c2g_ghost,
+                           const int *cmap, int ng, int n, int Wp, long long cs, double lo, double h, int *g_idx,
+                           int *g_st, int *g_stc, double *g_w, double *g_B, double *g_nrm, int *g_order, int *g_bfall,
+                           int *err, hipStream_t s);
+void launch_band_mark(int dim, const int64_t *c2g_cghost, int ngc, int nc, const uint8_t *ftype_split, int nf, int fWp,
+                      long long fcs, uint8_t *flag_lin, hipStream_t s);
+void launch_band_geometry(int dim, const double *phi, const int64_t *band_lin, int nb, const uint8_t *type_split,
+                          const int *bandid_lin, int n, int Wp, long long cs, double h, int *up_s, int *up_b,
+                          double *up_w, int *b_idx, hipStream_t s);
+void launch_band_layer(int dim, int layer, int nb, int maxc, const int *up_s, const int *up_b, const double *up_w,
+                       int *blayer, int *b_cnt, int *b_src, double *b_wt, hipStream_t s);
+void launch_band_ext(int nb, const int *b_idx, const int *blayer, uint8_t *ext, hipStream_t s);
+void launch_ghost_ext(int ng, const int *g_idx, uint8_t *ext, hipStream_t s);
+void launch_fill_bandid(const int64_t *band_lin, int nb, int *bandid_lin, hipStream_t s);
+template <typename D, typename S> void launch_convert(D *dst, const S *src, long long n, hipStream_t s);
+
+}  // namespace lsmg

@@ -1,0 +1,286 @@
+"""Python binding of the lsmg C ABI (``include/lsmg.h``): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``liblsmg.so``; PyTorch supplies
+device memory (tensors' ``data_ptr()``) and the HIP stream.  The library must
+have been built (``paper_1902_07029_amd.build.build()``); there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsmg.so")
+
+OK, EINVAL, EGEOM, ENOCONV, ENONFINITE, EOOM, EHIP, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6, -7
+
+
+class LsmgError(RuntimeError):
+    def __init__(self, code, what, msg):
+        super().__init__(f"{what} failed with status {code}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("d", ctypes.c_double), ("m_s", ctypes.c_double),
+                ("m_c", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("tau_s", ctypes.c_double), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+                ("ghost_sweeps", ctypes.c_int), ("band_steps", ctypes.c_int), ("ghost_c_new", ctypes.c_int),
+                ("coarsest_n", ctypes.c_int), ("precision", ctypes.c_int), ("newton_tol", ctypes.c_double),
+                ("newton_max", ctypes.c_int), ("lin_rtol", ctypes.c_double), ("cycles_max", ctypes.c_int)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int), ("vcycles", ctypes.c_int), ("res_inf", ctypes.c_double),
+                ("rho_last", ctypes.c_double), ("rho_geo", ctypes.c_double), ("dw_rel", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_d = ctypes.c_double
+_i = ctypes.c_int
+
+
+def load():
+    """Load liblsmg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -m paper_1902_07029_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    sigs = {
+        "lsmg_default_params": (None, [ctypes.POINTER(Params)]),
+        "lsmg_last_error": (ctypes.c_char_p, []),
+        "lsmg_build_hierarchy": (_i, [_vp, ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]),
+        "lsmg_destroy_hierarchy": (None, [_vp]),
+        "lsmg_set_params": (_i, [_vp, ctypes.POINTER(Params)]),
+        "lsmg_num_levels": (_i, [_vp, ctypes.POINTER(_i)]),
+        "lsmg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_i),
+                                 ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+        "lsmg_compact_to_grid": (_i, [_vp, _i, _vp]),
+        "lsmg_ghost_table": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "lsmg_state_create": (_i, [_vp, ctypes.POINTER(_vp)]),
+        "lsmg_state_destroy": (None, [_vp]),
+        "lsmg_state_set": (_i, [_vp, _vp]),
+        "lsmg_state_get": (_i, [_vp, _vp]),
+        "lsmg_state_set_grid": (_i, [_vp, _vp, _vp]),
+        "lsmg_state_get_grid": (_i, [_vp, _vp, _vp]),
+        "lsmg_newton_cn_step": (_i, [_vp, _vp, _d, _vp, _d, _vp, _vp, ctypes.POINTER(StepStats)]),
+        "lsmg_residual": (_i, [_vp, _vp, _vp, _d, _vp, _d, _vp, _vp, _vp, ctypes.POINTER(_d)]),
+        "lsmg_set_linearization": (_i, [_vp, _vp, _d]),
+        "lsmg_level_state": (_i, [_vp, _i, _vp]),
+        "lsmg_apply_J": (_i, [_vp, _i, _vp, _vp]),
+        "lsmg_smooth": (_i, [_vp, _i, _vp, _vp, _i]),
+        "lsmg_defect": (_i, [_vp, _i, _vp, _vp, _vp, ctypes.POINTER(_d)]),
+        "lsmg_restrict": (_i, [_vp, _i, _vp, _vp]),
+        "lsmg_prolong_add": (_i, [_vp, _i, _vp, _vp]),
+        "lsmg_coarse_solve": (_i, [_vp, _vp, _vp]),
+        "lsmg_vcycle": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d)]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return [n for n in dir(load()) if n.startswith("lsmg_")]
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise LsmgError(rc, what, load().lsmg_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t):
+    assert t.dtype == torch.float64
+    return _ptr(t)
+
+
+def default_params(**overrides):
+    p = Params()
+    load().lsmg_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+class Hierarchy:
+    """A domain's grid hierarchy on the current CUDA device and stream."""
+
+    def __init__(self, phi, dim, n, lo=-1.0, hi=1.0, params=None, stream=None):
+        lib = load()
+        self.params = params if params is not None else default_params()
+        self.dim, self.n, self.lo, self.hi = dim, n, lo, hi
+        phi = phi.to(device="cuda", dtype=torch.float64).contiguous()
+        assert phi.numel() == n ** dim
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        grid = Grid(dim, n, lo, hi)
+        h = _vp()
+        _check(lib.lsmg_build_hierarchy(_f64(phi), ctypes.byref(grid), ctypes.byref(self.params),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "lsmg_build_hierarchy")
+        self._h = h
+        nl = _i()
+        _check(lib.lsmg_num_levels(h, ctypes.byref(nl)), "lsmg_num_levels")
+        self.nlev = nl.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lsmg_destroy_hierarchy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        _check(load().lsmg_set_params(self._h, ctypes.byref(params)), "lsmg_set_params")
+        self.params = params
+
+    def level_info(self, l):
+        n, h, ni, ng, nb = _i(), _d(), _i(), _i(), _i()
+        _check(load().lsmg_level_info(self._h, l, ctypes.byref(n), ctypes.byref(h), ctypes.byref(ni),
+                                      ctypes.byref(ng), ctypes.byref(nb)), "lsmg_level_info")
+        return dict(n=n.value, h=h.value, ni=ni.value, ng=ng.value, na=ni.value + ng.value, nb=nb.value)
+
+    def _vec(self, l):
+        return torch.zeros(2 * self.level_info(l)["na"], dtype=torch.float64, device="cuda")
+
+    def compact_to_grid(self, l):
+        out = torch.empty(self.level_info(l)["na"], dtype=torch.int64, device="cuda")
+        _check(load().lsmg_compact_to_grid(self._h, l, _ptr(out)), "lsmg_compact_to_grid")
+        return out
+
+    def ghost_table(self, l):
+        info = self.level_info(l)
+        ng, nst, dim = info["ng"], 3 ** self.dim, self.dim
+        st = torch.empty((ng, nst), dtype=torch.int32, device="cuda")
+        w = torch.empty((ng, nst), dtype=torch.float64, device="cuda")
+        B = torch.empty((ng, dim), dtype=torch.float64, device="cuda")
+        nrm = torch.empty((ng, dim), dtype=torch.float64, device="cuda")
+        order = torch.empty(ng, dtype=torch.int32, device="cuda")
+        bf = torch.empty(ng, dtype=torch.int32, device="cuda")
+        _check(load().lsmg_ghost_table(self._h, l, _ptr(st), _ptr(w), _ptr(B), _ptr(nrm), _ptr(order), _ptr(bf)),
+               "lsmg_ghost_table")
+        return dict(st=st, w=w, B=B, normal=nrm, order=order, bfallback=bf)
+
+    def residual(self, W, Wn, dt, sb=None, sb_const=1.0, fn=None, fnp1=None):
+        F = torch.empty_like(W)
+        nrm = _d()
+        _check(load().lsmg_residual(self._h, _f64(W), _f64(Wn), dt, _ptr(sb), sb_const, _ptr(fn), _ptr(fnp1),
+                                    _f64(F), ctypes.byref(nrm)), "lsmg_residual")
+        return F, nrm.value
+
+    def set_linearization(self, W, dt):
+        _check(load().lsmg_set_linearization(self._h, _f64(W), dt), "lsmg_set_linearization")
+
+    def level_state(self, l):
+        out = self._vec(l)
+        _check(load().lsmg_level_state(self._h, l, _f64(out)), "lsmg_level_state")
+        return out
+
+    def apply_J(self, l, x):
+        y = torch.empty_like(x)
+        _check(load().lsmg_apply_J(self._h, l, _f64(x), _f64(y)), "lsmg_apply_J")
+        return y
+
+    def smooth(self, l, rhs, x, nsweeps=1):
+        x = x.clone()
+        _check(load().lsmg_smooth(self._h, l, _f64(rhs), _f64(x), nsweeps), "lsmg_smooth")
+        return x
+
+    def defect(self, l, rhs, x):
+        r = torch.empty_like(x)
+        nrm = _d()
+        _check(load().lsmg_defect(self._h, l, _f64(rhs), _f64(x), _f64(r), ctypes.byref(nrm)), "lsmg_defect")
+        return r, nrm.value
+
+    def restrict(self, l, r):
+        rc = self._vec(l + 1)
+        _check(load().lsmg_restrict(self._h, l, _f64(r), _f64(rc)), "lsmg_restrict")
+        return rc
+
+    def prolong_add(self, l, ec, x):
+        x = x.clone()
+        _check(load().lsmg_prolong_add(self._h, l, _f64(ec), _f64(x)), "lsmg_prolong_add")
+        return x
+
+    def coarse_solve(self, rhs):
+        x = torch.empty_like(rhs)
+        _check(load().lsmg_coarse_solve(self._h, _f64(rhs), _f64(x)), "lsmg_coarse_solve")
+        return x
+
+    def vcycle(self, l, rhs, x):
+        x = x.clone()
+        nrm = _d()
+        _check(load().lsmg_vcycle(self._h, l, _f64(rhs), _f64(x), ctypes.byref(nrm)), "lsmg_vcycle")
+        return x, nrm.value
+
+
+class State:
+    """W = (s, c) on the finest active nodes of a hierarchy."""
+
+    def __init__(self, hier):
+        self.hier = hier
+        st = _vp()
+        _check(load().lsmg_state_create(hier._h, ctypes.byref(st)), "lsmg_state_create")
+        self._s = st
+
+    def close(self):
+        if getattr(self, "_s", None):
+            load().lsmg_state_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, W):
+        _check(load().lsmg_state_set(self._s, _f64(W)), "lsmg_state_set")
+
+    def get(self):
+        W = self.hier._vec(0)
+        _check(load().lsmg_state_get(self._s, _f64(W)), "lsmg_state_get")
+        return W
+
+    def set_grid(self, s, c):
+        _check(load().lsmg_state_set_grid(self._s, _f64(s), _f64(c)), "lsmg_state_set_grid")
+
+    def get_grid(self):
+        nn = self.hier.n ** self.hier.dim
+        s = torch.empty(nn, dtype=torch.float64, device="cuda")
+        c = torch.empty(nn, dtype=torch.float64, device="cuda")
+        _check(load().lsmg_state_get_grid(self._s, _f64(s), _f64(c)), "lsmg_state_get_grid")
+        return s, c
+
+    def step(self, dt, sb=None, sb_const=1.0, fn=None, fnp1=None, check=True):
+        """One Crank-Nicolson step; returns (status, stats dict)."""
+        st = StepStats()
+        rc = load().lsmg_newton_cn_step(self.hier._h, self._s, dt, _ptr(sb), sb_const, _ptr(fn), _ptr(fnp1),
+                                        ctypes.byref(st))
+        if check:
+            _check(rc, "lsmg_newton_cn_step")
+        return rc, st.as_dict()

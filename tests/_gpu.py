@@ -1,0 +1,50 @@
+"""Helpers shared by the GPU parity tests: build the GPU hierarchy and the oracle
+hierarchy of the same seeded domain with the same parameters."""
+import numpy as np
+import torch
+
+import lsmg_inputs as I
+import oracle
+from paper_1902_07029_amd import lsmg
+
+LEVELSETS = {"disk": I.disk, "star": I.star, "torus": I.torus}
+DIM = {"disk": 2, "star": 2, "torus": 3}
+
+
+def oracle_params(p):
+    return dict(a=p.a, d=p.d, m_s=p.m_s, m_c=p.m_c, alpha=p.alpha, beta=p.beta, tau_s=p.tau_s, nu1=p.nu1,
+                nu2=p.nu2, ghost_c_new=p.ghost_c_new, band_steps=p.band_steps, ghost_sweeps=p.ghost_sweeps)
+
+
+def pair(kind, n, coarsest, phi=None, **params):
+    dim = DIM[kind]
+    if phi is None:
+        phi = LEVELSETS[kind](n)
+    p = lsmg.default_params(coarsest_n=coarsest, **params)
+    H = lsmg.Hierarchy(torch.from_numpy(phi), dim, n, params=p)
+    O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=oracle_params(p))
+    return H, O
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    scale = np.max(np.abs(b)) if b.size else 0.0
+    if scale == 0.0:
+        return float(np.max(np.abs(a))) if a.size else 0.0
+    return float(np.max(np.abs(a - b)) / scale)
+
+
+def random_state(O, l, rng):
+    na = O.level_info(l)["na"]
+    return np.concatenate([rng.uniform(0.0, 1.0, na), rng.uniform(0.5, 1.5, na)])
+
+
+def say(msg):
+    print(msg, flush=True)

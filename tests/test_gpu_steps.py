@@ -1,0 +1,141 @@
+"""Whole Crank-Nicolson steps on the GPU against the oracle, advanced independently:
+after every step ||x_gpu - x_oracle||_inf / ||x_oracle||_inf <= 1e-10 for s and for c
+over the active nodes, in FP64 and in mixed precision; plus the failure paths."""
+import numpy as np
+import pytest
+import torch
+
+import lsmg_inputs as I
+from _gpu import cuda, host, pair, rel, say
+from paper_1902_07029_amd import lsmg
+
+TOL = 1e-10
+
+
+def _run(kind, n, coarsest, dt, steps, precision=0, s0=0.0, c0=1.0, **params):
+    H, O = pair(kind, n, coarsest, precision=precision, **params)
+    dim = H.dim
+    info = O.level_info(0)
+    na = info["na"]
+    s, c = I.initial_state(n, dim, s0, c0)
+    W = O.to_compact(0, s, c)
+    st = lsmg.State(H)
+    st.set(cuda(W))
+    sb = np.ones(info["ng"])
+    worst = 0.0
+    for k in range(steps):
+        rc, gstats = st.step(dt, sb_const=1.0)
+        orc, W, ostats = O.newton_cn_step(W, dt, sb)
+        assert orc == 0
+        G = host(st.get())
+        es, ec = rel(G[:na], W[:na]), rel(G[na:], W[na:])
+        say(f"{kind} n={n} prec={precision} step {k}: err s {es:.2e} c {ec:.2e} "
+            f"newton {gstats['newton_iters']}/{ostats['newton_iters']} cycles {gstats['vcycles']}/{ostats['vcycles']}")
+        assert es <= TOL and ec <= TOL, (k, es, ec)
+        worst = max(worst, es, ec)
+    return worst
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_disk_config(precision):
+    _run("disk", 65, 5, 1e-3, 10, precision)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_star_257(precision):
+    _run("star", 257, 9, 1e-4, 3, precision)
+
+
+@pytest.mark.gpu
+def test_star_1025_full_size():
+    _run("star", 1025, 9, 1e-4, 2, 0)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_torus_65(precision):
+    _run("torus", 65, 9, 1e-4, 2, precision)
+
+
+@pytest.mark.gpu
+def test_manufactured_solution_steps():
+    n = 65
+    H, O = pair("disk", n, 5)
+    info = O.level_info(0)
+    na = info["na"]
+    h = info["h"]
+    x, y = I.grid_points(n, 2)
+    g = O.compact_to_grid(0)
+    B = O.ghost_table(0)["B"]
+    W = np.concatenate([I.s_exact(x[g], y[g], 0.0), I.c_exact(x[g], y[g], 0.0)])
+    st = lsmg.State(H)
+    st.set(cuda(W))
+
+    def forcing(t):
+        f1, f2 = I.mms_sources(x[g], y[g], t)
+        return np.concatenate([f1, f2])
+
+    for k in range(4):
+        t0, t1 = k * h, (k + 1) * h
+        sb = I.s_exact(B[:, 0], B[:, 1], t1)
+        st.step(h, sb=cuda(sb), fn=cuda(forcing(t0)), fnp1=cuda(forcing(t1)))
+        rc, W, _ = O.newton_cn_step(W, h, sb, forcing(t0), forcing(t1))
+        G = host(st.get())
+        assert rel(G[:na], W[:na]) <= TOL and rel(G[na:], W[na:]) <= TOL
+
+
+@pytest.mark.gpu
+def test_nonconvergence_leaves_state():
+    H, O = pair("disk", 65, 5, newton_max=1, newton_tol=1e-300)
+    s, c = I.initial_state(65, 2)
+    W = O.to_compact(0, s, c)
+    st = lsmg.State(H)
+    st.set(cuda(W))
+    rc, _ = st.step(1e-3, check=False)
+    assert rc == lsmg.ENOCONV
+    assert np.array_equal(host(st.get()), W)
+
+
+@pytest.mark.gpu
+def test_nonfinite_state_is_reported():
+    H, O = pair("disk", 65, 5)
+    s, c = I.initial_state(65, 2)
+    W = O.to_compact(0, s, c)
+    W[3] = np.nan
+    st = lsmg.State(H)
+    st.set(cuda(W))
+    rc, _ = st.step(1e-3, check=False)
+    assert rc == lsmg.ENONFINITE
+    G = host(st.get())
+    assert np.isnan(G[3]) and np.array_equal(np.delete(G, 3), np.delete(W, 3))
+
+
+@pytest.mark.gpu
+def test_empty_domain():
+    n = 33
+    phi = np.ones(n * n)
+    H, O = pair("disk", n, 5, phi=phi)
+    assert H.level_info(0)["na"] == 0
+    st = lsmg.State(H)
+    rc, stats = st.step(1e-3)
+    assert rc == 0
+
+
+@pytest.mark.gpu
+def test_grid_state_roundtrip():
+    n = 65
+    H, O = pair("disk", n, 5)
+    rng = np.random.default_rng(0)
+    s, c = rng.uniform(0, 1, n * n), rng.uniform(0, 1, n * n)
+    st = lsmg.State(H)
+    st.set_grid(cuda(s), cuda(c))
+    gs, gc = st.get_grid()
+    gs, gc = host(gs), host(gc)
+    idx = O.compact_to_grid(0)
+    assert np.array_equal(gs[idx], s[idx]) and np.array_equal(gc[idx], c[idx])
+    mask = np.ones(n * n, bool)
+    mask[idx] = False
+    assert np.all(np.isnan(gs[mask])) and np.all(np.isnan(gc[mask]))
+    assert np.array_equal(host(st.get()), O.to_compact(0, s, c))
