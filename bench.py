@@ -1,0 +1,228 @@
+"""Benchmark of the level-set multigrid Crank-Nicolson step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star1025|torus257|disk65]
+                    [--precision 0|1] [--no-cpu-baseline]
+
+A step is one Crank-Nicolson step: Newton iterations whose linear systems are
+solved by V-cycles, on synthetic seeded inputs already resident in HBM.  The
+metric is V-cycle throughput, 2 (Ni + Ng) finest unknowns times the V-cycles
+executed in the timed steps per second.  One JSON line is printed.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import lsmg_inputs as I  # noqa: E402
+
+METRIC = "V-cycle unknowns·cycles/s at 1e-10 rel, mixed vs FP64; %HBM roofline; p99 step"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "star1025": dict(kind="star", dim=2, n=1025, coarsest=9, dt=1e-4, steps=100),
+    "torus257": dict(kind="torus", dim=3, n=257, coarsest=9, dt=1e-4, steps=20),
+    "disk65": dict(kind="disk", dim=2, n=65, coarsest=5, dt=1e-3, steps=10),
+}
+
+
+def levelset(w):
+    return {"star": I.star, "torus": I.torus, "disk": I.disk}[w["kind"]](w["n"])
+
+
+def smoother_bytes(c2g, ni, ng, n, dim, P):
+    """Algorithmic bytes of one colour launch of the collective smoother on a level:
+    reads s and c at every active node (2P each), the correction (2P) at active
+    nodes of the other colour, the right-hand side (2P) and the type byte at the
+    updated nodes, and writes the correction (2P) at the updated nodes.
+    Returned for colour 0 and colour 1."""
+    g = c2g.astype(np.int64)
+    idx = [g % n, (g // n) % n] + ([g // (n * n)] if dim == 3 else [])
+    col = sum(idx) & 1
+    out = []
+    for c in (0, 1):
+        upd = int(np.sum(col[:ni] == c))
+        other = int(np.sum(col != c))
+        out.append(2 * P * (ni + ng) + 2 * P * other + (2 * P + 1) * upd + 2 * P * upd)
+    return out
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "lsmg_dev.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1902_07029_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload, precision):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        rec = data.get(f"{kernel}:{workload}:p{precision}")
+        if rec and rec.get("source_hash") == source_hash():
+            return rec["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def cpu_baseline(w, params, budget_s, gpu_states):
+    """The oracle (serial, one core) on the first steps of the same workload; its
+    states also give a parity check of the GPU trajectory."""
+    import oracle
+    phi = levelset(w)
+    O = oracle.Hierarchy(phi, w["dim"], w["n"], coarsest_n=w["coarsest"], params=params)
+    info = O.level_info(0)
+    na = info["na"]
+    s0, c0 = I.initial_state(w["n"], w["dim"])
+    W = O.to_compact(0, s0, c0)
+    sb = np.ones(info["ng"])
+    cycles = 0
+    worst = 0.0
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < len(gpu_states):
+        rc, W, st = O.newton_cn_step(W, w["dt"], sb)
+        if rc != 0:
+            raise RuntimeError(f"oracle step failed with {rc}")
+        cycles += st["vcycles"]
+        G = gpu_states[steps]
+        for blk in (slice(0, na), slice(na, 2 * na)):
+            worst = max(worst, float(np.max(np.abs(G[blk] - W[blk])) / np.max(np.abs(W[blk]))))
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=2 * na * cycles / el, unit="unknowns*cycles/s", cores=1, kind="oracle",
+                sample=f"first {steps} Crank-Nicolson steps of {w['kind']} {w['n']}^{w['dim']} "
+                       f"({cycles} V-cycles, {el:.1f} s, serial C, one host core)"), \
+        dict(steps_checked=steps, max_rel_err=worst)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--parity-steps", type=int, default=6)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1902_07029_amd import lsmg
+
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=args.precision)
+    phi = torch.from_numpy(levelset(w)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = lsmg.Hierarchy(phi, w["dim"], w["n"], params=params)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = H.level_info(0)
+    na, ni, ng = info["na"], info["ni"], info["ng"]
+    unknowns = 2 * na
+    s0, c0 = I.initial_state(w["n"], w["dim"])
+
+    def fresh_state():
+        st = lsmg.State(H)
+        st.set_grid(torch.from_numpy(s0).cuda(), torch.from_numpy(c0).cuda())
+        return st
+
+    st = fresh_state()
+    for _ in range(args.warmup):
+        st.step(w["dt"])
+    # timed region: K steps, the dominant kernel timed by HIP events on the hierarchy's stream
+    H.profile_start(lsmg.KERNEL_SMOOTH, 0)
+    lat = []
+    cycles = 0
+    newton = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, stats = st.step(w["dt"])
+        lat.append(time.perf_counter() - ts)
+        cycles += stats["vcycles"]
+        newton += stats["newton_iters"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    launches, prof_ms = H.profile_stop()
+
+    # roofline of the dominant kernel: one colour of the finest-level smoother
+    P = 8 if args.precision == 0 else 4
+    b0, b1 = smoother_bytes(H.compact_to_grid(0).cpu().numpy(), ni, ng, w["n"], w["dim"], P)
+    bytes_per_launch = 0.5 * (b0 + b1)
+    avg_s = prof_ms * 1e-3 / max(launches, 1)
+    achieved = bytes_per_launch / avg_s / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=load_traffic("smooth_colour", args.workload, args.precision),
+                    kernel="k_smooth_colour (finest level, one colour)", launches=launches,
+                    avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(bytes_per_launch))
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        # GPU trajectory from the initial state for the parity check
+        st2 = fresh_state()
+        states = []
+        for _ in range(args.parity_steps):
+            st2.step(w["dt"])
+            states.append(st2.get().cpu().numpy())
+        op = {k: getattr(params, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
+                                               "ghost_c_new", "band_steps", "ghost_sweeps")}
+        cpu, parity = cpu_baseline(w, op, args.cpu_budget, states)
+
+    lat_ms = np.array(lat) * 1e3
+    value = unknowns * cycles / elapsed
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknowns*cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}_{'fp64' if args.precision == 0 else 'mixed'}",
+            "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": w["dt"], "coarsest": w["coarsest"],
+            "unknowns": unknowns, "inside": ni, "ghost": ng, "levels": H.nlev,
+            "cycle": f"V({params.nu1},{params.nu2}) red-black, {params.ghost_sweeps} ghost sweeps",
+            "build_ms": round(build_ms, 1),
+        },
+        "vcycles": cycles,
+        "newton_iters": newton,
+        "solution_throughput": unknowns * args.steps / elapsed,
+        "p50_step_ms": float(np.percentile(lat_ms, 50)),
+        "p99_step_ms": float(np.percentile(lat_ms, 99)),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -207,6 +207,26 @@ lsmg_status lsmg_coarse_solve(lsmg_hierarchy *h, const double *d_rhs, double *d_
  * res_inf (host, may be NULL) receives |rhs - J x|_inf after the cycle. */
 lsmg_status lsmg_vcycle(lsmg_hierarchy *h, int level, const double *d_rhs, double *d_x, double *res_inf);
 
+/* ---- launch timing ---------------------------------------------------------- */
+
+/* Kernel classes that can be timed. */
+enum {
+    LSMG_KERNEL_SMOOTH = 0,    /* one colour of the collective red-black sweep */
+    LSMG_KERNEL_DEFECT = 1,    /* defect r = rhs - J x */
+    LSMG_KERNEL_RESTRICT = 2,  /* restriction onto `level` from level - 1 */
+    LSMG_KERNEL_PROLONG = 3,   /* prolongation onto `level` from level + 1 */
+    LSMG_KERNEL_GHOST = 4      /* one ghost relaxation sweep */
+};
+
+/* Start timing every launch of `kernel` on `level` of this hierarchy: a HIP
+ * event is recorded on the hierarchy's stream before and after each launch.
+ * Synchronises the stream.  Timing adds two event records per launch. */
+lsmg_status lsmg_profile_start(lsmg_hierarchy *h, int kernel, int level);
+
+/* Stop timing; host outs: number of timed launches and the sum of their
+ * event-to-event durations in milliseconds.  Synchronises the stream. */
+lsmg_status lsmg_profile_stop(lsmg_hierarchy *h, int *launches, double *total_ms);
+
 /* Thread-local message for the last non-OK status of this thread. */
 const char *lsmg_last_error(void);
 

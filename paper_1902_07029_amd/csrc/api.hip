@@ -93,8 +93,13 @@ struct lsmg_hierarchy {
     unsigned long long *d_norms = nullptr, *h_norms = nullptr;
     int *h_status = nullptr;
     std::vector<void *> allocs;
+    // launch timing of one kernel class on one level (HIP events on the stream)
+    int prof_kernel = -1, prof_level = -1;
+    std::vector<hipEvent_t> prof_pool;
+    size_t prof_used = 0;
     ~lsmg_hierarchy()
     {
+        for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
         if (h_norms) (void)hipHostFree(h_norms);
         if (h_status) (void)hipHostFree(h_status);
@@ -218,6 +223,25 @@ double norm_value(const lsmg_hierarchy *H, int slot)
 }
 
 // ---------------------------------------------------------------------------
+// launch timing: events bracket each launch of the selected kernel class on
+// the selected level
+// ---------------------------------------------------------------------------
+inline bool prof_on(const lsmg_hierarchy *H, int kernel, int l)
+{
+    return H->prof_kernel == kernel && H->prof_level == l;
+}
+
+void prof_mark(lsmg_hierarchy *H)
+{
+    if (H->prof_used >= H->prof_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        H->prof_pool.push_back(e);
+    }
+    (void)hipEventRecord(H->prof_pool[H->prof_used++], H->stream);
+}
+
+// ---------------------------------------------------------------------------
 // V-cycle
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -232,9 +256,17 @@ void smooth_level(lsmg_hierarchy *H, int l)
 {
     const Level &Lv = H->L[l];
     const LevelDesc<T> *d = descs<T>(H);
-    launch_smooth_colour<T>(H->dim, d, Lv.w_seg(0), Lv.nseg[0], 0, H->stream);
-    launch_smooth_colour<T>(H->dim, d, Lv.w_seg(1), Lv.nseg[1], 1, H->stream);
-    for (int g = 0; g < H->p.ghost_sweeps; ++g) launch_ghost<T>(H->dim, d, Lv.w_gh(), Lv.nghc, H->stream);
+    const bool ps = prof_on(H, LSMG_KERNEL_SMOOTH, l), pg = prof_on(H, LSMG_KERNEL_GHOST, l);
+    for (int colour = 0; colour < 2; ++colour) {
+        if (ps) prof_mark(H);
+        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour, H->stream);
+        if (ps) prof_mark(H);
+    }
+    for (int g = 0; g < H->p.ghost_sweeps; ++g) {
+        if (pg) prof_mark(H);
+        launch_ghost<T>(H->dim, d, Lv.w_gh(), Lv.nghc, H->stream);
+        if (pg) prof_mark(H);
+    }
 }
 
 template <typename T>
@@ -247,12 +279,20 @@ void vcycle_rec(lsmg_hierarchy *H, int l)
         return;
     }
     for (int i = 0; i < H->p.nu1; ++i) smooth_level<T>(H, l);
+    const bool pd = prof_on(H, LSMG_KERNEL_DEFECT, l), pr = prof_on(H, LSMG_KERNEL_RESTRICT, l + 1),
+               pp = prof_on(H, LSMG_KERNEL_PROLONG, l);
+    if (pd) prof_mark(H);
     launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), nullptr, H->stream);
+    if (pd) prof_mark(H);
     launch_band<T>(d, Lv.w_band(), Lv.nbandc, H->stream);
     const Level &C = H->L[l + 1];
+    if (pr) prof_mark(H);
     launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), H->stream);
+    if (pr) prof_mark(H);
     vcycle_rec<T>(H, l + 1);
+    if (pp) prof_mark(H);
     launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), H->stream);
+    if (pp) prof_mark(H);
     for (int i = 0; i < H->p.nu2; ++i) smooth_level<T>(H, l);
 }
 
@@ -1031,6 +1071,36 @@ lsmg_status lsmg_vcycle(lsmg_hierarchy *h, int level, const double *d_rhs, doubl
         LSMGCHK(read_norms(h, 2));
         *res_inf = norm_value(h, 1);
     }
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_profile_start(lsmg_hierarchy *h, int kernel, int level)
+{
+    LSMGCHK(level_ok(h, level));
+    if (kernel < LSMG_KERNEL_SMOOTH || kernel > LSMG_KERNEL_GHOST) return fail(LSMG_EINVAL, "unknown kernel class");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->prof_kernel = kernel;
+    h->prof_level = level;
+    h->prof_used = 0;
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_profile_stop(lsmg_hierarchy *h, int *launches, double *total_ms)
+{
+    if (!h) return fail(LSMG_EINVAL, "hierarchy is NULL");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    const size_t pairs = h->prof_used / 2;
+    for (size_t i = 0; i < pairs; ++i) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, h->prof_pool[2 * i], h->prof_pool[2 * i + 1]));
+        tot += ms;
+    }
+    if (launches) *launches = (int)pairs;
+    if (total_ms) *total_ms = tot;
+    h->prof_kernel = -1;
+    h->prof_level = -1;
+    h->prof_used = 0;
     return LSMG_OK;
 }
 

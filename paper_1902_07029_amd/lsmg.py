@@ -13,6 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblsmg.so")
 
 OK, EINVAL, EGEOM, ENOCONV, ENONFINITE, EOOM, EHIP, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6, -7
+KERNEL_SMOOTH, KERNEL_DEFECT, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_GHOST = 0, 1, 2, 3, 4
 
 
 class LsmgError(RuntimeError):
@@ -85,6 +86,8 @@ def load():
         "lsmg_prolong_add": (_i, [_vp, _i, _vp, _vp]),
         "lsmg_coarse_solve": (_i, [_vp, _vp, _vp]),
         "lsmg_vcycle": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d)]),
+        "lsmg_profile_start": (_i, [_vp, _i, _i]),
+        "lsmg_profile_stop": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -230,6 +233,14 @@ class Hierarchy:
         x = torch.empty_like(rhs)
         _check(load().lsmg_coarse_solve(self._h, _f64(rhs), _f64(x)), "lsmg_coarse_solve")
         return x
+
+    def profile_start(self, kernel, level):
+        _check(load().lsmg_profile_start(self._h, kernel, level), "lsmg_profile_start")
+
+    def profile_stop(self):
+        n, ms = _i(), _d()
+        _check(load().lsmg_profile_stop(self._h, ctypes.byref(n), ctypes.byref(ms)), "lsmg_profile_stop")
+        return n.value, ms.value
 
     def vcycle(self, l, rhs, x):
         x = x.clone()
