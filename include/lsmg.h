@@ -220,7 +220,9 @@ enum {
 
 /* Start timing every launch of `kernel` on `level` of this hierarchy: a HIP
  * event is recorded on the hierarchy's stream before and after each launch.
- * Synchronises the stream.  Timing adds two event records per launch. */
+ * While timing is on, V-cycles run as direct launches rather than as a
+ * replayed graph (events inside a graph cannot be timed).  Synchronises the
+ * stream.  Timing adds two event records per launch. */
 lsmg_status lsmg_profile_start(lsmg_hierarchy *h, int kernel, int level);
 
 /* Stop timing; host outs: number of timed launches and the sum of their

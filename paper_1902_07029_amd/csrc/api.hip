@@ -8,6 +8,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -55,13 +57,19 @@ struct Level {
     int64_t *c2g = nullptr;
     double *s = nullptr, *c = nullptr, *rhs_s = nullptr, *rhs_c = nullptr, *x_s = nullptr, *x_c = nullptr,
            *r_s = nullptr, *r_c = nullptr;
-    int *g_idx = nullptr, *g_st = nullptr, *g_stc = nullptr, *g_order = nullptr, *g_bfall = nullptr;
-    double *g_w = nullptr, *g_B = nullptr, *g_nrm = nullptr, *g_tmp = nullptr, *g_old = nullptr;
+    int *g_idx = nullptr, *g_ijk = nullptr, *g_st = nullptr, *g_stg = nullptr, *g_stc = nullptr, *g_order = nullptr,
+        *g_bfall = nullptr;
+    double *g_w = nullptr, *g_B = nullptr, *g_nrm = nullptr, *g_buf0 = nullptr, *g_buf1 = nullptr;
     int *b_idx = nullptr, *b_cnt = nullptr, *b_src = nullptr;
     double *b_wt = nullptr;
     float *s32 = nullptr, *c32 = nullptr, *rhs_s32 = nullptr, *rhs_c32 = nullptr, *x_s32 = nullptr, *x_c32 = nullptr,
-          *r_s32 = nullptr, *r_c32 = nullptr, *g_w32 = nullptr, *g_tmp32 = nullptr, *g_old32 = nullptr,
+          *r_s32 = nullptr, *r_c32 = nullptr, *g_w32 = nullptr, *g_buf0_32 = nullptr, *g_buf1_32 = nullptr,
           *b_wt32 = nullptr;
+    int *in_ijk = nullptr;                      // packed coordinates of inside nodes, colour 0 then 1
+    int nin[2] = {0, 0};
+    int *go_ptr = nullptr, *go_col = nullptr;   // composed ghost relaxation (CSR over ghosts)
+    double *go_a = nullptr, *go_b = nullptr;
+    float *go_a32 = nullptr, *go_b32 = nullptr;
     int4 *items = nullptr;              // [seg colour 0 | seg colour 1 | ghost chunks | band chunks]
     int nseg[2] = {0, 0}, nghc = 0, nbandc = 0;
     const int4 *w_seg(int colour) const { return items + (colour ? nseg[0] : 0); }
@@ -87,9 +95,10 @@ struct lsmg_hierarchy {
     double dt = 0.0;
     bool lin_set = false;
     double *bs = nullptr, *bc = nullptr, *tmp_s = nullptr, *tmp_c = nullptr;
-    double *lu = nullptr;
+    double *lu = nullptr, *ainv = nullptr;
     int *piv = nullptr, *lu_status = nullptr;
     int luN = 0;
+    int tail_l0 = 0;   // first level handled by the coarse-tail kernel
     unsigned long long *d_norms = nullptr, *h_norms = nullptr;
     int *h_status = nullptr;
     std::vector<void *> allocs;
@@ -97,8 +106,21 @@ struct lsmg_hierarchy {
     int prof_kernel = -1, prof_level = -1;
     std::vector<hipEvent_t> prof_pool;
     size_t prof_used = 0;
+    double prof_acc_ms = 0.0;
+    long long prof_acc_n = 0;
+    // V-cycle graphs (0: FP64 cycle, 1: mixed-precision refinement step), captured on a private stream
+    bool use_graphs = true;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    size_t gprof_pairs[2] = {0, 0}, gprof_first[2] = {0, 0}, prof_pending = 0;
+    // composed ghost relaxation tables (CSR over ghosts), owned separately: rebuilt with the parameters
+    std::vector<void *> ghost_ops;
     ~lsmg_hierarchy()
     {
+        for (int i = 0; i < 2; ++i)
+            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (void *p : ghost_ops) (void)hipFree(p);
         for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
         if (h_norms) (void)hipHostFree(h_norms);
@@ -207,18 +229,28 @@ lsmg_status set_dt(lsmg_hierarchy *H, double dt)
     return LSMG_OK;
 }
 
+// norm k lives in kNormSlots partial slots starting at d_norms + k * kNormSlots
+unsigned long long *norm_slot(lsmg_hierarchy *H, int k) { return H->d_norms + k * kNormSlots; }
+
+void zero_norms(lsmg_hierarchy *H, int first, int count, hipStream_t s = nullptr)
+{
+    launch_zero_u64(norm_slot(H, first), count * kNormSlots, s ? s : H->stream);
+}
+
 lsmg_status read_norms(lsmg_hierarchy *H, int count)
 {
-    HIPCHK(hipMemcpyAsync(H->h_norms, H->d_norms, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost,
-                          H->stream));
+    HIPCHK(hipMemcpyAsync(H->h_norms, H->d_norms, sizeof(unsigned long long) * count * kNormSlots,
+                          hipMemcpyDeviceToHost, H->stream));
     HIPCHK(hipStreamSynchronize(H->stream));
     return LSMG_OK;
 }
 
-double norm_value(const lsmg_hierarchy *H, int slot)
+double norm_value(const lsmg_hierarchy *H, int k)
 {
+    unsigned long long m = 0;
+    for (int i = 0; i < kNormSlots; ++i) m = H->h_norms[k * kNormSlots + i] > m ? H->h_norms[k * kNormSlots + i] : m;
     double v;
-    std::memcpy(&v, &H->h_norms[slot], sizeof(double));
+    std::memcpy(&v, &m, sizeof(double));
     return v;
 }
 
@@ -231,14 +263,26 @@ inline bool prof_on(const lsmg_hierarchy *H, int kernel, int l)
     return H->prof_kernel == kernel && H->prof_level == l;
 }
 
-void prof_mark(lsmg_hierarchy *H)
+void prof_mark(lsmg_hierarchy *H, hipStream_t s)
 {
     if (H->prof_used >= H->prof_pool.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
         H->prof_pool.push_back(e);
     }
-    (void)hipEventRecord(H->prof_pool[H->prof_used++], H->stream);
+    (void)hipEventRecord(H->prof_pool[H->prof_used++], s);
+}
+
+// sum of the event pairs [first, last) into the accumulators
+void prof_collect(lsmg_hierarchy *H, size_t first, size_t last)
+{
+    for (size_t i = first; i + 1 < last; i += 2) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, H->prof_pool[i], H->prof_pool[i + 1]) == hipSuccess) {
+            H->prof_acc_ms += ms;
+            ++H->prof_acc_n;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -252,48 +296,114 @@ template <>
 const LevelDesc<float> *descs<float>(const lsmg_hierarchy *H) { return H->d32; }
 
 template <typename T>
-void smooth_level(lsmg_hierarchy *H, int l)
+void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s)
 {
     const Level &Lv = H->L[l];
     const LevelDesc<T> *d = descs<T>(H);
     const bool ps = prof_on(H, LSMG_KERNEL_SMOOTH, l), pg = prof_on(H, LSMG_KERNEL_GHOST, l);
     for (int colour = 0; colour < 2; ++colour) {
-        if (ps) prof_mark(H);
-        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour, H->stream);
-        if (ps) prof_mark(H);
+        if (ps) prof_mark(H, s);
+        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour, s);
+        if (ps) prof_mark(H, s);
     }
-    for (int g = 0; g < H->p.ghost_sweeps; ++g) {
-        if (pg) prof_mark(H);
-        launch_ghost<T>(H->dim, d, Lv.w_gh(), Lv.nghc, H->stream);
-        if (pg) prof_mark(H);
+    if (pg) prof_mark(H, s);
+    launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.ng, H->p.ghost_sweeps, Lv.go_ptr != nullptr, s);
+    if (pg) prof_mark(H, s);
+}
+
+TailArgs tail_args(const lsmg_hierarchy *H, int l0)
+{
+    TailArgs a{};
+    a.l0 = l0;
+    a.nlev = H->nlev;
+    a.nu1 = H->p.nu1;
+    a.nu2 = H->p.nu2;
+    a.ghost_sweeps = H->p.ghost_sweeps;
+    a.c2s = H->L[H->nlev - 1].c2s;
+    a.ainv = H->ainv;
+    for (int l = 0; l < H->nlev; ++l) {
+        const Level &Lv = H->L[l];
+        a.lev[l].in_ijk = Lv.in_ijk;
+        a.lev[l].nin0 = Lv.nin[0];
+        a.lev[l].nin1 = Lv.nin[1];
     }
+    return a;
 }
 
 template <typename T>
-void vcycle_rec(lsmg_hierarchy *H, int l)
+void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
 {
     const Level &Lv = H->L[l];
     const LevelDesc<T> *d = descs<T>(H);
-    if (l == H->nlev - 1) {
-        launch_coarse_solve<T>(d, l, 2 * Lv.na, Lv.c2s, H->lu, H->piv, H->stream);
+    if (l >= H->tail_l0) {
+        // this level and every coarser one in one workgroup
+        launch_tail<T>(H->dim, d, tail_args(H, l), H->L[H->nlev - 1].na, s);
         return;
     }
-    for (int i = 0; i < H->p.nu1; ++i) smooth_level<T>(H, l);
+    for (int i = 0; i < H->p.nu1; ++i) smooth_level<T>(H, l, s);
     const bool pd = prof_on(H, LSMG_KERNEL_DEFECT, l), pr = prof_on(H, LSMG_KERNEL_RESTRICT, l + 1),
                pp = prof_on(H, LSMG_KERNEL_PROLONG, l);
-    if (pd) prof_mark(H);
-    launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), nullptr, H->stream);
-    if (pd) prof_mark(H);
-    launch_band<T>(d, Lv.w_band(), Lv.nbandc, H->stream);
+    if (pd) prof_mark(H, s);
+    launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), nullptr, s);
+    if (pd) prof_mark(H, s);
+    launch_band<T>(d, Lv.w_band(), Lv.nbandc, s);
     const Level &C = H->L[l + 1];
-    if (pr) prof_mark(H);
-    launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), H->stream);
-    if (pr) prof_mark(H);
-    vcycle_rec<T>(H, l + 1);
-    if (pp) prof_mark(H);
-    launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), H->stream);
-    if (pp) prof_mark(H);
-    for (int i = 0; i < H->p.nu2; ++i) smooth_level<T>(H, l);
+    if (pr) prof_mark(H, s);
+    launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), s);
+    if (pr) prof_mark(H, s);
+    vcycle_rec<T>(H, l + 1, s);
+    if (pp) prof_mark(H, s);
+    launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), s);
+    if (pp) prof_mark(H, s);
+    for (int i = 0; i < H->p.nu2; ++i) smooth_level<T>(H, l, s);
+}
+
+// one linear-solve iteration on level 0: a V-cycle on the correction (FP64), or
+// an FP32 V-cycle on the current FP64 defect added to the FP64 correction; then
+// the FP64 defect and its norm in slot 1
+void cycle_enqueue(lsmg_hierarchy *H, bool mixed, hipStream_t s)
+{
+    const Level &L0 = H->L[0];
+    zero_norms(H, 1, 1, s);
+    if (!mixed) {
+        vcycle_rec<double>(H, 0, s);
+    } else {
+        launch_to_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), 1, s);
+        vcycle_rec<float>(H, 0, s);
+        launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), s);
+    }
+    launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), norm_slot(H, 1), s);
+}
+
+void invalidate_graphs(lsmg_hierarchy *H)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (H->gexec[i]) (void)hipGraphExecDestroy(H->gexec[i]);
+        H->gexec[i] = nullptr;
+        H->gprof_pairs[i] = 0;
+    }
+}
+
+// capture the cycle of precision `mixed` once; replays run on the hierarchy's stream
+lsmg_status cycle_graph(lsmg_hierarchy *H, bool mixed, hipGraphExec_t *out)
+{
+    const int gi = mixed ? 1 : 0;
+    if (!H->gexec[gi]) {
+        if (!H->cap) HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
+        const size_t first = H->prof_used;
+        HIPCHK(hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal));
+        cycle_enqueue(H, mixed, H->cap);
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(H->cap, &g));
+        hipError_t e = hipGraphInstantiate(&H->gexec[gi], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(LSMG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        H->gprof_first[gi] = first;
+        H->gprof_pairs[gi] = (H->prof_used - first) / 2;
+        H->prof_pending = H->prof_used;
+    }
+    *out = H->gexec[gi];
+    return LSMG_OK;
 }
 
 // linearisation on every level from level 0's (s, c); factors the coarsest operator
@@ -309,7 +419,7 @@ lsmg_status linearize(lsmg_hierarchy *H)
             launch_to_f32(H->dim, H->d64, H->d32, Lv.w_act(), Lv.nw_act(), 0, H->stream);
         }
     const Level &Lc = H->L[H->nlev - 1];
-    launch_coarse_factor(H->dim, H->d64, H->nlev - 1, Lc.c2s, H->lu, H->piv, H->lu_status, H->stream);
+    launch_coarse_factor(H->dim, H->d64, H->nlev - 1, 2 * Lc.na, Lc.c2s, H->lu, H->ainv, H->lu_status, H->stream);
     H->lin_set = true;
     return LSMG_OK;
 }
@@ -347,9 +457,14 @@ lsmg_status build_level_arrays(lsmg_hierarchy *H, int l, const double *phi, uint
     if (ni > 0) compact_flags(fin, nn, Lv.c2g, scratch, nscratch, H->stream);
     if (ng > 0) compact_flags(fgh, nn, Lv.c2g + ni, scratch, nscratch, H->stream);
     launch_c2s(dim, Lv.c2g, Lv.na, Lv.n, Lv.Wp, Lv.cs, Lv.c2s, Lv.cmap, H->stream);
+    LSMGCHK(H->alloc(&Lv.in_ijk, ni));
+    if (build_inside_lists(dim, Lv.c2g, ni, Lv.n, Lv.in_ijk, Lv.nin, scratch, nscratch, H->stream) != 0)
+        return fail(LSMG_EHIP, "inside-node lists failed on level %d", l);
     // ghost geometry
     const int nst = H->nst;
     LSMGCHK(H->alloc(&Lv.g_idx, ng));
+    LSMGCHK(H->alloc(&Lv.g_ijk, ng));
+    LSMGCHK(H->alloc(&Lv.g_stg, (long long)ng * nst));
     LSMGCHK(H->alloc(&Lv.g_st, (long long)ng * nst));
     LSMGCHK(H->alloc(&Lv.g_stc, (long long)ng * nst));
     LSMGCHK(H->alloc(&Lv.g_w, (long long)ng * nst));
@@ -357,10 +472,11 @@ lsmg_status build_level_arrays(lsmg_hierarchy *H, int l, const double *phi, uint
     LSMGCHK(H->alloc(&Lv.g_nrm, (long long)ng * dim));
     LSMGCHK(H->alloc(&Lv.g_order, ng));
     LSMGCHK(H->alloc(&Lv.g_bfall, ng));
-    LSMGCHK(H->zalloc(&Lv.g_tmp, ng));
-    LSMGCHK(H->zalloc(&Lv.g_old, ng));
-    launch_ghost_geometry(dim, l, phi, Lv.type, Lv.c2g + ni, Lv.cmap, ng, Lv.n, Lv.Wp, Lv.cs, H->lo, Lv.h, Lv.g_idx,
-                          Lv.g_st, Lv.g_stc, Lv.g_w, Lv.g_B, Lv.g_nrm, Lv.g_order, Lv.g_bfall, err, H->stream);
+    LSMGCHK(H->zalloc(&Lv.g_buf0, ng));
+    LSMGCHK(H->zalloc(&Lv.g_buf1, ng));
+    launch_ghost_geometry(dim, l, phi, Lv.type, Lv.c2g + ni, Lv.cmap, ni, ng, Lv.n, Lv.Wp, Lv.cs, H->lo, Lv.h,
+                          Lv.g_idx, Lv.g_ijk, Lv.g_st, Lv.g_stg, Lv.g_stc, Lv.g_w, Lv.g_B, Lv.g_nrm, Lv.g_order,
+                          Lv.g_bfall, err, H->stream);
     launch_ghost_ext(ng, Lv.g_idx, Lv.ext, H->stream);
     // vectors
     LSMGCHK(H->zalloc(&Lv.s, Lv.ssize));
@@ -464,13 +580,103 @@ lsmg_status build_f32(lsmg_hierarchy *H)
         LSMGCHK(H->zalloc(&Lv.r_s32, Lv.ssize));
         LSMGCHK(H->zalloc(&Lv.r_c32, Lv.ssize));
         LSMGCHK(H->alloc(&Lv.g_w32, (long long)Lv.ng * H->nst));
-        LSMGCHK(H->zalloc(&Lv.g_tmp32, Lv.ng));
-        LSMGCHK(H->zalloc(&Lv.g_old32, Lv.ng));
+        LSMGCHK(H->zalloc(&Lv.g_buf0_32, Lv.ng));
+        LSMGCHK(H->zalloc(&Lv.g_buf1_32, Lv.ng));
         launch_convert<float, double>(Lv.g_w32, Lv.g_w, (long long)Lv.ng * H->nst, H->stream);
         LSMGCHK(H->zalloc(&Lv.b_wt32, (long long)Lv.nb * (Lv.bmax > 0 ? Lv.bmax : 1)));
         if (Lv.nb > 0) launch_convert<float, double>(Lv.b_wt32, Lv.b_wt, (long long)Lv.nb * Lv.bmax, H->stream);
     }
     H->have32 = true;
+    return LSMG_OK;
+}
+
+// ghost_sweeps Jacobi sweeps of eq. (RelGhost) with the inside values fixed are
+// the linear map  ds <- M ds + tau b,  M = I - tau W_GG, W_GG the boundary-row
+// weights between ghosts.  After S sweeps ds = M^S ds0 + tau sum_{i<S} M^i b.
+// Both matrices depend on the geometry and tau only; their rows are composed
+// here once and stored as one CSR table with two value arrays.
+lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
+{
+    Level &Lv = H->L[l];
+    for (void *p : {(void *)Lv.go_ptr, (void *)Lv.go_col, (void *)Lv.go_a, (void *)Lv.go_b, (void *)Lv.go_a32,
+                    (void *)Lv.go_b32}) {
+        if (!p) continue;
+        (void)hipFree(p);
+        for (auto &q : H->ghost_ops)
+            if (q == p) q = nullptr;
+    }
+    Lv.go_ptr = Lv.go_col = nullptr;
+    Lv.go_a = Lv.go_b = nullptr;
+    Lv.go_a32 = Lv.go_b32 = nullptr;
+    const int ng = Lv.ng, nst = H->nst, S = H->p.ghost_sweeps;
+    if (ng == 0 || !H->p.ghost_c_new) return LSMG_OK;
+    std::vector<int> stg((size_t)ng * nst);
+    std::vector<double> w((size_t)ng * nst);
+    HIPCHK(hipMemcpyAsync(stg.data(), Lv.g_stg, sizeof(int) * stg.size(), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipMemcpyAsync(w.data(), Lv.g_w, sizeof(double) * w.size(), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    const double tau = H->p.tau_s;
+    std::vector<int> ptr(ng + 1, 0), col;
+    std::vector<double> va, vb;
+    std::vector<double> cur(ng, 0.0), nxt(ng, 0.0), acc(ng, 0.0);
+    std::vector<char> in_cur(ng, 0), in_nxt(ng, 0), in_acc(ng, 0);
+    std::vector<int> lcur, lnxt, lacc;
+    for (int q = 0; q < ng; ++q) {
+        lcur.assign(1, q);
+        cur[q] = 1.0;
+        in_cur[q] = 1;
+        for (int it = 0; it < S; ++it) {
+            for (int p : lcur) {
+                if (!in_acc[p]) { in_acc[p] = 1; lacc.push_back(p); }
+                acc[p] += cur[p];
+            }
+            // row vector times M: nxt = cur - tau cur W
+            for (int p : lcur) {
+                if (!in_nxt[p]) { in_nxt[p] = 1; lnxt.push_back(p); }
+                nxt[p] += cur[p];
+                for (int k = 0; k < nst; ++k) {
+                    const int j = stg[(size_t)k * ng + p];
+                    if (j < 0) continue;
+                    if (!in_nxt[j]) { in_nxt[j] = 1; lnxt.push_back(j); }
+                    nxt[j] -= tau * cur[p] * w[(size_t)k * ng + p];
+                }
+            }
+            for (int p : lcur) { cur[p] = 0.0; in_cur[p] = 0; }
+            lcur.swap(lnxt);
+            lnxt.clear();
+            for (int p : lcur) { cur[p] = nxt[p]; nxt[p] = 0.0; in_nxt[p] = 0; in_cur[p] = 1; }
+        }
+        // union of the supports, sorted by ghost index
+        std::vector<int> cols(lcur);
+        for (int p : lacc)
+            if (!in_cur[p]) cols.push_back(p);
+        std::sort(cols.begin(), cols.end());
+        for (int c : cols) {
+            col.push_back(c);
+            va.push_back(in_cur[c] ? cur[c] : 0.0);
+            vb.push_back(in_acc[c] ? tau * acc[c] : 0.0);
+        }
+        ptr[q + 1] = (int)col.size();
+        for (int p : lcur) { cur[p] = 0.0; in_cur[p] = 0; }
+        for (int p : lacc) { acc[p] = 0.0; in_acc[p] = 0; }
+        lcur.clear();
+        lacc.clear();
+    }
+    const size_t nnz = col.size();
+    std::vector<float> va32(va.begin(), va.end()), vb32(vb.begin(), vb.end());
+    auto up = [&](void **dst, const void *src, size_t bytes) -> lsmg_status {
+        if (hipMalloc(dst, bytes ? bytes : 1) != hipSuccess) return fail(LSMG_EOOM, "ghost operator allocation");
+        H->ghost_ops.push_back(*dst);
+        if (bytes) HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, H->stream));
+        return LSMG_OK;
+    };
+    LSMGCHK(up((void **)&Lv.go_ptr, ptr.data(), sizeof(int) * ptr.size()));
+    LSMGCHK(up((void **)&Lv.go_col, col.data(), sizeof(int) * nnz));
+    LSMGCHK(up((void **)&Lv.go_a, va.data(), sizeof(double) * nnz));
+    LSMGCHK(up((void **)&Lv.go_b, vb.data(), sizeof(double) * nnz));
+    LSMGCHK(up((void **)&Lv.go_a32, va32.data(), sizeof(float) * nnz));
+    LSMGCHK(up((void **)&Lv.go_b32, vb32.data(), sizeof(float) * nnz));
+    HIPCHK(hipStreamSynchronize(H->stream));
     return LSMG_OK;
 }
 
@@ -487,7 +693,9 @@ void make_descs(lsmg_hierarchy *H)
         D.type = Lv.type; D.ext = Lv.ext; D.cmap = Lv.cmap;
         D.s = Lv.s; D.c = Lv.c; D.rhs_s = Lv.rhs_s; D.rhs_c = Lv.rhs_c; D.x_s = Lv.x_s; D.x_c = Lv.x_c;
         D.r_s = Lv.r_s; D.r_c = Lv.r_c;
-        D.g_idx = Lv.g_idx; D.g_st = Lv.g_st; D.g_w = Lv.g_w; D.g_tmp = Lv.g_tmp; D.g_old = Lv.g_old;
+        D.g_idx = Lv.g_idx; D.g_ijk = Lv.g_ijk; D.g_st = Lv.g_st; D.g_stg = Lv.g_stg; D.g_w = Lv.g_w;
+        D.g_buf0 = Lv.g_buf0; D.g_buf1 = Lv.g_buf1;
+        D.go_ptr = Lv.go_ptr; D.go_col = Lv.go_col; D.go_a = Lv.go_a; D.go_b = Lv.go_b;
         D.b_idx = Lv.b_idx; D.b_cnt = Lv.b_cnt; D.b_src = Lv.b_src; D.b_wt = Lv.b_wt;
         LevelDesc<float> &E = H->hd32[l];
         E.dim = D.dim; E.n = D.n; E.Wp = D.Wp; E.nst = D.nst;
@@ -496,7 +704,9 @@ void make_descs(lsmg_hierarchy *H)
         E.type = D.type; E.ext = D.ext; E.cmap = D.cmap;
         E.s = Lv.s32; E.c = Lv.c32; E.rhs_s = Lv.rhs_s32; E.rhs_c = Lv.rhs_c32; E.x_s = Lv.x_s32; E.x_c = Lv.x_c32;
         E.r_s = Lv.r_s32; E.r_c = Lv.r_c32;
-        E.g_idx = D.g_idx; E.g_st = D.g_st; E.g_w = Lv.g_w32; E.g_tmp = Lv.g_tmp32; E.g_old = Lv.g_old32;
+        E.g_idx = D.g_idx; E.g_ijk = D.g_ijk; E.g_st = D.g_st; E.g_stg = D.g_stg; E.g_w = Lv.g_w32;
+        E.g_buf0 = Lv.g_buf0_32; E.g_buf1 = Lv.g_buf1_32;
+        E.go_ptr = Lv.go_ptr; E.go_col = Lv.go_col; E.go_a = Lv.go_a32; E.go_b = Lv.go_b32;
         E.b_idx = D.b_idx; E.b_cnt = D.b_cnt; E.b_src = D.b_src; E.b_wt = Lv.b_wt32;
     }
 }
@@ -516,6 +726,7 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
         if (nlev > 16) return fail(LSMG_EINVAL, "too many levels");
     }
     if (nl != H->p.coarsest_n) return fail(LSMG_EINVAL, "n - 1 must be (coarsest_n - 1) * 2^k");
+    if (g->n > (dim == 2 ? 2048 : 1024)) return fail(LSMG_EINVAL, "n too large (2-D: 2048, 3-D: 1024 at most)");
     H->nlev = nlev;
     H->L.assign(nlev, Level{});
     nl = g->n;
@@ -575,6 +786,7 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     if (herr & 1) return fail(LSMG_EGEOM, "an inside node lies on the box edge");
     if (herr & 2) return fail(LSMG_EGEOM, "a finest-level ghost's boundary point lies outside its stencil");
     for (int l = 0; l < nlev; ++l) LSMGCHK(build_items(H, l));
+    for (int l = 0; l < nlev; ++l) LSMGCHK(build_ghost_ops(H, l));
     // Newton work arrays, coarsest LU, norms
     const Level &L0 = H->L[0];
     LSMGCHK(H->zalloc(&H->bs, L0.ssize));
@@ -582,11 +794,15 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     LSMGCHK(H->zalloc(&H->tmp_s, L0.ssize));
     LSMGCHK(H->zalloc(&H->tmp_c, L0.ssize));
     H->luN = 2 * H->L[nlev - 1].na;
-    LSMGCHK(H->alloc(&H->lu, (long long)H->luN * H->luN));
+    if (H->luN > 1024) return fail(LSMG_EINVAL, "coarsest grid has more than 512 active nodes; use a smaller coarsest_n");
+    LSMGCHK(H->alloc(&H->lu, 2LL * H->luN * H->luN));
+    LSMGCHK(H->alloc(&H->ainv, (long long)H->luN * H->luN));
+    H->tail_l0 = nlev - 1;
+    while (H->tail_l0 > 0 && H->L[H->tail_l0 - 1].na <= kTailMaxNodes) --H->tail_l0;
     LSMGCHK(H->alloc(&H->piv, H->luN));
     LSMGCHK(H->zalloc(&H->lu_status, 1));
-    LSMGCHK(H->zalloc(&H->d_norms, 16));
-    HIPCHK(hipHostMalloc(&H->h_norms, sizeof(unsigned long long) * 16, hipHostMallocDefault));
+    LSMGCHK(H->zalloc(&H->d_norms, 4 * kNormSlots));
+    HIPCHK(hipHostMalloc(&H->h_norms, sizeof(unsigned long long) * 4 * kNormSlots, hipHostMallocDefault));
     HIPCHK(hipHostMalloc(&H->h_status, sizeof(int), hipHostMallocDefault));
     if (H->p.precision == 1) LSMGCHK(build_f32(H));
     LSMGCHK(H->alloc(&H->d64, nlev));
@@ -637,18 +853,23 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
         // r = F - J 0 in FP64
         launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), nullptr, H->stream);
     }
+    hipGraphExec_t ge = nullptr;
+    // events recorded inside a graph cannot be timed: while launch timing is on,
+    // cycles run as direct launches
+    if (H->use_graphs && H->prof_kernel < 0) LSMGCHK(cycle_graph(H, mixed, &ge));
+    const int gi = mixed ? 1 : 0;
     for (int q = 0; q < H->p.cycles_max; ++q) {
         if (rprev <= H->p.lin_rtol * nF) break;
-        launch_zero_u64(H->d_norms + 1, 1, H->stream);
-        if (!mixed) {
-            vcycle_rec<double>(H, 0);
-        } else {
-            launch_to_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), 1, H->stream);
-            vcycle_rec<float>(H, 0);
-            launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), H->stream);
-        }
-        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), H->d_norms + 1, H->stream);
+        const size_t mark0 = H->prof_used;
+        if (ge) HIPCHK(hipGraphLaunch(ge, H->stream));
+        else cycle_enqueue(H, mixed, H->stream);
         LSMGCHK(read_norms(H, 2));
+        if (ge) {
+            prof_collect(H, H->gprof_first[gi], H->gprof_first[gi] + 2 * H->gprof_pairs[gi]);
+        } else {
+            prof_collect(H, mark0, H->prof_used);
+            H->prof_used = mark0;
+        }
         const double rq = norm_value(H, 1);
         ++*cycles;
         *rho_last = rprev > 0.0 ? rq / rprev : 0.0;
@@ -720,6 +941,8 @@ lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid
     if (!H) return fail(LSMG_EOOM, "host allocation");
     H->p = *params;
     H->stream = (hipStream_t)stream;
+    // LSMG_GRAPHS=0 replays the V-cycle as direct launches instead of a captured graph
+    if (const char *e = std::getenv("LSMG_GRAPHS")) H->use_graphs = std::atoi(e) != 0;
     lsmg_status st = build(H, d_levelset, grid);
     if (st != LSMG_OK) {
         (void)hipStreamSynchronize(H->stream);
@@ -743,12 +966,17 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
     LSMGCHK(check_params(params));
     if (params->coarsest_n != h->p.coarsest_n || params->band_steps != h->p.band_steps)
         return fail(LSMG_EINVAL, "coarsest_n and band_steps are fixed at build");
+    const bool ghost_ops_change = params->ghost_sweeps != h->p.ghost_sweeps || params->tau_s != h->p.tau_s ||
+                                  params->ghost_c_new != h->p.ghost_c_new;
+    invalidate_graphs(h);
     if (params->precision == 1 && !h->have32) {
         h->p.precision = 1;
         LSMGCHK(build_f32(h));
-        make_descs(h);
     }
     h->p = *params;
+    if (ghost_ops_change)
+        for (int l = 0; l < h->nlev; ++l) LSMGCHK(build_ghost_ops(h, l));
+    make_descs(h);
     return push_desc(h);
 }
 
@@ -889,8 +1117,8 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
     HIPCHK(hipMemcpyAsync(L0.c, st->c, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
     const StepArgsHost A = step_args(h, st->s, st->c, d_sb, sb_const, d_fn, d_fnp1);
     launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, s);
-    launch_zero_u64(h->d_norms, 4, s);
-    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->d_norms, s);
+    zero_norms(h, 0, 4);
+    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, norm_slot(h, 0), s);
     LSMGCHK(read_norms(h, 1));
     double nF = norm_value(h, 0);
     lsmg_status rc = LSMG_ENOCONV;
@@ -904,9 +1132,9 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
         LSMGCHK(linearize(h));
         LSMGCHK(check_factor(h));
         LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho));
-        launch_zero_u64(h->d_norms, 4, s);
-        launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), h->d_norms + 2, h->d_norms + 3, s);
-        launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->d_norms, s);
+        zero_norms(h, 0, 4);
+        launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), norm_slot(h, 2), norm_slot(h, 3), s);
+        launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, norm_slot(h, 0), s);
         LSMGCHK(read_norms(h, 4));
         nF = norm_value(h, 0);
         const double nD = norm_value(h, 2), nW = norm_value(h, 3);
@@ -948,8 +1176,8 @@ lsmg_status lsmg_residual(lsmg_hierarchy *h, const double *d_W, const double *d_
     scatter<double>(h, 0, d_Wn, h->tmp_s, h->tmp_c);
     const StepArgsHost A = step_args(h, h->tmp_s, h->tmp_c, d_sb, sb_const, d_fn, d_fnp1);
     launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->stream);
-    launch_zero_u64(h->d_norms, 1, h->stream);
-    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->d_norms, h->stream);
+    zero_norms(h, 0, 1);
+    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, norm_slot(h, 0), h->stream);
     gather<double>(h, 0, L0.rhs_s, L0.rhs_c, d_F);
     h->lin_set = false;
     if (res_inf) {
@@ -995,7 +1223,7 @@ lsmg_status lsmg_smooth(lsmg_hierarchy *h, int level, const double *d_rhs, doubl
     const Level &Lv = h->L[level];
     scatter<double>(h, level, d_rhs, Lv.rhs_s, Lv.rhs_c);
     scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
-    for (int i = 0; i < nsweeps; ++i) smooth_level<double>(h, level);
+    for (int i = 0; i < nsweeps; ++i) smooth_level<double>(h, level, h->stream);
     gather<double>(h, level, Lv.x_s, Lv.x_c, d_x);
     return LSMG_OK;
 }
@@ -1008,8 +1236,8 @@ lsmg_status lsmg_defect(lsmg_hierarchy *h, int level, const double *d_rhs, const
     const Level &Lv = h->L[level];
     scatter<double>(h, level, d_rhs, Lv.rhs_s, Lv.rhs_c);
     scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
-    launch_zero_u64(h->d_norms + 1, 1, h->stream);
-    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), h->d_norms + 1, h->stream);
+    zero_norms(h, 1, 1);
+    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), norm_slot(h, 1), h->stream);
     if (d_r) gather<double>(h, level, Lv.r_s, Lv.r_c, d_r);
     if (res_inf) {
         LSMGCHK(read_norms(h, 2));
@@ -1051,7 +1279,7 @@ lsmg_status lsmg_coarse_solve(lsmg_hierarchy *h, const double *d_rhs, double *d_
     const int lc = h->nlev - 1;
     const Level &Lc = h->L[lc];
     scatter<double>(h, lc, d_rhs, Lc.rhs_s, Lc.rhs_c);
-    launch_coarse_solve<double>(h->d64, lc, 2 * Lc.na, Lc.c2s, h->lu, h->piv, h->stream);
+    launch_coarse_apply<double>(h->d64, lc, 2 * Lc.na, Lc.c2s, h->ainv, h->stream);
     gather<double>(h, lc, Lc.x_s, Lc.x_c, d_x);
     return LSMG_OK;
 }
@@ -1063,9 +1291,9 @@ lsmg_status lsmg_vcycle(lsmg_hierarchy *h, int level, const double *d_rhs, doubl
     const Level &Lv = h->L[level];
     scatter<double>(h, level, d_rhs, Lv.rhs_s, Lv.rhs_c);
     scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
-    vcycle_rec<double>(h, level);
-    launch_zero_u64(h->d_norms + 1, 1, h->stream);
-    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), h->d_norms + 1, h->stream);
+    vcycle_rec<double>(h, level, h->stream);
+    zero_norms(h, 1, 1);
+    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), norm_slot(h, 1), h->stream);
     gather<double>(h, level, Lv.x_s, Lv.x_c, d_x);
     if (res_inf) {
         LSMGCHK(read_norms(h, 2));
@@ -1079,9 +1307,13 @@ lsmg_status lsmg_profile_start(lsmg_hierarchy *h, int kernel, int level)
     LSMGCHK(level_ok(h, level));
     if (kernel < LSMG_KERNEL_SMOOTH || kernel > LSMG_KERNEL_GHOST) return fail(LSMG_EINVAL, "unknown kernel class");
     HIPCHK(hipStreamSynchronize(h->stream));
+    invalidate_graphs(h);
     h->prof_kernel = kernel;
     h->prof_level = level;
     h->prof_used = 0;
+    h->prof_pending = 0;
+    h->prof_acc_ms = 0.0;
+    h->prof_acc_n = 0;
     return LSMG_OK;
 }
 
@@ -1089,18 +1321,14 @@ lsmg_status lsmg_profile_stop(lsmg_hierarchy *h, int *launches, double *total_ms
 {
     if (!h) return fail(LSMG_EINVAL, "hierarchy is NULL");
     HIPCHK(hipStreamSynchronize(h->stream));
-    double tot = 0.0;
-    const size_t pairs = h->prof_used / 2;
-    for (size_t i = 0; i < pairs; ++i) {
-        float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, h->prof_pool[2 * i], h->prof_pool[2 * i + 1]));
-        tot += ms;
-    }
-    if (launches) *launches = (int)pairs;
-    if (total_ms) *total_ms = tot;
+    prof_collect(h, h->prof_pending, h->prof_used);
+    if (launches) *launches = (int)h->prof_acc_n;
+    if (total_ms) *total_ms = h->prof_acc_ms;
     h->prof_kernel = -1;
     h->prof_level = -1;
     h->prof_used = 0;
+    h->prof_pending = 0;
+    invalidate_graphs(h);
     return LSMG_OK;
 }
 

@@ -159,41 +159,91 @@ __global__ void k_c2s(int dim, const int64_t *__restrict__ c2g, int na, int n, i
 }
 
 // ---------------------------------------------------------------------------
-// work segments of inside nodes: per (colour, row) the range [pmin, pmax] of
-// inside positions cut into pieces of at most 64
+// work segments of inside nodes: per (colour, row) every maximal run of
+// consecutive inside positions, cut into pieces of at most 64, so a segment
+// holds inside nodes only
 // ---------------------------------------------------------------------------
 __global__ void k_seg_count(const uint8_t *__restrict__ type, long long rows, int Wp, long long cs,
-                            int64_t *__restrict__ cnt, int *__restrict__ pmin)
+                            int64_t *__restrict__ cnt)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * rows) return;
     const long long colour = t / rows, row = t - colour * rows;
     const uint8_t *rp = type + colour * cs + row * Wp;
-    int lo = -1, hi = -1;
-    for (int p = 0; p < Wp; ++p)
-        if (rp[p] == kIn) {
-            if (lo < 0) lo = p;
-            hi = p;
-        }
-    cnt[t] = lo < 0 ? 0 : (hi - lo + kWave) / kWave;
-    pmin[t] = lo;
-    if (lo >= 0) pmin[t + 2 * rows] = hi;
+    long long c = 0;
+    int p = 0;
+    while (p < Wp) {
+        if (rp[p] != kIn) { ++p; continue; }
+        int e = p;
+        while (e < Wp && rp[e] == kIn) ++e;
+        c += (e - p + kWave - 1) / kWave;
+        p = e;
+    }
+    cnt[t] = c;
 }
 
-__global__ void k_seg_emit(long long rows, const int64_t *__restrict__ offs, const int *__restrict__ pmin, int desc,
-                           int4 *__restrict__ items)
+__global__ void k_seg_emit(const uint8_t *__restrict__ type, long long rows, int Wp, long long cs,
+                           const int64_t *__restrict__ offs, int desc, int4 *__restrict__ items)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * rows) return;
     const long long colour = t / rows, row = t - colour * rows;
-    const int lo = pmin[t];
-    if (lo < 0) return;
-    const int hi = pmin[t + 2 * rows];
+    const uint8_t *rp = type + colour * cs + row * Wp;
     long long o = offs[t];
-    for (int p = lo; p <= hi; p += kWave) {
-        const int e = p + kWave <= hi + 1 ? p + kWave : hi + 1;
-        items[o++] = make_int4((desc << 2) | (int)colour, (int)row, p, e);
+    int p = 0;
+    while (p < Wp) {
+        if (rp[p] != kIn) { ++p; continue; }
+        int e = p;
+        while (e < Wp && rp[e] == kIn) ++e;
+        for (int b = p; b < e; b += kWave) items[o++] = make_int4((desc << 2) | (int)colour, (int)row, b, b + kWave < e ? b + kWave : e);
+        p = e;
     }
+}
+
+// packed coordinates i | j << 11 | k << 22 of the inside nodes of one colour,
+// in lexicographic order
+__global__ void k_colour_flags(const int64_t *__restrict__ c2g, int ni, int n, int dim, int colour,
+                               uint8_t *__restrict__ flags)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ni) return;
+    const long long g = c2g[r];
+    const int i = (int)(g % n), j = (int)((g / n) % n), k = dim == 3 ? (int)(g / ((long long)n * n)) : 0;
+    flags[r] = ((i + j + k) & 1) == colour;
+}
+
+__global__ void k_pack_ijk(const int64_t *__restrict__ c2g, const int64_t *__restrict__ sel, int cnt, int n, int dim,
+                           int *__restrict__ out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const long long g = c2g[sel[t]];
+    const int i = (int)(g % n), j = (int)((g / n) % n), k = dim == 3 ? (int)(g / ((long long)n * n)) : 0;
+    out[t] = i | (j << 11) | (k << 22);
+}
+
+int build_inside_lists(int dim, const int64_t *c2g, int ni, int n, int *out, int *count, int64_t *scratch,
+                       int nscratch, hipStream_t s)
+{
+    count[0] = count[1] = 0;
+    if (ni <= 0) return 0;
+    uint8_t *flags = nullptr;
+    int64_t *sel = nullptr;
+    if (hipMalloc(&flags, ni) != hipSuccess) return -1;
+    if (hipMalloc(&sel, sizeof(int64_t) * ni) != hipSuccess) { (void)hipFree(flags); return -1; }
+    int off = 0;
+    for (int colour = 0; colour < 2; ++colour) {
+        k_colour_flags<<<(ni + 255) / 256, 256, 0, s>>>(c2g, ni, n, dim, colour, flags);
+        const int c = compact_flags(flags, ni, sel, scratch, nscratch, s);
+        if (c < 0) { off = -1; break; }
+        if (c > 0) k_pack_ijk<<<(c + 255) / 256, 256, 0, s>>>(c2g, sel, c, n, dim, out + off);
+        count[colour] = c;
+        off += c;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(flags);
+    (void)hipFree(sel);
+    return off < 0 ? -1 : 0;
 }
 
 void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows, long long cs, int desc,
@@ -202,13 +252,11 @@ void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows,
     (void)dim;
     (void)n;
     int64_t *cnt = nullptr;
-    int *pmin = nullptr;
     out_items[0] = out_items[1] = nullptr;
     out_count[0] = out_count[1] = 0;
     if (hipMalloc(&cnt, sizeof(int64_t) * (2 * rows + 1)) != hipSuccess) return;
-    if (hipMalloc(&pmin, sizeof(int) * 4 * rows) != hipSuccess) { (void)hipFree(cnt); return; }
     const unsigned nb = (unsigned)((2 * rows + 255) / 256);
-    k_seg_count<<<nb, 256, 0, s>>>(type, rows, Wp, cs, cnt, pmin);
+    k_seg_count<<<nb, 256, 0, s>>>(type, rows, Wp, cs, cnt);
     // per-colour totals come from the exclusive scan at rows and 2 rows
     k_scan_single<<<1, 1024, 0, s>>>(cnt, 2 * rows);
     int64_t h[2] = {0, 0};
@@ -218,7 +266,7 @@ void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows,
     const long long total = h[1];
     int4 *items = nullptr;
     if (total > 0 && hipMalloc(&items, sizeof(int4) * total) == hipSuccess) {
-        k_seg_emit<<<nb, 256, 0, s>>>(rows, cnt, pmin, desc, items);
+        k_seg_emit<<<nb, 256, 0, s>>>(type, rows, Wp, cs, cnt, desc, items);
         (void)hipStreamSynchronize(s);
         out_items[0] = items;
         out_items[1] = items + h[0];
@@ -226,7 +274,6 @@ void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows,
         out_count[1] = (int)(total - h[0]);
     }
     (void)hipFree(cnt);
-    (void)hipFree(pmin);
 }
 
 // ---------------------------------------------------------------------------
@@ -273,11 +320,12 @@ __device__ double phi_interp(const double *phi, const long long *stl, const int 
 
 template <int DIM>
 __global__ void k_ghost_geometry(int level, const double *__restrict__ phi, const uint8_t *__restrict__ type,
-                                 const int64_t *__restrict__ c2g_gh, const int *__restrict__ cmap, int ng, int n,
+                                 const int64_t *__restrict__ c2g_gh, const int *__restrict__ cmap, int ni, int ng, int n,
                                  int Wp, long long cs, double lo, double h, int *__restrict__ g_idx,
-                                 int *__restrict__ g_st, int *__restrict__ g_stc, double *__restrict__ g_w,
-                                 double *__restrict__ g_B, double *__restrict__ g_nrm, int *__restrict__ g_order,
-                                 int *__restrict__ g_bfall, int *__restrict__ err)
+                                 int *__restrict__ g_ijk, int *__restrict__ g_st, int *__restrict__ g_stg,
+                                 int *__restrict__ g_stc, double *__restrict__ g_w, double *__restrict__ g_B,
+                                 double *__restrict__ g_nrm, int *__restrict__ g_order, int *__restrict__ g_bfall,
+                                 int *__restrict__ err)
 {
     constexpr int NST = DIM == 2 ? 9 : 27;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -385,11 +433,14 @@ __global__ void k_ghost_geometry(int level, const double *__restrict__ phi, cons
     if (order == 0)
         for (int k = 0; k < NST; ++k) w[k] = k == 0 ? 1.0 : 0.0;
     g_idx[q] = (int)gs;
+    g_ijk[q] = gi[0] | (gi[1] << 11) | (gi[2] << 22);
     for (int k = 0; k < NST; ++k) {
         // zero-weight entries point at the ghost itself, which is always active
         const long long tgt = w[k] != 0.0 ? sts[k] : gs;
+        const int cm = cmap[sts[k]];
         g_st[k * ng + q] = (int)tgt;
-        g_stc[k * ng + q] = cmap[sts[k]];
+        g_stg[k * ng + q] = (w[k] != 0.0 && cm >= ni) ? cm - ni : -1;
+        g_stc[k * ng + q] = cm;
         g_w[k * ng + q] = w[k];
     }
     for (int a = 0; a < DIM; ++a) {
@@ -573,17 +624,19 @@ void launch_c2s(int dim, const int64_t *c2g, int na, int n, int Wp, long long cs
 }
 
 void launch_ghost_geometry(int dim, int level, const double *phi, const uint8_t *type, const int64_t *c2g_gh,
-                           const int *cmap, int ng, int n, int Wp, long long cs, double lo, double h, int *g_idx,
-                           int *g_st, int *g_stc, double *g_w, double *g_B, double *g_nrm, int *g_order, int *g_bfall,
-                           int *err, hipStream_t s)
+                           const int *cmap, int ni, int ng, int n, int Wp, long long cs, double lo, double h, int *g_idx,
+                           int *g_ijk, int *g_st, int *g_stg, int *g_stc, double *g_w, double *g_B, double *g_nrm,
+                           int *g_order, int *g_bfall, int *err, hipStream_t s)
 {
     if (ng <= 0) return;
     if (dim == 2)
-        k_ghost_geometry<2><<<blocks(ng, 64), 64, 0, s>>>(level, phi, type, c2g_gh, cmap, ng, n, Wp, cs, lo, h, g_idx,
-                                                          g_st, g_stc, g_w, g_B, g_nrm, g_order, g_bfall, err);
+        k_ghost_geometry<2><<<blocks(ng, 64), 64, 0, s>>>(level, phi, type, c2g_gh, cmap, ni, ng, n, Wp, cs, lo, h,
+                                                          g_idx, g_ijk, g_st, g_stg, g_stc, g_w, g_B, g_nrm, g_order,
+                                                          g_bfall, err);
     else
-        k_ghost_geometry<3><<<blocks(ng, 64), 64, 0, s>>>(level, phi, type, c2g_gh, cmap, ng, n, Wp, cs, lo, h, g_idx,
-                                                          g_st, g_stc, g_w, g_B, g_nrm, g_order, g_bfall, err);
+        k_ghost_geometry<3><<<blocks(ng, 64), 64, 0, s>>>(level, phi, type, c2g_gh, cmap, ni, ng, n, Wp, cs, lo, h,
+                                                          g_idx, g_ijk, g_st, g_stg, g_stc, g_w, g_B, g_nrm, g_order,
+                                                          g_bfall, err);
 }
 
 void launch_band_mark(int dim, const int64_t *c2g_cg, int ngc, int nc, const uint8_t *ftype, int nf, int fWp,

@@ -1,11 +1,16 @@
 // Hot-path kernels of the level-set multigrid V-cycle and of the Newton /
-// Crank-Nicolson step (gfx950, 64-lane wavefronts, one work item per wavefront).
+// Crank-Nicolson step (gfx950, 64-lane wavefronts).
 //
-// Every kernel is templated on the working precision T (double, or float for the
-// mixed-precision V-cycle) and on the dimension.  Jacobian entries are never
-// stored: each kernel evaluates the rows it needs from the linearisation point
-// (s, c) held in registers, so a sweep moves only s, c, the right-hand side and
-// the correction.
+// Each operation is a per-node device function ("element") applied to a work
+// item and a lane.  Fine levels launch one wavefront per work item; the coarse
+// tail of the hierarchy (levels small enough for one workgroup) runs as a
+// single 1024-thread workgroup that walks its work lists with workgroup
+// barriers between phases, so the whole lower part of a V-cycle is one launch.
+//
+// Every element is templated on the working precision T (double, or float for
+// the mixed-precision V-cycle) and on the dimension.  Jacobian entries are never
+// stored: each element evaluates the rows it needs from the linearisation point
+// (s, c), so a sweep moves only s, c, the right-hand side and the correction.
 #include "lsmg_dev.hpp"
 #include "lsmg_host.hpp"
 
@@ -15,30 +20,36 @@ namespace lsmg {
 // inside-row Jacobian (section 3.4, exact derivatives of eqs. FDs and FDc;
 // the printed forms of eqs. JssI, JscI, JcsI, JccI are garbled)
 // ---------------------------------------------------------------------------
-template <typename T, int DIM>
+template <typename T>
 struct InsideRow {
     T ss_d, sc_d, cs_d, cc_d;   // diagonal 2x2 block P (eq. matrixP)
-    T off_s;                    // sum over neighbours of J^ss x_s + J^sc x_c
+    T off_s;                    // sum over the axis neighbours of J^ss x_s + J^sc x_c
 };
 
 template <typename T, int DIM>
-__device__ __forceinline__ InsideRow<T, DIM> inside_row(const LevelDesc<T> *D, long long idx, const long long *nb,
-                                                        const T *xs, const T *xc)
+__device__ __forceinline__ InsideRow<T> inside_row(const LevelDesc<T> *D, long long idx, const long long *nb)
 {
     const T sr = D->s[idx], cr = D->c[idx];
+    T se[2 * DIM], ce[2 * DIM], xse[2 * DIM], xce[2 * DIM];
+#pragma unroll
+    for (int e = 0; e < 2 * DIM; ++e) {
+        se[e] = D->s[nb[e]];
+        ce[e] = D->c[nb[e]];
+        xse[e] = D->x_s[nb[e]];
+        xce[e] = D->x_c[nb[e]];
+    }
     const T al = D->alpha, be = D->beta, kap = D->kap;
     const T phr = al * cr + be;
     T sum_ss = 0, sum_sc = 0, off = 0;
 #pragma unroll
     for (int e = 0; e < 2 * DIM; ++e) {
-        const T se = D->s[nb[e]], ce = D->c[nb[e]];
-        const T a_ss = (al * ce + be) + phr;
-        const T a_sc = sr - se;
+        const T a_ss = (al * ce[e] + be) + phr;
+        const T a_sc = sr - se[e];
         sum_ss += a_ss;
         sum_sc += a_sc;
-        off += -kap * a_ss * xs[nb[e]] + kap * al * a_sc * xc[nb[e]];
+        off += -kap * a_ss * xse[e] + kap * al * a_sc * xce[e];
     }
-    InsideRow<T, DIM> R;
+    InsideRow<T> R;
     R.ss_d = phr * D->dt_inv + D->ks_half * phr * cr + kap * sum_ss;
     R.sc_d = al * sr * D->dt_inv + D->ks_half * (al * sr * cr + phr * sr) + kap * al * sum_sc;
     R.cs_d = D->kc_half * phr * cr;
@@ -57,29 +68,39 @@ __device__ __forceinline__ void c_row(const LevelDesc<T> *D, long long idx, T &c
     cc_d = D->dt_inv + D->kc_half * (D->alpha * sr * cr + phr * sr);
 }
 
-// ---------------------------------------------------------------------------
-// collective red-black Gauss-Seidel on inside nodes (section 3.5.1): the 2x2
-// block of eq. (matrixP) is solved for the node's (delta s, delta c) with its
-// neighbours (the other colour) fixed
-// ---------------------------------------------------------------------------
+// node of (item, lane): inside node of a segment (kinds 0/1) or a ghost (kind 2)
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_smooth_colour(const LevelDesc<T> *__restrict__ descs,
-                                                          const int4 *__restrict__ work, int nwork, int colour)
+__device__ __forceinline__ bool node_of(const LevelDesc<T> *D, int4 w, int lane, long long &idx, int &i, int &j,
+                                        int &k)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *D = descs + item_desc(w);
-    const int p = w.z + (threadIdx.x & 63);
-    if (p >= w.w) return;
-    const long long row = w.y;
-    const long long idx = colour * D->cs + row * D->Wp + p;
-    if (D->type[idx] != kIn) return;
-    int i, j, k;
-    node_coords<DIM>(D->n, colour, row, p, i, j, k);
+    const int kind = item_kind(w);
+    if (kind < 2) {
+        const int p = w.z + lane;
+        if (p >= w.w) return false;
+        idx = kind * D->cs + (long long)w.y * D->Wp + p;   // segments hold inside nodes only
+        node_coords<DIM>(D->n, kind, w.y, p, i, j, k);
+    } else {
+        const int q = w.z + lane;
+        if (q >= w.w) return false;
+        idx = D->g_idx[q];
+        unpack_ijk(D->g_ijk[q], i, j, k);
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// elements
+// ---------------------------------------------------------------------------
+
+// collective red-black Gauss-Seidel on one inside node (section 3.5.1): the 2x2
+// block of eq. (matrixP) is solved for (delta s, delta c) with the neighbours
+// (the other colour) fixed
+template <typename T, int DIM>
+__device__ __forceinline__ void smooth_node(const LevelDesc<T> *D, long long idx, int i, int j, int k, int colour)
+{
     long long nb[2 * DIM];
-    neighbours<DIM>(D->n, D->Wp, D->cs, colour, row, i, p, nb);
-    const InsideRow<T, DIM> R = inside_row<T, DIM>(D, idx, nb, D->x_s, D->x_c);
+    neighbours<DIM>(D->n, D->Wp, D->cs, colour, (long long)j + (long long)D->n * k, i, i >> 1, nb);
+    const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
     const T rs = D->rhs_s[idx] - R.off_s;
     const T rc = D->rhs_c[idx];
     const T det = R.ss_d * R.cc_d - R.sc_d * R.cs_d;
@@ -87,165 +108,172 @@ __global__ __launch_bounds__(kBlock) void k_smooth_colour(const LevelDesc<T> *__
     D->x_c[idx] = (R.ss_d * rc - R.cs_d * rs) / det;
 }
 
-// ---------------------------------------------------------------------------
-// ghost relaxation (eq. RelGhost), Jacobi over the ghosts of a level:
-// phase A computes delta s_g + tau (rhs_g - sum_k w_k delta s_k) for all ghosts,
-// phase B writes it back and relaxes the ghost c-row with the new (or old)
-// delta s_g
-// ---------------------------------------------------------------------------
-template <typename T, int NST>
-__global__ __launch_bounds__(kBlock) void k_ghost_a(const LevelDesc<T> *__restrict__ descs,
-                                                    const int4 *__restrict__ work, int nwork)
+template <typename T, int DIM>
+__device__ __forceinline__ void smooth_elem(const LevelDesc<T> *D, int4 w, int lane, int colour)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *D = descs + item_desc(w);
-    const int q = w.z + (threadIdx.x & 63);
-    if (q >= w.w) return;
+    const int p = w.z + lane;
+    if (p >= w.w) return;
+    const long long idx = colour * D->cs + (long long)w.y * D->Wp + p;
+    int i, j, k;
+    node_coords<DIM>(D->n, colour, w.y, p, i, j, k);
+    smooth_node<T, DIM>(D, idx, i, j, k, colour);
+}
+
+// ghost relaxation of eq. (RelGhost), Jacobi over the ghosts of a level with the
+// ghost values of delta s double-buffered by ghost index: load, sweeps, final
+template <typename T>
+__device__ __forceinline__ void ghost_load_elem(const LevelDesc<T> *D, int q)
+{
+    D->g_buf0[q] = D->x_s[D->g_idx[q]];
+}
+
+template <typename T, int NST>
+__device__ __forceinline__ void ghost_sweep_elem(const LevelDesc<T> *D, int q, const T *bin, T *bout)
+{
     const int ng = D->ng;
     const long long g = D->g_idx[q];
+    T val[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+        const int gq = D->g_stg[k * ng + q];
+        val[k] = gq >= 0 ? bin[gq] : D->x_s[D->g_st[k * ng + q]];
+    }
     T v = 0;
 #pragma unroll
-    for (int k = 0; k < NST; ++k) v += D->g_w[k * ng + q] * D->x_s[D->g_st[k * ng + q]];
-    const T old = D->x_s[g];
-    D->g_old[q] = old;
-    D->g_tmp[q] = old + D->tau_s * (D->rhs_s[g] - v);
+    for (int k = 0; k < NST; ++k) v += D->g_w[k * ng + q] * val[k];
+    bout[q] = bin[q] + D->tau_s * (D->rhs_s[g] - v);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ghost_b(const LevelDesc<T> *__restrict__ descs,
-                                                    const int4 *__restrict__ work, int nwork)
+__device__ __forceinline__ void ghost_final_elem(const LevelDesc<T> *D, int q, const T *bfin, const T *bprev)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *D = descs + item_desc(w);
-    const int q = w.z + (threadIdx.x & 63);
-    if (q >= w.w) return;
     const long long g = D->g_idx[q];
-    const T ns = D->g_tmp[q];
+    const T ns = bfin[q];
     D->x_s[g] = ns;
     T cs_d, cc_d;
     c_row<T>(D, g, cs_d, cc_d);
-    const T dsv = D->ghost_c_new ? ns : D->g_old[q];
+    const T dsv = D->ghost_c_new ? ns : bprev[q];
     const T xc = D->x_c[g];
     D->x_c[g] = xc + (D->rhs_c[g] - (cs_d * dsv + cc_d * xc)) / cc_d;
 }
 
-// ---------------------------------------------------------------------------
-// defect r = rhs - J x on all active rows (section 3.5.2), with its max norm
-// ---------------------------------------------------------------------------
-template <typename T, int DIM, int NST>
-__global__ __launch_bounds__(kBlock) void k_defect(const LevelDesc<T> *__restrict__ descs,
-                                                   const int4 *__restrict__ work, int nwork,
-                                                   unsigned long long *norm_slot)
+// composed form of the same sweeps: phase 1 stores the ghost's current delta s
+// and b = rhs - (its stencil terms on non-ghost nodes); phase 2 applies the
+// composed map and relaxes the c-row with the new delta s
+template <typename T, int NST>
+__device__ __forceinline__ void ghost_b_elem(const LevelDesc<T> *D, int q)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *D = descs + item_desc(w);
-    const int kind = item_kind(w);
-    const int lane = threadIdx.x & 63;
-    unsigned long long bits = 0;
-    if (kind < 2) {
-        const int p = w.z + lane;
-        const long long row = w.y;
-        const long long idx = kind * D->cs + row * D->Wp + p;
-        if (p < w.w && D->type[idx] == kIn) {
-            int i, j, k;
-            node_coords<DIM>(D->n, kind, row, p, i, j, k);
-            long long nb[2 * DIM];
-            neighbours<DIM>(D->n, D->Wp, D->cs, kind, row, i, p, nb);
-            const InsideRow<T, DIM> R = inside_row<T, DIM>(D, idx, nb, D->x_s, D->x_c);
-            const T xs = D->x_s[idx], xc = D->x_c[idx];
-            const T rs = D->rhs_s[idx] - (R.ss_d * xs + R.sc_d * xc + R.off_s);
-            const T rc = D->rhs_c[idx] - (R.cs_d * xs + R.cc_d * xc);
-            D->r_s[idx] = rs;
-            D->r_c[idx] = rc;
-            if (norm_slot) {
-                unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
-                bits = a > b ? a : b;
-            }
-        }
-    } else {
-        const int q = w.z + lane;
-        if (q < w.w) {
-            const int ng = D->ng;
-            const long long g = D->g_idx[q];
-            T v = 0;
+    const int ng = D->ng;
+    const long long g = D->g_idx[q];
+    T val[NST];
 #pragma unroll
-            for (int k = 0; k < NST; ++k) v += D->g_w[k * ng + q] * D->x_s[D->g_st[k * ng + q]];
-            T cs_d, cc_d;
-            c_row<T>(D, g, cs_d, cc_d);
-            const T rs = D->rhs_s[g] - v;
-            const T rc = D->rhs_c[g] - (cs_d * D->x_s[g] + cc_d * D->x_c[g]);
-            D->r_s[g] = rs;
-            D->r_c[g] = rc;
-            if (norm_slot) {
-                unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
-                bits = a > b ? a : b;
-            }
-        }
-    }
-    if (norm_slot) norm_accumulate(norm_slot, bits);
+    for (int k = 0; k < NST; ++k) val[k] = D->g_stg[k * ng + q] >= 0 ? T(0) : D->x_s[D->g_st[k * ng + q]];
+    T v = 0;
+#pragma unroll
+    for (int k = 0; k < NST; ++k) v += D->g_w[k * ng + q] * val[k];
+    D->g_buf0[q] = D->rhs_s[g] - v;
+    D->g_buf1[q] = D->x_s[g];
 }
 
-// y = J x on all active rows
-template <typename T, int DIM, int NST>
-__global__ __launch_bounds__(kBlock) void k_apply_J(const LevelDesc<T> *__restrict__ descs,
-                                                    const int4 *__restrict__ work, int nwork)
+template <typename T>
+__device__ __forceinline__ void ghost_apply_elem(const LevelDesc<T> *D, int q)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *D = descs + item_desc(w);
-    const int kind = item_kind(w);
-    const int lane = threadIdx.x & 63;
-    if (kind < 2) {
-        const int p = w.z + lane;
-        if (p >= w.w) return;
-        const long long row = w.y;
-        const long long idx = kind * D->cs + row * D->Wp + p;
-        if (D->type[idx] != kIn) return;
-        int i, j, k;
-        node_coords<DIM>(D->n, kind, row, p, i, j, k);
+    const long long g = D->g_idx[q];
+    const int e0 = D->go_ptr[q], e1 = D->go_ptr[q + 1];
+    T v = 0;
+    for (int e = e0; e < e1; ++e) {
+        const int c = D->go_col[e];
+        v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
+    }
+    D->x_s[g] = v;
+    T cs_d, cc_d;
+    c_row<T>(D, g, cs_d, cc_d);
+    const T xc = D->x_c[g];
+    D->x_c[g] = xc + (D->rhs_c[g] - (cs_d * v + cc_d * xc)) / cc_d;
+}
+
+// defect r = rhs - J x on one active row pair (section 3.5.2); returns |r| bits
+template <typename T, int DIM>
+__device__ __forceinline__ unsigned long long defect_inside(const LevelDesc<T> *D, long long idx, int i, int j, int k)
+{
+    long long nb[2 * DIM];
+    neighbours<DIM>(D->n, D->Wp, D->cs, (i + j + k) & 1, (long long)j + (long long)D->n * k, i, i >> 1, nb);
+    const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
+    const T xs = D->x_s[idx], xc = D->x_c[idx];
+    const T rs = D->rhs_s[idx] - (R.ss_d * xs + R.sc_d * xc + R.off_s);
+    const T rc = D->rhs_c[idx] - (R.cs_d * xs + R.cc_d * xc);
+    D->r_s[idx] = rs;
+    D->r_c[idx] = rc;
+    const unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
+    return a > b ? a : b;
+}
+
+template <typename T, int NST>
+__device__ __forceinline__ unsigned long long defect_ghost(const LevelDesc<T> *D, int q)
+{
+    const int ng = D->ng;
+    const long long idx = D->g_idx[q];
+    T val[NST];
+#pragma unroll
+    for (int kk = 0; kk < NST; ++kk) val[kk] = D->x_s[D->g_st[kk * ng + q]];
+    T v = 0;
+#pragma unroll
+    for (int kk = 0; kk < NST; ++kk) v += D->g_w[kk * ng + q] * val[kk];
+    T cs_d, cc_d;
+    c_row<T>(D, idx, cs_d, cc_d);
+    const T rs = D->rhs_s[idx] - v;
+    const T rc = D->rhs_c[idx] - (cs_d * D->x_s[idx] + cc_d * D->x_c[idx]);
+    D->r_s[idx] = rs;
+    D->r_c[idx] = rc;
+    const unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
+    return a > b ? a : b;
+}
+
+template <typename T, int DIM, int NST>
+__device__ __forceinline__ unsigned long long defect_elem(const LevelDesc<T> *D, int4 w, int lane)
+{
+    if (item_kind(w) == 2) {
+        const int q = w.z + lane;
+        return q < w.w ? defect_ghost<T, NST>(D, q) : 0ull;
+    }
+    long long idx;
+    int i, j, k;
+    if (!node_of<T, DIM>(D, w, lane, idx, i, j, k)) return 0ull;
+    return defect_inside<T, DIM>(D, idx, i, j, k);
+}
+
+// y = J x on one active row pair (into r)
+template <typename T, int DIM, int NST>
+__device__ __forceinline__ void apply_J_elem(const LevelDesc<T> *D, int4 w, int lane)
+{
+    long long idx;
+    int i, j, k;
+    if (!node_of<T, DIM>(D, w, lane, idx, i, j, k)) return;
+    if (item_kind(w) < 2) {
         long long nb[2 * DIM];
-        neighbours<DIM>(D->n, D->Wp, D->cs, kind, row, i, p, nb);
-        const InsideRow<T, DIM> R = inside_row<T, DIM>(D, idx, nb, D->x_s, D->x_c);
+        neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), (long long)j + (long long)D->n * k, i, i >> 1, nb);
+        const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
         const T xs = D->x_s[idx], xc = D->x_c[idx];
         D->r_s[idx] = R.ss_d * xs + R.sc_d * xc + R.off_s;
         D->r_c[idx] = R.cs_d * xs + R.cc_d * xc;
     } else {
-        const int q = w.z + lane;
-        if (q >= w.w) return;
-        const int ng = D->ng;
-        const long long g = D->g_idx[q];
+        const int q = w.z + lane, ng = D->ng;
         T v = 0;
 #pragma unroll
-        for (int k = 0; k < NST; ++k) v += D->g_w[k * ng + q] * D->x_s[D->g_st[k * ng + q]];
+        for (int kk = 0; kk < NST; ++kk) v += D->g_w[kk * ng + q] * D->x_s[D->g_st[kk * ng + q]];
         T cs_d, cc_d;
-        c_row<T>(D, g, cs_d, cc_d);
-        D->r_s[g] = v;
-        D->r_c[g] = cs_d * D->x_s[g] + cc_d * D->x_c[g];
+        c_row<T>(D, idx, cs_d, cc_d);
+        D->r_s[idx] = v;
+        D->r_c[idx] = cs_d * D->x_s[idx] + cc_d * D->x_c[idx];
     }
 }
 
-// ---------------------------------------------------------------------------
-// boundary-defect band: value of each reached band node as its fixed linear
-// combination of ghost defects (the layered upwind extension of section 3.5.2
-// composed at build time)
-// ---------------------------------------------------------------------------
+// boundary-defect band: each reached band node is a fixed linear combination
+// of ghost defects (the layered upwind extension of section 3.5.2, composed at
+// build time)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_band(const LevelDesc<T> *__restrict__ descs,
-                                                 const int4 *__restrict__ work, int nwork)
+__device__ __forceinline__ void band_elem(const LevelDesc<T> *D, int b)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *D = descs + item_desc(w);
-    const int b = w.z + (threadIdx.x & 63);
-    if (b >= w.w) return;
     const int cnt = D->b_cnt[b];
     if (cnt == 0) return;
     const int nb = D->nb;
@@ -254,146 +282,88 @@ __global__ __launch_bounds__(kBlock) void k_band(const LevelDesc<T> *__restrict_
     D->r_s[D->b_idx[b]] = v;
 }
 
-// ---------------------------------------------------------------------------
-// restriction to the next coarser level (section 3.5.2, Fig. Neigh): modified
-// full weighting; inside rows read inside fine defects, boundary rows read
-// ghost and reached band defects, c-rows use full weighting renormalised over
-// active fine nodes.  Also clears the coarse correction.
-// ---------------------------------------------------------------------------
+// restriction onto one coarse node (section 3.5.2, Fig. Neigh): modified full
+// weighting; inside rows read inside fine defects, boundary rows read ghost and
+// reached band defects, c-rows use full weighting renormalised over active fine
+// nodes.  Also clears the coarse correction.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_restrict(const LevelDesc<T> *__restrict__ descs,
-                                                     const int4 *__restrict__ work, int nwork)
+__device__ __forceinline__ void restrict_node(const LevelDesc<T> *C, long long cidx, int ci, int cj, int ck,
+                                              bool coarse_inside)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *C = descs + item_desc(w);
     const LevelDesc<T> *F = C - 1;
-    const int kind = item_kind(w);
-    const int lane = threadIdx.x & 63;
-    long long cidx;
-    int ci, cj, ck;
-    bool coarse_inside;
-    if (kind < 2) {
-        const int p = w.z + lane;
-        if (p >= w.w) return;
-        cidx = kind * C->cs + (long long)w.y * C->Wp + p;
-        if (C->type[cidx] != kIn) return;
-        node_coords<DIM>(C->n, kind, w.y, p, ci, cj, ck);
-        coarse_inside = true;
-    } else {
-        const int q = w.z + lane;
-        if (q >= w.w) return;
-        cidx = C->g_idx[q];
-        // coordinates of the ghost from its storage index
-        const long long colour = cidx / C->cs;
-        const long long rem = cidx - colour * C->cs;
-        const long long row = rem / C->Wp;
-        const int p = (int)(rem - row * C->Wp);
-        node_coords<DIM>(C->n, (int)colour, row, p, ci, cj, ck);
-        coarse_inside = false;
-    }
+    constexpr int NST = DIM == 2 ? 9 : 27;
     const int fn = F->n, fWp = F->Wp;
     const long long fcs = F->cs;
-    const int fc[3] = {2 * ci, 2 * cj, 2 * ck};
+    const int fc0 = 2 * ci, fc1 = 2 * cj, fc2 = 2 * ck;
+    const long long fcentre = sidx(fn, fWp, fcs, fc0, fc1, fc2);
+    // gather the 3^d fine neighbourhood (out-of-box entries read the centre with type "excluded")
+    uint8_t ex[NST], act[NST];
+    T rs[NST], rc[NST];
+#pragma unroll
+    for (int kk = 0; kk < NST; ++kk) {
+        const int id0 = fc0 + kk % 3 - 1, id1 = fc1 + (kk / 3) % 3 - 1, id2 = DIM == 3 ? fc2 + kk / 9 - 1 : 0;
+        const bool inb = id0 >= 0 && id0 < fn && id1 >= 0 && id1 < fn && (DIM == 2 || (id2 >= 0 && id2 < fn));
+        const long long q = inb ? sidx(fn, fWp, fcs, id0, id1, id2) : fcentre;
+        const uint8_t t = F->type[q];
+        const uint8_t e = F->ext[q];
+        rs[kk] = F->r_s[q];
+        rc[kk] = F->r_c[q];
+        bool excl = coarse_inside ? (t != kIn) : (t == kIn || (t == kOut && !e));
+        ex[kk] = inb ? (uint8_t)excl : (uint8_t)1;
+        act[kk] = inb && t != kOut;
+    }
+    constexpr int CEN = DIM == 2 ? 4 : 13;
+    ex[CEN] = 0;
+    // per-axis weights: [1,2,1]/4, [2,2,0]/4 if +1 excluded, [0,2,2]/4 if -1 excluded, [0,4,0]/4 if both
     T wa[3][3];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        bool ex[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            int id[3] = {fc[0], fc[1], fc[2]};
-            id[a] += e ? 1 : -1;
-            if (id[a] < 0 || id[a] >= fn) {
-                ex[e] = true;
-                continue;
-            }
-            const long long q = sidx(fn, fWp, fcs, id[0], id[1], id[2]);
-            const uint8_t t = F->type[q];
-            ex[e] = coarse_inside ? (t != kIn) : (t == kIn || (t == kOut && !F->ext[q]));
-        }
-        if (!ex[0] && !ex[1]) { wa[a][0] = T(0.25); wa[a][1] = T(0.5); wa[a][2] = T(0.25); }
-        else if (!ex[0] && ex[1]) { wa[a][0] = T(0.5); wa[a][1] = T(0.5); wa[a][2] = T(0); }
-        else if (ex[0] && !ex[1]) { wa[a][0] = T(0); wa[a][1] = T(0.5); wa[a][2] = T(0.5); }
-        else { wa[a][0] = T(0); wa[a][1] = T(1); wa[a][2] = T(0); }
+        const int st = a == 0 ? 1 : (a == 1 ? 3 : 9);
+        const bool em = ex[CEN - st], ep = ex[CEN + st];
+        wa[a][0] = em ? T(0) : (ep ? T(0.5) : T(0.25));
+        wa[a][1] = (em && ep) ? T(1) : T(0.5);
+        wa[a][2] = ep ? T(0) : (em ? T(0.5) : T(0.25));
     }
-    const long long fcentre = sidx(fn, fWp, fcs, fc[0], fc[1], fc[2]);
     T vs = 0, wcen = 0, vc = 0, wcs = 0;
-    constexpr int NST = DIM == 2 ? 9 : 27;
 #pragma unroll
     for (int kk = 0; kk < NST; ++kk) {
-        const int d0 = kk % 3 - 1, d1 = (kk / 3) % 3 - 1, d2 = DIM == 3 ? kk / 9 - 1 : 0;
-        const int id0 = fc[0] + d0, id1 = fc[1] + d1, id2 = fc[2] + d2;
-        T wk = wa[0][d0 + 1] * wa[1][d1 + 1];
-        T wf = (d0 == 0 ? T(0.5) : T(0.25)) * (d1 == 0 ? T(0.5) : T(0.25));
+        const int d0 = kk % 3, d1 = (kk / 3) % 3, d2 = kk / 9;
+        T wk = wa[0][d0] * wa[1][d1];
+        T wf = (d0 == 1 ? T(0.5) : T(0.25)) * (d1 == 1 ? T(0.5) : T(0.25));
         if (DIM == 3) {
-            wk *= wa[2][d2 + 1];
-            wf *= (d2 == 0 ? T(0.5) : T(0.25));
+            wk *= wa[2][d2];
+            wf *= (d2 == 1 ? T(0.5) : T(0.25));
         }
-        if (id0 < 0 || id0 >= fn || id1 < 0 || id1 >= fn || (DIM == 3 && (id2 < 0 || id2 >= fn))) {
-            wcen += wk;
-            continue;
-        }
-        const long long q = sidx(fn, fWp, fcs, id0, id1, id2);
-        const uint8_t t = F->type[q];
-        bool excluded = coarse_inside ? (t != kIn) : (t == kIn || (t == kOut && !F->ext[q]));
-        if (q == fcentre) excluded = false;
-        if (excluded) wcen += wk;
-        else if (wk != T(0)) vs += wk * F->r_s[q];
-        if (t != kOut) {
-            vc += wf * F->r_c[q];
+        if (ex[kk]) wcen += wk;
+        else vs += wk * rs[kk];
+        if (act[kk]) {
+            vc += wf * rc[kk];
             wcs += wf;
         }
     }
-    vs += wcen * F->r_s[fcentre];
+    vs += wcen * rs[CEN];
     C->rhs_s[cidx] = vs;
     C->rhs_c[cidx] = wcs > T(0) ? vc / wcs : T(0);
     C->x_s[cidx] = T(0);
     C->x_c[cidx] = T(0);
 }
 
-// ---------------------------------------------------------------------------
-// prolongation (section 3.5.3): bilinear (trilinear) interpolation of the
-// coarse correction over active coarse nodes, renormalised, added to x
-// ---------------------------------------------------------------------------
 template <typename T, int DIM>
-__device__ __forceinline__ void node_from_item(const LevelDesc<T> *D, int4 w, int lane, bool &ok, long long &idx,
-                                               int &i, int &j, int &k)
+__device__ __forceinline__ void restrict_elem(const LevelDesc<T> *C, int4 w, int lane)
 {
-    const int kind = item_kind(w);
-    ok = false;
-    if (kind < 2) {
-        const int p = w.z + lane;
-        if (p >= w.w) return;
-        idx = kind * D->cs + (long long)w.y * D->Wp + p;
-        if (D->type[idx] != kIn) return;
-        node_coords<DIM>(D->n, kind, w.y, p, i, j, k);
-    } else {
-        const int q = w.z + lane;
-        if (q >= w.w) return;
-        idx = D->g_idx[q];
-        const long long colour = idx / D->cs;
-        const long long rem = idx - colour * D->cs;
-        const long long row = rem / D->Wp;
-        node_coords<DIM>(D->n, (int)colour, row, (int)(rem - row * D->Wp), i, j, k);
-    }
-    ok = true;
+    long long cidx;
+    int ci, cj, ck;
+    if (!node_of<T, DIM>(C, w, lane, cidx, ci, cj, ck)) return;
+    restrict_node<T, DIM>(C, cidx, ci, cj, ck, item_kind(w) < 2);
 }
 
+// bilinear (trilinear) prolongation onto one fine node (section 3.5.3), over
+// active coarse nodes and renormalised, added to x
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_prolong(const LevelDesc<T> *__restrict__ descs,
-                                                    const int4 *__restrict__ work, int nwork)
+__device__ __forceinline__ void prolong_node(const LevelDesc<T> *F, long long idx, int i, int j, int k)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *F = descs + item_desc(w);
     const LevelDesc<T> *C = F + 1;
-    bool ok;
-    long long idx;
-    int fi[3];
-    node_from_item<T, DIM>(F, w, threadIdx.x & 63, ok, idx, fi[0], fi[1], fi[2]);
-    if (!ok) return;
+    const int fi[3] = {i, j, k};
     T ws = 0, es = 0, ec = 0;
 #pragma unroll
     for (int corner = 0; corner < (1 << DIM); ++corner) {
@@ -424,24 +394,24 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const LevelDesc<T> *__restri
     }
 }
 
-// ---------------------------------------------------------------------------
-// coarse linearisation point: injection where the fine centre is active,
-// otherwise full weighting over the active fine neighbours
-// ---------------------------------------------------------------------------
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_inject(const LevelDesc<T> *__restrict__ descs,
-                                                   const int4 *__restrict__ work, int nwork)
+__device__ __forceinline__ void prolong_elem(const LevelDesc<T> *F, int4 w, int lane)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
-    const LevelDesc<T> *C = descs + item_desc(w);
+    long long idx;
+    int i, j, k;
+    if (!node_of<T, DIM>(F, w, lane, idx, i, j, k)) return;
+    prolong_node<T, DIM>(F, idx, i, j, k);
+}
+
+// coarse linearisation point on one coarse node: injection where the fine centre
+// is active, otherwise full weighting over the active fine neighbours
+template <typename T, int DIM>
+__device__ __forceinline__ void inject_elem(const LevelDesc<T> *C, int4 w, int lane)
+{
     const LevelDesc<T> *F = C - 1;
-    bool ok;
     long long cidx;
     int ci[3];
-    node_from_item<T, DIM>(C, w, threadIdx.x & 63, ok, cidx, ci[0], ci[1], ci[2]);
-    if (!ok) return;
+    if (!node_of<T, DIM>(C, w, lane, cidx, ci[0], ci[1], ci[2])) return;
     const int fn = F->n;
     const int fc[3] = {2 * ci[0], 2 * ci[1], 2 * ci[2]};
     const long long fq = sidx(fn, F->Wp, F->cs, fc[0], fc[1], fc[2]);
@@ -476,6 +446,259 @@ __global__ __launch_bounds__(kBlock) void k_inject(const LevelDesc<T> *__restric
 }
 
 // ---------------------------------------------------------------------------
+// per-item kernels (fine levels): one wavefront per work item
+// ---------------------------------------------------------------------------
+#define LSMG_ITEM_PROLOGUE                                                          \
+    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);               \
+    if (it >= nwork) return;                                                       \
+    const int4 w = work[it];                                                       \
+    const int lane = threadIdx.x & 63;
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_smooth_colour(const LevelDesc<T> *__restrict__ descs,
+                                                          const int4 *__restrict__ work, int nwork, int colour)
+{
+    LSMG_ITEM_PROLOGUE
+    smooth_elem<T, DIM>(descs + item_desc(w), w, lane, colour);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ghost_load(const LevelDesc<T> *__restrict__ descs,
+                                                       const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    const int q = w.z + lane;
+    if (q < w.w) ghost_load_elem<T>(descs + item_desc(w), q);
+}
+
+template <typename T, int NST>
+__global__ __launch_bounds__(kBlock) void k_ghost_sweep(const LevelDesc<T> *__restrict__ descs,
+                                                        const int4 *__restrict__ work, int nwork, int parity)
+{
+    LSMG_ITEM_PROLOGUE
+    const LevelDesc<T> *D = descs + item_desc(w);
+    const int q = w.z + lane;
+    if (q < w.w) ghost_sweep_elem<T, NST>(D, q, parity ? D->g_buf1 : D->g_buf0, parity ? D->g_buf0 : D->g_buf1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ghost_final(const LevelDesc<T> *__restrict__ descs,
+                                                        const int4 *__restrict__ work, int nwork, int parity)
+{
+    LSMG_ITEM_PROLOGUE
+    const LevelDesc<T> *D = descs + item_desc(w);
+    const int q = w.z + lane;
+    if (q < w.w) ghost_final_elem<T>(D, q, parity ? D->g_buf1 : D->g_buf0, parity ? D->g_buf0 : D->g_buf1);
+}
+
+template <typename T, int NST>
+__global__ __launch_bounds__(kBlock) void k_ghost_b(const LevelDesc<T> *__restrict__ descs,
+                                                    const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    const int q = w.z + lane;
+    if (q < w.w) ghost_b_elem<T, NST>(descs + item_desc(w), q);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ghost_apply(const LevelDesc<T> *__restrict__ descs,
+                                                        const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    const int q = w.z + lane;
+    if (q < w.w) ghost_apply_elem<T>(descs + item_desc(w), q);
+}
+
+// all ghost sweeps of one level in one workgroup (sweep by sweep)
+template <typename T, int NST>
+__global__ __launch_bounds__(1024) void k_ghost_fused(const LevelDesc<T> *__restrict__ descs, int desc, int sweeps)
+{
+    const LevelDesc<T> *D = descs + desc;
+    const int ng = D->ng;
+    for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_load_elem<T>(D, q);
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const T *bin = (sw & 1) ? D->g_buf1 : D->g_buf0;
+        T *bout = (sw & 1) ? D->g_buf0 : D->g_buf1;
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_sweep_elem<T, NST>(D, q, bin, bout);
+        __syncthreads();
+    }
+    const T *bfin = (sweeps & 1) ? D->g_buf1 : D->g_buf0;
+    const T *bprev = (sweeps & 1) ? D->g_buf0 : D->g_buf1;
+    for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_final_elem<T>(D, q, bfin, bprev);
+}
+
+template <typename T, int DIM, int NST>
+__global__ __launch_bounds__(kBlock) void k_defect(const LevelDesc<T> *__restrict__ descs,
+                                                   const int4 *__restrict__ work, int nwork,
+                                                   unsigned long long *norm_slot)
+{
+    LSMG_ITEM_PROLOGUE
+    const unsigned long long bits = defect_elem<T, DIM, NST>(descs + item_desc(w), w, lane);
+    if (norm_slot) norm_accumulate(norm_slot, bits);
+}
+
+template <typename T, int DIM, int NST>
+__global__ __launch_bounds__(kBlock) void k_apply_J(const LevelDesc<T> *__restrict__ descs,
+                                                    const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    apply_J_elem<T, DIM, NST>(descs + item_desc(w), w, lane);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_band(const LevelDesc<T> *__restrict__ descs,
+                                                 const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    const int b = w.z + lane;
+    if (b < w.w) band_elem<T>(descs + item_desc(w), b);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_restrict(const LevelDesc<T> *__restrict__ descs,
+                                                     const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    restrict_elem<T, DIM>(descs + item_desc(w), w, lane);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_prolong(const LevelDesc<T> *__restrict__ descs,
+                                                    const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    prolong_elem<T, DIM>(descs + item_desc(w), w, lane);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_inject(const LevelDesc<T> *__restrict__ descs,
+                                                   const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    inject_elem<T, DIM>(descs + item_desc(w), w, lane);
+}
+
+// ---------------------------------------------------------------------------
+// coarse tail: levels l0 .. L-1 of a V-cycle in one workgroup, walking packed
+// node lists (one node per thread and pass) with barriers between phases
+// ---------------------------------------------------------------------------
+// node t of a level's active list: inside nodes (colour 0, colour 1), then ghosts
+template <typename T>
+__device__ __forceinline__ void tail_node(const LevelDesc<T> *D, const TailLevel &TL, int t, long long &idx, int &i,
+                                          int &j, int &k)
+{
+    const int nin = TL.nin0 + TL.nin1;
+    unpack_ijk(t < nin ? TL.in_ijk[t] : D->g_ijk[t - nin], i, j, k);
+    idx = sidx(D->n, D->Wp, D->cs, i, j, k);
+}
+
+template <typename T, int DIM, int NST>
+__device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, int sweeps)
+{
+    for (int colour = 0; colour < 2; ++colour) {
+        const int off = colour ? TL.nin0 : 0, cnt = colour ? TL.nin1 : TL.nin0;
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            int i, j, k;
+            unpack_ijk(TL.in_ijk[off + t], i, j, k);
+            smooth_node<T, DIM>(D, sidx(D->n, D->Wp, D->cs, i, j, k), i, j, k, colour);
+        }
+        __syncthreads();
+    }
+    const int ng = D->ng;
+    if (D->go_ptr) {
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_b_elem<T, NST>(D, q);
+        __syncthreads();
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_apply_elem<T>(D, q);
+        __syncthreads();
+        return;
+    }
+    for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_load_elem<T>(D, q);
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const T *bin = (sw & 1) ? D->g_buf1 : D->g_buf0;
+        T *bout = (sw & 1) ? D->g_buf0 : D->g_buf1;
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_sweep_elem<T, NST>(D, q, bin, bout);
+        __syncthreads();
+    }
+    const T *bfin = (sweeps & 1) ? D->g_buf1 : D->g_buf0;
+    const T *bprev = (sweeps & 1) ? D->g_buf0 : D->g_buf1;
+    for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_final_elem<T>(D, q, bfin, bprev);
+    __syncthreads();
+}
+
+// x = A^{-1} rhs on the coarsest level with the explicit inverse (FP64)
+template <typename T>
+__device__ void wg_coarse_apply(const LevelDesc<T> *D, const int *__restrict__ c2s, const double *__restrict__ Ainv,
+                                double *b)
+{
+    const int na = D->na, N = 2 * na;
+    for (int r = threadIdx.x; r < na; r += blockDim.x) {
+        b[r] = (double)D->rhs_s[c2s[r]];
+        b[na + r] = (double)D->rhs_c[c2s[r]];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+        double v = 0.0;
+        for (int jj = 0; jj < N; ++jj) v += Ainv[(long long)r * N + jj] * b[jj];
+        const long long q = c2s[r < na ? r : r - na];
+        if (r < na) D->x_s[q] = (T)v;
+        else D->x_c[q] = (T)v;
+    }
+    __syncthreads();
+}
+
+template <typename T, int DIM, int NST>
+__global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ descs, TailArgs A)
+{
+    extern __shared__ double sb[];
+    const int L = A.nlev;
+    for (int l = A.l0; l < L - 1; ++l) {
+        const LevelDesc<T> *D = descs + l;
+        const TailLevel &TL = A.lev[l];
+        for (int it = 0; it < A.nu1; ++it) wg_smooth<T, DIM, NST>(D, TL, A.ghost_sweeps);
+        const int nin = TL.nin0 + TL.nin1;
+        for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
+            if (t < nin) {
+                long long idx;
+                int i, j, k;
+                tail_node<T>(D, TL, t, idx, i, j, k);
+                (void)defect_inside<T, DIM>(D, idx, i, j, k);
+            } else {
+                (void)defect_ghost<T, NST>(D, t - nin);
+            }
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < D->nb; b += blockDim.x) band_elem<T>(D, b);
+        __syncthreads();
+        const TailLevel &TC = A.lev[l + 1];
+        const LevelDesc<T> *C = D + 1;
+        const int ninc = TC.nin0 + TC.nin1;
+        for (int t = threadIdx.x; t < ninc + C->ng; t += blockDim.x) {
+            long long idx;
+            int i, j, k;
+            tail_node<T>(C, TC, t, idx, i, j, k);
+            restrict_node<T, DIM>(C, idx, i, j, k, t < ninc);
+        }
+        __syncthreads();
+    }
+    wg_coarse_apply<T>(descs + (L - 1), A.c2s, A.ainv, sb);
+    for (int l = L - 2; l >= A.l0; --l) {
+        const LevelDesc<T> *D = descs + l;
+        const TailLevel &TL = A.lev[l];
+        const int nin = TL.nin0 + TL.nin1;
+        for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
+            long long idx;
+            int i, j, k;
+            tail_node<T>(D, TL, t, idx, i, j, k);
+            prolong_node<T, DIM>(D, idx, i, j, k);
+        }
+        __syncthreads();
+        for (int it = 0; it < A.nu2; ++it) wg_smooth<T, DIM, NST>(D, TL, A.ghost_sweeps);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // finest level, FP64: explicit half of the Crank-Nicolson step (section 3.1,
 // eq. discTime) and the Newton residual (eqs. FDs, FDc, BCs)
 // ---------------------------------------------------------------------------
@@ -507,19 +730,14 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_explicit_half(const LevelDesc<double> *__restrict__ descs,
                                                           const int4 *__restrict__ work, int nwork, StepArgs A)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
+    LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = descs + item_desc(w);
-    bool ok;
     long long idx;
     int i, j, k;
-    node_from_item<double, DIM>(D, w, threadIdx.x & 63, ok, idx, i, j, k);
-    if (!ok) return;
-    const bool inside = item_kind(w) < 2;
+    if (!node_of<double, DIM>(D, w, lane, idx, i, j, k)) return;
     const int r = D->cmap[idx];
     const int na = D->na;
-    if (inside) {
+    if (item_kind(w) < 2) {
         long long nb[2 * DIM];
         neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), (long long)j + (long long)D->n * k, i, i >> 1, nb);
         double bsv = (D->alpha * A.cn[idx] + D->beta) * A.sn[idx] * D->dt_inv + 0.5 * Ls_h<DIM>(D, A.sn, A.cn, idx, nb);
@@ -539,17 +757,12 @@ __global__ __launch_bounds__(kBlock) void k_residual(const LevelDesc<double> *__
                                                      const int4 *__restrict__ work, int nwork, StepArgs A,
                                                      unsigned long long *norm_slot)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
+    LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = descs + item_desc(w);
-    bool ok;
     long long idx;
     int i, j, k;
-    const int lane = threadIdx.x & 63;
-    node_from_item<double, DIM>(D, w, lane, ok, idx, i, j, k);
     unsigned long long bits = 0;
-    if (ok) {
+    if (node_of<double, DIM>(D, w, lane, idx, i, j, k)) {
         const double *s = D->s, *c = D->c;
         double fs;
         if (item_kind(w) < 2) {
@@ -567,10 +780,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const LevelDesc<double> *__
         const double fc = c[idx] * D->dt_inv - 0.5 * Lc_h(D, s, c, idx) - A.bc[idx];
         D->rhs_s[idx] = fs;
         D->rhs_c[idx] = fc;
-        if (norm_slot) {
-            unsigned long long a = abs_bits(fs), b = abs_bits(fc);
-            bits = a > b ? a : b;
-        }
+        const unsigned long long a = abs_bits(fs), b = abs_bits(fc);
+        bits = a > b ? a : b;
     }
     if (norm_slot) norm_accumulate(norm_slot, bits);
 }
@@ -581,16 +792,12 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(const LevelDesc<double
                                                           const int4 *__restrict__ work, int nwork,
                                                           unsigned long long *norm_dw, unsigned long long *norm_w)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
+    LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = descs + item_desc(w);
-    bool ok;
     long long idx;
     int i, j, k;
-    node_from_item<double, DIM>(D, w, threadIdx.x & 63, ok, idx, i, j, k);
     unsigned long long bd = 0, bw = 0;
-    if (ok) {
+    if (node_of<double, DIM>(D, w, lane, idx, i, j, k)) {
         const double s = D->s[idx], c = D->c[idx], xs = D->x_s[idx], xc = D->x_c[idx];
         unsigned long long a = abs_bits(xs), b = abs_bits(xc);
         bd = a > b ? a : b;
@@ -612,16 +819,12 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const LevelDesc<double> *__re
                                                    const LevelDesc<float> *__restrict__ d32,
                                                    const int4 *__restrict__ work, int nwork, int what)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
+    LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = d64 + item_desc(w);
     const LevelDesc<float> *E = d32 + item_desc(w);
-    bool ok;
     long long idx;
     int i, j, k;
-    node_from_item<double, DIM>(D, w, threadIdx.x & 63, ok, idx, i, j, k);
-    if (!ok) return;
+    if (!node_of<double, DIM>(D, w, lane, idx, i, j, k)) return;
     if (what == 0) {            // linearisation point
         E->s[idx] = (float)D->s[idx];
         E->c[idx] = (float)D->c[idx];
@@ -638,16 +841,12 @@ __global__ __launch_bounds__(kBlock) void k_add_f32(const LevelDesc<double> *__r
                                                     const LevelDesc<float> *__restrict__ d32,
                                                     const int4 *__restrict__ work, int nwork)
 {
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);
-    if (it >= nwork) return;
-    const int4 w = work[it];
+    LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = d64 + item_desc(w);
     const LevelDesc<float> *E = d32 + item_desc(w);
-    bool ok;
     long long idx;
     int i, j, k;
-    node_from_item<double, DIM>(D, w, threadIdx.x & 63, ok, idx, i, j, k);
-    if (!ok) return;
+    if (!node_of<double, DIM>(D, w, lane, idx, i, j, k)) return;
     D->x_s[idx] += (double)E->x_s[idx];
     D->x_c[idx] += (double)E->x_c[idx];
 }
@@ -686,8 +885,7 @@ __global__ void k_fill(T *__restrict__ p, long long n, T v)
 
 __global__ void k_zero_u64(unsigned long long *p, int n)
 {
-    const int i = threadIdx.x;
-    if (i < n) p[i] = 0ull;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
 }
 
 // grid form of a compact vector pair: NaN at inactive nodes
@@ -716,18 +914,30 @@ __global__ void k_grid_to_split(const int64_t *__restrict__ c2g, int na, const d
 }
 
 // ---------------------------------------------------------------------------
-// coarsest level: dense LU with partial pivoting in one workgroup (FP64)
+// coarsest level (FP64): the dense 2Na x 2Na operator assembled from the same
+// rows and inverted by Gauss-Jordan elimination with partial pivoting on
+// [A | I], in LDS when it fits, in one workgroup
 // ---------------------------------------------------------------------------
 template <int DIM, int NST>
-__global__ __launch_bounds__(1024) void k_coarse_factor(const LevelDesc<double> *__restrict__ descs, int lev,
-                                                        const int *__restrict__ c2s, double *__restrict__ A,
-                                                        int *__restrict__ piv, int *__restrict__ status)
+__global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> *__restrict__ descs, int lev,
+                                                        const int *__restrict__ c2s, double *__restrict__ Mglob,
+                                                        double *__restrict__ Ainv, int use_lds, int *__restrict__ status)
 {
+    extern __shared__ double Mlds[];
     const LevelDesc<double> *D = descs + lev;
-    const int na = D->na, ni = D->ni, N = 2 * na;
+    const int na = D->na, ni = D->ni, N = 2 * na, N2 = 2 * N;
+    double *M = use_lds ? Mlds : Mglob;     // row-major N x 2N
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (long long e = tid; e < (long long)N * N; e += nt) A[e] = 0.0;
+    __shared__ double fac[1024];
+    __shared__ double s_pv;
+    __shared__ int s_pr, s_bad;
+    for (long long e = tid; e < (long long)N * N2; e += nt) {
+        const int r = (int)(e / N2), c = (int)(e % N2);
+        M[e] = (c - N == r) ? 1.0 : 0.0;
+    }
+    if (tid == 0) s_bad = 0;
     __syncthreads();
+    // rows of the Jacobian on the coarsest level (section 3.4)
     for (int r = tid; r < na; r += nt) {
         const long long idx = c2s[r];
         const long long colour = idx / D->cs;
@@ -738,6 +948,7 @@ __global__ __launch_bounds__(1024) void k_coarse_factor(const LevelDesc<double> 
         node_coords<DIM>(D->n, (int)colour, row, p, i, j, k);
         double cs_d, cc_d;
         c_row<double>(D, idx, cs_d, cc_d);
+        double *Rs = M + (long long)r * N2, *Rc = M + (long long)(na + r) * N2;
         if (r < ni) {
             long long nb[2 * DIM];
             neighbours<DIM>(D->n, D->Wp, D->cs, (int)colour, row, i, p, nb);
@@ -751,111 +962,79 @@ __global__ __launch_bounds__(1024) void k_coarse_factor(const LevelDesc<double> 
                 sum_ss += a_ss;
                 sum_sc += a_sc;
                 const int q = D->cmap[nb[e]];
-                A[(long long)r * N + q] += -kap * a_ss;
-                A[(long long)r * N + na + q] += kap * al * a_sc;
+                Rs[q] += -kap * a_ss;
+                Rs[na + q] += kap * al * a_sc;
             }
-            A[(long long)r * N + r] += phr * D->dt_inv + D->ks_half * phr * cr + kap * sum_ss;
-            A[(long long)r * N + na + r] += al * sr * D->dt_inv + D->ks_half * (al * sr * cr + phr * sr) + kap * al * sum_sc;
+            Rs[r] += phr * D->dt_inv + D->ks_half * phr * cr + kap * sum_ss;
+            Rs[na + r] += al * sr * D->dt_inv + D->ks_half * (al * sr * cr + phr * sr) + kap * al * sum_sc;
         } else {
             const int q = r - ni, ng = D->ng;
             for (int kk = 0; kk < NST; ++kk) {
                 const double wk = D->g_w[kk * ng + q];
                 if (wk == 0.0) continue;
-                A[(long long)r * N + D->cmap[D->g_st[kk * ng + q]]] += wk;
+                Rs[D->cmap[D->g_st[kk * ng + q]]] += wk;
             }
         }
-        A[(long long)(na + r) * N + r] += cs_d;
-        A[(long long)(na + r) * N + na + r] += cc_d;
+        Rc[r] += cs_d;
+        Rc[na + r] += cc_d;
     }
     __syncthreads();
-    __shared__ double red_v[1024];
-    __shared__ int red_i[1024];
-    __shared__ int s_bad;
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
     for (int kc = 0; kc < N; ++kc) {
-        // pivot: largest |A[i][kc]| for i >= kc, first index on ties
-        double best = -1.0;
-        int bi = N;
-        for (int i2 = kc + tid; i2 < N; i2 += nt) {
-            const double v = fabs(A[(long long)i2 * N + kc]);
-            if (v > best) { best = v; bi = i2; }
-        }
-        red_v[tid] = best;
-        red_i[tid] = bi;
-        __syncthreads();
-        for (int off = nt >> 1; off > 0; off >>= 1) {
-            if (tid < off) {
-                const double ov = red_v[tid + off];
-                const int oi = red_i[tid + off];
-                if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) { red_v[tid] = ov; red_i[tid] = oi; }
+        // pivot: largest |M[i][kc]|, i >= kc, first index on ties (one wavefront)
+        if (tid < kWave) {
+            double best = -1.0;
+            int bi = N;
+            for (int i2 = kc + tid; i2 < N; i2 += kWave) {
+                const double v = fabs(M[(long long)i2 * N2 + kc]);
+                if (v > best) { best = v; bi = i2; }
             }
-            __syncthreads();
-        }
-        const int pr = red_i[0];
-        const double pv = red_v[0];
-        if (tid == 0) {
-            piv[kc] = pr;
-            if (!(pv > 0.0) || pv != pv || pr >= N) s_bad = 1;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(best, off, kWave);
+                const int oi = __shfl_xor(bi, off, kWave);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (tid == 0) {
+                s_pr = bi;
+                s_pv = best;
+                if (!(best > 0.0) || bi >= N) s_bad = 1;
+            }
         }
         __syncthreads();
         if (s_bad) break;
+        const int pr = s_pr;
         if (pr != kc)
-            for (int jj = tid; jj < N; jj += nt) {
-                const double t = A[(long long)kc * N + jj];
-                A[(long long)kc * N + jj] = A[(long long)pr * N + jj];
-                A[(long long)pr * N + jj] = t;
+            for (int c = kc + tid; c < N2; c += nt) {
+                const double t = M[(long long)kc * N2 + c];
+                M[(long long)kc * N2 + c] = M[(long long)pr * N2 + c];
+                M[(long long)pr * N2 + c] = t;
             }
         __syncthreads();
-        const double dk = A[(long long)kc * N + kc];
-        for (int i2 = kc + 1 + tid; i2 < N; i2 += nt) A[(long long)i2 * N + kc] /= dk;
+        const double inv = 1.0 / M[(long long)kc * N2 + kc];
         __syncthreads();
-        const int m = N - kc - 1;
-        for (long long e = tid; e < (long long)m * m; e += nt) {
-            const int i2 = kc + 1 + (int)(e / m), jj = kc + 1 + (int)(e % m);
-            A[(long long)i2 * N + jj] -= A[(long long)i2 * N + kc] * A[(long long)kc * N + jj];
+        for (int c = kc + tid; c < N2; c += nt) M[(long long)kc * N2 + c] *= inv;
+        for (int i2 = tid; i2 < N; i2 += nt) fac[i2 & 1023] = M[(long long)i2 * N2 + kc];
+        __syncthreads();
+        const int width = N2 - kc;
+        for (long long e = tid; e < (long long)N * width; e += nt) {
+            const int i2 = (int)(e / width), c = kc + (int)(e % width);
+            if (i2 == kc) continue;
+            M[(long long)i2 * N2 + c] -= fac[i2 & 1023] * M[(long long)kc * N2 + c];
         }
         __syncthreads();
+    }
+    for (long long e = tid; e < (long long)N * N; e += nt) {
+        const int r = (int)(e / N), c = (int)(e % N);
+        Ainv[e] = M[(long long)r * N2 + N + c];
     }
     if (tid == 0) *status = s_bad ? 1 : 0;
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse_solve(const LevelDesc<T> *__restrict__ descs, int lev,
-                                                       const int *__restrict__ c2s, const double *__restrict__ A,
-                                                       const int *__restrict__ piv)
+__global__ __launch_bounds__(1024) void k_coarse_apply(const LevelDesc<T> *__restrict__ descs, int lev,
+                                                       const int *__restrict__ c2s, const double *__restrict__ Ainv)
 {
     extern __shared__ double b[];
-    const LevelDesc<T> *D = descs + lev;
-    const int na = D->na, N = 2 * na;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int r = tid; r < na; r += nt) {
-        b[r] = (double)D->rhs_s[c2s[r]];
-        b[na + r] = (double)D->rhs_c[c2s[r]];
-    }
-    __syncthreads();
-    if (tid == 0)
-        for (int kc = 0; kc < N; ++kc) {
-            const int p = piv[kc];
-            if (p != kc) { const double t = b[kc]; b[kc] = b[p]; b[p] = t; }
-        }
-    __syncthreads();
-    for (int jj = 0; jj < N; ++jj) {
-        const double bj = b[jj];
-        for (int i2 = jj + 1 + tid; i2 < N; i2 += nt) b[i2] -= A[(long long)i2 * N + jj] * bj;
-        __syncthreads();
-    }
-    for (int jj = N - 1; jj >= 0; --jj) {
-        if (tid == 0) b[jj] /= A[(long long)jj * N + jj];
-        __syncthreads();
-        const double bj = b[jj];
-        for (int i2 = tid; i2 < jj; i2 += nt) b[i2] -= A[(long long)i2 * N + jj] * bj;
-        __syncthreads();
-    }
-    for (int r = tid; r < na; r += nt) {
-        D->x_s[c2s[r]] = (T)b[r];
-        D->x_c[c2s[r]] = (T)b[na + r];
-    }
+    wg_coarse_apply<T>(descs + lev, c2s, Ainv, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -875,11 +1054,23 @@ void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw,
 }
 
 template <typename T>
-void launch_ghost(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s)
+void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, int ng, int sweeps, bool composed,
+                  hipStream_t s)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_a<T, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
-    k_ghost_b<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
+    if (composed) {
+        LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_b<T, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
+        k_ghost_apply<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
+        return;
+    }
+    if (ng <= kGhostFusedMax) {
+        LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_fused<T, NST><<<1, 1024, 0, s>>>(d, desc, sweeps));
+        return;
+    }
+    k_ghost_load<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
+    for (int sw = 0; sw < sweeps; ++sw)
+        LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_sweep<T, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, sw & 1));
+    k_ghost_final<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, sweeps & 1);
 }
 
 template <typename T>
@@ -922,6 +1113,13 @@ void launch_inject(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStr
 {
     if (nw <= 0) return;
     LSMG_DISPATCH_DIM(dim, (void)NST; k_inject<T, DIM><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
+}
+
+template <typename T>
+void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs &a, int ncoarse, hipStream_t s)
+{
+    const size_t shm = (size_t)2 * ncoarse * sizeof(double);
+    LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST><<<1, 1024, shm, s>>>(d, a));
 }
 
 void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const StepArgsHost &a,
@@ -982,7 +1180,7 @@ void launch_fill(T *p, long long n, T v, hipStream_t s)
     k_fill<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
 }
 
-void launch_zero_u64(unsigned long long *p, int n, hipStream_t s) { k_zero_u64<<<1, 64, 0, s>>>(p, n); }
+void launch_zero_u64(unsigned long long *p, int n, hipStream_t s) { k_zero_u64<<<1, 256, 0, s>>>(p, n); }
 
 void launch_compact_to_grid(const int64_t *c2g, int na, const double *a, const double *b, const int *c2s,
                             double *gs, double *gc, hipStream_t s)
@@ -998,33 +1196,35 @@ void launch_grid_to_split(const int64_t *c2g, int na, const double *gs, const do
     k_grid_to_split<<<(na + 255) / 256, 256, 0, s>>>(c2g, na, gs, gc, c2s, a, b);
 }
 
-void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, const int *c2s, double *A, int *piv,
-                          int *status, hipStream_t s)
+void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, int N, const int *c2s, double *M,
+                          double *Ainv, int *status, hipStream_t s)
 {
-    LSMG_DISPATCH_DIM(dim, k_coarse_factor<DIM, NST><<<1, 1024, 0, s>>>(d, lev, c2s, A, piv, status));
+    const size_t bytes = (size_t)N * 2 * N * sizeof(double);
+    const int use_lds = bytes <= 64 * 1024;
+    LSMG_DISPATCH_DIM(dim, k_coarse_invert<DIM, NST><<<1, 1024, use_lds ? bytes : 0, s>>>(d, lev, c2s, M, Ainv, use_lds,
+                                                                                          status));
 }
 
 template <typename T>
-void launch_coarse_solve(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *A, const int *piv,
-                         hipStream_t s)
+void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *Ainv, hipStream_t s)
 {
-    k_coarse_solve<T><<<1, 1024, (size_t)N * sizeof(double), s>>>(d, lev, c2s, A, piv);
+    k_coarse_apply<T><<<1, 1024, (size_t)N * sizeof(double), s>>>(d, lev, c2s, Ainv);
 }
 
 #define LSMG_INST(T) \
     template void launch_smooth_colour<T>(int, const LevelDesc<T> *, const int4 *, int, int, hipStream_t); \
-    template void launch_ghost<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
+    template void launch_ghost<T>(int, const LevelDesc<T> *, int, const int4 *, int, int, int, bool, hipStream_t); \
     template void launch_defect<T>(int, const LevelDesc<T> *, const int4 *, int, unsigned long long *, hipStream_t); \
     template void launch_apply_J<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
     template void launch_band<T>(const LevelDesc<T> *, const int4 *, int, hipStream_t); \
     template void launch_restrict<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
     template void launch_prolong<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
     template void launch_inject<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
+    template void launch_tail<T>(int, const LevelDesc<T> *, const TailArgs &, int, hipStream_t); \
     template void launch_gather_compact<T>(const int *, int, const T *, const T *, double *, hipStream_t); \
     template void launch_scatter_compact<T>(const int *, int, const double *, T *, T *, hipStream_t); \
     template void launch_fill<T>(T *, long long, T, hipStream_t); \
-    template void launch_coarse_solve<T>(const LevelDesc<T> *, int, int, const int *, const double *, const int *, \
-                                         hipStream_t);
+    template void launch_coarse_apply<T>(const LevelDesc<T> *, int, int, const int *, const double *, hipStream_t);
 LSMG_INST(double)
 LSMG_INST(float)
 template void launch_fill<int>(int *, long long, int, hipStream_t);

@@ -53,9 +53,16 @@ struct LevelDesc {
     T *r_s, *r_c;
     // ghost table (structure of arrays, entry k of ghost q at k * ng + q)
     const int *g_idx;        // storage index of ghost q
+    const int *g_ijk;        // packed grid coordinates i | j << 11 | k << 22
     const int *g_st;         // storage index of stencil node k
+    const int *g_stg;        // ghost index of stencil node k if it is a ghost with nonzero weight, else -1
     const T *g_w;            // boundary-row weight of stencil node k
-    T *g_tmp, *g_old;        // Jacobi buffers
+    T *g_buf0, *g_buf1;      // Jacobi buffers of the ghost values of delta s
+    // ghost_sweeps Jacobi sweeps composed into one linear map (CSR over ghosts):
+    // delta s_q <- sum_e go_a[e] delta s_{go_col[e]} + go_b[e] b_{go_col[e]}, b the
+    // ghost rows' right-hand sides minus their non-ghost stencil terms
+    const int *go_ptr, *go_col;
+    const T *go_a, *go_b;
     // band of inactive nodes used by the boundary-defect restriction
     const int *b_idx;        // storage index of band node b
     const int *b_cnt;        // number of ghost sources
@@ -74,10 +81,18 @@ __device__ __forceinline__ void node_coords(int n, int colour, long long row, in
         j = (int)row;
         k = 0;
     } else {
-        j = (int)(row % n);
-        k = (int)(row / n);
+        const int r = (int)row;
+        k = r / n;
+        j = r - k * n;
     }
     i = 2 * p + ((colour + j + k) & 1);
+}
+
+__device__ __forceinline__ void unpack_ijk(int v, int &i, int &j, int &k)
+{
+    i = v & 2047;
+    j = (v >> 11) & 2047;
+    k = (v >> 22) & 1023;
 }
 
 __device__ __forceinline__ long long sidx(int n, int Wp, long long cs, int i, int j, int k)
@@ -119,10 +134,15 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// A norm is kept in kNormSlots partial slots (the host takes their max): each
+// wavefront folds its lanes and one lane updates slot blockIdx.x % kNormSlots,
+// which keeps atomics on any one address to a few per microsecond.
+constexpr int kNormSlots = 64;
+
 __device__ __forceinline__ void norm_accumulate(unsigned long long *slot, unsigned long long bits)
 {
     bits = wave_max_u64(bits);
-    if ((threadIdx.x & (kWave - 1)) == 0 && bits != 0ull) atomicMax(slot, bits);
+    if ((threadIdx.x & (kWave - 1)) == 0 && bits != 0ull) atomicMax(slot + (blockIdx.x & (kNormSlots - 1)), bits);
 }
 
 }  // namespace lsmg

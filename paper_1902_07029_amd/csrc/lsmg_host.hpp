@@ -9,6 +9,24 @@
 
 namespace lsmg {
 
+// ghost sets up to this size are relaxed by one workgroup per smoothing step
+constexpr int kGhostFusedMax = 256;
+// levels with at most this many active nodes run inside the coarse-tail kernel
+constexpr int kTailMaxNodes = 1024;
+constexpr int kMaxLevels = 16;
+
+struct TailLevel {
+    const int *in_ijk;   // packed coordinates of the inside nodes, colour 0 then colour 1
+    int nin0, nin1;
+};
+
+struct TailArgs {
+    int l0, nlev, nu1, nu2, ghost_sweeps, pad;
+    const int *c2s;      // coarsest level: compact -> storage
+    const double *ainv;  // coarsest level: explicit inverse (FP64, 2Na x 2Na)
+    TailLevel lev[kMaxLevels];
+};
+
 struct StepArgsHost {
     const double *sn, *cn;
     double *bs, *bc;
@@ -19,7 +37,9 @@ struct StepArgsHost {
 
 // ---- V-cycle and Newton kernels (kernels.hip) ----
 template <typename T> void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int colour, hipStream_t s);
-template <typename T> void launch_ghost(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
+template <typename T> void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, int ng, int sweeps,
+                                        bool composed, hipStream_t s);
+template <typename T> void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs &a, int ncoarse, hipStream_t s);
 template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, unsigned long long *slot, hipStream_t s);
 template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
 template <typename T> void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
@@ -43,10 +63,11 @@ void launch_compact_to_grid(const int64_t *c2g, int na, const double *a, const d
                             double *gc, hipStream_t s);
 void launch_grid_to_split(const int64_t *c2g, int na, const double *gs, const double *gc, const int *c2s, double *a,
                           double *b, hipStream_t s);
-void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, const int *c2s, double *A, int *piv, int *status,
-                          hipStream_t s);
-template <typename T> void launch_coarse_solve(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *A,
-                                               const int *piv, hipStream_t s);
+// builds the coarsest operator and its inverse (FP64); M: 2N^2 doubles of scratch
+void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, int N, const int *c2s, double *M, double *Ainv,
+                          int *status, hipStream_t s);
+template <typename T> void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *Ainv,
+                                               hipStream_t s);
 
 // ---- hierarchy build (build.hip) ----
 struct BuildLevel {
@@ -68,10 +89,13 @@ void launch_c2s(int dim, const int64_t *c2g, int na, int n, int Wp, long long cs
 // inside-segment work items of a level: returns the item count per colour (synchronises)
 void build_segments(int dim, const uint8_t *type_split, int n, int Wp, long long rows, long long cs, int desc,
                     int4 **out_items, int *out_count, hipStream_t s);
+// packed coordinates of the inside nodes of each colour (out: ni ints, colour 0 then 1)
+int build_inside_lists(int dim, const int64_t *c2g, int ni, int n, int *out, int *count, int64_t *scratch,
+                       int nscratch, hipStream_t s);
 void launch_ghost_geometry(int dim, int level, const double *phi, const uint8_t *type_split, const int64_t *c2g_ghost,
-                           const int *cmap, int ng, int n, int Wp, long long cs, double lo, double h, int *g_idx,
-                           int *g_st, int *g_stc, double *g_w, double *g_B, double *g_nrm, int *g_order, int *g_bfall,
-                           int *err, hipStream_t s);
+                           const int *cmap, int ni, int ng, int n, int Wp, long long cs, double lo, double h, int *g_idx,
+                           int *g_ijk, int *g_st, int *g_stg, int *g_stc, double *g_w, double *g_B, double *g_nrm,
+                           int *g_order, int *g_bfall, int *err, hipStream_t s);
 void launch_band_mark(int dim, const int64_t *c2g_cghost, int ngc, int nc, const uint8_t *ftype_split, int nf, int fWp,
                       long long fcs, uint8_t *flag_lin, hipStream_t s);
 void launch_band_geometry(int dim, const double *phi, const int64_t *band_lin, int nb, const uint8_t *type_split,
