@@ -196,8 +196,9 @@ def main():
         for _ in range(args.parity_steps):
             st2.step(w["dt"])
             states.append(st2.get().cpu().numpy())
-        op = {k: getattr(params, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
-                                               "ghost_c_new", "band_steps", "ghost_sweeps")}
+        eff = H.params
+        op = {k: getattr(eff, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
+                                            "ghost_c_new", "band_steps", "ghost_sweeps")}
         cpu, parity = cpu_baseline(w, op, args.cpu_budget, states)
 
     lat_ms = np.array(lat) * 1e3
@@ -219,7 +220,7 @@ def main():
             "workload": f"{args.workload}_{'fp64' if args.precision == 0 else 'mixed'}",
             "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": w["dt"], "coarsest": w["coarsest"],
             "unknowns": unknowns, "inside": ni, "ghost": ng, "levels": H.nlev,
-            "cycle": f"V({params.nu1},{params.nu2}) red-black, {params.ghost_sweeps} ghost sweeps",
+            "cycle": f"V({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps",
             "build_ms": round(build_ms, 1),
         },
         "vcycles": cycles,

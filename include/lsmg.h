@@ -65,7 +65,7 @@ typedef struct {
     /* ghost-row relaxation parameter tau^s of eq. (RelGhost), 0 < tau_s < 1 (eq. CFLcond) */
     double tau_s;
     int nu1, nu2;          /* pre- and post-smoothing steps of the V-cycle */
-    int ghost_sweeps;      /* ghost relaxations per smoothing step (>= 1) */
+    int ghost_sweeps;      /* ghost relaxations per smoothing step; 0: 5 in 2-D, 15 in 3-D */
     int band_steps;        /* layers of the boundary-defect extension (section 3.5.2) */
     int ghost_c_new;       /* 1: the ghost c-row relaxation uses the new delta s */
     int coarsest_n;        /* nodes per axis of the coarsest grid (>= 3) */
@@ -89,8 +89,9 @@ typedef struct {
 } lsmg_step_stats;
 
 /* Default parameters: the model data of eq. (dataeq), tau_s = 0.9 (section
- * 3.5.1), V(2,2), 5 ghost sweeps, 3 band layers, ghost_c_new = 1, coarsest 5,
- * FP64, newton_tol 1e-10, newton_max 20, lin_rtol 1e-3, cycles_max 30. */
+ * 3.5.1), V(2,2), automatic ghost sweeps (0), 3 band layers, ghost_c_new = 1,
+ * coarsest 5, FP64, newton_tol 1e-10, newton_max 20, lin_rtol 1e-3,
+ * cycles_max 30. */
 void lsmg_default_params(lsmg_params *p);
 
 /* Build the grid hierarchy of one domain (sections 3.2-3.3, 3.5).
@@ -113,6 +114,9 @@ void lsmg_destroy_hierarchy(lsmg_hierarchy *h);
 
 /* Replace the solver parameters (the model constants and the grid are fixed at build). */
 lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params);
+
+/* Parameters in effect (host out), with automatic choices resolved. */
+lsmg_status lsmg_get_params(const lsmg_hierarchy *h, lsmg_params *params);
 
 /* Number of levels (host out). */
 lsmg_status lsmg_num_levels(const lsmg_hierarchy *h, int *nlev);

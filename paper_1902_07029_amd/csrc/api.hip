@@ -169,7 +169,7 @@ int ipow(int b, int e)
 lsmg_status check_params(const lsmg_params *p)
 {
     if (!p) return fail(LSMG_EINVAL, "params is NULL");
-    if (!(p->tau_s > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->ghost_sweeps < 1 || p->band_steps < 0 ||
+    if (!(p->tau_s > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->ghost_sweeps < 0 || p->band_steps < 0 ||
         p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
         !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1))
         return fail(LSMG_EINVAL, "invalid solver parameters");
@@ -915,7 +915,7 @@ void lsmg_default_params(lsmg_params *p)
     p->tau_s = 0.9;
     p->nu1 = 2;
     p->nu2 = 2;
-    p->ghost_sweeps = 5;
+    p->ghost_sweeps = 0;
     p->band_steps = 3;
     p->ghost_c_new = 1;
     p->coarsest_n = 5;
@@ -940,6 +940,7 @@ lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid
     lsmg_hierarchy *H = new (std::nothrow) lsmg_hierarchy();
     if (!H) return fail(LSMG_EOOM, "host allocation");
     H->p = *params;
+    if (H->p.ghost_sweeps == 0) H->p.ghost_sweeps = grid->dim == 2 ? 5 : 15;
     H->stream = (hipStream_t)stream;
     // LSMG_GRAPHS=0 replays the V-cycle as direct launches instead of a captured graph
     if (const char *e = std::getenv("LSMG_GRAPHS")) H->use_graphs = std::atoi(e) != 0;
@@ -966,7 +967,8 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
     LSMGCHK(check_params(params));
     if (params->coarsest_n != h->p.coarsest_n || params->band_steps != h->p.band_steps)
         return fail(LSMG_EINVAL, "coarsest_n and band_steps are fixed at build");
-    const bool ghost_ops_change = params->ghost_sweeps != h->p.ghost_sweeps || params->tau_s != h->p.tau_s ||
+    const int sweeps = params->ghost_sweeps > 0 ? params->ghost_sweeps : (h->dim == 2 ? 5 : 15);
+    const bool ghost_ops_change = sweeps != h->p.ghost_sweeps || params->tau_s != h->p.tau_s ||
                                   params->ghost_c_new != h->p.ghost_c_new;
     invalidate_graphs(h);
     if (params->precision == 1 && !h->have32) {
@@ -974,10 +976,18 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
         LSMGCHK(build_f32(h));
     }
     h->p = *params;
+    h->p.ghost_sweeps = sweeps;
     if (ghost_ops_change)
         for (int l = 0; l < h->nlev; ++l) LSMGCHK(build_ghost_ops(h, l));
     make_descs(h);
     return push_desc(h);
+}
+
+lsmg_status lsmg_get_params(const lsmg_hierarchy *h, lsmg_params *params)
+{
+    if (!h || !params) return fail(LSMG_EINVAL, "NULL argument");
+    *params = h->p;
+    return LSMG_OK;
 }
 
 lsmg_status lsmg_num_levels(const lsmg_hierarchy *h, int *nlev)

@@ -448,8 +448,19 @@ __device__ __forceinline__ void inject_elem(const LevelDesc<T> *C, int4 w, int l
 // ---------------------------------------------------------------------------
 // per-item kernels (fine levels): one wavefront per work item
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// The logical block number gives XCD x a contiguous range of work items, so the
+// rows above and below an item (its y and z neighbours) are mostly processed by
+// the same XCD and found in its L2.
+__device__ __forceinline__ int logical_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
 #define LSMG_ITEM_PROLOGUE                                                          \
-    const int it = blockIdx.x * kItemsPerBlock + (threadIdx.x >> 6);               \
+    const int it = logical_block() * kItemsPerBlock + (threadIdx.x >> 6);          \
     if (it >= nwork) return;                                                       \
     const int4 w = work[it];                                                       \
     const int lane = threadIdx.x & 63;
@@ -507,6 +518,37 @@ __global__ __launch_bounds__(kBlock) void k_ghost_apply(const LevelDesc<T> *__re
     LSMG_ITEM_PROLOGUE
     const int q = w.z + lane;
     if (q < w.w) ghost_apply_elem<T>(descs + item_desc(w), q);
+}
+
+// the same for long composed rows (3-D): 16 lanes share a row, each wavefront
+// walks the 64 ghosts of its item four rows at a time with coalesced reads
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ghost_apply_grouped(const LevelDesc<T> *__restrict__ descs,
+                                                                const int4 *__restrict__ work, int nwork)
+{
+    LSMG_ITEM_PROLOGUE
+    const LevelDesc<T> *D = descs + item_desc(w);
+    const int sub = lane & 15, grp = lane >> 4;
+    for (int q0 = w.z; q0 < w.w; q0 += 4) {
+        const int q = q0 + grp;
+        T v = 0;
+        if (q < w.w) {
+            const int e0 = D->go_ptr[q], e1 = D->go_ptr[q + 1];
+            for (int e = e0 + sub; e < e1; e += 16) {
+                const int c = D->go_col[e];
+                v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
+            }
+        }
+        for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+        if (q < w.w && sub == 0) {
+            const long long g = D->g_idx[q];
+            D->x_s[g] = v;
+            T cs_d, cc_d;
+            c_row<T>(D, g, cs_d, cc_d);
+            const T xc = D->x_c[g];
+            D->x_c[g] = xc + (D->rhs_c[g] - (cs_d * v + cc_d * xc)) / cc_d;
+        }
+    }
 }
 
 // all ghost sweeps of one level in one workgroup (sweep by sweep)
@@ -915,9 +957,12 @@ __global__ void k_grid_to_split(const int64_t *__restrict__ c2g, int na, const d
 
 // ---------------------------------------------------------------------------
 // coarsest level (FP64): the dense 2Na x 2Na operator assembled from the same
-// rows and inverted by Gauss-Jordan elimination with partial pivoting on
-// [A | I], in LDS when it fits, in one workgroup
+// rows and inverted in place by Gauss-Jordan elimination with partial (row)
+// pivoting, in LDS when it fits, in one workgroup; the row interchanges are
+// undone as column interchanges at the end
 // ---------------------------------------------------------------------------
+constexpr int kMaxCoarseN = 1024;
+
 template <int DIM, int NST>
 __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> *__restrict__ descs, int lev,
                                                         const int *__restrict__ c2s, double *__restrict__ Mglob,
@@ -925,16 +970,15 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
 {
     extern __shared__ double Mlds[];
     const LevelDesc<double> *D = descs + lev;
-    const int na = D->na, ni = D->ni, N = 2 * na, N2 = 2 * N;
-    double *M = use_lds ? Mlds : Mglob;     // row-major N x 2N
+    const int na = D->na, ni = D->ni, N = 2 * na;
+    double *M = use_lds ? Mlds : Mglob;     // row-major N x N
     const int tid = threadIdx.x, nt = blockDim.x;
-    __shared__ double fac[1024];
-    __shared__ double s_pv;
+    const int lane = tid & (kWave - 1), wv = tid >> 6, nwv = nt >> 6;
+    __shared__ double fac[kMaxCoarseN];
+    __shared__ int piv[kMaxCoarseN];
     __shared__ int s_pr, s_bad;
-    for (long long e = tid; e < (long long)N * N2; e += nt) {
-        const int r = (int)(e / N2), c = (int)(e % N2);
-        M[e] = (c - N == r) ? 1.0 : 0.0;
-    }
+    for (int r = wv; r < N; r += nwv)
+        for (int c = lane; c < N; c += kWave) M[r * N + c] = 0.0;
     if (tid == 0) s_bad = 0;
     __syncthreads();
     // rows of the Jacobian on the coarsest level (section 3.4)
@@ -948,7 +992,7 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
         node_coords<DIM>(D->n, (int)colour, row, p, i, j, k);
         double cs_d, cc_d;
         c_row<double>(D, idx, cs_d, cc_d);
-        double *Rs = M + (long long)r * N2, *Rc = M + (long long)(na + r) * N2;
+        double *Rs = M + r * N, *Rc = M + (na + r) * N;
         if (r < ni) {
             long long nb[2 * DIM];
             neighbours<DIM>(D->n, D->Wp, D->cs, (int)colour, row, i, p, nb);
@@ -985,7 +1029,7 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
             double best = -1.0;
             int bi = N;
             for (int i2 = kc + tid; i2 < N; i2 += kWave) {
-                const double v = fabs(M[(long long)i2 * N2 + kc]);
+                const double v = fabs(M[i2 * N + kc]);
                 if (v > best) { best = v; bi = i2; }
             }
             for (int off = 32; off > 0; off >>= 1) {
@@ -995,7 +1039,7 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
             }
             if (tid == 0) {
                 s_pr = bi;
-                s_pv = best;
+                piv[kc] = bi;
                 if (!(best > 0.0) || bi >= N) s_bad = 1;
             }
         }
@@ -1003,29 +1047,42 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
         if (s_bad) break;
         const int pr = s_pr;
         if (pr != kc)
-            for (int c = kc + tid; c < N2; c += nt) {
-                const double t = M[(long long)kc * N2 + c];
-                M[(long long)kc * N2 + c] = M[(long long)pr * N2 + c];
-                M[(long long)pr * N2 + c] = t;
+            for (int c = tid; c < N; c += nt) {
+                const double t = M[kc * N + c];
+                M[kc * N + c] = M[pr * N + c];
+                M[pr * N + c] = t;
             }
         __syncthreads();
-        const double inv = 1.0 / M[(long long)kc * N2 + kc];
+        const double inv = 1.0 / M[kc * N + kc];
+        for (int i2 = tid; i2 < N; i2 += nt) fac[i2] = M[i2 * N + kc];
         __syncthreads();
-        for (int c = kc + tid; c < N2; c += nt) M[(long long)kc * N2 + c] *= inv;
-        for (int i2 = tid; i2 < N; i2 += nt) fac[i2 & 1023] = M[(long long)i2 * N2 + kc];
+        // pivot row: column kc becomes 1/pivot, the rest is scaled
+        for (int c = tid; c < N; c += nt) M[kc * N + c] = (c == kc ? 1.0 : M[kc * N + c]) * inv;
         __syncthreads();
-        const int width = N2 - kc;
-        for (long long e = tid; e < (long long)N * width; e += nt) {
-            const int i2 = (int)(e / width), c = kc + (int)(e % width);
+        // other rows: column kc becomes -f/pivot, the rest loses f times the pivot row
+        for (int i2 = wv; i2 < N; i2 += nwv) {
             if (i2 == kc) continue;
-            M[(long long)i2 * N2 + c] -= fac[i2 & 1023] * M[(long long)kc * N2 + c];
+            const double f = fac[i2];
+            double *Ri = M + i2 * N;
+            const double *Rk = M + kc * N;
+            for (int c = lane; c < N; c += kWave) Ri[c] = (c == kc ? 0.0 : Ri[c]) - f * Rk[c];
         }
         __syncthreads();
     }
-    for (long long e = tid; e < (long long)N * N; e += nt) {
-        const int r = (int)(e / N), c = (int)(e % N);
-        Ainv[e] = M[(long long)r * N2 + N + c];
-    }
+    // undo the row interchanges as column interchanges, last first
+    if (!s_bad)
+        for (int kc = N - 1; kc >= 0; --kc) {
+            const int pr = piv[kc];
+            if (pr != kc)
+                for (int r = tid; r < N; r += nt) {
+                    const double t = M[r * N + kc];
+                    M[r * N + kc] = M[r * N + pr];
+                    M[r * N + pr] = t;
+                }
+            __syncthreads();
+        }
+    for (int r = wv; r < N; r += nwv)
+        for (int c = lane; c < N; c += kWave) Ainv[r * N + c] = M[r * N + c];
     if (tid == 0) *status = s_bad ? 1 : 0;
 }
 
@@ -1060,7 +1117,8 @@ void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int n
     if (nw <= 0) return;
     if (composed) {
         LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_b<T, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
-        k_ghost_apply<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
+        if (dim == 3) k_ghost_apply_grouped<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
+        else k_ghost_apply<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
         return;
     }
     if (ng <= kGhostFusedMax) {
@@ -1196,13 +1254,24 @@ void launch_grid_to_split(const int64_t *c2g, int na, const double *gs, const do
     k_grid_to_split<<<(na + 255) / 256, 256, 0, s>>>(c2g, na, gs, gc, c2s, a, b);
 }
 
+// dynamic LDS for the coarsest matrix: 147 KiB of the 160 KiB of a gfx950 CU
+// (the kernel's own shared arrays take 12 KiB)
+constexpr size_t kCoarseLdsMax = 147 * 1024;
+
 void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, int N, const int *c2s, double *M,
                           double *Ainv, int *status, hipStream_t s)
 {
-    const size_t bytes = (size_t)N * 2 * N * sizeof(double);
-    const int use_lds = bytes <= 64 * 1024;
-    LSMG_DISPATCH_DIM(dim, k_coarse_invert<DIM, NST><<<1, 1024, use_lds ? bytes : 0, s>>>(d, lev, c2s, M, Ainv, use_lds,
-                                                                                          status));
+    const size_t bytes = (size_t)N * N * sizeof(double);
+    const int use_lds = bytes <= kCoarseLdsMax;
+    LSMG_DISPATCH_DIM(dim, {
+        static bool attr_set = false;
+        if (use_lds && bytes > 64 * 1024 && !attr_set) {
+            (void)hipFuncSetAttribute((const void *)k_coarse_invert<DIM, NST>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLdsMax);
+            attr_set = true;
+        }
+        k_coarse_invert<DIM, NST><<<1, 1024, use_lds ? bytes : 0, s>>>(d, lev, c2s, M, Ainv, use_lds, status);
+    });
 }
 
 template <typename T>

@@ -135,14 +135,15 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 }
 
 // A norm is kept in kNormSlots partial slots (the host takes their max): each
-// wavefront folds its lanes and one lane updates slot blockIdx.x % kNormSlots,
-// which keeps atomics on any one address to a few per microsecond.
-constexpr int kNormSlots = 64;
+// wavefront folds its lanes and one lane updates the slot of its wavefront
+// number, which keeps the atomics on any one address few.
+constexpr int kNormSlots = 256;
 
 __device__ __forceinline__ void norm_accumulate(unsigned long long *slot, unsigned long long bits)
 {
     bits = wave_max_u64(bits);
-    if ((threadIdx.x & (kWave - 1)) == 0 && bits != 0ull) atomicMax(slot + (blockIdx.x & (kNormSlots - 1)), bits);
+    const int wslot = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kNormSlots - 1);
+    if ((threadIdx.x & (kWave - 1)) == 0 && bits != 0ull) atomicMax(slot + wslot, bits);
 }
 
 }  // namespace lsmg

@@ -64,6 +64,7 @@ def load():
         "lsmg_build_hierarchy": (_i, [_vp, ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]),
         "lsmg_destroy_hierarchy": (None, [_vp]),
         "lsmg_set_params": (_i, [_vp, ctypes.POINTER(Params)]),
+        "lsmg_get_params": (_i, [_vp, ctypes.POINTER(Params)]),
         "lsmg_num_levels": (_i, [_vp, ctypes.POINTER(_i)]),
         "lsmg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_i),
                                  ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -145,6 +146,12 @@ class Hierarchy:
         nl = _i()
         _check(lib.lsmg_num_levels(h, ctypes.byref(nl)), "lsmg_num_levels")
         self.nlev = nl.value
+        self.params = self.get_params()
+
+    def get_params(self):
+        p = Params()
+        _check(load().lsmg_get_params(self._h, ctypes.byref(p)), "lsmg_get_params")
+        return p
 
     def close(self):
         if getattr(self, "_h", None):
@@ -159,7 +166,7 @@ class Hierarchy:
 
     def set_params(self, params):
         _check(load().lsmg_set_params(self._h, ctypes.byref(params)), "lsmg_set_params")
-        self.params = params
+        self.params = self.get_params()
 
     def level_info(self, l):
         n, h, ni, ng, nb = _i(), _d(), _i(), _i(), _i()

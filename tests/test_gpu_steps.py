@@ -60,6 +60,13 @@ def test_torus_65(precision):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("precision", [1, 0])
+def test_torus_257_full_size(precision):
+    # the 3-D configuration at its full size: one step checked against the oracle
+    _run("torus", 257, 9, 1e-4, 1, precision)
+
+
+@pytest.mark.gpu
 def test_manufactured_solution_steps():
     n = 65
     H, O = pair("disk", n, 5)
