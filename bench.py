@@ -3,6 +3,14 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star1025|torus257|disk65]
                     [--precision 0|1] [--no-cpu-baseline]
 
+Profiling helpers (they print text, not the benchmark line):
+    python bench.py --copy-probe MIB          one plain device copy kernel over MIB MiB, 5 times
+    python bench.py --trace-summary DIR       kernel table of a rocprofv3 --kernel-trace --stats run
+    python bench.py --traffic FETCH WRITE COPY_FETCH COPY_WRITE [--copy-mib M]
+                                              HBM bytes per launch of the finest-level smoother
+                                              from four rocprofv3 --pmc runs; updates
+                                              profiles/traffic.json
+
 A step is one Crank-Nicolson step: Newton iterations whose linear systems are
 solved by V-cycles, on synthetic seeded inputs already resident in HBM.  The
 metric is V-cycle throughput, 2 (Ni + Ng) finest unknowns times the V-cycles
@@ -107,6 +115,111 @@ def cpu_baseline(w, params, budget_s, gpu_states):
         dict(steps_checked=steps, max_rel_err=worst)
 
 
+# ---------------------------------------------------------------- profiling helpers
+
+SMOOTH_KERNEL = "k_smooth_colour"
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    rows = []
+    for f in files:
+        rows.extend(csv.DictReader(open(f)))
+    return rows
+
+
+def _short(name):
+    name = name.replace("void ", "")
+    head = name.split("(")[0]
+    return head.replace("lsmg::", "")
+
+
+def copy_probe(mib):
+    """A plain elementwise copy (dst = -src) over mib MiB, five launches: the
+    reference kernel of known size for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
+
+
+def _finest(rows, key):
+    """Rows of the finest-level smoother: the k_smooth_colour dispatches whose grid is
+    at least half the largest grid (the next coarser level has about a quarter)."""
+    sm = [r for r in rows if SMOOTH_KERNEL in r["Kernel_Name"]]
+    if not sm:
+        raise SystemExit("no smoother dispatches in the profile")
+    gmax = max(int(r[key]) for r in sm)
+    return [r for r in sm if 2 * int(r[key]) >= gmax]
+
+
+def trace_summary(directory):
+    stats = _csv_rows(directory, "kernel_stats.csv")
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in stats)
+    print(f"{'calls':>7} {'total ms':>9} {'share':>6} {'avg us':>8}  kernel")
+    for r in stats[:20]:
+        t = float(r["TotalDurationNs"])
+        print(f"{int(r['Calls']):7d} {t / 1e6:9.3f} {100 * t / total:5.1f}% {float(r['AverageNs']) / 1e3:8.2f}  "
+              f"{_short(r['Name'])}")
+    trace = _csv_rows(directory, "kernel_trace.csv")
+    sm = [r for r in trace if SMOOTH_KERNEL in r["Kernel_Name"]]
+    by = {}
+    for r in sm:
+        g = int(r["Grid_Size_X"]) if "Grid_Size_X" in r else int(r["Grid_Size"])
+        by.setdefault(g, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    print(f"\n{SMOOTH_KERNEL} by grid size (threads), from the kernel trace:")
+    for g in sorted(by, reverse=True):
+        v = by[g]
+        print(f"  grid {g:9d}  launches {len(v):6d}  avg {sum(v) / len(v) / 1e3:8.2f} us")
+    fin = _finest(trace, "Grid_Size_X" if "Grid_Size_X" in trace[0] else "Grid_Size")
+    d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in fin]
+    print(f"finest level: {len(d)} launches, average {sum(d) / len(d) / 1e3:.2f} us")
+
+
+def _pmc_per_dispatch(directory, counter, finest):
+    rows = [r for r in _csv_rows(directory, "counter_collection.csv") if r["Counter_Name"] == counter]
+    if finest:
+        rows = _finest(rows, "Grid_Size")
+    vals = [float(r["Counter_Value"]) for r in rows]
+    if not vals:
+        raise SystemExit(f"no {counter} values under {directory}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def _pmc_copy(directory, counter, mib):
+    rows = [r for r in _csv_rows(directory, "counter_collection.csv") if r["Counter_Name"] == counter]
+    big = max(float(r["Counter_Value"]) for r in rows)
+    rows = [float(r["Counter_Value"]) for r in rows if float(r["Counter_Value"]) > 0.5 * big]
+    kib = sum(rows) / len(rows)
+    return (mib * 1024.0) / kib
+
+
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, precision, mib):
+    f_kib, nf = _pmc_per_dispatch(fetch_dir, "FETCH_SIZE", True)
+    w_kib, nw = _pmc_per_dispatch(write_dir, "WRITE_SIZE", True)
+    sf = _pmc_copy(copy_fetch_dir, "FETCH_SIZE", mib)
+    sw = _pmc_copy(copy_write_dir, "WRITE_SIZE", mib)
+    fetch_b = f_kib * 1024 * sf
+    write_b = w_kib * 1024 * sw
+    key = f"smooth_colour:{workload}:p{precision}"
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    data[key] = dict(bytes_per_launch=int(fetch_b + write_b), fetch_bytes=int(fetch_b), write_bytes=int(write_b),
+                     fetch_kib_raw=f_kib, write_kib_raw=w_kib, copy_scale_fetch=sf, copy_scale_write=sw,
+                     dispatches=[nf, nw], source_hash=source_hash())
+    json.dump(data, open(path, "w"), indent=1, sort_keys=True)
+    print(json.dumps({key: data[key]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,7 +230,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--parity-steps", type=int, default=6)
+    ap.add_argument("--copy-probe", type=int, metavar="MIB")
+    ap.add_argument("--trace-summary", metavar="DIR")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
+    ap.add_argument("--copy-mib", type=int, default=512)
     args = ap.parse_args()
+    if args.trace_summary:
+        return trace_summary(args.trace_summary)
+    if args.traffic:
+        return traffic(*args.traffic, args.workload, args.precision, args.copy_mib)
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
               "described in DESIGN.md and not built", file=sys.stderr)
