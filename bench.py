@@ -1,7 +1,12 @@
 """Benchmark of the level-set multigrid Crank-Nicolson step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star1025|torus257|disk65]
-                    [--precision 0|1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star1025|torus257|disk65|batch64]
+                    [--precision 0|1] [--no-cpu-baseline] [--no-sequential]
+
+Workloads: star1025 (default, FP64), torus257 and disk65 are single domains;
+batch64 is 64 star domains of grid sizes 129^2 .. 1025^2 stepped together in
+mixed precision (one launch per kernel and grid size), reported beside the same
+domains stepped one after another with the plain FP64 path.
 
 Profiling helpers (they print text, not the benchmark line):
     python bench.py --copy-probe MIB          one plain device copy kernel over MIB MiB, 5 times
@@ -82,15 +87,15 @@ def load_traffic(kernel, workload, precision):
     return None
 
 
-def cpu_baseline(w, params, budget_s, gpu_states):
-    """The oracle (serial, one core) on the first steps of the same workload; its
-    states also give a parity check of the GPU trajectory."""
+def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label):
+    """The oracle (serial, one core) on the first steps of a domain of the workload;
+    its states also give a parity check of the GPU trajectory (gpu_states[k] is the
+    compact GPU state after step k + 1)."""
     import oracle
-    phi = levelset(w)
-    O = oracle.Hierarchy(phi, w["dim"], w["n"], coarsest_n=w["coarsest"], params=params)
+    O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=params)
     info = O.level_info(0)
     na = info["na"]
-    s0, c0 = I.initial_state(w["n"], w["dim"])
+    s0, c0 = I.initial_state(n, dim)
     W = O.to_compact(0, s0, c0)
     sb = np.ones(info["ng"])
     cycles = 0
@@ -98,7 +103,7 @@ def cpu_baseline(w, params, budget_s, gpu_states):
     steps = 0
     t0 = time.perf_counter()
     while steps < len(gpu_states):
-        rc, W, st = O.newton_cn_step(W, w["dt"], sb)
+        rc, W, st = O.newton_cn_step(W, dt, sb)
         if rc != 0:
             raise RuntimeError(f"oracle step failed with {rc}")
         cycles += st["vcycles"]
@@ -110,9 +115,15 @@ def cpu_baseline(w, params, budget_s, gpu_states):
             break
     el = time.perf_counter() - t0
     return dict(value=2 * na * cycles / el, unit="unknowns*cycles/s", cores=1, kind="oracle",
-                sample=f"first {steps} Crank-Nicolson steps of {w['kind']} {w['n']}^{w['dim']} "
-                       f"({cycles} V-cycles, {el:.1f} s, serial C, one host core)"), \
-        dict(steps_checked=steps, max_rel_err=worst)
+                sample=f"first {steps} Crank-Nicolson steps of {label} ({cycles} V-cycles, {el:.1f} s, "
+                       f"serial C, one host core)"), \
+        dict(steps_checked=steps, max_rel_err=worst, domain=label)
+
+
+def oracle_params(H):
+    eff = H.params
+    return {k: getattr(eff, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
+                                         "ghost_c_new", "band_steps", "ghost_sweeps")}
 
 
 # ---------------------------------------------------------------- profiling helpers
@@ -220,39 +231,15 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, prec
     print(json.dumps({key: data[key]}))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", type=int, default=0, choices=(0, 1))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--parity-steps", type=int, default=6)
-    ap.add_argument("--copy-probe", type=int, metavar="MIB")
-    ap.add_argument("--trace-summary", metavar="DIR")
-    ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
-    ap.add_argument("--copy-mib", type=int, default=512)
-    args = ap.parse_args()
-    if args.trace_summary:
-        return trace_summary(args.trace_summary)
-    if args.traffic:
-        return traffic(*args.traffic, args.workload, args.precision, args.copy_mib)
-    if args.copy_probe:
-        return copy_probe(args.copy_probe)
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not built", file=sys.stderr)
-        sys.exit(2)
-
+def run_single(args):
     import torch
     from paper_1902_07029_amd import lsmg
 
-    torch.cuda.set_device(0)
     w = WORKLOADS[args.workload]
-    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=args.precision)
-    phi = torch.from_numpy(levelset(w)).cuda()
+    prec = args.precision if args.precision is not None else 0
+    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec)
+    phi_np = levelset(w)
+    phi = torch.from_numpy(phi_np).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     H = lsmg.Hierarchy(phi, w["dim"], w["n"], params=params)
@@ -285,8 +272,8 @@ def main():
         newton += stats["newton_iters"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    # kernel timing pass: the next K steps of the same run with every launch of the
-    # dominant kernel bracketed by HIP events on the hierarchy's stream
+    # kernel timing pass: the next K steps of the same run, every finest-level
+    # smoother launch timed by its own dispatch events on the hierarchy's stream
     H.profile_start(lsmg.KERNEL_SMOOTH, 0)
     prof_t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -298,37 +285,32 @@ def main():
         raise RuntimeError("no timed launches of the dominant kernel")
 
     # roofline of the dominant kernel: one colour of the finest-level smoother
-    P = 8 if args.precision == 0 else 4
+    P = 8 if prec == 0 else 4
     b0, b1 = smoother_bytes(H.compact_to_grid(0).cpu().numpy(), ni, ng, w["n"], w["dim"], P)
     bytes_per_launch = 0.5 * (b0 + b1)
-    avg_s = prof_ms * 1e-3 / max(launches, 1)
+    avg_s = prof_ms * 1e-3 / launches
     achieved = bytes_per_launch / avg_s / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=load_traffic("smooth_colour", args.workload, args.precision),
+                    traffic=load_traffic("smooth_colour", args.workload, prec),
                     kernel="k_smooth_colour (finest level, one colour)", launches=launches,
                     avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(bytes_per_launch),
                     timing_pass_ms_per_step=round(prof_elapsed * 1e3 / args.steps, 3))
 
-    cpu = None
-    parity = None
+    cpu = parity = None
     if not args.no_cpu_baseline:
-        # GPU trajectory from the initial state for the parity check
         st2 = fresh_state()
         states = []
         for _ in range(args.parity_steps):
             st2.step(w["dt"])
             states.append(st2.get().cpu().numpy())
-        eff = H.params
-        op = {k: getattr(eff, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
-                                            "ghost_c_new", "band_steps", "ghost_sweeps")}
-        cpu, parity = cpu_baseline(w, op, args.cpu_budget, states)
+        cpu, parity = cpu_baseline(phi_np, w["dim"], w["n"], w["coarsest"], w["dt"], oracle_params(H),
+                                   args.cpu_budget, states, f"{w['kind']} {w['n']}^{w['dim']}")
 
     lat_ms = np.array(lat) * 1e3
-    value = unknowns * cycles / elapsed
-    out = {
+    return {
         "metric": METRIC,
-        "value": value,
+        "value": unknowns * cycles / elapsed,
         "unit": "unknowns*cycles/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -337,10 +319,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32+f64",
+        "dtype": "f64" if prec == 0 else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}_{'fp64' if args.precision == 0 else 'mixed'}",
+            "workload": f"{args.workload}_{'fp64' if prec == 0 else 'mixed'}",
             "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": w["dt"], "coarsest": w["coarsest"],
             "unknowns": unknowns, "inside": ni, "ghost": ng, "levels": H.nlev,
             "cycle": f"V({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps",
@@ -355,6 +337,177 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
     }
+
+
+def run_batch(args):
+    """64 star domains of uneven grid sizes (129^2 .. 1025^2) stepped together in
+    mixed precision, against the same domains stepped one after another with the
+    plain FP64 path."""
+    import torch
+    from paper_1902_07029_amd import lsmg
+
+    doms = I.batch_domains(64, seed=0)
+    prec = args.precision if args.precision is not None else 1
+    dt = doms[0]["dt"]
+    phis = [I.star(d["n"], **d["shape"]) for d in doms]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Hs = [lsmg.Hierarchy(torch.from_numpy(phi).cuda(), 2, d["n"],
+                         params=lsmg.default_params(coarsest_n=d["coarsest"], precision=prec))
+          for phi, d in zip(phis, doms)]
+    B = lsmg.Batch(Hs)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    infos = [H.level_info(0) for H in Hs]
+    unk = np.array([2 * inf["na"] for inf in infos], dtype=np.float64)
+
+    def fresh_states(hs):
+        out = []
+        for H, d in zip(hs, doms):
+            st = lsmg.State(H)
+            s0, c0 = I.initial_state(d["n"], 2)
+            st.set_grid(torch.from_numpy(s0).cuda(), torch.from_numpy(c0).cuda())
+            out.append(st)
+        return out
+
+    states = fresh_states(Hs)
+    # sample members for the oracle parity check: the two smallest domains
+    sample = sorted(range(len(doms)), key=lambda k: infos[k]["na"])[:2]
+    traj = {k: [] for k in sample}
+    for _ in range(args.warmup):
+        B.step(states, dt)
+        for k in sample:
+            traj[k].append(states[k].get().cpu().numpy())
+    lat = []
+    cyc = np.zeros(len(doms))
+    newton = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, stats = B.step(states, dt)
+        lat.append(time.perf_counter() - ts)
+        for k, stt in enumerate(stats):
+            cyc[k] += stt["vcycles"]
+            newton += stt["newton_iters"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    value = float(np.dot(unk, cyc)) / elapsed
+    # kernel timing pass: the smoother launches at the largest grid size
+    nmax = max(d["n"] for d in doms)
+    B.profile_start(lsmg.KERNEL_SMOOTH, nmax)
+    for _ in range(args.steps):
+        B.step(states, dt)
+    torch.cuda.synchronize()
+    launches, prof_ms = B.profile_stop()
+    P = 8 if prec == 0 else 4
+    byts = 0.0
+    for H, d, inf in zip(Hs, doms, infos):
+        if d["n"] == nmax:
+            b0, b1 = smoother_bytes(H.compact_to_grid(0).cpu().numpy(), inf["ni"], inf["ng"], d["n"], 2, P)
+            byts += 0.5 * (b0 + b1)
+    avg_s = prof_ms * 1e-3 / max(launches, 1)
+    achieved = byts / avg_s / 1e9 if launches else 0.0
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic("smooth_colour", "batch64", prec),
+                    kernel=f"k_smooth_colour (all {nmax}^2 levels of the batch, one colour)", launches=launches,
+                    avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(byts))
+    # the plain FP64 path, domain after domain, same steps
+    seq = None
+    if not args.no_sequential:
+        H64 = [lsmg.Hierarchy(torch.from_numpy(phi).cuda(), 2, d["n"],
+                              params=lsmg.default_params(coarsest_n=d["coarsest"], precision=0))
+               for phi, d in zip(phis, doms)]
+        st64 = fresh_states(H64)
+        for st in st64:
+            st.step(dt)
+        nseq = max(1, min(args.steps, 5))
+        cyc64 = np.zeros(len(doms))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(nseq):
+            for k, st in enumerate(st64):
+                cyc64[k] += st.step(dt)[1]["vcycles"]
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t1
+        seq = dict(value=float(np.dot(unk, cyc64)) / el64, steps=nseq, ms_per_round=el64 * 1e3 / nseq,
+                   solution_throughput=float(unk.sum()) * nseq / el64)
+        del st64, H64
+    cpu = parity = None
+    if not args.no_cpu_baseline and sample:
+        k = sample[0]
+        d = doms[k]
+        cpu, parity = cpu_baseline(phis[k], 2, d["n"], d["coarsest"], dt, oracle_params(Hs[k]), args.cpu_budget,
+                                   traj[k], f"batch member {k} (star {d['n']}^2, inside the 64-domain batch)")
+        if len(sample) > 1:
+            k2 = sample[1]
+            d2 = doms[k2]
+            _, par2 = cpu_baseline(phis[k2], 2, d2["n"], d2["coarsest"], dt, oracle_params(Hs[k2]),
+                                   args.cpu_budget, traj[k2], f"batch member {k2} (star {d2['n']}^2)")
+            parity = dict(parity, second=par2)
+    lat_ms = np.array(lat) * 1e3
+    sizes = {}
+    for d in doms:
+        sizes[str(d["n"])] = sizes.get(str(d["n"]), 0) + 1
+    return {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknowns*cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch64_{'fp64' if prec == 0 else 'mixed'}", "domains": len(doms),
+                   "grid_sizes": sizes, "dt": dt, "coarsest": 9, "unknowns": int(unk.sum()),
+                   "build_ms": round(build_ms, 1), "tuning": {str(k): v for k, v in B.tuning().items()}},
+        "vcycles": int(cyc.sum()),
+        "newton_iters": newton,
+        "solution_throughput": float(unk.sum()) * args.steps / elapsed,
+        "p50_step_ms": float(np.percentile(lat_ms, 50)),
+        "p99_step_ms": float(np.percentile(lat_ms, 99)),
+        "fp64_sequential": seq,
+        "speedup_vs_fp64_sequential": (value / seq["value"]) if seq else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS) + ["batch64"])
+    ap.add_argument("--precision", type=int, default=None, choices=(0, 1),
+                    help="0 = FP64, 1 = mixed (default: FP64, batch64: mixed)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true", help="batch64: skip the sequential FP64 comparison")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--parity-steps", type=int, default=6)
+    ap.add_argument("--copy-probe", type=int, metavar="MIB")
+    ap.add_argument("--trace-summary", metavar="DIR")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
+    ap.add_argument("--copy-mib", type=int, default=512)
+    args = ap.parse_args()
+    if args.trace_summary:
+        return trace_summary(args.trace_summary)
+    if args.traffic:
+        return traffic(*args.traffic, args.workload, args.precision or 0, args.copy_mib)
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs "
+              "is designed but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    out = run_batch(args) if args.workload == "batch64" else run_single(args)
     print(json.dumps(out))
 
 

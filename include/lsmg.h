@@ -219,7 +219,7 @@ enum {
     LSMG_KERNEL_DEFECT = 1,    /* defect r = rhs - J x */
     LSMG_KERNEL_RESTRICT = 2,  /* restriction onto `level` from level - 1 */
     LSMG_KERNEL_PROLONG = 3,   /* prolongation onto `level` from level + 1 */
-    LSMG_KERNEL_GHOST = 4      /* one ghost relaxation sweep */
+    LSMG_KERNEL_GHOST = 4      /* the ghost relaxation of a smoothing step (each of its launches) */
 };
 
 /* Start timing every launch of `kernel` on `level` of this hierarchy: a HIP
@@ -232,6 +232,65 @@ lsmg_status lsmg_profile_start(lsmg_hierarchy *h, int kernel, int level);
 /* Stop timing; host outs: number of timed launches and the sum of their
  * event-to-event durations in milliseconds.  Synchronises the stream. */
 lsmg_status lsmg_profile_stop(lsmg_hierarchy *h, int *launches, double *total_ms);
+
+/* ------------------------------------------------------------------------
+ * Batches: many hierarchies advanced by one Crank-Nicolson step together
+ * (sections 3.1-3.5 for each member), with one launch per kernel and grid
+ * size for all members.  A member's results are bitwise those of
+ * lsmg_newton_cn_step on it alone: the batch runs each member's own V-cycle
+ * operations in the same order on its own data, and its stopping decisions per
+ * member with the same rules.
+ * ------------------------------------------------------------------------ */
+typedef struct lsmg_batch lsmg_batch;
+
+/* Build a batch over count >= 1 distinct hierarchies (host array of handles).
+ * All members must have the same dim and the same parameters (precision,
+ * cycle, tolerances, ghost_c_new = 1); a mixed-precision batch needs members
+ * built (or set) with precision 1.  The members stay owned by the caller and
+ * must outlive the batch; while a batch call runs, a member must not be used
+ * on its own.  All batch work runs on `stream` (NULL = null stream); building
+ * synchronises it.  The batch holds the members' concatenated level
+ * descriptors and work lists, per-member norm slots and flags.
+ * Errors: EINVAL (NULL, duplicates, mismatched members), ENOTIMPL
+ * (ghost_c_new = 0), EOOM, EHIP. */
+lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, void *stream, lsmg_batch **out);
+void lsmg_batch_destroy(lsmg_batch *b);
+
+/* One Crank-Nicolson step with time step dt for every member k: states[k]
+ * (host array; a state of members[k]) goes from W^n to W^{n+1}.  Boundary
+ * values s_b at t_{n+1}: d_sb[k] (device, Ng doubles of member k) if d_sb and
+ * d_sb[k] are non-NULL, else sb_const[k] (host array; 1.0 if sb_const is
+ * NULL).  status[k] (host, optional) gets member k's own status with the
+ * meaning of lsmg_newton_cn_step's; a member that fails keeps W^n.  stats[k]
+ * (host, optional) as for lsmg_newton_cn_step.  Returns LSMG_OK if every
+ * member converged, else the first failing member's status.  Synchronises the
+ * batch stream.  On the first step the batch autotunes its launch shapes
+ * (lsmg_batch_set_autotune), which changes no result. */
+lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt, const double *const *d_sb,
+                            const double *sb_const, lsmg_status *status, lsmg_step_stats *stats);
+
+/* Autotuning of the batch's launch shapes (enable != 0, the default): on the
+ * first step, for every grid size and kernel class (smoother, ghost
+ * relaxation, defect, restriction, prolongation, band), the workgroup size of
+ * 1, 2, 4 or 8 wavefronts with the least measured launch time is kept.
+ * Disabling it restores the default of 4. */
+lsmg_status lsmg_batch_set_autotune(lsmg_batch *b, int enable);
+
+/* The batch's grid sizes (finest first) and their chosen workgroup sizes in
+ * wavefronts, 6 per size in the class order above; cap bounds the entries
+ * written (host arrays sizes[cap], ipb[6 * cap]); *count gets the number of
+ * sizes. */
+lsmg_status lsmg_batch_tuning(const lsmg_batch *b, int cap, int *count, int *sizes, int *ipb);
+
+/* Launch timing inside a batch, as lsmg_profile_start / lsmg_profile_stop:
+ * every launch of kernel class `kernel` (LSMG_KERNEL_*) at grid size n (for
+ * LSMG_KERNEL_RESTRICT: the launch that restricts from size n) is timed by
+ * its own dispatch events until lsmg_batch_profile_stop, which returns the
+ * number of timed launches and their total time in ms; while timing is on,
+ * the batch's V-cycles run as direct launches instead of its captured graph.
+ * Both synchronise the batch stream. */
+lsmg_status lsmg_batch_profile_start(lsmg_batch *b, int kernel, int n);
+lsmg_status lsmg_batch_profile_stop(lsmg_batch *b, int *launches, double *total_ms);
 
 /* Thread-local message for the last non-OK status of this thread. */
 const char *lsmg_last_error(void);

@@ -1,9 +1,9 @@
 """Build the lsmg HIP library for gfx950 in-tree (``liblsmg.so`` next to this file).
 
-Three translation units: ``build.hip`` (hierarchy construction, compiled with
+Four translation units: ``build.hip`` (hierarchy construction, compiled with
 FMA contraction off so the discrete geometry is evaluated in plain IEEE order),
-``kernels.hip`` (V-cycle and Newton kernels) and ``api.hip`` (the C ABI and the
-host drivers).  Every HIP compile line disables packed FP32 instructions.
+``kernels.hip`` (V-cycle and Newton kernels), ``api.hip`` (the C ABI and the
+single-hierarchy drivers) and ``batch.hip`` (batches of hierarchies).  Every HIP compile line disables packed FP32 instructions.
 """
 import os
 import shutil
@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = os.environ.get("LSMG_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
-UNITS = [("build.hip", ["-ffp-contract=off"]), ("kernels.hip", []), ("api.hip", [])]
+UNITS = [("build.hip", ["-ffp-contract=off"]), ("kernels.hip", []), ("api.hip", []), ("batch.hip", [])]
 
 
 def hipcc():

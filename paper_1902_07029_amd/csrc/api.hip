@@ -14,15 +14,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lsmg.h"
-#include "lsmg_dev.hpp"
-#include "lsmg_host.hpp"
+#include "hier.hpp"
 
-using namespace lsmg;
+namespace lsmg {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 lsmg_status fail(lsmg_status st, const char *fmt, ...)
 {
@@ -35,129 +33,6 @@ lsmg_status fail(lsmg_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIPCHK(x)                                                                                      \
-    do {                                                                                               \
-        hipError_t e_ = (x);                                                                           \
-        if (e_ != hipSuccess) return fail(LSMG_EHIP, "%s failed: %s", #x, hipGetErrorString(e_));      \
-    } while (0)
-
-#define LSMGCHK(x)                        \
-    do {                                  \
-        lsmg_status s_ = (x);             \
-        if (s_ != LSMG_OK) return s_;     \
-    } while (0)
-
-struct Level {
-    int n = 0, Wp = 0;
-    long long rows = 0, cs = 0, ssize = 0;
-    double h = 0.0;
-    int ni = 0, ng = 0, na = 0, nb = 0, bmax = 0;
-    uint8_t *type = nullptr, *ext = nullptr;
-    int *cmap = nullptr, *c2s = nullptr;
-    int64_t *c2g = nullptr;
-    double *s = nullptr, *c = nullptr, *rhs_s = nullptr, *rhs_c = nullptr, *x_s = nullptr, *x_c = nullptr,
-           *r_s = nullptr, *r_c = nullptr;
-    int *g_idx = nullptr, *g_ijk = nullptr, *g_st = nullptr, *g_stg = nullptr, *g_stc = nullptr, *g_order = nullptr,
-        *g_bfall = nullptr;
-    double *g_w = nullptr, *g_B = nullptr, *g_nrm = nullptr, *g_buf0 = nullptr, *g_buf1 = nullptr;
-    int *b_idx = nullptr, *b_cnt = nullptr, *b_src = nullptr;
-    double *b_wt = nullptr;
-    float *s32 = nullptr, *c32 = nullptr, *rhs_s32 = nullptr, *rhs_c32 = nullptr, *x_s32 = nullptr, *x_c32 = nullptr,
-          *r_s32 = nullptr, *r_c32 = nullptr, *g_w32 = nullptr, *g_buf0_32 = nullptr, *g_buf1_32 = nullptr,
-          *b_wt32 = nullptr;
-    int *in_ijk = nullptr;                      // packed coordinates of inside nodes, colour 0 then 1
-    int nin[2] = {0, 0};
-    int *go_ptr = nullptr, *go_col = nullptr;   // composed ghost relaxation (CSR over ghosts)
-    double *go_a = nullptr, *go_b = nullptr;
-    float *go_a32 = nullptr, *go_b32 = nullptr;
-    int4 *items = nullptr;              // [seg colour 0 | seg colour 1 | ghost chunks | band chunks]
-    int nseg[2] = {0, 0}, nghc = 0, nbandc = 0;
-    const int4 *w_seg(int colour) const { return items + (colour ? nseg[0] : 0); }
-    const int4 *w_act() const { return items; }
-    int nw_act() const { return nseg[0] + nseg[1] + nghc; }
-    const int4 *w_gh() const { return items + nseg[0] + nseg[1]; }
-    const int4 *w_band() const { return items + nseg[0] + nseg[1] + nghc; }
-};
-
-}  // namespace
-
-struct lsmg_hierarchy {
-    int dim = 2, nst = 9, nlev = 0;
-    double lo = -1.0, hi = 1.0;
-    lsmg_params p{};
-    hipStream_t stream = nullptr;
-    std::vector<Level> L;
-    std::vector<LevelDesc<double>> hd64;
-    std::vector<LevelDesc<float>> hd32;
-    LevelDesc<double> *d64 = nullptr;
-    LevelDesc<float> *d32 = nullptr;
-    bool have32 = false;
-    double dt = 0.0;
-    bool lin_set = false;
-    double *bs = nullptr, *bc = nullptr, *tmp_s = nullptr, *tmp_c = nullptr;
-    double *lu = nullptr, *ainv = nullptr;
-    int *piv = nullptr, *lu_status = nullptr;
-    int luN = 0;
-    int tail_l0 = 0;   // first level handled by the coarse-tail kernel
-    unsigned long long *d_norms = nullptr, *h_norms = nullptr;
-    int *h_status = nullptr;
-    std::vector<void *> allocs;
-    // launch timing of one kernel class on one level (HIP events on the stream)
-    int prof_kernel = -1, prof_level = -1;
-    std::vector<hipEvent_t> prof_pool;
-    size_t prof_used = 0;
-    double prof_acc_ms = 0.0;
-    long long prof_acc_n = 0;
-    // V-cycle graphs (0: FP64 cycle, 1: mixed-precision refinement step), captured on a private stream
-    bool use_graphs = true;
-    hipStream_t cap = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    size_t gprof_pairs[2] = {0, 0}, gprof_first[2] = {0, 0}, prof_pending = 0;
-    // composed ghost relaxation tables (CSR over ghosts), owned separately: rebuilt with the parameters
-    std::vector<void *> ghost_ops;
-    ~lsmg_hierarchy()
-    {
-        for (int i = 0; i < 2; ++i)
-            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
-        if (cap) (void)hipStreamDestroy(cap);
-        for (void *p : ghost_ops) (void)hipFree(p);
-        for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
-        for (void *p : allocs) (void)hipFree(p);
-        if (h_norms) (void)hipHostFree(h_norms);
-        if (h_status) (void)hipHostFree(h_status);
-    }
-    template <typename T>
-    lsmg_status alloc(T **ptr, long long count)
-    {
-        *ptr = nullptr;
-        if (count <= 0) count = 1;
-        void *p = nullptr;
-        if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess)
-            return fail(LSMG_EOOM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
-        allocs.push_back(p);
-        *ptr = (T *)p;
-        return LSMG_OK;
-    }
-    template <typename T>
-    lsmg_status zalloc(T **ptr, long long count)
-    {
-        LSMGCHK(alloc(ptr, count));
-        HIPCHK(hipMemsetAsync(*ptr, 0, sizeof(T) * (size_t)(count > 0 ? count : 1), stream));
-        return LSMG_OK;
-    }
-};
-
-struct lsmg_state {
-    lsmg_hierarchy *h = nullptr;
-    double *s = nullptr, *c = nullptr;
-    ~lsmg_state()
-    {
-        (void)hipFree(s);
-        (void)hipFree(c);
-    }
-};
-
-namespace {
 
 int ipow(int b, int e)
 {
@@ -255,22 +130,26 @@ double norm_value(const lsmg_hierarchy *H, int k)
 }
 
 // ---------------------------------------------------------------------------
-// launch timing: events bracket each launch of the selected kernel class on
-// the selected level
+// launch timing: each launch of the selected kernel class on the selected level
+// carries a pair of events that its own dispatch records
 // ---------------------------------------------------------------------------
 inline bool prof_on(const lsmg_hierarchy *H, int kernel, int l)
 {
     return H->prof_kernel == kernel && H->prof_level == l;
 }
 
-void prof_mark(lsmg_hierarchy *H, hipStream_t s)
+Exec prof_exec(lsmg_hierarchy *H, hipStream_t s, int kernel, int l)
 {
-    if (H->prof_used >= H->prof_pool.size()) {
+    Exec x(s);
+    if (!prof_on(H, kernel, l)) return x;
+    while (H->prof_pool.size() < H->prof_used + 2) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
+        if (hipEventCreate(&e) != hipSuccess) return x;
         H->prof_pool.push_back(e);
     }
-    (void)hipEventRecord(H->prof_pool[H->prof_used++], s);
+    x.ev0 = H->prof_pool[H->prof_used++];
+    x.ev1 = H->prof_pool[H->prof_used++];
+    return x;
 }
 
 // sum of the event pairs [first, last) into the accumulators
@@ -300,20 +179,18 @@ void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s)
 {
     const Level &Lv = H->L[l];
     const LevelDesc<T> *d = descs<T>(H);
-    const bool ps = prof_on(H, LSMG_KERNEL_SMOOTH, l), pg = prof_on(H, LSMG_KERNEL_GHOST, l);
-    for (int colour = 0; colour < 2; ++colour) {
-        if (ps) prof_mark(H, s);
-        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour, s);
-        if (ps) prof_mark(H, s);
-    }
-    if (pg) prof_mark(H, s);
-    launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.ng, H->p.ghost_sweeps, Lv.go_ptr != nullptr, s);
-    if (pg) prof_mark(H, s);
+    for (int colour = 0; colour < 2; ++colour)
+        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour,
+                                prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
+    const Exec xb = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
+    const Exec xa = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
+    launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.ng, H->p.ghost_sweeps, Lv.go_ptr != nullptr, xb, xa);
 }
 
-TailArgs tail_args(const lsmg_hierarchy *H, int l0)
+TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
 {
     TailArgs a{};
+    a.d0 = d0;
     a.l0 = l0;
     a.nlev = H->nlev;
     a.nu1 = H->p.nu1;
@@ -337,24 +214,16 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
     const LevelDesc<T> *d = descs<T>(H);
     if (l >= H->tail_l0) {
         // this level and every coarser one in one workgroup
-        launch_tail<T>(H->dim, d, tail_args(H, l), H->L[H->nlev - 1].na, s);
+        launch_tail<T>(H->dim, d, H->d_tail + l, 1, H->L[H->nlev - 1].na, Exec(s));
         return;
     }
     for (int i = 0; i < H->p.nu1; ++i) smooth_level<T>(H, l, s);
-    const bool pd = prof_on(H, LSMG_KERNEL_DEFECT, l), pr = prof_on(H, LSMG_KERNEL_RESTRICT, l + 1),
-               pp = prof_on(H, LSMG_KERNEL_PROLONG, l);
-    if (pd) prof_mark(H, s);
-    launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), nullptr, s);
-    if (pd) prof_mark(H, s);
-    launch_band<T>(d, Lv.w_band(), Lv.nbandc, s);
+    launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), -1, prof_exec(H, s, LSMG_KERNEL_DEFECT, l));
+    launch_band<T>(d, Lv.w_band(), Lv.nbandc, Exec(s));
     const Level &C = H->L[l + 1];
-    if (pr) prof_mark(H, s);
-    launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), s);
-    if (pr) prof_mark(H, s);
+    launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), prof_exec(H, s, LSMG_KERNEL_RESTRICT, l + 1));
     vcycle_rec<T>(H, l + 1, s);
-    if (pp) prof_mark(H, s);
-    launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), s);
-    if (pp) prof_mark(H, s);
+    launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), prof_exec(H, s, LSMG_KERNEL_PROLONG, l));
     for (int i = 0; i < H->p.nu2; ++i) smooth_level<T>(H, l, s);
 }
 
@@ -372,7 +241,7 @@ void cycle_enqueue(lsmg_hierarchy *H, bool mixed, hipStream_t s)
         vcycle_rec<float>(H, 0, s);
         launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), s);
     }
-    launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), norm_slot(H, 1), s);
+    launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), 1, s);
 }
 
 void invalidate_graphs(lsmg_hierarchy *H)
@@ -380,7 +249,6 @@ void invalidate_graphs(lsmg_hierarchy *H)
     for (int i = 0; i < 2; ++i) {
         if (H->gexec[i]) (void)hipGraphExecDestroy(H->gexec[i]);
         H->gexec[i] = nullptr;
-        H->gprof_pairs[i] = 0;
     }
 }
 
@@ -390,7 +258,6 @@ lsmg_status cycle_graph(lsmg_hierarchy *H, bool mixed, hipGraphExec_t *out)
     const int gi = mixed ? 1 : 0;
     if (!H->gexec[gi]) {
         if (!H->cap) HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
-        const size_t first = H->prof_used;
         HIPCHK(hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal));
         cycle_enqueue(H, mixed, H->cap);
         hipGraph_t g = nullptr;
@@ -398,9 +265,6 @@ lsmg_status cycle_graph(lsmg_hierarchy *H, bool mixed, hipGraphExec_t *out)
         hipError_t e = hipGraphInstantiate(&H->gexec[gi], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail(LSMG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
-        H->gprof_first[gi] = first;
-        H->gprof_pairs[gi] = (H->prof_used - first) / 2;
-        H->prof_pending = H->prof_used;
     }
     *out = H->gexec[gi];
     return LSMG_OK;
@@ -418,8 +282,7 @@ lsmg_status linearize(lsmg_hierarchy *H)
             const Level &Lv = H->L[l];
             launch_to_f32(H->dim, H->d64, H->d32, Lv.w_act(), Lv.nw_act(), 0, H->stream);
         }
-    const Level &Lc = H->L[H->nlev - 1];
-    launch_coarse_factor(H->dim, H->d64, H->nlev - 1, 2 * Lc.na, Lc.c2s, H->lu, H->ainv, H->lu_status, H->stream);
+    launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->luN, H->stream);
     H->lin_set = true;
     return LSMG_OK;
 }
@@ -697,6 +560,12 @@ void make_descs(lsmg_hierarchy *H)
         D.g_buf0 = Lv.g_buf0; D.g_buf1 = Lv.g_buf1;
         D.go_ptr = Lv.go_ptr; D.go_col = Lv.go_col; D.go_a = Lv.go_a; D.go_b = Lv.go_b;
         D.b_idx = Lv.b_idx; D.b_cnt = Lv.b_cnt; D.b_src = Lv.b_src; D.b_wt = Lv.b_wt;
+        D.norms = H->d_norms; D.norm_stride = kNormSlots;
+        if (l == 0) {
+            D.sn = const_cast<double *>(H->step_sn); D.cn = const_cast<double *>(H->step_cn);
+            D.bs = H->bs; D.bc = H->bc;
+            D.fn = H->step_fn; D.fnp1 = H->step_fnp1; D.sb = H->step_sb; D.sb_const = H->step_sb_const;
+        }
         LevelDesc<float> &E = H->hd32[l];
         E.dim = D.dim; E.n = D.n; E.Wp = D.Wp; E.nst = D.nst;
         E.ni = D.ni; E.ng = D.ng; E.na = D.na; E.nb = D.nb; E.bmax = D.bmax; E.level = l;
@@ -708,6 +577,7 @@ void make_descs(lsmg_hierarchy *H)
         E.g_buf0 = Lv.g_buf0_32; E.g_buf1 = Lv.g_buf1_32;
         E.go_ptr = Lv.go_ptr; E.go_col = Lv.go_col; E.go_a = Lv.go_a32; E.go_b = Lv.go_b32;
         E.b_idx = D.b_idx; E.b_cnt = D.b_cnt; E.b_src = D.b_src; E.b_wt = Lv.b_wt32;
+        E.norms = D.norms; E.norm_stride = D.norm_stride;
     }
 }
 
@@ -807,6 +677,23 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     if (H->p.precision == 1) LSMGCHK(build_f32(H));
     LSMGCHK(H->alloc(&H->d64, nlev));
     LSMGCHK(H->alloc(&H->d32, nlev));
+    // coarse-tail and coarsest-operator arguments
+    LSMGCHK(H->alloc(&H->d_tail, nlev));
+    LSMGCHK(H->alloc(&H->d_coarse, 1));
+    {
+        std::vector<TailArgs> ta(nlev);
+        for (int l = 0; l < nlev; ++l) ta[l] = tail_args(H, l, 0);
+        const Level &Lc = H->L[nlev - 1];
+        CoarseArgs ca{};
+        ca.desc = nlev - 1;
+        ca.c2s = Lc.c2s;
+        ca.M = H->lu;
+        ca.Ainv = H->ainv;
+        ca.status = H->lu_status;
+        HIPCHK(hipMemcpyAsync(H->d_tail, ta.data(), sizeof(TailArgs) * nlev, hipMemcpyHostToDevice, H->stream));
+        HIPCHK(hipMemcpyAsync(H->d_coarse, &ca, sizeof(CoarseArgs), hipMemcpyHostToDevice, H->stream));
+        HIPCHK(hipStreamSynchronize(H->stream));
+    }
     make_descs(H);
     LSMGCHK(push_desc(H));
     return LSMG_OK;
@@ -834,11 +721,11 @@ void gather(lsmg_hierarchy *H, int l, const T *a, const T *b, double *v)
     launch_gather_compact<T>(Lv.c2s, Lv.na, a, b, v, H->stream);
 }
 
+// x = 0 on the active nodes of a level (inactive positions are never written)
 void zero_active_x(lsmg_hierarchy *H, int l)
 {
     const Level &Lv = H->L[l];
-    launch_fill<double>(Lv.x_s, Lv.ssize, 0.0, H->stream);
-    launch_fill<double>(Lv.x_c, Lv.ssize, 0.0, H->stream);
+    launch_zero_x<double>(H->dim, H->d64, Lv.w_act(), Lv.nw_act(), H->stream);
 }
 
 // linear solve J dW = F on level 0 (rhs already in rhs_s / rhs_c) by V-cycles from zero;
@@ -851,22 +738,19 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
     const bool mixed = H->p.precision == 1;
     if (mixed) {
         // r = F - J 0 in FP64
-        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), nullptr, H->stream);
+        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), -1, H->stream);
     }
     hipGraphExec_t ge = nullptr;
     // events recorded inside a graph cannot be timed: while launch timing is on,
     // cycles run as direct launches
     if (H->use_graphs && H->prof_kernel < 0) LSMGCHK(cycle_graph(H, mixed, &ge));
-    const int gi = mixed ? 1 : 0;
     for (int q = 0; q < H->p.cycles_max; ++q) {
         if (rprev <= H->p.lin_rtol * nF) break;
         const size_t mark0 = H->prof_used;
         if (ge) HIPCHK(hipGraphLaunch(ge, H->stream));
         else cycle_enqueue(H, mixed, H->stream);
         LSMGCHK(read_norms(H, 2));
-        if (ge) {
-            prof_collect(H, H->gprof_first[gi], H->gprof_first[gi] + 2 * H->gprof_pairs[gi]);
-        } else {
+        if (!ge) {
             prof_collect(H, mark0, H->prof_used);
             H->prof_used = mark0;
         }
@@ -881,26 +765,38 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
     return LSMG_OK;
 }
 
-StepArgsHost step_args(lsmg_hierarchy *H, const double *sn, const double *cn, const double *sb, double sb_const,
-                       const double *fn, const double *fnp1)
+// names the Crank-Nicolson step's arrays in the level-0 descriptor (pushed
+// only when they change)
+lsmg_status set_step(lsmg_hierarchy *H, const double *sn, const double *cn, const double *sb, double sb_const,
+                     const double *fn, const double *fnp1)
 {
-    StepArgsHost a;
-    a.sn = sn;
-    a.cn = cn;
-    a.bs = H->bs;
-    a.bc = H->bc;
-    a.fn = (fn && fnp1) ? fn : nullptr;
-    a.fnp1 = (fn && fnp1) ? fnp1 : nullptr;
-    a.sb = sb;
-    a.sb_const = sb_const;
-    return a;
+    if (!(fn && fnp1)) fn = fnp1 = nullptr;
+    if (sn == H->step_sn && cn == H->step_cn && sb == H->step_sb && sb_const == H->step_sb_const &&
+        fn == H->step_fn && fnp1 == H->step_fnp1)
+        return LSMG_OK;
+    H->step_sn = sn;
+    H->step_cn = cn;
+    H->step_sb = sb;
+    H->step_sb_const = sb_const;
+    H->step_fn = fn;
+    H->step_fnp1 = fnp1;
+    LevelDesc<double> &D = H->hd64[0];
+    D.sn = const_cast<double *>(sn);
+    D.cn = const_cast<double *>(cn);
+    D.sb = sb;
+    D.sb_const = sb_const;
+    D.fn = fn;
+    D.fnp1 = fnp1;
+    return push_desc(H);
 }
 
-}  // namespace
+}  // namespace lsmg
 
 // ===========================================================================
 // C ABI
 // ===========================================================================
+using namespace lsmg;
+
 extern "C" {
 
 void lsmg_default_params(lsmg_params *p)
@@ -1120,15 +1016,13 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
 {
     if (!h || !st || st->h != h) return fail(LSMG_EINVAL, "bad hierarchy or state");
     LSMGCHK(set_dt(h, dt));
+    LSMGCHK(set_step(h, st->s, st->c, d_sb, sb_const, d_fn, d_fnp1));
     const Level &L0 = h->L[0];
     hipStream_t s = h->stream;
-    // W^{(n+1,0)} = W^n
-    HIPCHK(hipMemcpyAsync(L0.s, st->s, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(L0.c, st->c, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
-    const StepArgsHost A = step_args(h, st->s, st->c, d_sb, sb_const, d_fn, d_fnp1);
-    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, s);
+    // explicit half, and the first iterate W^{(n+1,0)} = W^n
+    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), s);
     zero_norms(h, 0, 4);
-    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, norm_slot(h, 0), s);
+    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, s);
     LSMGCHK(read_norms(h, 1));
     double nF = norm_value(h, 0);
     lsmg_status rc = LSMG_ENOCONV;
@@ -1143,8 +1037,8 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
         LSMGCHK(check_factor(h));
         LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho));
         zero_norms(h, 0, 4);
-        launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), norm_slot(h, 2), norm_slot(h, 3), s);
-        launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, norm_slot(h, 0), s);
+        launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), s);
+        launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, s);
         LSMGCHK(read_norms(h, 4));
         nF = norm_value(h, 0);
         const double nD = norm_value(h, 2), nW = norm_value(h, 3);
@@ -1168,8 +1062,7 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
         stats->dw_rel = dwrel;
     }
     if (rc == LSMG_OK) {
-        HIPCHK(hipMemcpyAsync(st->s, L0.s, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(st->c, L0.c, sizeof(double) * L0.ssize, hipMemcpyDeviceToDevice, s));
+        launch_commit(h->dim, h->d64, L0.w_act(), L0.nw_act(), s);
         HIPCHK(hipStreamSynchronize(s));
     }
     h->lin_set = false;
@@ -1182,12 +1075,13 @@ lsmg_status lsmg_residual(lsmg_hierarchy *h, const double *d_W, const double *d_
     if (!h || !d_W || !d_Wn || !d_F) return fail(LSMG_EINVAL, "NULL argument");
     LSMGCHK(set_dt(h, dt));
     const Level &L0 = h->L[0];
-    scatter<double>(h, 0, d_W, L0.s, L0.c);
     scatter<double>(h, 0, d_Wn, h->tmp_s, h->tmp_c);
-    const StepArgsHost A = step_args(h, h->tmp_s, h->tmp_c, d_sb, sb_const, d_fn, d_fnp1);
-    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, h->stream);
+    LSMGCHK(set_step(h, h->tmp_s, h->tmp_c, d_sb, sb_const, d_fn, d_fnp1));
+    // the explicit half also sets the iterate to W^n; W replaces it afterwards
+    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), h->stream);
+    scatter<double>(h, 0, d_W, L0.s, L0.c);
     zero_norms(h, 0, 1);
-    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), A, norm_slot(h, 0), h->stream);
+    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, h->stream);
     gather<double>(h, 0, L0.rhs_s, L0.rhs_c, d_F);
     h->lin_set = false;
     if (res_inf) {
@@ -1247,7 +1141,7 @@ lsmg_status lsmg_defect(lsmg_hierarchy *h, int level, const double *d_rhs, const
     scatter<double>(h, level, d_rhs, Lv.rhs_s, Lv.rhs_c);
     scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
     zero_norms(h, 1, 1);
-    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), norm_slot(h, 1), h->stream);
+    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), 1, h->stream);
     if (d_r) gather<double>(h, level, Lv.r_s, Lv.r_c, d_r);
     if (res_inf) {
         LSMGCHK(read_norms(h, 2));
@@ -1303,7 +1197,7 @@ lsmg_status lsmg_vcycle(lsmg_hierarchy *h, int level, const double *d_rhs, doubl
     scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
     vcycle_rec<double>(h, level, h->stream);
     zero_norms(h, 1, 1);
-    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), norm_slot(h, 1), h->stream);
+    launch_defect<double>(h->dim, h->d64, Lv.w_act(), Lv.nw_act(), 1, h->stream);
     gather<double>(h, level, Lv.x_s, Lv.x_c, d_x);
     if (res_inf) {
         LSMGCHK(read_norms(h, 2));

@@ -1,0 +1,810 @@
+// Batches: many hierarchies (domains of different shapes and grid sizes)
+// advanced together, one launch per kernel and grid size covering every domain
+// that has a level of that size.
+//
+// The batch concatenates its members' level descriptors and work lists
+// (rebasing the descriptor index of every item).  Its V-cycle walks the grid
+// sizes from the finest down: at each size it smooths, forms the defect and
+// restricts for every member level of that size that is not part of the
+// member's coarse tail, then one launch runs the coarse tails of all members
+// (one workgroup each), and the walk back up prolongs and post-smooths.  Each
+// member therefore sees exactly the operations of its own V-cycle, in the same
+// order, on its own data, so its results are bitwise those of running it alone.
+//
+// Newton and the cycle loop run in lockstep on the host with the same stopping
+// rules as a single hierarchy, evaluated per member; a member that has
+// converged (or failed) is switched off through the per-descriptor flags the
+// item kernels check, so the captured cycle graph stays valid for any subset.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "hier.hpp"
+
+using namespace lsmg;
+
+namespace {
+
+// kernel classes the autotuner picks a workgroup size for
+enum { kTSmooth = 0, kTGhost = 1, kTDefect = 2, kTRestrict = 3, kTProlong = 4, kTBand = 5, kTClasses = 6 };
+
+struct BList {
+    int off = 0, n = 0;   // range in the batch's item pool
+};
+
+struct BSize {
+    int n = 0;                       // nodes per axis
+    BList seg[2], gh, act, band;     // member levels of this size outside the coarse tails
+    BList rcoarse;                   // their next coarser levels (restriction targets)
+    BList icoarse;                   // next coarser levels of every member level of this size (injection)
+    int ipb[kTClasses];
+};
+
+}  // namespace
+
+struct lsmg_batch {
+    int dim = 2, ndom = 0, ndesc = 0;
+    lsmg_params p{};
+    hipStream_t stream = nullptr, cap = nullptr;
+    std::vector<lsmg_hierarchy *> mem;
+    std::vector<int> d0;
+    std::vector<LevelDesc<double>> hd64;
+    std::vector<LevelDesc<float>> hd32;
+    LevelDesc<double> *d64 = nullptr;
+    LevelDesc<float> *d32 = nullptr;
+    std::vector<BSize> sizes;       // descending n
+    BList lev0, all;
+    int4 *pool = nullptr;
+    int npool = 0;
+    TailArgs *d_tail = nullptr;
+    int tail_na_max = 0;
+    CoarseArgs *d_coarse = nullptr;
+    int coarse_n_max = 0;
+    int *d_act = nullptr, *h_act = nullptr;
+    std::vector<int> act_last;
+    int *d_cstatus = nullptr, *h_cstatus = nullptr;
+    unsigned long long *d_norms = nullptr, *d_nred = nullptr, *h_nred = nullptr;
+    long long norm_stride = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool use_graphs = true;
+    int autotune = 1, tuned = 0;
+    double dt = 0.0;
+    std::vector<const lsmg_state *> last_states;
+    std::vector<const double *> last_sb;
+    std::vector<double> last_sbc;
+    std::vector<void *> allocs;
+    std::vector<hipEvent_t> evpool;
+    // launch timing of one kernel class at one grid size
+    int prof_kernel = -1, prof_n = -1;
+    std::vector<hipEvent_t> prof_pool;
+    size_t prof_used = 0;
+    double prof_acc_ms = 0.0;
+    long long prof_acc_n = 0;
+    ~lsmg_batch()
+    {
+        for (int i = 0; i < 2; ++i)
+            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
+        for (void *q : allocs) (void)hipFree(q);
+        if (h_act) (void)hipHostFree(h_act);
+        if (h_cstatus) (void)hipHostFree(h_cstatus);
+        if (h_nred) (void)hipHostFree(h_nred);
+    }
+    template <typename T>
+    lsmg_status alloc(T **ptr, long long count)
+    {
+        *ptr = nullptr;
+        if (count <= 0) count = 1;
+        void *q = nullptr;
+        if (hipMalloc(&q, sizeof(T) * (size_t)count) != hipSuccess)
+            return fail(LSMG_EOOM, "batch allocation of %lld bytes failed", (long long)(sizeof(T) * count));
+        allocs.push_back(q);
+        *ptr = (T *)q;
+        return LSMG_OK;
+    }
+};
+
+namespace {
+
+template <typename T>
+const LevelDesc<T> *bdescs(const lsmg_batch *B);
+template <>
+const LevelDesc<double> *bdescs<double>(const lsmg_batch *B) { return B->d64; }
+template <>
+const LevelDesc<float> *bdescs<float>(const lsmg_batch *B) { return B->d32; }
+
+inline const int4 *items(const lsmg_batch *B, const BList &l) { return B->pool + l.off; }
+
+Exec bexec(const lsmg_batch *B, hipStream_t s, int ipb) { return Exec(s, B->d_act, ipb); }
+
+// the same, with a pair of timing events when kernel class `kernel` at grid
+// size n is being timed
+Exec bexec_t(lsmg_batch *B, hipStream_t s, int ipb, int kernel, int n)
+{
+    Exec x(s, B->d_act, ipb);
+    if (B->prof_kernel != kernel || B->prof_n != n) return x;
+    while (B->prof_pool.size() < B->prof_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return x;
+        B->prof_pool.push_back(e);
+    }
+    x.ev0 = B->prof_pool[B->prof_used++];
+    x.ev1 = B->prof_pool[B->prof_used++];
+    return x;
+}
+
+// adds the timed launches recorded so far (the stream has been synchronised)
+void b_prof_collect(lsmg_batch *B)
+{
+    for (size_t i = 0; i + 1 < B->prof_used; i += 2) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, B->prof_pool[i], B->prof_pool[i + 1]) == hipSuccess) {
+            B->prof_acc_ms += ms;
+            ++B->prof_acc_n;
+        }
+    }
+    B->prof_used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// descriptors
+// ---------------------------------------------------------------------------
+// the batch's descriptors: the members' own, with the norms moved to the
+// batch's slots and the step arrays of the states being advanced
+lsmg_status refresh_descs(lsmg_batch *B, lsmg_state *const *states, const double *const *sb, const double *sbc)
+{
+    for (int k = 0; k < B->ndom; ++k) {
+        const lsmg_hierarchy *H = B->mem[k];
+        for (int l = 0; l < H->nlev; ++l) {
+            LevelDesc<double> D = H->hd64[l];
+            D.norms = B->d_norms + (long long)k * kNormSlots;
+            D.norm_stride = B->norm_stride;
+            if (l == 0) {
+                D.sn = states ? states[k]->s : nullptr;
+                D.cn = states ? states[k]->c : nullptr;
+                D.bs = H->bs;
+                D.bc = H->bc;
+                D.fn = D.fnp1 = nullptr;
+                D.sb = sb ? sb[k] : nullptr;
+                D.sb_const = sbc ? sbc[k] : 1.0;
+            }
+            B->hd64[B->d0[k] + l] = D;
+            if (H->have32) {
+                LevelDesc<float> E = H->hd32[l];
+                E.norms = D.norms;
+                E.norm_stride = D.norm_stride;
+                B->hd32[B->d0[k] + l] = E;
+            }
+        }
+    }
+    HIPCHK(hipMemcpyAsync(B->d64, B->hd64.data(), sizeof(LevelDesc<double>) * B->ndesc, hipMemcpyHostToDevice,
+                          B->stream));
+    if (B->p.precision == 1)
+        HIPCHK(hipMemcpyAsync(B->d32, B->hd32.data(), sizeof(LevelDesc<float>) * B->ndesc, hipMemcpyHostToDevice,
+                              B->stream));
+    HIPCHK(hipStreamSynchronize(B->stream));
+    return LSMG_OK;
+}
+
+// per-descriptor flags from per-member flags; the pinned staging buffer is
+// rewritten only after the stream has been synchronised since its last copy
+// (every caller reads norms or statuses back before changing the flags again)
+lsmg_status set_flags(lsmg_batch *B, const std::vector<char> &on)
+{
+    std::vector<int> v(B->ndesc, 0);
+    for (int k = 0; k < B->ndom; ++k)
+        for (int l = 0; l < B->mem[k]->nlev; ++l) v[B->d0[k] + l] = on[k] ? 1 : 0;
+    if (v == B->act_last) return LSMG_OK;
+    HIPCHK(hipStreamSynchronize(B->stream));
+    std::memcpy(B->h_act, v.data(), sizeof(int) * B->ndesc);
+    HIPCHK(hipMemcpyAsync(B->d_act, B->h_act, sizeof(int) * B->ndesc, hipMemcpyHostToDevice, B->stream));
+    B->act_last = v;
+    return LSMG_OK;
+}
+
+void zero_bnorms(lsmg_batch *B, int first, int count, hipStream_t s)
+{
+    launch_fill<unsigned long long>(B->d_norms + first * B->norm_stride, count * B->norm_stride, 0ull, s);
+}
+
+// per-member maxima of norms [first, first + count) into h_nred[k * 4 + norm]
+lsmg_status read_bnorms(lsmg_batch *B, int first, int count)
+{
+    launch_norm_reduce(B->d_norms, B->norm_stride, B->ndom, first, count, B->d_nred, B->stream);
+    HIPCHK(hipMemcpyAsync(B->h_nred, B->d_nred, sizeof(unsigned long long) * 4 * B->ndom, hipMemcpyDeviceToHost,
+                          B->stream));
+    HIPCHK(hipStreamSynchronize(B->stream));
+    return LSMG_OK;
+}
+
+double bnorm(const lsmg_batch *B, int k, int norm)
+{
+    double v;
+    std::memcpy(&v, &B->h_nred[k * 4 + norm], sizeof(double));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle over all members
+// ---------------------------------------------------------------------------
+template <typename T>
+void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s)
+{
+    const LevelDesc<T> *d = bdescs<T>(B);
+    for (int colour = 0; colour < 2; ++colour)
+        launch_smooth_colour<T>(B->dim, d, items(B, S.seg[colour]), S.seg[colour].n, colour,
+                                bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
+    const Exec xb = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
+    const Exec xa = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
+    launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, 0, B->p.ghost_sweeps, true, xb, xa);
+}
+
+template <typename T>
+void b_vcycle(lsmg_batch *B, hipStream_t s)
+{
+    const LevelDesc<T> *d = bdescs<T>(B);
+    const int nz = (int)B->sizes.size();
+    for (int z = 0; z < nz; ++z) {
+        const BSize &S = B->sizes[z];
+        if (S.act.n == 0) continue;
+        for (int i = 0; i < B->p.nu1; ++i) b_smooth<T>(B, S, s);
+        launch_defect<T>(B->dim, d, items(B, S.act), S.act.n, -1,
+                         bexec_t(B, s, S.ipb[kTDefect], LSMG_KERNEL_DEFECT, S.n));
+        launch_band<T>(d, items(B, S.band), S.band.n, bexec(B, s, S.ipb[kTBand]));
+        launch_restrict<T>(B->dim, d, items(B, S.rcoarse), S.rcoarse.n,
+                           bexec_t(B, s, S.ipb[kTRestrict], LSMG_KERNEL_RESTRICT, S.n));
+    }
+    launch_tail<T>(B->dim, d, B->d_tail, B->ndom, B->tail_na_max, Exec(s, B->d_act));
+    for (int z = nz - 1; z >= 0; --z) {
+        const BSize &S = B->sizes[z];
+        if (S.act.n == 0) continue;
+        launch_prolong<T>(B->dim, d, items(B, S.act), S.act.n,
+                          bexec_t(B, s, S.ipb[kTProlong], LSMG_KERNEL_PROLONG, S.n));
+        for (int i = 0; i < B->p.nu2; ++i) b_smooth<T>(B, S, s);
+    }
+}
+
+// one linear-solve iteration for every active member (see the single-hierarchy
+// driver): V-cycle, or FP32 V-cycle on the FP64 defect; then the FP64 defect
+// with its norm in slot 1
+void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s)
+{
+    zero_bnorms(B, 1, 1, s);
+    const Exec x0(s, B->d_act);
+    if (!mixed) {
+        b_vcycle<double>(B, s);
+    } else {
+        launch_to_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, 1, x0);
+        b_vcycle<float>(B, s);
+        launch_add_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, x0);
+    }
+    launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 1, x0);
+    launch_norm_reduce(B->d_norms, B->norm_stride, B->ndom, 1, 1, B->d_nred, s);
+}
+
+void b_invalidate(lsmg_batch *B)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (B->gexec[i]) (void)hipGraphExecDestroy(B->gexec[i]);
+        B->gexec[i] = nullptr;
+    }
+}
+
+lsmg_status b_graph(lsmg_batch *B, bool mixed, hipGraphExec_t *out)
+{
+    const int gi = mixed ? 1 : 0;
+    if (!B->gexec[gi]) {
+        if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+        b_cycle_enqueue(B, mixed, B->cap);
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(B->cap, &g));
+        hipError_t e = hipGraphInstantiate(&B->gexec[gi], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(LSMG_EHIP, "batch graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    *out = B->gexec[gi];
+    return LSMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: per grid size and kernel class, the workgroup size (work items
+// per workgroup: 1, 2, 4 or 8 wavefronts) with the least launch time, measured
+// on the batch's own lists with the launches' own dispatch events.  The
+// kernels only touch scratch arrays (corrections, defects, coarse right-hand
+// sides) that every cycle rewrites before reading, and the workgroup size does
+// not change any result.
+// ---------------------------------------------------------------------------
+lsmg_status ensure_events(lsmg_batch *B, size_t n)
+{
+    while (B->evpool.size() < n) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        B->evpool.push_back(e);
+    }
+    return LSMG_OK;
+}
+
+template <typename T>
+void tune_launch(lsmg_batch *B, const BSize &S, int cls, const Exec &x)
+{
+    const LevelDesc<T> *d = bdescs<T>(B);
+    switch (cls) {
+    case kTSmooth:
+        launch_smooth_colour<T>(B->dim, d, items(B, S.seg[0]), S.seg[0].n, 0, x);
+        break;
+    case kTGhost:
+        launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, 0, B->p.ghost_sweeps, true, x, Exec(x.s, x.act, x.ipb));
+        break;
+    case kTDefect:
+        launch_defect<T>(B->dim, d, items(B, S.act), S.act.n, -1, x);
+        break;
+    case kTRestrict:
+        launch_restrict<T>(B->dim, d, items(B, S.rcoarse), S.rcoarse.n, x);
+        break;
+    case kTProlong:
+        launch_prolong<T>(B->dim, d, items(B, S.act), S.act.n, x);
+        break;
+    default:
+        launch_band<T>(d, items(B, S.band), S.band.n, x);
+        break;
+    }
+}
+
+template <typename T>
+lsmg_status b_autotune(lsmg_batch *B, int reps)
+{
+    static const int cand[4] = {1, 2, 4, 8};
+    LSMGCHK(ensure_events(B, (size_t)2 * reps));
+    for (BSize &S : B->sizes) {
+        if (S.act.n == 0) continue;
+        for (int cls = 0; cls < kTClasses; ++cls) {
+            double best = 1e300;
+            int best_ipb = kItemsPerBlock;
+            for (int ci = 0; ci < 4; ++ci) {
+                // one untimed launch, then reps timed ones
+                tune_launch<T>(B, S, cls, bexec(B, B->stream, cand[ci]));
+                for (int r = 0; r < reps; ++r) {
+                    Exec x = bexec(B, B->stream, cand[ci]);
+                    x.ev0 = B->evpool[2 * r];
+                    x.ev1 = B->evpool[2 * r + 1];
+                    tune_launch<T>(B, S, cls, x);
+                }
+                HIPCHK(hipStreamSynchronize(B->stream));
+                double tot = 0.0;
+                for (int r = 0; r < reps; ++r) {
+                    float ms = 0.0f;
+                    if (hipEventElapsedTime(&ms, B->evpool[2 * r], B->evpool[2 * r + 1]) == hipSuccess) tot += ms;
+                }
+                if (tot < best) {
+                    best = tot;
+                    best_ipb = cand[ci];
+                }
+            }
+            S.ipb[cls] = best_ipb;
+        }
+    }
+    B->tuned = 1;
+    b_invalidate(B);
+    return LSMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// construction
+// ---------------------------------------------------------------------------
+struct Job {
+    const int4 *src;
+    int cnt, dshift;
+};
+
+lsmg_status build_lists(lsmg_batch *B)
+{
+    // grid sizes present in the batch, finest first
+    std::vector<int> ns;
+    for (lsmg_hierarchy *H : B->mem)
+        for (int l = 0; l < H->nlev; ++l) ns.push_back(H->L[l].n);
+    std::sort(ns.begin(), ns.end(), std::greater<int>());
+    ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
+    B->sizes.assign(ns.size(), BSize{});
+    std::map<int, int> zi;
+    for (size_t z = 0; z < ns.size(); ++z) {
+        zi[ns[z]] = (int)z;
+        B->sizes[z].n = ns[z];
+        for (int c = 0; c < kTClasses; ++c) B->sizes[z].ipb[c] = kItemsPerBlock;
+    }
+    std::vector<Job> jobs;
+    int total = 0;
+    auto add = [&](BList &L, const std::vector<Job> &js) {
+        L.off = total;
+        L.n = 0;
+        for (const Job &j : js) {
+            if (j.cnt <= 0) continue;
+            jobs.push_back(j);
+            L.n += j.cnt;
+            total += j.cnt;
+        }
+    };
+    const int nk = B->ndom;
+    for (size_t z = 0; z < ns.size(); ++z) {
+        BSize &S = B->sizes[z];
+        std::vector<Job> seg0, seg1, gh, act, band, rco, ico;
+        for (int k = 0; k < nk; ++k) {
+            const lsmg_hierarchy *H = B->mem[k];
+            for (int l = 0; l < H->nlev; ++l) {
+                const Level &Lv = H->L[l];
+                if (Lv.n != ns[z]) continue;
+                const int ds = B->d0[k];
+                if (l + 1 < H->nlev) {
+                    const Level &C = H->L[l + 1];
+                    ico.push_back({C.w_act(), C.nw_act(), ds});
+                }
+                if (l >= H->tail_l0) continue;
+                seg0.push_back({Lv.w_seg(0), Lv.nseg[0], ds});
+                seg1.push_back({Lv.w_seg(1), Lv.nseg[1], ds});
+                gh.push_back({Lv.w_gh(), Lv.nghc, ds});
+                act.push_back({Lv.w_act(), Lv.nw_act(), ds});
+                band.push_back({Lv.w_band(), Lv.nbandc, ds});
+                const Level &C = H->L[l + 1];
+                rco.push_back({C.w_act(), C.nw_act(), ds});
+            }
+        }
+        add(S.seg[0], seg0);
+        add(S.seg[1], seg1);
+        add(S.gh, gh);
+        add(S.act, act);
+        add(S.band, band);
+        add(S.rcoarse, rco);
+        add(S.icoarse, ico);
+    }
+    std::vector<Job> l0, al;
+    for (int k = 0; k < nk; ++k) {
+        const lsmg_hierarchy *H = B->mem[k];
+        l0.push_back({H->L[0].w_act(), H->L[0].nw_act(), B->d0[k]});
+        for (int l = 0; l < H->nlev; ++l) al.push_back({H->L[l].w_act(), H->L[l].nw_act(), B->d0[k]});
+    }
+    add(B->lev0, l0);
+    add(B->all, al);
+    B->npool = total;
+    LSMGCHK(B->alloc(&B->pool, total));
+    // one launch copies every block; the job table is freed after the copy
+    std::vector<ItemCopy> hj(jobs.size());
+    int off = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        hj[i].src = jobs[i].src;
+        hj[i].cnt = jobs[i].cnt;
+        hj[i].off = off;
+        hj[i].dshift = jobs[i].dshift;
+        hj[i].pad = 0;
+        off += jobs[i].cnt;
+    }
+    if (!hj.empty()) {
+        ItemCopy *dj = nullptr;
+        HIPCHK(hipMalloc(&dj, sizeof(ItemCopy) * hj.size()));
+        HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(ItemCopy) * hj.size(), hipMemcpyHostToDevice, B->stream));
+        launch_copy_items(dj, (int)hj.size(), B->pool, B->stream);
+        HIPCHK(hipStreamSynchronize(B->stream));
+        (void)hipFree(dj);
+    }
+    return LSMG_OK;
+}
+
+bool same_params(const lsmg_params &a, const lsmg_params &b)
+{
+    return a.a == b.a && a.d == b.d && a.m_s == b.m_s && a.m_c == b.m_c && a.alpha == b.alpha && a.beta == b.beta &&
+           a.tau_s == b.tau_s && a.nu1 == b.nu1 && a.nu2 == b.nu2 && a.ghost_sweeps == b.ghost_sweeps &&
+           a.band_steps == b.band_steps && a.ghost_c_new == b.ghost_c_new && a.coarsest_n == b.coarsest_n &&
+           a.precision == b.precision && a.newton_tol == b.newton_tol && a.newton_max == b.newton_max &&
+           a.lin_rtol == b.lin_rtol && a.cycles_max == b.cycles_max;
+}
+
+lsmg_status b_build(lsmg_batch *B)
+{
+    const int nk = B->ndom;
+    B->d0.assign(nk, 0);
+    int nd = 0;
+    for (int k = 0; k < nk; ++k) {
+        B->d0[k] = nd;
+        nd += B->mem[k]->nlev;
+    }
+    B->ndesc = nd;
+    B->hd64.assign(nd, LevelDesc<double>{});
+    B->hd32.assign(nd, LevelDesc<float>{});
+    LSMGCHK(B->alloc(&B->d64, nd));
+    LSMGCHK(B->alloc(&B->d32, nd));
+    B->norm_stride = (long long)nk * kNormSlots;
+    LSMGCHK(B->alloc(&B->d_norms, 4 * B->norm_stride));
+    LSMGCHK(B->alloc(&B->d_nred, 4LL * nk));
+    LSMGCHK(B->alloc(&B->d_act, nd));
+    LSMGCHK(B->alloc(&B->d_cstatus, nk));
+    HIPCHK(hipHostMalloc(&B->h_nred, sizeof(unsigned long long) * 4 * nk, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&B->h_act, sizeof(int) * nd, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&B->h_cstatus, sizeof(int) * nk, hipHostMallocDefault));
+    // coarse tails and coarsest operators, one workgroup per member
+    std::vector<TailArgs> ta(nk);
+    std::vector<CoarseArgs> ca(nk);
+    for (int k = 0; k < nk; ++k) {
+        const lsmg_hierarchy *H = B->mem[k];
+        ta[k] = tail_args(H, H->tail_l0, B->d0[k]);
+        B->tail_na_max = std::max(B->tail_na_max, H->L[H->nlev - 1].na);
+        ca[k] = CoarseArgs{};
+        ca[k].desc = B->d0[k] + H->nlev - 1;
+        ca[k].c2s = H->L[H->nlev - 1].c2s;
+        ca[k].M = H->lu;
+        ca[k].Ainv = H->ainv;
+        ca[k].status = B->d_cstatus + k;
+        B->coarse_n_max = std::max(B->coarse_n_max, H->luN);
+    }
+    LSMGCHK(B->alloc(&B->d_tail, nk));
+    LSMGCHK(B->alloc(&B->d_coarse, nk));
+    HIPCHK(hipMemcpyAsync(B->d_tail, ta.data(), sizeof(TailArgs) * nk, hipMemcpyHostToDevice, B->stream));
+    HIPCHK(hipMemcpyAsync(B->d_coarse, ca.data(), sizeof(CoarseArgs) * nk, hipMemcpyHostToDevice, B->stream));
+    LSMGCHK(build_lists(B));
+    LSMGCHK(refresh_descs(B, nullptr, nullptr, nullptr));
+    return LSMG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, void *stream, lsmg_batch **out)
+{
+    if (!out) return fail(LSMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!members || count < 1) return fail(LSMG_EINVAL, "a batch needs at least one member");
+    for (int k = 0; k < count; ++k) {
+        if (!members[k]) return fail(LSMG_EINVAL, "member %d is NULL", k);
+        for (int j = 0; j < k; ++j)
+            if (members[j] == members[k]) return fail(LSMG_EINVAL, "member %d appears twice", k);
+        if (members[k]->dim != members[0]->dim) return fail(LSMG_EINVAL, "members differ in dimension");
+        if (!same_params(members[k]->p, members[0]->p)) return fail(LSMG_EINVAL, "members differ in parameters");
+        if (!members[k]->p.ghost_c_new)
+            return fail(LSMG_ENOTIMPL, "batches use the composed ghost relaxation (ghost_c_new = 1)");
+        if (members[k]->p.precision == 1 && !members[k]->have32) return fail(LSMG_EINVAL, "member %d has no FP32 copy", k);
+    }
+    lsmg_batch *B = new (std::nothrow) lsmg_batch();
+    if (!B) return fail(LSMG_EOOM, "host allocation");
+    B->dim = members[0]->dim;
+    B->p = members[0]->p;
+    B->ndom = count;
+    B->stream = (hipStream_t)stream;
+    B->mem.assign(members, members + count);
+    if (const char *e = std::getenv("LSMG_GRAPHS")) B->use_graphs = std::atoi(e) != 0;
+    lsmg_status st = b_build(B);
+    if (st != LSMG_OK) {
+        (void)hipStreamSynchronize(B->stream);
+        delete B;
+        return st;
+    }
+    *out = B;
+    return LSMG_OK;
+}
+
+void lsmg_batch_destroy(lsmg_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+lsmg_status lsmg_batch_set_autotune(lsmg_batch *b, int enable)
+{
+    if (!b) return fail(LSMG_EINVAL, "batch is NULL");
+    b->autotune = enable ? 1 : 0;
+    if (!enable && b->tuned) {
+        for (BSize &S : b->sizes)
+            for (int c = 0; c < kTClasses; ++c) S.ipb[c] = kItemsPerBlock;
+        b->tuned = 0;
+        b_invalidate(b);
+    }
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_batch_tuning(const lsmg_batch *b, int cap, int *count, int *sizes, int *ipb)
+{
+    if (!b || !count) return fail(LSMG_EINVAL, "NULL argument");
+    *count = (int)b->sizes.size();
+    for (int z = 0; z < *count && z < cap; ++z) {
+        if (sizes) sizes[z] = b->sizes[z].n;
+        if (ipb)
+            for (int c = 0; c < kTClasses; ++c) ipb[z * kTClasses + c] = b->sizes[z].ipb[c];
+    }
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt, const double *const *d_sb,
+                            const double *sb_const, lsmg_status *status, lsmg_step_stats *stats)
+{
+    if (!b || !states) return fail(LSMG_EINVAL, "NULL argument");
+    lsmg_batch *B = b;
+    const int nk = B->ndom;
+    for (int k = 0; k < nk; ++k)
+        if (!states[k] || states[k]->h != B->mem[k]) return fail(LSMG_EINVAL, "state %d does not belong to member %d", k, k);
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LSMG_EINVAL, "dt must be positive and finite");
+    // descriptors: dt of every member and the arrays of this step
+    bool changed = dt != B->dt;
+    B->dt = dt;
+    for (int k = 0; k < nk; ++k)
+        if (B->mem[k]->dt != dt) {
+            LSMGCHK(set_dt(B->mem[k], dt));
+            changed = true;
+        }
+    std::vector<const lsmg_state *> sv(states, states + nk);
+    std::vector<const double *> sbv(nk, nullptr);
+    std::vector<double> sbc(nk, 1.0);
+    for (int k = 0; k < nk; ++k) {
+        if (d_sb) sbv[k] = d_sb[k];
+        if (sb_const) sbc[k] = sb_const[k];
+    }
+    if (changed || sv != B->last_states || sbv != B->last_sb || sbc != B->last_sbc) {
+        LSMGCHK(refresh_descs(B, states, sbv.data(), sbc.data()));
+        B->last_states = sv;
+        B->last_sb = sbv;
+        B->last_sbc = sbc;
+    }
+    const bool mixed = B->p.precision == 1;
+    hipStream_t s = B->stream;
+    const Exec x0(s, B->d_act);
+    std::vector<lsmg_status> rc(nk, LSMG_ENOCONV);
+    std::vector<char> on(nk, 1), lin(nk, 0);
+    std::vector<int> cycles(nk, 0), nrho(nk, 0), iters(nk, 0);
+    std::vector<double> nF(nk, 0.0), rho_last(nk, 0.0), logsum(nk, 0.0), dwrel(nk, 0.0), rprev(nk, 0.0);
+    LSMGCHK(set_flags(B, on));
+    // explicit half, first iterate and F(W^n)
+    launch_explicit_half(B->dim, B->d64, items(B, B->lev0), B->lev0.n, x0);
+    zero_bnorms(B, 0, 4, s);
+    launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, x0);
+    LSMGCHK(read_bnorms(B, 0, 1));
+    for (int k = 0; k < nk; ++k) nF[k] = bnorm(B, k, 0);
+    for (int it = 1; it <= B->p.newton_max; ++it) {
+        int nact = 0;
+        for (int k = 0; k < nk; ++k) {
+            if (!on[k]) continue;
+            if (!std::isfinite(nF[k])) {
+                rc[k] = LSMG_ENONFINITE;
+                on[k] = 0;
+                continue;
+            }
+            iters[k] = it;
+            ++nact;
+        }
+        if (nact == 0) break;
+        LSMGCHK(set_flags(B, on));
+        // linearisation: coarse (s, c) level by level, FP32 copies, coarsest inverses
+        for (const BSize &S : B->sizes) launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, x0);
+        if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, x0);
+        launch_coarse_factor(B->dim, B->d64, B->d_coarse, nk, B->coarse_n_max, x0);
+        HIPCHK(hipMemcpyAsync(B->h_cstatus, B->d_cstatus, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < nk; ++k)
+            if (on[k] && B->h_cstatus[k] != 0) {
+                rc[k] = LSMG_ENONFINITE;
+                on[k] = 0;
+            }
+        LSMGCHK(set_flags(B, on));
+        if (B->autotune && !B->tuned) {
+            if (mixed) LSMGCHK(b_autotune<float>(B, 3));
+            else LSMGCHK(b_autotune<double>(B, 3));
+        }
+        // linear solves J dW = F from dW = 0
+        launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, x0);
+        if (mixed) launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, x0);
+        hipGraphExec_t ge = nullptr;
+        // timed launches run direct: events inside a graph cannot be timed
+        if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &ge));
+        for (int k = 0; k < nk; ++k) {
+            lin[k] = on[k];
+            rprev[k] = nF[k];
+        }
+        for (int q = 0; q < B->p.cycles_max; ++q) {
+            int nlin = 0;
+            for (int k = 0; k < nk; ++k) {
+                if (lin[k] && rprev[k] <= B->p.lin_rtol * nF[k]) lin[k] = 0;
+                nlin += lin[k];
+            }
+            if (nlin == 0) break;
+            LSMGCHK(set_flags(B, lin));
+            if (ge) HIPCHK(hipGraphLaunch(ge, s));
+            else b_cycle_enqueue(B, mixed, s);
+            HIPCHK(hipMemcpyAsync(B->h_nred, B->d_nred, sizeof(unsigned long long) * 4 * nk, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (!ge) b_prof_collect(B);
+            for (int k = 0; k < nk; ++k) {
+                if (!lin[k]) continue;
+                const double rq = bnorm(B, k, 1);
+                ++cycles[k];
+                rho_last[k] = rprev[k] > 0.0 ? rq / rprev[k] : 0.0;
+                if (rho_last[k] > 0.0) logsum[k] += std::log(rho_last[k]);
+                ++nrho[k];
+                rprev[k] = rq;
+                if (!std::isfinite(rq)) lin[k] = 0;
+            }
+        }
+        // Newton update and the new residual
+        LSMGCHK(set_flags(B, on));
+        zero_bnorms(B, 0, 4, s);
+        launch_newton_update(B->dim, B->d64, items(B, B->lev0), B->lev0.n, x0);
+        launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, x0);
+        LSMGCHK(read_bnorms(B, 0, 4));
+        for (int k = 0; k < nk; ++k) {
+            if (!on[k]) continue;
+            nF[k] = bnorm(B, k, 0);
+            const double nD = bnorm(B, k, 2), nW = bnorm(B, k, 3);
+            dwrel[k] = nW > 0.0 ? nD / nW : nD;
+            if (!std::isfinite(nF[k]) || !std::isfinite(dwrel[k])) {
+                rc[k] = LSMG_ENONFINITE;
+                on[k] = 0;
+            } else if ((nF[k] < dwrel[k] ? nF[k] : dwrel[k]) < B->p.newton_tol) {
+                rc[k] = LSMG_OK;
+                on[k] = 0;
+            }
+        }
+    }
+    // commit the members that converged
+    std::vector<char> ok(nk, 0);
+    lsmg_status first_bad = LSMG_OK;
+    for (int k = 0; k < nk; ++k) {
+        ok[k] = rc[k] == LSMG_OK;
+        if (!ok[k] && first_bad == LSMG_OK) first_bad = rc[k];
+    }
+    LSMGCHK(set_flags(B, ok));
+    launch_commit(B->dim, B->d64, items(B, B->lev0), B->lev0.n, x0);
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < nk; ++k) {
+        if (status) status[k] = rc[k];
+        if (stats) {
+            stats[k].newton_iters = iters[k];
+            stats[k].vcycles = cycles[k];
+            stats[k].res_inf = nF[k];
+            stats[k].rho_last = rho_last[k];
+            stats[k].rho_geo = nrho[k] > 0 ? std::exp(logsum[k] / nrho[k]) : 0.0;
+            stats[k].dw_rel = dwrel[k];
+        }
+        B->mem[k]->lin_set = false;
+    }
+    if (first_bad != LSMG_OK) {
+        for (int k = 0; k < nk; ++k)
+            if (rc[k] != LSMG_OK) {
+                fail(rc[k], "member %d: %s", k,
+                     rc[k] == LSMG_ENOCONV ? "Newton did not converge" : "non-finite iterate or singular coarsest operator");
+                break;
+            }
+    }
+    return first_bad;
+}
+
+lsmg_status lsmg_batch_profile_start(lsmg_batch *b, int kernel, int n)
+{
+    if (!b) return fail(LSMG_EINVAL, "batch is NULL");
+    if (kernel < LSMG_KERNEL_SMOOTH || kernel > LSMG_KERNEL_GHOST) return fail(LSMG_EINVAL, "unknown kernel class");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->prof_kernel = kernel;
+    b->prof_n = n;
+    b->prof_used = 0;
+    b->prof_acc_ms = 0.0;
+    b->prof_acc_n = 0;
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_batch_profile_stop(lsmg_batch *b, int *launches, double *total_ms)
+{
+    if (!b) return fail(LSMG_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b_prof_collect(b);
+    if (launches) *launches = (int)b->prof_acc_n;
+    if (total_ms) *total_ms = b->prof_acc_ms;
+    b->prof_kernel = -1;
+    b->prof_n = -1;
+    return LSMG_OK;
+}
+
+}  // extern "C"

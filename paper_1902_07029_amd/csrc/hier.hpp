@@ -1,0 +1,163 @@
+// Host-side state of the lsmg library shared by its translation units: the
+// hierarchy and state objects behind the opaque C handles, error reporting and
+// the helpers both the single-hierarchy and the batch drivers use.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lsmg.h"
+#include "lsmg_dev.hpp"
+#include "lsmg_host.hpp"
+
+namespace lsmg {
+
+// records the message of a failing call (thread-local) and returns its status
+lsmg_status fail(lsmg_status st, const char *fmt, ...);
+
+#define HIPCHK(x)                                                                                      \
+    do {                                                                                               \
+        hipError_t e_ = (x);                                                                           \
+        if (e_ != hipSuccess) return ::lsmg::fail(LSMG_EHIP, "%s failed: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LSMGCHK(x)                        \
+    do {                                  \
+        lsmg_status s_ = (x);             \
+        if (s_ != LSMG_OK) return s_;     \
+    } while (0)
+
+struct Level {
+    int n = 0, Wp = 0;
+    long long rows = 0, cs = 0, ssize = 0;
+    double h = 0.0;
+    int ni = 0, ng = 0, na = 0, nb = 0, bmax = 0;
+    uint8_t *type = nullptr, *ext = nullptr;
+    int *cmap = nullptr, *c2s = nullptr;
+    int64_t *c2g = nullptr;
+    double *s = nullptr, *c = nullptr, *rhs_s = nullptr, *rhs_c = nullptr, *x_s = nullptr, *x_c = nullptr,
+           *r_s = nullptr, *r_c = nullptr;
+    int *g_idx = nullptr, *g_ijk = nullptr, *g_st = nullptr, *g_stg = nullptr, *g_stc = nullptr, *g_order = nullptr,
+        *g_bfall = nullptr;
+    double *g_w = nullptr, *g_B = nullptr, *g_nrm = nullptr, *g_buf0 = nullptr, *g_buf1 = nullptr;
+    int *b_idx = nullptr, *b_cnt = nullptr, *b_src = nullptr;
+    double *b_wt = nullptr;
+    float *s32 = nullptr, *c32 = nullptr, *rhs_s32 = nullptr, *rhs_c32 = nullptr, *x_s32 = nullptr, *x_c32 = nullptr,
+          *r_s32 = nullptr, *r_c32 = nullptr, *g_w32 = nullptr, *g_buf0_32 = nullptr, *g_buf1_32 = nullptr,
+          *b_wt32 = nullptr;
+    int *in_ijk = nullptr;                      // packed coordinates of inside nodes, colour 0 then 1
+    int nin[2] = {0, 0};
+    int *go_ptr = nullptr, *go_col = nullptr;   // composed ghost relaxation (CSR over ghosts)
+    double *go_a = nullptr, *go_b = nullptr;
+    float *go_a32 = nullptr, *go_b32 = nullptr;
+    int4 *items = nullptr;              // [seg colour 0 | seg colour 1 | ghost chunks | band chunks]
+    int nseg[2] = {0, 0}, nghc = 0, nbandc = 0;
+    const int4 *w_seg(int colour) const { return items + (colour ? nseg[0] : 0); }
+    const int4 *w_act() const { return items; }
+    int nw_act() const { return nseg[0] + nseg[1] + nghc; }
+    const int4 *w_gh() const { return items + nseg[0] + nseg[1]; }
+    const int4 *w_band() const { return items + nseg[0] + nseg[1] + nghc; }
+};
+
+}  // namespace lsmg
+
+using namespace lsmg;
+
+struct lsmg_hierarchy {
+    int dim = 2, nst = 9, nlev = 0;
+    double lo = -1.0, hi = 1.0;
+    lsmg_params p{};
+    hipStream_t stream = nullptr;
+    std::vector<lsmg::Level> L;
+    std::vector<LevelDesc<double>> hd64;
+    std::vector<LevelDesc<float>> hd32;
+    LevelDesc<double> *d64 = nullptr;
+    LevelDesc<float> *d32 = nullptr;
+    bool have32 = false;
+    double dt = 0.0;
+    bool lin_set = false;
+    double *bs = nullptr, *bc = nullptr, *tmp_s = nullptr, *tmp_c = nullptr;
+    double *lu = nullptr, *ainv = nullptr;
+    int *piv = nullptr, *lu_status = nullptr;
+    int luN = 0;
+    int tail_l0 = 0;   // first level handled by the coarse-tail kernel
+    unsigned long long *d_norms = nullptr, *h_norms = nullptr;
+    TailArgs *d_tail = nullptr;      // coarse-tail arguments, entry l for a tail starting at level l
+    CoarseArgs *d_coarse = nullptr;  // coarsest-operator arguments
+    // the Crank-Nicolson step's arrays currently named by the level-0 descriptor
+    const double *step_sn = nullptr, *step_cn = nullptr, *step_fn = nullptr, *step_fnp1 = nullptr,
+                 *step_sb = nullptr;
+    double step_sb_const = 0.0;
+    int *h_status = nullptr;
+    std::vector<void *> allocs;
+    // launch timing of one kernel class on one level (HIP events on the stream)
+    int prof_kernel = -1, prof_level = -1;
+    std::vector<hipEvent_t> prof_pool;
+    size_t prof_used = 0;
+    double prof_acc_ms = 0.0;
+    long long prof_acc_n = 0;
+    // V-cycle graphs (0: FP64 cycle, 1: mixed-precision refinement step), captured on a private stream
+    bool use_graphs = true;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    size_t prof_pending = 0;
+    // composed ghost relaxation tables (CSR over ghosts), owned separately: rebuilt with the parameters
+    std::vector<void *> ghost_ops;
+    ~lsmg_hierarchy()
+    {
+        for (int i = 0; i < 2; ++i)
+            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (void *p : ghost_ops) (void)hipFree(p);
+        for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
+        for (void *p : allocs) (void)hipFree(p);
+        if (h_norms) (void)hipHostFree(h_norms);
+        if (h_status) (void)hipHostFree(h_status);
+    }
+    template <typename T>
+    lsmg_status alloc(T **ptr, long long count)
+    {
+        *ptr = nullptr;
+        if (count <= 0) count = 1;
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess)
+            return fail(LSMG_EOOM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
+        allocs.push_back(p);
+        *ptr = (T *)p;
+        return LSMG_OK;
+    }
+    template <typename T>
+    lsmg_status zalloc(T **ptr, long long count)
+    {
+        LSMGCHK(alloc(ptr, count));
+        HIPCHK(hipMemsetAsync(*ptr, 0, sizeof(T) * (size_t)(count > 0 ? count : 1), stream));
+        return LSMG_OK;
+    }
+};
+
+struct lsmg_state {
+    lsmg_hierarchy *h = nullptr;
+    double *s = nullptr, *c = nullptr;
+    ~lsmg_state()
+    {
+        (void)hipFree(s);
+        (void)hipFree(c);
+    }
+};
+
+
+namespace lsmg {
+
+// sets dt (and the descriptor scalars that depend on it) on a hierarchy
+lsmg_status set_dt(lsmg_hierarchy *H, double dt);
+// fills the model and solver scalars of the host copies of the descriptors
+void fill_desc_scalars(lsmg_hierarchy *H);
+// FP32 copies of every level (mixed precision)
+lsmg_status build_f32(lsmg_hierarchy *H);
+// the coarse-tail arguments of hierarchy H for a tail starting at level l0,
+// its descriptors starting at d0 in the descriptor array the launch uses
+TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0);
+
+}  // namespace lsmg

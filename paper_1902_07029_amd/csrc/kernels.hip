@@ -11,6 +11,8 @@
 // the mixed-precision V-cycle) and on the dimension.  Jacobian entries are never
 // stored: each element evaluates the rows it needs from the linearisation point
 // (s, c), so a sweep moves only s, c, the right-hand side and the correction.
+#include <hip/hip_ext.h>
+
 #include "lsmg_dev.hpp"
 #include "lsmg_host.hpp"
 
@@ -459,23 +461,29 @@ __device__ __forceinline__ int logical_block()
     return x * q + (x < r ? x : r) + i;
 }
 
-#define LSMG_ITEM_PROLOGUE                                                          \
-    const int it = logical_block() * kItemsPerBlock + (threadIdx.x >> 6);          \
-    if (it >= nwork) return;                                                       \
-    const int4 w = work[it];                                                       \
+// Every item kernel ends with `act`, per-descriptor flags (null: all active);
+// the items of a descriptor whose flag is 0 are skipped.  A wavefront returns
+// as a whole, so the wavefront reductions that follow never see part of one.
+#define LSMG_ITEM_PROLOGUE                                                                  \
+    const int it = logical_block() * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);     \
+    if (it >= nwork) return;                                                               \
+    const int4 w = work[it];                                                               \
+    if (act && !act[item_desc(w)]) return;                                                 \
     const int lane = threadIdx.x & 63;
 
+#define LSMG_ITEMS const int4 *__restrict__ work, int nwork
+#define LSMG_ACT const int *__restrict__ act
+
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_smooth_colour(const LevelDesc<T> *__restrict__ descs,
-                                                          const int4 *__restrict__ work, int nwork, int colour)
+__global__ __launch_bounds__(kMaxBlock) void k_smooth_colour(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS,
+                                                             int colour, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     smooth_elem<T, DIM>(descs + item_desc(w), w, lane, colour);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ghost_load(const LevelDesc<T> *__restrict__ descs,
-                                                       const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_ghost_load(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const int q = w.z + lane;
@@ -483,8 +491,8 @@ __global__ __launch_bounds__(kBlock) void k_ghost_load(const LevelDesc<T> *__res
 }
 
 template <typename T, int NST>
-__global__ __launch_bounds__(kBlock) void k_ghost_sweep(const LevelDesc<T> *__restrict__ descs,
-                                                        const int4 *__restrict__ work, int nwork, int parity)
+__global__ __launch_bounds__(kMaxBlock) void k_ghost_sweep(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS,
+                                                           int parity, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<T> *D = descs + item_desc(w);
@@ -493,8 +501,8 @@ __global__ __launch_bounds__(kBlock) void k_ghost_sweep(const LevelDesc<T> *__re
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ghost_final(const LevelDesc<T> *__restrict__ descs,
-                                                        const int4 *__restrict__ work, int nwork, int parity)
+__global__ __launch_bounds__(kMaxBlock) void k_ghost_final(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS,
+                                                           int parity, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<T> *D = descs + item_desc(w);
@@ -503,8 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_final(const LevelDesc<T> *__re
 }
 
 template <typename T, int NST>
-__global__ __launch_bounds__(kBlock) void k_ghost_b(const LevelDesc<T> *__restrict__ descs,
-                                                    const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_ghost_b(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const int q = w.z + lane;
@@ -512,8 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_b(const LevelDesc<T> *__restri
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ghost_apply(const LevelDesc<T> *__restrict__ descs,
-                                                        const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_ghost_apply(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const int q = w.z + lane;
@@ -523,8 +529,8 @@ __global__ __launch_bounds__(kBlock) void k_ghost_apply(const LevelDesc<T> *__re
 // the same for long composed rows (3-D): 16 lanes share a row, each wavefront
 // walks the 64 ghosts of its item four rows at a time with coalesced reads
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ghost_apply_grouped(const LevelDesc<T> *__restrict__ descs,
-                                                                const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_ghost_apply_grouped(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS,
+                                                                   LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<T> *D = descs + item_desc(w);
@@ -570,27 +576,26 @@ __global__ __launch_bounds__(1024) void k_ghost_fused(const LevelDesc<T> *__rest
     for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_final_elem<T>(D, q, bfin, bprev);
 }
 
+// defect on the items' rows; norm_k >= 0 also accumulates |r|_inf into that norm
 template <typename T, int DIM, int NST>
-__global__ __launch_bounds__(kBlock) void k_defect(const LevelDesc<T> *__restrict__ descs,
-                                                   const int4 *__restrict__ work, int nwork,
-                                                   unsigned long long *norm_slot)
+__global__ __launch_bounds__(kMaxBlock) void k_defect(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, int norm_k,
+                                                      LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
-    const unsigned long long bits = defect_elem<T, DIM, NST>(descs + item_desc(w), w, lane);
-    if (norm_slot) norm_accumulate(norm_slot, bits);
+    const LevelDesc<T> *D = descs + item_desc(w);
+    const unsigned long long bits = defect_elem<T, DIM, NST>(D, w, lane);
+    if (norm_k >= 0) norm_accumulate(D, norm_k, bits);
 }
 
 template <typename T, int DIM, int NST>
-__global__ __launch_bounds__(kBlock) void k_apply_J(const LevelDesc<T> *__restrict__ descs,
-                                                    const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_apply_J(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     apply_J_elem<T, DIM, NST>(descs + item_desc(w), w, lane);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_band(const LevelDesc<T> *__restrict__ descs,
-                                                 const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_band(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const int b = w.z + lane;
@@ -598,32 +603,43 @@ __global__ __launch_bounds__(kBlock) void k_band(const LevelDesc<T> *__restrict_
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_restrict(const LevelDesc<T> *__restrict__ descs,
-                                                     const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_restrict(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     restrict_elem<T, DIM>(descs + item_desc(w), w, lane);
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_prolong(const LevelDesc<T> *__restrict__ descs,
-                                                    const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_prolong(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     prolong_elem<T, DIM>(descs + item_desc(w), w, lane);
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_inject(const LevelDesc<T> *__restrict__ descs,
-                                                   const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_inject(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     inject_elem<T, DIM>(descs + item_desc(w), w, lane);
 }
 
+// zero correction on the items' nodes
+template <typename T, int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_zero_x(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
+{
+    LSMG_ITEM_PROLOGUE
+    const LevelDesc<T> *D = descs + item_desc(w);
+    long long idx;
+    int i, j, k;
+    if (!node_of<T, DIM>(D, w, lane, idx, i, j, k)) return;
+    D->x_s[idx] = T(0);
+    D->x_c[idx] = T(0);
+}
+
 // ---------------------------------------------------------------------------
 // coarse tail: levels l0 .. L-1 of a V-cycle in one workgroup, walking packed
-// node lists (one node per thread and pass) with barriers between phases
+// node lists (one node per thread and pass) with barriers between phases.
+// Workgroup b runs the tail of the hierarchy described by args[b].
 // ---------------------------------------------------------------------------
 // node t of a level's active list: inside nodes (colour 0, colour 1), then ghosts
 template <typename T>
@@ -691,12 +707,16 @@ __device__ void wg_coarse_apply(const LevelDesc<T> *D, const int *__restrict__ c
 }
 
 template <typename T, int DIM, int NST>
-__global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ descs, TailArgs A)
+__global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ descs,
+                                               const TailArgs *__restrict__ args, LSMG_ACT)
 {
     extern __shared__ double sb[];
+    const TailArgs &A = args[blockIdx.x];
+    if (act && !act[A.d0]) return;
+    const LevelDesc<T> *base = descs + A.d0;
     const int L = A.nlev;
     for (int l = A.l0; l < L - 1; ++l) {
-        const LevelDesc<T> *D = descs + l;
+        const LevelDesc<T> *D = base + l;
         const TailLevel &TL = A.lev[l];
         for (int it = 0; it < A.nu1; ++it) wg_smooth<T, DIM, NST>(D, TL, A.ghost_sweeps);
         const int nin = TL.nin0 + TL.nin1;
@@ -724,9 +744,9 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
         }
         __syncthreads();
     }
-    wg_coarse_apply<T>(descs + (L - 1), A.c2s, A.ainv, sb);
+    wg_coarse_apply<T>(base + (L - 1), A.c2s, A.ainv, sb);
     for (int l = L - 2; l >= A.l0; --l) {
-        const LevelDesc<T> *D = descs + l;
+        const LevelDesc<T> *D = base + l;
         const TailLevel &TL = A.lev[l];
         const int nin = TL.nin0 + TL.nin1;
         for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
@@ -742,16 +762,10 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // finest level, FP64: explicit half of the Crank-Nicolson step (section 3.1,
-// eq. discTime) and the Newton residual (eqs. FDs, FDc, BCs)
+// eq. discTime), the Newton residual (eqs. FDs, FDc, BCs), the Newton update
+// and the commit of W^{n+1}; the step's arrays are named by the level-0
+// descriptor
 // ---------------------------------------------------------------------------
-struct StepArgs {
-    const double *sn, *cn;          // W^n (split layout)
-    double *bs, *bc;                // explicit half (split layout)
-    const double *fn, *fnp1;        // compact [f1 | f2] or null
-    const double *sb;               // per-ghost boundary values or null
-    double sb_const;
-};
-
 template <int DIM>
 __device__ __forceinline__ double Ls_h(const LevelDesc<double> *D, const double *s, const double *c, long long idx,
                                        const long long *nb)
@@ -768,36 +782,40 @@ __device__ __forceinline__ double Lc_h(const LevelDesc<double> *D, const double 
     return -(2.0 * D->kc_half) * (D->alpha * c[idx] + D->beta) * s[idx] * c[idx];
 }
 
+// b = W^n / dt + L_h(W^n) / 2 (+ source average), and the first Newton iterate W = W^n
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_explicit_half(const LevelDesc<double> *__restrict__ descs,
-                                                          const int4 *__restrict__ work, int nwork, StepArgs A)
+__global__ __launch_bounds__(kMaxBlock) void k_explicit_half(const LevelDesc<double> *__restrict__ descs, LSMG_ITEMS,
+                                                             LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = descs + item_desc(w);
     long long idx;
     int i, j, k;
     if (!node_of<double, DIM>(D, w, lane, idx, i, j, k)) return;
+    const double *sn = D->sn, *cn = D->cn;
     const int r = D->cmap[idx];
     const int na = D->na;
     if (item_kind(w) < 2) {
         long long nb[2 * DIM];
         neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), (long long)j + (long long)D->n * k, i, i >> 1, nb);
-        double bsv = (D->alpha * A.cn[idx] + D->beta) * A.sn[idx] * D->dt_inv + 0.5 * Ls_h<DIM>(D, A.sn, A.cn, idx, nb);
-        if (A.fn) bsv += 0.5 * (A.fn[r] + A.fnp1[r]);
-        A.bs[idx] = bsv;
+        double bsv = (D->alpha * cn[idx] + D->beta) * sn[idx] * D->dt_inv + 0.5 * Ls_h<DIM>(D, sn, cn, idx, nb);
+        if (D->fn) bsv += 0.5 * (D->fn[r] + D->fnp1[r]);
+        D->bs[idx] = bsv;
     } else {
-        A.bs[idx] = 0.0;
+        D->bs[idx] = 0.0;
     }
-    double bcv = A.cn[idx] * D->dt_inv + 0.5 * Lc_h(D, A.sn, A.cn, idx);
-    if (A.fn) bcv += 0.5 * (A.fn[na + r] + A.fnp1[na + r]);
-    A.bc[idx] = bcv;
+    double bcv = cn[idx] * D->dt_inv + 0.5 * Lc_h(D, sn, cn, idx);
+    if (D->fn) bcv += 0.5 * (D->fn[na + r] + D->fnp1[na + r]);
+    D->bc[idx] = bcv;
+    D->s[idx] = sn[idx];
+    D->c[idx] = cn[idx];
 }
 
-// F(W) at the linearisation point (s, c) of level 0, written to rhs_s / rhs_c
+// F(W) at the linearisation point (s, c) of level 0, written to rhs_s / rhs_c;
+// norm_k >= 0 also accumulates |F|_inf
 template <int DIM, int NST>
-__global__ __launch_bounds__(kBlock) void k_residual(const LevelDesc<double> *__restrict__ descs,
-                                                     const int4 *__restrict__ work, int nwork, StepArgs A,
-                                                     unsigned long long *norm_slot)
+__global__ __launch_bounds__(kMaxBlock) void k_residual(const LevelDesc<double> *__restrict__ descs, LSMG_ITEMS,
+                                                        int norm_k, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = descs + item_desc(w);
@@ -810,29 +828,28 @@ __global__ __launch_bounds__(kBlock) void k_residual(const LevelDesc<double> *__
         if (item_kind(w) < 2) {
             long long nb[2 * DIM];
             neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), (long long)j + (long long)D->n * k, i, i >> 1, nb);
-            fs = (D->alpha * c[idx] + D->beta) * s[idx] * D->dt_inv - 0.5 * Ls_h<DIM>(D, s, c, idx, nb) - A.bs[idx];
+            fs = (D->alpha * c[idx] + D->beta) * s[idx] * D->dt_inv - 0.5 * Ls_h<DIM>(D, s, c, idx, nb) - D->bs[idx];
         } else {
             const int q = w.z + lane;
             const int ng = D->ng;
             double v = 0.0;
 #pragma unroll
             for (int kk = 0; kk < NST; ++kk) v += D->g_w[kk * ng + q] * s[D->g_st[kk * ng + q]];
-            fs = v - (A.sb ? A.sb[q] : A.sb_const);
+            fs = v - (D->sb ? D->sb[q] : D->sb_const);
         }
-        const double fc = c[idx] * D->dt_inv - 0.5 * Lc_h(D, s, c, idx) - A.bc[idx];
+        const double fc = c[idx] * D->dt_inv - 0.5 * Lc_h(D, s, c, idx) - D->bc[idx];
         D->rhs_s[idx] = fs;
         D->rhs_c[idx] = fc;
         const unsigned long long a = abs_bits(fs), b = abs_bits(fc);
         bits = a > b ? a : b;
     }
-    if (norm_slot) norm_accumulate(norm_slot, bits);
+    if (norm_k >= 0) norm_accumulate(D, norm_k, bits);
 }
 
-// W <- W - dW on active nodes, with |dW|_inf and |W_old|_inf
+// W <- W - dW on active nodes, with |dW|_inf into norm 2 and |W_old|_inf into norm 3
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_newton_update(const LevelDesc<double> *__restrict__ descs,
-                                                          const int4 *__restrict__ work, int nwork,
-                                                          unsigned long long *norm_dw, unsigned long long *norm_w)
+__global__ __launch_bounds__(kMaxBlock) void k_newton_update(const LevelDesc<double> *__restrict__ descs, LSMG_ITEMS,
+                                                             LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = descs + item_desc(w);
@@ -849,17 +866,30 @@ __global__ __launch_bounds__(kBlock) void k_newton_update(const LevelDesc<double
         D->s[idx] = s - xs;
         D->c[idx] = c - xc;
     }
-    norm_accumulate(norm_dw, bd);
-    norm_accumulate(norm_w, bw);
+    norm_accumulate(D, 2, bd);
+    norm_accumulate(D, 3, bw);
+}
+
+// W^{n+1} = W on active nodes
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_commit(const LevelDesc<double> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
+{
+    LSMG_ITEM_PROLOGUE
+    const LevelDesc<double> *D = descs + item_desc(w);
+    long long idx;
+    int i, j, k;
+    if (!node_of<double, DIM>(D, w, lane, idx, i, j, k)) return;
+    D->sn[idx] = D->s[idx];
+    D->cn[idx] = D->c[idx];
 }
 
 // ---------------------------------------------------------------------------
 // mixed precision: FP64 <-> FP32 transfers on a level
 // ---------------------------------------------------------------------------
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_to_f32(const LevelDesc<double> *__restrict__ d64,
-                                                   const LevelDesc<float> *__restrict__ d32,
-                                                   const int4 *__restrict__ work, int nwork, int what)
+__global__ __launch_bounds__(kMaxBlock) void k_to_f32(const LevelDesc<double> *__restrict__ d64,
+                                                      const LevelDesc<float> *__restrict__ d32, LSMG_ITEMS, int what,
+                                                      LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = d64 + item_desc(w);
@@ -879,9 +909,8 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const LevelDesc<double> *__re
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_add_f32(const LevelDesc<double> *__restrict__ d64,
-                                                    const LevelDesc<float> *__restrict__ d32,
-                                                    const int4 *__restrict__ work, int nwork)
+__global__ __launch_bounds__(kMaxBlock) void k_add_f32(const LevelDesc<double> *__restrict__ d64,
+                                                       const LevelDesc<float> *__restrict__ d32, LSMG_ITEMS, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<double> *D = d64 + item_desc(w);
@@ -956,22 +985,63 @@ __global__ void k_grid_to_split(const int64_t *__restrict__ c2g, int na, const d
 }
 
 // ---------------------------------------------------------------------------
+// batches: per-domain norm reduction and work-list assembly
+// ---------------------------------------------------------------------------
+// out[dom * 4 + k] = max over the kNormSlots slots of norm k of domain dom, for
+// k in [first, first + count); one 256-thread workgroup per domain
+__global__ __launch_bounds__(kNormSlots) void k_norm_reduce(const unsigned long long *__restrict__ base,
+                                                            long long stride, int first, int count,
+                                                            unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long part[kNormSlots / kWave];
+    const int dom = blockIdx.x;
+    for (int k = first; k < first + count; ++k) {
+        unsigned long long v = base[k * stride + (long long)dom * kNormSlots + threadIdx.x];
+        v = wave_max_u64(v);
+        if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long m = 0;
+            for (int i = 0; i < kNormSlots / kWave; ++i) m = part[i] > m ? part[i] : m;
+            out[dom * 4 + k] = m;
+        }
+        __syncthreads();
+    }
+}
+
+// concatenation of work lists: job b copies cnt items from src to dst + off,
+// adding dshift to each item's descriptor index
+__global__ void k_copy_items(const ItemCopy *__restrict__ jobs, int4 *__restrict__ dst)
+{
+    const ItemCopy J = jobs[blockIdx.x];
+    for (int t = threadIdx.x; t < J.cnt; t += blockDim.x) {
+        int4 v = J.src[t];
+        v.x += J.dshift << 2;
+        dst[J.off + t] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // coarsest level (FP64): the dense 2Na x 2Na operator assembled from the same
 // rows and inverted in place by Gauss-Jordan elimination with partial (row)
 // pivoting, in LDS when it fits, in one workgroup; the row interchanges are
-// undone as column interchanges at the end
+// undone as column interchanges at the end.  Workgroup b inverts the operator
+// described by args[b].
 // ---------------------------------------------------------------------------
 constexpr int kMaxCoarseN = 1024;
 
 template <int DIM, int NST>
-__global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> *__restrict__ descs, int lev,
-                                                        const int *__restrict__ c2s, double *__restrict__ Mglob,
-                                                        double *__restrict__ Ainv, int use_lds, int *__restrict__ status)
+__global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> *__restrict__ descs,
+                                                        const CoarseArgs *__restrict__ args, int use_lds, LSMG_ACT)
 {
     extern __shared__ double Mlds[];
-    const LevelDesc<double> *D = descs + lev;
+    const CoarseArgs &CA = args[blockIdx.x];
+    if (act && !act[CA.desc]) return;
+    const LevelDesc<double> *D = descs + CA.desc;
+    const int *__restrict__ c2s = CA.c2s;
+    double *__restrict__ Ainv = CA.Ainv;
     const int na = D->na, ni = D->ni, N = 2 * na;
-    double *M = use_lds ? Mlds : Mglob;     // row-major N x N
+    double *M = use_lds ? Mlds : CA.M;      // row-major N x N
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid >> 6, nwv = nt >> 6;
     __shared__ double fac[kMaxCoarseN];
@@ -1083,7 +1153,7 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
         }
     for (int r = wv; r < N; r += nwv)
         for (int c = lane; c < N; c += kWave) Ainv[r * N + c] = M[r * N + c];
-    if (tid == 0) *status = s_bad ? 1 : 0;
+    if (tid == 0) *CA.status = s_bad ? 1 : 0;
 }
 
 template <typename T>
@@ -1097,124 +1167,151 @@ __global__ __launch_bounds__(1024) void k_coarse_apply(const LevelDesc<T> *__res
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-static inline unsigned grid_of(int nwork) { return (unsigned)((nwork + kItemsPerBlock - 1) / kItemsPerBlock); }
+static inline unsigned grid_of(int nwork, int ipb) { return (unsigned)((nwork + ipb - 1) / ipb); }
+
+// one wavefront per item, x.ipb items per workgroup, `act` appended; with a
+// pair of events the launch is timed by its own dispatch
+template <auto KERN, typename... Args>
+static void item_launch(int nw, const Exec &x, Args... args)
+{
+    const int ipb = x.ipb >= 1 && x.ipb <= kMaxItemsPerBlock ? x.ipb : kItemsPerBlock;
+    const dim3 g(grid_of(nw, ipb)), b(kWave * ipb);
+    if (x.ev0) hipExtLaunchKernelGGL(KERN, g, b, 0, x.s, x.ev0, x.ev1, 0, args..., x.act);
+    else KERN<<<g, b, 0, x.s>>>(args..., x.act);
+}
 
 #define LSMG_DISPATCH_DIM(dim, ...) \
     do { if ((dim) == 2) { constexpr int DIM = 2; constexpr int NST = 9; __VA_ARGS__; } \
          else { constexpr int DIM = 3; constexpr int NST = 27; __VA_ARGS__; } } while (0)
 
 template <typename T>
-void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int colour, hipStream_t s)
+void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int colour, const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, (void)NST; k_smooth_colour<T, DIM><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, colour));
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_smooth_colour<T, DIM>>(nw, x, d, w, nw, colour));
 }
 
+// the ghost relaxation of one smoothing step: the composed map (two launches,
+// xb and xa), or the sweeps one by one (timed as a whole with xb's events)
 template <typename T>
 void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, int ng, int sweeps, bool composed,
-                  hipStream_t s)
+                  const Exec &xb, const Exec &xa)
 {
     if (nw <= 0) return;
     if (composed) {
-        LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_b<T, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
-        if (dim == 3) k_ghost_apply_grouped<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
-        else k_ghost_apply<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
+        LSMG_DISPATCH_DIM(dim, (void)DIM; item_launch<k_ghost_b<T, NST>>(nw, xb, d, w, nw));
+        if (dim == 3) item_launch<k_ghost_apply_grouped<T>>(nw, xa, d, w, nw);
+        else item_launch<k_ghost_apply<T>>(nw, xa, d, w, nw);
         return;
     }
+    Exec x = xb;
+    const hipEvent_t e0 = x.ev0, e1 = x.ev1;
+    x.ev0 = x.ev1 = nullptr;
+    if (e0) (void)hipEventRecord(e0, x.s);
     if (ng <= kGhostFusedMax) {
-        LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_fused<T, NST><<<1, 1024, 0, s>>>(d, desc, sweeps));
-        return;
+        LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_fused<T, NST><<<1, 1024, 0, x.s>>>(d, desc, sweeps));
+    } else {
+        item_launch<k_ghost_load<T>>(nw, x, d, w, nw);
+        for (int sw = 0; sw < sweeps; ++sw)
+            LSMG_DISPATCH_DIM(dim, (void)DIM; item_launch<k_ghost_sweep<T, NST>>(nw, x, d, w, nw, sw & 1));
+        item_launch<k_ghost_final<T>>(nw, x, d, w, nw, sweeps & 1);
     }
-    k_ghost_load<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
-    for (int sw = 0; sw < sweeps; ++sw)
-        LSMG_DISPATCH_DIM(dim, (void)DIM; k_ghost_sweep<T, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, sw & 1));
-    k_ghost_final<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, sweeps & 1);
+    if (e1) (void)hipEventRecord(e1, x.s);
 }
 
 template <typename T>
-void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, unsigned long long *slot, hipStream_t s)
+void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, k_defect<T, DIM, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, slot));
+    LSMG_DISPATCH_DIM(dim, item_launch<k_defect<T, DIM, NST>>(nw, x, d, w, nw, norm_k));
 }
 
 template <typename T>
-void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s)
+void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, k_apply_J<T, DIM, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
+    LSMG_DISPATCH_DIM(dim, item_launch<k_apply_J<T, DIM, NST>>(nw, x, d, w, nw));
 }
 
 template <typename T>
-void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s)
+void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x)
 {
     if (nw <= 0) return;
-    k_band<T><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw);
+    item_launch<k_band<T>>(nw, x, d, w, nw);
 }
 
 template <typename T>
-void launch_restrict(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s)
+void launch_restrict(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, (void)NST; k_restrict<T, DIM><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_restrict<T, DIM>>(nw, x, d, w, nw));
 }
 
 template <typename T>
-void launch_prolong(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s)
+void launch_prolong(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, (void)NST; k_prolong<T, DIM><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_prolong<T, DIM>>(nw, x, d, w, nw));
 }
 
 template <typename T>
-void launch_inject(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s)
+void launch_inject(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, (void)NST; k_inject<T, DIM><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw));
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_inject<T, DIM>>(nw, x, d, w, nw));
 }
 
 template <typename T>
-void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs &a, int ncoarse, hipStream_t s)
-{
-    const size_t shm = (size_t)2 * ncoarse * sizeof(double);
-    LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST><<<1, 1024, shm, s>>>(d, a));
-}
-
-void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const StepArgsHost &a,
-                          hipStream_t s)
+void launch_zero_x(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x)
 {
     if (nw <= 0) return;
-    StepArgs A{a.sn, a.cn, a.bs, a.bc, a.fn, a.fnp1, a.sb, a.sb_const};
-    LSMG_DISPATCH_DIM(dim, (void)NST; k_explicit_half<DIM><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, A));
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_zero_x<T, DIM>>(nw, x, d, w, nw));
 }
 
-void launch_residual(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const StepArgsHost &a,
-                     unsigned long long *slot, hipStream_t s)
+template <typename T>
+void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max, const Exec &x)
 {
-    if (nw <= 0) return;
-    StepArgs A{a.sn, a.cn, a.bs, a.bc, a.fn, a.fnp1, a.sb, a.sb_const};
-    LSMG_DISPATCH_DIM(dim, k_residual<DIM, NST><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, A, slot));
+    if (nblocks <= 0) return;
+    const size_t shm = (size_t)2 * ncoarse_max * sizeof(double);
+    LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST><<<nblocks, 1024, shm, x.s>>>(d, args, x.act));
 }
 
-void launch_newton_update(int dim, const LevelDesc<double> *d, const int4 *w, int nw, unsigned long long *ndw,
-                          unsigned long long *nw_slot, hipStream_t s)
+void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, (void)NST; k_newton_update<DIM><<<grid_of(nw), kBlock, 0, s>>>(d, w, nw, ndw, nw_slot));
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_explicit_half<DIM>>(nw, x, d, w, nw));
+}
+
+void launch_residual(int dim, const LevelDesc<double> *d, const int4 *w, int nw, int norm_k, const Exec &x)
+{
+    if (nw <= 0) return;
+    LSMG_DISPATCH_DIM(dim, item_launch<k_residual<DIM, NST>>(nw, x, d, w, nw, norm_k));
+}
+
+void launch_newton_update(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x)
+{
+    if (nw <= 0) return;
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_newton_update<DIM>>(nw, x, d, w, nw));
+}
+
+void launch_commit(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x)
+{
+    if (nw <= 0) return;
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_commit<DIM>>(nw, x, d, w, nw));
 }
 
 void launch_to_f32(int dim, const LevelDesc<double> *d64, const LevelDesc<float> *d32, const int4 *w, int nw,
-                   int what, hipStream_t s)
+                   int what, const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, (void)NST; k_to_f32<DIM><<<grid_of(nw), kBlock, 0, s>>>(d64, d32, w, nw, what));
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_to_f32<DIM>>(nw, x, d64, d32, w, nw, what));
 }
 
 void launch_add_f32(int dim, const LevelDesc<double> *d64, const LevelDesc<float> *d32, const int4 *w, int nw,
-                    hipStream_t s)
+                    const Exec &x)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, (void)NST; k_add_f32<DIM><<<grid_of(nw), kBlock, 0, s>>>(d64, d32, w, nw));
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_add_f32<DIM>>(nw, x, d64, d32, w, nw));
 }
 
 template <typename T>
@@ -1240,6 +1337,19 @@ void launch_fill(T *p, long long n, T v, hipStream_t s)
 
 void launch_zero_u64(unsigned long long *p, int n, hipStream_t s) { k_zero_u64<<<1, 256, 0, s>>>(p, n); }
 
+void launch_norm_reduce(const unsigned long long *base, long long stride, int ndom, int first, int count,
+                        unsigned long long *out, hipStream_t s)
+{
+    if (ndom <= 0) return;
+    k_norm_reduce<<<ndom, kNormSlots, 0, s>>>(base, stride, first, count, out);
+}
+
+void launch_copy_items(const ItemCopy *jobs, int njobs, int4 *dst, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    k_copy_items<<<njobs, 256, 0, s>>>(jobs, dst);
+}
+
 void launch_compact_to_grid(const int64_t *c2g, int na, const double *a, const double *b, const int *c2s,
                             double *gs, double *gc, hipStream_t s)
 {
@@ -1258,10 +1368,11 @@ void launch_grid_to_split(const int64_t *c2g, int na, const double *gs, const do
 // (the kernel's own shared arrays take 12 KiB)
 constexpr size_t kCoarseLdsMax = 147 * 1024;
 
-void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, int N, const int *c2s, double *M,
-                          double *Ainv, int *status, hipStream_t s)
+void launch_coarse_factor(int dim, const LevelDesc<double> *d, const CoarseArgs *args, int nblocks, int n_max,
+                          const Exec &x)
 {
-    const size_t bytes = (size_t)N * N * sizeof(double);
+    if (nblocks <= 0) return;
+    const size_t bytes = (size_t)n_max * n_max * sizeof(double);
     const int use_lds = bytes <= kCoarseLdsMax;
     LSMG_DISPATCH_DIM(dim, {
         static bool attr_set = false;
@@ -1270,7 +1381,7 @@ void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, int N, c
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLdsMax);
             attr_set = true;
         }
-        k_coarse_invert<DIM, NST><<<1, 1024, use_lds ? bytes : 0, s>>>(d, lev, c2s, M, Ainv, use_lds, status);
+        k_coarse_invert<DIM, NST><<<nblocks, 1024, use_lds ? bytes : 0, x.s>>>(d, args, use_lds, x.act);
     });
 }
 
@@ -1281,15 +1392,16 @@ void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, 
 }
 
 #define LSMG_INST(T) \
-    template void launch_smooth_colour<T>(int, const LevelDesc<T> *, const int4 *, int, int, hipStream_t); \
-    template void launch_ghost<T>(int, const LevelDesc<T> *, int, const int4 *, int, int, int, bool, hipStream_t); \
-    template void launch_defect<T>(int, const LevelDesc<T> *, const int4 *, int, unsigned long long *, hipStream_t); \
-    template void launch_apply_J<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
-    template void launch_band<T>(const LevelDesc<T> *, const int4 *, int, hipStream_t); \
-    template void launch_restrict<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
-    template void launch_prolong<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
-    template void launch_inject<T>(int, const LevelDesc<T> *, const int4 *, int, hipStream_t); \
-    template void launch_tail<T>(int, const LevelDesc<T> *, const TailArgs &, int, hipStream_t); \
+    template void launch_smooth_colour<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
+    template void launch_ghost<T>(int, const LevelDesc<T> *, int, const int4 *, int, int, int, bool, const Exec &, const Exec &); \
+    template void launch_defect<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
+    template void launch_apply_J<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
+    template void launch_band<T>(const LevelDesc<T> *, const int4 *, int, const Exec &); \
+    template void launch_restrict<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
+    template void launch_prolong<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
+    template void launch_inject<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
+    template void launch_zero_x<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
+    template void launch_tail<T>(int, const LevelDesc<T> *, const TailArgs *, int, int, const Exec &); \
     template void launch_gather_compact<T>(const int *, int, const T *, const T *, double *, hipStream_t); \
     template void launch_scatter_compact<T>(const int *, int, const double *, T *, T *, hipStream_t); \
     template void launch_fill<T>(T *, long long, T, hipStream_t); \
@@ -1298,5 +1410,6 @@ LSMG_INST(double)
 LSMG_INST(float)
 template void launch_fill<int>(int *, long long, int, hipStream_t);
 template void launch_fill<uint8_t>(uint8_t *, long long, uint8_t, hipStream_t);
+template void launch_fill<unsigned long long>(unsigned long long *, long long, unsigned long long, hipStream_t);
 
 }  // namespace lsmg

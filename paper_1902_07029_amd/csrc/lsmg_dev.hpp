@@ -16,6 +16,9 @@
 //   kind 3: band nodes [z, w) of the level's boundary band.
 // Descriptors of one hierarchy are contiguous by level (finest first), so the
 // next coarser level of descriptor d is d + 1 and the next finer is d - 1.
+// A batch of hierarchies concatenates their descriptor arrays; its work lists
+// carry the rebased descriptor indices, and an optional array of per-descriptor
+// flags lets a launch skip the items of domains that have already converged.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,8 +27,10 @@
 namespace lsmg {
 
 constexpr int kWave = 64;
-constexpr int kItemsPerBlock = 4;          // 256-thread workgroups, one item per wavefront
+constexpr int kItemsPerBlock = 4;          // default: 256-thread workgroups, one item per wavefront
 constexpr int kBlock = kWave * kItemsPerBlock;
+constexpr int kMaxItemsPerBlock = 8;       // workgroup sizes 64 .. 512 (chosen per launch)
+constexpr int kMaxBlock = kWave * kMaxItemsPerBlock;
 constexpr int kMaxBandEntries2 = 8;        // 2^band_steps with band_steps <= 3 (2-D)
 constexpr int kMaxBandEntries3 = 27;       // 3^band_steps (3-D)
 
@@ -68,6 +73,15 @@ struct LevelDesc {
     const int *b_cnt;        // number of ghost sources
     const int *b_src;        // entry j at j * nb + b: storage index of a ghost
     const T *b_wt;           // its weight
+    // max-norm slots of this domain: norm k occupies kNormSlots words at norms + k * norm_stride
+    unsigned long long *norms;
+    long long norm_stride;
+    // level 0 only: data of the Crank-Nicolson step (section 3.1)
+    double *sn, *cn;         // W^n (split layout); W^{n+1} is written back on commit
+    double *bs, *bc;         // explicit half of the step
+    const double *fn, *fnp1; // compact [f1 | f2] source terms at t_n and t_{n+1}, or null
+    const double *sb;        // per-ghost boundary values at t_{n+1}, or null (then sb_const)
+    double sb_const;
 };
 
 __device__ __forceinline__ int item_desc(int4 w) { return w.x >> 2; }
@@ -144,6 +158,13 @@ __device__ __forceinline__ void norm_accumulate(unsigned long long *slot, unsign
     bits = wave_max_u64(bits);
     const int wslot = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kNormSlots - 1);
     if ((threadIdx.x & (kWave - 1)) == 0 && bits != 0ull) atomicMax(slot + wslot, bits);
+}
+
+// norm k of the domain that owns descriptor D
+template <typename T>
+__device__ __forceinline__ void norm_accumulate(const LevelDesc<T> *D, int k, unsigned long long bits)
+{
+    norm_accumulate(D->norms + k * D->norm_stride, bits);
 }
 
 }  // namespace lsmg

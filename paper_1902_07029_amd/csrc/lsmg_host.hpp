@@ -20,52 +20,75 @@ struct TailLevel {
     int nin0, nin1;
 };
 
+// one hierarchy's coarse tail (levels l0 .. nlev-1), its descriptors starting at d0
 struct TailArgs {
-    int l0, nlev, nu1, nu2, ghost_sweeps, pad;
+    int d0, l0, nlev, nu1, nu2, ghost_sweeps;
     const int *c2s;      // coarsest level: compact -> storage
     const double *ainv;  // coarsest level: explicit inverse (FP64, 2Na x 2Na)
     TailLevel lev[kMaxLevels];
 };
 
-struct StepArgsHost {
-    const double *sn, *cn;
-    double *bs, *bc;
-    const double *fn, *fnp1;
-    const double *sb;
-    double sb_const;
+// one hierarchy's coarsest operator: descriptor, compact -> storage map, global
+// scratch (used when the matrix does not fit in LDS), inverse and status word
+struct CoarseArgs {
+    int desc, pad;
+    const int *c2s;
+    double *M, *Ainv;
+    int *status;
+};
+
+// one block of a work-list concatenation
+struct ItemCopy {
+    const int4 *src;
+    int cnt, off, dshift, pad;
+};
+
+// launch configuration of the item kernels: stream, optional per-descriptor
+// active flags, work items (wavefronts) per workgroup, optional timing events
+struct Exec {
+    hipStream_t s = nullptr;
+    const int *act = nullptr;
+    int ipb = kItemsPerBlock;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    Exec(hipStream_t s_ = nullptr) : s(s_) {}
+    Exec(hipStream_t s_, const int *a, int ipb_ = kItemsPerBlock) : s(s_), act(a), ipb(ipb_) {}
 };
 
 // ---- V-cycle and Newton kernels (kernels.hip) ----
-template <typename T> void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int colour, hipStream_t s);
+template <typename T> void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int colour, const Exec &x);
 template <typename T> void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, int ng, int sweeps,
-                                        bool composed, hipStream_t s);
-template <typename T> void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs &a, int ncoarse, hipStream_t s);
-template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, unsigned long long *slot, hipStream_t s);
-template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
-template <typename T> void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
-template <typename T> void launch_restrict(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
-template <typename T> void launch_prolong(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
-template <typename T> void launch_inject(int dim, const LevelDesc<T> *d, const int4 *w, int nw, hipStream_t s);
-void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const StepArgsHost &a, hipStream_t s);
-void launch_residual(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const StepArgsHost &a,
-                     unsigned long long *slot, hipStream_t s);
-void launch_newton_update(int dim, const LevelDesc<double> *d, const int4 *w, int nw, unsigned long long *ndw,
-                          unsigned long long *nw_slot, hipStream_t s);
+                                        bool composed, const Exec &xb, const Exec &xa);
+template <typename T> void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max,
+                                       const Exec &x);
+template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x);
+template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
+template <typename T> void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
+template <typename T> void launch_restrict(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
+template <typename T> void launch_prolong(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
+template <typename T> void launch_inject(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
+template <typename T> void launch_zero_x(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
+void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x);
+void launch_residual(int dim, const LevelDesc<double> *d, const int4 *w, int nw, int norm_k, const Exec &x);
+void launch_newton_update(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x);
+void launch_commit(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x);
 void launch_to_f32(int dim, const LevelDesc<double> *d64, const LevelDesc<float> *d32, const int4 *w, int nw, int what,
-                   hipStream_t s);
+                   const Exec &x);
 void launch_add_f32(int dim, const LevelDesc<double> *d64, const LevelDesc<float> *d32, const int4 *w, int nw,
-                    hipStream_t s);
+                    const Exec &x);
 template <typename T> void launch_gather_compact(const int *c2s, int na, const T *a, const T *b, double *out, hipStream_t s);
 template <typename T> void launch_scatter_compact(const int *c2s, int na, const double *v, T *a, T *b, hipStream_t s);
 template <typename T> void launch_fill(T *p, long long n, T v, hipStream_t s);
 void launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+void launch_norm_reduce(const unsigned long long *base, long long stride, int ndom, int first, int count,
+                        unsigned long long *out, hipStream_t s);
+void launch_copy_items(const ItemCopy *jobs, int njobs, int4 *dst, hipStream_t s);
 void launch_compact_to_grid(const int64_t *c2g, int na, const double *a, const double *b, const int *c2s, double *gs,
                             double *gc, hipStream_t s);
 void launch_grid_to_split(const int64_t *c2g, int na, const double *gs, const double *gc, const int *c2s, double *a,
                           double *b, hipStream_t s);
-// builds the coarsest operator and its inverse (FP64); M: 2N^2 doubles of scratch
-void launch_coarse_factor(int dim, const LevelDesc<double> *d, int lev, int N, const int *c2s, double *M, double *Ainv,
-                          int *status, hipStream_t s);
+// builds the coarsest operators and their inverses (FP64), one workgroup per args entry
+void launch_coarse_factor(int dim, const LevelDesc<double> *d, const CoarseArgs *args, int nblocks, int n_max,
+                          const Exec &x);
 template <typename T> void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *Ainv,
                                                hipStream_t s);
 

@@ -89,6 +89,14 @@ def load():
         "lsmg_vcycle": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d)]),
         "lsmg_profile_start": (_i, [_vp, _i, _i]),
         "lsmg_profile_stop": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+        "lsmg_batch_create": (_i, [ctypes.POINTER(_vp), _i, _vp, ctypes.POINTER(_vp)]),
+        "lsmg_batch_destroy": (None, [_vp]),
+        "lsmg_batch_step": (_i, [_vp, ctypes.POINTER(_vp), _d, ctypes.POINTER(_vp), ctypes.POINTER(_d),
+                                 ctypes.POINTER(_i), ctypes.POINTER(StepStats)]),
+        "lsmg_batch_set_autotune": (_i, [_vp, _i]),
+        "lsmg_batch_tuning": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+        "lsmg_batch_profile_start": (_i, [_vp, _i, _i]),
+        "lsmg_batch_profile_stop": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -302,3 +310,72 @@ class State:
         if check:
             _check(rc, "lsmg_newton_cn_step")
         return rc, st.as_dict()
+
+
+TUNE_CLASSES = ("smooth", "ghost", "defect", "restrict", "prolong", "band")
+
+
+class Batch:
+    """Hierarchies advanced together, one launch per kernel and grid size (lsmg_batch_*).
+
+    The members (Hierarchy objects) must outlive the batch; they are kept
+    referenced here."""
+
+    def __init__(self, hierarchies, stream=None, autotune=True):
+        lib = load()
+        self.members = list(hierarchies)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (_vp * len(self.members))(*[h._h for h in self.members])
+        b = _vp()
+        _check(lib.lsmg_batch_create(arr, len(self.members), ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(b)), "lsmg_batch_create")
+        self._b = b
+        if not autotune:
+            _check(lib.lsmg_batch_set_autotune(b, 0), "lsmg_batch_set_autotune")
+
+    def close(self):
+        if getattr(self, "_b", None):
+            load().lsmg_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, states, dt, sb=None, sb_const=None, check=True):
+        """One Crank-Nicolson step of every member; returns (status list, stats list)."""
+        n = len(self.members)
+        assert len(states) == n
+        st_arr = (_vp * n)(*[st._s for st in states])
+        sb_arr = None
+        if sb is not None:
+            sb_arr = (_vp * n)(*[(t.data_ptr() if t is not None else None) for t in sb])
+        sbc = None
+        if sb_const is not None:
+            sbc = (_d * n)(*sb_const)
+        status = (_i * n)()
+        stats = (StepStats * n)()
+        rc = load().lsmg_batch_step(self._b, st_arr, dt, sb_arr, sbc, status, stats)
+        if check:
+            _check(rc, "lsmg_batch_step")
+        return [status[k] for k in range(n)], [stats[k].as_dict() for k in range(n)]
+
+    def tuning(self):
+        """{grid size: {kernel class: wavefronts per workgroup}}."""
+        cnt = _i()
+        _check(load().lsmg_batch_tuning(self._b, 0, ctypes.byref(cnt), None, None), "lsmg_batch_tuning")
+        m = cnt.value
+        sizes = (_i * max(m, 1))()
+        ipb = (_i * max(6 * m, 1))()
+        _check(load().lsmg_batch_tuning(self._b, m, ctypes.byref(cnt), sizes, ipb), "lsmg_batch_tuning")
+        return {sizes[z]: {c: ipb[6 * z + i] for i, c in enumerate(TUNE_CLASSES)} for z in range(m)}
+
+    def profile_start(self, kernel, n):
+        _check(load().lsmg_batch_profile_start(self._b, kernel, n), "lsmg_batch_profile_start")
+
+    def profile_stop(self):
+        n, ms = _i(), _d()
+        _check(load().lsmg_batch_profile_stop(self._b, ctypes.byref(n), ctypes.byref(ms)), "lsmg_batch_profile_stop")
+        return n.value, ms.value

@@ -1,0 +1,147 @@
+"""Batches of hierarchies (lsmg_batch_*): each member's result after every step
+must be bitwise the result of stepping it alone with lsmg_newton_cn_step (same
+state, same Newton and V-cycle counts), in FP64 and in mixed precision, 2-D and
+3-D; the batch must agree with the oracle to 1e-10 per step; and the autotuner
+must change no result."""
+import numpy as np
+import pytest
+import torch
+
+import lsmg_inputs as I
+import oracle
+from _gpu import cuda, host, oracle_params, rel, say
+from paper_1902_07029_amd import lsmg
+
+# stars of different shapes and grid sizes (levels 257 .. 9 and 129 .. 9 mix)
+STARS2 = [dict(n=129, a=0.45, b=0.1, k=4, p=0.3), dict(n=257, a=0.5, b=0.15, k=5, p=0.0),
+          dict(n=65, a=0.55, b=0.08, k=3, p=1.0), dict(n=129, a=0.38, b=0.18, k=7, p=2.5)]
+# unions of ellipsoids, 3-D
+ELL3 = [dict(n=33, centres=[(0.0, 0.0, 0.0)], semi=[(0.5, 0.35, 0.4)]),
+        dict(n=65, centres=[(-0.2, 0.1, 0.0), (0.25, -0.1, 0.1)], semi=[(0.4, 0.3, 0.3), (0.3, 0.35, 0.25)])]
+
+
+def _phi(dim, d):
+    if dim == 2:
+        return I.star(d["n"], d["a"], d["b"], d["k"], d["p"])
+    return I.ellipsoids(d["n"], np.array(d["centres"]), np.array(d["semi"]))
+
+
+def _hier(dim, d, precision):
+    p = lsmg.default_params(coarsest_n=9, precision=precision)
+    return lsmg.Hierarchy(torch.from_numpy(_phi(dim, d)), dim, d["n"], params=p)
+
+
+def _state(H, d, dim):
+    st = lsmg.State(H)
+    s, c = I.initial_state(d["n"], dim)
+    st.set_grid(cuda(s), cuda(c))
+    return st
+
+
+def _alone_vs_batch(dim, domains, precision, steps, dt=1e-4):
+    alone = [_hier(dim, d, precision) for d in domains]
+    members = [_hier(dim, d, precision) for d in domains]
+    sa = [_state(H, d, dim) for H, d in zip(alone, domains)]
+    sb = [_state(H, d, dim) for H, d in zip(members, domains)]
+    B = lsmg.Batch(members)
+    differ = False
+    for k in range(steps):
+        ref = [st.step(dt)[1] for st in sa]
+        status, stats = B.step(sb, dt)
+        assert all(s == lsmg.OK for s in status)
+        cyc = set()
+        for m in range(len(domains)):
+            ga, gb = sa[m].get(), sb[m].get()
+            assert torch.equal(ga, gb), (k, m, float((ga - gb).abs().max()))
+            assert stats[m]["newton_iters"] == ref[m]["newton_iters"]
+            assert stats[m]["vcycles"] == ref[m]["vcycles"]
+            cyc.add((stats[m]["newton_iters"], stats[m]["vcycles"]))
+        differ |= len(cyc) > 1
+        say(f"dim {dim} prec {precision} step {k}: members bitwise equal to alone; "
+            f"(newton, cycles) per member {[(s['newton_iters'], s['vcycles']) for s in stats]}")
+    return B, differ
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_2d_bitwise_alone(precision):
+    _alone_vs_batch(2, STARS2, precision, 3)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_3d_bitwise_alone(precision):
+    _alone_vs_batch(3, ELL3, precision, 2)
+
+
+@pytest.mark.gpu
+def test_batch_autotune_changes_nothing():
+    members = [_hier(2, d, 1) for d in STARS2]
+    plain = [_hier(2, d, 1) for d in STARS2]
+    s1 = [_state(H, d, 2) for H, d in zip(members, STARS2)]
+    s2 = [_state(H, d, 2) for H, d in zip(plain, STARS2)]
+    B1 = lsmg.Batch(members, autotune=True)
+    B2 = lsmg.Batch(plain, autotune=False)
+    for k in range(2):
+        B1.step(s1, 1e-4)
+        B2.step(s2, 1e-4)
+        for m in range(len(STARS2)):
+            assert torch.equal(s1[m].get(), s2[m].get())
+    tune = B1.tuning()
+    say(f"tuned workgroup sizes: {tune}")
+    assert set(tune) == {257, 129, 65, 33, 17, 9}
+    for z in tune.values():
+        assert all(v in (1, 2, 4, 8) for v in z.values())
+    assert all(v == 4 for z in B2.tuning().values() for v in z.values())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_vs_oracle(precision):
+    domains = [STARS2[2], STARS2[0]]
+    members = [_hier(2, d, precision) for d in domains]
+    states = [_state(H, d, 2) for H, d in zip(members, domains)]
+    B = lsmg.Batch(members)
+    Os, Ws, sbs = [], [], []
+    for H, d in zip(members, domains):
+        O = oracle.Hierarchy(_phi(2, d), 2, d["n"], coarsest_n=9, params=oracle_params(H.params))
+        s, c = I.initial_state(d["n"], 2)
+        Os.append(O)
+        Ws.append(O.to_compact(0, s, c))
+        sbs.append(np.ones(O.level_info(0)["ng"]))
+    for k in range(3):
+        B.step(states, 1e-4)
+        for m, O in enumerate(Os):
+            rc, Ws[m], _ = O.newton_cn_step(Ws[m], 1e-4, sbs[m])
+            assert rc == 0
+            na = O.level_info(0)["na"]
+            G = host(states[m].get())
+            es, ec = rel(G[:na], Ws[m][:na]), rel(G[na:], Ws[m][na:])
+            say(f"batch prec {precision} step {k} member {m}: err s {es:.2e} c {ec:.2e}")
+            assert es <= 1e-10 and ec <= 1e-10
+
+
+@pytest.mark.gpu
+def test_batch_rejects_bad_members():
+    a = _hier(2, STARS2[2], 0)
+    b = _hier(2, STARS2[0], 1)
+    with pytest.raises(lsmg.LsmgError) as e:
+        lsmg.Batch([a, a])
+    assert e.value.code == lsmg.EINVAL
+    with pytest.raises(lsmg.LsmgError) as e:
+        lsmg.Batch([a, b])
+    assert e.value.code == lsmg.EINVAL
+    c = _hier(3, ELL3[0], 0)
+    with pytest.raises(lsmg.LsmgError) as e:
+        lsmg.Batch([a, c])
+    assert e.value.code == lsmg.EINVAL
+
+
+@pytest.mark.gpu
+def test_batch_state_of_other_member_rejected():
+    a, b = _hier(2, STARS2[2], 0), _hier(2, STARS2[0], 0)
+    sa, sb = _state(a, STARS2[2], 2), _state(b, STARS2[0], 2)
+    B = lsmg.Batch([a, b])
+    with pytest.raises(lsmg.LsmgError) as e:
+        B.step([sb, sa], 1e-4)
+    assert e.value.code == lsmg.EINVAL
