@@ -123,7 +123,8 @@ def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label)
 def oracle_params(H):
     eff = H.params
     return {k: getattr(eff, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
-                                         "ghost_c_new", "band_steps", "ghost_sweeps")}
+                                         "ghost_c_new", "band_steps", "ghost_sweeps", "ghost_sweeps_coarse",
+                                         "sweeps_lambda")}
 
 
 # ---------------------------------------------------------------- profiling helpers
@@ -325,7 +326,8 @@ def run_single(args):
             "workload": f"{args.workload}_{'fp64' if prec == 0 else 'mixed'}",
             "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": w["dt"], "coarsest": w["coarsest"],
             "unknowns": unknowns, "inside": ni, "ghost": ng, "levels": H.nlev,
-            "cycle": f"V({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps",
+            "cycle": f"V({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps "
+                     f"({H.params.ghost_sweeps_coarse} where d dt/h^2 < {H.params.sweeps_lambda})",
             "build_ms": round(build_ms, 1),
         },
         "vcycles": cycles,

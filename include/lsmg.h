@@ -66,6 +66,8 @@ typedef struct {
     double tau_s;
     int nu1, nu2;          /* pre- and post-smoothing steps of the V-cycle */
     int ghost_sweeps;      /* ghost relaxations per smoothing step; 0: 5 in 2-D, 15 in 3-D */
+    int ghost_sweeps_coarse; /* the same on levels whose diffusion number d dt / h^2 is below
+                              * sweeps_lambda; 0: 20 in 2-D, ghost_sweeps in 3-D */
     int band_steps;        /* layers of the boundary-defect extension (section 3.5.2) */
     int ghost_c_new;       /* 1: the ghost c-row relaxation uses the new delta s */
     int coarsest_n;        /* nodes per axis of the coarsest grid (>= 3) */
@@ -74,6 +76,7 @@ typedef struct {
     int newton_max;
     double lin_rtol;       /* linear solve stops when |J dW - F|_inf <= lin_rtol |F|_inf */
     int cycles_max;        /* V-cycles per linear solve at most */
+    double sweeps_lambda;  /* threshold of d dt / h^2 for ghost_sweeps_coarse (> 0) */
 } lsmg_params;
 
 typedef struct lsmg_hierarchy lsmg_hierarchy;

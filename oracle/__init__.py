@@ -57,7 +57,7 @@ def _load():
                              ctypes.c_int, ctypes.POINTER(vp)]
     lib.or_free.argtypes = [vp]
     lib.or_free.restype = None
-    lib.or_set_params.argtypes = [vp] + [ctypes.c_double] * 7 + [ctypes.c_int] * 5
+    lib.or_set_params.argtypes = [vp] + [ctypes.c_double] * 7 + [ctypes.c_int] * 6 + [ctypes.c_double]
     lib.or_num_levels.argtypes = [vp]
     lib.or_level_info.argtypes = [vp, ctypes.c_int, _I, _D, _I, _I, _I]
     lib.or_compact_to_grid.argtypes = [vp, ctypes.c_int, _L]
@@ -126,7 +126,7 @@ class Hierarchy:
         self.nlev = lib.or_num_levels(h)
         self.params = dict(a=1e4, d=0.1, m_s=64.06, m_c=100.09, alpha=0.01, beta=0.1,
                            tau_s=0.9, nu1=2, nu2=2, ghost_c_new=1, band_steps=3,
-                           ghost_sweeps=1)
+                           ghost_sweeps=1, ghost_sweeps_coarse=None, sweeps_lambda=0.3)
         if params:
             self.set_params(**params)
 
@@ -141,7 +141,10 @@ class Hierarchy:
         _check(_load().or_set_params(self._h, p["a"], p["d"], p["m_s"], p["m_c"], p["alpha"],
                                      p["beta"], p["tau_s"], int(p["nu1"]), int(p["nu2"]),
                                      int(p["ghost_c_new"]), int(p["band_steps"]),
-                                     int(p["ghost_sweeps"])), "set_params")
+                                     int(p["ghost_sweeps"]),
+                                     int(p["ghost_sweeps"] if p["ghost_sweeps_coarse"] is None
+                                         else p["ghost_sweeps_coarse"]),
+                                     float(p["sweeps_lambda"])), "set_params")
 
     # --- geometry ---------------------------------------------------------
     def level_info(self, l):

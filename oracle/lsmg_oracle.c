@@ -64,6 +64,10 @@ typedef struct {
 typedef struct {
     double a, d, m_s, m_c, alpha, beta, tau_s;
     int nu1, nu2, ghost_c_new, band_steps, ghost_sweeps;
+    /* READING (sweeps per smoothing step): levels whose diffusion number
+     * d dt / h^2 is below sweeps_lambda use ghost_sweeps_coarse */
+    int ghost_sweeps_coarse;
+    double sweeps_lambda;
 } OPar;
 
 typedef struct or_hier {
@@ -305,6 +309,10 @@ static int build_level_geometry(or_hier *H, int l)
         } else {
             order = 0;
         }
+        /* READING: a ghost whose own weight w[0] is negative (theta outside
+         * [0, 1] on an axis, outside the paper's analysis) cannot meet eq.
+         * CFLcond with 0 < tau < 1; its row takes the constant rule */
+        if (w[0] < 0.0) order = 0;
         if (order == 0)
             for (int k = 0; k < nst; ++k) w[k] = (k == 0) ? 1.0 : 0.0;
         L->order[q] = order;
@@ -395,6 +403,7 @@ int or_build(const double *phi, int dim, int n, double lo, double hi, int coarse
     H->p.a = 1e4; H->p.d = 0.1; H->p.m_s = 64.06; H->p.m_c = 100.09;
     H->p.alpha = 0.01; H->p.beta = 0.1; H->p.tau_s = 0.9;
     H->p.nu1 = 2; H->p.nu2 = 2; H->p.ghost_c_new = 1; H->p.band_steps = 3; H->p.ghost_sweeps = 1;
+    H->p.ghost_sweeps_coarse = 1; H->p.sweeps_lambda = 0.3;
     nl = n;
     for (int l = 0; l < nlev; ++l) {
         OLevel *L = &H->L[l];
@@ -446,9 +455,12 @@ void or_free(or_hier *H)
 }
 
 int or_set_params(or_hier *H, double a, double d, double m_s, double m_c, double alpha, double beta,
-                  double tau_s, int nu1, int nu2, int ghost_c_new, int band_steps, int ghost_sweeps)
+                  double tau_s, int nu1, int nu2, int ghost_c_new, int band_steps, int ghost_sweeps,
+                  int ghost_sweeps_coarse, double sweeps_lambda)
 {
     H->p.ghost_sweeps = ghost_sweeps;
+    H->p.ghost_sweeps_coarse = ghost_sweeps_coarse;
+    H->p.sweeps_lambda = sweeps_lambda;
     H->p.a = a; H->p.d = d; H->p.m_s = m_s; H->p.m_c = m_c;
     H->p.alpha = alpha; H->p.beta = beta; H->p.tau_s = tau_s;
     H->p.nu1 = nu1; H->p.nu2 = nu2; H->p.ghost_c_new = ghost_c_new; H->p.band_steps = band_steps;
@@ -757,6 +769,17 @@ int or_lu_solve_dense(double *A, double *b, int n)
 /* multigrid components (§3.5)                                         */
 /* ------------------------------------------------------------------ */
 
+/* number of ghost relaxations per smoothing step on a level (READING; the
+ * paper relaxes the ghosts once): ghost_sweeps, or ghost_sweeps_coarse where
+ * the level's diffusion number d dt / h^2 is below sweeps_lambda.  On such
+ * mass-dominated levels the inside rows hardly couple to the ghosts and the
+ * boundary error is removed by the ghost relaxation alone. */
+static int level_sweeps(const or_hier *H, const OLevel *L)
+{
+    const double lam = H->p.d * H->dt / (L->h * L->h);
+    return lam < H->p.sweeps_lambda ? H->p.ghost_sweeps_coarse : H->p.ghost_sweeps;
+}
+
 /* one smoothing step on level l (§3.5.1): collective Gauss-Seidel on the
  * inside nodes in red-black order (2x2 block solve with P of eq. matrixP),
  * then the ghost relaxation of eq. RelGhost on all ghosts at once. */
@@ -787,7 +810,8 @@ static void smooth_level(or_hier *H, int l)
      * the c-row with the updated (READING) or previous delta s */
     int ng = L->ng, nst = H->nst;
     double *news = dalloc(ng), *olds = dalloc(ng);
-    for (int gs = 0; gs < H->p.ghost_sweeps; ++gs) {
+    const int sweeps = level_sweeps(H, L);
+    for (int gs = 0; gs < sweeps; ++gs) {
     for (int q = 0; q < ng; ++q) {
         long g = L->c2g[L->ni + q];
         double v = 0.0;

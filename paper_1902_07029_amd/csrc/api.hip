@@ -44,7 +44,8 @@ int ipow(int b, int e)
 lsmg_status check_params(const lsmg_params *p)
 {
     if (!p) return fail(LSMG_EINVAL, "params is NULL");
-    if (!(p->tau_s > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->ghost_sweeps < 0 || p->band_steps < 0 ||
+    if (!(p->tau_s > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->ghost_sweeps < 0 || p->ghost_sweeps_coarse < 0 ||
+        !(p->sweeps_lambda > 0.0) || p->band_steps < 0 ||
         p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
         !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1))
         return fail(LSMG_EINVAL, "invalid solver parameters");
@@ -94,11 +95,45 @@ lsmg_status push_desc(lsmg_hierarchy *H)
     return LSMG_OK;
 }
 
+// ghost relaxations per smoothing step on level l: ghost_sweeps, or
+// ghost_sweeps_coarse where the level's diffusion number d dt / h^2 is below
+// sweeps_lambda (mass-dominated levels, where the inside rows hardly couple to
+// the ghosts and the boundary error is removed by the ghost relaxation alone)
+int level_sweeps(const lsmg_hierarchy *H, int l)
+{
+    const double hl = H->L[l].h;
+    if (H->dt > 0.0 && H->p.d * H->dt / (hl * hl) < H->p.sweeps_lambda) return H->p.ghost_sweeps_coarse;
+    return H->p.ghost_sweeps;
+}
+
+lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l);
+void make_descs(lsmg_hierarchy *H);
+lsmg_status upload_tail_args(lsmg_hierarchy *H);
+
+// recomputes every level's sweep count (force: rebuild every composed map)
+lsmg_status update_sweeps(lsmg_hierarchy *H, bool force)
+{
+    bool changed = false;
+    for (int l = 0; l < H->nlev; ++l) {
+        const int S = level_sweeps(H, l);
+        if (!force && S == H->L[l].sweeps) continue;
+        H->L[l].sweeps = S;
+        LSMGCHK(build_ghost_ops(H, l));
+        changed = true;
+    }
+    if (changed) {
+        make_descs(H);
+        LSMGCHK(upload_tail_args(H));
+    }
+    return LSMG_OK;
+}
+
 lsmg_status set_dt(lsmg_hierarchy *H, double dt)
 {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LSMG_EINVAL, "dt must be positive and finite");
     if (dt != H->dt) {
         H->dt = dt;
+        LSMGCHK(update_sweeps(H, false));
         LSMGCHK(push_desc(H));
     }
     return LSMG_OK;
@@ -184,7 +219,7 @@ void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s)
                                 prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
     const Exec xb = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
     const Exec xa = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
-    launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.ng, H->p.ghost_sweeps, Lv.go_ptr != nullptr, xb, xa);
+    launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.ng, Lv.sweeps, Lv.go_ptr != nullptr, xb, xa);
 }
 
 TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
@@ -195,7 +230,6 @@ TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
     a.nlev = H->nlev;
     a.nu1 = H->p.nu1;
     a.nu2 = H->p.nu2;
-    a.ghost_sweeps = H->p.ghost_sweeps;
     a.c2s = H->L[H->nlev - 1].c2s;
     a.ainv = H->ainv;
     for (int l = 0; l < H->nlev; ++l) {
@@ -203,6 +237,7 @@ TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
         a.lev[l].in_ijk = Lv.in_ijk;
         a.lev[l].nin0 = Lv.nin[0];
         a.lev[l].nin1 = Lv.nin[1];
+        a.lev[l].sweeps = Lv.sweeps;
     }
     return a;
 }
@@ -471,7 +506,7 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     Lv.go_ptr = Lv.go_col = nullptr;
     Lv.go_a = Lv.go_b = nullptr;
     Lv.go_a32 = Lv.go_b32 = nullptr;
-    const int ng = Lv.ng, nst = H->nst, S = H->p.ghost_sweeps;
+    const int ng = Lv.ng, nst = H->nst, S = Lv.sweeps;
     if (ng == 0 || !H->p.ghost_c_new) return LSMG_OK;
     std::vector<int> stg((size_t)ng * nst);
     std::vector<double> w((size_t)ng * nst);
@@ -539,6 +574,16 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     LSMGCHK(up((void **)&Lv.go_b, vb.data(), sizeof(double) * nnz));
     LSMGCHK(up((void **)&Lv.go_a32, va32.data(), sizeof(float) * nnz));
     LSMGCHK(up((void **)&Lv.go_b32, vb32.data(), sizeof(float) * nnz));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    return LSMG_OK;
+}
+
+// the coarse-tail arguments of every start level (entry l starts at level l)
+lsmg_status upload_tail_args(lsmg_hierarchy *H)
+{
+    std::vector<TailArgs> ta(H->nlev);
+    for (int l = 0; l < H->nlev; ++l) ta[l] = tail_args(H, l, 0);
+    HIPCHK(hipMemcpyAsync(H->d_tail, ta.data(), sizeof(TailArgs) * H->nlev, hipMemcpyHostToDevice, H->stream));
     HIPCHK(hipStreamSynchronize(H->stream));
     return LSMG_OK;
 }
@@ -656,7 +701,10 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     if (herr & 1) return fail(LSMG_EGEOM, "an inside node lies on the box edge");
     if (herr & 2) return fail(LSMG_EGEOM, "a finest-level ghost's boundary point lies outside its stencil");
     for (int l = 0; l < nlev; ++l) LSMGCHK(build_items(H, l));
-    for (int l = 0; l < nlev; ++l) LSMGCHK(build_ghost_ops(H, l));
+    for (int l = 0; l < nlev; ++l) {
+        H->L[l].sweeps = level_sweeps(H, l);
+        LSMGCHK(build_ghost_ops(H, l));
+    }
     // Newton work arrays, coarsest LU, norms
     const Level &L0 = H->L[0];
     LSMGCHK(H->zalloc(&H->bs, L0.ssize));
@@ -681,8 +729,6 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     LSMGCHK(H->alloc(&H->d_tail, nlev));
     LSMGCHK(H->alloc(&H->d_coarse, 1));
     {
-        std::vector<TailArgs> ta(nlev);
-        for (int l = 0; l < nlev; ++l) ta[l] = tail_args(H, l, 0);
         const Level &Lc = H->L[nlev - 1];
         CoarseArgs ca{};
         ca.desc = nlev - 1;
@@ -690,9 +736,8 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
         ca.M = H->lu;
         ca.Ainv = H->ainv;
         ca.status = H->lu_status;
-        HIPCHK(hipMemcpyAsync(H->d_tail, ta.data(), sizeof(TailArgs) * nlev, hipMemcpyHostToDevice, H->stream));
         HIPCHK(hipMemcpyAsync(H->d_coarse, &ca, sizeof(CoarseArgs), hipMemcpyHostToDevice, H->stream));
-        HIPCHK(hipStreamSynchronize(H->stream));
+        LSMGCHK(upload_tail_args(H));
     }
     make_descs(H);
     LSMGCHK(push_desc(H));
@@ -812,6 +857,8 @@ void lsmg_default_params(lsmg_params *p)
     p->nu1 = 2;
     p->nu2 = 2;
     p->ghost_sweeps = 0;
+    p->ghost_sweeps_coarse = 0;
+    p->sweeps_lambda = 0.3;
     p->band_steps = 3;
     p->ghost_c_new = 1;
     p->coarsest_n = 5;
@@ -837,6 +884,7 @@ lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid
     if (!H) return fail(LSMG_EOOM, "host allocation");
     H->p = *params;
     if (H->p.ghost_sweeps == 0) H->p.ghost_sweeps = grid->dim == 2 ? 5 : 15;
+    if (H->p.ghost_sweeps_coarse == 0) H->p.ghost_sweeps_coarse = grid->dim == 2 ? 20 : H->p.ghost_sweeps;
     H->stream = (hipStream_t)stream;
     // LSMG_GRAPHS=0 replays the V-cycle as direct launches instead of a captured graph
     if (const char *e = std::getenv("LSMG_GRAPHS")) H->use_graphs = std::atoi(e) != 0;
@@ -863,18 +911,20 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
     LSMGCHK(check_params(params));
     if (params->coarsest_n != h->p.coarsest_n || params->band_steps != h->p.band_steps)
         return fail(LSMG_EINVAL, "coarsest_n and band_steps are fixed at build");
-    const int sweeps = params->ghost_sweeps > 0 ? params->ghost_sweeps : (h->dim == 2 ? 5 : 15);
-    const bool ghost_ops_change = sweeps != h->p.ghost_sweeps || params->tau_s != h->p.tau_s ||
-                                  params->ghost_c_new != h->p.ghost_c_new;
+    lsmg_params np = *params;
+    if (np.ghost_sweeps == 0) np.ghost_sweeps = h->dim == 2 ? 5 : 15;
+    if (np.ghost_sweeps_coarse == 0) np.ghost_sweeps_coarse = h->dim == 2 ? 20 : np.ghost_sweeps;
+    const bool ghost_ops_change = np.ghost_sweeps != h->p.ghost_sweeps ||
+                                  np.ghost_sweeps_coarse != h->p.ghost_sweeps_coarse ||
+                                  np.sweeps_lambda != h->p.sweeps_lambda || np.tau_s != h->p.tau_s ||
+                                  np.ghost_c_new != h->p.ghost_c_new;
     invalidate_graphs(h);
-    if (params->precision == 1 && !h->have32) {
+    if (np.precision == 1 && !h->have32) {
         h->p.precision = 1;
         LSMGCHK(build_f32(h));
     }
-    h->p = *params;
-    h->p.ghost_sweeps = sweeps;
-    if (ghost_ops_change)
-        for (int l = 0; l < h->nlev; ++l) LSMGCHK(build_ghost_ops(h, l));
+    h->p = np;
+    LSMGCHK(update_sweeps(h, ghost_ops_change));
     make_descs(h);
     return push_desc(h);
 }

@@ -183,6 +183,10 @@ lsmg_status refresh_descs(lsmg_batch *B, lsmg_state *const *states, const double
             }
         }
     }
+    // coarse tails (their per-level sweep counts follow dt)
+    std::vector<TailArgs> ta(B->ndom);
+    for (int k = 0; k < B->ndom; ++k) ta[k] = tail_args(B->mem[k], B->mem[k]->tail_l0, B->d0[k]);
+    HIPCHK(hipMemcpyAsync(B->d_tail, ta.data(), sizeof(TailArgs) * B->ndom, hipMemcpyHostToDevice, B->stream));
     HIPCHK(hipMemcpyAsync(B->d64, B->hd64.data(), sizeof(LevelDesc<double>) * B->ndesc, hipMemcpyHostToDevice,
                           B->stream));
     if (B->p.precision == 1)
@@ -498,6 +502,7 @@ bool same_params(const lsmg_params &a, const lsmg_params &b)
 {
     return a.a == b.a && a.d == b.d && a.m_s == b.m_s && a.m_c == b.m_c && a.alpha == b.alpha && a.beta == b.beta &&
            a.tau_s == b.tau_s && a.nu1 == b.nu1 && a.nu2 == b.nu2 && a.ghost_sweeps == b.ghost_sweeps &&
+           a.ghost_sweeps_coarse == b.ghost_sweeps_coarse && a.sweeps_lambda == b.sweeps_lambda &&
            a.band_steps == b.band_steps && a.ghost_c_new == b.ghost_c_new && a.coarsest_n == b.coarsest_n &&
            a.precision == b.precision && a.newton_tol == b.newton_tol && a.newton_max == b.newton_max &&
            a.lin_rtol == b.lin_rtol && a.cycles_max == b.cycles_max;

@@ -430,6 +430,9 @@ __global__ void k_ghost_geometry(int level, const double *__restrict__ phi, cons
     } else {
         order = 0;
     }
+    // a negative weight of the ghost itself (theta outside [0, 1] on an axis)
+    // cannot meet eq. CFLcond with 0 < tau < 1: the row takes the constant rule
+    if (w[0] < 0.0) order = 0;
     if (order == 0)
         for (int k = 0; k < NST; ++k) w[k] = k == 0 ? 1.0 : 0.0;
     g_idx[q] = (int)gs;

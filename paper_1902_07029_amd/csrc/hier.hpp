@@ -47,6 +47,7 @@ struct Level {
     float *s32 = nullptr, *c32 = nullptr, *rhs_s32 = nullptr, *rhs_c32 = nullptr, *x_s32 = nullptr, *x_c32 = nullptr,
           *r_s32 = nullptr, *r_c32 = nullptr, *g_w32 = nullptr, *g_buf0_32 = nullptr, *g_buf1_32 = nullptr,
           *b_wt32 = nullptr;
+    int sweeps = 0;                             // ghost relaxations per smoothing step
     int *in_ijk = nullptr;                      // packed coordinates of inside nodes, colour 0 then 1
     int nin[2] = {0, 0};
     int *go_ptr = nullptr, *go_col = nullptr;   // composed ghost relaxation (CSR over ghosts)

@@ -718,7 +718,7 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
     for (int l = A.l0; l < L - 1; ++l) {
         const LevelDesc<T> *D = base + l;
         const TailLevel &TL = A.lev[l];
-        for (int it = 0; it < A.nu1; ++it) wg_smooth<T, DIM, NST>(D, TL, A.ghost_sweeps);
+        for (int it = 0; it < A.nu1; ++it) wg_smooth<T, DIM, NST>(D, TL, TL.sweeps);
         const int nin = TL.nin0 + TL.nin1;
         for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
             if (t < nin) {
@@ -756,7 +756,7 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
             prolong_node<T, DIM>(D, idx, i, j, k);
         }
         __syncthreads();
-        for (int it = 0; it < A.nu2; ++it) wg_smooth<T, DIM, NST>(D, TL, A.ghost_sweeps);
+        for (int it = 0; it < A.nu2; ++it) wg_smooth<T, DIM, NST>(D, TL, TL.sweeps);
     }
 }
 

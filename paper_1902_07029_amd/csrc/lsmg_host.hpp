@@ -18,11 +18,12 @@ constexpr int kMaxLevels = 16;
 struct TailLevel {
     const int *in_ijk;   // packed coordinates of the inside nodes, colour 0 then colour 1
     int nin0, nin1;
+    int sweeps, pad;     // ghost relaxations per smoothing step on this level
 };
 
 // one hierarchy's coarse tail (levels l0 .. nlev-1), its descriptors starting at d0
 struct TailArgs {
-    int d0, l0, nlev, nu1, nu2, ghost_sweeps;
+    int d0, l0, nlev, nu1, nu2, pad;
     const int *c2s;      // coarsest level: compact -> storage
     const double *ainv;  // coarsest level: explicit inverse (FP64, 2Na x 2Na)
     TailLevel lev[kMaxLevels];

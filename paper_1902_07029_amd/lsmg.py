@@ -30,9 +30,11 @@ class Params(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("d", ctypes.c_double), ("m_s", ctypes.c_double),
                 ("m_c", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("tau_s", ctypes.c_double), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
-                ("ghost_sweeps", ctypes.c_int), ("band_steps", ctypes.c_int), ("ghost_c_new", ctypes.c_int),
+                ("ghost_sweeps", ctypes.c_int), ("ghost_sweeps_coarse", ctypes.c_int),
+                ("band_steps", ctypes.c_int), ("ghost_c_new", ctypes.c_int),
                 ("coarsest_n", ctypes.c_int), ("precision", ctypes.c_int), ("newton_tol", ctypes.c_double),
-                ("newton_max", ctypes.c_int), ("lin_rtol", ctypes.c_double), ("cycles_max", ctypes.c_int)]
+                ("newton_max", ctypes.c_int), ("lin_rtol", ctypes.c_double), ("cycles_max", ctypes.c_int),
+                ("sweeps_lambda", ctypes.c_double)]
 
 
 class StepStats(ctypes.Structure):

@@ -4,16 +4,19 @@ ghost stencil indices bit-exact; weights, boundary points and normals to roundin
 import numpy as np
 import pytest
 
+import lsmg_inputs as I
 from _gpu import host, pair, say
 
 CASES = [("disk", 65, 5), ("star", 257, 9), ("star", 1025, 9), ("torus", 65, 9), ("torus", 257, 9)]
 
 
-@pytest.mark.gpu
-@pytest.mark.parametrize("kind,n,coarsest", CASES)
-def test_hierarchy_matches_oracle(kind, n, coarsest):
-    say(f"geometry {kind} n={n}")
-    H, O = pair(kind, n, coarsest)
+# stars of the 64-domain batch (seed 0) whose concave corners give ghosts with a negative
+# biquadratic self-weight (constant rule) and order fallbacks
+BATCH_MEMBERS = [36, 47]
+
+
+def _check(kind, n, coarsest, phi=None):
+    H, O = pair(kind, n, coarsest, phi=phi)
     assert H.nlev == O.nlev
     for l in range(H.nlev):
         gi, oi = H.level_info(l), O.level_info(l)
@@ -30,3 +33,18 @@ def test_hierarchy_matches_oracle(kind, n, coarsest):
         assert np.max(np.abs(G["w"] - R["w"])) <= 1e-14, l
         assert np.max(np.abs(G["B"] - R["B"])) <= 1e-14, l
         assert np.max(np.abs(G["normal"] - R["normal"])) <= 1e-15, l
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind,n,coarsest", CASES)
+def test_hierarchy_matches_oracle(kind, n, coarsest):
+    say(f"geometry {kind} n={n}")
+    _check(kind, n, coarsest)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("member", BATCH_MEMBERS)
+def test_batch_star_hierarchy_matches_oracle(member):
+    d = I.batch_domains(64, 0)[member]
+    say(f"geometry batch member {member} n={d['n']}")
+    _check("star", d["n"], 9, phi=I.star(d["n"], **d["shape"]))

@@ -81,4 +81,6 @@ def test_vcycle(kind, n, coarsest):
         xg, rg = H.vcycle(0, cuda(rhs), xg)
         xo, ro = O.vcycle(0, rhs, xo)
         assert rel(host(xg), xo) <= 1e-10, q
-        assert abs(rg - ro) <= 1e-8 * ro + 1e-14, q
+        # the defect of a nearly converged iterate is a difference of terms of the size of
+        # rhs: its rounding is a few ulps of |rhs|, whatever the size of the defect itself
+        assert abs(rg - ro) <= 1e-8 * ro + 1e-12 * np.max(np.abs(rhs)), q

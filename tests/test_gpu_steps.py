@@ -12,8 +12,8 @@ from paper_1902_07029_amd import lsmg
 TOL = 1e-10
 
 
-def _run(kind, n, coarsest, dt, steps, precision=0, s0=0.0, c0=1.0, **params):
-    H, O = pair(kind, n, coarsest, precision=precision, **params)
+def _run(kind, n, coarsest, dt, steps, precision=0, s0=0.0, c0=1.0, phi=None, **params):
+    H, O = pair(kind, n, coarsest, phi=phi, precision=precision, **params)
     dim = H.dim
     info = O.level_info(0)
     na = info["na"]
@@ -46,6 +46,15 @@ def test_disk_config(precision):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_star_257(precision):
     _run("star", 257, 9, 1e-4, 3, precision)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("member,precision", [(36, 0), (47, 1)])
+def test_batch_star_members(member, precision):
+    # thin-armed 129^2 stars of the 64-domain batch: constant-rule ghosts and the extra
+    # ghost relaxations on mass-dominated levels
+    d = I.batch_domains(64, 0)[member]
+    _run("star", d["n"], 9, 1e-4, 3, precision, phi=I.star(d["n"], **d["shape"]))
 
 
 @pytest.mark.gpu

@@ -180,3 +180,46 @@ def test_coarse_levels_use_order_fallback_only_where_needed(oracle_mod):
     for l in range(4):
         assert counts[l][2] == H.level_info(l)["ng"]
     assert sum(c[0] + c[1] for c in counts) > 0
+
+
+def _lag2(k, t):
+    # 1-D quadratic Lagrange weight of stencil node k at local coordinate t (nodes k = 0, 1, 2 at
+    # t = 1, 0, -1: the ghost, its inner neighbour, the next one)
+    return {0: t * (1 + t) / 2, 1: (1 - t) * (1 + t), 2: t * (t - 1) / 2}[k]
+
+
+def test_negative_ghost_weight_takes_constant_rule(oracle_mod):
+    # Reading of eq. (CFLcond) outside theta in [0, 1]: where the biquadratic weight of the ghost
+    # itself is negative (possible only if theta leaves [0, 1] on an axis), the row takes the
+    # constant rule w = 1 on the ghost; everywhere else the biquadratic weights stand.
+    # The domain is a star of the 64-domain batch (seed 0, member 36) whose concave corners
+    # produce such ghosts on the 129^2 grid.
+    d = I.batch_domains(64, 0)[36]
+    n = d["n"]
+    H = oracle_mod.Hierarchy(I.star(n, **d["shape"]), 2, n, coarsest_n=9)
+    info = H.level_info(0)
+    gt = H.ghost_table(0)
+    c2g = H.compact_to_grid(0)
+    x, y = I.grid_points(n, 2)
+    h = info["h"]
+    flipped = 0
+    for q in range(info["ng"]):
+        g = c2g[info["ni"] + q]
+        m = np.where(gt["normal"][q] >= 0, 1, -1)
+        G = np.array([x[g], y[g]])
+        th = m * (gt["B"][q] - (G - m * h)) / h
+        wq = np.array([_lag2(k % 3, th[0]) * _lag2(k // 3, th[1]) for k in range(9)])
+        if wq[0] < 0:
+            flipped += 1
+            assert gt["order"][q] == 0
+            assert np.array_equal(gt["w"][q], np.eye(9)[0])
+        elif gt["order"][q] == 2:
+            assert np.max(np.abs(gt["w"][q] - wq)) < 1e-13
+    assert flipped == 4
+    for l in range(H.nlev):
+        g2 = H.ghost_table(l)
+        li = H.level_info(l)
+        cg = H.compact_to_grid(l)
+        for q in range(li["ng"]):
+            own = g2["w"][q][g2["st"][q] == li["ni"] + q].sum()
+            assert own >= 0.0 and abs(1 - 0.9 * own) < 1

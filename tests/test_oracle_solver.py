@@ -19,7 +19,7 @@ import scipy.sparse.linalg
 
 import lsmg_inputs as I
 
-SOLVER = dict(ghost_sweeps=5)
+SOLVER = dict(ghost_sweeps=5, ghost_sweeps_coarse=20, sweeps_lambda=0.3)
 
 
 def _hier(oracle_mod, kind, n, coarsest, **params):
@@ -155,7 +155,25 @@ def _rho(oracle_mod, kind, n, coarsest, dt):
 
 def test_multigrid_convergence_factor(oracle_mod):
     r65 = _rho(oracle_mod, "disk", 65, 5, 1e-3)
-    assert r65 < 0.15
+    assert r65 < 0.05
     r257 = _rho(oracle_mod, "star", 257, 9, 1e-4)
     r513 = _rho(oracle_mod, "star", 513, 9, 1e-4)
-    assert r257 < 0.3 and r513 < 0.3
+    assert r257 < 0.1 and r513 < 0.2
+
+
+@pytest.mark.parametrize("member", [36, 47, 14])
+def test_batch_star_domains_converge(oracle_mod, member):
+    # 129^2 stars of the 64-domain batch (seed 0) with thin arms and concave corners: with the
+    # constant rule for negative ghost weights and the extra ghost relaxations on mass-dominated
+    # levels, Newton converges in the same few iterations as on the smooth domains and the
+    # V-cycle factor stays well below 1
+    d = I.batch_domains(64, 0)[member]
+    n = d["n"]
+    H = oracle_mod.Hierarchy(I.star(n, **d["shape"]), 2, n, coarsest_n=9, params=dict(SOLVER))
+    W = _initial(H)
+    sb = np.ones(H.level_info(0)["ng"])
+    for _ in range(2):
+        rc, W, st = H.newton_cn_step(W, 1e-4, sb, rho_cap=200)
+        assert rc == 0
+        assert st["newton_iters"] <= 5
+        assert np.median(st["rho"][1:st["vcycles"]]) < 0.5
