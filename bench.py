@@ -1,12 +1,15 @@
 """Benchmark of the level-set multigrid Crank-Nicolson step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star1025|torus257|disk65|batch64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star1025|torus257|disk65|batch64|serve]
                     [--precision 0|1] [--no-cpu-baseline] [--no-sequential]
+                    [--requests R] [--load X] [--budget-gb G]
 
 Workloads: star1025 (default, FP64), torus257 and disk65 are single domains;
 batch64 is 64 star domains of grid sizes 129^2 .. 1025^2 stepped together in
 mixed precision (one launch per kernel and grid size), reported beside the same
-domains stepped one after another with the plain FP64 path.
+domains stepped one after another with the plain FP64 path; serve is a seeded
+Poisson stream of 3-D simulations continuously batched under a memory budget,
+with p50/p99 step latency, against the same requests run one after another.
 
 Profiling helpers (they print text, not the benchmark line):
     python bench.py --copy-probe MIB          one plain device copy kernel over MIB MiB, 5 times
@@ -87,10 +90,10 @@ def load_traffic(kernel, workload, precision):
     return None
 
 
-def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label):
-    """The oracle (serial, one core) on the first steps of a domain of the workload;
-    its states also give a parity check of the GPU trajectory (gpu_states[k] is the
-    compact GPU state after step k + 1)."""
+def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label, max_steps=200):
+    """The oracle (serial, one core) on the first steps of a domain of the workload,
+    for about budget_s seconds; the steps it shares with gpu_states (gpu_states[k] is
+    the compact GPU state after step k + 1) give a parity check of the GPU trajectory."""
     import oracle
     O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=params)
     info = O.level_info(0)
@@ -102,22 +105,23 @@ def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label)
     worst = 0.0
     steps = 0
     t0 = time.perf_counter()
-    while steps < len(gpu_states):
+    while steps < max_steps:
         rc, W, st = O.newton_cn_step(W, dt, sb)
         if rc != 0:
             raise RuntimeError(f"oracle step failed with {rc}")
         cycles += st["vcycles"]
-        G = gpu_states[steps]
-        for blk in (slice(0, na), slice(na, 2 * na)):
-            worst = max(worst, float(np.max(np.abs(G[blk] - W[blk])) / np.max(np.abs(W[blk]))))
+        if steps < len(gpu_states):
+            G = gpu_states[steps]
+            for blk in (slice(0, na), slice(na, 2 * na)):
+                worst = max(worst, float(np.max(np.abs(G[blk] - W[blk])) / np.max(np.abs(W[blk]))))
         steps += 1
-        if time.perf_counter() - t0 > budget_s:
+        if time.perf_counter() - t0 > budget_s and steps >= len(gpu_states):
             break
     el = time.perf_counter() - t0
     return dict(value=2 * na * cycles / el, unit="unknowns*cycles/s", cores=1, kind="oracle",
                 sample=f"first {steps} Crank-Nicolson steps of {label} ({cycles} V-cycles, {el:.1f} s, "
                        f"serial C, one host core)"), \
-        dict(steps_checked=steps, max_rel_err=worst, domain=label)
+        dict(steps_checked=min(steps, len(gpu_states)), max_rel_err=worst, domain=label)
 
 
 def oracle_params(H):
@@ -373,8 +377,11 @@ def run_batch(args):
         return out
 
     states = fresh_states(Hs)
-    # sample members for the oracle parity check: the two smallest domains
+    # members for the oracle: the two smallest domains (parity) and the first of the
+    # largest grid size (timed CPU baseline, parity on its first steps too)
     sample = sorted(range(len(doms)), key=lambda k: infos[k]["na"])[:2]
+    big = next(k for k, d in enumerate(doms) if d["n"] == max(dd["n"] for dd in doms))
+    sample.append(big)
     traj = {k: [] for k in sample}
     for _ in range(args.warmup):
         B.step(states, dt)
@@ -436,17 +443,18 @@ def run_batch(args):
                    solution_throughput=float(unk.sum()) * nseq / el64)
         del st64, H64
     cpu = parity = None
-    if not args.no_cpu_baseline and sample:
-        k = sample[0]
-        d = doms[k]
-        cpu, parity = cpu_baseline(phis[k], 2, d["n"], d["coarsest"], dt, oracle_params(Hs[k]), args.cpu_budget,
-                                   traj[k], f"batch member {k} (star {d['n']}^2, inside the 64-domain batch)")
-        if len(sample) > 1:
-            k2 = sample[1]
-            d2 = doms[k2]
-            _, par2 = cpu_baseline(phis[k2], 2, d2["n"], d2["coarsest"], dt, oracle_params(Hs[k2]),
-                                   args.cpu_budget, traj[k2], f"batch member {k2} (star {d2['n']}^2)")
-            parity = dict(parity, second=par2)
+    if not args.no_cpu_baseline:
+        d = doms[big]
+        cpu, parity = cpu_baseline(phis[big], 2, d["n"], d["coarsest"], dt, oracle_params(Hs[big]),
+                                   args.cpu_budget, traj[big],
+                                   f"batch member {big} (star {d['n']}^2, stepped inside the 64-domain batch)")
+        parity = dict(parity, small=[])
+        for k in sample[:2]:
+            dk = doms[k]
+            _, pk = cpu_baseline(phis[k], 2, dk["n"], dk["coarsest"], dt, oracle_params(Hs[k]), 0.0, traj[k],
+                                 f"batch member {k} (star {dk['n']}^2)", max_steps=len(traj[k]))
+            parity["small"].append(pk)
+        parity["max_rel_err_all"] = max([parity["max_rel_err"]] + [q["max_rel_err"] for q in parity["small"]])
     lat_ms = np.array(lat) * 1e3
     sizes = {}
     for d in doms:
@@ -480,12 +488,99 @@ def run_batch(args):
     }
 
 
+def run_serve(args):
+    """Serving: a seeded Poisson stream of 3-D simulations on unions of ellipsoids
+    (grids 65^3 .. 257^3, 10-200 steps), continuously batched in mixed precision
+    under a memory budget, against the same requests run one after another with the
+    plain FP64 path."""
+    import torch
+    from paper_1902_07029_amd import lsmg
+    from paper_1902_07029_amd.serve import Request, Server
+
+    prec = args.precision if args.precision is not None else 1
+    base = I.serving_requests(args.requests, rate=1.0, seed=0)
+    phis = [I.ellipsoids(r["n"], r["centres"], r["semi"]) for r in base]
+    # the plain FP64 path, request after request: per-step time and cycles measured on
+    # the first steps of each request, scaled to its number of steps
+    p64 = lsmg.default_params(coarsest_n=9, precision=0)
+    seq_time = 0.0
+    seq_work = 0.0
+    for r, phi in zip(base, phis):
+        H = lsmg.Hierarchy(torch.from_numpy(phi).cuda(), 3, r["n"], params=p64)
+        st = lsmg.State(H)
+        s0, c0 = I.initial_state(r["n"], 3)
+        st.set_grid(torch.from_numpy(s0).cuda(), torch.from_numpy(c0).cuda())
+        st.step(r["dt"])
+        k = max(1, min(r["steps"], args.seq_steps))
+        cyc = 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(k):
+            cyc += st.step(r["dt"])[1]["vcycles"]
+        el = time.perf_counter() - t1
+        seq_time += el / k * r["steps"]
+        seq_work += 2 * H.level_info(0)["na"] * cyc / k * r["steps"]
+        del st, H
+    seq_value = seq_work / seq_time
+    # arrivals at `load` times the request rate the sequential path sustains
+    rate = args.load * len(base) / seq_time
+    stream = I.serving_requests(args.requests, rate=rate, seed=0)
+    reqs = [Request(r["id"], r["arrival"], 3, r["n"], r["steps"], r["dt"], phi) for r, phi in zip(stream, phis)]
+    params = lsmg.default_params(coarsest_n=9, precision=prec)
+    budget = int(args.budget_gb * (1 << 30)) if args.budget_gb else None
+    server = Server(params, budget_bytes=budget)
+    rep = server.run(reqs)
+    sizes = {}
+    for r in base:
+        sizes[str(r["n"])] = sizes.get(str(r["n"]), 0) + 1
+    return {
+        "metric": METRIC,
+        "value": rep["throughput"],
+        "unit": "unknowns*cycles/s",
+        "n_gpus": 1,
+        "steps": sum(r["steps"] for r in base),
+        "warmup": 0,
+        "ms_per_step": rep["makespan_s"] * 1e3 / max(rep["batched_steps"], 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"serve{args.requests}_{'fp64' if prec == 0 else 'mixed'}",
+                   "requests": len(reqs), "grid_sizes": sizes, "arrival_rate_per_s": rate, "load": args.load,
+                   "budget_bytes": server.budget, "dt": 1e-4, "coarsest": 9},
+        "p50_step_ms": rep["p50_step_ms"],
+        "p99_step_ms": rep["p99_step_ms"],
+        "completed": rep["completed"],
+        "makespan_s": rep["makespan_s"],
+        "batched_steps": rep["batched_steps"],
+        "busy_s": rep["busy_s"],
+        "busy_throughput": rep["busy_throughput"],
+        "busy_speedup_vs_fp64_sequential": rep["busy_throughput"] / seq_value,
+        "mean_members": rep["mean_members"],
+        "max_members": rep["max_members"],
+        "mean_queue_wait_s": rep["queue_wait_s"],
+        "solution_throughput": rep["solution_throughput"],
+        "fp64_sequential": dict(value=seq_value, time_s=seq_time, steps_measured_per_request=args.seq_steps),
+        "speedup_vs_fp64_sequential": rep["throughput"] / seq_value,
+        "est_vs_actual_bytes": max(f["bytes"] / f["est_bytes"] for f in rep["finished"] if "bytes" in f),
+        "roofline": None,
+        "cpu_baseline": None,
+        "parity": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS) + ["batch64"])
+    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS) + ["batch64", "serve"])
+    ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
+    ap.add_argument("--load", type=float, default=2.0,
+                    help="serve: arrival rate as a multiple of the sequential FP64 request rate")
+    ap.add_argument("--seq-steps", type=int, default=6, help="serve: steps timed per request on the FP64 path")
+    ap.add_argument("--budget-gb", type=float, default=None, help="serve: memory budget (default 80%% of free)")
     ap.add_argument("--precision", type=int, default=None, choices=(0, 1),
                     help="0 = FP64, 1 = mixed (default: FP64, batch64: mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -509,7 +604,12 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    out = run_batch(args) if args.workload == "batch64" else run_single(args)
+    if args.workload == "batch64":
+        out = run_batch(args)
+    elif args.workload == "serve":
+        out = run_serve(args)
+    else:
+        out = run_single(args)
     print(json.dumps(out))
 
 

@@ -67,7 +67,7 @@ typedef struct {
     int nu1, nu2;          /* pre- and post-smoothing steps of the V-cycle */
     int ghost_sweeps;      /* ghost relaxations per smoothing step; 0: 5 in 2-D, 15 in 3-D */
     int ghost_sweeps_coarse; /* the same on levels whose diffusion number d dt / h^2 is below
-                              * sweeps_lambda; 0: 20 in 2-D, ghost_sweeps in 3-D */
+                              * sweeps_lambda; 0: 20 in 2-D, 30 in 3-D */
     int band_steps;        /* layers of the boundary-defect extension (section 3.5.2) */
     int ghost_c_new;       /* 1: the ghost c-row relaxation uses the new delta s */
     int coarsest_n;        /* nodes per axis of the coarsest grid (>= 3) */
@@ -76,7 +76,7 @@ typedef struct {
     int newton_max;
     double lin_rtol;       /* linear solve stops when |J dW - F|_inf <= lin_rtol |F|_inf */
     int cycles_max;        /* V-cycles per linear solve at most */
-    double sweeps_lambda;  /* threshold of d dt / h^2 for ghost_sweeps_coarse (> 0) */
+    double sweeps_lambda;  /* threshold of d dt / h^2 for ghost_sweeps_coarse; 0: 0.3 in 2-D, 0.1 in 3-D */
 } lsmg_params;
 
 typedef struct lsmg_hierarchy lsmg_hierarchy;
@@ -92,7 +92,7 @@ typedef struct {
 } lsmg_step_stats;
 
 /* Default parameters: the model data of eq. (dataeq), tau_s = 0.9 (section
- * 3.5.1), V(2,2), automatic ghost sweeps (0), 3 band layers, ghost_c_new = 1,
+ * 3.5.1), V(2,2), automatic ghost sweeps (0, 0, 0), 3 band layers, ghost_c_new = 1,
  * coarsest 5, FP64, newton_tol 1e-10, newton_max 20, lin_rtol 1e-3,
  * cycles_max 30. */
 void lsmg_default_params(lsmg_params *p);
@@ -103,14 +103,14 @@ void lsmg_default_params(lsmg_params *p);
  * Per level (phi injected to every coarser grid): node classification
  * (inside / ghost / inactive), the compact ordering, ghost geometry (normal by
  * central differences, eq. nij; upwind stencil ST; boundary point B by
- * bisection; the biquadratic/triquadratic weights of eq. JssD with a lower-
- * order fallback where ST reaches an inactive node) and the tables of the
- * boundary-aware restriction.
+ * bisection; the biquadratic/triquadratic weights of eq. JssD, with a lower-
+ * order fallback where ST reaches an inactive node, and the constant rule
+ * (w = 1 on the ghost) where the ghost's own weight would be negative or B
+ * lies outside the stencil) and the tables of the boundary-aware restriction.
  * stream: a hipStream_t (NULL for the null stream); every later call of this
  *   hierarchy runs on it.
  * Errors: LSMG_EINVAL (bad grid or parameters), LSMG_EGEOM (an inside node on
- *   the box edge, or a finest-level ghost whose boundary point falls outside
- *   its stencil), LSMG_EOOM, LSMG_EHIP.  *out is NULL on error. */
+ *   the box edge), LSMG_EOOM, LSMG_EHIP.  *out is NULL on error. */
 lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid,
                                  const lsmg_params *params, void *stream, lsmg_hierarchy **out);
 void lsmg_destroy_hierarchy(lsmg_hierarchy *h);
@@ -235,6 +235,17 @@ lsmg_status lsmg_profile_start(lsmg_hierarchy *h, int kernel, int level);
 /* Stop timing; host outs: number of timed launches and the sum of their
  * event-to-event durations in milliseconds.  Synchronises the stream. */
 lsmg_status lsmg_profile_stop(lsmg_hierarchy *h, int *launches, double *total_ms);
+
+/* Device memory: the bytes a hierarchy holds now (its levels, tables and
+ * composed ghost maps) and the bytes of one state of it.  Host pointers;
+ * either may be NULL. */
+lsmg_status lsmg_memory_bytes(const lsmg_hierarchy *h, size_t *hierarchy_bytes, size_t *state_bytes);
+
+/* The same before building, from the grid and parameters alone: the storage-
+ * layout arrays of every level exactly, plus an allowance (10 % and 64 MiB)
+ * for the geometry-dependent tables; for admission by memory footprint. */
+lsmg_status lsmg_estimate_bytes(const lsmg_grid *grid, const lsmg_params *params, size_t *hierarchy_bytes,
+                                size_t *state_bytes);
 
 /* ------------------------------------------------------------------------
  * Batches: many hierarchies advanced by one Crank-Nicolson step together

@@ -50,13 +50,20 @@ def torus(n, R=0.5, r=0.2):
     return np.sqrt((np.sqrt(x * x + y * y) - R) ** 2 + z * z) - r
 
 
-def ellipsoids(n, centres, semi):
+def ellipsoids(n, centres, semi, smooth=0.02):
+    """Union of axis-aligned ellipsoids: the minimum of their scaled level sets, taken as
+    a smooth (log-sum-exp) minimum of width `smooth` so that the grooves where two
+    ellipsoids meet are rounded instead of creased; smooth=0 gives the plain minimum."""
     x, y, z = grid_points(n, 3)
-    out = np.full(x.shape, np.inf)
+    qs = []
     for c, s in zip(centres, semi):
         q = np.sqrt(((x - c[0]) / s[0]) ** 2 + ((y - c[1]) / s[1]) ** 2 + ((z - c[2]) / s[2]) ** 2) - 1.0
-        out = np.minimum(out, min(s) * q)
-    return out
+        qs.append(min(s) * q)
+    qs = np.array(qs)
+    m = qs.min(axis=0)
+    if smooth <= 0.0 or len(qs) == 1:
+        return m
+    return m - smooth * np.log(np.exp(-(qs - m) / smooth).sum(axis=0))
 
 
 # ----------------------------------------------------------------------------

@@ -287,7 +287,8 @@ static int build_level_geometry(or_hier *H, int l)
         for (int a = 0; a < dim; ++a) th[a] = m[a] * (Bp[a] - xcoord(H, L, gi[a] - m[a])) / L->h;
         int bad_theta = 0;
         for (int a = 0; a < dim; ++a) if (!(th[a] >= -1.0 && th[a] <= 2.0)) bad_theta = 1;
-        if (bad_theta && l == 0) return OR_EGEOM;
+        /* READING: theta outside [-1, 2] (B found by the first-order projection far from G,
+         * e.g. where the level set has a crease): the constant rule, on every level */
         /* boundary-row weights (eq. JssD) with the order fallback */
         double *w = &L->w[(long)q * nst];
         int order = 2;

@@ -45,7 +45,7 @@ lsmg_status check_params(const lsmg_params *p)
 {
     if (!p) return fail(LSMG_EINVAL, "params is NULL");
     if (!(p->tau_s > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->ghost_sweeps < 0 || p->ghost_sweeps_coarse < 0 ||
-        !(p->sweeps_lambda > 0.0) || p->band_steps < 0 ||
+        !(p->sweeps_lambda >= 0.0) || p->band_steps < 0 ||
         p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
         !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1))
         return fail(LSMG_EINVAL, "invalid solver parameters");
@@ -506,6 +506,7 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     Lv.go_ptr = Lv.go_col = nullptr;
     Lv.go_a = Lv.go_b = nullptr;
     Lv.go_a32 = Lv.go_b32 = nullptr;
+    Lv.go_bytes = 0;
     const int ng = Lv.ng, nst = H->nst, S = Lv.sweeps;
     if (ng == 0 || !H->p.ghost_c_new) return LSMG_OK;
     std::vector<int> stg((size_t)ng * nst);
@@ -565,6 +566,7 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     auto up = [&](void **dst, const void *src, size_t bytes) -> lsmg_status {
         if (hipMalloc(dst, bytes ? bytes : 1) != hipSuccess) return fail(LSMG_EOOM, "ghost operator allocation");
         H->ghost_ops.push_back(*dst);
+        Lv.go_bytes += bytes ? bytes : 1;
         if (bytes) HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, H->stream));
         return LSMG_OK;
     };
@@ -699,7 +701,6 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     cleanup();
     if (st != LSMG_OK) return st;
     if (herr & 1) return fail(LSMG_EGEOM, "an inside node lies on the box edge");
-    if (herr & 2) return fail(LSMG_EGEOM, "a finest-level ghost's boundary point lies outside its stencil");
     for (int l = 0; l < nlev; ++l) LSMGCHK(build_items(H, l));
     for (int l = 0; l < nlev; ++l) {
         H->L[l].sweeps = level_sweeps(H, l);
@@ -858,7 +859,7 @@ void lsmg_default_params(lsmg_params *p)
     p->nu2 = 2;
     p->ghost_sweeps = 0;
     p->ghost_sweeps_coarse = 0;
-    p->sweeps_lambda = 0.3;
+    p->sweeps_lambda = 0.0;
     p->band_steps = 3;
     p->ghost_c_new = 1;
     p->coarsest_n = 5;
@@ -884,7 +885,8 @@ lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid
     if (!H) return fail(LSMG_EOOM, "host allocation");
     H->p = *params;
     if (H->p.ghost_sweeps == 0) H->p.ghost_sweeps = grid->dim == 2 ? 5 : 15;
-    if (H->p.ghost_sweeps_coarse == 0) H->p.ghost_sweeps_coarse = grid->dim == 2 ? 20 : H->p.ghost_sweeps;
+    if (H->p.ghost_sweeps_coarse == 0) H->p.ghost_sweeps_coarse = grid->dim == 2 ? 20 : 30;
+    if (H->p.sweeps_lambda == 0.0) H->p.sweeps_lambda = grid->dim == 2 ? 0.3 : 0.1;
     H->stream = (hipStream_t)stream;
     // LSMG_GRAPHS=0 replays the V-cycle as direct launches instead of a captured graph
     if (const char *e = std::getenv("LSMG_GRAPHS")) H->use_graphs = std::atoi(e) != 0;
@@ -913,7 +915,8 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
         return fail(LSMG_EINVAL, "coarsest_n and band_steps are fixed at build");
     lsmg_params np = *params;
     if (np.ghost_sweeps == 0) np.ghost_sweeps = h->dim == 2 ? 5 : 15;
-    if (np.ghost_sweeps_coarse == 0) np.ghost_sweeps_coarse = h->dim == 2 ? 20 : np.ghost_sweeps;
+    if (np.ghost_sweeps_coarse == 0) np.ghost_sweeps_coarse = h->dim == 2 ? 20 : 30;
+    if (np.sweeps_lambda == 0.0) np.sweeps_lambda = h->dim == 2 ? 0.3 : 0.1;
     const bool ghost_ops_change = np.ghost_sweeps != h->p.ghost_sweeps ||
                                   np.ghost_sweeps_coarse != h->p.ghost_sweeps_coarse ||
                                   np.sweeps_lambda != h->p.sweeps_lambda || np.tau_s != h->p.tau_s ||
@@ -933,6 +936,40 @@ lsmg_status lsmg_get_params(const lsmg_hierarchy *h, lsmg_params *params)
 {
     if (!h || !params) return fail(LSMG_EINVAL, "NULL argument");
     *params = h->p;
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_memory_bytes(const lsmg_hierarchy *h, size_t *hierarchy_bytes, size_t *state_bytes)
+{
+    if (!h) return fail(LSMG_EINVAL, "hierarchy is NULL");
+    size_t b = h->alloc_bytes;
+    for (const Level &Lv : h->L) b += Lv.go_bytes;
+    if (hierarchy_bytes) *hierarchy_bytes = b;
+    if (state_bytes) *state_bytes = 2 * sizeof(double) * (size_t)h->L[0].ssize;
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_estimate_bytes(const lsmg_grid *grid, const lsmg_params *params, size_t *hierarchy_bytes,
+                                size_t *state_bytes)
+{
+    if (!grid || !params) return fail(LSMG_EINVAL, "NULL argument");
+    if (grid->dim != 2 && grid->dim != 3) return fail(LSMG_EINVAL, "dim must be 2 or 3");
+    // the storage-layout arrays of every level (as built), plus 10 % and 64 MiB for the
+    // tables whose size depends on the geometry (ghosts, band, work lists, composed maps)
+    size_t full = 0, ss0 = 0;
+    int nl = grid->n;
+    for (int l = 0; l < 16; ++l) {
+        const long long Wp = ((nl + 1) / 2 + 15) / 16 * 16;
+        const long long rows = grid->dim == 2 ? nl : (long long)nl * nl;
+        const size_t ss = (size_t)(2 * rows * Wp);
+        if (l == 0) ss0 = ss;
+        full += ss * (2 + 4 + 8 * sizeof(double) + (params->precision == 1 ? 8 * sizeof(float) : 0));
+        if (nl <= params->coarsest_n || (nl - 1) % 2) break;
+        nl = (nl - 1) / 2 + 1;
+    }
+    full += 4 * sizeof(double) * ss0;
+    if (hierarchy_bytes) *hierarchy_bytes = full + full / 10 + ((size_t)64 << 20);
+    if (state_bytes) *state_bytes = 2 * sizeof(double) * ss0;
     return LSMG_OK;
 }
 

@@ -399,7 +399,8 @@ __global__ void k_ghost_geometry(int level, const double *__restrict__ phi, cons
     bool bad = false;
     for (int a = 0; a < DIM; ++a)
         if (!(th[a] >= -1.0 && th[a] <= 2.0)) bad = true;
-    if (bad && level == 0) atomicOr(err, 2);
+    // theta outside [-1, 2] (B from the first-order projection far from G, e.g. at a
+    // crease of the level set): the constant rule below, on every level
     double w[NST];
     int order = 2;
     if (!bad) {

@@ -48,6 +48,7 @@ struct Level {
           *r_s32 = nullptr, *r_c32 = nullptr, *g_w32 = nullptr, *g_buf0_32 = nullptr, *g_buf1_32 = nullptr,
           *b_wt32 = nullptr;
     int sweeps = 0;                             // ghost relaxations per smoothing step
+    size_t go_bytes = 0;                        // device bytes of the composed ghost relaxation
     int *in_ijk = nullptr;                      // packed coordinates of inside nodes, colour 0 then 1
     int nin[2] = {0, 0};
     int *go_ptr = nullptr, *go_col = nullptr;   // composed ghost relaxation (CSR over ghosts)
@@ -93,6 +94,7 @@ struct lsmg_hierarchy {
     double step_sb_const = 0.0;
     int *h_status = nullptr;
     std::vector<void *> allocs;
+    size_t alloc_bytes = 0;  // device bytes held through alloc()
     // launch timing of one kernel class on one level (HIP events on the stream)
     int prof_kernel = -1, prof_level = -1;
     std::vector<hipEvent_t> prof_pool;
@@ -126,6 +128,7 @@ struct lsmg_hierarchy {
         if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess)
             return fail(LSMG_EOOM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
         allocs.push_back(p);
+        alloc_bytes += sizeof(T) * (size_t)count;
         *ptr = (T *)p;
         return LSMG_OK;
     }

@@ -91,6 +91,9 @@ def load():
         "lsmg_vcycle": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d)]),
         "lsmg_profile_start": (_i, [_vp, _i, _i]),
         "lsmg_profile_stop": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+        "lsmg_memory_bytes": (_i, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+        "lsmg_estimate_bytes": (_i, [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t)]),
         "lsmg_batch_create": (_i, [ctypes.POINTER(_vp), _i, _vp, ctypes.POINTER(_vp)]),
         "lsmg_batch_destroy": (None, [_vp]),
         "lsmg_batch_step": (_i, [_vp, ctypes.POINTER(_vp), _d, ctypes.POINTER(_vp), ctypes.POINTER(_d),
@@ -137,6 +140,15 @@ def default_params(**overrides):
     return p
 
 
+def estimate_bytes(dim, n, params, lo=-1.0, hi=1.0):
+    """(hierarchy bytes, state bytes) a hierarchy of this grid would hold (before building it)."""
+    hb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    grid = Grid(dim, n, lo, hi)
+    _check(load().lsmg_estimate_bytes(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(hb), ctypes.byref(sb)),
+           "lsmg_estimate_bytes")
+    return hb.value, sb.value
+
+
 class Hierarchy:
     """A domain's grid hierarchy on the current CUDA device and stream."""
 
@@ -173,6 +185,12 @@ class Hierarchy:
             self.close()
         except Exception:
             pass
+
+    def memory_bytes(self):
+        """(hierarchy bytes, bytes of one state) on the device."""
+        hb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().lsmg_memory_bytes(self._h, ctypes.byref(hb), ctypes.byref(sb)), "lsmg_memory_bytes")
+        return hb.value, sb.value
 
     def set_params(self, params):
         _check(load().lsmg_set_params(self._h, ctypes.byref(params)), "lsmg_set_params")

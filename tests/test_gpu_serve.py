@@ -1,0 +1,69 @@
+"""Continuous batching (paper_1902_07029_amd.serve): requests that arrive while
+others run join the batch at step boundaries; each result must be bitwise the
+result of the same simulation run alone with lsmg_newton_cn_step; admission must
+respect the memory budget."""
+import numpy as np
+import pytest
+import torch
+
+import lsmg_inputs as I
+from _gpu import say
+from paper_1902_07029_amd import lsmg
+from paper_1902_07029_amd.serve import Request, Server
+
+
+def _requests(count, seed, sizes=(33, 65), steps=(3, 7), gap=0.02):
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for i in range(count):
+        t += gap * rng.uniform(0.5, 1.5)
+        m = int(rng.integers(1, 3))
+        centres = [tuple(rng.uniform(-0.3, 0.3, 3)) for _ in range(m)]
+        semi = [tuple(rng.uniform(0.25, 0.4, 3)) for _ in range(m)]
+        n = int(rng.choice(sizes))
+        out.append(Request(i, t, 3, n, int(rng.integers(*steps)), 1e-4, I.ellipsoids(n, centres, semi)))
+    return out
+
+
+def _alone(req, params):
+    H = lsmg.Hierarchy(torch.from_numpy(req.phi), req.dim, req.n, params=params)
+    st = lsmg.State(H)
+    nn = req.n ** req.dim
+    st.set_grid(torch.full((nn,), req.s0, dtype=torch.float64, device="cuda"),
+                torch.full((nn,), req.c0, dtype=torch.float64, device="cuda"))
+    for _ in range(req.steps):
+        st.step(req.dt, sb_const=req.sb)
+    return st.get().cpu().numpy()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [1, 0])
+def test_served_results_equal_alone(precision):
+    params = lsmg.default_params(coarsest_n=9, precision=precision)
+    reqs = _requests(6, 3, steps=(8, 15), gap=0.01)
+    rep = Server(params, keep_states=True).run(reqs)
+    assert rep["completed"] == len(reqs), rep["errors"]
+    say(f"served {len(reqs)} requests, {rep['batched_steps']} batched steps, up to {rep['max_members']} "
+        f"members at once, p50 {rep['p50_step_ms']:.2f} ms p99 {rep['p99_step_ms']:.2f} ms")
+    # requests overlapped on the device: some batched step held several members
+    assert rep["max_members"] >= 2
+    by_id = {f["id"]: f for f in rep["finished"]}
+    for r in reqs:
+        f = by_id[r.id]
+        assert f["steps"] == r.steps
+        assert np.array_equal(f["state"], _alone(r, params)), r.id
+
+
+@pytest.mark.gpu
+def test_admission_respects_budget():
+    params = lsmg.default_params(coarsest_n=9, precision=1)
+    reqs = _requests(5, 5, sizes=(65,), steps=(3, 5), gap=0.0)
+    est = sum(lsmg.estimate_bytes(3, 65, params))
+    # room for two simulations at a time
+    rep = Server(params, budget_bytes=int(2.5 * est)).run(reqs)
+    assert rep["completed"] == len(reqs)
+    say(f"budget for 2.5 estimates: up to {rep['max_members']} members at once")
+    assert rep["max_members"] <= 2
+    for f in rep["finished"]:
+        assert f["bytes"] <= f["est_bytes"], (f["bytes"], f["est_bytes"])

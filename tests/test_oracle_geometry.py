@@ -223,3 +223,31 @@ def test_negative_ghost_weight_takes_constant_rule(oracle_mod):
         for q in range(li["ng"]):
             own = g2["w"][q][g2["st"][q] == li["ni"] + q].sum()
             assert own >= 0.0 and abs(1 - 0.9 * own) < 1
+
+
+def test_boundary_point_outside_stencil_takes_constant_rule(oracle_mod):
+    # Reading of the case the paper assumes away (no sign change on PG, B from the projection
+    # along the gradient landing outside the stencil, theta outside [-1, 2]): the constant rule,
+    # on the finest level as on coarse ones.  The domain is request 12 of the seeded serving
+    # stream taken as the plain (creased) union of its ellipsoids, whose crease produces such a
+    # ghost on the 129^3 grid.
+    r = I.serving_requests(24, 1.0, 0)[12]
+    n = r["n"]
+    H = oracle_mod.Hierarchy(I.ellipsoids(n, r["centres"], r["semi"], smooth=0.0), 3, n, coarsest_n=9)
+    info = H.level_info(0)
+    gt = H.ghost_table(0)
+    c2g = H.compact_to_grid(0)
+    x, y, z = I.grid_points(n, 3)
+    h = info["h"]
+    far = 0
+    for q in range(info["ng"]):
+        g = c2g[info["ni"] + q]
+        m = np.where(gt["normal"][q] >= 0, 1, -1)
+        G = np.array([x[g], y[g], z[g]])
+        th = m * (gt["B"][q] - (G - m * h)) / h
+        if np.any(th < -1.0) or np.any(th > 2.0):
+            far += 1
+            assert gt["bfallback"][q] == 1
+            assert gt["order"][q] == 0
+            assert np.array_equal(gt["w"][q], np.eye(27)[0])
+    assert far >= 1
