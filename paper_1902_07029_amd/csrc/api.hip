@@ -317,7 +317,7 @@ lsmg_status linearize(lsmg_hierarchy *H)
             const Level &Lv = H->L[l];
             launch_to_f32(H->dim, H->d64, H->d32, Lv.w_act(), Lv.nw_act(), 0, H->stream);
         }
-    launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->luN, H->stream);
+    launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, H->stream);
     H->lin_set = true;
     return LSMG_OK;
 }
@@ -714,8 +714,13 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     LSMGCHK(H->zalloc(&H->tmp_c, L0.ssize));
     H->luN = 2 * H->L[nlev - 1].na;
     if (H->luN > 1024) return fail(LSMG_EINVAL, "coarsest grid has more than 512 active nodes; use a smaller coarsest_n");
-    LSMGCHK(H->alloc(&H->lu, 2LL * H->luN * H->luN));
-    LSMGCHK(H->alloc(&H->ainv, (long long)H->luN * H->luN));
+    {
+        // coarsest solve storage: Schur-complement scratch (global when it does not fit
+        // in LDS) and [S^{-1} | J^sc | J^cs | J^cc]
+        const long long na_c = H->L[nlev - 1].na;
+        LSMGCHK(H->alloc(&H->lu, na_c * na_c));
+        LSMGCHK(H->alloc(&H->ainv, 2 * na_c * na_c + 2 * na_c));
+    }
     H->tail_l0 = nlev - 1;
     while (H->tail_l0 > 0 && H->L[H->tail_l0 - 1].na <= kTailMaxNodes) --H->tail_l0;
     LSMGCHK(H->alloc(&H->piv, H->luN));
@@ -1270,7 +1275,7 @@ lsmg_status lsmg_coarse_solve(lsmg_hierarchy *h, const double *d_rhs, double *d_
     const int lc = h->nlev - 1;
     const Level &Lc = h->L[lc];
     scatter<double>(h, lc, d_rhs, Lc.rhs_s, Lc.rhs_c);
-    launch_coarse_apply<double>(h->d64, lc, 2 * Lc.na, Lc.c2s, h->ainv, h->stream);
+    launch_coarse_apply<double>(h->d64, lc, Lc.na, Lc.c2s, h->ainv, h->stream);
     gather<double>(h, lc, Lc.x_s, Lc.x_c, d_x);
     return LSMG_OK;
 }

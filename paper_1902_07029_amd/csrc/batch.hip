@@ -543,7 +543,7 @@ lsmg_status b_build(lsmg_batch *B)
         ca[k].M = H->lu;
         ca[k].Ainv = H->ainv;
         ca[k].status = B->d_cstatus + k;
-        B->coarse_n_max = std::max(B->coarse_n_max, H->luN);
+        B->coarse_n_max = std::max(B->coarse_n_max, H->L[H->nlev - 1].na);
     }
     LSMGCHK(B->alloc(&B->d_tail, nk));
     LSMGCHK(B->alloc(&B->d_coarse, nk));

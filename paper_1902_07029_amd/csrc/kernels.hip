@@ -685,23 +685,36 @@ __device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, int sweeps
     __syncthreads();
 }
 
-// x = A^{-1} rhs on the coarsest level with the explicit inverse (FP64)
+// x = A^{-1} rhs on the coarsest level (FP64).  The c-rows couple a node only to
+// itself (J^cs and J^cc are diagonal), so A^{-1} rhs is applied through the
+// Schur complement S = J^ss - J^sc diag(J^cs / J^cc) of the c-block:
+//     t = r_s - J^sc (r_c / J^cc),   x_s = S^{-1} t,   x_c = (r_c - J^cs x_s) / J^cc.
+// Coarse storage (from k_coarse_invert): [S^{-1} | J^sc | J^cs | J^cc], Na x Na,
+// Na x Na, Na, Na doubles.  b: 3 Na doubles of LDS.
 template <typename T>
 __device__ void wg_coarse_apply(const LevelDesc<T> *D, const int *__restrict__ c2s, const double *__restrict__ Ainv,
                                 double *b)
 {
-    const int na = D->na, N = 2 * na;
+    const int na = D->na;
+    const double *Sinv = Ainv, *Jsc = Ainv + (long long)na * na, *cs = Ainv + 2LL * na * na, *cc = cs + na;
+    double *rs = b, *rc = b + na, *t = b + 2 * na;
     for (int r = threadIdx.x; r < na; r += blockDim.x) {
-        b[r] = (double)D->rhs_s[c2s[r]];
-        b[na + r] = (double)D->rhs_c[c2s[r]];
+        rs[r] = (double)D->rhs_s[c2s[r]];
+        rc[r] = (double)D->rhs_c[c2s[r]];
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+    for (int r = threadIdx.x; r < na; r += blockDim.x) {
+        double v = rs[r];
+        for (int q = 0; q < na; ++q) v -= Jsc[(long long)r * na + q] * (rc[q] / cc[q]);
+        t[r] = v;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < na; r += blockDim.x) {
         double v = 0.0;
-        for (int jj = 0; jj < N; ++jj) v += Ainv[(long long)r * N + jj] * b[jj];
-        const long long q = c2s[r < na ? r : r - na];
-        if (r < na) D->x_s[q] = (T)v;
-        else D->x_c[q] = (T)v;
+        for (int q = 0; q < na; ++q) v += Sinv[(long long)r * na + q] * t[q];
+        const long long node = c2s[r];
+        D->x_s[node] = (T)v;
+        D->x_c[node] = (T)((rc[r] - cs[r] * v) / cc[r]);
     }
     __syncthreads();
 }
@@ -1022,11 +1035,13 @@ __global__ void k_copy_items(const ItemCopy *__restrict__ jobs, int4 *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// coarsest level (FP64): the dense 2Na x 2Na operator assembled from the same
-// rows and inverted in place by Gauss-Jordan elimination with partial (row)
-// pivoting, in LDS when it fits, in one workgroup; the row interchanges are
-// undone as column interchanges at the end.  Workgroup b inverts the operator
-// described by args[b].
+// coarsest level (FP64): the operator assembled from the same rows as the
+// smoother's, reduced to the Na x Na Schur complement S = J^ss - J^sc diag(J^cs /
+// J^cc) of its diagonal c-block (the exact solve needs only S^{-1}, J^sc and the
+// c-row diagonals, see wg_coarse_apply), and S inverted in place by Gauss-Jordan
+// elimination with partial (row) pivoting, in LDS when it fits, in one workgroup;
+// the row interchanges are undone as column interchanges at the end.  Workgroup
+// b works on the operator described by args[b].
 // ---------------------------------------------------------------------------
 constexpr int kMaxCoarseN = 1024;
 
@@ -1040,30 +1055,34 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
     const LevelDesc<double> *D = descs + CA.desc;
     const int *__restrict__ c2s = CA.c2s;
     double *__restrict__ Ainv = CA.Ainv;
-    const int na = D->na, ni = D->ni, N = 2 * na;
-    double *M = use_lds ? Mlds : CA.M;      // row-major N x N
+    const int na = D->na, ni = D->ni, N = na;
+    double *M = use_lds ? Mlds : CA.M;      // row-major N x N: the Schur complement S
+    double *Jsc = Ainv + (long long)na * na, *csv = Ainv + 2LL * na * na, *ccv = csv + na;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid >> 6, nwv = nt >> 6;
     __shared__ double fac[kMaxCoarseN];
     __shared__ int piv[kMaxCoarseN];
     __shared__ int s_pr, s_bad;
     for (int r = wv; r < N; r += nwv)
-        for (int c = lane; c < N; c += kWave) M[r * N + c] = 0.0;
+        for (int c = lane; c < N; c += kWave) {
+            M[r * N + c] = 0.0;
+            Jsc[(long long)r * N + c] = 0.0;
+        }
+    // c-row diagonals J^cs, J^cc of every node
+    for (int r = tid; r < na; r += nt) c_row<double>(D, c2s[r], csv[r], ccv[r]);
     if (tid == 0) s_bad = 0;
     __syncthreads();
-    // rows of the Jacobian on the coarsest level (section 3.4)
+    // s-rows of the Jacobian on the coarsest level (section 3.4): J^ss into S, J^sc kept
     for (int r = tid; r < na; r += nt) {
         const long long idx = c2s[r];
-        const long long colour = idx / D->cs;
-        const long long rem = idx - colour * D->cs;
-        const long long row = rem / D->Wp;
-        const int p = (int)(rem - row * D->Wp);
-        int i, j, k;
-        node_coords<DIM>(D->n, (int)colour, row, p, i, j, k);
-        double cs_d, cc_d;
-        c_row<double>(D, idx, cs_d, cc_d);
-        double *Rs = M + r * N, *Rc = M + (na + r) * N;
+        double *Rs = M + r * N, *Rsc = Jsc + (long long)r * N;
         if (r < ni) {
+            const long long colour = idx / D->cs;
+            const long long rem = idx - colour * D->cs;
+            const long long row = rem / D->Wp;
+            const int p = (int)(rem - row * D->Wp);
+            int i, j, k;
+            node_coords<DIM>(D->n, (int)colour, row, p, i, j, k);
             long long nb[2 * DIM];
             neighbours<DIM>(D->n, D->Wp, D->cs, (int)colour, row, i, p, nb);
             const double sr = D->s[idx], cr = D->c[idx];
@@ -1077,10 +1096,10 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
                 sum_sc += a_sc;
                 const int q = D->cmap[nb[e]];
                 Rs[q] += -kap * a_ss;
-                Rs[na + q] += kap * al * a_sc;
+                Rsc[q] += kap * al * a_sc;
             }
             Rs[r] += phr * D->dt_inv + D->ks_half * phr * cr + kap * sum_ss;
-            Rs[na + r] += al * sr * D->dt_inv + D->ks_half * (al * sr * cr + phr * sr) + kap * al * sum_sc;
+            Rsc[r] += al * sr * D->dt_inv + D->ks_half * (al * sr * cr + phr * sr) + kap * al * sum_sc;
         } else {
             const int q = r - ni, ng = D->ng;
             for (int kk = 0; kk < NST; ++kk) {
@@ -1089,9 +1108,11 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
                 Rs[D->cmap[D->g_st[kk * ng + q]]] += wk;
             }
         }
-        Rc[r] += cs_d;
-        Rc[na + r] += cc_d;
     }
+    __syncthreads();
+    // S = J^ss - J^sc diag(J^cs / J^cc)
+    for (int r = wv; r < N; r += nwv)
+        for (int c = lane; c < N; c += kWave) M[r * N + c] -= Jsc[(long long)r * N + c] * (csv[c] / ccv[c]);
     __syncthreads();
     for (int kc = 0; kc < N; ++kc) {
         // pivot: largest |M[i][kc]|, i >= kc, first index on ties (one wavefront)
@@ -1152,7 +1173,7 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
             __syncthreads();
         }
     for (int r = wv; r < N; r += nwv)
-        for (int c = lane; c < N; c += kWave) Ainv[r * N + c] = M[r * N + c];
+        for (int c = lane; c < N; c += kWave) Ainv[(long long)r * N + c] = M[r * N + c];
     if (tid == 0) *CA.status = s_bad ? 1 : 0;
 }
 
@@ -1272,7 +1293,7 @@ template <typename T>
 void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max, const Exec &x)
 {
     if (nblocks <= 0) return;
-    const size_t shm = (size_t)2 * ncoarse_max * sizeof(double);
+    const size_t shm = (size_t)3 * ncoarse_max * sizeof(double);
     LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST><<<nblocks, 1024, shm, x.s>>>(d, args, x.act));
 }
 
@@ -1388,7 +1409,7 @@ void launch_coarse_factor(int dim, const LevelDesc<double> *d, const CoarseArgs 
 template <typename T>
 void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *Ainv, hipStream_t s)
 {
-    k_coarse_apply<T><<<1, 1024, (size_t)N * sizeof(double), s>>>(d, lev, c2s, Ainv);
+    k_coarse_apply<T><<<1, 1024, (size_t)3 * N * sizeof(double), s>>>(d, lev, c2s, Ainv);
 }
 
 #define LSMG_INST(T) \

@@ -87,7 +87,8 @@ void launch_compact_to_grid(const int64_t *c2g, int na, const double *a, const d
                             double *gc, hipStream_t s);
 void launch_grid_to_split(const int64_t *c2g, int na, const double *gs, const double *gc, const int *c2s, double *a,
                           double *b, hipStream_t s);
-// builds the coarsest operators and their inverses (FP64), one workgroup per args entry
+// builds the coarsest operators' Schur complements and their inverses (FP64), one
+// workgroup per args entry; n_max: the largest number of coarsest active nodes
 void launch_coarse_factor(int dim, const LevelDesc<double> *d, const CoarseArgs *args, int nblocks, int n_max,
                           const Exec &x);
 template <typename T> void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *Ainv,
