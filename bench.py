@@ -56,7 +56,8 @@ def smoother_bytes(c2g, ni, ng, n, dim, P):
     """Algorithmic bytes of one colour launch of the collective smoother on a level:
     reads s and c at every active node (2P each), the correction (2P) at active
     nodes of the other colour, the right-hand side (2P) and the type byte at the
-    updated nodes, and writes the correction (2P) at the updated nodes.
+    updated nodes, and writes the correction (2P) at the updated nodes; in 2-D the
+    colour-1 launch also copies each ghost's correction (index 4 + P read, P written).
     Returned for colour 0 and colour 1."""
     g = c2g.astype(np.int64)
     idx = [g % n, (g // n) % n] + ([g // (n * n)] if dim == 3 else [])
@@ -65,7 +66,8 @@ def smoother_bytes(c2g, ni, ng, n, dim, P):
     for c in (0, 1):
         upd = int(np.sum(col[:ni] == c))
         other = int(np.sum(col != c))
-        out.append(2 * P * (ni + ng) + 2 * P * other + (2 * P + 1) * upd + 2 * P * upd)
+        out.append(2 * P * (ni + ng) + 2 * P * other + (2 * P + 1) * upd + 2 * P * upd
+                   + (ng * (4 + 2 * P) if (dim == 2 and c == 1) else 0))
     return out
 
 

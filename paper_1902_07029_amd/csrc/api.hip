@@ -214,12 +214,22 @@ void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s)
 {
     const Level &Lv = H->L[l];
     const LevelDesc<T> *d = descs<T>(H);
+    if (Lv.gc_ptr) {
+        // 2-D: the black launch also snapshots the ghosts' delta s (its list is
+        // followed by the ghost items), then one launch applies the folded map
+        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(0), Lv.nseg[0], 0, prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
+        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(1), Lv.nseg[1] + Lv.nghc, 1,
+                                prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
+        launch_ghost_apply<T>(H->dim, d, Lv.w_gh4(), Lv.nghc4, prof_exec(H, s, LSMG_KERNEL_GHOST, l));
+        return;
+    }
     for (int colour = 0; colour < 2; ++colour)
         launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour,
                                 prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
     const Exec xb = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
     const Exec xa = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
-    launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.ng, Lv.sweeps, Lv.go_ptr != nullptr, xb, xa);
+    launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.w_gh4(), Lv.nghc4, Lv.ng, Lv.sweeps, Lv.go_ptr != nullptr,
+                    xb, xa);
 }
 
 TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
@@ -444,7 +454,9 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
     Lv.nseg[1] = cnt[1];
     Lv.nghc = (Lv.ng + kWave - 1) / kWave;
     Lv.nbandc = (Lv.nb + kWave - 1) / kWave;
-    const int total = cnt[0] + cnt[1] + Lv.nghc + Lv.nbandc;
+    // the composed ghost map's rows are applied 4 rows per wavefront
+    Lv.nghc4 = (Lv.ng + 3) / 4;
+    const int total = cnt[0] + cnt[1] + Lv.nghc + Lv.nbandc + Lv.nghc4;
     LSMGCHK(H->alloc(&Lv.items, total));
     if (cnt[0] + cnt[1] > 0)
         HIPCHK(hipMemcpyAsync(Lv.items, seg[0], sizeof(int4) * (cnt[0] + cnt[1]), hipMemcpyDeviceToDevice, H->stream));
@@ -456,6 +468,10 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
     for (int c = 0; c < Lv.nbandc; ++c) {
         const int e = (c + 1) * kWave < Lv.nb ? (c + 1) * kWave : Lv.nb;
         hv.push_back(make_int4((l << 2) | 3, 0, c * kWave, e));
+    }
+    for (int c = 0; c < Lv.nghc4; ++c) {
+        const int e = (c + 1) * 4 < Lv.ng ? (c + 1) * 4 : Lv.ng;
+        hv.push_back(make_int4((l << 2) | 2, 0, c * 4, e));
     }
     if (!hv.empty())
         HIPCHK(hipMemcpyAsync(Lv.items + cnt[0] + cnt[1], hv.data(), sizeof(int4) * hv.size(), hipMemcpyHostToDevice,
@@ -497,7 +513,7 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
 {
     Level &Lv = H->L[l];
     for (void *p : {(void *)Lv.go_ptr, (void *)Lv.go_col, (void *)Lv.go_a, (void *)Lv.go_b, (void *)Lv.go_a32,
-                    (void *)Lv.go_b32}) {
+                    (void *)Lv.go_b32, (void *)Lv.gc_ptr, (void *)Lv.gc_idx, (void *)Lv.gc_w, (void *)Lv.gc_w32}) {
         if (!p) continue;
         (void)hipFree(p);
         for (auto &q : H->ghost_ops)
@@ -506,6 +522,9 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     Lv.go_ptr = Lv.go_col = nullptr;
     Lv.go_a = Lv.go_b = nullptr;
     Lv.go_a32 = Lv.go_b32 = nullptr;
+    Lv.gc_ptr = Lv.gc_idx = nullptr;
+    Lv.gc_w = nullptr;
+    Lv.gc_w32 = nullptr;
     Lv.go_bytes = 0;
     const int ng = Lv.ng, nst = H->nst, S = Lv.sweeps;
     if (ng == 0 || !H->p.ghost_c_new) return LSMG_OK;
@@ -576,6 +595,45 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     LSMGCHK(up((void **)&Lv.go_b, vb.data(), sizeof(double) * nnz));
     LSMGCHK(up((void **)&Lv.go_a32, va32.data(), sizeof(float) * nnz));
     LSMGCHK(up((void **)&Lv.go_b32, vb32.data(), sizeof(float) * nnz));
+    if (H->dim == 2) {
+        // C = B W_GI: the inside-node part of the b-terms, over storage indices
+        std::vector<int> st((size_t)ng * nst);
+        HIPCHK(hipMemcpyAsync(st.data(), Lv.g_st, sizeof(int) * st.size(), hipMemcpyDeviceToHost, H->stream));
+        HIPCHK(hipStreamSynchronize(H->stream));
+        std::vector<int> cptr(ng + 1, 0), cidx;
+        std::vector<double> cw;
+        std::vector<std::pair<int, double>> rowv;
+        for (int q = 0; q < ng; ++q) {
+            rowv.clear();
+            for (int e = ptr[q]; e < ptr[q + 1]; ++e) {
+                const int c = col[e];
+                const double bq = vb[e];
+                if (bq == 0.0) continue;
+                for (int k = 0; k < nst; ++k) {
+                    const double wk = w[(size_t)k * ng + c];
+                    if (wk == 0.0 || stg[(size_t)k * ng + c] >= 0) continue;
+                    rowv.push_back({st[(size_t)k * ng + c], bq * wk});
+                }
+            }
+            std::sort(rowv.begin(), rowv.end(),
+                      [](const std::pair<int, double> &a, const std::pair<int, double> &b) { return a.first < b.first; });
+            for (size_t i = 0; i < rowv.size(); ++i) {
+                if (i > 0 && rowv[i].first == rowv[i - 1].first) {
+                    cw.back() += rowv[i].second;
+                } else {
+                    cidx.push_back(rowv[i].first);
+                    cw.push_back(rowv[i].second);
+                }
+            }
+            cptr[q + 1] = (int)cidx.size();
+        }
+        const size_t cn = cidx.size();
+        std::vector<float> cw32(cw.begin(), cw.end());
+        LSMGCHK(up((void **)&Lv.gc_ptr, cptr.data(), sizeof(int) * cptr.size()));
+        LSMGCHK(up((void **)&Lv.gc_idx, cidx.data(), sizeof(int) * cn));
+        LSMGCHK(up((void **)&Lv.gc_w, cw.data(), sizeof(double) * cn));
+        LSMGCHK(up((void **)&Lv.gc_w32, cw32.data(), sizeof(float) * cn));
+    }
     HIPCHK(hipStreamSynchronize(H->stream));
     return LSMG_OK;
 }
@@ -606,6 +664,7 @@ void make_descs(lsmg_hierarchy *H)
         D.g_idx = Lv.g_idx; D.g_ijk = Lv.g_ijk; D.g_st = Lv.g_st; D.g_stg = Lv.g_stg; D.g_w = Lv.g_w;
         D.g_buf0 = Lv.g_buf0; D.g_buf1 = Lv.g_buf1;
         D.go_ptr = Lv.go_ptr; D.go_col = Lv.go_col; D.go_a = Lv.go_a; D.go_b = Lv.go_b;
+        D.gc_ptr = Lv.gc_ptr; D.gc_idx = Lv.gc_idx; D.gc_w = Lv.gc_w;
         D.b_idx = Lv.b_idx; D.b_cnt = Lv.b_cnt; D.b_src = Lv.b_src; D.b_wt = Lv.b_wt;
         D.norms = H->d_norms; D.norm_stride = kNormSlots;
         if (l == 0) {
@@ -623,6 +682,7 @@ void make_descs(lsmg_hierarchy *H)
         E.g_idx = D.g_idx; E.g_ijk = D.g_ijk; E.g_st = D.g_st; E.g_stg = D.g_stg; E.g_w = Lv.g_w32;
         E.g_buf0 = Lv.g_buf0_32; E.g_buf1 = Lv.g_buf1_32;
         E.go_ptr = Lv.go_ptr; E.go_col = Lv.go_col; E.go_a = Lv.go_a32; E.go_b = Lv.go_b32;
+        E.gc_ptr = Lv.gc_ptr; E.gc_idx = Lv.gc_idx; E.gc_w = Lv.gc_w32;
         E.b_idx = D.b_idx; E.b_cnt = D.b_cnt; E.b_src = D.b_src; E.b_wt = Lv.b_wt32;
         E.norms = D.norms; E.norm_stride = D.norm_stride;
     }

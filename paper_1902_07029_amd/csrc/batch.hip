@@ -39,6 +39,8 @@ struct BList {
 struct BSize {
     int n = 0;                       // nodes per axis
     BList seg[2], gh, act, band;     // member levels of this size outside the coarse tails
+    BList gh4;                       // their ghosts in items of 4 (the composed map)
+    BList seg1g;                     // 2-D: colour-1 segments, each member's followed by its ghost items
     BList rcoarse;                   // their next coarser levels (restriction targets)
     BList icoarse;                   // next coarser levels of every member level of this size (injection)
     int ipb[kTClasses];
@@ -241,12 +243,23 @@ template <typename T>
 void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s)
 {
     const LevelDesc<T> *d = bdescs<T>(B);
+    if (B->dim == 2) {
+        // folded ghost relaxation: the black launch snapshots the ghosts, one apply launch
+        launch_smooth_colour<T>(B->dim, d, items(B, S.seg[0]), S.seg[0].n, 0,
+                                bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
+        launch_smooth_colour<T>(B->dim, d, items(B, S.seg1g), S.seg1g.n, 1,
+                                bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
+        launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n,
+                              bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n));
+        return;
+    }
     for (int colour = 0; colour < 2; ++colour)
         launch_smooth_colour<T>(B->dim, d, items(B, S.seg[colour]), S.seg[colour].n, colour,
                                 bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
     const Exec xb = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
     const Exec xa = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
-    launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, 0, B->p.ghost_sweeps, true, xb, xa);
+    launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, items(B, S.gh4), S.gh4.n, 0, B->p.ghost_sweeps, true, xb,
+                    xa);
 }
 
 template <typename T>
@@ -344,7 +357,12 @@ void tune_launch(lsmg_batch *B, const BSize &S, int cls, const Exec &x)
         launch_smooth_colour<T>(B->dim, d, items(B, S.seg[0]), S.seg[0].n, 0, x);
         break;
     case kTGhost:
-        launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, 0, B->p.ghost_sweeps, true, x, Exec(x.s, x.act, x.ipb));
+        if (B->dim == 2) {
+            launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, x);
+            break;
+        }
+        launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, items(B, S.gh4), S.gh4.n, 0, B->p.ghost_sweeps, true, x,
+                        Exec(x.s, x.act, x.ipb));
         break;
     case kTDefect:
         launch_defect<T>(B->dim, d, items(B, S.act), S.act.n, -1, x);
@@ -437,7 +455,7 @@ lsmg_status build_lists(lsmg_batch *B)
     const int nk = B->ndom;
     for (size_t z = 0; z < ns.size(); ++z) {
         BSize &S = B->sizes[z];
-        std::vector<Job> seg0, seg1, gh, act, band, rco, ico;
+        std::vector<Job> seg0, seg1, seg1g, gh, gh4, act, band, rco, ico;
         for (int k = 0; k < nk; ++k) {
             const lsmg_hierarchy *H = B->mem[k];
             for (int l = 0; l < H->nlev; ++l) {
@@ -451,7 +469,9 @@ lsmg_status build_lists(lsmg_batch *B)
                 if (l >= H->tail_l0) continue;
                 seg0.push_back({Lv.w_seg(0), Lv.nseg[0], ds});
                 seg1.push_back({Lv.w_seg(1), Lv.nseg[1], ds});
+                seg1g.push_back({Lv.w_seg(1), Lv.nseg[1] + Lv.nghc, ds});
                 gh.push_back({Lv.w_gh(), Lv.nghc, ds});
+                gh4.push_back({Lv.w_gh4(), Lv.nghc4, ds});
                 act.push_back({Lv.w_act(), Lv.nw_act(), ds});
                 band.push_back({Lv.w_band(), Lv.nbandc, ds});
                 const Level &C = H->L[l + 1];
@@ -460,7 +480,9 @@ lsmg_status build_lists(lsmg_batch *B)
         }
         add(S.seg[0], seg0);
         add(S.seg[1], seg1);
+        add(S.seg1g, seg1g);
         add(S.gh, gh);
+        add(S.gh4, gh4);
         add(S.act, act);
         add(S.band, band);
         add(S.rcoarse, rco);

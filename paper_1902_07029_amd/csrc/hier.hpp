@@ -54,13 +54,18 @@ struct Level {
     int *go_ptr = nullptr, *go_col = nullptr;   // composed ghost relaxation (CSR over ghosts)
     double *go_a = nullptr, *go_b = nullptr;
     float *go_a32 = nullptr, *go_b32 = nullptr;
-    int4 *items = nullptr;              // [seg colour 0 | seg colour 1 | ghost chunks | band chunks]
-    int nseg[2] = {0, 0}, nghc = 0, nbandc = 0;
+    int *gc_ptr = nullptr, *gc_idx = nullptr;   // 2-D: the folded b-part (C = B W_GI)
+    double *gc_w = nullptr;
+    float *gc_w32 = nullptr;
+    // [seg colour 0 | seg colour 1 | ghost chunks of 64 | band chunks | ghost chunks of 4 (3-D)]
+    int4 *items = nullptr;
+    int nseg[2] = {0, 0}, nghc = 0, nbandc = 0, nghc4 = 0;
     const int4 *w_seg(int colour) const { return items + (colour ? nseg[0] : 0); }
     const int4 *w_act() const { return items; }
     int nw_act() const { return nseg[0] + nseg[1] + nghc; }
     const int4 *w_gh() const { return items + nseg[0] + nseg[1]; }
     const int4 *w_band() const { return items + nseg[0] + nseg[1] + nghc; }
+    const int4 *w_gh4() const { return items + nseg[0] + nseg[1] + nghc + nbandc; }
 };
 
 }  // namespace lsmg

@@ -183,9 +183,19 @@ __device__ __forceinline__ void ghost_apply_elem(const LevelDesc<T> *D, int q)
     const long long g = D->g_idx[q];
     const int e0 = D->go_ptr[q], e1 = D->go_ptr[q + 1];
     T v = 0;
-    for (int e = e0; e < e1; ++e) {
-        const int c = D->go_col[e];
-        v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
+    if (D->gc_ptr) {
+        // folded b-part: rhs of the ghosts in the row, inside terms through C
+        for (int e = e0; e < e1; ++e) {
+            const int c = D->go_col[e];
+            v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->rhs_s[D->g_idx[c]];
+        }
+        const int f0 = D->gc_ptr[q], f1 = D->gc_ptr[q + 1];
+        for (int f = f0; f < f1; ++f) v -= D->gc_w[f] * D->x_s[D->gc_idx[f]];
+    } else {
+        for (int e = e0; e < e1; ++e) {
+            const int c = D->go_col[e];
+            v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
+        }
     }
     D->x_s[g] = v;
     T cs_d, cc_d;
@@ -479,6 +489,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_smooth_colour(const LevelDesc<T> 
                                                              int colour, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
+    if (item_kind(w) == 2) {
+        // ghost items after the segments: snapshot the ghosts' delta s for the folded
+        // ghost relaxation (ghost values do not change during the colour sweeps)
+        const LevelDesc<T> *D = descs + item_desc(w);
+        const int q = w.z + lane;
+        if (q < w.w) D->g_buf1[q] = D->x_s[D->g_idx[q]];
+        return;
+    }
     smooth_elem<T, DIM>(descs + item_desc(w), w, lane, colour);
 }
 
@@ -526,8 +544,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply(const LevelDesc<T> *_
     if (q < w.w) ghost_apply_elem<T>(descs + item_desc(w), q);
 }
 
-// the same for long composed rows (3-D): 16 lanes share a row, each wavefront
-// walks the 64 ghosts of its item four rows at a time with coalesced reads
+// the same with 16 lanes per row (items of 4 ghosts: one row per 16-lane group),
+// for the long composed rows; in 2-D the rows carry the folded b-part
 template <typename T>
 __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply_grouped(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS,
                                                                    LSMG_ACT)
@@ -540,9 +558,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply_grouped(const LevelDe
         T v = 0;
         if (q < w.w) {
             const int e0 = D->go_ptr[q], e1 = D->go_ptr[q + 1];
-            for (int e = e0 + sub; e < e1; e += 16) {
-                const int c = D->go_col[e];
-                v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
+            if (D->gc_ptr) {
+                for (int e = e0 + sub; e < e1; e += 16) {
+                    const int c = D->go_col[e];
+                    v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->rhs_s[D->g_idx[c]];
+                }
+                const int f0 = D->gc_ptr[q], f1 = D->gc_ptr[q + 1];
+                for (int f = f0 + sub; f < f1; f += 16) v -= D->gc_w[f] * D->x_s[D->gc_idx[f]];
+            } else {
+                for (int e = e0 + sub; e < e1; e += 16) {
+                    const int c = D->go_col[e];
+                    v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
+                }
             }
         }
         for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
@@ -1213,15 +1240,16 @@ void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw,
 }
 
 // the ghost relaxation of one smoothing step: the composed map (two launches,
-// xb and xa), or the sweeps one by one (timed as a whole with xb's events)
+// xb and xa; in 3-D the map is applied over w4, items of 4 ghosts), or the sweeps
+// one by one (timed as a whole with xb's events)
 template <typename T>
-void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, int ng, int sweeps, bool composed,
-                  const Exec &xb, const Exec &xa)
+void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, const int4 *w4, int nw4, int ng,
+                  int sweeps, bool composed, const Exec &xb, const Exec &xa)
 {
     if (nw <= 0) return;
     if (composed) {
         LSMG_DISPATCH_DIM(dim, (void)DIM; item_launch<k_ghost_b<T, NST>>(nw, xb, d, w, nw));
-        if (dim == 3) item_launch<k_ghost_apply_grouped<T>>(nw, xa, d, w, nw);
+        if (dim == 3) item_launch<k_ghost_apply_grouped<T>>(nw4, xa, d, w4, nw4);
         else item_launch<k_ghost_apply<T>>(nw, xa, d, w, nw);
         return;
     }
@@ -1238,6 +1266,15 @@ void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int n
         item_launch<k_ghost_final<T>>(nw, x, d, w, nw, sweeps & 1);
     }
     if (e1) (void)hipEventRecord(e1, x.s);
+}
+
+// the composed ghost map alone, 16 lanes per row over items of 4 ghosts
+template <typename T>
+void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w4, int nw4, const Exec &x)
+{
+    (void)dim;
+    if (nw4 <= 0) return;
+    item_launch<k_ghost_apply_grouped<T>>(nw4, x, d, w4, nw4);
 }
 
 template <typename T>
@@ -1414,8 +1451,10 @@ void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, 
 
 #define LSMG_INST(T) \
     template void launch_smooth_colour<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
-    template void launch_ghost<T>(int, const LevelDesc<T> *, int, const int4 *, int, int, int, bool, const Exec &, const Exec &); \
+    template void launch_ghost<T>(int, const LevelDesc<T> *, int, const int4 *, int, const int4 *, int, int, int, bool, \
+                                  const Exec &, const Exec &); \
     template void launch_defect<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
+    template void launch_ghost_apply<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
     template void launch_apply_J<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
     template void launch_band<T>(const LevelDesc<T> *, const int4 *, int, const Exec &); \
     template void launch_restrict<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \

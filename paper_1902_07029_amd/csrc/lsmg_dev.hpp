@@ -68,6 +68,11 @@ struct LevelDesc {
     // ghost rows' right-hand sides minus their non-ghost stencil terms
     const int *go_ptr, *go_col;
     const T *go_a, *go_b;
+    // 2-D: the b-part folded into the map, b = rhs - W_GI x_I, so that
+    // delta s_q <- sum_e go_a[e] s_old + go_b[e] rhs_s[ghost go_col[e]] - sum_f gc_w[f] x_s[gc_idx[f]],
+    // with C = B W_GI composed over inside storage indices (null in 3-D)
+    const int *gc_ptr, *gc_idx;
+    const T *gc_w;
     // band of inactive nodes used by the boundary-defect restriction
     const int *b_idx;        // storage index of band node b
     const int *b_cnt;        // number of ghost sources

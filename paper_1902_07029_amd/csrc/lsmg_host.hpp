@@ -57,10 +57,11 @@ struct Exec {
 
 // ---- V-cycle and Newton kernels (kernels.hip) ----
 template <typename T> void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int colour, const Exec &x);
-template <typename T> void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, int ng, int sweeps,
-                                        bool composed, const Exec &xb, const Exec &xa);
+template <typename T> void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, const int4 *w4,
+                                        int nw4, int ng, int sweeps, bool composed, const Exec &xb, const Exec &xa);
 template <typename T> void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max,
                                        const Exec &x);
+template <typename T> void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x);
 template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
