@@ -183,19 +183,10 @@ __device__ __forceinline__ void ghost_apply_elem(const LevelDesc<T> *D, int q)
     const long long g = D->g_idx[q];
     const int e0 = D->go_ptr[q], e1 = D->go_ptr[q + 1];
     T v = 0;
-    if (D->gc_ptr) {
-        // folded b-part: rhs of the ghosts in the row, inside terms through C
-        for (int e = e0; e < e1; ++e) {
-            const int c = D->go_col[e];
-            v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->rhs_s[D->g_idx[c]];
-        }
-        const int f0 = D->gc_ptr[q], f1 = D->gc_ptr[q + 1];
-        for (int f = f0; f < f1; ++f) v -= D->gc_w[f] * D->x_s[D->gc_idx[f]];
-    } else {
-        for (int e = e0; e < e1; ++e) {
-            const int c = D->go_col[e];
-            v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
-        }
+    // b-values from ghost_b_elem (the folded rows serve the 16-lane kernel only)
+    for (int e = e0; e < e1; ++e) {
+        const int c = D->go_col[e];
+        v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
     }
     D->x_s[g] = v;
     T cs_d, cc_d;
