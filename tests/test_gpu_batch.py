@@ -145,3 +145,39 @@ def test_batch_state_of_other_member_rejected():
     with pytest.raises(lsmg.LsmgError) as e:
         B.step([sb, sa], 1e-4)
     assert e.value.code == lsmg.EINVAL
+
+
+@pytest.mark.gpu
+def test_full_64_domain_batch_members_equal_alone():
+    # the 64-star batch of the benchmark (seed 0, mixed precision, grids 129^2 .. 1025^2) in the
+    # launch shapes the benchmark times (autotuned); sampled members of every grid size are
+    # checked bitwise against the same domain stepped alone
+    doms = I.batch_domains(64, 0)
+    params = lambda d: lsmg.default_params(coarsest_n=d["coarsest"], precision=d["precision"])
+    Hs = [lsmg.Hierarchy(torch.from_numpy(I.star(d["n"], **d["shape"])), 2, d["n"], params=params(d)) for d in doms]
+    states = []
+    for H, d in zip(Hs, doms):
+        st = lsmg.State(H)
+        s, c = I.initial_state(d["n"], 2)
+        st.set_grid(cuda(s), cuda(c))
+        states.append(st)
+    B = lsmg.Batch(Hs)
+    sample = []
+    for n in (129, 257, 513, 1025):
+        sample += [k for k, d in enumerate(doms) if d["n"] == n][:2]
+    alone = {}
+    for k in sample:
+        d = doms[k]
+        H = lsmg.Hierarchy(torch.from_numpy(I.star(d["n"], **d["shape"])), 2, d["n"], params=params(d))
+        st = lsmg.State(H)
+        s, c = I.initial_state(d["n"], 2)
+        st.set_grid(cuda(s), cuda(c))
+        alone[k] = (H, st)
+    for step in range(2):
+        status, stats = B.step(states, doms[0]["dt"])
+        assert all(s == lsmg.OK for s in status)
+        for k in sample:
+            _, ref = alone[k][1].step(doms[k]["dt"])
+            assert torch.equal(states[k].get(), alone[k][1].get()), (step, k)
+            assert stats[k]["vcycles"] == ref["vcycles"]
+        say(f"64-domain batch step {step}: {len(sample)} sampled members bitwise equal to alone")
