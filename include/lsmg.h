@@ -115,6 +115,12 @@ lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid
                                  const lsmg_params *params, void *stream, lsmg_hierarchy **out);
 void lsmg_destroy_hierarchy(lsmg_hierarchy *h);
 
+/* Set the time step ahead of the first step: the level descriptors and the
+ * per-level ghost relaxation maps (whose sweep counts depend on d dt / h^2)
+ * are prepared for dt.  Every stepping call does this itself when dt
+ * changes.  Synchronises the hierarchy's stream.  Errors: EINVAL. */
+lsmg_status lsmg_set_dt(lsmg_hierarchy *h, double dt);
+
 /* Replace the solver parameters (the model constants and the grid are fixed at build). */
 lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params);
 
@@ -282,6 +288,30 @@ void lsmg_batch_destroy(lsmg_batch *b);
  * (lsmg_batch_set_autotune), which changes no result. */
 lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt, const double *const *d_sb,
                             const double *sb_const, lsmg_status *status, lsmg_step_stats *stats);
+
+/* Continuous batching at V-cycle granularity.  Every member runs its own
+ * Crank-Nicolson steps with the stopping rules of lsmg_newton_cn_step, and
+ * each tick of the batch issues, for every member, the next piece of its step:
+ * the explicit half and residual of a new step with its first linearisation,
+ * one V-cycle (or FP64 refinement step), a Newton update and residual, or the
+ * linearisation of a new Newton iteration (with its first cycle).  Members in
+ * different phases share every launch of a tick; a member's results are
+ * bitwise those of lsmg_newton_cn_step alone.
+ * remaining[k] (host): 0 or the number of steps member k still has to do;
+ *   a member starts a new step only when remaining[k] > 0, and a step in
+ *   progress always continues.  The progress of a step lives with the
+ *   hierarchy, so a member can move to a new batch between calls.
+ * Runs ticks until some member ends a step (converged or failed) or
+ * max_ticks ticks have run, then returns.  Per member (host arrays, each
+ * optional): ended[k] = 1 if its step ended in this call, status[k] its
+ * outcome (a failed step keeps W^n and the member starts no further step
+ * until called with remaining[k] > 0 again), stats[k] that step's statistics,
+ * step_ms[k] its wall time from the tick that started it to the tick that
+ * ended it.  *ticks_run: ticks run.  Boundary values sb_const[k] (NULL: 1.0).
+ * Synchronises the batch stream. */
+lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double dt, const double *sb_const,
+                               const int *remaining, int max_ticks, int *ended, lsmg_status *status,
+                               lsmg_step_stats *stats, double *step_ms, int *ticks_run);
 
 /* Autotuning of the batch's launch shapes (enable != 0, the default): on the
  * first step, for every grid size and kernel class (smoother, ghost

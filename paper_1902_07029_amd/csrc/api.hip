@@ -997,6 +997,12 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
     return push_desc(h);
 }
 
+lsmg_status lsmg_set_dt(lsmg_hierarchy *h, double dt)
+{
+    if (!h) return fail(LSMG_EINVAL, "hierarchy is NULL");
+    return set_dt(h, dt);
+}
+
 lsmg_status lsmg_get_params(const lsmg_hierarchy *h, lsmg_params *params)
 {
     if (!h || !params) return fail(LSMG_EINVAL, "NULL argument");

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -31,6 +32,8 @@ namespace {
 
 // kernel classes the autotuner picks a workgroup size for
 enum { kTSmooth = 0, kTGhost = 1, kTDefect = 2, kTRestrict = 3, kTProlong = 4, kTBand = 5, kTClasses = 6 };
+// rows of per-descriptor flags (see b_build)
+enum { kFCycle = 0, kFStart = 1, kFLin = 2, kFUpdate = 3, kFCommit = 4, kFlagRows = 5 };
 
 struct BList {
     int off = 0, n = 0;   // range in the batch's item pool
@@ -212,6 +215,28 @@ lsmg_status set_flags(lsmg_batch *B, const std::vector<char> &on)
     HIPCHK(hipMemcpyAsync(B->d_act, B->h_act, sizeof(int) * B->ndesc, hipMemcpyHostToDevice, B->stream));
     B->act_last = v;
     return LSMG_OK;
+}
+
+// all flag rows at once (member flags per row); the stream is synchronised
+// before the pinned staging buffer is rewritten
+lsmg_status set_flag_rows(lsmg_batch *B, const std::vector<std::vector<char>> &rows)
+{
+    const int nd = B->ndesc;
+    std::vector<int> v((size_t)kFlagRows * nd, 0);
+    for (int r = 0; r < kFlagRows && r < (int)rows.size(); ++r)
+        for (int k = 0; k < B->ndom; ++k)
+            for (int l = 0; l < B->mem[k]->nlev; ++l) v[(size_t)r * nd + B->d0[k] + l] = rows[r][k] ? 1 : 0;
+    HIPCHK(hipStreamSynchronize(B->stream));
+    std::memcpy(B->h_act, v.data(), sizeof(int) * v.size());
+    HIPCHK(hipMemcpyAsync(B->d_act, B->h_act, sizeof(int) * v.size(), hipMemcpyHostToDevice, B->stream));
+    B->act_last.assign(v.begin(), v.begin() + nd);
+    return LSMG_OK;
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
 void zero_bnorms(lsmg_batch *B, int first, int count, hipStream_t s)
@@ -547,10 +572,12 @@ lsmg_status b_build(lsmg_batch *B)
     B->norm_stride = (long long)nk * kNormSlots;
     LSMGCHK(B->alloc(&B->d_norms, 4 * B->norm_stride));
     LSMGCHK(B->alloc(&B->d_nred, 4LL * nk));
-    LSMGCHK(B->alloc(&B->d_act, nd));
+    // flag rows: 0 the cycle (and every launch of lsmg_batch_step), 1 step starts,
+    // 2 linearisations, 3 Newton updates, 4 commits (lsmg_batch_advance)
+    LSMGCHK(B->alloc(&B->d_act, (long long)kFlagRows * nd));
     LSMGCHK(B->alloc(&B->d_cstatus, nk));
     HIPCHK(hipHostMalloc(&B->h_nred, sizeof(unsigned long long) * 4 * nk, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc(&B->h_act, sizeof(int) * nd, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&B->h_act, sizeof(int) * kFlagRows * nd, hipHostMallocDefault));
     HIPCHK(hipHostMalloc(&B->h_cstatus, sizeof(int) * nk, hipHostMallocDefault));
     // coarse tails and coarsest operators, one workgroup per member
     std::vector<TailArgs> ta(nk);
@@ -807,6 +834,198 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
             }
     }
     return first_bad;
+}
+
+lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double dt, const double *sb_const,
+                               const int *remaining, int max_ticks, int *ended, lsmg_status *status,
+                               lsmg_step_stats *stats, double *step_ms, int *ticks_run)
+{
+    if (!b || !states || !remaining) return fail(LSMG_EINVAL, "NULL argument");
+    lsmg_batch *B = b;
+    const int nk = B->ndom;
+    for (int k = 0; k < nk; ++k)
+        if (!states[k] || states[k]->h != B->mem[k]) return fail(LSMG_EINVAL, "state %d does not belong to member %d", k, k);
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LSMG_EINVAL, "dt must be positive and finite");
+    bool changed = dt != B->dt;
+    B->dt = dt;
+    for (int k = 0; k < nk; ++k)
+        if (B->mem[k]->dt != dt) {
+            LSMGCHK(set_dt(B->mem[k], dt));
+            changed = true;
+        }
+    std::vector<const lsmg_state *> sv(states, states + nk);
+    std::vector<const double *> sbv(nk, nullptr);
+    std::vector<double> sbc(nk, 1.0);
+    for (int k = 0; k < nk; ++k)
+        if (sb_const) sbc[k] = sb_const[k];
+    if (changed || sv != B->last_states || sbv != B->last_sb || sbc != B->last_sbc) {
+        LSMGCHK(refresh_descs(B, states, sbv.data(), sbc.data()));
+        B->last_states = sv;
+        B->last_sb = sbv;
+        B->last_sbc = sbc;
+    }
+    const bool mixed = B->p.precision == 1;
+    hipStream_t s = B->stream;
+    const int nd = B->ndesc;
+    const Exec xs(s, B->d_act + (size_t)kFStart * nd), xl(s, B->d_act + (size_t)kFLin * nd),
+        xu(s, B->d_act + (size_t)kFUpdate * nd), xm(s, B->d_act + (size_t)kFCommit * nd);
+    for (int k = 0; k < nk; ++k) {
+        if (ended) ended[k] = 0;
+        if (status) status[k] = LSMG_OK;
+        RunState &R = B->mem[k]->run;
+        if (R.next == RunState::Idle && remaining[k] > 0) R.next = RunState::Start;
+    }
+    int ticks = 0;
+    bool any_end = false;
+    while (ticks < max_ticks && !any_end) {
+        std::vector<std::vector<char>> rows(kFlagRows, std::vector<char>(nk, 0));
+        std::vector<char> &fc = rows[kFCycle], &fs = rows[kFStart], &fl = rows[kFLin], &fu = rows[kFUpdate];
+        int nwork = 0;
+        for (int k = 0; k < nk; ++k) {
+            RunState &R = B->mem[k]->run;
+            switch (R.next) {
+            case RunState::Start:
+                fs[k] = fl[k] = 1;
+                break;
+            case RunState::Lin:
+                fl[k] = 1;
+                // the first cycle of the new linear solve runs unless |F| = 0
+                if (!(R.nF <= B->p.lin_rtol * R.nF)) fc[k] = 1;
+                break;
+            case RunState::Solve:
+                if (!R.force_update && R.q < B->p.cycles_max && !(R.rprev <= B->p.lin_rtol * R.nF)) fc[k] = 1;
+                else fu[k] = 1;
+                break;
+            default:
+                break;
+            }
+            nwork += fs[k] | fl[k] | fc[k] | fu[k];
+        }
+        if (nwork == 0) break;
+        LSMGCHK(set_flag_rows(B, rows));
+        const double t_tick = now_ms();
+        for (int k = 0; k < nk; ++k)
+            if (fs[k]) B->mem[k]->run.t_start = t_tick;
+        zero_bnorms(B, 0, 4, s);
+        bool has_s = false, has_l = false, has_c = false, has_u = false;
+        for (int k = 0; k < nk; ++k) {
+            has_s |= fs[k];
+            has_l |= fl[k];
+            has_c |= fc[k];
+            has_u |= fu[k];
+        }
+        if (has_s) {
+            launch_explicit_half(B->dim, B->d64, items(B, B->lev0), B->lev0.n, xs);
+            launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, xs);
+        }
+        if (has_l) {
+            for (const BSize &S : B->sizes) launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, xl);
+            if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, xl);
+            launch_coarse_factor(B->dim, B->d64, B->d_coarse, nk, B->coarse_n_max, xl);
+            if (B->autotune && !B->tuned) {
+                // workgroup sizes, timed on the members being linearised (flag row 0 set to
+                // them for the tuner's launches): their scratch arrays are reset below and
+                // by their first cycle, and no other member's arrays are touched
+                std::vector<std::vector<char>> trow = rows;
+                trow[kFCycle] = fl;
+                LSMGCHK(set_flag_rows(B, trow));
+                if (mixed) LSMGCHK(b_autotune<float>(B, 3));
+                else LSMGCHK(b_autotune<double>(B, 3));
+                LSMGCHK(set_flag_rows(B, rows));
+            }
+            launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, xl);
+            if (mixed) launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, xl);
+        }
+        if (has_c) {
+            hipGraphExec_t ge = nullptr;
+            if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &ge));
+            if (ge) HIPCHK(hipGraphLaunch(ge, s));
+            else b_cycle_enqueue(B, mixed, s);
+        }
+        if (has_u) {
+            launch_newton_update(B->dim, B->d64, items(B, B->lev0), B->lev0.n, xu);
+            launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, xu);
+        }
+        launch_norm_reduce(B->d_norms, B->norm_stride, nk, 0, 4, B->d_nred, s);
+        HIPCHK(hipMemcpyAsync(B->h_nred, B->d_nred, sizeof(unsigned long long) * 4 * nk, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(B->h_cstatus, B->d_cstatus, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (B->prof_kernel >= 0) b_prof_collect(B);
+        ++ticks;
+        const double t_end = now_ms();
+        std::vector<char> commit(nk, 0);
+        for (int k = 0; k < nk; ++k) {
+            RunState &R = B->mem[k]->run;
+            lsmg_status rc = LSMG_OK;
+            bool done = false;
+            if (fs[k]) {
+                R.nF = bnorm(B, k, 0);
+                R.it = 1;
+                R.cycles = R.nrho = 0;
+                R.rho_last = R.logsum = R.dwrel = 0.0;
+                if (!std::isfinite(R.nF)) rc = LSMG_ENONFINITE;
+            }
+            if (fl[k] && rc == LSMG_OK) {
+                if (B->h_cstatus[k] != 0) rc = LSMG_ENONFINITE;
+                R.q = 0;
+                R.rprev = R.nF;
+                R.force_update = false;
+                R.next = RunState::Solve;
+            }
+            if (fc[k] && rc == LSMG_OK) {
+                const double rq = bnorm(B, k, 1);
+                ++R.q;
+                ++R.cycles;
+                R.rho_last = R.rprev > 0.0 ? rq / R.rprev : 0.0;
+                if (R.rho_last > 0.0) R.logsum += std::log(R.rho_last);
+                ++R.nrho;
+                R.rprev = rq;
+                if (!std::isfinite(rq)) R.force_update = true;
+            }
+            if (fu[k]) {
+                R.nF = bnorm(B, k, 0);
+                const double nD = bnorm(B, k, 2), nW = bnorm(B, k, 3);
+                R.dwrel = nW > 0.0 ? nD / nW : nD;
+                if (!std::isfinite(R.nF) || !std::isfinite(R.dwrel)) rc = LSMG_ENONFINITE;
+                else if ((R.nF < R.dwrel ? R.nF : R.dwrel) < B->p.newton_tol) done = true;
+                else if (R.it >= B->p.newton_max) rc = LSMG_ENOCONV;
+                else {
+                    ++R.it;
+                    R.next = RunState::Lin;
+                }
+            }
+            if (rc != LSMG_OK || done) {
+                any_end = true;
+                if (ended) ended[k] = 1;
+                if (status) status[k] = rc;
+                if (stats) {
+                    stats[k].newton_iters = R.it;
+                    stats[k].vcycles = R.cycles;
+                    stats[k].res_inf = R.nF;
+                    stats[k].rho_last = R.rho_last;
+                    stats[k].rho_geo = R.nrho > 0 ? std::exp(R.logsum / R.nrho) : 0.0;
+                    stats[k].dw_rel = R.dwrel;
+                }
+                if (step_ms) step_ms[k] = t_end - R.t_start;
+                if (done) commit[k] = 1;
+                // a failed step keeps W^n and ends the member's run; a finished one
+                // starts the next step in the following call if steps remain
+                R.next = RunState::Idle;
+                B->mem[k]->lin_set = false;
+            }
+        }
+        bool any_commit = false;
+        for (int k = 0; k < nk; ++k) any_commit |= commit[k];
+        if (any_commit) {
+            std::vector<std::vector<char>> crow(kFlagRows, std::vector<char>(nk, 0));
+            crow[kFCommit] = commit;
+            LSMGCHK(set_flag_rows(B, crow));
+            launch_commit(B->dim, B->d64, items(B, B->lev0), B->lev0.n, xm);
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
+    if (ticks_run) *ticks_run = ticks;
+    return LSMG_OK;
 }
 
 lsmg_status lsmg_batch_profile_start(lsmg_batch *b, int kernel, int n)

@@ -68,6 +68,18 @@ struct Level {
     const int4 *w_gh4() const { return items + nseg[0] + nseg[1] + nghc + nbandc; }
 };
 
+// Progress of one hierarchy's Crank-Nicolson step inside a batch advanced at
+// V-cycle granularity (lsmg_batch_advance): the stopping state of the Newton
+// and linear-solve loops.  It lives with the hierarchy so that a step in
+// progress survives a change of batch membership.
+struct RunState {
+    enum Next { Idle = 0, Start, Solve, Lin } next = Idle;
+    int it = 0, q = 0, cycles = 0, nrho = 0;
+    bool force_update = false;
+    double nF = 0.0, rprev = 0.0, rho_last = 0.0, logsum = 0.0, dwrel = 0.0;
+    double t_start = 0.0;   // host clock (ms) when the step's first launch was issued
+};
+
 }  // namespace lsmg
 
 using namespace lsmg;
@@ -83,6 +95,7 @@ struct lsmg_hierarchy {
     LevelDesc<double> *d64 = nullptr;
     LevelDesc<float> *d32 = nullptr;
     bool have32 = false;
+    RunState run;
     double dt = 0.0;
     bool lin_set = false;
     double *bs = nullptr, *bc = nullptr, *tmp_s = nullptr, *tmp_c = nullptr;

@@ -66,6 +66,7 @@ def load():
         "lsmg_build_hierarchy": (_i, [_vp, ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]),
         "lsmg_destroy_hierarchy": (None, [_vp]),
         "lsmg_set_params": (_i, [_vp, ctypes.POINTER(Params)]),
+        "lsmg_set_dt": (_i, [_vp, _d]),
         "lsmg_get_params": (_i, [_vp, ctypes.POINTER(Params)]),
         "lsmg_num_levels": (_i, [_vp, ctypes.POINTER(_i)]),
         "lsmg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_i),
@@ -99,6 +100,9 @@ def load():
         "lsmg_batch_step": (_i, [_vp, ctypes.POINTER(_vp), _d, ctypes.POINTER(_vp), ctypes.POINTER(_d),
                                  ctypes.POINTER(_i), ctypes.POINTER(StepStats)]),
         "lsmg_batch_set_autotune": (_i, [_vp, _i]),
+        "lsmg_batch_advance": (_i, [_vp, ctypes.POINTER(_vp), _d, ctypes.POINTER(_d), ctypes.POINTER(_i), _i,
+                                    ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(StepStats),
+                                    ctypes.POINTER(_d), ctypes.POINTER(_i)]),
         "lsmg_batch_tuning": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "lsmg_batch_profile_start": (_i, [_vp, _i, _i]),
         "lsmg_batch_profile_stop": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
@@ -185,6 +189,10 @@ class Hierarchy:
             self.close()
         except Exception:
             pass
+
+    def set_dt(self, dt):
+        """Prepare the hierarchy for time step dt (done by the first step otherwise)."""
+        _check(load().lsmg_set_dt(self._h, dt), "lsmg_set_dt")
 
     def memory_bytes(self):
         """(hierarchy bytes, bytes of one state) on the device."""
@@ -381,6 +389,23 @@ class Batch:
         if check:
             _check(rc, "lsmg_batch_step")
         return [status[k] for k in range(n)], [stats[k].as_dict() for k in range(n)]
+
+    def advance(self, states, dt, remaining, sb_const=None, max_ticks=1 << 30):
+        """Ticks at V-cycle granularity until some member ends a step; returns a list of
+        (member, status, stats, step_ms) for the members whose step ended, and the ticks run."""
+        n = len(self.members)
+        st_arr = (_vp * n)(*[st._s for st in states])
+        sbc = (_d * n)(*sb_const) if sb_const is not None else None
+        rem = (_i * n)(*remaining)
+        ended = (_i * n)()
+        status = (_i * n)()
+        stats = (StepStats * n)()
+        ms = (_d * n)()
+        ticks = _i()
+        _check(load().lsmg_batch_advance(self._b, st_arr, dt, sbc, rem, max_ticks, ended, status, stats, ms,
+                                         ctypes.byref(ticks)), "lsmg_batch_advance")
+        out = [(k, status[k], stats[k].as_dict(), ms[k]) for k in range(n) if ended[k]]
+        return out, ticks.value
 
     def tuning(self):
         """{grid size: {kernel class: wavefronts per workgroup}}."""

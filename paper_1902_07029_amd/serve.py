@@ -3,15 +3,19 @@
 Requests arrive over time, each a domain (level set on an n^dim grid), a number
 of steps and dt.  The server admits a waiting request when its estimated device
 footprint fits the memory budget and a batch slot is free.  A builder thread
-builds the admitted request's hierarchy and state on a stream of its own while
-the GPU keeps stepping the resident simulations.  At every step boundary
-finished builds join the batch, and each batched step (``lsmg_batch_step``)
-advances every resident simulation by one Crank-Nicolson step.  A simulation
-that has done its steps leaves the batch and frees its memory.
+builds the admitted request's hierarchy and state, and prepares it for dt, on a
+stream of its own while the GPU keeps working on the resident simulations.
 
-Every member's result is bitwise what it would be alone: the batch runs each
-member's own operations in its own order.  The numerics are all in the HIP
-library; this module only schedules.
+The resident simulations advance together at V-cycle granularity
+(``lsmg_batch_advance``): each tick gives every member the next piece of its own
+step (a step start, a V-cycle, a Newton update, a new linearisation), so a
+member whose step converges quickly goes on to its next step while another is
+still iterating.  Between ticks, finished builds join and finished simulations
+leave; a simulation in the middle of a step keeps its progress when the batch
+is rebuilt around it.
+
+Every member's result is bitwise what it would be alone.  The numerics are all
+in the HIP library; this module only schedules.
 """
 import collections
 import queue
@@ -52,7 +56,8 @@ class Server:
     budget_bytes: device memory the resident simulations may hold (default 80 % of
     the free memory); max_members: batch slots."""
 
-    def __init__(self, params, budget_bytes=None, max_members=64, autotune=False, keep_states=False):
+    def __init__(self, params, budget_bytes=None, max_members=64, autotune=False, keep_states=False,
+                 max_ticks=8):
         self.params = params
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
@@ -61,6 +66,7 @@ class Server:
         self.max_members = max_members
         self.autotune = autotune
         self.keep_states = keep_states
+        self.max_ticks = max_ticks
 
     def _build(self, req, stream):
         with torch.cuda.stream(stream):
@@ -71,6 +77,7 @@ class Server:
             s = torch.full((nn,), req.s0, dtype=torch.float64, device="cuda")
             c = torch.full((nn,), req.c0, dtype=torch.float64, device="cuda")
             st.set_grid(s, c)
+            H.set_dt(req.dt)
         stream.synchronize()
         return H, st
 
@@ -104,7 +111,7 @@ class Server:
         reserved = 0          # estimated bytes of admitted requests not yet built
         used = 0              # bytes held by resident members
         in_build = 0
-        steps_log = []        # (t, members, ms)
+        steps_log = []        # (t, members, ms, ticks) per advance call
         batch = None
         dirty = False
         t0 = time.perf_counter()
@@ -155,13 +162,15 @@ class Server:
                 if len(dts) != 1:
                     raise ValueError("resident simulations must share dt")
                 ts = time.perf_counter()
-                status, stats = batch.step([m.st for m in resident], dts.pop(),
-                                           sb_const=[m.req.sb for m in resident], check=False)
+                ended, ticks = batch.advance([m.st for m in resident], dts.pop(),
+                                             [m.req.steps - m.done for m in resident],
+                                             sb_const=[m.req.sb for m in resident], max_ticks=self.max_ticks)
                 ms = (time.perf_counter() - ts) * 1e3
-                steps_log.append((ts - t0, len(resident), ms))
-                keep = []
-                for m, s, stt in zip(resident, status, stats):
-                    m.lat.append(ms)
+                steps_log.append((ts - t0, len(resident), ms, ticks))
+                leave = set()
+                for k, s, stt, step_ms in ended:
+                    m = resident[k]
+                    m.lat.append(step_ms)
                     m.cycles += stt["vcycles"]
                     m.newton += stt["newton_iters"]
                     if s == lsmg.OK:
@@ -169,26 +178,31 @@ class Server:
                     else:
                         m.status = s
                     if m.done >= m.req.steps or s != lsmg.OK:
-                        t_end = time.perf_counter() - t0
-                        rec = dict(id=m.req.id, n=m.req.n, dim=m.req.dim, steps=m.done, status=m.status,
-                                   arrival=m.req.arrival, admitted=m.t_admit, ready=m.t_ready, finished=t_end,
-                                   unknowns=m.unknowns, cycles=m.cycles, newton=m.newton, bytes=m.bytes,
-                                   est_bytes=m.est, lat_ms=m.lat)
-                        if self.keep_states:
-                            rec["state"] = m.st.get().cpu().numpy()
-                        finished.append(rec)
-                        used -= m.bytes
-                        m.st.close()
-                        m.H.close()
-                        dirty = True
-                    else:
+                        leave.add(k)
+                keep = []
+                for k, m in enumerate(resident):
+                    if k not in leave:
                         keep.append(m)
+                        continue
+                    t_end = time.perf_counter() - t0
+                    rec = dict(id=m.req.id, n=m.req.n, dim=m.req.dim, steps=m.done, status=m.status,
+                               arrival=m.req.arrival, admitted=m.t_admit, ready=m.t_ready, finished=t_end,
+                               unknowns=m.unknowns, cycles=m.cycles, newton=m.newton, bytes=m.bytes,
+                               est_bytes=m.est, lat_ms=m.lat)
+                    if self.keep_states:
+                        rec["state"] = m.st.get().cpu().numpy()
+                    finished.append(rec)
+                    used -= m.bytes
+                    m.st.close()
+                    m.H.close()
+                    dirty = True
                 resident = keep
                 if dirty:
                     batch = None
                 if log:
-                    log(f"t={ts - t0:7.3f}s step of {len(status)} members {ms:7.2f} ms, "
-                        f"resident {len(resident)} waiting {len(waiting)} building {in_build}")
+                    log(f"t={ts - t0:7.3f}s {ticks} ticks over {steps_log[-1][1]} members {ms:7.2f} ms, "
+                        f"{len(ended)} steps ended, resident {len(resident)} waiting {len(waiting)} "
+                        f"building {in_build}")
         finally:
             todo.put(None)
             th.join()
@@ -207,7 +221,8 @@ class Server:
             p99_step_ms=float(np.percentile(lat, 99)) if lat.size else None,
             busy_s=sum(s[2] for s in steps_log) * 1e-3,
             busy_throughput=work / max(sum(s[2] for s in steps_log) * 1e-3, 1e-9),
-            batched_steps=len(steps_log),
+            advance_calls=len(steps_log),
+            ticks=sum(s[3] for s in steps_log),
             mean_members=float(np.mean([s[1] for s in steps_log])) if steps_log else 0.0,
             max_members=max((s[1] for s in steps_log), default=0),
             queue_wait_s=float(np.mean([f["admitted"] - f["arrival"] for f in finished if "admitted" in f]))

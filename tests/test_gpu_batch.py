@@ -181,3 +181,54 @@ def test_full_64_domain_batch_members_equal_alone():
             assert torch.equal(states[k].get(), alone[k][1].get()), (step, k)
             assert stats[k]["vcycles"] == ref["vcycles"]
         say(f"64-domain batch step {step}: {len(sample)} sampled members bitwise equal to alone")
+
+
+def _advance_all(B, states, steps, dt=1e-4, max_ticks=1 << 30):
+    done = [0] * len(states)
+    got = [[] for _ in states]
+    while any(done[k] < steps[k] for k in range(len(states))):
+        ended, ticks = B.advance(states, dt, [steps[k] - done[k] for k in range(len(states))], max_ticks=max_ticks)
+        assert ticks >= 1
+        for k, s, stt, ms in ended:
+            assert s == lsmg.OK, (k, s)
+            assert ms > 0.0
+            done[k] += 1
+            got[k].append(stt)
+    return got
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_advance_bitwise_alone(precision):
+    # members with different numbers of steps advanced at V-cycle granularity: every member's
+    # states, Newton iterations and V-cycles per step equal those of stepping it alone
+    steps = [3, 1, 4, 2]
+    alone = [_hier(2, d, precision) for d in STARS2]
+    members = [_hier(2, d, precision) for d in STARS2]
+    sa = [_state(H, d, 2) for H, d in zip(alone, STARS2)]
+    sb = [_state(H, d, 2) for H, d in zip(members, STARS2)]
+    ref = [[st.step(1e-4)[1] for _ in range(n)] for st, n in zip(sa, steps)]
+    got = _advance_all(lsmg.Batch(members), sb, steps)
+    for k in range(len(STARS2)):
+        assert torch.equal(sa[k].get(), sb[k].get()), k
+        assert [(r["newton_iters"], r["vcycles"]) for r in ref[k]] == \
+            [(g["newton_iters"], g["vcycles"]) for g in got[k]], k
+    say(f"advance prec {precision}: per-member (newton, cycles) {[[(g['newton_iters'], g['vcycles']) for g in gk] for gk in got]}")
+
+
+@pytest.mark.gpu
+def test_step_in_progress_survives_new_batch():
+    # a member stopped in the middle of a step (a few ticks) continues in a rebuilt batch with
+    # other members, and ends with the same state as alone
+    a, b, c = (_hier(3, d, 1) for d in (ELL3[1], ELL3[0], ELL3[0]))
+    ref = _hier(3, ELL3[1], 1)
+    sa, sb, sc, sr = _state(a, ELL3[1], 3), _state(b, ELL3[0], 3), _state(c, ELL3[0], 3), _state(ref, ELL3[1], 3)
+    for _ in range(2):
+        sr.step(1e-4)
+    B1 = lsmg.Batch([a, b])
+    ended, ticks = B1.advance([sa, sb], 1e-4, [2, 1], max_ticks=3)
+    assert ticks == 3 and all(k != 0 for k, *_ in ended)
+    B1.close()
+    got = _advance_all(lsmg.Batch([c, a]), [sc, sa], [1, 2])
+    assert len(got[1]) == 2
+    assert torch.equal(sa.get(), sr.get())

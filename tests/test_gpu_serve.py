@@ -44,7 +44,7 @@ def test_served_results_equal_alone(precision):
     reqs = _requests(6, 3, steps=(8, 15), gap=0.01)
     rep = Server(params, keep_states=True).run(reqs)
     assert rep["completed"] == len(reqs), rep["errors"]
-    say(f"served {len(reqs)} requests, {rep['batched_steps']} batched steps, up to {rep['max_members']} "
+    say(f"served {len(reqs)} requests in {rep['ticks']} ticks, up to {rep['max_members']} "
         f"members at once, p50 {rep['p50_step_ms']:.2f} ms p99 {rep['p99_step_ms']:.2f} ms")
     # requests overlapped on the device: some batched step held several members
     assert rep["max_members"] >= 2
