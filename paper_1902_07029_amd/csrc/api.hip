@@ -242,13 +242,17 @@ TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
     a.nu2 = H->p.nu2;
     a.c2s = H->L[H->nlev - 1].c2s;
     a.ainv = H->ainv;
+    int off = 0;
     for (int l = 0; l < H->nlev; ++l) {
         const Level &Lv = H->L[l];
         a.lev[l].in_ijk = Lv.in_ijk;
         a.lev[l].nin0 = Lv.nin[0];
         a.lev[l].nin1 = Lv.nin[1];
         a.lev[l].sweeps = Lv.sweeps;
+        a.lev[l].soff = l >= l0 ? off : 0;
+        if (l >= l0) off += Lv.nin[0] + Lv.nin[1] + 2 * Lv.ng + 1;
     }
+    a.nstage = off;
     return a;
 }
 
@@ -259,7 +263,8 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
     const LevelDesc<T> *d = descs<T>(H);
     if (l >= H->tail_l0) {
         // this level and every coarser one in one workgroup
-        launch_tail<T>(H->dim, d, H->d_tail + l, 1, H->L[H->nlev - 1].na, Exec(s));
+        launch_tail<T>(H->dim, d, H->d_tail + l, 1, H->L[H->nlev - 1].na,
+                       tail_args(H, l, 0).nstage <= kTailStageInts, Exec(s));
         return;
     }
     for (int i = 0; i < H->p.nu1; ++i) smooth_level<T>(H, l, s);

@@ -67,6 +67,7 @@ struct lsmg_batch {
     int npool = 0;
     TailArgs *d_tail = nullptr;
     int tail_na_max = 0;
+    bool tail_stage = true;     // every member's tail node lists fit the LDS copy
     CoarseArgs *d_coarse = nullptr;
     int coarse_n_max = 0;
     int *d_act = nullptr, *h_act = nullptr;
@@ -302,7 +303,7 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
         launch_restrict<T>(B->dim, d, items(B, S.rcoarse), S.rcoarse.n,
                            bexec_t(B, s, S.ipb[kTRestrict], LSMG_KERNEL_RESTRICT, S.n));
     }
-    launch_tail<T>(B->dim, d, B->d_tail, B->ndom, B->tail_na_max, Exec(s, B->d_act));
+    launch_tail<T>(B->dim, d, B->d_tail, B->ndom, B->tail_na_max, B->tail_stage, Exec(s, B->d_act));
     for (int z = nz - 1; z >= 0; --z) {
         const BSize &S = B->sizes[z];
         if (S.act.n == 0) continue;
@@ -586,6 +587,7 @@ lsmg_status b_build(lsmg_batch *B)
         const lsmg_hierarchy *H = B->mem[k];
         ta[k] = tail_args(H, H->tail_l0, B->d0[k]);
         B->tail_na_max = std::max(B->tail_na_max, H->L[H->nlev - 1].na);
+        B->tail_stage = B->tail_stage && ta[k].nstage <= kTailStageInts;
         ca[k] = CoarseArgs{};
         ca[k].desc = B->d0[k] + H->nlev - 1;
         ca[k].c2s = H->L[H->nlev - 1].c2s;

@@ -281,7 +281,22 @@ __device__ __forceinline__ void band_elem(const LevelDesc<T> *D, int b)
     if (cnt == 0) return;
     const int nb = D->nb;
     T v = 0;
-    for (int j = 0; j < cnt; ++j) v += D->b_wt[j * nb + b] * D->r_s[D->b_src[j * nb + b]];
+    // sources fetched eight at a time, summed in order
+    for (int j0 = 0; j0 < cnt; j0 += 8) {
+        int src[8];
+        T wt[8], r[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool ok = j0 + u < cnt;
+            src[u] = ok ? D->b_src[(j0 + u) * nb + b] : 0;
+            wt[u] = ok ? D->b_wt[(j0 + u) * nb + b] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) r[u] = D->r_s[src[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < cnt) v += wt[u] * r[u];
+    }
     D->r_s[D->b_idx[b]] = v;
 }
 
@@ -385,11 +400,14 @@ __device__ __forceinline__ void prolong_node(const LevelDesc<T> *F, long long id
             }
         }
         if (skip) continue;
+        // the corrections are read with the node type (one round trip); an inactive
+        // corner adds +0, which leaves the sums unchanged (they are never -0)
         const long long q = sidx(C->n, C->Wp, C->cs, id[0], id[1], id[2]);
-        if (C->type[q] == kOut) continue;
-        ws += wk;
-        es += wk * C->x_s[q];
-        ec += wk * C->x_c[q];
+        const bool on = C->type[q] != kOut;
+        const T xs = C->x_s[q], xc = C->x_c[q];
+        ws += on ? wk : T(0);
+        es += on ? wk * xs : T(0);
+        ec += on ? wk * xc : T(0);
     }
     if (ws > T(0)) {
         F->x_s[idx] += es / ws;
@@ -658,37 +676,124 @@ __global__ __launch_bounds__(kMaxBlock) void k_zero_x(const LevelDesc<T> *__rest
 // coarse tail: levels l0 .. L-1 of a V-cycle in one workgroup, walking packed
 // node lists (one node per thread and pass) with barriers between phases.
 // Workgroup b runs the tail of the hierarchy described by args[b].
+//
+// Each phase costs about the latency of its chain of dependent loads, so the
+// chains are kept short: the levels' node lists and composed-map row pointers
+// are copied to LDS first (STAGE), the ghost relaxation keeps its per-ghost
+// values in LDS, and row entries are fetched in groups before they are summed
+// in their original order (the arithmetic, and so the result, is unchanged).
+// LDS: [4 ncoarse_max doubles: coarsest solve][2 x kTailMaxNodes T: ghost values]
+//      [nstage ints: node lists, STAGE only]
 // ---------------------------------------------------------------------------
-// node t of a level's active list: inside nodes (colour 0, colour 1), then ghosts
 template <typename T>
-__device__ __forceinline__ void tail_node(const LevelDesc<T> *D, const TailLevel &TL, int t, long long &idx, int &i,
-                                          int &j, int &k)
+struct TailLds {
+    double *coarse;
+    T *gb0, *gb1;    // per ghost: b = rhs - non-ghost stencil terms, and the old delta s
+    int *si;         // per level at soff: inside coordinates, ghost coordinates, map row pointers
+};
+
+// packed coordinates of node t of a level's active list: inside nodes (colour 0,
+// colour 1), then ghosts
+template <typename T, bool STAGE>
+__device__ __forceinline__ int tail_ijk(const LevelDesc<T> *D, const TailLevel &TL, const int *si, int t)
 {
+    if (STAGE) return si[TL.soff + t];
     const int nin = TL.nin0 + TL.nin1;
-    unpack_ijk(t < nin ? TL.in_ijk[t] : D->g_ijk[t - nin], i, j, k);
+    return t < nin ? TL.in_ijk[t] : D->g_ijk[t - nin];
+}
+
+template <typename T, bool STAGE>
+__device__ __forceinline__ void tail_node(const LevelDesc<T> *D, const TailLevel &TL, const int *si, int t,
+                                          long long &idx, int &i, int &j, int &k)
+{
+    unpack_ijk(tail_ijk<T, STAGE>(D, TL, si, t), i, j, k);
     idx = sidx(D->n, D->Wp, D->cs, i, j, k);
 }
 
-template <typename T, int DIM, int NST>
-__device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, int sweeps)
+template <typename T, bool STAGE>
+__device__ __forceinline__ int tail_goptr(const LevelDesc<T> *D, const TailLevel &TL, const int *si, int q)
+{
+    return STAGE ? si[TL.soff + TL.nin0 + TL.nin1 + D->ng + q] : D->go_ptr[q];
+}
+
+// composed ghost relaxation, phase 1 (as ghost_b_elem, values into LDS)
+template <typename T, int NST>
+__device__ __forceinline__ void tail_ghost_b(const LevelDesc<T> *D, int q, long long g, T *gb0, T *gb1)
+{
+    const int ng = D->ng;
+    T val[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+        const T xv = D->x_s[D->g_st[k * ng + q]];
+        val[k] = D->g_stg[k * ng + q] >= 0 ? T(0) : xv;
+    }
+    T v = 0;
+#pragma unroll
+    for (int k = 0; k < NST; ++k) v += D->g_w[k * ng + q] * val[k];
+    gb0[q] = D->rhs_s[g] - v;
+    gb1[q] = D->x_s[g];
+}
+
+// composed ghost relaxation, phase 2 (as ghost_apply_elem, row entries [e0, e1))
+template <typename T>
+__device__ __forceinline__ void tail_ghost_apply(const LevelDesc<T> *D, long long g, int e0, int e1, const T *gb0,
+                                                 const T *gb1)
+{
+    T cs_d, cc_d;
+    c_row<T>(D, g, cs_d, cc_d);
+    const T xc = D->x_c[g], rc = D->rhs_c[g];
+    T v = 0;
+    for (int e = e0; e < e1; e += 4) {
+        int col[4];
+        T a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = e + u < e1;
+            col[u] = ok ? D->go_col[e + u] : 0;
+            a[u] = ok ? D->go_a[e + u] : T(0);
+            b[u] = ok ? D->go_b[e + u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e + u < e1) v += a[u] * gb1[col[u]] + b[u] * gb0[col[u]];
+    }
+    D->x_s[g] = v;
+    D->x_c[g] = xc + (rc - (cs_d * v + cc_d * xc)) / cc_d;
+}
+
+template <typename T, int DIM, int NST, bool STAGE>
+__device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, const TailLds<T> &S)
 {
     for (int colour = 0; colour < 2; ++colour) {
         const int off = colour ? TL.nin0 : 0, cnt = colour ? TL.nin1 : TL.nin0;
         for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            long long idx;
             int i, j, k;
-            unpack_ijk(TL.in_ijk[off + t], i, j, k);
-            smooth_node<T, DIM>(D, sidx(D->n, D->Wp, D->cs, i, j, k), i, j, k, colour);
+            tail_node<T, STAGE>(D, TL, S.si, off + t, idx, i, j, k);
+            smooth_node<T, DIM>(D, idx, i, j, k, colour);
         }
         __syncthreads();
     }
-    const int ng = D->ng;
+    const int ng = D->ng, nin = TL.nin0 + TL.nin1;
     if (D->go_ptr) {
-        for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_b_elem<T, NST>(D, q);
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) {
+            long long g;
+            int i, j, k;
+            tail_node<T, STAGE>(D, TL, S.si, nin + q, g, i, j, k);
+            tail_ghost_b<T, NST>(D, q, g, S.gb0, S.gb1);
+        }
         __syncthreads();
-        for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_apply_elem<T>(D, q);
+        for (int q = threadIdx.x; q < ng; q += blockDim.x) {
+            long long g;
+            int i, j, k;
+            tail_node<T, STAGE>(D, TL, S.si, nin + q, g, i, j, k);
+            tail_ghost_apply<T>(D, g, tail_goptr<T, STAGE>(D, TL, S.si, q), tail_goptr<T, STAGE>(D, TL, S.si, q + 1),
+                                S.gb0, S.gb1);
+        }
         __syncthreads();
         return;
     }
+    const int sweeps = TL.sweeps;
     for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_load_elem<T>(D, q);
     __syncthreads();
     for (int sw = 0; sw < sweeps; ++sw) {
@@ -703,59 +808,96 @@ __device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, int sweeps
     __syncthreads();
 }
 
+// sum_q M[r][q] v[q] subtracted from (SIGN < 0) or added to acc, with the row's
+// entries fetched eight at a time and summed in order q = 0 .. na-1
+template <int SIGN>
+__device__ __forceinline__ double row_dot(const double *__restrict__ row, const double *v, int na, double acc)
+{
+    for (int q0 = 0; q0 < na; q0 += 8) {
+        double m[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) m[e] = q0 + e < na ? row[q0 + e] : 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (q0 + e < na) {
+                if (SIGN < 0) acc -= m[e] * v[q0 + e];
+                else acc += m[e] * v[q0 + e];
+            }
+        }
+    }
+    return acc;
+}
+
 // x = A^{-1} rhs on the coarsest level (FP64).  The c-rows couple a node only to
 // itself (J^cs and J^cc are diagonal), so A^{-1} rhs is applied through the
 // Schur complement S = J^ss - J^sc diag(J^cs / J^cc) of the c-block:
 //     t = r_s - J^sc (r_c / J^cc),   x_s = S^{-1} t,   x_c = (r_c - J^cs x_s) / J^cc.
 // Coarse storage (from k_coarse_invert): [S^{-1} | J^sc | J^cs | J^cc], Na x Na,
-// Na x Na, Na, Na doubles.  b: 3 Na doubles of LDS.
+// Na x Na, Na, Na doubles.  b: 4 Na doubles of LDS.
 template <typename T>
 __device__ void wg_coarse_apply(const LevelDesc<T> *D, const int *__restrict__ c2s, const double *__restrict__ Ainv,
                                 double *b)
 {
     const int na = D->na;
     const double *Sinv = Ainv, *Jsc = Ainv + (long long)na * na, *cs = Ainv + 2LL * na * na, *cc = cs + na;
-    double *rs = b, *rc = b + na, *t = b + 2 * na;
+    double *rs = b, *rc = b + na, *t = b + 2 * na, *u = b + 3 * na;
     for (int r = threadIdx.x; r < na; r += blockDim.x) {
-        rs[r] = (double)D->rhs_s[c2s[r]];
-        rc[r] = (double)D->rhs_c[c2s[r]];
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < na; r += blockDim.x) {
-        double v = rs[r];
-        for (int q = 0; q < na; ++q) v -= Jsc[(long long)r * na + q] * (rc[q] / cc[q]);
-        t[r] = v;
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < na; r += blockDim.x) {
-        double v = 0.0;
-        for (int q = 0; q < na; ++q) v += Sinv[(long long)r * na + q] * t[q];
         const long long node = c2s[r];
+        const double vc = (double)D->rhs_c[node];
+        rs[r] = (double)D->rhs_s[node];
+        rc[r] = vc;
+        u[r] = vc / cc[r];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < na; r += blockDim.x) t[r] = row_dot<-1>(Jsc + (long long)r * na, u, na, rs[r]);
+    __syncthreads();
+    for (int r = threadIdx.x; r < na; r += blockDim.x) {
+        const long long node = c2s[r];
+        const double csr = cs[r], ccr = cc[r];
+        const double v = row_dot<1>(Sinv + (long long)r * na, t, na, 0.0);
         D->x_s[node] = (T)v;
-        D->x_c[node] = (T)((rc[r] - cs[r] * v) / cc[r]);
+        D->x_c[node] = (T)((rc[r] - csr * v) / ccr);
     }
     __syncthreads();
 }
 
-template <typename T, int DIM, int NST>
+template <typename T, int DIM, int NST, bool STAGE>
 __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ descs,
-                                               const TailArgs *__restrict__ args, LSMG_ACT)
+                                               const TailArgs *__restrict__ args, int ncoarse_max, LSMG_ACT)
 {
     extern __shared__ double sb[];
     const TailArgs &A = args[blockIdx.x];
     if (act && !act[A.d0]) return;
+    TailLds<T> S;
+    S.coarse = sb;
+    S.gb0 = reinterpret_cast<T *>(sb + 4 * ncoarse_max);
+    S.gb1 = S.gb0 + kTailMaxNodes;
+    S.si = reinterpret_cast<int *>(S.gb1 + kTailMaxNodes);
     const LevelDesc<T> *base = descs + A.d0;
     const int L = A.nlev;
+    if (STAGE) {
+        for (int l = A.l0; l < L; ++l) {
+            const LevelDesc<T> *D = base + l;
+            const TailLevel &TL = A.lev[l];
+            const int nin = TL.nin0 + TL.nin1, ng = D->ng;
+            int *dst = S.si + TL.soff;
+            for (int t = threadIdx.x; t < nin; t += blockDim.x) dst[t] = TL.in_ijk[t];
+            for (int t = threadIdx.x; t < ng; t += blockDim.x) dst[nin + t] = D->g_ijk[t];
+            if (D->go_ptr)
+                for (int t = threadIdx.x; t <= ng; t += blockDim.x) dst[nin + ng + t] = D->go_ptr[t];
+        }
+        __syncthreads();
+    }
     for (int l = A.l0; l < L - 1; ++l) {
         const LevelDesc<T> *D = base + l;
         const TailLevel &TL = A.lev[l];
-        for (int it = 0; it < A.nu1; ++it) wg_smooth<T, DIM, NST>(D, TL, TL.sweeps);
+        for (int it = 0; it < A.nu1; ++it) wg_smooth<T, DIM, NST, STAGE>(D, TL, S);
         const int nin = TL.nin0 + TL.nin1;
         for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
             if (t < nin) {
                 long long idx;
                 int i, j, k;
-                tail_node<T>(D, TL, t, idx, i, j, k);
+                tail_node<T, STAGE>(D, TL, S.si, t, idx, i, j, k);
                 (void)defect_inside<T, DIM>(D, idx, i, j, k);
             } else {
                 (void)defect_ghost<T, NST>(D, t - nin);
@@ -770,12 +912,12 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
         for (int t = threadIdx.x; t < ninc + C->ng; t += blockDim.x) {
             long long idx;
             int i, j, k;
-            tail_node<T>(C, TC, t, idx, i, j, k);
+            tail_node<T, STAGE>(C, TC, S.si, t, idx, i, j, k);
             restrict_node<T, DIM>(C, idx, i, j, k, t < ninc);
         }
         __syncthreads();
     }
-    wg_coarse_apply<T>(base + (L - 1), A.c2s, A.ainv, sb);
+    wg_coarse_apply<T>(base + (L - 1), A.c2s, A.ainv, S.coarse);
     for (int l = L - 2; l >= A.l0; --l) {
         const LevelDesc<T> *D = base + l;
         const TailLevel &TL = A.lev[l];
@@ -783,11 +925,11 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
         for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
             long long idx;
             int i, j, k;
-            tail_node<T>(D, TL, t, idx, i, j, k);
+            tail_node<T, STAGE>(D, TL, S.si, t, idx, i, j, k);
             prolong_node<T, DIM>(D, idx, i, j, k);
         }
         __syncthreads();
-        for (int it = 0; it < A.nu2; ++it) wg_smooth<T, DIM, NST>(D, TL, TL.sweeps);
+        for (int it = 0; it < A.nu2; ++it) wg_smooth<T, DIM, NST, STAGE>(D, TL, S);
     }
 }
 
@@ -1318,11 +1460,16 @@ void launch_zero_x(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const 
 }
 
 template <typename T>
-void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max, const Exec &x)
+void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max, bool stage,
+                 const Exec &x)
 {
     if (nblocks <= 0) return;
-    const size_t shm = (size_t)3 * ncoarse_max * sizeof(double);
-    LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST><<<nblocks, 1024, shm, x.s>>>(d, args, x.act));
+    const size_t shm = (size_t)4 * ncoarse_max * sizeof(double) + 2 * kTailMaxNodes * sizeof(T) +
+                       (stage ? kTailStageInts * sizeof(int) : 0);
+    if (stage)
+        LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST, true><<<nblocks, 1024, shm, x.s>>>(d, args, ncoarse_max, x.act));
+    else
+        LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST, false><<<nblocks, 1024, shm, x.s>>>(d, args, ncoarse_max, x.act));
 }
 
 void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x)
@@ -1437,7 +1584,7 @@ void launch_coarse_factor(int dim, const LevelDesc<double> *d, const CoarseArgs 
 template <typename T>
 void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, const double *Ainv, hipStream_t s)
 {
-    k_coarse_apply<T><<<1, 1024, (size_t)3 * N * sizeof(double), s>>>(d, lev, c2s, Ainv);
+    k_coarse_apply<T><<<1, 1024, (size_t)4 * N * sizeof(double), s>>>(d, lev, c2s, Ainv);
 }
 
 #define LSMG_INST(T) \
@@ -1452,7 +1599,7 @@ void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, 
     template void launch_prolong<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
     template void launch_inject<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
     template void launch_zero_x<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
-    template void launch_tail<T>(int, const LevelDesc<T> *, const TailArgs *, int, int, const Exec &); \
+    template void launch_tail<T>(int, const LevelDesc<T> *, const TailArgs *, int, int, bool, const Exec &); \
     template void launch_gather_compact<T>(const int *, int, const T *, const T *, double *, hipStream_t); \
     template void launch_scatter_compact<T>(const int *, int, const double *, T *, T *, hipStream_t); \
     template void launch_fill<T>(T *, long long, T, hipStream_t); \

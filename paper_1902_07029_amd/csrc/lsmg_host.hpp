@@ -14,16 +14,21 @@ constexpr int kGhostFusedMax = 256;
 // levels with at most this many active nodes run inside the coarse-tail kernel
 constexpr int kTailMaxNodes = 1024;
 constexpr int kMaxLevels = 16;
+// the coarse tail copies its levels' node lists into LDS when they fit in this many ints
+constexpr int kTailStageInts = 6144;
 
 struct TailLevel {
     const int *in_ijk;   // packed coordinates of the inside nodes, colour 0 then colour 1
     int nin0, nin1;
-    int sweeps, pad;     // ghost relaxations per smoothing step on this level
+    int sweeps;          // ghost relaxations per smoothing step on this level
+    int soff;            // offset of the level's node lists in the tail's LDS copy:
+                         // inside coordinates, ghost coordinates, composed-map row pointers
 };
 
 // one hierarchy's coarse tail (levels l0 .. nlev-1), its descriptors starting at d0
 struct TailArgs {
-    int d0, l0, nlev, nu1, nu2, pad;
+    int d0, l0, nlev, nu1, nu2;
+    int nstage;          // ints of the LDS copy of the node lists (sum over the tail's levels)
     const int *c2s;      // coarsest level: compact -> storage
     const double *ainv;  // coarsest level: explicit inverse (FP64, 2Na x 2Na)
     TailLevel lev[kMaxLevels];
@@ -60,7 +65,7 @@ template <typename T> void launch_smooth_colour(int dim, const LevelDesc<T> *d, 
 template <typename T> void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int nw, const int4 *w4,
                                         int nw4, int ng, int sweeps, bool composed, const Exec &xb, const Exec &xa);
 template <typename T> void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max,
-                                       const Exec &x);
+                                       bool stage, const Exec &x);
 template <typename T> void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x);
 template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
