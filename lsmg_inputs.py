@@ -77,6 +77,12 @@ def s_exact(x, y, t):
     return 2.0 + np.sin(x) * np.cos(y) * np.sin(t + SQ2)
 
 
+def s_exact_grad(x, y, t):
+    """(ds/dx, ds/dy) of s_exact, for Neumann boundary data ds/dn = grad s . n."""
+    st = np.sin(t + SQ2)
+    return np.cos(x) * np.cos(y) * st, -np.sin(x) * np.sin(y) * st
+
+
 def c_exact(x, y, t):
     return 3.0 + np.sin(0.5 * x) * np.cos(3.0 * y) * np.sin(2.0 * t + SQ3)
 

@@ -54,14 +54,14 @@ def _load():
     lib = ctypes.CDLL(_LIB)
     vp = ctypes.c_void_p
     lib.or_build.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                             ctypes.c_int, ctypes.POINTER(vp)]
+                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     lib.or_free.argtypes = [vp]
     lib.or_free.restype = None
     lib.or_set_params.argtypes = [vp] + [ctypes.c_double] * 7 + [ctypes.c_int] * 6 + [ctypes.c_double]
     lib.or_num_levels.argtypes = [vp]
     lib.or_level_info.argtypes = [vp, ctypes.c_int, _I, _D, _I, _I, _I]
     lib.or_compact_to_grid.argtypes = [vp, ctypes.c_int, _L]
-    lib.or_ghost_table.argtypes = [vp, ctypes.c_int, _I, _D, _D, _D, _I, _I]
+    lib.or_ghost_table.argtypes = [vp, ctypes.c_int, _I, _D, _D, _D, _D, _I, _I]
     lib.or_set_linearization.argtypes = [vp, _D, ctypes.c_double]
     lib.or_apply_J.argtypes = [vp, ctypes.c_int, _D, _D]
     lib.or_smooth.argtypes = [vp, ctypes.c_int, _D, _D, ctypes.c_int]
@@ -112,17 +112,18 @@ def lu_solve_dense(A, b):
 
 
 class Hierarchy:
-    """Level hierarchy of one domain: level 0 is the finest grid."""
+    """Level hierarchy of one domain: level 0 is the finest grid.  bc: boundary
+    condition for s, 0 Dirichlet (eq. BCs) or 1 Neumann (section 3.6, eq. BCsN)."""
 
-    def __init__(self, phi, dim, n, lo=-1.0, hi=1.0, coarsest_n=5, params=None):
+    def __init__(self, phi, dim, n, lo=-1.0, hi=1.0, coarsest_n=5, params=None, bc=0):
         lib = _load()
         phi = _f64(phi).reshape(-1)
         assert phi.size == n ** dim
         self._phi = phi
         h = ctypes.c_void_p()
-        _check(lib.or_build(_dp(phi), dim, n, lo, hi, coarsest_n, ctypes.byref(h)), "build")
+        _check(lib.or_build(_dp(phi), dim, n, lo, hi, coarsest_n, int(bc), ctypes.byref(h)), "build")
         self._h = h
-        self.dim, self.n, self.lo, self.hi = dim, n, lo, hi
+        self.dim, self.n, self.lo, self.hi, self.bc = dim, n, lo, hi, int(bc)
         self.nlev = lib.or_num_levels(h)
         self.params = dict(a=1e4, d=0.1, m_s=64.06, m_c=100.09, alpha=0.01, beta=0.1,
                            tau_s=0.9, nu1=2, nu2=2, ghost_c_new=1, band_steps=3,
@@ -166,10 +167,12 @@ class Hierarchy:
         ng, nst, dim = info["ng"], 3 ** self.dim, self.dim
         st = np.zeros((ng, nst), dtype=np.int32)
         w = np.zeros((ng, nst)); B = np.zeros((ng, dim)); nrm = np.zeros((ng, dim))
+        nrow = np.zeros((ng, dim))
         order = np.zeros(ng, dtype=np.int32); bfall = np.zeros(ng, dtype=np.int32)
         _check(_load().or_ghost_table(self._h, l, st.ctypes.data_as(_I), _dp(w), _dp(B), _dp(nrm),
-                                      order.ctypes.data_as(_I), bfall.ctypes.data_as(_I)), "ghosts")
-        return dict(st=st, w=w, B=B, normal=nrm, order=order, bfallback=bfall)
+                                      _dp(nrow), order.ctypes.data_as(_I), bfall.ctypes.data_as(_I)),
+               "ghosts")
+        return dict(st=st, w=w, B=B, normal=nrm, row_normal=nrow, order=order, bfallback=bfall)
 
     def band_nodes(self, l):
         info = self.level_info(l)

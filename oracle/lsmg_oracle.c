@@ -49,8 +49,10 @@ typedef struct {
     long *st;        /* ng * nst grid indices of the upwind stencil ST */
     double *w;       /* ng * nst boundary-row weights */
     double *B;       /* ng * dim boundary points */
-    double *nrm;     /* ng * dim unit outward normals */
-    int *order;      /* 2 biquadratic, 1 bilinear, 0 constant */
+    double *nrm;     /* ng * dim unit outward normals (central differences, eq. nij) */
+    double *nrow;    /* ng * dim normal of the boundary row: nrm (Dirichlet), or the unit
+                        gradient of the interpolated level set at B (Neumann, eq. Neumanntilde) */
+    int *order;      /* 2 biquadratic, 1 bilinear, 0 constant (Neumann: one-sided) */
     int *bfall;      /* 1 if B came from the first-order projection */
     /* band of inactive nodes around coarse ghost centres (for the BC defect) */
     int nb;
@@ -72,6 +74,7 @@ typedef struct {
 
 typedef struct or_hier {
     int dim, nlev, nst;
+    int bctype;        /* boundary condition for s: 0 Dirichlet (eq. BCs), 1 Neumann (eq. BCsN) */
     double lo, hi;
     OLevel L[MAXLEV];
     OPar p;
@@ -140,6 +143,29 @@ static double lag1(int k, double t)
     return 0.0;
 }
 
+/* derivatives d/dt of the quadratic weights, the coefficients of eq.
+ * (intcoeffsN) times h: theta + 1/2, -2 theta, theta - 1/2 for k = 0, 1, 2 */
+static double dlag2(int k, double t)
+{
+    if (k == 0) return t + 0.5;
+    if (k == 1) return -2.0 * t;
+    return t - 0.5;
+}
+
+/* derivatives d/dt of the linear weights */
+static double dlag1(int k)
+{
+    if (k == 0) return 1.0;
+    if (k == 1) return -1.0;
+    return 0.0;
+}
+
+/* relaxation parameter of the ghost rows on a level: tau_s for the Dirichlet
+ * row (eq. CFLcond); for the Neumann row tau_s times the bound of eq.
+ * CFLcondN, 2 sqrt(2) h / 3 (READING in 3-D: 4 h / (3 sqrt(3)), the same
+ * bound taken over three axes) */
+static double tau_level(const struct or_hier *H, const OLevel *L);
+
 /* ------------------------------------------------------------------ */
 /* hierarchy: classification (§3.3, eq. ghostdef) and ghost geometry    */
 /* ------------------------------------------------------------------ */
@@ -178,6 +204,92 @@ static void grad_phi(const or_hier *H, const OLevel *L, const int *gi, double *n
         else
             nt[a] = (L->phi[g] - L->phi[g - sa]) / L->h;
     }
+}
+
+static double tau_level(const or_hier *H, const OLevel *L)
+{
+    if (H->bctype == 0) return H->p.tau_s;
+    if (H->dim == 2) return H->p.tau_s * (2.0 * sqrt(2.0) * L->h / 3.0);
+    return H->p.tau_s * (4.0 * L->h / (3.0 * sqrt(3.0)));
+}
+
+/* Neumann boundary row of a ghost (§3.6, eqs. BCsN, Neumanntilde, JccN): the
+ * derivative at B of the biquadratic (triquadratic) interpolant of s on ST
+ * along the row normal, the unit gradient at B of the interpolant of phi on
+ * ST (the central-difference normal where ST leaves the box, theta is out of
+ * range or that gradient vanishes).  With the local coordinate t_a of the
+ * stencil, d/dx_a = (m_a / h) d/dt_a.
+ * READING (order fallback, as for the Dirichlet row): the quadratic rule, else
+ * the gradient of the bilinear interpolant on the box of the nodes k in
+ * {0,1}^d, else one-sided differences s_G - s_{G - m_a e_a} on the axes with
+ * n_a m_a > 0 whose inward neighbour is active (the bilinear rule at theta = 1
+ * without the other axes).  A rule is taken only if its nonzero weights sit on
+ * active nodes and its self weight w_G lies in (0, 2 / tau_max], tau_max the
+ * bound of eq. CFLcondN, so that the relaxation factor stays below 1 in
+ * modulus.  No admissible rule (no such axis): EGEOM. */
+static int neumann_row(const or_hier *H, const OLevel *L, const int *m, const long *st, const char *oob,
+                       int any_oob, const double *th, int bad_theta, const double *nrm, double *w,
+                       double *nr, int *order_out)
+{
+    int dim = H->dim, nst = H->nst;
+    double h = L->h;
+    for (int a = 0; a < dim; ++a) nr[a] = nrm[a];
+    if (!any_oob && !bad_theta) {
+        double gr[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) {
+            double v = 0.0;
+            for (int k = 0; k < nst; ++k) {
+                int kk = k;
+                double wk = 1.0;
+                for (int b = 0; b < dim; ++b) {
+                    wk *= (b == a) ? dlag2(kk % 3, th[b]) : lag2(kk % 3, th[b]);
+                    kk /= 3;
+                }
+                v += wk * L->phi[st[k]];
+            }
+            gr[a] = m[a] * v / h;
+        }
+        double g2 = 0.0;
+        for (int a = 0; a < dim; ++a) g2 += gr[a] * gr[a];
+        if (g2 > 0.0) {
+            double gl = sqrt(g2);
+            for (int a = 0; a < dim; ++a) nr[a] = gr[a] / gl;
+        }
+    }
+    double wmax = (dim == 2) ? 3.0 / (sqrt(2.0) * h) : 3.0 * sqrt(3.0) / (2.0 * h);
+    for (int order = 2; order >= 1 && !bad_theta; --order) {
+        for (int k = 0; k < nst; ++k) {
+            double v = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                int kk = k;
+                double wk = 1.0;
+                for (int b = 0; b < dim; ++b) {
+                    int kb = kk % 3;
+                    if (order == 2) wk *= (b == a) ? dlag2(kb, th[b]) : lag2(kb, th[b]);
+                    else wk *= (b == a) ? dlag1(kb) : lag1(kb, th[b]);
+                    kk /= 3;
+                }
+                v += nr[a] * m[a] * wk / h;
+            }
+            w[k] = v;
+        }
+        int ok = w[0] > 0.0 && w[0] <= wmax;
+        for (int k = 0; k < nst; ++k) if (w[k] != 0.0 && (oob[k] || L->type[st[k]] == 0)) ok = 0;
+        if (ok) { *order_out = order; return OR_OK; }
+    }
+    for (int k = 0; k < nst; ++k) w[k] = 0.0;
+    double wg = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        int k = (a == 0) ? 1 : (a == 1) ? 3 : 9;   /* stencil entry of G - m_a e_a */
+        double c = nr[a] * m[a];
+        if (!(c > 0.0) || oob[k] || L->type[st[k]] == 0) continue;
+        w[k] = -c / h;
+        wg += c / h;
+    }
+    if (!(wg > 0.0)) return OR_EGEOM;
+    w[0] = wg;
+    *order_out = 0;
+    return OR_OK;
 }
 
 static int build_level_geometry(or_hier *H, int l)
@@ -224,6 +336,7 @@ static int build_level_geometry(or_hier *H, int l)
     L->w = (double *)malloc(sizeof(double) * nst * (ng > 0 ? ng : 1));
     L->B = (double *)malloc(sizeof(double) * dim * (ng > 0 ? ng : 1));
     L->nrm = (double *)malloc(sizeof(double) * dim * (ng > 0 ? ng : 1));
+    L->nrow = (double *)malloc(sizeof(double) * dim * (ng > 0 ? ng : 1));
     L->order = (int *)malloc(sizeof(int) * (ng > 0 ? ng : 1));
     L->bfall = (int *)malloc(sizeof(int) * (ng > 0 ? ng : 1));
     for (int q = 0; q < ng; ++q) {
@@ -289,9 +402,16 @@ static int build_level_geometry(or_hier *H, int l)
         for (int a = 0; a < dim; ++a) if (!(th[a] >= -1.0 && th[a] <= 2.0)) bad_theta = 1;
         /* READING: theta outside [-1, 2] (B found by the first-order projection far from G,
          * e.g. where the level set has a crease): the constant rule, on every level */
-        /* boundary-row weights (eq. JssD) with the order fallback */
         double *w = &L->w[(long)q * nst];
         int order = 2;
+        if (H->bctype == 1) {
+            int rc = neumann_row(H, L, m, st, oob, any_oob, th, bad_theta, nrm, w, &L->nrow[q * dim], &order);
+            if (rc != OR_OK) return rc;
+            L->order[q] = order;
+            continue;
+        }
+        for (int a = 0; a < dim; ++a) L->nrow[q * dim + a] = nrm[a];
+        /* boundary-row weights (eq. JssD) with the order fallback */
         if (!bad_theta) {
             for (int k = 0; k < nst; ++k) {
                 int kk = k; double wk = 1.0;
@@ -387,10 +507,10 @@ static double *dalloc(long n) { return (double *)calloc(n > 0 ? n : 1, sizeof(do
 
 void or_free(or_hier *H);
 
-int or_build(const double *phi, int dim, int n, double lo, double hi, int coarsest_n, or_hier **out)
+int or_build(const double *phi, int dim, int n, double lo, double hi, int coarsest_n, int bc, or_hier **out)
 {
     *out = NULL;
-    if (dim < 2 || dim > 3 || n < 3 || coarsest_n < 3 || !(hi > lo)) return OR_EINVAL;
+    if (dim < 2 || dim > 3 || n < 3 || coarsest_n < 3 || !(hi > lo) || bc < 0 || bc > 1) return OR_EINVAL;
     int nlev = 1, nl = n;
     while (nl > coarsest_n) {
         if ((nl - 1) % 2) return OR_EINVAL;
@@ -400,7 +520,7 @@ int or_build(const double *phi, int dim, int n, double lo, double hi, int coarse
     }
     if (nl != coarsest_n) return OR_EINVAL;
     or_hier *H = (or_hier *)calloc(1, sizeof(or_hier));
-    H->dim = dim; H->nlev = nlev; H->nst = ipow3(dim); H->lo = lo; H->hi = hi;
+    H->dim = dim; H->nlev = nlev; H->nst = ipow3(dim); H->lo = lo; H->hi = hi; H->bctype = bc;
     H->p.a = 1e4; H->p.d = 0.1; H->p.m_s = 64.06; H->p.m_c = 100.09;
     H->p.alpha = 0.01; H->p.beta = 0.1; H->p.tau_s = 0.9;
     H->p.nu1 = 2; H->p.nu2 = 2; H->p.ghost_c_new = 1; H->p.band_steps = 3; H->p.ghost_sweeps = 1;
@@ -446,7 +566,7 @@ void or_free(or_hier *H)
     for (int l = 0; l < H->nlev; ++l) {
         OLevel *L = &H->L[l];
         free(L->phi); free(L->type); free(L->c2g); free(L->g2c);
-        free(L->st); free(L->w); free(L->B); free(L->nrm); free(L->order); free(L->bfall);
+        free(L->st); free(L->w); free(L->B); free(L->nrm); free(L->nrow); free(L->order); free(L->bfall);
         free(L->band); free(L->bup); free(L->bwt);
         free(L->s); free(L->c); free(L->rhs_s); free(L->rhs_c);
         free(L->x_s); free(L->x_c); free(L->r_s); free(L->r_c);
@@ -487,13 +607,13 @@ int or_compact_to_grid(const or_hier *H, int l, long *out)
 /* ghost table of level l: ST entries as compact indices (-1 for inactive nodes),
  * weights, boundary points, normals, order, fallback flags */
 int or_ghost_table(const or_hier *H, int l, int *st_compact, double *w, double *B, double *nrm,
-                   int *order, int *bfall)
+                   double *nrow, int *order, int *bfall)
 {
     if (l < 0 || l >= H->nlev) return OR_EINVAL;
     const OLevel *L = &H->L[l];
     int nst = H->nst, dim = H->dim;
     for (long k = 0; k < (long)L->ng * nst; ++k) { st_compact[k] = L->g2c[L->st[k]]; w[k] = L->w[k]; }
-    for (long k = 0; k < (long)L->ng * dim; ++k) { B[k] = L->B[k]; nrm[k] = L->nrm[k]; }
+    for (long k = 0; k < (long)L->ng * dim; ++k) { B[k] = L->B[k]; nrm[k] = L->nrm[k]; nrow[k] = L->nrow[k]; }
     for (int q = 0; q < L->ng; ++q) { order[q] = L->order[q]; bfall[q] = L->bfall[q]; }
     return OR_OK;
 }
@@ -818,7 +938,7 @@ static void smooth_level(or_hier *H, int l)
         double v = 0.0;
         for (int k = 0; k < nst; ++k) v += L->w[(long)q * nst + k] * xs[L->st[(long)q * nst + k]];
         olds[q] = xs[g];
-        news[q] = xs[g] + H->p.tau_s * (L->rhs_s[g] - v);
+        news[q] = xs[g] + tau_level(H, L) * (L->rhs_s[g] - v);
     }
     for (int q = 0; q < ng; ++q) xs[L->c2g[L->ni + q]] = news[q];
     for (int q = 0; q < ng; ++q) {
