@@ -92,12 +92,12 @@ def load_traffic(kernel, workload, precision):
     return None
 
 
-def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label, max_steps=200):
+def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label, max_steps=200, bc=0):
     """The oracle (serial, one core) on the first steps of a domain of the workload,
     for about budget_s seconds; the steps it shares with gpu_states (gpu_states[k] is
     the compact GPU state after step k + 1) give a parity check of the GPU trajectory."""
     import oracle
-    O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=params)
+    O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=params, bc=bc)
     info = O.level_info(0)
     na = info["na"]
     s0, c0 = I.initial_state(n, dim)
@@ -244,7 +244,8 @@ def run_single(args):
 
     w = WORKLOADS[args.workload]
     prec = args.precision if args.precision is not None else 0
-    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec)
+    bc = 1 if args.bc == "neumann" else 0
+    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec, bc=bc)
     phi_np = levelset(w)
     phi = torch.from_numpy(phi_np).cuda()
     torch.cuda.synchronize()
@@ -312,7 +313,7 @@ def run_single(args):
             st2.step(w["dt"])
             states.append(st2.get().cpu().numpy())
         cpu, parity = cpu_baseline(phi_np, w["dim"], w["n"], w["coarsest"], w["dt"], oracle_params(H),
-                                   args.cpu_budget, states, f"{w['kind']} {w['n']}^{w['dim']}")
+                                   args.cpu_budget, states, f"{w['kind']} {w['n']}^{w['dim']}", bc=bc)
 
     lat_ms = np.array(lat) * 1e3
     return {
@@ -329,7 +330,8 @@ def run_single(args):
         "dtype": "f64" if prec == 0 else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}_{'fp64' if prec == 0 else 'mixed'}",
+            "workload": f"{args.workload}_{'fp64' if prec == 0 else 'mixed'}" + ("_neumann" if bc else ""),
+            "boundary": "neumann ds/dn = 1" if bc else "dirichlet s = 1",
             "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": w["dt"], "coarsest": w["coarsest"],
             "unknowns": unknowns, "inside": ni, "ghost": ng, "levels": H.nlev,
             "cycle": f"V({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps "
@@ -586,6 +588,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=None, help="serve: memory budget (default 80%% of free)")
     ap.add_argument("--precision", type=int, default=None, choices=(0, 1),
                     help="0 = FP64, 1 = mixed (default: FP64, batch64: mixed)")
+    ap.add_argument("--bc", default="dirichlet", choices=("dirichlet", "neumann"),
+                    help="star1025 / torus257 / disk65: boundary condition for s (section 3.6 for Neumann)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true", help="batch64: skip the sequential FP64 comparison")
     ap.add_argument("--cpu-budget", type=float, default=20.0)

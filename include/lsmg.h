@@ -77,6 +77,10 @@ typedef struct {
     double lin_rtol;       /* linear solve stops when |J dW - F|_inf <= lin_rtol |F|_inf */
     int cycles_max;        /* V-cycles per linear solve at most */
     double sweeps_lambda;  /* threshold of d dt / h^2 for ghost_sweeps_coarse; 0: 0.3 in 2-D, 0.1 in 3-D */
+    int bc;                /* boundary condition for s, fixed at build: 0 Dirichlet s = s_b (eq. BCs);
+                            * 1 Neumann ds/dn = s_b (section 3.6, eq. BCsN), with the relaxation
+                            * parameter tau_s * 2 sqrt(2) h / 3 per level (eq. CFLcondN; in 3-D
+                            * tau_s * 4 h / (3 sqrt(3))) */
 } lsmg_params;
 
 typedef struct lsmg_hierarchy lsmg_hierarchy;
@@ -94,7 +98,7 @@ typedef struct {
 /* Default parameters: the model data of eq. (dataeq), tau_s = 0.9 (section
  * 3.5.1), V(2,2), automatic ghost sweeps (0, 0, 0), 3 band layers, ghost_c_new = 1,
  * coarsest 5, FP64, newton_tol 1e-10, newton_max 20, lin_rtol 1e-3,
- * cycles_max 30. */
+ * cycles_max 30, Dirichlet boundary. */
 void lsmg_default_params(lsmg_params *p);
 
 /* Build the grid hierarchy of one domain (sections 3.2-3.3, 3.5).
@@ -107,10 +111,17 @@ void lsmg_default_params(lsmg_params *p);
  * order fallback where ST reaches an inactive node, and the constant rule
  * (w = 1 on the ghost) where the ghost's own weight would be negative or B
  * lies outside the stencil) and the tables of the boundary-aware restriction.
+ * With params->bc = 1 the boundary rows are Neumann rows (section 3.6): the
+ * derivative at B of the interpolant of s on ST along the unit gradient of the
+ * interpolant of phi at B (eqs. Neumanntilde, JccN), with the fallbacks
+ * bilinear gradient -> one-sided differences along the inward axes, each taken
+ * only where its nonzero weights sit on active nodes and the ghost's own
+ * weight meets eq. CFLcondN.
  * stream: a hipStream_t (NULL for the null stream); every later call of this
  *   hierarchy runs on it.
  * Errors: LSMG_EINVAL (bad grid or parameters), LSMG_EGEOM (an inside node on
- *   the box edge), LSMG_EOOM, LSMG_EHIP.  *out is NULL on error. */
+ *   the box edge, or a Neumann ghost with no admissible row), LSMG_EOOM,
+ *   LSMG_EHIP.  *out is NULL on error. */
 lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid,
                                  const lsmg_params *params, void *stream, lsmg_hierarchy **out);
 void lsmg_destroy_hierarchy(lsmg_hierarchy *h);
@@ -121,7 +132,8 @@ void lsmg_destroy_hierarchy(lsmg_hierarchy *h);
  * changes.  Synchronises the hierarchy's stream.  Errors: EINVAL. */
 lsmg_status lsmg_set_dt(lsmg_hierarchy *h, double dt);
 
-/* Replace the solver parameters (the model constants and the grid are fixed at build). */
+/* Replace the solver parameters (coarsest_n, band_steps and bc are fixed at
+ * build: EINVAL if they differ). */
 lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params);
 
 /* Parameters in effect (host out), with automatic choices resolved. */
@@ -142,11 +154,14 @@ lsmg_status lsmg_compact_to_grid(lsmg_hierarchy *h, int level, int64_t *d_out);
  * d_st: Ng*nst int32 compact indices of the stencil ST (k = (k_x, k_y[, k_z]) in
  *   {0,1,2}^dim, x fastest, node G - h (m_x k_x, ...)), -1 where inactive;
  * d_w: Ng*nst weights of the boundary row (eq. JssD); d_B: Ng*dim boundary
- * points; d_normal: Ng*dim unit normals; d_order: Ng int32 (2 quadratic,
- * 1 linear, 0 constant); d_bfallback: Ng int32 (1 when B came from the
- * first-order projection instead of bisection).  Any pointer may be NULL. */
+ * points; d_normal: Ng*dim unit normals by central differences (eq. nij);
+ * d_row_normal: Ng*dim normal of the boundary row (d_normal for Dirichlet
+ * rows; for Neumann rows the unit gradient of the interpolated level set at
+ * B, eq. Neumanntilde); d_order: Ng int32 (2 quadratic, 1 linear, 0 constant
+ * or, for Neumann rows, one-sided); d_bfallback: Ng int32 (1 when B came from
+ * the first-order projection instead of bisection).  Any pointer may be NULL. */
 lsmg_status lsmg_ghost_table(lsmg_hierarchy *h, int level, int32_t *d_st, double *d_w, double *d_B,
-                             double *d_normal, int32_t *d_order, int32_t *d_bfallback);
+                             double *d_normal, double *d_row_normal, int32_t *d_order, int32_t *d_bfallback);
 
 /* ---- one Crank-Nicolson step ---------------------------------------------- */
 
@@ -166,7 +181,7 @@ lsmg_status lsmg_state_get_grid(const lsmg_state *st, double *d_s, double *d_c);
  * V-cycles from dW = 0, W <- W - dW, stop when
  * min(|F|_inf, |dW|_inf / |W|_inf) < newton_tol after at least one iteration.
  * d_sb: device, Ng boundary values s_b(B_g, t_{n+1}) in ghost order, or NULL to
- *   use sb_const for every ghost.
+ *   use sb_const for every ghost (Neumann rows: the values of ds/dn at B_g).
  * d_fn, d_fnp1: device compact vectors [f1 | f2] of the source terms of
  *   section 4.1 at t_n and t_{n+1}, or both NULL.
  * stats: host, may be NULL.  Synchronises the stream.

@@ -47,9 +47,20 @@ lsmg_status check_params(const lsmg_params *p)
     if (!(p->tau_s > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->ghost_sweeps < 0 || p->ghost_sweeps_coarse < 0 ||
         !(p->sweeps_lambda >= 0.0) || p->band_steps < 0 ||
         p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
-        !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1))
+        !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1) ||
+        (p->bc != 0 && p->bc != 1))
         return fail(LSMG_EINVAL, "invalid solver parameters");
     return LSMG_OK;
+}
+
+// relaxation parameter of the ghost rows of level l: tau_s for Dirichlet rows
+// (eq. CFLcond); for Neumann rows tau_s times the bound of eq. CFLcondN,
+// 2 sqrt(2) h / 3, in 3-D the same bound over three axes, 4 h / (3 sqrt(3))
+double tau_level(const lsmg_hierarchy *H, int l)
+{
+    const double h = H->L[l].h, t = H->p.tau_s;
+    if (H->p.bc == 0) return t;
+    return H->dim == 2 ? t * (2.0 * std::sqrt(2.0) * h / 3.0) : t * (4.0 * h / (3.0 * std::sqrt(3.0)));
 }
 
 void fill_desc_scalars(lsmg_hierarchy *H)
@@ -65,7 +76,7 @@ void fill_desc_scalars(lsmg_hierarchy *H)
         D.dt_inv = H->dt > 0.0 ? 1.0 / H->dt : 0.0;
         D.ks_half = 0.5 * (p.a / p.m_c);
         D.kc_half = 0.5 * (p.a / p.m_s);
-        D.tau_s = p.tau_s;
+        D.tau_s = tau_level(H, l);
         D.ghost_c_new = p.ghost_c_new;
         if (H->have32) {
             LevelDesc<float> &E = H->hd32[l];
@@ -383,13 +394,14 @@ lsmg_status build_level_arrays(lsmg_hierarchy *H, int l, const double *phi, uint
     LSMGCHK(H->alloc(&Lv.g_w, (long long)ng * nst));
     LSMGCHK(H->alloc(&Lv.g_B, (long long)ng * dim));
     LSMGCHK(H->alloc(&Lv.g_nrm, (long long)ng * dim));
+    LSMGCHK(H->alloc(&Lv.g_nrow, (long long)ng * dim));
     LSMGCHK(H->alloc(&Lv.g_order, ng));
     LSMGCHK(H->alloc(&Lv.g_bfall, ng));
     LSMGCHK(H->zalloc(&Lv.g_buf0, ng));
     LSMGCHK(H->zalloc(&Lv.g_buf1, ng));
-    launch_ghost_geometry(dim, l, phi, Lv.type, Lv.c2g + ni, Lv.cmap, ni, ng, Lv.n, Lv.Wp, Lv.cs, H->lo, Lv.h,
-                          Lv.g_idx, Lv.g_ijk, Lv.g_st, Lv.g_stg, Lv.g_stc, Lv.g_w, Lv.g_B, Lv.g_nrm, Lv.g_order,
-                          Lv.g_bfall, err, H->stream);
+    launch_ghost_geometry(dim, l, H->p.bc, phi, Lv.type, Lv.c2g + ni, Lv.cmap, ni, ng, Lv.n, Lv.Wp, Lv.cs, H->lo,
+                          Lv.h, Lv.g_idx, Lv.g_ijk, Lv.g_st, Lv.g_stg, Lv.g_stc, Lv.g_w, Lv.g_B, Lv.g_nrm, Lv.g_nrow,
+                          Lv.g_order, Lv.g_bfall, err, H->stream);
     launch_ghost_ext(ng, Lv.g_idx, Lv.ext, H->stream);
     // vectors
     LSMGCHK(H->zalloc(&Lv.s, Lv.ssize));
@@ -538,7 +550,7 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     HIPCHK(hipMemcpyAsync(stg.data(), Lv.g_stg, sizeof(int) * stg.size(), hipMemcpyDeviceToHost, H->stream));
     HIPCHK(hipMemcpyAsync(w.data(), Lv.g_w, sizeof(double) * w.size(), hipMemcpyDeviceToHost, H->stream));
     HIPCHK(hipStreamSynchronize(H->stream));
-    const double tau = H->p.tau_s;
+    const double tau = tau_level(H, l);
     std::vector<int> ptr(ng + 1, 0), col;
     std::vector<double> va, vb;
     std::vector<double> cur(ng, 0.0), nxt(ng, 0.0), acc(ng, 0.0);
@@ -766,6 +778,7 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     cleanup();
     if (st != LSMG_OK) return st;
     if (herr & 1) return fail(LSMG_EGEOM, "an inside node lies on the box edge");
+    if (herr & 2) return fail(LSMG_EGEOM, "a ghost has no admissible Neumann row");
     for (int l = 0; l < nlev; ++l) LSMGCHK(build_items(H, l));
     for (int l = 0; l < nlev; ++l) {
         H->L[l].sweeps = level_sweeps(H, l);
@@ -938,6 +951,7 @@ void lsmg_default_params(lsmg_params *p)
     p->newton_max = 20;
     p->lin_rtol = 1e-3;
     p->cycles_max = 30;
+    p->bc = 0;
 }
 
 const char *lsmg_last_error(void) { return g_err.c_str(); }
@@ -981,8 +995,8 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
 {
     if (!h) return fail(LSMG_EINVAL, "hierarchy is NULL");
     LSMGCHK(check_params(params));
-    if (params->coarsest_n != h->p.coarsest_n || params->band_steps != h->p.band_steps)
-        return fail(LSMG_EINVAL, "coarsest_n and band_steps are fixed at build");
+    if (params->coarsest_n != h->p.coarsest_n || params->band_steps != h->p.band_steps || params->bc != h->p.bc)
+        return fail(LSMG_EINVAL, "coarsest_n, band_steps and bc are fixed at build");
     lsmg_params np = *params;
     if (np.ghost_sweeps == 0) np.ghost_sweeps = h->dim == 2 ? 5 : 15;
     if (np.ghost_sweeps_coarse == 0) np.ghost_sweeps_coarse = h->dim == 2 ? 20 : 30;
@@ -1079,7 +1093,7 @@ lsmg_status lsmg_compact_to_grid(lsmg_hierarchy *h, int level, int64_t *d_out)
 }
 
 lsmg_status lsmg_ghost_table(lsmg_hierarchy *h, int level, int32_t *d_st, double *d_w, double *d_B, double *d_normal,
-                             int32_t *d_order, int32_t *d_bfallback)
+                             double *d_row_normal, int32_t *d_order, int32_t *d_bfallback)
 {
     LSMGCHK(level_ok(h, level));
     const Level &Lv = h->L[level];
@@ -1104,6 +1118,9 @@ lsmg_status lsmg_ghost_table(lsmg_hierarchy *h, int level, int32_t *d_st, double
     if (d_B) HIPCHK(hipMemcpyAsync(d_B, Lv.g_B, sizeof(double) * ng * dim, hipMemcpyDeviceToDevice, h->stream));
     if (d_normal)
         HIPCHK(hipMemcpyAsync(d_normal, Lv.g_nrm, sizeof(double) * ng * dim, hipMemcpyDeviceToDevice, h->stream));
+    if (d_row_normal)
+        HIPCHK(hipMemcpyAsync(d_row_normal, Lv.g_nrow, sizeof(double) * ng * dim, hipMemcpyDeviceToDevice,
+                              h->stream));
     if (d_order) HIPCHK(hipMemcpyAsync(d_order, Lv.g_order, sizeof(int) * ng, hipMemcpyDeviceToDevice, h->stream));
     if (d_bfallback)
         HIPCHK(hipMemcpyAsync(d_bfallback, Lv.g_bfall, sizeof(int) * ng, hipMemcpyDeviceToDevice, h->stream));

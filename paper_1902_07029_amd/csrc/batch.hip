@@ -553,7 +553,7 @@ bool same_params(const lsmg_params &a, const lsmg_params &b)
            a.ghost_sweeps_coarse == b.ghost_sweeps_coarse && a.sweeps_lambda == b.sweeps_lambda &&
            a.band_steps == b.band_steps && a.ghost_c_new == b.ghost_c_new && a.coarsest_n == b.coarsest_n &&
            a.precision == b.precision && a.newton_tol == b.newton_tol && a.newton_max == b.newton_max &&
-           a.lin_rtol == b.lin_rtol && a.cycles_max == b.cycles_max;
+           a.lin_rtol == b.lin_rtol && a.cycles_max == b.cycles_max && a.bc == b.bc;
 }
 
 lsmg_status b_build(lsmg_batch *B)

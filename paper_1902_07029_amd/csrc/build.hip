@@ -298,6 +298,101 @@ __device__ __forceinline__ double lag1(int k, double t)
     return 0.0;
 }
 
+// d/dt of the quadratic weights (eq. intcoeffsN times h) and of the linear ones
+__device__ __forceinline__ double dlag2(int k, double t)
+{
+    if (k == 0) return t + 0.5;
+    if (k == 1) return -2.0 * t;
+    return t - 0.5;
+}
+
+__device__ __forceinline__ double dlag1(int k)
+{
+    if (k == 0) return 1.0;
+    if (k == 1) return -1.0;
+    return 0.0;
+}
+
+// Neumann boundary row (section 3.6, eqs. BCsN, Neumanntilde, JccN): the
+// derivative at B of the interpolant of s on ST along nr, the unit gradient at
+// B of the interpolant of phi on ST (the central-difference normal where ST
+// leaves the box, theta is out of range or that gradient vanishes);
+// d/dx_a = (m_a / h) d/dt_a.  Rules in order: quadratic, bilinear gradient on
+// the nodes k in {0,1}^d, one-sided differences s_G - s_{G - m_a e_a} on the
+// axes with nr_a m_a > 0 whose inward neighbour is active.  A rule is taken
+// only where its nonzero weights sit on active nodes and its own weight w_G
+// lies in (0, 2 / tau_max] (eq. CFLcondN).  Returns false if no rule is
+// admissible.  The operations follow the same order as the CPU reference,
+// so that equal inputs give equal rows.
+template <int DIM>
+__device__ bool neumann_row(const double *phi, const uint8_t *type, const long long *stl, const long long *sts,
+                            const bool *oob, bool any_oob, const double *th, bool bad, const int *m,
+                            const double *nrm, double h, double *w, double *nr, int &order)
+{
+    constexpr int NST = DIM == 2 ? 9 : 27;
+    for (int a = 0; a < DIM; ++a) nr[a] = nrm[a];
+    if (!any_oob && !bad) {
+        double gr[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < DIM; ++a) {
+            double v = 0.0;
+            for (int k = 0; k < NST; ++k) {
+                int kk = k;
+                double wk = 1.0;
+                for (int b = 0; b < DIM; ++b) {
+                    wk *= (b == a) ? dlag2(kk % 3, th[b]) : lag2(kk % 3, th[b]);
+                    kk /= 3;
+                }
+                v += wk * phi[stl[k]];
+            }
+            gr[a] = (double)m[a] * v / h;
+        }
+        double g2 = 0.0;
+        for (int a = 0; a < DIM; ++a) g2 += gr[a] * gr[a];
+        if (g2 > 0.0) {
+            const double gl = sqrt(g2);
+            for (int a = 0; a < DIM; ++a) nr[a] = gr[a] / gl;
+        }
+    }
+    const double wmax = DIM == 2 ? 3.0 / (sqrt(2.0) * h) : 3.0 * sqrt(3.0) / (2.0 * h);
+    for (int o = 2; o >= 1 && !bad; --o) {
+        for (int k = 0; k < NST; ++k) {
+            double v = 0.0;
+            for (int a = 0; a < DIM; ++a) {
+                int kk = k;
+                double wk = 1.0;
+                for (int b = 0; b < DIM; ++b) {
+                    const int kb = kk % 3;
+                    if (o == 2) wk *= (b == a) ? dlag2(kb, th[b]) : lag2(kb, th[b]);
+                    else wk *= (b == a) ? dlag1(kb) : lag1(kb, th[b]);
+                    kk /= 3;
+                }
+                v += nr[a] * (double)m[a] * wk / h;
+            }
+            w[k] = v;
+        }
+        bool ok = w[0] > 0.0 && w[0] <= wmax;
+        for (int k = 0; k < NST; ++k)
+            if (w[k] != 0.0 && (oob[k] || type[sts[k]] == kOut)) ok = false;
+        if (ok) {
+            order = o;
+            return true;
+        }
+    }
+    for (int k = 0; k < NST; ++k) w[k] = 0.0;
+    double wg = 0.0;
+    for (int a = 0; a < DIM; ++a) {
+        const int k = a == 0 ? 1 : (a == 1 ? 3 : 9);   // stencil entry of G - m_a e_a
+        const double c = nr[a] * (double)m[a];
+        if (!(c > 0.0) || oob[k] || type[sts[k]] == kOut) continue;
+        w[k] = -c / h;
+        wg += c / h;
+    }
+    order = 0;
+    if (!(wg > 0.0)) return false;
+    w[0] = wg;
+    return true;
+}
+
 template <int DIM>
 __device__ double phi_interp(const double *phi, const long long *stl, const int *gi, const int *m, const double *X,
                              double lo, double h)
@@ -319,13 +414,13 @@ __device__ double phi_interp(const double *phi, const long long *stl, const int 
 }
 
 template <int DIM>
-__global__ void k_ghost_geometry(int level, const double *__restrict__ phi, const uint8_t *__restrict__ type,
+__global__ void k_ghost_geometry(int level, int bc, const double *__restrict__ phi, const uint8_t *__restrict__ type,
                                  const int64_t *__restrict__ c2g_gh, const int *__restrict__ cmap, int ni, int ng, int n,
                                  int Wp, long long cs, double lo, double h, int *__restrict__ g_idx,
                                  int *__restrict__ g_ijk, int *__restrict__ g_st, int *__restrict__ g_stg,
                                  int *__restrict__ g_stc, double *__restrict__ g_w, double *__restrict__ g_B,
-                                 double *__restrict__ g_nrm, int *__restrict__ g_order, int *__restrict__ g_bfall,
-                                 int *__restrict__ err)
+                                 double *__restrict__ g_nrm, double *__restrict__ g_nrow,
+                                 int *__restrict__ g_order, int *__restrict__ g_bfall, int *__restrict__ err)
 {
     constexpr int NST = DIM == 2 ? 9 : 27;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -402,8 +497,11 @@ __global__ void k_ghost_geometry(int level, const double *__restrict__ phi, cons
     // theta outside [-1, 2] (B from the first-order projection far from G, e.g. at a
     // crease of the level set): the constant rule below, on every level
     double w[NST];
+    double nr[3] = {nrm[0], nrm[1], nrm[2]};
     int order = 2;
-    if (!bad) {
+    if (bc == 1) {
+        if (!neumann_row<DIM>(phi, type, stl, sts, oob, any_oob, th, bad, m, nrm, h, w, nr, order)) atomicOr(err, 2);
+    } else if (!bad) {
         for (int k = 0; k < NST; ++k) {
             int kk = k;
             double wk = 1.0;
@@ -431,11 +529,13 @@ __global__ void k_ghost_geometry(int level, const double *__restrict__ phi, cons
     } else {
         order = 0;
     }
-    // a negative weight of the ghost itself (theta outside [0, 1] on an axis)
-    // cannot meet eq. CFLcond with 0 < tau < 1: the row takes the constant rule
-    if (w[0] < 0.0) order = 0;
-    if (order == 0)
-        for (int k = 0; k < NST; ++k) w[k] = k == 0 ? 1.0 : 0.0;
+    if (bc != 1) {
+        // a negative weight of the ghost itself (theta outside [0, 1] on an axis)
+        // cannot meet eq. CFLcond with 0 < tau < 1: the row takes the constant rule
+        if (!bad && w[0] < 0.0) order = 0;
+        if (order == 0)
+            for (int k = 0; k < NST; ++k) w[k] = k == 0 ? 1.0 : 0.0;
+    }
     g_idx[q] = (int)gs;
     g_ijk[q] = gi[0] | (gi[1] << 11) | (gi[2] << 22);
     for (int k = 0; k < NST; ++k) {
@@ -450,6 +550,7 @@ __global__ void k_ghost_geometry(int level, const double *__restrict__ phi, cons
     for (int a = 0; a < DIM; ++a) {
         g_B[q * DIM + a] = Bp[a];
         g_nrm[q * DIM + a] = nrm[a];
+        g_nrow[q * DIM + a] = nr[a];
     }
     g_order[q] = order;
     g_bfall[q] = bfall;
@@ -627,20 +728,20 @@ void launch_c2s(int dim, const int64_t *c2g, int na, int n, int Wp, long long cs
     if (na > 0) k_c2s<<<blocks(na), 256, 0, s>>>(dim, c2g, na, n, Wp, cs, c2s, cmap);
 }
 
-void launch_ghost_geometry(int dim, int level, const double *phi, const uint8_t *type, const int64_t *c2g_gh,
+void launch_ghost_geometry(int dim, int level, int bc, const double *phi, const uint8_t *type, const int64_t *c2g_gh,
                            const int *cmap, int ni, int ng, int n, int Wp, long long cs, double lo, double h, int *g_idx,
                            int *g_ijk, int *g_st, int *g_stg, int *g_stc, double *g_w, double *g_B, double *g_nrm,
-                           int *g_order, int *g_bfall, int *err, hipStream_t s)
+                           double *g_nrow, int *g_order, int *g_bfall, int *err, hipStream_t s)
 {
     if (ng <= 0) return;
     if (dim == 2)
-        k_ghost_geometry<2><<<blocks(ng, 64), 64, 0, s>>>(level, phi, type, c2g_gh, cmap, ni, ng, n, Wp, cs, lo, h,
-                                                          g_idx, g_ijk, g_st, g_stg, g_stc, g_w, g_B, g_nrm, g_order,
-                                                          g_bfall, err);
+        k_ghost_geometry<2><<<blocks(ng, 64), 64, 0, s>>>(level, bc, phi, type, c2g_gh, cmap, ni, ng, n, Wp, cs, lo, h,
+                                                          g_idx, g_ijk, g_st, g_stg, g_stc, g_w, g_B, g_nrm, g_nrow,
+                                                          g_order, g_bfall, err);
     else
-        k_ghost_geometry<3><<<blocks(ng, 64), 64, 0, s>>>(level, phi, type, c2g_gh, cmap, ni, ng, n, Wp, cs, lo, h,
-                                                          g_idx, g_ijk, g_st, g_stg, g_stc, g_w, g_B, g_nrm, g_order,
-                                                          g_bfall, err);
+        k_ghost_geometry<3><<<blocks(ng, 64), 64, 0, s>>>(level, bc, phi, type, c2g_gh, cmap, ni, ng, n, Wp, cs, lo, h,
+                                                          g_idx, g_ijk, g_st, g_stg, g_stc, g_w, g_B, g_nrm, g_nrow,
+                                                          g_order, g_bfall, err);
 }
 
 void launch_band_mark(int dim, const int64_t *c2g_cg, int ngc, int nc, const uint8_t *ftype, int nf, int fWp,

@@ -41,7 +41,7 @@ struct Level {
            *r_s = nullptr, *r_c = nullptr;
     int *g_idx = nullptr, *g_ijk = nullptr, *g_st = nullptr, *g_stg = nullptr, *g_stc = nullptr, *g_order = nullptr,
         *g_bfall = nullptr;
-    double *g_w = nullptr, *g_B = nullptr, *g_nrm = nullptr, *g_buf0 = nullptr, *g_buf1 = nullptr;
+    double *g_w = nullptr, *g_B = nullptr, *g_nrm = nullptr, *g_nrow = nullptr, *g_buf0 = nullptr, *g_buf1 = nullptr;
     int *b_idx = nullptr, *b_cnt = nullptr, *b_src = nullptr;
     double *b_wt = nullptr;
     float *s32 = nullptr, *c32 = nullptr, *rhs_s32 = nullptr, *rhs_c32 = nullptr, *x_s32 = nullptr, *x_c32 = nullptr,

@@ -123,10 +123,11 @@ void build_segments(int dim, const uint8_t *type_split, int n, int Wp, long long
 // packed coordinates of the inside nodes of each colour (out: ni ints, colour 0 then 1)
 int build_inside_lists(int dim, const int64_t *c2g, int ni, int n, int *out, int *count, int64_t *scratch,
                        int nscratch, hipStream_t s);
-void launch_ghost_geometry(int dim, int level, const double *phi, const uint8_t *type_split, const int64_t *c2g_ghost,
-                           const int *cmap, int ni, int ng, int n, int Wp, long long cs, double lo, double h, int *g_idx,
-                           int *g_ijk, int *g_st, int *g_stg, int *g_stc, double *g_w, double *g_B, double *g_nrm,
-                           int *g_order, int *g_bfall, int *err, hipStream_t s);
+void launch_ghost_geometry(int dim, int level, int bc, const double *phi, const uint8_t *type_split,
+                           const int64_t *c2g_ghost, const int *cmap, int ni, int ng, int n, int Wp, long long cs,
+                           double lo, double h, int *g_idx, int *g_ijk, int *g_st, int *g_stg, int *g_stc, double *g_w,
+                           double *g_B, double *g_nrm, double *g_nrow, int *g_order, int *g_bfall, int *err,
+                           hipStream_t s);
 void launch_band_mark(int dim, const int64_t *c2g_cghost, int ngc, int nc, const uint8_t *ftype_split, int nf, int fWp,
                       long long fcs, uint8_t *flag_lin, hipStream_t s);
 void launch_band_geometry(int dim, const double *phi, const int64_t *band_lin, int nb, const uint8_t *type_split,

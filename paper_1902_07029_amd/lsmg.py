@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
                 ("band_steps", ctypes.c_int), ("ghost_c_new", ctypes.c_int),
                 ("coarsest_n", ctypes.c_int), ("precision", ctypes.c_int), ("newton_tol", ctypes.c_double),
                 ("newton_max", ctypes.c_int), ("lin_rtol", ctypes.c_double), ("cycles_max", ctypes.c_int),
-                ("sweeps_lambda", ctypes.c_double)]
+                ("sweeps_lambda", ctypes.c_double), ("bc", ctypes.c_int)]
 
 
 class StepStats(ctypes.Structure):
@@ -72,7 +72,7 @@ def load():
         "lsmg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_i),
                                  ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "lsmg_compact_to_grid": (_i, [_vp, _i, _vp]),
-        "lsmg_ghost_table": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "lsmg_ghost_table": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "lsmg_state_create": (_i, [_vp, ctypes.POINTER(_vp)]),
         "lsmg_state_destroy": (None, [_vp]),
         "lsmg_state_set": (_i, [_vp, _vp]),
@@ -225,11 +225,12 @@ class Hierarchy:
         w = torch.empty((ng, nst), dtype=torch.float64, device="cuda")
         B = torch.empty((ng, dim), dtype=torch.float64, device="cuda")
         nrm = torch.empty((ng, dim), dtype=torch.float64, device="cuda")
+        nrow = torch.empty((ng, dim), dtype=torch.float64, device="cuda")
         order = torch.empty(ng, dtype=torch.int32, device="cuda")
         bf = torch.empty(ng, dtype=torch.int32, device="cuda")
-        _check(load().lsmg_ghost_table(self._h, l, _ptr(st), _ptr(w), _ptr(B), _ptr(nrm), _ptr(order), _ptr(bf)),
-               "lsmg_ghost_table")
-        return dict(st=st, w=w, B=B, normal=nrm, order=order, bfallback=bf)
+        _check(load().lsmg_ghost_table(self._h, l, _ptr(st), _ptr(w), _ptr(B), _ptr(nrm), _ptr(nrow), _ptr(order),
+                                       _ptr(bf)), "lsmg_ghost_table")
+        return dict(st=st, w=w, B=B, normal=nrm, row_normal=nrow, order=order, bfallback=bf)
 
     def residual(self, W, Wn, dt, sb=None, sb_const=1.0, fn=None, fnp1=None):
         F = torch.empty_like(W)

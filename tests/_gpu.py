@@ -23,7 +23,7 @@ def pair(kind, n, coarsest, phi=None, **params):
         phi = LEVELSETS[kind](n)
     p = lsmg.default_params(coarsest_n=coarsest, **params)
     H = lsmg.Hierarchy(torch.from_numpy(phi), dim, n, params=p)
-    O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=oracle_params(H.params))
+    O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=oracle_params(H.params), bc=H.params.bc)
     return H, O
 
 

@@ -1,0 +1,154 @@
+"""Neumann boundary rows (section 3.6) on the GPU against the oracle: the hierarchy
+(orders, stencils and fallback flags bit-exact; weights, boundary points and both
+normals to rounding), whole Crank-Nicolson steps to 1e-10 per step in FP64 and mixed
+precision in 2-D and 3-D, the manufactured solution with Neumann data, and a batch of
+Neumann domains bitwise equal to the same domains stepped alone."""
+import numpy as np
+import pytest
+import torch
+
+import lsmg_inputs as I
+from _gpu import cuda, host, pair, rel, say
+from paper_1902_07029_amd import lsmg
+
+TOL = 1e-10
+GEOMETRY = [("disk", 65, 5), ("star", 257, 9), ("star", 1025, 9), ("torus", 65, 9), ("torus", 257, 9)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind,n,coarsest", GEOMETRY)
+def test_neumann_hierarchy_matches_oracle(kind, n, coarsest):
+    say(f"neumann geometry {kind} n={n}")
+    H, O = pair(kind, n, coarsest, bc=1)
+    assert H.nlev == O.nlev
+    orders = np.zeros(3, dtype=int)
+    for l in range(H.nlev):
+        gi, oi = H.level_info(l), O.level_info(l)
+        assert (gi["ni"], gi["ng"], gi["nb"]) == (oi["ni"], oi["ng"], oi["nb"]), l
+        if gi["ng"] == 0:
+            continue
+        G = {k: host(v) for k, v in H.ghost_table(l).items()}
+        R = O.ghost_table(l)
+        assert np.array_equal(G["order"], R["order"]), l
+        assert np.array_equal(G["bfallback"], R["bfallback"]), l
+        assert np.array_equal(G["st"], R["st"]), l
+        h = gi["h"]
+        # Neumann weights scale as 1/h
+        assert np.max(np.abs(G["w"] - R["w"])) * h <= 1e-13, l
+        assert np.max(np.abs(G["B"] - R["B"])) <= 1e-14, l
+        assert np.max(np.abs(G["normal"] - R["normal"])) <= 1e-15, l
+        assert np.max(np.abs(G["row_normal"] - R["row_normal"])) <= 1e-13, l
+        orders += np.bincount(G["order"], minlength=3)
+    say(f"  rows by order (0, 1, 2) over all levels: {orders.tolist()}")
+
+
+def _run(kind, n, coarsest, dt, steps, precision=0, flux=1.0):
+    H, O = pair(kind, n, coarsest, precision=precision, bc=1)
+    info = O.level_info(0)
+    na = info["na"]
+    s, c = I.initial_state(n, H.dim)
+    W = O.to_compact(0, s, c)
+    st = lsmg.State(H)
+    st.set(cuda(W))
+    sb = np.full(info["ng"], flux)
+    for k in range(steps):
+        rc, gstats = st.step(dt, sb_const=flux)
+        orc, W, ostats = O.newton_cn_step(W, dt, sb)
+        assert orc == 0
+        G = host(st.get())
+        es, ec = rel(G[:na], W[:na]), rel(G[na:], W[na:])
+        say(f"neumann {kind} n={n} prec={precision} step {k}: err s {es:.2e} c {ec:.2e} "
+            f"newton {gstats['newton_iters']}/{ostats['newton_iters']} cycles {gstats['vcycles']}/{ostats['vcycles']}")
+        assert es <= TOL and ec <= TOL, (k, es, ec)
+    assert np.max(W[:na]) > 0.0   # the boundary flux has entered
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_neumann_star_257(precision):
+    _run("star", 257, 9, 1e-4, 3, precision)
+
+
+@pytest.mark.gpu
+def test_neumann_star_1025_full_size():
+    _run("star", 1025, 9, 1e-4, 1, 0)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_neumann_torus_65(precision):
+    _run("torus", 65, 9, 1e-4, 2, precision)
+
+
+@pytest.mark.gpu
+def test_neumann_manufactured_solution_steps():
+    n = 65
+    H, O = pair("disk", n, 5, bc=1)
+    info = O.level_info(0)
+    na, h = info["na"], info["h"]
+    x, y = I.grid_points(n, 2)
+    g = O.compact_to_grid(0)
+    gt = O.ghost_table(0)
+    B, nr = gt["B"], gt["row_normal"]
+    W = np.concatenate([I.s_exact(x[g], y[g], 0.0), I.c_exact(x[g], y[g], 0.0)])
+    st = lsmg.State(H)
+    st.set(cuda(W))
+
+    def forcing(t):
+        return np.concatenate(I.mms_sources(x[g], y[g], t))
+
+    for k in range(4):
+        t0, t1 = k * h, (k + 1) * h
+        gx, gy = I.s_exact_grad(B[:, 0], B[:, 1], t1)
+        sb = gx * nr[:, 0] + gy * nr[:, 1]
+        st.step(h, sb=cuda(sb), fn=cuda(forcing(t0)), fnp1=cuda(forcing(t1)))
+        rc, W, _ = O.newton_cn_step(W, h, sb, forcing(t0), forcing(t1))
+        assert rc == 0
+        G = host(st.get())
+        es, ec = rel(G[:na], W[:na]), rel(G[na:], W[na:])
+        say(f"neumann manufactured step {k}: err s {es:.2e} c {ec:.2e}")
+        assert es <= TOL and ec <= TOL
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [1, 0])
+def test_neumann_batch_bitwise_alone(precision):
+    shapes = [dict(n=129, a=0.45, b=0.1, k=4, p=0.3), dict(n=257, a=0.5, b=0.15, k=5, p=0.0),
+              dict(n=65, a=0.55, b=0.08, k=3, p=1.0)]
+
+    def hier(d):
+        p = lsmg.default_params(coarsest_n=9, precision=precision, bc=1)
+        phi = I.star(d["n"], d["a"], d["b"], d["k"], d["p"])
+        return lsmg.Hierarchy(torch.from_numpy(phi), 2, d["n"], params=p)
+
+    def state(H, d):
+        st = lsmg.State(H)
+        s, c = I.initial_state(d["n"], 2)
+        st.set_grid(cuda(s), cuda(c))
+        return st
+
+    alone = [hier(d) for d in shapes]
+    members = [hier(d) for d in shapes]
+    sa = [state(H, d) for H, d in zip(alone, shapes)]
+    sb = [state(H, d) for H, d in zip(members, shapes)]
+    B = lsmg.Batch(members)
+    for k in range(2):
+        ref = [st.step(1e-4, sb_const=0.5)[1] for st in sa]
+        status, stats = B.step(sb, 1e-4, sb_const=[0.5] * len(shapes))
+        assert all(s == lsmg.OK for s in status)
+        for m in range(len(shapes)):
+            assert torch.equal(sa[m].get(), sb[m].get()), (k, m)
+            assert stats[m]["vcycles"] == ref[m]["vcycles"]
+        say(f"neumann batch prec {precision} step {k}: members bitwise equal to alone, "
+            f"cycles {[s['vcycles'] for s in stats]}")
+
+
+@pytest.mark.gpu
+def test_bc_is_fixed_at_build():
+    H, _ = pair("disk", 33, 5, bc=1)
+    p = lsmg.default_params(coarsest_n=5, bc=0)
+    with pytest.raises(lsmg.LsmgError) as e:
+        H.set_params(p)
+    assert e.value.code == lsmg.EINVAL
+    with pytest.raises(lsmg.LsmgError):
+        lsmg.Batch([H, pair("disk", 33, 5)[0]])
