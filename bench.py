@@ -45,11 +45,24 @@ WORKLOADS = {
     "star1025": dict(kind="star", dim=2, n=1025, coarsest=9, dt=1e-4, steps=100),
     "torus257": dict(kind="torus", dim=3, n=257, coarsest=9, dt=1e-4, steps=20),
     "disk65": dict(kind="disk", dim=2, n=65, coarsest=5, dt=1e-3, steps=10),
+    # the paper's own efficiency test (section 4.2, Test 3): circle, s0 = 0, c0 = 10,
+    # s_B = 1, dt = h, N = 256, W(2,1), 8 x 8 coarsest grid; box [-pi/2, pi/2]^2
+    "paper3": dict(kind="paper_circle", dim=2, n=257, coarsest=9, dt=None, steps=20, box=I.PAPER_BOX, c0=10.0,
+                   params=dict(nu1=2, nu2=1, cycle_gamma=2)),
 }
 
 
 def levelset(w):
-    return {"star": I.star, "torus": I.torus, "disk": I.disk}[w["kind"]](w["n"])
+    return {"star": I.star, "torus": I.torus, "disk": I.disk, "paper_circle": I.paper_circle}[w["kind"]](w["n"])
+
+
+def box_of(w):
+    return w.get("box", (-1.0, 1.0))
+
+
+def dt_of(w):
+    lo, hi = box_of(w)
+    return w["dt"] if w["dt"] is not None else (hi - lo) / (w["n"] - 1)
 
 
 def smoother_bytes(c2g, ni, ng, n, dim, P):
@@ -92,16 +105,17 @@ def load_traffic(kernel, workload, precision):
     return None
 
 
-def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label, max_steps=200, bc=0):
+def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label, max_steps=200, bc=0,
+                 box=(-1.0, 1.0), c0=1.0):
     """The oracle (serial, one core) on the first steps of a domain of the workload,
     for about budget_s seconds; the steps it shares with gpu_states (gpu_states[k] is
     the compact GPU state after step k + 1) give a parity check of the GPU trajectory."""
     import oracle
-    O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=params, bc=bc)
+    O = oracle.Hierarchy(phi, dim, n, *box, coarsest_n=coarsest, params=params, bc=bc)
     info = O.level_info(0)
     na = info["na"]
-    s0, c0 = I.initial_state(n, dim)
-    W = O.to_compact(0, s0, c0)
+    s0, cc0 = I.initial_state(n, dim, 0.0, c0)
+    W = O.to_compact(0, s0, cc0)
     sb = np.ones(info["ng"])
     cycles = 0
     worst = 0.0
@@ -130,7 +144,7 @@ def oracle_params(H):
     eff = H.params
     return {k: getattr(eff, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
                                          "ghost_c_new", "band_steps", "ghost_sweeps", "ghost_sweeps_coarse",
-                                         "sweeps_lambda")}
+                                         "sweeps_lambda")} | {"gamma": eff.cycle_gamma}
 
 
 # ---------------------------------------------------------------- profiling helpers
@@ -245,18 +259,20 @@ def run_single(args):
     w = WORKLOADS[args.workload]
     prec = args.precision if args.precision is not None else 0
     bc = 1 if args.bc == "neumann" else 0
-    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec, bc=bc)
+    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec, bc=bc, **w.get("params", {}))
     phi_np = levelset(w)
+    lo, hi = box_of(w)
+    dt = dt_of(w)
     phi = torch.from_numpy(phi_np).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    H = lsmg.Hierarchy(phi, w["dim"], w["n"], params=params)
+    H = lsmg.Hierarchy(phi, w["dim"], w["n"], lo, hi, params=params)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     info = H.level_info(0)
     na, ni, ng = info["na"], info["ni"], info["ng"]
     unknowns = 2 * na
-    s0, c0 = I.initial_state(w["n"], w["dim"])
+    s0, c0 = I.initial_state(w["n"], w["dim"], 0.0, w.get("c0", 1.0))
 
     def fresh_state():
         st = lsmg.State(H)
@@ -265,19 +281,21 @@ def run_single(args):
 
     st = fresh_state()
     for _ in range(args.warmup):
-        st.step(w["dt"])
+        st.step(dt)
     # timed region: K steps (V-cycles replayed as captured graphs)
     lat = []
+    rho = []
     cycles = 0
     newton = 0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        _, stats = st.step(w["dt"])
+        _, stats = st.step(dt)
         lat.append(time.perf_counter() - ts)
         cycles += stats["vcycles"]
         newton += stats["newton_iters"]
+        rho.append((stats["rho_geo"], stats["rho_last"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     # kernel timing pass: the next K steps of the same run, every finest-level
@@ -285,7 +303,7 @@ def run_single(args):
     H.profile_start(lsmg.KERNEL_SMOOTH, 0)
     prof_t0 = time.perf_counter()
     for _ in range(args.steps):
-        st.step(w["dt"])
+        st.step(dt)
     torch.cuda.synchronize()
     prof_elapsed = time.perf_counter() - prof_t0
     launches, prof_ms = H.profile_stop()
@@ -310,10 +328,11 @@ def run_single(args):
         st2 = fresh_state()
         states = []
         for _ in range(args.parity_steps):
-            st2.step(w["dt"])
+            st2.step(dt)
             states.append(st2.get().cpu().numpy())
-        cpu, parity = cpu_baseline(phi_np, w["dim"], w["n"], w["coarsest"], w["dt"], oracle_params(H),
-                                   args.cpu_budget, states, f"{w['kind']} {w['n']}^{w['dim']}", bc=bc)
+        cpu, parity = cpu_baseline(phi_np, w["dim"], w["n"], w["coarsest"], dt, oracle_params(H),
+                                   args.cpu_budget, states, f"{w['kind']} {w['n']}^{w['dim']}", bc=bc,
+                                   box=(lo, hi), c0=w.get("c0", 1.0))
 
     lat_ms = np.array(lat) * 1e3
     return {
@@ -332,14 +351,19 @@ def run_single(args):
         "config": {
             "workload": f"{args.workload}_{'fp64' if prec == 0 else 'mixed'}" + ("_neumann" if bc else ""),
             "boundary": "neumann ds/dn = 1" if bc else "dirichlet s = 1",
-            "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": w["dt"], "coarsest": w["coarsest"],
+            "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": dt, "coarsest": w["coarsest"],
+            "box": [lo, hi], "c0": w.get("c0", 1.0),
             "unknowns": unknowns, "inside": ni, "ghost": ng, "levels": H.nlev,
-            "cycle": f"V({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps "
+            "cycle": f"{'VW'[H.params.cycle_gamma - 1]}({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps "
                      f"({H.params.ghost_sweeps_coarse} where d dt/h^2 < {H.params.sweeps_lambda})",
             "build_ms": round(build_ms, 1),
         },
         "vcycles": cycles,
         "newton_iters": newton,
+        # per step: geometric mean of all its convergence factors (the first cycle of each
+        # Newton system included) and the factor of its last cycle
+        "rho_geo_median": float(np.median([r[0] for r in rho])),
+        "rho_last_median": float(np.median([r[1] for r in rho])),
         "solution_throughput": unknowns * args.steps / elapsed,
         "p50_step_ms": float(np.percentile(lat_ms, 50)),
         "p99_step_ms": float(np.percentile(lat_ms, 99)),
@@ -580,7 +604,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS) + ["batch64", "serve"])
+    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS) + ["batch64", "serve"],
+                    help="paper3: the paper's Test 3 with its W(2,1) cycle (section 4.2)")
     ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
     ap.add_argument("--load", type=float, default=2.0,
                     help="serve: arrival rate as a multiple of the sequential FP64 request rate")

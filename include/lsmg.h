@@ -81,6 +81,9 @@ typedef struct {
                             * 1 Neumann ds/dn = s_b (section 3.6, eq. BCsN), with the relaxation
                             * parameter tau_s * 2 sqrt(2) h / 3 per level (eq. CFLcondN; in 3-D
                             * tau_s * 4 h / (3 sqrt(3))) */
+    int cycle_gamma;       /* cycle index: 1 V-cycle, 2 W-cycle (the paper's cycle, section 4: the
+                            * coarse-grid correction is two cycles on the next level, the second
+                            * starting from the first one's result); batches take 1 only */
 } lsmg_params;
 
 typedef struct lsmg_hierarchy lsmg_hierarchy;
@@ -98,7 +101,7 @@ typedef struct {
 /* Default parameters: the model data of eq. (dataeq), tau_s = 0.9 (section
  * 3.5.1), V(2,2), automatic ghost sweeps (0, 0, 0), 3 band layers, ghost_c_new = 1,
  * coarsest 5, FP64, newton_tol 1e-10, newton_max 20, lin_rtol 1e-3,
- * cycles_max 30, Dirichlet boundary. */
+ * cycles_max 30, Dirichlet boundary, V-cycles. */
 void lsmg_default_params(lsmg_params *p);
 
 /* Build the grid hierarchy of one domain (sections 3.2-3.3, 3.5).

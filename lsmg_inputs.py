@@ -38,6 +38,27 @@ def disk(n, r=0.4, x0=0.0, y0=0.0):
     return np.sqrt((x - x0) ** 2 + (y - y0) ** 2) - r
 
 
+# The paper's Tests 3 and 4 (section 4.2): the box is not printed; [-pi/2, pi/2]^2
+# is the reading used here, the smallest symmetric box of this family holding
+# both domains (circle radius 1.486, square-with-discs extent 1.2567).
+PAPER_BOX = (-math.pi / 2, math.pi / 2)
+
+
+def paper_circle(n, lo=PAPER_BOX[0], hi=PAPER_BOX[1]):
+    """eq. (test13): circle of radius 1.486 centred at (sqrt(2)/30, sqrt(3)/40)."""
+    x, y = grid_points(n, 2, lo, hi)
+    return np.sqrt((x - math.sqrt(2) / 30) ** 2 + (y - math.sqrt(3) / 40) ** 2) - 1.486
+
+
+def paper_square(n, lo=PAPER_BOX[0], hi=PAPER_BOX[1], L=0.9567, D=0.3):
+    """eq. (test24): union of the square max(|x|, |y|) < L and four discs of radius D
+    centred on its vertices."""
+    x, y = grid_points(n, 2, lo, hi)
+    p1 = np.maximum(np.abs(x), np.abs(y)) - L
+    p2 = np.sqrt((np.abs(x) - L) ** 2 + (np.abs(y) - L) ** 2) - D
+    return np.minimum(p1, p2)
+
+
 def star(n, a=0.5, b=0.15, k=5, p=0.0):
     x, y = grid_points(n, 2)
     r = np.sqrt(x * x + y * y)

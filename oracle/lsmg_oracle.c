@@ -70,6 +70,9 @@ typedef struct {
      * d dt / h^2 is below sweeps_lambda use ghost_sweeps_coarse */
     int ghost_sweeps_coarse;
     double sweeps_lambda;
+    int gamma;         /* cycle index: 1 V-cycle, 2 W-cycle (the paper's cycle, §4) */
+    int lex;           /* 1: inside nodes relaxed in lexicographic order (the paper's
+                          collective Gauss-Seidel, §3.5.1); 0: red-black */
 } OPar;
 
 typedef struct or_hier {
@@ -525,6 +528,7 @@ int or_build(const double *phi, int dim, int n, double lo, double hi, int coarse
     H->p.alpha = 0.01; H->p.beta = 0.1; H->p.tau_s = 0.9;
     H->p.nu1 = 2; H->p.nu2 = 2; H->p.ghost_c_new = 1; H->p.band_steps = 3; H->p.ghost_sweeps = 1;
     H->p.ghost_sweeps_coarse = 1; H->p.sweeps_lambda = 0.3;
+    H->p.gamma = 1; H->p.lex = 0;
     nl = n;
     for (int l = 0; l < nlev; ++l) {
         OLevel *L = &H->L[l];
@@ -577,8 +581,11 @@ void or_free(or_hier *H)
 
 int or_set_params(or_hier *H, double a, double d, double m_s, double m_c, double alpha, double beta,
                   double tau_s, int nu1, int nu2, int ghost_c_new, int band_steps, int ghost_sweeps,
-                  int ghost_sweeps_coarse, double sweeps_lambda)
+                  int ghost_sweeps_coarse, double sweeps_lambda, int gamma, int lex)
 {
+    if (gamma < 1 || gamma > 2 || lex < 0 || lex > 1) return OR_EINVAL;
+    H->p.gamma = gamma;
+    H->p.lex = lex;
     H->p.ghost_sweeps = ghost_sweeps;
     H->p.ghost_sweeps_coarse = ghost_sweeps_coarse;
     H->p.sweeps_lambda = sweeps_lambda;
@@ -902,19 +909,21 @@ static int level_sweeps(const or_hier *H, const OLevel *L)
 }
 
 /* one smoothing step on level l (§3.5.1): collective Gauss-Seidel on the
- * inside nodes in red-black order (2x2 block solve with P of eq. matrixP),
- * then the ghost relaxation of eq. RelGhost on all ghosts at once. */
+ * inside nodes in red-black order, or in the lexicographic order of the map
+ * (eq. maprij) with lex = 1 (2x2 block solve with P of eq. matrixP), then the
+ * ghost relaxation of eq. RelGhost on all ghosts at once. */
 static void smooth_level(or_hier *H, int l)
 {
     OLevel *L = &H->L[l];
     int nd = 2 * H->dim, dim = H->dim;
     double *xs = L->x_s, *xc = L->x_c;
-    for (int colour = 0; colour < 2; ++colour) {
+    const int passes = H->p.lex ? 1 : 2;
+    for (int colour = 0; colour < passes; ++colour) {
         for (int r = 0; r < L->ni; ++r) {
             long g = L->c2g[r];
             int gi[3];
             unravel(g, L->n, dim, gi);
-            if (((gi[0] + gi[1] + gi[2]) & 1) != colour) continue;
+            if (!H->p.lex && ((gi[0] + gi[1] + gi[2]) & 1) != colour) continue;
             JRow J;
             jrow_inside(H, L, g, &J);
             double rs = L->rhs_s[g] - (J.ss_d * xs[g] + J.sc_d * xc[g]);
@@ -1117,7 +1126,9 @@ static void coarse_solve_level(or_hier *H)
     free(b);
 }
 
-/* one V(nu1, nu2) cycle on level l with the level's rhs and x (§3.5) */
+/* one V(nu1, nu2) cycle (gamma = 1) or W(nu1, nu2) cycle (gamma = 2: the
+ * coarse-grid correction is two cycles on the next level, the second from the
+ * first one's result) on level l with the level's rhs and x (§3.5, §4) */
 static void vcycle_rec(or_hier *H, int l)
 {
     if (l == H->nlev - 1) { coarse_solve_level(H); return; }
@@ -1129,7 +1140,7 @@ static void vcycle_rec(or_hier *H, int l)
     restrict_level(H, l, ext);
     free(ext);
     for (long g = 0; g < C->nn; ++g) { C->x_s[g] = 0.0; C->x_c[g] = 0.0; }
-    vcycle_rec(H, l + 1);
+    for (int i = 0; i < H->p.gamma; ++i) vcycle_rec(H, l + 1);
     prolong_add_level(H, l);
     for (int i = 0; i < H->p.nu2; ++i) smooth_level(H, l);
 }

@@ -48,7 +48,7 @@ lsmg_status check_params(const lsmg_params *p)
         !(p->sweeps_lambda >= 0.0) || p->band_steps < 0 ||
         p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
         !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1) ||
-        (p->bc != 0 && p->bc != 1))
+        (p->bc != 0 && p->bc != 1) || p->cycle_gamma < 1 || p->cycle_gamma > 2)
         return fail(LSMG_EINVAL, "invalid solver parameters");
     return LSMG_OK;
 }
@@ -251,6 +251,7 @@ TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
     a.nlev = H->nlev;
     a.nu1 = H->p.nu1;
     a.nu2 = H->p.nu2;
+    a.gamma = H->p.cycle_gamma;
     a.c2s = H->L[H->nlev - 1].c2s;
     a.ainv = H->ainv;
     int off = 0;
@@ -283,7 +284,10 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
     launch_band<T>(d, Lv.w_band(), Lv.nbandc, Exec(s));
     const Level &C = H->L[l + 1];
     launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), prof_exec(H, s, LSMG_KERNEL_RESTRICT, l + 1));
-    vcycle_rec<T>(H, l + 1, s);
+    // W-cycle: a second cycle on the next level from the first one's result; the
+    // coarsest solve is exact, so it is not repeated
+    const int reps = l + 1 == H->nlev - 1 ? 1 : H->p.cycle_gamma;
+    for (int i = 0; i < reps; ++i) vcycle_rec<T>(H, l + 1, s);
     launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), prof_exec(H, s, LSMG_KERNEL_PROLONG, l));
     for (int i = 0; i < H->p.nu2; ++i) smooth_level<T>(H, l, s);
 }
@@ -952,6 +956,7 @@ void lsmg_default_params(lsmg_params *p)
     p->lin_rtol = 1e-3;
     p->cycles_max = 30;
     p->bc = 0;
+    p->cycle_gamma = 1;
 }
 
 const char *lsmg_last_error(void) { return g_err.c_str(); }
@@ -1012,6 +1017,8 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
     }
     h->p = np;
     LSMGCHK(update_sweeps(h, ghost_ops_change));
+    // the coarse tails read nu1, nu2 and the cycle index from their arguments
+    LSMGCHK(upload_tail_args(h));
     make_descs(h);
     return push_desc(h);
 }

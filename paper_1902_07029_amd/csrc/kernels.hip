@@ -888,39 +888,63 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
         }
         __syncthreads();
     }
-    for (int l = A.l0; l < L - 1; ++l) {
-        const LevelDesc<T> *D = base + l;
-        const TailLevel &TL = A.lev[l];
-        for (int it = 0; it < A.nu1; ++it) wg_smooth<T, DIM, NST, STAGE>(D, TL, S);
-        const int nin = TL.nin0 + TL.nin1;
-        for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
-            if (t < nin) {
+    // cycle(l): pre-smoothing, defect, band, restriction to l + 1 (which clears
+    // the coarse correction), gamma cycles on l + 1 (the second one from the
+    // first one's result; the coarsest solve is exact and runs once),
+    // prolongation, post-smoothing.  Walked without recursion: `done` holds, per
+    // level p, whether one child cycle of p has finished.  Every thread takes the
+    // same path.
+    int l = A.l0;
+    unsigned done = 0u;
+    bool down = true;
+    while (true) {
+        if (down) {
+            if (l == L - 1) {
+                wg_coarse_apply<T>(base + l, A.c2s, A.ainv, S.coarse);
+                down = false;
+                continue;
+            }
+            const LevelDesc<T> *D = base + l;
+            const TailLevel &TL = A.lev[l];
+            for (int it = 0; it < A.nu1; ++it) wg_smooth<T, DIM, NST, STAGE>(D, TL, S);
+            const int nin = TL.nin0 + TL.nin1;
+            for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
+                if (t < nin) {
+                    long long idx;
+                    int i, j, k;
+                    tail_node<T, STAGE>(D, TL, S.si, t, idx, i, j, k);
+                    (void)defect_inside<T, DIM>(D, idx, i, j, k);
+                } else {
+                    (void)defect_ghost<T, NST>(D, t - nin);
+                }
+            }
+            __syncthreads();
+            for (int b = threadIdx.x; b < D->nb; b += blockDim.x) band_elem<T>(D, b);
+            __syncthreads();
+            const TailLevel &TC = A.lev[l + 1];
+            const LevelDesc<T> *C = D + 1;
+            const int ninc = TC.nin0 + TC.nin1;
+            for (int t = threadIdx.x; t < ninc + C->ng; t += blockDim.x) {
                 long long idx;
                 int i, j, k;
-                tail_node<T, STAGE>(D, TL, S.si, t, idx, i, j, k);
-                (void)defect_inside<T, DIM>(D, idx, i, j, k);
-            } else {
-                (void)defect_ghost<T, NST>(D, t - nin);
+                tail_node<T, STAGE>(C, TC, S.si, t, idx, i, j, k);
+                restrict_node<T, DIM>(C, idx, i, j, k, t < ninc);
             }
+            __syncthreads();
+            done &= ~(1u << l);
+            ++l;
+            continue;
         }
-        __syncthreads();
-        for (int b = threadIdx.x; b < D->nb; b += blockDim.x) band_elem<T>(D, b);
-        __syncthreads();
-        const TailLevel &TC = A.lev[l + 1];
-        const LevelDesc<T> *C = D + 1;
-        const int ninc = TC.nin0 + TC.nin1;
-        for (int t = threadIdx.x; t < ninc + C->ng; t += blockDim.x) {
-            long long idx;
-            int i, j, k;
-            tail_node<T, STAGE>(C, TC, S.si, t, idx, i, j, k);
-            restrict_node<T, DIM>(C, idx, i, j, k, t < ninc);
+        // cycle(l) has finished
+        if (l == A.l0) break;
+        const int p = l - 1;
+        if (A.gamma == 2 && l != L - 1 && !(done & (1u << p))) {
+            done |= 1u << p;
+            down = true;   // the second cycle on level l
+            continue;
         }
-        __syncthreads();
-    }
-    wg_coarse_apply<T>(base + (L - 1), A.c2s, A.ainv, S.coarse);
-    for (int l = L - 2; l >= A.l0; --l) {
-        const LevelDesc<T> *D = base + l;
-        const TailLevel &TL = A.lev[l];
+        const LevelDesc<T> *D = base + p;
+        const TailLevel &TL = A.lev[p];
         const int nin = TL.nin0 + TL.nin1;
         for (int t = threadIdx.x; t < nin + D->ng; t += blockDim.x) {
             long long idx;
@@ -930,6 +954,7 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
         }
         __syncthreads();
         for (int it = 0; it < A.nu2; ++it) wg_smooth<T, DIM, NST, STAGE>(D, TL, S);
+        l = p;
     }
 }
 

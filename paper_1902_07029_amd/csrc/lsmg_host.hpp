@@ -29,6 +29,7 @@ struct TailLevel {
 struct TailArgs {
     int d0, l0, nlev, nu1, nu2;
     int nstage;          // ints of the LDS copy of the node lists (sum over the tail's levels)
+    int gamma, pad;      // cycle index (1 V, 2 W)
     const int *c2s;      // coarsest level: compact -> storage
     const double *ainv;  // coarsest level: explicit inverse (FP64, 2Na x 2Na)
     TailLevel lev[kMaxLevels];

@@ -1,0 +1,88 @@
+"""W-cycles (cycle index 2, the paper's cycle of section 4.2) on the GPU against the
+oracle: the iterates of whole W(2,1) cycles on identical inputs, and whole
+Crank-Nicolson steps of the paper's Test 3 (s0 = 0, c0 = 10, s_B = 1, dt = h, N = 256,
+8 x 8 coarsest grid) to 1e-10 per step in FP64 and mixed precision.  The GPU relaxes
+the inside nodes in red-black order; the oracle does the same here."""
+import numpy as np
+import pytest
+import torch
+
+import lsmg_inputs as I
+from _gpu import cuda, host, pair, random_state, rel, say
+from paper_1902_07029_amd import lsmg
+
+W21 = dict(nu1=2, nu2=1, cycle_gamma=2)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind,n,coarsest", [("paper3", 129, 9), ("star", 257, 9), ("torus", 33, 5)])
+def test_wcycle_iterates_match_oracle(kind, n, coarsest):
+    say(f"W(2,1) cycle {kind} n={n}")
+    H, O = pair(kind, n, coarsest, **W21)
+    assert H.params.cycle_gamma == 2
+    rng = np.random.default_rng(5)
+    W = random_state(O, 0, rng)
+    H.set_linearization(cuda(W), 1e-3)
+    O.set_linearization(W, 1e-3)
+    na = O.level_info(0)["na"]
+    rhs = rng.standard_normal(2 * na)
+    xg, xo = cuda(np.zeros(2 * na)), np.zeros(2 * na)
+    for q in range(3):
+        xg, rg = H.vcycle(0, cuda(rhs), xg)
+        xo, ro = O.vcycle(0, rhs, xo)
+        assert rel(host(xg), xo) <= 1e-10, q
+        assert abs(rg - ro) <= 1e-8 * ro + 1e-12 * np.max(np.abs(rhs)), q
+    say(f"  defect after 3 cycles: {ro:.3e} (|rhs| {np.max(np.abs(rhs)):.2e})")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_paper_test3_steps(precision):
+    n = 257
+    H, O = pair("paper3", n, 9, precision=precision, **W21)
+    info = O.level_info(0)
+    na, h = info["na"], info["h"]
+    W = np.concatenate([np.zeros(na), np.full(na, 10.0)])
+    st = lsmg.State(H)
+    st.set(cuda(W))
+    sb = np.ones(info["ng"])
+    for k in range(3):
+        rc, gs = st.step(h, sb_const=1.0)
+        orc, W, os_ = O.newton_cn_step(W, h, sb)
+        assert orc == 0
+        G = host(st.get())
+        es, ec = rel(G[:na], W[:na]), rel(G[na:], W[na:])
+        say(f"paper Test 3 W(2,1) prec {precision} step {k}: err s {es:.2e} c {ec:.2e} newton "
+            f"{gs['newton_iters']}/{os_['newton_iters']} cycles {gs['vcycles']}/{os_['vcycles']} "
+            f"rho_geo {gs['rho_geo']:.3f}")
+        assert es <= 1e-10 and ec <= 1e-10
+
+
+@pytest.mark.gpu
+def test_batches_reject_wcycles():
+    a = pair("disk", 33, 5, **W21)[0]
+    b = pair("disk", 65, 5, **W21)[0]
+    with pytest.raises(lsmg.LsmgError) as e:
+        lsmg.Batch([a, b])
+    assert e.value.code == lsmg.ENOTIMPL
+
+
+@pytest.mark.gpu
+def test_set_params_switches_cycle():
+    # the coarse tail reads the cycle index and nu1, nu2 from its own arguments: a hierarchy
+    # switched to W(2,1) by set_params must give the iterates of one built with W(2,1)
+    built, _ = pair("star", 257, 9, **W21)
+    switched, O = pair("star", 257, 9)
+    switched.set_params(lsmg.default_params(coarsest_n=9, **W21))
+    rng = np.random.default_rng(9)
+    W = random_state(O, 0, rng)
+    na = O.level_info(0)["na"]
+    rhs = cuda(rng.standard_normal(2 * na))
+    xs = []
+    for H in (built, switched):
+        H.set_linearization(cuda(W), 1e-3)
+        x = cuda(np.zeros(2 * na))
+        for _ in range(2):
+            x, _ = H.vcycle(0, rhs, x)
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1])
