@@ -57,7 +57,7 @@ def _load():
                              ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     lib.or_free.argtypes = [vp]
     lib.or_free.restype = None
-    lib.or_set_params.argtypes = [vp] + [ctypes.c_double] * 7 + [ctypes.c_int] * 6 + [ctypes.c_double] + [ctypes.c_int] * 2
+    lib.or_set_params.argtypes = [vp] + [ctypes.c_double] * 7 + [ctypes.c_int] * 6 + [ctypes.c_double] + [ctypes.c_int] * 3
     lib.or_num_levels.argtypes = [vp]
     lib.or_level_info.argtypes = [vp, ctypes.c_int, _I, _D, _I, _I, _I]
     lib.or_compact_to_grid.argtypes = [vp, ctypes.c_int, _L]
@@ -127,7 +127,7 @@ class Hierarchy:
         self.nlev = lib.or_num_levels(h)
         self.params = dict(a=1e4, d=0.1, m_s=64.06, m_c=100.09, alpha=0.01, beta=0.1,
                            tau_s=0.9, nu1=2, nu2=2, ghost_c_new=1, band_steps=3,
-                           ghost_sweeps=1, ghost_sweeps_coarse=None, sweeps_lambda=0.3, gamma=1, lex=0)
+                           ghost_sweeps=1, ghost_sweeps_coarse=None, sweeps_lambda=0.3, gamma=1, lex=0, fmg=0)
         if params:
             self.set_params(**params)
 
@@ -145,7 +145,8 @@ class Hierarchy:
                                      int(p["ghost_sweeps"]),
                                      int(p["ghost_sweeps"] if p["ghost_sweeps_coarse"] is None
                                          else p["ghost_sweeps_coarse"]),
-                                     float(p["sweeps_lambda"]), int(p["gamma"]), int(p["lex"])), "set_params")
+                                     float(p["sweeps_lambda"]), int(p["gamma"]), int(p["lex"]),
+                                     int(p["fmg"])), "set_params")
 
     # --- geometry ---------------------------------------------------------
     def level_info(self, l):

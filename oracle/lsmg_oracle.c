@@ -73,6 +73,8 @@ typedef struct {
     int gamma;         /* cycle index: 1 V-cycle, 2 W-cycle (the paper's cycle, §4) */
     int lex;           /* 1: inside nodes relaxed in lexicographic order (the paper's
                           collective Gauss-Seidel, §3.5.1); 0: red-black */
+    int fmg;           /* full multigrid as the first iteration of the linear solves:
+                          0 never, 1 in the first Newton iteration of a step, 2 in every one */
 } OPar;
 
 typedef struct or_hier {
@@ -528,7 +530,7 @@ int or_build(const double *phi, int dim, int n, double lo, double hi, int coarse
     H->p.alpha = 0.01; H->p.beta = 0.1; H->p.tau_s = 0.9;
     H->p.nu1 = 2; H->p.nu2 = 2; H->p.ghost_c_new = 1; H->p.band_steps = 3; H->p.ghost_sweeps = 1;
     H->p.ghost_sweeps_coarse = 1; H->p.sweeps_lambda = 0.3;
-    H->p.gamma = 1; H->p.lex = 0;
+    H->p.gamma = 1; H->p.lex = 0; H->p.fmg = 0;
     nl = n;
     for (int l = 0; l < nlev; ++l) {
         OLevel *L = &H->L[l];
@@ -581,9 +583,10 @@ void or_free(or_hier *H)
 
 int or_set_params(or_hier *H, double a, double d, double m_s, double m_c, double alpha, double beta,
                   double tau_s, int nu1, int nu2, int ghost_c_new, int band_steps, int ghost_sweeps,
-                  int ghost_sweeps_coarse, double sweeps_lambda, int gamma, int lex)
+                  int ghost_sweeps_coarse, double sweeps_lambda, int gamma, int lex, int fmg)
 {
-    if (gamma < 1 || gamma > 2 || lex < 0 || lex > 1) return OR_EINVAL;
+    if (gamma < 1 || gamma > 2 || lex < 0 || lex > 1 || fmg < 0 || fmg > 2) return OR_EINVAL;
+    H->p.fmg = fmg;
     H->p.gamma = gamma;
     H->p.lex = lex;
     H->p.ghost_sweeps = ghost_sweeps;
@@ -1145,6 +1148,30 @@ static void vcycle_rec(or_hier *H, int l)
     for (int i = 0; i < H->p.nu2; ++i) smooth_level(H, l);
 }
 
+/* full multigrid (the paper names it as a first solver, §3.5; READING of how):
+ * with x = 0 on level 0 the right-hand side is restricted level by level with
+ * the same boundary-aware restriction as the cycle's defect; the coarsest
+ * problem is solved; on every finer level the prolongated coarser solution is
+ * the start of one cycle on that level */
+static void fmg_level0(or_hier *H)
+{
+    int L = H->nlev;
+    for (int l = 0; l + 1 < L; ++l) {
+        OLevel *F = &H->L[l], *C = &H->L[l + 1];
+        defect_level(H, l);          /* x_l = 0: the defect is the right-hand side */
+        char *ext = (char *)malloc(F->nn);
+        extend_band(H, l, ext);
+        restrict_level(H, l, ext);
+        free(ext);
+        for (long g = 0; g < C->nn; ++g) { C->x_s[g] = 0.0; C->x_c[g] = 0.0; }
+    }
+    coarse_solve_level(H);
+    for (int l = L - 2; l >= 0; --l) {
+        prolong_add_level(H, l);
+        vcycle_rec(H, l);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* public per-component entry points (compact vectors)                 */
 /* ------------------------------------------------------------------ */
@@ -1413,7 +1440,8 @@ int or_newton_cn_step(or_hier *H, double *W, double dt, const double *sb, const 
         double rprev = nF;
         for (int q = 0; q < cycles_max; ++q) {
             if (rprev <= lin_rtol * nF) break;
-            vcycle_rec(H, 0);
+            if (q == 0 && (H->p.fmg == 2 || (H->p.fmg == 1 && it == 1))) fmg_level0(H);
+            else vcycle_rec(H, 0);
             double rq = defect_level(H, 0);
             ++cycles;
             rho_last = rprev > 0.0 ? rq / rprev : 0.0;

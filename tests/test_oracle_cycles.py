@@ -5,6 +5,8 @@ efficiency test (section 4.2).
   to convergence equal scipy's sparse direct solve of the assembled Jacobian;
 * on a two-level hierarchy a W-cycle is a V-cycle (the coarse problem is solved
   exactly, so its second solve repeats the first): identical iterates;
+* a full-multigrid first iteration (restricted right-hand side, exact coarsest solve,
+  one cycle per level on the way up) leads to the same step, in no more cycles;
 * Tests 3 and 4 of section 4.2 (s0 = 0, c0 = 10, s_B = 1, dt = h, N = 256, W(2,1),
   lexicographic collective Gauss-Seidel, 8 x 8 coarsest grid): the paper reports
   convergence factors distributed around 0.119 once the first linear systems are
@@ -76,3 +78,24 @@ def test_paper_efficiency_test_convergence_factor(oracle_mod, kind):
         assert rc == 0
     med = float(np.median(st["rho"]))
     assert 0.08 <= med <= 0.16, med
+
+
+@pytest.mark.parametrize("fmg", [1, 2])
+def test_full_multigrid_start_reaches_the_same_step(oracle_mod, fmg):
+    # a full-multigrid first iteration changes how the linear systems are solved, not the
+    # Crank-Nicolson step they converge to
+    n = 257
+    out = []
+    for f in (0, fmg):
+        H = oracle_mod.Hierarchy(I.star(n), 2, n, coarsest_n=9, params=dict(SWEEPS, fmg=f))
+        na = H.level_info(0)["na"]
+        W = np.concatenate([np.zeros(na), np.ones(na)])
+        sb = np.ones(H.level_info(0)["ng"])
+        cyc = 0
+        for _ in range(3):
+            rc, W, st = H.newton_cn_step(W, 1e-4, sb)
+            assert rc == 0
+            cyc += st["vcycles"]
+        out.append((W, cyc))
+    assert np.max(np.abs(out[1][0] - out[0][0])) <= 1e-12 * np.max(np.abs(out[0][0]))
+    assert out[1][1] <= out[0][1]
