@@ -139,6 +139,13 @@ lsmg_status lsmg_set_dt(lsmg_hierarchy *h, double dt);
  * build: EINVAL if they differ). */
 lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params);
 
+/* Whether the coarse tail of the cycle (the levels of at most 1024 active nodes,
+ * run by one workgroup) holds its levels in LDS for the given precision (0:
+ * FP64 cycle, 1: FP32 cycle): *in_lds = 1, or 0 where they do not fit or the
+ * environment variable LSMG_TAIL_LDS=0 was set when h was built (the tail then
+ * reads its levels from HBM; the results are the same bits). */
+lsmg_status lsmg_tail_in_lds(const lsmg_hierarchy *h, int precision, int *in_lds);
+
 /* Parameters in effect (host out), with automatic choices resolved. */
 lsmg_status lsmg_get_params(const lsmg_hierarchy *h, lsmg_params *params);
 

@@ -265,6 +265,14 @@ TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
         if (l >= l0) off += Lv.nin[0] + Lv.nin[1] + 2 * Lv.ng + 1;
     }
     a.nstage = off;
+    if (H->tail_lds) {
+        a.tab = H->tail_tab;
+        a.tab_words = H->tail_sz.tab_words;
+        a.nvals = H->tail_sz.nvals;
+        a.nints = H->tail_sz.nints;
+        a.ngmax = H->tail_sz.ngmax;
+        for (int l = H->tail_l0; l < H->nlev; ++l) a.ll[l] = H->tail_ll[l];
+    }
     return a;
 }
 
@@ -275,8 +283,11 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
     const LevelDesc<T> *d = descs<T>(H);
     if (l >= H->tail_l0) {
         // this level and every coarser one in one workgroup
-        launch_tail<T>(H->dim, d, H->d_tail + l, 1, H->L[H->nlev - 1].na,
-                       tail_args(H, l, 0).nstage <= kTailStageInts, Exec(s));
+        if (tail_in_lds<T>(H))
+            launch_tail_lds<T>(H->dim, d, H->d_tail + l, 1, H->tail_sz, Exec(s));
+        else
+            launch_tail<T>(H->dim, d, H->d_tail + l, 1, H->L[H->nlev - 1].na,
+                           tail_args(H, l, 0).nstage <= kTailStageInts, Exec(s));
         return;
     }
     for (int i = 0; i < H->p.nu1; ++i) smooth_level<T>(H, l, s);
@@ -805,6 +816,7 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     }
     H->tail_l0 = nlev - 1;
     while (H->tail_l0 > 0 && H->L[H->tail_l0 - 1].na <= kTailMaxNodes) --H->tail_l0;
+    LSMGCHK(build_tail_tables(H));
     LSMGCHK(H->alloc(&H->piv, H->luN));
     LSMGCHK(H->zalloc(&H->lu_status, 1));
     LSMGCHK(H->zalloc(&H->d_norms, 4 * kNormSlots));
@@ -979,6 +991,8 @@ lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid
     H->stream = (hipStream_t)stream;
     // LSMG_GRAPHS=0 replays the V-cycle as direct launches instead of a captured graph
     if (const char *e = std::getenv("LSMG_GRAPHS")) H->use_graphs = std::atoi(e) != 0;
+    // LSMG_TAIL_LDS=0 runs the coarse tail from HBM instead of LDS
+    if (const char *e = std::getenv("LSMG_TAIL_LDS")) H->tail_lds_use = std::atoi(e) != 0;
     lsmg_status st = build(H, d_levelset, grid);
     if (st != LSMG_OK) {
         (void)hipStreamSynchronize(H->stream);
@@ -1021,6 +1035,13 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params)
     LSMGCHK(upload_tail_args(h));
     make_descs(h);
     return push_desc(h);
+}
+
+lsmg_status lsmg_tail_in_lds(const lsmg_hierarchy *h, int precision, int *in_lds)
+{
+    if (!h || !in_lds || (precision != 0 && precision != 1)) return fail(LSMG_EINVAL, "bad argument");
+    *in_lds = precision == 0 ? tail_in_lds<double>(h) : tail_in_lds<float>(h);
+    return LSMG_OK;
 }
 
 lsmg_status lsmg_set_dt(lsmg_hierarchy *h, double dt)

@@ -103,6 +103,12 @@ struct lsmg_hierarchy {
     int *piv = nullptr, *lu_status = nullptr;
     int luN = 0;
     int tail_l0 = 0;   // first level handled by the coarse-tail kernel
+    // coarse tail held in LDS: table image (device), per-level layout, sizes
+    uint32_t *tail_tab = nullptr;
+    std::vector<TailLdsLevel> tail_ll;
+    TailLdsSize tail_sz{};
+    bool tail_lds = false;     // tables built (the tail's levels fit the table encoding)
+    bool tail_lds_use = true;  // LSMG_TAIL_LDS=0 turns the LDS tail off
     unsigned long long *d_norms = nullptr, *h_norms = nullptr;
     TailArgs *d_tail = nullptr;      // coarse-tail arguments, entry l for a tail starting at level l
     CoarseArgs *d_coarse = nullptr;  // coarsest-operator arguments
@@ -181,5 +187,14 @@ lsmg_status build_f32(lsmg_hierarchy *H);
 // the coarse-tail arguments of hierarchy H for a tail starting at level l0,
 // its descriptors starting at d0 in the descriptor array the launch uses
 TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0);
+// index tables of the coarse tail held in LDS (tail.hip); leaves tail_lds false
+// where the tail's levels do not fit the tables' encoding
+lsmg_status build_tail_tables(lsmg_hierarchy *H);
+// whether the coarse tail of H runs in LDS in precision T
+template <typename T>
+bool tail_in_lds(const lsmg_hierarchy *H)
+{
+    return H->tail_lds && H->tail_lds_use && H->p.ghost_c_new && H->tail_sz.bytes<T>() <= kTailLdsMax;
+}
 
 }  // namespace lsmg

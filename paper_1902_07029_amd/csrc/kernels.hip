@@ -15,19 +15,13 @@
 
 #include "lsmg_dev.hpp"
 #include "lsmg_host.hpp"
+#include "rows.hpp"
 
 namespace lsmg {
 
 // ---------------------------------------------------------------------------
-// inside-row Jacobian (section 3.4, exact derivatives of eqs. FDs and FDc;
-// the printed forms of eqs. JssI, JscI, JcsI, JccI are garbled)
+// rows read from a level in HBM (arithmetic in rows.hpp)
 // ---------------------------------------------------------------------------
-template <typename T>
-struct InsideRow {
-    T ss_d, sc_d, cs_d, cc_d;   // diagonal 2x2 block P (eq. matrixP)
-    T off_s;                    // sum over the axis neighbours of J^ss x_s + J^sc x_c
-};
-
 template <typename T, int DIM>
 __device__ __forceinline__ InsideRow<T> inside_row(const LevelDesc<T> *D, long long idx, const long long *nb)
 {
@@ -40,34 +34,14 @@ __device__ __forceinline__ InsideRow<T> inside_row(const LevelDesc<T> *D, long l
         xse[e] = D->x_s[nb[e]];
         xce[e] = D->x_c[nb[e]];
     }
-    const T al = D->alpha, be = D->beta, kap = D->kap;
-    const T phr = al * cr + be;
-    T sum_ss = 0, sum_sc = 0, off = 0;
-#pragma unroll
-    for (int e = 0; e < 2 * DIM; ++e) {
-        const T a_ss = (al * ce[e] + be) + phr;
-        const T a_sc = sr - se[e];
-        sum_ss += a_ss;
-        sum_sc += a_sc;
-        off += -kap * a_ss * xse[e] + kap * al * a_sc * xce[e];
-    }
-    InsideRow<T> R;
-    R.ss_d = phr * D->dt_inv + D->ks_half * phr * cr + kap * sum_ss;
-    R.sc_d = al * sr * D->dt_inv + D->ks_half * (al * sr * cr + phr * sr) + kap * al * sum_sc;
-    R.cs_d = D->kc_half * phr * cr;
-    R.cc_d = D->dt_inv + D->kc_half * (al * sr * cr + phr * sr);
-    R.off_s = off;
-    return R;
+    return inside_row_vals<T, DIM>(D, sr, cr, se, ce, xse, xce);
 }
 
 // c-row diagonal entries of a node (inside or ghost)
 template <typename T>
 __device__ __forceinline__ void c_row(const LevelDesc<T> *D, long long idx, T &cs_d, T &cc_d)
 {
-    const T sr = D->s[idx], cr = D->c[idx];
-    const T phr = D->alpha * cr + D->beta;
-    cs_d = D->kc_half * phr * cr;
-    cc_d = D->dt_inv + D->kc_half * (D->alpha * sr * cr + phr * sr);
+    c_row_vals<T>(D, D->s[idx], D->c[idx], cs_d, cc_d);
 }
 
 // node of (item, lane): inside node of a segment (kinds 0/1) or a ghost (kind 2)
@@ -103,11 +77,10 @@ __device__ __forceinline__ void smooth_node(const LevelDesc<T> *D, long long idx
     long long nb[2 * DIM];
     neighbours<DIM>(D->n, D->Wp, D->cs, colour, (long long)j + (long long)D->n * k, i, i >> 1, nb);
     const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
-    const T rs = D->rhs_s[idx] - R.off_s;
-    const T rc = D->rhs_c[idx];
-    const T det = R.ss_d * R.cc_d - R.sc_d * R.cs_d;
-    D->x_s[idx] = (R.cc_d * rs - R.sc_d * rc) / det;
-    D->x_c[idx] = (R.ss_d * rc - R.cs_d * rs) / det;
+    T xs, xc;
+    block_solve<T>(R, D->rhs_s[idx], D->rhs_c[idx], xs, xc);
+    D->x_s[idx] = xs;
+    D->x_c[idx] = xc;
 }
 
 template <typename T, int DIM>
@@ -155,8 +128,7 @@ __device__ __forceinline__ void ghost_final_elem(const LevelDesc<T> *D, int q, c
     T cs_d, cc_d;
     c_row<T>(D, g, cs_d, cc_d);
     const T dsv = D->ghost_c_new ? ns : bprev[q];
-    const T xc = D->x_c[g];
-    D->x_c[g] = xc + (D->rhs_c[g] - (cs_d * dsv + cc_d * xc)) / cc_d;
+    D->x_c[g] = ghost_c_update<T>(cs_d, cc_d, D->rhs_c[g], dsv, D->x_c[g]);
 }
 
 // composed form of the same sweeps: phase 1 stores the ghost's current delta s
@@ -191,8 +163,7 @@ __device__ __forceinline__ void ghost_apply_elem(const LevelDesc<T> *D, int q)
     D->x_s[g] = v;
     T cs_d, cc_d;
     c_row<T>(D, g, cs_d, cc_d);
-    const T xc = D->x_c[g];
-    D->x_c[g] = xc + (D->rhs_c[g] - (cs_d * v + cc_d * xc)) / cc_d;
+    D->x_c[g] = ghost_c_update<T>(cs_d, cc_d, D->rhs_c[g], v, D->x_c[g]);
 }
 
 // defect r = rhs - J x on one active row pair (section 3.5.2); returns |r| bits
@@ -202,9 +173,8 @@ __device__ __forceinline__ unsigned long long defect_inside(const LevelDesc<T> *
     long long nb[2 * DIM];
     neighbours<DIM>(D->n, D->Wp, D->cs, (i + j + k) & 1, (long long)j + (long long)D->n * k, i, i >> 1, nb);
     const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
-    const T xs = D->x_s[idx], xc = D->x_c[idx];
-    const T rs = D->rhs_s[idx] - (R.ss_d * xs + R.sc_d * xc + R.off_s);
-    const T rc = D->rhs_c[idx] - (R.cs_d * xs + R.cc_d * xc);
+    T rs, rc;
+    inside_defect_vals<T>(R, D->rhs_s[idx], D->rhs_c[idx], D->x_s[idx], D->x_c[idx], rs, rc);
     D->r_s[idx] = rs;
     D->r_c[idx] = rc;
     const unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
@@ -330,38 +300,10 @@ __device__ __forceinline__ void restrict_node(const LevelDesc<T> *C, long long c
         ex[kk] = inb ? (uint8_t)excl : (uint8_t)1;
         act[kk] = inb && t != kOut;
     }
-    constexpr int CEN = DIM == 2 ? 4 : 13;
-    ex[CEN] = 0;
-    // per-axis weights: [1,2,1]/4, [2,2,0]/4 if +1 excluded, [0,2,2]/4 if -1 excluded, [0,4,0]/4 if both
-    T wa[3][3];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const int st = a == 0 ? 1 : (a == 1 ? 3 : 9);
-        const bool em = ex[CEN - st], ep = ex[CEN + st];
-        wa[a][0] = em ? T(0) : (ep ? T(0.5) : T(0.25));
-        wa[a][1] = (em && ep) ? T(1) : T(0.5);
-        wa[a][2] = ep ? T(0) : (em ? T(0.5) : T(0.25));
-    }
-    T vs = 0, wcen = 0, vc = 0, wcs = 0;
-#pragma unroll
-    for (int kk = 0; kk < NST; ++kk) {
-        const int d0 = kk % 3, d1 = (kk / 3) % 3, d2 = kk / 9;
-        T wk = wa[0][d0] * wa[1][d1];
-        T wf = (d0 == 1 ? T(0.5) : T(0.25)) * (d1 == 1 ? T(0.5) : T(0.25));
-        if (DIM == 3) {
-            wk *= wa[2][d2];
-            wf *= (d2 == 1 ? T(0.5) : T(0.25));
-        }
-        if (ex[kk]) wcen += wk;
-        else vs += wk * rs[kk];
-        if (act[kk]) {
-            vc += wf * rc[kk];
-            wcs += wf;
-        }
-    }
-    vs += wcen * rs[CEN];
+    T vs, vc;
+    restrict_vals<T, DIM>(ex, act, rs, rc, vs, vc);
     C->rhs_s[cidx] = vs;
-    C->rhs_c[cidx] = wcs > T(0) ? vc / wcs : T(0);
+    C->rhs_c[cidx] = vc;
     C->x_s[cidx] = T(0);
     C->x_c[cidx] = T(0);
 }
@@ -498,15 +440,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_smooth_colour(const LevelDesc<T> 
                                                              int colour, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
+    const LevelDesc<T> *D = descs + item_desc(w);
     if (item_kind(w) == 2) {
         // ghost items after the segments: snapshot the ghosts' delta s for the folded
         // ghost relaxation (ghost values do not change during the colour sweeps)
-        const LevelDesc<T> *D = descs + item_desc(w);
         const int q = w.z + lane;
         if (q < w.w) D->g_buf1[q] = D->x_s[D->g_idx[q]];
         return;
     }
-    smooth_elem<T, DIM>(descs + item_desc(w), w, lane, colour);
+    smooth_elem<T, DIM>(D, w, lane, colour);
 }
 
 template <typename T>
@@ -588,7 +530,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply_grouped(const LevelDe
             T cs_d, cc_d;
             c_row<T>(D, g, cs_d, cc_d);
             const T xc = D->x_c[g];
-            D->x_c[g] = xc + (D->rhs_c[g] - (cs_d * v + cc_d * xc)) / cc_d;
+            D->x_c[g] = ghost_c_update<T>(cs_d, cc_d, D->rhs_c[g], v, xc);
         }
     }
 }
@@ -758,7 +700,7 @@ __device__ __forceinline__ void tail_ghost_apply(const LevelDesc<T> *D, long lon
             if (e + u < e1) v += a[u] * gb1[col[u]] + b[u] * gb0[col[u]];
     }
     D->x_s[g] = v;
-    D->x_c[g] = xc + (rc - (cs_d * v + cc_d * xc)) / cc_d;
+    D->x_c[g] = ghost_c_update<T>(cs_d, cc_d, rc, v, xc);
 }
 
 template <typename T, int DIM, int NST, bool STAGE>
@@ -806,26 +748,6 @@ __device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, const Tail
     const T *bprev = (sweeps & 1) ? D->g_buf0 : D->g_buf1;
     for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_final_elem<T>(D, q, bfin, bprev);
     __syncthreads();
-}
-
-// sum_q M[r][q] v[q] subtracted from (SIGN < 0) or added to acc, with the row's
-// entries fetched eight at a time and summed in order q = 0 .. na-1
-template <int SIGN>
-__device__ __forceinline__ double row_dot(const double *__restrict__ row, const double *v, int na, double acc)
-{
-    for (int q0 = 0; q0 < na; q0 += 8) {
-        double m[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) m[e] = q0 + e < na ? row[q0 + e] : 0.0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            if (q0 + e < na) {
-                if (SIGN < 0) acc -= m[e] * v[q0 + e];
-                else acc += m[e] * v[q0 + e];
-            }
-        }
-    }
-    return acc;
 }
 
 // x = A^{-1} rhs on the coarsest level (FP64).  The c-rows couple a node only to

@@ -25,6 +25,26 @@ struct TailLevel {
                          // inside coordinates, ghost coordinates, composed-map row pointers
 };
 
+// coarse tail held in LDS: where a level's index tables sit in the tail's table
+// image (16-bit entries, offsets in entries) and its values in the value region
+// (offsets in values: s, c, x_s, x_c, rhs_s, rhs_c, r_c with na entries each,
+// then r_s with na + nb + 1: the band nodes and a zero)
+struct TailLdsLevel {
+    int nbr;     // inside nodes: tail indices of the 2 dim axis neighbours
+    int gst;     // ghosts: tail indices of the stencil nodes, bit 15 set where the node
+                 // is a ghost with nonzero weight
+    int bcnt;    // band nodes: number of sources
+    int bsrc;    // band nodes: tail indices of the source ghosts (entry j at j * nb + b)
+    int pro;     // active nodes: the 2^dim coarse corners (tail index, kSkip, kOff) and the
+                 // number of odd coordinates
+    int rst;     // active nodes of the next coarser level: their 3^dim fine neighbours
+                 // (slot | type << 12 | ext << 14 | in-box << 15)
+    int perm;    // coarsest level: tail index of compact node r
+    int gop;     // composed-map row pointers (ints, copied from the level at entry)
+    int v;       // first value of the level
+    int na, nb, pad;
+};
+
 // one hierarchy's coarse tail (levels l0 .. nlev-1), its descriptors starting at d0
 struct TailArgs {
     int d0, l0, nlev, nu1, nu2;
@@ -33,6 +53,10 @@ struct TailArgs {
     const int *c2s;      // coarsest level: compact -> storage
     const double *ainv;  // coarsest level: explicit inverse (FP64, 2Na x 2Na)
     TailLevel lev[kMaxLevels];
+    // coarse tail held in LDS (when the hierarchy's tail fits)
+    const uint32_t *tab;        // table image
+    int tab_words, nvals, nints, ngmax;
+    TailLdsLevel ll[kMaxLevels];
 };
 
 // one hierarchy's coarsest operator: descriptor, compact -> storage map, global
@@ -67,6 +91,19 @@ template <typename T> void launch_ghost(int dim, const LevelDesc<T> *d, int desc
                                         int nw4, int ng, int sweeps, bool composed, const Exec &xb, const Exec &xa);
 template <typename T> void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max,
                                        bool stage, const Exec &x);
+// the same tail with every tail level held in LDS (tail.hip); sizes are the
+// maxima over the blocks' TailArgs
+struct TailLdsSize {
+    int ncoarse, ngmax, nvals, nints, tab_words;
+    template <typename T> size_t bytes() const
+    {
+        return (size_t)4 * ncoarse * sizeof(double) + (size_t)(2 * ngmax + nvals) * sizeof(T) +
+               (size_t)(nints + tab_words) * sizeof(int);
+    }
+};
+template <typename T> void launch_tail_lds(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks,
+                                           const TailLdsSize &sz, const Exec &x);
+constexpr size_t kTailLdsMax = 158 * 1024;   // of the 160 KiB of a gfx950 CU
 template <typename T> void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x);
 template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);

@@ -72,6 +72,7 @@ def load():
         "lsmg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_i),
                                  ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "lsmg_compact_to_grid": (_i, [_vp, _i, _vp]),
+        "lsmg_tail_in_lds": (_i, [_vp, _i, _vp]),
         "lsmg_ghost_table": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "lsmg_state_create": (_i, [_vp, ctypes.POINTER(_vp)]),
         "lsmg_state_destroy": (None, [_vp]),
@@ -217,6 +218,11 @@ class Hierarchy:
         out = torch.empty(self.level_info(l)["na"], dtype=torch.int64, device="cuda")
         _check(load().lsmg_compact_to_grid(self._h, l, _ptr(out)), "lsmg_compact_to_grid")
         return out
+
+    def tail_in_lds(self, precision=0):
+        v = _i()
+        _check(load().lsmg_tail_in_lds(self._h, precision, ctypes.byref(v)), "lsmg_tail_in_lds")
+        return bool(v.value)
 
     def ghost_table(self, l):
         info = self.level_info(l)
