@@ -59,6 +59,17 @@ def paper_square(n, lo=PAPER_BOX[0], hi=PAPER_BOX[1], L=0.9567, D=0.3):
     return np.minimum(p1, p2)
 
 
+def necklace_mask(n, beads=8, ring=0.55, radius=0.17):
+    """A pixel mask standing in for the paper's image geometries (section 4.3, whose
+    images are not available): a ring of eight discs on an n x n grid."""
+    x, y = grid_points(n, 2)
+    m = np.zeros(n * n, dtype=bool)
+    for k in range(beads):
+        a = 2 * math.pi * k / beads
+        m |= (x - ring * math.cos(a)) ** 2 + (y - ring * math.sin(a)) ** 2 < radius ** 2
+    return m
+
+
 def star(n, a=0.5, b=0.15, k=5, p=0.0):
     x, y = grid_points(n, 2)
     r = np.sqrt(x * x + y * y)

@@ -79,6 +79,9 @@ def _load():
                                       ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                       ctypes.POINTER(_Stats), _D, ctypes.c_int]
     lib.or_lu_solve_dense.argtypes = [_D, _D, ctypes.c_int]
+    lib.or_reinitialize.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _D]
+    lib.or_levelset_from_mask.argtypes = [ctypes.POINTER(ctypes.c_ubyte), ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
+    lib.or_extrapolate.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int, _D]
     _lib = lib
     return lib
 
@@ -109,6 +112,32 @@ def lu_solve_dense(A, b):
     x = _f64(b).copy()
     _check(lib.or_lu_solve_dense(_dp(A), _dp(x), A.shape[0]), "lu")
     return x
+
+
+def reinitialize(phi0, dim, n, h, iters):
+    """Re-initialisation of a level set towards the signed distance (section 2)."""
+    phi0 = _f64(phi0).reshape(-1)
+    out = np.empty_like(phi0)
+    _check(_load().or_reinitialize(_dp(phi0), dim, n, h, iters, _dp(out)), "reinitialize")
+    return out
+
+
+def levelset_from_mask(mask, dim, n, iters):
+    """Level set -1 inside the mask, +1 outside, smoothed by iters heat steps (section 2)."""
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    out = np.empty(m.size)
+    _check(_load().or_levelset_from_mask(m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), dim, n, iters, _dp(out)),
+           "levelset_from_mask")
+    return out
+
+
+def extrapolate(phi, dim, n, h, q, iters):
+    """Second-order extrapolation of q from phi < 0 to the rest of the grid (section 3.3)."""
+    phi = _f64(phi).reshape(-1)
+    q = _f64(q).reshape(-1)
+    out = np.empty_like(q)
+    _check(_load().or_extrapolate(_dp(phi), dim, n, h, _dp(q), iters, _dp(out)), "extrapolate")
+    return out
 
 
 class Hierarchy:

@@ -1479,3 +1479,212 @@ int or_newton_cn_step(or_hier *H, double *W, double dt, const double *sb, const 
 
 /* Newton step with an externally supplied exact linear solve is done in the
  * tests (scipy) through or_residual and or_assemble_coo. */
+
+/* ------------------------------------------------------------------ */
+/* level-set and initial-data preparation on a full grid (§2, §3.3)    */
+/* ------------------------------------------------------------------ */
+
+/* value of array v at node g shifted by s (+-1) along axis a; the node itself
+ * where the neighbour leaves the box (zero one-sided difference there) */
+static double nbv(const double *v, long g, const int *gi, int n, int a, long sa, int s)
+{
+    int k = gi[a] + s;
+    if (k < 0 || k >= n) return v[g];
+    return v[g + s * sa];
+}
+
+/* Re-initialisation of a level set towards the signed distance (§2): the
+ * pseudo-time equation d phi/d mu = sgn(phi0) (1 - |grad phi|) from phi = phi0,
+ * forward Euler with d mu = h / dim.  READING (the paper cites the PDE only):
+ * the scheme with the subcell fix of Russo and Smereka, which keeps the zero
+ * level set where phi0 puts it.  Nodes with a sign change of phi0 towards an
+ * axis neighbour relax to D = h phi0 / dphi0, their distance estimated from
+ * phi0, with dphi0 the largest of the central, forward and backward undivided
+ * gradient norms of phi0:
+ *     phi <- phi - (d mu / h) (sgn(phi0) |phi| - D);
+ * every other node takes the upwind (Godunov) update
+ *     phi <- phi - d mu sgn(phi0) (|grad phi| - 1).
+ * One-sided differences vanish at the box edge.  iters steps. */
+int or_reinitialize(const double *phi0, int dim, int n, double h, int iters, double *phi)
+{
+    if (dim < 2 || dim > 3 || n < 2 || !(h > 0.0) || iters < 0) return OR_EINVAL;
+    long nn = 1;
+    for (int a = 0; a < dim; ++a) nn *= n;
+    double *cur = dalloc(nn), *nxt = dalloc(nn), *D = dalloc(nn);
+    char *near = (char *)calloc(nn, 1);
+    for (long g = 0; g < nn; ++g) {
+        int gi[3];
+        unravel(g, n, dim, gi);
+        double p0 = phi0[g], c2 = 0.0, f2 = 0.0, b2 = 0.0;
+        int nr = 0;
+        for (int a = 0; a < dim; ++a) {
+            long sa = stride_of(n, a);
+            double pm = nbv(phi0, g, gi, n, a, sa, -1), pp = nbv(phi0, g, gi, n, a, sa, +1);
+            if (p0 * pm <= 0.0 || p0 * pp <= 0.0) nr = 1;
+            double c = (pp - pm) / 2.0, f = pp - p0, bk = p0 - pm;
+            c2 += c * c;
+            f2 += f * f;
+            b2 += bk * bk;
+        }
+        double dp = sqrt(c2);
+        if (sqrt(f2) > dp) dp = sqrt(f2);
+        if (sqrt(b2) > dp) dp = sqrt(b2);
+        if (dp < 1e-300) dp = 1e-300;
+        near[g] = (char)nr;
+        D[g] = h * p0 / dp;
+    }
+    memcpy(cur, phi0, sizeof(double) * nn);
+    double dmu = h / dim;
+    for (int it = 0; it < iters; ++it) {
+        for (long g = 0; g < nn; ++g) {
+            double p0 = phi0[g];
+            double sg = p0 > 0.0 ? 1.0 : (p0 < 0.0 ? -1.0 : 0.0);
+            if (near[g]) {
+                nxt[g] = cur[g] - (dmu / h) * (sg * fabs(cur[g]) - D[g]);
+                continue;
+            }
+            int gi[3];
+            unravel(g, n, dim, gi);
+            double g2 = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                long sa = stride_of(n, a);
+                double dm = (cur[g] - nbv(cur, g, gi, n, a, sa, -1)) / h;   /* backward */
+                double dpp = (nbv(cur, g, gi, n, a, sa, +1) - cur[g]) / h;  /* forward */
+                double u, w;
+                if (p0 > 0.0) { u = dm > 0.0 ? dm : 0.0; w = dpp < 0.0 ? dpp : 0.0; }
+                else { u = dm < 0.0 ? dm : 0.0; w = dpp > 0.0 ? dpp : 0.0; }
+                double m = u * u > w * w ? u * u : w * w;
+                g2 += m;
+            }
+            nxt[g] = cur[g] - dmu * sg * (sqrt(g2) - 1.0);
+        }
+        double *tt = cur; cur = nxt; nxt = tt;
+    }
+    memcpy(phi, cur, sizeof(double) * nn);
+    free(cur); free(nxt); free(D); free(near);
+    return OR_OK;
+}
+
+/* Level set from a mask (§2, the paper's treatment of image data): phi = -1
+ * where mask != 0 (inside), +1 elsewhere, then iters explicit steps of the
+ * heat equation, phi += (1 / (2 dim)) sum over the axes of the second
+ * difference (READING: the step size, the largest stable one for the
+ * five/seven-point Laplacian; the paper says "a few iterations"). */
+int or_levelset_from_mask(const unsigned char *mask, int dim, int n, int iters, double *phi)
+{
+    if (dim < 2 || dim > 3 || n < 2 || iters < 0) return OR_EINVAL;
+    long nn = 1;
+    for (int a = 0; a < dim; ++a) nn *= n;
+    double *cur = dalloc(nn), *nxt = dalloc(nn);
+    for (long g = 0; g < nn; ++g) cur[g] = mask[g] ? -1.0 : 1.0;
+    double k = 1.0 / (2.0 * dim);
+    for (int it = 0; it < iters; ++it) {
+        for (long g = 0; g < nn; ++g) {
+            int gi[3];
+            unravel(g, n, dim, gi);
+            double lap = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                long sa = stride_of(n, a);
+                lap += nbv(cur, g, gi, n, a, sa, -1) - 2.0 * cur[g] + nbv(cur, g, gi, n, a, sa, +1);
+            }
+            nxt[g] = cur[g] + k * lap;
+        }
+        double *t = cur; cur = nxt; nxt = t;
+    }
+    memcpy(phi, cur, sizeof(double) * nn);
+    free(cur); free(nxt);
+    return OR_OK;
+}
+
+/* one pseudo-time stage of the extension along the outward normal: where
+ * known[g] is 0, v <- v - dtau (n . grad_up v - src), grad_up the one-sided
+ * difference against the normal component (upwind: information flows out of
+ * the domain along n); src = NULL for 0 */
+static void extend_stage(const double *nrm, const char *known, const double *src, int dim, int n, long nn, double h,
+                         int iters, double *v)
+{
+    double *nxt = dalloc(nn);
+    double dtau = h / dim;
+    for (int it = 0; it < iters; ++it) {
+        for (long g = 0; g < nn; ++g) {
+            if (known[g]) { nxt[g] = v[g]; continue; }
+            int gi[3];
+            unravel(g, n, dim, gi);
+            double adv = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                long sa = stride_of(n, a);
+                double na = nrm[g * dim + a], d;
+                if (na > 0.0) d = (v[g] - nbv(v, g, gi, n, a, sa, -1)) / h;
+                else if (na < 0.0) d = (nbv(v, g, gi, n, a, sa, +1) - v[g]) / h;
+                else d = 0.0;
+                adv += na * d;
+            }
+            nxt[g] = v[g] - dtau * (adv - (src ? src[g] : 0.0));
+        }
+        memcpy(v, nxt, sizeof(double) * nn);
+    }
+    free(nxt);
+}
+
+/* Second-order extrapolation of data q from the inside (phi < 0) to the rest
+ * of the grid (§3.3: initial data at the ghosts), by the PDE approach the paper
+ * cites (Aslam): with n = grad phi / |grad phi| (central differences),
+ *   q_n = n . grad q and q_nn = n . grad q_n by central differences where their
+ *   stencils are known, then, each over iters pseudo-time steps,
+ *   q_nn extended constantly along n   (d/dtau q_nn + n . grad q_nn = 0),
+ *   q_n  extended linearly              (d/dtau q_n + n . grad q_n = q_nn),
+ *   q    extended                       (d/dtau q + n . grad q = q_n).
+ * Values at phi < 0 are returned unchanged. */
+int or_extrapolate(const double *phi, int dim, int n, double h, const double *q, int iters, double *out)
+{
+    if (dim < 2 || dim > 3 || n < 3 || !(h > 0.0) || iters < 0) return OR_EINVAL;
+    long nn = 1;
+    for (int a = 0; a < dim; ++a) nn *= n;
+    double *nrm = dalloc(nn * dim), *qn = dalloc(nn), *qnn = dalloc(nn);
+    char *k0 = (char *)calloc(nn, 1), *k1 = (char *)calloc(nn, 1), *k2 = (char *)calloc(nn, 1);
+    for (long g = 0; g < nn; ++g) {
+        int gi[3];
+        unravel(g, n, dim, gi);
+        double gr[3] = {0, 0, 0}, l2 = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            long sa = stride_of(n, a);
+            if (gi[a] > 0 && gi[a] < n - 1) gr[a] = (phi[g + sa] - phi[g - sa]) / (2.0 * h);
+            else if (gi[a] == 0) gr[a] = (phi[g + sa] - phi[g]) / h;
+            else gr[a] = (phi[g] - phi[g - sa]) / h;
+            l2 += gr[a] * gr[a];
+        }
+        double l = sqrt(l2);
+        for (int a = 0; a < dim; ++a) nrm[g * dim + a] = l > 0.0 ? gr[a] / l : 0.0;
+        k0[g] = phi[g] < 0.0;
+    }
+    /* known set of a derived quantity: a known node whose axis neighbours are all known and in the box */
+    for (int pass = 0; pass < 2; ++pass) {
+        const char *kin = pass ? k1 : k0;
+        char *kout = pass ? k2 : k1;
+        const double *vin = pass ? qn : q;
+        double *vout = pass ? qnn : qn;
+        for (long g = 0; g < nn; ++g) {
+            int gi[3];
+            unravel(g, n, dim, gi);
+            int ok = kin[g];
+            for (int a = 0; a < dim && ok; ++a) {
+                long sa = stride_of(n, a);
+                if (gi[a] == 0 || gi[a] == n - 1 || !kin[g - sa] || !kin[g + sa]) ok = 0;
+            }
+            kout[g] = (char)ok;
+            double v = 0.0;
+            if (ok)
+                for (int a = 0; a < dim; ++a) {
+                    long sa = stride_of(n, a);
+                    v += nrm[g * dim + a] * (vin[g + sa] - vin[g - sa]) / (2.0 * h);
+                }
+            vout[g] = v;
+        }
+    }
+    for (long g = 0; g < nn; ++g) out[g] = k0[g] ? q[g] : 0.0;
+    extend_stage(nrm, k2, NULL, dim, n, nn, h, iters, qnn);
+    extend_stage(nrm, k1, qnn, dim, n, nn, h, iters, qn);
+    extend_stage(nrm, k0, qn, dim, n, nn, h, iters, out);
+    free(nrm); free(qn); free(qnn); free(k0); free(k1); free(k2);
+    return OR_OK;
+}
