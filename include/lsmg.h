@@ -139,6 +139,37 @@ lsmg_status lsmg_set_dt(lsmg_hierarchy *h, double dt);
  * build: EINVAL if they differ). */
 lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params);
 
+/* ---- preparation of a domain's inputs (full grids, device, x fastest) -------
+ * Each call runs on `stream` (a hipStream_t, NULL for the null stream), uses
+ * device scratch of a few grid-sized arrays that it frees again, and returns
+ * after synchronising the stream.  Errors: EINVAL (bad grid or argument),
+ * EOOM, EHIP. */
+
+/* Re-initialisation of a level set towards the signed distance function
+ * (section 2): `iterations` forward-Euler steps of d phi/d mu = sgn(phi0)(1 -
+ * |grad phi|) with d mu = h / dim.  Nodes next to a sign change of phi0 relax
+ * to their distance estimated from phi0 (the subcell fix of Russo and
+ * Smereka, which keeps the zero level set in place); the others take the
+ * upwind (Godunov) update.  One-sided differences vanish at the box edge.
+ * d_phi: n^dim doubles, in place.  The solver itself does not need a distance
+ * function (section 2). */
+lsmg_status lsmg_reinitialize(double *d_phi, const lsmg_grid *grid, int iterations, void *stream);
+
+/* A level set from a mask (section 2, images): phi = -1 where d_mask != 0
+ * (n^dim bytes), +1 elsewhere, then `iterations` explicit heat steps phi +=
+ * (1 / (2 dim)) * (sum of the second differences).  d_phi: n^dim doubles out. */
+lsmg_status lsmg_levelset_from_mask(const uint8_t *d_mask, const lsmg_grid *grid, int iterations, double *d_phi,
+                                    void *stream);
+
+/* Second-order extrapolation of data (initial s or c, section 3.3) from the
+ * inside (phi < 0) to every other node, by the pseudo-time PDE approach the
+ * paper cites: the normal derivatives q_n and q_nn by central differences where
+ * their stencils are inside, then q_nn extended constantly, q_n linearly and q
+ * quadratically along n = grad phi / |grad phi|, `iterations` upwind steps of
+ * d tau = h / dim each (20-40 reach the ghost nodes).  d_q: n^dim doubles, in
+ * place; values where phi < 0 are unchanged. */
+lsmg_status lsmg_extrapolate(const double *d_phi, const lsmg_grid *grid, double *d_q, int iterations, void *stream);
+
 /* Whether the coarse tail of the cycle (the levels of at most 1024 active nodes,
  * run by one workgroup) holds its levels in LDS for the given precision (0:
  * FP64 cycle, 1: FP32 cycle): *in_lds = 1, or 0 where they do not fit or the

@@ -19,7 +19,8 @@ BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = os.environ.get("LSMG_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
-UNITS = [("build.hip", ["-ffp-contract=off"]), ("kernels.hip", []), ("tail.hip", []), ("api.hip", []),
+UNITS = [("build.hip", ["-ffp-contract=off"]), ("kernels.hip", []), ("tail.hip", []), ("init.hip", ["-ffp-contract=off"]),
+         ("api.hip", []),
          ("batch.hip", [])]
 
 

@@ -72,6 +72,9 @@ def load():
         "lsmg_level_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_i),
                                  ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "lsmg_compact_to_grid": (_i, [_vp, _i, _vp]),
+        "lsmg_reinitialize": (_i, [_vp, _vp, _i, _vp]),
+        "lsmg_levelset_from_mask": (_i, [_vp, _vp, _i, _vp, _vp]),
+        "lsmg_extrapolate": (_i, [_vp, _vp, _vp, _i, _vp]),
         "lsmg_tail_in_lds": (_i, [_vp, _i, _vp]),
         "lsmg_ghost_table": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "lsmg_state_create": (_i, [_vp, ctypes.POINTER(_vp)]),
@@ -143,6 +146,34 @@ def default_params(**overrides):
     for k, v in overrides.items():
         setattr(p, k, v)
     return p
+
+
+def _stream(stream):
+    return _vp(stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+
+
+def reinitialize(phi, dim, n, iterations, lo=-1.0, hi=1.0, stream=None):
+    """Level set phi (CUDA float64, n^dim) re-initialised towards the signed distance, in place."""
+    grid = Grid(dim, n, lo, hi)
+    _check(load().lsmg_reinitialize(_ptr(phi), ctypes.byref(grid), iterations, _stream(stream)), "lsmg_reinitialize")
+    return phi
+
+
+def levelset_from_mask(mask, dim, n, iterations, lo=-1.0, hi=1.0, stream=None):
+    """Level set from a mask (CUDA uint8, n^dim; nonzero = inside): -1 / +1 smoothed by heat steps."""
+    grid = Grid(dim, n, lo, hi)
+    phi = torch.empty(mask.numel(), dtype=torch.float64, device=mask.device)
+    _check(load().lsmg_levelset_from_mask(_ptr(mask), ctypes.byref(grid), iterations, _ptr(phi), _stream(stream)),
+           "lsmg_levelset_from_mask")
+    return phi
+
+
+def extrapolate(phi, q, dim, n, iterations=40, lo=-1.0, hi=1.0, stream=None):
+    """q (CUDA float64, n^dim) extrapolated from phi < 0 to every other node at second order, in place."""
+    grid = Grid(dim, n, lo, hi)
+    _check(load().lsmg_extrapolate(_ptr(phi), ctypes.byref(grid), _ptr(q), iterations, _stream(stream)),
+           "lsmg_extrapolate")
+    return q
 
 
 def estimate_bytes(dim, n, params, lo=-1.0, hi=1.0):
