@@ -599,12 +599,77 @@ def run_serve(args):
     }
 
 
+def run_prepare(args):
+    """Input preparation of a 1025^2 domain (sections 2 and 3.3): a pixel mask (the
+    necklace of discs) made a level set, re-initialised, and non-constant initial
+    data extrapolated to the ghosts.  Throughput in grid-node iterations per second
+    of the re-initialisation, whose step is the dominant kernel."""
+    import torch
+    from paper_1902_07029_amd import lsmg
+    import oracle
+    n, dim, iters = 1025, 2, 200
+    h = 2.0 / (n - 1)
+    nn = n * n
+    mask = torch.from_numpy(I.necklace_mask(n).astype(np.uint8)).cuda()
+    phi_mask = lsmg.levelset_from_mask(mask, dim, n, 8)
+    x, y = I.grid_points(n, 2)
+    q = torch.from_numpy(np.ascontiguousarray(I.s_exact(x, y, 0.0))).cuda()
+    for _ in range(args.warmup):
+        lsmg.reinitialize(phi_mask.clone(), dim, n, iters)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms_reinit = []
+    for _ in range(args.steps):
+        phi = phi_mask.clone()
+        ev0.record()
+        lsmg.reinitialize(phi, dim, n, iters)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_reinit.append(ev0.elapsed_time(ev1))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lsmg.extrapolate(phi, q.clone(), dim, n, 40)
+    torch.cuda.synchronize()
+    ms_extrap = (time.perf_counter() - t0) * 1e3 / args.steps
+    per_call = float(np.median(ms_reinit))
+    value = nn * iters / (per_call * 1e-3)
+    # one re-initialisation step reads phi (its four neighbours come from the same
+    # rows), phi0, the near flag and the target D, and writes phi: 8 + 8 + 1 + 8 + 8 bytes
+    bytes_per_iter = nn * 33
+    achieved = bytes_per_iter * iters / (per_call * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        phi_np = phi_mask.cpu().numpy()
+        k = 0
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < min(args.cpu_budget, 10.0):
+            phi_np = oracle.reinitialize(phi_np, dim, n, h, 50)
+            k += 50
+        el = time.perf_counter() - t1
+        cpu = dict(value=nn * k / el, unit="node*iterations/s", cores=1, kind="oracle",
+                   sample=f"{k} re-initialisation steps on the 1025^2 necklace level set ({el:.1f} s, serial C)")
+    return {
+        "metric": "level-set re-initialisation node*iterations/s (input preparation)",
+        "value": value, "unit": "node*iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": per_call, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "prepare1025", "n": n, "reinit_iterations": iters, "extrapolation_iterations": 40,
+                   "mask": "necklace of 8 discs", "heat_steps": 8},
+        "extrapolate_ms": ms_extrap,
+        "roofline": dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                         kernel="k_reinit_step (whole re-initialisation call, events on the stream)",
+                         bytes_per_launch=bytes_per_iter, avg_us=round(per_call * 1e3 / iters, 2)),
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS) + ["batch64", "serve"],
+    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS) + ["batch64", "serve", "prepare1025"],
                     help="paper3: the paper's Test 3 with its W(2,1) cycle (section 4.2)")
     ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
     ap.add_argument("--load", type=float, default=2.0,
@@ -640,6 +705,8 @@ def main():
         out = run_batch(args)
     elif args.workload == "serve":
         out = run_serve(args)
+    elif args.workload == "prepare1025":
+        out = run_prepare(args)
     else:
         out = run_single(args)
     print(json.dumps(out))
