@@ -144,7 +144,7 @@ def oracle_params(H):
     eff = H.params
     return {k: getattr(eff, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
                                          "ghost_c_new", "band_steps", "ghost_sweeps", "ghost_sweeps_coarse",
-                                         "sweeps_lambda")} | {"gamma": eff.cycle_gamma}
+                                         "sweeps_lambda")} | {"gamma": eff.cycle_gamma, "fmg": eff.fmg}
 
 
 # ---------------------------------------------------------------- profiling helpers
@@ -259,7 +259,7 @@ def run_single(args):
     w = WORKLOADS[args.workload]
     prec = args.precision if args.precision is not None else 0
     bc = 1 if args.bc == "neumann" else 0
-    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec, bc=bc, **w.get("params", {}))
+    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec, bc=bc, fmg=args.fmg, **w.get("params", {}))
     phi_np = levelset(w)
     lo, hi = box_of(w)
     dt = dt_of(w)
@@ -349,7 +349,8 @@ def run_single(args):
         "dtype": "f64" if prec == 0 else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}_{'fp64' if prec == 0 else 'mixed'}" + ("_neumann" if bc else ""),
+            "workload": f"{args.workload}_{'fp64' if prec == 0 else 'mixed'}" + ("_neumann" if bc else "")
+                        + (f"_fmg{args.fmg}" if args.fmg else ""),
             "boundary": "neumann ds/dn = 1" if bc else "dirichlet s = 1",
             "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": dt, "coarsest": w["coarsest"],
             "box": [lo, hi], "c0": w.get("c0", 1.0),
@@ -680,6 +681,9 @@ def main():
                     help="0 = FP64, 1 = mixed (default: FP64, batch64: mixed)")
     ap.add_argument("--bc", default="dirichlet", choices=("dirichlet", "neumann"),
                     help="star1025 / torus257 / disk65: boundary condition for s (section 3.6 for Neumann)")
+    ap.add_argument("--fmg", type=int, default=0, choices=(0, 1, 2),
+                    help="single domains: full multigrid as the first iteration of the first (1) or every (2) "
+                         "linear solve of a step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true", help="batch64: skip the sequential FP64 comparison")
     ap.add_argument("--cpu-budget", type=float, default=20.0)

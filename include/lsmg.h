@@ -84,6 +84,11 @@ typedef struct {
     int cycle_gamma;       /* cycle index: 1 V-cycle, 2 W-cycle (the paper's cycle, section 4: the
                             * coarse-grid correction is two cycles on the next level, the second
                             * starting from the first one's result); batches take 1 only */
+    int fmg;               /* full multigrid as the first iteration of a linear solve: 0 never,
+                            * 1 in the first Newton iteration of a step, 2 in every one (the right-
+                            * hand side restricted to every level, the coarsest problem solved, then
+                            * on each finer level the prolongated solution as the start of one
+                            * cycle); batches take 0 only */
 } lsmg_params;
 
 typedef struct lsmg_hierarchy lsmg_hierarchy;

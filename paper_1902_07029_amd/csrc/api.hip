@@ -48,7 +48,7 @@ lsmg_status check_params(const lsmg_params *p)
         !(p->sweeps_lambda >= 0.0) || p->band_steps < 0 ||
         p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
         !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1) ||
-        (p->bc != 0 && p->bc != 1) || p->cycle_gamma < 1 || p->cycle_gamma > 2)
+        (p->bc != 0 && p->bc != 1) || p->cycle_gamma < 1 || p->cycle_gamma > 2 || p->fmg < 0 || p->fmg > 2)
         return fail(LSMG_EINVAL, "invalid solver parameters");
     return LSMG_OK;
 }
@@ -303,18 +303,44 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
     for (int i = 0; i < H->p.nu2; ++i) smooth_level<T>(H, l, s);
 }
 
+// full multigrid from a zero correction on level 0: the right-hand side
+// restricted level by level (the defect of a zero correction is the right-hand
+// side; the restriction clears the coarser correction), the coarsest problem
+// solved, then on every finer level the prolongated coarser solution is the
+// start of one cycle
+template <typename T>
+void fmg_enqueue(lsmg_hierarchy *H, hipStream_t s)
+{
+    const LevelDesc<T> *d = descs<T>(H);
+    const int L = H->nlev;
+    for (int l = 0; l + 1 < L; ++l) {
+        const Level &Lv = H->L[l], &C = H->L[l + 1];
+        launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), -1, Exec(s));
+        launch_band<T>(d, Lv.w_band(), Lv.nbandc, Exec(s));
+        launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), Exec(s));
+    }
+    vcycle_rec<T>(H, L - 1, s);
+    for (int l = L - 2; l >= 0; --l) {
+        launch_prolong<T>(H->dim, d, H->L[l].w_act(), H->L[l].nw_act(), Exec(s));
+        vcycle_rec<T>(H, l, s);
+    }
+}
+
 // one linear-solve iteration on level 0: a V-cycle on the correction (FP64), or
 // an FP32 V-cycle on the current FP64 defect added to the FP64 correction; then
-// the FP64 defect and its norm in slot 1
-void cycle_enqueue(lsmg_hierarchy *H, bool mixed, hipStream_t s)
+// the FP64 defect and its norm in slot 1.  fmg: a full-multigrid pass instead of
+// the cycle (the correction is zero then)
+void cycle_enqueue(lsmg_hierarchy *H, bool mixed, hipStream_t s, bool fmg = false)
 {
     const Level &L0 = H->L[0];
     zero_norms(H, 1, 1, s);
     if (!mixed) {
-        vcycle_rec<double>(H, 0, s);
+        if (fmg) fmg_enqueue<double>(H, s);
+        else vcycle_rec<double>(H, 0, s);
     } else {
         launch_to_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), 1, s);
-        vcycle_rec<float>(H, 0, s);
+        if (fmg) fmg_enqueue<float>(H, s);
+        else vcycle_rec<float>(H, 0, s);
         launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), s);
     }
     launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), 1, s);
@@ -322,20 +348,21 @@ void cycle_enqueue(lsmg_hierarchy *H, bool mixed, hipStream_t s)
 
 void invalidate_graphs(lsmg_hierarchy *H)
 {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 4; ++i) {
         if (H->gexec[i]) (void)hipGraphExecDestroy(H->gexec[i]);
         H->gexec[i] = nullptr;
     }
 }
 
-// capture the cycle of precision `mixed` once; replays run on the hierarchy's stream
-lsmg_status cycle_graph(lsmg_hierarchy *H, bool mixed, hipGraphExec_t *out)
+// capture the cycle of precision `mixed` (fmg: the full-multigrid iteration)
+// once; replays run on the hierarchy's stream
+lsmg_status cycle_graph(lsmg_hierarchy *H, bool mixed, hipGraphExec_t *out, bool fmg = false)
 {
-    const int gi = mixed ? 1 : 0;
+    const int gi = (mixed ? 1 : 0) + (fmg ? 2 : 0);
     if (!H->gexec[gi]) {
         if (!H->cap) HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal));
-        cycle_enqueue(H, mixed, H->cap);
+        cycle_enqueue(H, mixed, H->cap, fmg);
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamEndCapture(H->cap, &g));
         hipError_t e = hipGraphInstantiate(&H->gexec[gi], g, nullptr, nullptr, 0);
@@ -875,7 +902,8 @@ void zero_active_x(lsmg_hierarchy *H, int l)
 
 // linear solve J dW = F on level 0 (rhs already in rhs_s / rhs_c) by V-cycles from zero;
 // nF = |F|_inf.  Returns cycles run; rho statistics accumulate into the outs.
-lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_last, double *logsum, int *nrho)
+lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_last, double *logsum, int *nrho,
+                         bool fmg_first)
 {
     const Level &L0 = H->L[0];
     zero_active_x(H, 0);
@@ -885,17 +913,20 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
         // r = F - J 0 in FP64
         launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), -1, H->stream);
     }
-    hipGraphExec_t ge = nullptr;
+    hipGraphExec_t ge = nullptr, gf = nullptr;
     // events recorded inside a graph cannot be timed: while launch timing is on,
     // cycles run as direct launches
-    if (H->use_graphs && H->prof_kernel < 0) LSMGCHK(cycle_graph(H, mixed, &ge));
+    const bool graphs = H->use_graphs && H->prof_kernel < 0;
+    if (graphs) LSMGCHK(cycle_graph(H, mixed, &ge));
+    if (graphs && fmg_first) LSMGCHK(cycle_graph(H, mixed, &gf, true));
     for (int q = 0; q < H->p.cycles_max; ++q) {
         if (rprev <= H->p.lin_rtol * nF) break;
         const size_t mark0 = H->prof_used;
-        if (ge) HIPCHK(hipGraphLaunch(ge, H->stream));
-        else cycle_enqueue(H, mixed, H->stream);
+        const bool fmg = fmg_first && q == 0;
+        if (graphs) HIPCHK(hipGraphLaunch(fmg ? gf : ge, H->stream));
+        else cycle_enqueue(H, mixed, H->stream, fmg);
         LSMGCHK(read_norms(H, 2));
-        if (!ge) {
+        if (!graphs) {
             prof_collect(H, mark0, H->prof_used);
             H->prof_used = mark0;
         }
@@ -969,6 +1000,7 @@ void lsmg_default_params(lsmg_params *p)
     p->cycles_max = 30;
     p->bc = 0;
     p->cycle_gamma = 1;
+    p->fmg = 0;
 }
 
 const char *lsmg_last_error(void) { return g_err.c_str(); }
@@ -1243,7 +1275,8 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
         }
         LSMGCHK(linearize(h));
         LSMGCHK(check_factor(h));
-        LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho));
+        LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho,
+                             h->p.fmg == 2 || (h->p.fmg == 1 && it == 1)));
         zero_norms(h, 0, 4);
         launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), s);
         launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, s);

@@ -559,7 +559,7 @@ bool same_params(const lsmg_params &a, const lsmg_params &b)
            a.band_steps == b.band_steps && a.ghost_c_new == b.ghost_c_new && a.coarsest_n == b.coarsest_n &&
            a.precision == b.precision && a.newton_tol == b.newton_tol && a.newton_max == b.newton_max &&
            a.lin_rtol == b.lin_rtol && a.cycles_max == b.cycles_max && a.bc == b.bc &&
-           a.cycle_gamma == b.cycle_gamma;
+           a.cycle_gamma == b.cycle_gamma && a.fmg == b.fmg;
 }
 
 lsmg_status b_build(lsmg_batch *B)
@@ -636,8 +636,8 @@ lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, void *s
             if (members[j] == members[k]) return fail(LSMG_EINVAL, "member %d appears twice", k);
         if (members[k]->dim != members[0]->dim) return fail(LSMG_EINVAL, "members differ in dimension");
         if (!same_params(members[k]->p, members[0]->p)) return fail(LSMG_EINVAL, "members differ in parameters");
-        if (members[k]->p.cycle_gamma != 1)
-            return fail(LSMG_ENOTIMPL, "batches run V-cycles (cycle_gamma = 1)");
+        if (members[k]->p.cycle_gamma != 1 || members[k]->p.fmg != 0)
+            return fail(LSMG_ENOTIMPL, "batches run V-cycles (cycle_gamma = 1) without full multigrid (fmg = 0)");
         if (!members[k]->p.ghost_c_new)
             return fail(LSMG_ENOTIMPL, "batches use the composed ghost relaxation (ghost_c_new = 1)");
         if (members[k]->p.precision == 1 && !members[k]->have32) return fail(LSMG_EINVAL, "member %d has no FP32 copy", k);

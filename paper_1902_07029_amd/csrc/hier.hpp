@@ -128,13 +128,13 @@ struct lsmg_hierarchy {
     // V-cycle graphs (0: FP64 cycle, 1: mixed-precision refinement step), captured on a private stream
     bool use_graphs = true;
     hipStream_t cap = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};   // + 2: full-multigrid first iterations
     size_t prof_pending = 0;
     // composed ghost relaxation tables (CSR over ghosts), owned separately: rebuilt with the parameters
     std::vector<void *> ghost_ops;
     ~lsmg_hierarchy()
     {
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 4; ++i)
             if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
         if (cap) (void)hipStreamDestroy(cap);
         for (void *p : ghost_ops) (void)hipFree(p);

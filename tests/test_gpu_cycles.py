@@ -1,7 +1,8 @@
 """W-cycles (cycle index 2, the paper's cycle of section 4.2) on the GPU against the
 oracle: the iterates of whole W(2,1) cycles on identical inputs, and whole
 Crank-Nicolson steps of the paper's Test 3 (s0 = 0, c0 = 10, s_B = 1, dt = h, N = 256,
-8 x 8 coarsest grid) to 1e-10 per step in FP64 and mixed precision.  The GPU relaxes
+8 x 8 coarsest grid) to 1e-10 per step in FP64 and mixed precision, and the
+full-multigrid first iteration of the linear solves.  The GPU relaxes
 the inside nodes in red-black order; the oracle does the same here."""
 import numpy as np
 import pytest
@@ -86,3 +87,38 @@ def test_set_params_switches_cycle():
             x, _ = H.vcycle(0, rhs, x)
         xs.append(x)
     assert torch.equal(xs[0], xs[1])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("fmg,precision", [(1, 0), (2, 0), (2, 1)])
+def test_full_multigrid_steps_match_oracle(fmg, precision):
+    # a full-multigrid first iteration of the linear solves (restricted right-hand side,
+    # exact coarsest solve, prolongation and one cycle per level on the way up)
+    n = 257
+    H, O = pair("star", n, 9, precision=precision, fmg=fmg)
+    info = O.level_info(0)
+    na = info["na"]
+    s, c = I.initial_state(n, 2)
+    W = O.to_compact(0, s, c)
+    st = lsmg.State(H)
+    st.set(cuda(W))
+    sb = np.ones(info["ng"])
+    for k in range(3):
+        rc, gs = st.step(1e-4, sb_const=1.0)
+        orc, W, os_ = O.newton_cn_step(W, 1e-4, sb)
+        assert orc == 0
+        G = host(st.get())
+        es, ec = rel(G[:na], W[:na]), rel(G[na:], W[na:])
+        say(f"FMG {fmg} prec {precision} step {k}: err s {es:.2e} c {ec:.2e} cycles {gs['vcycles']}/{os_['vcycles']}")
+        assert es <= 1e-10 and ec <= 1e-10
+        if precision == 0:
+            assert gs["vcycles"] == os_["vcycles"]
+
+
+@pytest.mark.gpu
+def test_batches_reject_full_multigrid():
+    a = pair("disk", 33, 5, fmg=1)[0]
+    b = pair("disk", 65, 5, fmg=1)[0]
+    with pytest.raises(lsmg.LsmgError) as e:
+        lsmg.Batch([a, b])
+    assert e.value.code == lsmg.ENOTIMPL
