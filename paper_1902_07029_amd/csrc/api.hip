@@ -282,6 +282,11 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
     const Level &Lv = H->L[l];
     const LevelDesc<T> *d = descs<T>(H);
     if (l >= H->tail_l0) {
+        // the coarsest factorisation forked off in this captured cycle joins here
+        if (H->join_pending) {
+            (void)hipStreamWaitEvent(s, H->ev_join, 0);
+            H->join_pending = false;
+        }
         // this level and every coarser one in one workgroup
         if (tail_in_lds<T>(H))
             launch_tail_lds<T>(H->dim, d, H->d_tail + l, 1, H->tail_sz, Exec(s));
@@ -348,21 +353,38 @@ void cycle_enqueue(lsmg_hierarchy *H, bool mixed, hipStream_t s, bool fmg = fals
 
 void invalidate_graphs(lsmg_hierarchy *H)
 {
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
         if (H->gexec[i]) (void)hipGraphExecDestroy(H->gexec[i]);
         H->gexec[i] = nullptr;
     }
 }
 
-// capture the cycle of precision `mixed` (fmg: the full-multigrid iteration)
-// once; replays run on the hierarchy's stream
-lsmg_status cycle_graph(lsmg_hierarchy *H, bool mixed, hipGraphExec_t *out, bool fmg = false)
+// capture the cycle of precision `mixed` (fmg: the full-multigrid iteration;
+// factor: the first cycle after a linearisation, with the coarsest operator
+// factorised on a side stream while the fine levels run, joined before the
+// coarse tail) once; replays run on the hierarchy's stream
+lsmg_status cycle_graph(lsmg_hierarchy *H, bool mixed, hipGraphExec_t *out, bool fmg = false, bool factor = false)
 {
-    const int gi = (mixed ? 1 : 0) + (fmg ? 2 : 0);
+    const int gi = (mixed ? 1 : 0) + (fmg ? 2 : 0) + (factor ? 4 : 0);
     if (!H->gexec[gi]) {
         if (!H->cap) HIPCHK(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal));
+        if (factor) {
+            if (!H->side) HIPCHK(hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking));
+            if (!H->ev_fork) HIPCHK(hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+            if (!H->ev_join) HIPCHK(hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(H->ev_fork, H->cap));
+            HIPCHK(hipStreamWaitEvent(H->side, H->ev_fork, 0));
+            launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, Exec(H->side));
+            HIPCHK(hipEventRecord(H->ev_join, H->side));
+            H->join_pending = true;
+        }
         cycle_enqueue(H, mixed, H->cap, fmg);
+        if (H->join_pending) {
+            // every cycle reaches the tail; joined here all the same before the capture ends
+            HIPCHK(hipStreamWaitEvent(H->cap, H->ev_join, 0));
+            H->join_pending = false;
+        }
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamEndCapture(H->cap, &g));
         hipError_t e = hipGraphInstantiate(&H->gexec[gi], g, nullptr, nullptr, 0);
@@ -373,8 +395,9 @@ lsmg_status cycle_graph(lsmg_hierarchy *H, bool mixed, hipGraphExec_t *out, bool
     return LSMG_OK;
 }
 
-// linearisation on every level from level 0's (s, c); factors the coarsest operator
-lsmg_status linearize(lsmg_hierarchy *H)
+// linearisation on every level from level 0's (s, c); factors the coarsest
+// operator unless the caller's first cycle does it (factor = false)
+lsmg_status linearize(lsmg_hierarchy *H, bool factor = true)
 {
     for (int l = 1; l < H->nlev; ++l) {
         const Level &C = H->L[l];
@@ -385,7 +408,7 @@ lsmg_status linearize(lsmg_hierarchy *H)
             const Level &Lv = H->L[l];
             launch_to_f32(H->dim, H->d64, H->d32, Lv.w_act(), Lv.nw_act(), 0, H->stream);
         }
-    launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, H->stream);
+    if (factor) launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, H->stream);
     H->lin_set = true;
     return LSMG_OK;
 }
@@ -903,7 +926,7 @@ void zero_active_x(lsmg_hierarchy *H, int l)
 // linear solve J dW = F on level 0 (rhs already in rhs_s / rhs_c) by V-cycles from zero;
 // nF = |F|_inf.  Returns cycles run; rho statistics accumulate into the outs.
 lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_last, double *logsum, int *nrho,
-                         bool fmg_first)
+                         bool fmg_first, bool factor_first)
 {
     const Level &L0 = H->L[0];
     zero_active_x(H, 0);
@@ -918,14 +941,26 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
     // cycles run as direct launches
     const bool graphs = H->use_graphs && H->prof_kernel < 0;
     if (graphs) LSMGCHK(cycle_graph(H, mixed, &ge));
-    if (graphs && fmg_first) LSMGCHK(cycle_graph(H, mixed, &gf, true));
+    if (graphs && (fmg_first || factor_first)) LSMGCHK(cycle_graph(H, mixed, &gf, fmg_first, factor_first));
+    if (!graphs && factor_first) launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, H->stream);
     for (int q = 0; q < H->p.cycles_max; ++q) {
-        if (rprev <= H->p.lin_rtol * nF) break;
+        if (rprev <= H->p.lin_rtol * nF) {
+            // no cycle ran: the factorisation still has to be done and checked
+            if (q == 0 && factor_first && graphs) {
+                launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, H->stream);
+                LSMGCHK(check_factor(H));
+            }
+            break;
+        }
         const size_t mark0 = H->prof_used;
-        const bool fmg = fmg_first && q == 0;
-        if (graphs) HIPCHK(hipGraphLaunch(fmg ? gf : ge, H->stream));
-        else cycle_enqueue(H, mixed, H->stream, fmg);
+        const bool first = q == 0 && (fmg_first || factor_first);
+        if (graphs) HIPCHK(hipGraphLaunch(first ? gf : ge, H->stream));
+        else cycle_enqueue(H, mixed, H->stream, q == 0 && fmg_first);
+        if (q == 0 && factor_first)
+            HIPCHK(hipMemcpyAsync(H->h_status, H->lu_status, sizeof(int), hipMemcpyDeviceToHost, H->stream));
         LSMGCHK(read_norms(H, 2));
+        if (q == 0 && factor_first && *H->h_status != 0)
+            return fail(LSMG_ENONFINITE, "coarsest operator is singular or not finite");
         if (!graphs) {
             prof_collect(H, mark0, H->prof_used);
             H->prof_used = mark0;
@@ -1273,10 +1308,10 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
             rc = fail(LSMG_ENONFINITE, "residual is not finite");
             break;
         }
-        LSMGCHK(linearize(h));
-        LSMGCHK(check_factor(h));
+        // the coarsest factorisation runs inside the first cycle, and is checked with its norms
+        LSMGCHK(linearize(h, false));
         LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho,
-                             h->p.fmg == 2 || (h->p.fmg == 1 && it == 1)));
+                             h->p.fmg == 2 || (h->p.fmg == 1 && it == 1), true));
         zero_norms(h, 0, 4);
         launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), s);
         launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, s);

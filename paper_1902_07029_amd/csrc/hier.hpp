@@ -128,14 +128,22 @@ struct lsmg_hierarchy {
     // V-cycle graphs (0: FP64 cycle, 1: mixed-precision refinement step), captured on a private stream
     bool use_graphs = true;
     hipStream_t cap = nullptr;
-    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};   // + 2: full-multigrid first iterations
+    // captured cycles, index mixed + 2 fmg + 4 factor: the full-multigrid first iteration, and the first
+    // cycle of a linearisation with the coarsest factorisation forked onto a side stream
+    hipGraphExec_t gexec[8] = {};
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool join_pending = false;       // during capture: the next tail launch waits for ev_join
     size_t prof_pending = 0;
     // composed ghost relaxation tables (CSR over ghosts), owned separately: rebuilt with the parameters
     std::vector<void *> ghost_ops;
     ~lsmg_hierarchy()
     {
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 8; ++i)
             if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+        if (side) (void)hipStreamDestroy(side);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         if (cap) (void)hipStreamDestroy(cap);
         for (void *p : ghost_ops) (void)hipFree(p);
         for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
