@@ -1,9 +1,12 @@
 """Build the lsmg HIP library for gfx950 in-tree (``liblsmg.so`` next to this file).
 
-Four translation units: ``build.hip`` (hierarchy construction, compiled with
+Six translation units: ``build.hip`` (hierarchy construction, compiled with
 FMA contraction off so the discrete geometry is evaluated in plain IEEE order),
-``kernels.hip`` (V-cycle and Newton kernels), ``api.hip`` (the C ABI and the
-single-hierarchy drivers) and ``batch.hip`` (batches of hierarchies).  Every HIP compile line disables packed FP32 instructions.
+``kernels.hip`` (V-cycle and Newton kernels), ``tail.hip`` (the coarse tail held
+in LDS and its tables), ``init.hip`` (level-set preparation, FMA contraction
+off), ``api.hip`` (the C ABI and the single-hierarchy drivers) and ``batch.hip``
+(batches of hierarchies).  Every HIP compile line disables packed FP32
+instructions.
 """
 import os
 import shutil

@@ -103,7 +103,7 @@ __device__ __forceinline__ void ghost_load_elem(const LevelDesc<T> *D, int q)
 }
 
 template <typename T, int NST>
-__device__ __forceinline__ void ghost_sweep_elem(const LevelDesc<T> *D, int q, const T *bin, T *bout)
+__device__ __forceinline__ void ghost_sweep_elem(const LevelDesc<T> *D, int q, gptr<T> bin, gptr<T> bout)
 {
     const int ng = D->ng;
     const long long g = D->g_idx[q];
@@ -120,7 +120,7 @@ __device__ __forceinline__ void ghost_sweep_elem(const LevelDesc<T> *D, int q, c
 }
 
 template <typename T>
-__device__ __forceinline__ void ghost_final_elem(const LevelDesc<T> *D, int q, const T *bfin, const T *bprev)
+__device__ __forceinline__ void ghost_final_elem(const LevelDesc<T> *D, int q, gptr<T> bfin, gptr<T> bprev)
 {
     const long long g = D->g_idx[q];
     const T ns = bfin[q];
@@ -425,11 +425,15 @@ __device__ __forceinline__ int logical_block()
 // Every item kernel ends with `act`, per-descriptor flags (null: all active);
 // the items of a descriptor whose flag is 0 are skipped.  A wavefront returns
 // as a whole, so the wavefront reductions that follow never see part of one.
-#define LSMG_ITEM_PROLOGUE                                                                  \
-    const int it = logical_block() * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);     \
-    if (it >= nwork) return;                                                               \
-    const int4 w = work[it];                                                               \
-    if (act && !act[item_desc(w)]) return;                                                 \
+// The item number is made wavefront-uniform explicitly (readfirstlane of the
+// wavefront index), so the item, its descriptor and the descriptor's pointers
+// are read with scalar loads and every data load of a lane can be issued at once.
+#define LSMG_ITEM_PROLOGUE                                                                   \
+    const int it = logical_block() * (int)(blockDim.x >> 6) +                               \
+                   __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));                  \
+    if (it >= nwork) return;                                                                \
+    const int4 w = work[it];                                                                \
+    if (act && !act[item_desc(w)]) return;                                                  \
     const int lane = threadIdx.x & 63;
 
 #define LSMG_ITEMS const int4 *__restrict__ work, int nwork
@@ -544,13 +548,13 @@ __global__ __launch_bounds__(1024) void k_ghost_fused(const LevelDesc<T> *__rest
     for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_load_elem<T>(D, q);
     __syncthreads();
     for (int sw = 0; sw < sweeps; ++sw) {
-        const T *bin = (sw & 1) ? D->g_buf1 : D->g_buf0;
-        T *bout = (sw & 1) ? D->g_buf0 : D->g_buf1;
+        const gptr<T> bin = (sw & 1) ? D->g_buf1 : D->g_buf0;
+        const gptr<T> bout = (sw & 1) ? D->g_buf0 : D->g_buf1;
         for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_sweep_elem<T, NST>(D, q, bin, bout);
         __syncthreads();
     }
-    const T *bfin = (sweeps & 1) ? D->g_buf1 : D->g_buf0;
-    const T *bprev = (sweeps & 1) ? D->g_buf0 : D->g_buf1;
+    const gptr<T> bfin = (sweeps & 1) ? D->g_buf1 : D->g_buf0;
+    const gptr<T> bprev = (sweeps & 1) ? D->g_buf0 : D->g_buf1;
     for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_final_elem<T>(D, q, bfin, bprev);
 }
 
@@ -739,13 +743,13 @@ __device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, const Tail
     for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_load_elem<T>(D, q);
     __syncthreads();
     for (int sw = 0; sw < sweeps; ++sw) {
-        const T *bin = (sw & 1) ? D->g_buf1 : D->g_buf0;
-        T *bout = (sw & 1) ? D->g_buf0 : D->g_buf1;
+        const gptr<T> bin = (sw & 1) ? D->g_buf1 : D->g_buf0;
+        const gptr<T> bout = (sw & 1) ? D->g_buf0 : D->g_buf1;
         for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_sweep_elem<T, NST>(D, q, bin, bout);
         __syncthreads();
     }
-    const T *bfin = (sweeps & 1) ? D->g_buf1 : D->g_buf0;
-    const T *bprev = (sweeps & 1) ? D->g_buf0 : D->g_buf1;
+    const gptr<T> bfin = (sweeps & 1) ? D->g_buf1 : D->g_buf0;
+    const gptr<T> bprev = (sweeps & 1) ? D->g_buf0 : D->g_buf1;
     for (int q = threadIdx.x; q < ng; q += blockDim.x) ghost_final_elem<T>(D, q, bfin, bprev);
     __syncthreads();
 }
@@ -757,11 +761,11 @@ __device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, const Tail
 // Coarse storage (from k_coarse_invert): [S^{-1} | J^sc | J^cs | J^cc], Na x Na,
 // Na x Na, Na, Na doubles.  b: 4 Na doubles of LDS.
 template <typename T>
-__device__ void wg_coarse_apply(const LevelDesc<T> *D, const int *__restrict__ c2s, const double *__restrict__ Ainv,
+__device__ void wg_coarse_apply(const LevelDesc<T> *D, gptr<const int> c2s, gptr<const double> Ainv,
                                 double *b)
 {
     const int na = D->na;
-    const double *Sinv = Ainv, *Jsc = Ainv + (long long)na * na, *cs = Ainv + 2LL * na * na, *cc = cs + na;
+    const gptr<const double> Sinv = Ainv, Jsc = Ainv + (long long)na * na, cs = Ainv + 2LL * na * na, cc = cs + na;
     double *rs = b, *rc = b + na, *t = b + 2 * na, *u = b + 3 * na;
     for (int r = threadIdx.x; r < na; r += blockDim.x) {
         const long long node = c2s[r];
@@ -887,7 +891,7 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
 // descriptor
 // ---------------------------------------------------------------------------
 template <int DIM>
-__device__ __forceinline__ double Ls_h(const LevelDesc<double> *D, const double *s, const double *c, long long idx,
+__device__ __forceinline__ double Ls_h(const LevelDesc<double> *D, gptr<double> s, gptr<double> c, long long idx,
                                        const long long *nb)
 {
     const double phg = D->alpha * c[idx] + D->beta;
@@ -897,7 +901,7 @@ __device__ __forceinline__ double Ls_h(const LevelDesc<double> *D, const double 
     return -(2.0 * D->ks_half) * phg * s[idx] * c[idx] + D->d_half_h2 * diff;
 }
 
-__device__ __forceinline__ double Lc_h(const LevelDesc<double> *D, const double *s, const double *c, long long idx)
+__device__ __forceinline__ double Lc_h(const LevelDesc<double> *D, gptr<double> s, gptr<double> c, long long idx)
 {
     return -(2.0 * D->kc_half) * (D->alpha * c[idx] + D->beta) * s[idx] * c[idx];
 }
@@ -912,7 +916,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_explicit_half(const LevelDesc<dou
     long long idx;
     int i, j, k;
     if (!node_of<double, DIM>(D, w, lane, idx, i, j, k)) return;
-    const double *sn = D->sn, *cn = D->cn;
+    const gptr<double> sn = D->sn, cn = D->cn;
     const int r = D->cmap[idx];
     const int na = D->na;
     if (item_kind(w) < 2) {
@@ -943,7 +947,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_residual(const LevelDesc<double> 
     int i, j, k;
     unsigned long long bits = 0;
     if (node_of<double, DIM>(D, w, lane, idx, i, j, k)) {
-        const double *s = D->s, *c = D->c;
+        const gptr<double> s = D->s, c = D->c;
         double fs;
         if (item_kind(w) < 2) {
             long long nb[2 * DIM];
@@ -1289,7 +1293,7 @@ __global__ __launch_bounds__(1024) void k_coarse_apply(const LevelDesc<T> *__res
                                                        const int *__restrict__ c2s, const double *__restrict__ Ainv)
 {
     extern __shared__ double b[];
-    wg_coarse_apply<T>(descs + lev, c2s, Ainv, b);
+    wg_coarse_apply<T>(descs + lev, gptr<const int>{c2s}, gptr<const double>{Ainv}, b);
 }
 
 // ---------------------------------------------------------------------------

@@ -36,6 +36,28 @@ constexpr int kMaxBandEntries3 = 27;       // 3^band_steps (3-D)
 
 enum : uint8_t { kOut = 0, kIn = 1, kGhost = 2 };
 
+// A device pointer held in a descriptor or an argument block.  On the device,
+// subscripts go through the global address space, so that loads and stores
+// through it compile to global (not flat) memory instructions: these take a
+// scalar base address and are counted apart from the scalar loads of the
+// descriptor itself.  Offsetting keeps the type; converting to T * gives a
+// generic pointer (flat accesses).
+template <typename T>
+struct gptr {
+    T *p;
+    __host__ __device__ gptr &operator=(T *q)
+    {
+        p = q;
+        return *this;
+    }
+    __host__ __device__ operator T *() const { return p; }
+    __host__ __device__ gptr operator+(long long i) const { return gptr{p + i}; }
+    __device__ __attribute__((address_space(1))) T &operator[](long long i) const
+    {
+        return ((__attribute__((address_space(1))) T *)p)[i];
+    }
+};
+
 template <typename T>
 struct LevelDesc {
     int dim, n, Wp, nst;
@@ -49,43 +71,43 @@ struct LevelDesc {
     T d_half_h2; // d / (2 h^2)
     int ghost_c_new, pad1;
     // per-node arrays (split layout)
-    const uint8_t *type;     // kOut / kIn / kGhost
-    const uint8_t *ext;      // 1 for ghosts and band nodes reached by the extension
-    const int *cmap;         // storage -> compact index, -1 if inactive
-    T *s, *c;                // linearisation point
-    T *rhs_s, *rhs_c;
-    T *x_s, *x_c;
-    T *r_s, *r_c;
+    gptr<const uint8_t> type;     // kOut / kIn / kGhost
+    gptr<const uint8_t> ext;      // 1 for ghosts and band nodes reached by the extension
+    gptr<const int> cmap;         // storage -> compact index, -1 if inactive
+    gptr<T> s, c;                // linearisation point
+    gptr<T> rhs_s, rhs_c;
+    gptr<T> x_s, x_c;
+    gptr<T> r_s, r_c;
     // ghost table (structure of arrays, entry k of ghost q at k * ng + q)
-    const int *g_idx;        // storage index of ghost q
-    const int *g_ijk;        // packed grid coordinates i | j << 11 | k << 22
-    const int *g_st;         // storage index of stencil node k
-    const int *g_stg;        // ghost index of stencil node k if it is a ghost with nonzero weight, else -1
-    const T *g_w;            // boundary-row weight of stencil node k
-    T *g_buf0, *g_buf1;      // Jacobi buffers of the ghost values of delta s
+    gptr<const int> g_idx;        // storage index of ghost q
+    gptr<const int> g_ijk;        // packed grid coordinates i | j << 11 | k << 22
+    gptr<const int> g_st;         // storage index of stencil node k
+    gptr<const int> g_stg;        // ghost index of stencil node k if it is a ghost with nonzero weight, else -1
+    gptr<const T> g_w;            // boundary-row weight of stencil node k
+    gptr<T> g_buf0, g_buf1;      // Jacobi buffers of the ghost values of delta s
     // ghost_sweeps Jacobi sweeps composed into one linear map (CSR over ghosts):
     // delta s_q <- sum_e go_a[e] delta s_{go_col[e]} + go_b[e] b_{go_col[e]}, b the
     // ghost rows' right-hand sides minus their non-ghost stencil terms
-    const int *go_ptr, *go_col;
-    const T *go_a, *go_b;
+    gptr<const int> go_ptr, go_col;
+    gptr<const T> go_a, go_b;
     // 2-D: the b-part folded into the map, b = rhs - W_GI x_I, so that
     // delta s_q <- sum_e go_a[e] s_old + go_b[e] rhs_s[ghost go_col[e]] - sum_f gc_w[f] x_s[gc_idx[f]],
     // with C = B W_GI composed over inside storage indices (null in 3-D)
-    const int *gc_ptr, *gc_idx;
-    const T *gc_w;
+    gptr<const int> gc_ptr, gc_idx;
+    gptr<const T> gc_w;
     // band of inactive nodes used by the boundary-defect restriction
-    const int *b_idx;        // storage index of band node b
-    const int *b_cnt;        // number of ghost sources
-    const int *b_src;        // entry j at j * nb + b: storage index of a ghost
-    const T *b_wt;           // its weight
+    gptr<const int> b_idx;        // storage index of band node b
+    gptr<const int> b_cnt;        // number of ghost sources
+    gptr<const int> b_src;        // entry j at j * nb + b: storage index of a ghost
+    gptr<const T> b_wt;           // its weight
     // max-norm slots of this domain: norm k occupies kNormSlots words at norms + k * norm_stride
-    unsigned long long *norms;
+    gptr<unsigned long long> norms;
     long long norm_stride;
     // level 0 only: data of the Crank-Nicolson step (section 3.1)
-    double *sn, *cn;         // W^n (split layout); W^{n+1} is written back on commit
-    double *bs, *bc;         // explicit half of the step
-    const double *fn, *fnp1; // compact [f1 | f2] source terms at t_n and t_{n+1}, or null
-    const double *sb;        // per-ghost boundary values at t_{n+1}, or null (then sb_const)
+    gptr<double> sn, cn;         // W^n (split layout); W^{n+1} is written back on commit
+    gptr<double> bs, bc;         // explicit half of the step
+    gptr<const double> fn, fnp1; // compact [f1 | f2] source terms at t_n and t_{n+1}, or null
+    gptr<const double> sb;        // per-ghost boundary values at t_{n+1}, or null (then sb_const)
     double sb_const;
 };
 

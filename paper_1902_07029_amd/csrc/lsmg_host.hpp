@@ -18,7 +18,7 @@ constexpr int kMaxLevels = 16;
 constexpr int kTailStageInts = 6144;
 
 struct TailLevel {
-    const int *in_ijk;   // packed coordinates of the inside nodes, colour 0 then colour 1
+    gptr<const int> in_ijk;  // packed coordinates of the inside nodes, colour 0 then colour 1
     int nin0, nin1;
     int sweeps;          // ghost relaxations per smoothing step on this level
     int soff;            // offset of the level's node lists in the tail's LDS copy:
@@ -50,11 +50,11 @@ struct TailArgs {
     int d0, l0, nlev, nu1, nu2;
     int nstage;          // ints of the LDS copy of the node lists (sum over the tail's levels)
     int gamma, pad;      // cycle index (1 V, 2 W)
-    const int *c2s;      // coarsest level: compact -> storage
-    const double *ainv;  // coarsest level: explicit inverse (FP64, 2Na x 2Na)
+    gptr<const int> c2s;      // coarsest level: compact -> storage
+    gptr<const double> ainv;  // coarsest level: explicit inverse (FP64, 2Na x 2Na)
     TailLevel lev[kMaxLevels];
     // coarse tail held in LDS (when the hierarchy's tail fits)
-    const uint32_t *tab;        // table image
+    gptr<const uint32_t> tab;   // table image
     int tab_words, nvals, nints, ngmax;
     TailLdsLevel ll[kMaxLevels];
 };

@@ -124,8 +124,8 @@ __device__ __forceinline__ void restrict_vals(uint8_t *ex, const uint8_t *act, c
 
 // sum_q M[r][q] v[q] subtracted from (SIGN < 0) or added to acc, with the row's
 // entries fetched eight at a time and summed in order q = 0 .. na-1
-template <int SIGN>
-__device__ __forceinline__ double row_dot(const double *__restrict__ row, const double *v, int na, double acc)
+template <int SIGN, typename P>
+__device__ __forceinline__ double row_dot(P row, const double *v, int na, double acc)
 {
     for (int q0 = 0; q0 < na; q0 += 8) {
         double m[8];

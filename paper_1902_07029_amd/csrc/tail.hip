@@ -463,10 +463,10 @@ __device__ void lds_prolong(const LdsLevel<T> &Z, const LdsLevel<T> &C)
 
 // x = A^{-1} rhs on the coarsest level through the Schur complement (as the HBM tail)
 template <typename T>
-__device__ void lds_coarse(const LevelDesc<T> *D, const LdsLevel<T> &Z, const double *__restrict__ Ainv, double *b)
+__device__ void lds_coarse(const LevelDesc<T> *D, const LdsLevel<T> &Z, gptr<const double> Ainv, double *b)
 {
     const int na = D->na;
-    const double *Sinv = Ainv, *Jsc = Ainv + (long long)na * na, *cs = Ainv + 2LL * na * na, *cc = cs + na;
+    const gptr<const double> Sinv = Ainv, Jsc = Ainv + (long long)na * na, cs = Ainv + 2LL * na * na, cc = cs + na;
     double *rs = b, *rc = b + na, *t = b + 2 * na, *u = b + 3 * na;
     for (int r = threadIdx.x; r < na; r += blockDim.x) {
         const int p = Z.perm[r];
