@@ -84,6 +84,21 @@ def smoother_bytes(c2g, ni, ng, n, dim, P):
     return out
 
 
+def fused_sweep_bytes(c2g, ni, ng, n, P):
+    """Algorithmic bytes of one fused 2-D sweep launch (both colours, k_smooth_rb):
+    reads s, c and the type byte at every active node, the right-hand side at the
+    inside nodes, the old correction (2P) at the black active nodes and the red
+    ghosts (the red corrections reach the black half-sweep through LDS), writes the
+    correction (2P) at every active node into the other copy, and snapshots each
+    ghost's correction (index 4 + P read, P written)."""
+    g = c2g.astype(np.int64)
+    col = (g % n + (g // n) % n) & 1
+    black_active = int(np.sum(col == 1))
+    red_ghosts = int(np.sum(col[ni:] == 0))
+    return ((2 * P + 1) * (ni + ng) + 2 * P * ni + 2 * P * (black_active + red_ghosts) + 2 * P * (ni + ng)
+            + ng * (4 + 2 * P))
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in ("kernels.hip", "lsmg_dev.hpp"):
@@ -149,7 +164,15 @@ def oracle_params(H):
 
 # ---------------------------------------------------------------- profiling helpers
 
-SMOOTH_KERNEL = "k_smooth_colour"
+SMOOTH_KERNELS = ("k_smooth_rb", "k_smooth_colour")
+
+
+def _smooth_kernel(rows):
+    """The smoother of a profile: the fused 2-D sweep where it ran, else the per-colour one."""
+    for k in SMOOTH_KERNELS:
+        if any(k in r["Kernel_Name"] for r in rows):
+            return k
+    raise SystemExit("no smoother dispatches in the profile")
 
 
 def _csv_rows(directory, suffix):
@@ -184,11 +207,10 @@ def copy_probe(mib):
 
 
 def _finest(rows, key):
-    """Rows of the finest-level smoother: the k_smooth_colour dispatches whose grid is
-    at least half the largest grid (the next coarser level has about a quarter)."""
-    sm = [r for r in rows if SMOOTH_KERNEL in r["Kernel_Name"]]
-    if not sm:
-        raise SystemExit("no smoother dispatches in the profile")
+    """Rows of the finest-level smoother: the dispatches of the smoother kernel whose
+    grid is at least half the largest grid (the next coarser level has about a quarter)."""
+    kern = _smooth_kernel(rows)
+    sm = [r for r in rows if kern in r["Kernel_Name"]]
     gmax = max(int(r[key]) for r in sm)
     return [r for r in sm if 2 * int(r[key]) >= gmax]
 
@@ -203,12 +225,13 @@ def trace_summary(directory):
         print(f"{int(r['Calls']):7d} {t / 1e6:9.3f} {100 * t / total:5.1f}% {float(r['AverageNs']) / 1e3:8.2f}  "
               f"{_short(r['Name'])}")
     trace = _csv_rows(directory, "kernel_trace.csv")
-    sm = [r for r in trace if SMOOTH_KERNEL in r["Kernel_Name"]]
+    kern = _smooth_kernel(trace)
+    sm = [r for r in trace if kern in r["Kernel_Name"]]
     by = {}
     for r in sm:
         g = int(r["Grid_Size_X"]) if "Grid_Size_X" in r else int(r["Grid_Size"])
         by.setdefault(g, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    print(f"\n{SMOOTH_KERNEL} by grid size (threads), from the kernel trace:")
+    print(f"\n{kern} by grid size (threads), from the kernel trace:")
     for g in sorted(by, reverse=True):
         v = by[g]
         print(f"  grid {g:9d}  launches {len(v):6d}  avg {sum(v) / len(v) / 1e3:8.2f} us")
@@ -242,7 +265,8 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, prec
     sw = _pmc_copy(copy_write_dir, "WRITE_SIZE", mib)
     fetch_b = f_kib * 1024 * sf
     write_b = w_kib * 1024 * sw
-    key = f"smooth_colour:{workload}:p{precision}"
+    kern = _smooth_kernel(_csv_rows(fetch_dir, "counter_collection.csv"))
+    key = f"{kern[2:]}:{workload}:p{precision}"
     path = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
     data[key] = dict(bytes_per_launch=int(fetch_b + write_b), fetch_bytes=int(fetch_b), write_bytes=int(write_b),
@@ -259,7 +283,8 @@ def run_single(args):
     w = WORKLOADS[args.workload]
     prec = args.precision if args.precision is not None else 0
     bc = 1 if args.bc == "neumann" else 0
-    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec, bc=bc, fmg=args.fmg, **w.get("params", {}))
+    params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec, bc=bc, fmg=args.fmg,
+                                 fused_sweep=args.fused, **w.get("params", {}))
     phi_np = levelset(w)
     lo, hi = box_of(w)
     dt = dt_of(w)
@@ -310,16 +335,30 @@ def run_single(args):
     if launches == 0:
         raise RuntimeError("no timed launches of the dominant kernel")
 
-    # roofline of the dominant kernel: one colour of the finest-level smoother
+    # roofline of the dominant kernel, the finest-level smoother: in 2-D pairs of
+    # smoothing steps run as fused sweeps (both colours per launch), an odd step
+    # as one launch per colour; the bytes per launch are averaged over one cycle
     P = 8 if prec == 0 else 4
-    b0, b1 = smoother_bytes(H.compact_to_grid(0).cpu().numpy(), ni, ng, w["n"], w["dim"], P)
-    bytes_per_launch = 0.5 * (b0 + b1)
+    c2g0 = H.compact_to_grid(0).cpu().numpy()
+    b0, b1 = smoother_bytes(c2g0, ni, ng, w["n"], w["dim"], P)
+    eff = H.params
+    if w["dim"] == 2 and eff.fused_sweep and eff.ghost_c_new:
+        bf = fused_sweep_bytes(c2g0, ni, ng, w["n"], P)
+        pairs = eff.nu1 // 2 + eff.nu2 // 2
+        single = eff.nu1 % 2 + eff.nu2 % 2
+        bytes_per_launch = (2 * pairs * bf + single * (b0 + b1)) / (2 * pairs + 2 * single)
+        kname = "k_smooth_rb (finest level, both colours of a sweep)" if single == 0 else \
+            "k_smooth_rb and k_smooth_colour (finest level)"
+        tkey = "smooth_rb"
+    else:
+        bytes_per_launch = 0.5 * (b0 + b1)
+        kname, tkey = "k_smooth_colour (finest level, one colour)", "smooth_colour"
     avg_s = prof_ms * 1e-3 / launches
     achieved = bytes_per_launch / avg_s / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=load_traffic("smooth_colour", args.workload, prec),
-                    kernel="k_smooth_colour (finest level, one colour)", launches=launches,
+                    traffic=load_traffic(tkey, args.workload, prec),
+                    kernel=kname, launches=launches,
                     avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(bytes_per_launch),
                     timing_pass_ms_per_step=round(prof_elapsed * 1e3 / args.steps, 3))
 
@@ -357,6 +396,7 @@ def run_single(args):
             "unknowns": unknowns, "inside": ni, "ghost": ng, "levels": H.nlev,
             "cycle": f"{'VW'[H.params.cycle_gamma - 1]}({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps "
                      f"({H.params.ghost_sweeps_coarse} where d dt/h^2 < {H.params.sweeps_lambda})",
+            "fused_sweep": bool(w["dim"] == 2 and H.params.fused_sweep),
             "build_ms": round(build_ms, 1),
         },
         "vcycles": cycles,
@@ -684,6 +724,8 @@ def main():
     ap.add_argument("--fmg", type=int, default=0, choices=(0, 1, 2),
                     help="single domains: full multigrid as the first iteration of the first (1) or every (2) "
                          "linear solve of a step")
+    ap.add_argument("--fused", type=int, default=1, choices=(0, 1),
+                    help="2-D: both colours of a smoothing sweep in one launch (1) or one launch per colour (0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true", help="batch64: skip the sequential FP64 comparison")
     ap.add_argument("--cpu-budget", type=float, default=20.0)

@@ -89,6 +89,10 @@ typedef struct {
                             * hand side restricted to every level, the coarsest problem solved, then
                             * on each finer level the prolongated solution as the start of one
                             * cycle); batches take 0 only */
+    int fused_sweep;       /* 2-D: 1 runs both colours of a smoothing sweep in one launch over
+                            * tiles of rows, the red half-sweep recomputed on a one-node halo
+                            * (same bits as one launch per colour); 0 one launch per colour.
+                            * Batches use one launch per colour */
 } lsmg_params;
 
 typedef struct lsmg_hierarchy lsmg_hierarchy;
@@ -106,7 +110,7 @@ typedef struct {
 /* Default parameters: the model data of eq. (dataeq), tau_s = 0.9 (section
  * 3.5.1), V(2,2), automatic ghost sweeps (0, 0, 0), 3 band layers, ghost_c_new = 1,
  * coarsest 5, FP64, newton_tol 1e-10, newton_max 20, lin_rtol 1e-3,
- * cycles_max 30, Dirichlet boundary, V-cycles. */
+ * cycles_max 30, Dirichlet boundary, V-cycles, no full multigrid, fused 2-D sweeps. */
 void lsmg_default_params(lsmg_params *p);
 
 /* Build the grid hierarchy of one domain (sections 3.2-3.3, 3.5).
@@ -285,7 +289,8 @@ lsmg_status lsmg_vcycle(lsmg_hierarchy *h, int level, const double *d_rhs, doubl
 
 /* Kernel classes that can be timed. */
 enum {
-    LSMG_KERNEL_SMOOTH = 0,    /* one colour of the collective red-black sweep */
+    LSMG_KERNEL_SMOOTH = 0,    /* one smoothing launch: one colour of the collective red-black
+                                * sweep, or both colours of a fused 2-D sweep (fused_sweep) */
     LSMG_KERNEL_DEFECT = 1,    /* defect r = rhs - J x */
     LSMG_KERNEL_RESTRICT = 2,  /* restriction onto `level` from level - 1 */
     LSMG_KERNEL_PROLONG = 3,   /* prolongation onto `level` from level + 1 */

@@ -48,7 +48,8 @@ lsmg_status check_params(const lsmg_params *p)
         !(p->sweeps_lambda >= 0.0) || p->band_steps < 0 ||
         p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
         !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1) ||
-        (p->bc != 0 && p->bc != 1) || p->cycle_gamma < 1 || p->cycle_gamma > 2 || p->fmg < 0 || p->fmg > 2)
+        (p->bc != 0 && p->bc != 1) || p->cycle_gamma < 1 || p->cycle_gamma > 2 || p->fmg < 0 || p->fmg > 2 ||
+        (p->fused_sweep != 0 && p->fused_sweep != 1))
         return fail(LSMG_EINVAL, "invalid solver parameters");
     return LSMG_OK;
 }
@@ -220,27 +221,46 @@ const LevelDesc<double> *descs<double>(const lsmg_hierarchy *H) { return H->d64;
 template <>
 const LevelDesc<float> *descs<float>(const lsmg_hierarchy *H) { return H->d32; }
 
+// `count` smoothing steps on level l (section 3.5.1: a collective red-black
+// sweep, then the ghost relaxation)
 template <typename T>
-void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s)
+void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s, int count)
 {
     const Level &Lv = H->L[l];
     const LevelDesc<T> *d = descs<T>(H);
     if (Lv.gc_ptr) {
-        // 2-D: the black launch also snapshots the ghosts' delta s (its list is
-        // followed by the ghost items), then one launch applies the folded map
-        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(0), Lv.nseg[0], 0, prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
-        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(1), Lv.nseg[1] + Lv.nghc, 1,
-                                prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
-        launch_ghost_apply<T>(H->dim, d, Lv.w_gh4(), Lv.nghc4, prof_exec(H, s, LSMG_KERNEL_GHOST, l));
+        // 2-D, folded ghost map.  Pairs of steps with fused sweeps: the first reads
+        // the corrections' first copy and writes the second, the folded map then
+        // works on the second, and the next step returns to the first
+        if (H->p.fused_sweep && Lv.tiles) {
+            for (; count >= 2; count -= 2) {
+                for (int flip = 0; flip < 2; ++flip) {
+                    launch_smooth_rb<T>(d, Lv.tiles, Lv.ntile, Lv.w_gh(), Lv.nghc, flip,
+                                        prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
+                    launch_ghost_apply<T>(H->dim, d, Lv.w_gh4(), Lv.nghc4, 1 - flip,
+                                          prof_exec(H, s, LSMG_KERNEL_GHOST, l));
+                }
+            }
+        }
+        // one launch per colour: the black launch also snapshots the ghosts' delta s
+        // (its list is followed by the ghost items), then one launch applies the map
+        for (; count > 0; --count) {
+            launch_smooth_colour<T>(H->dim, d, Lv.w_seg(0), Lv.nseg[0], 0, prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
+            launch_smooth_colour<T>(H->dim, d, Lv.w_seg(1), Lv.nseg[1] + Lv.nghc, 1,
+                                    prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
+            launch_ghost_apply<T>(H->dim, d, Lv.w_gh4(), Lv.nghc4, 0, prof_exec(H, s, LSMG_KERNEL_GHOST, l));
+        }
         return;
     }
-    for (int colour = 0; colour < 2; ++colour)
-        launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour,
-                                prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
-    const Exec xb = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
-    const Exec xa = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
-    launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.w_gh4(), Lv.nghc4, Lv.ng, Lv.sweeps, Lv.go_ptr != nullptr,
-                    xb, xa);
+    for (; count > 0; --count) {
+        for (int colour = 0; colour < 2; ++colour)
+            launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour,
+                                    prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
+        const Exec xb = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
+        const Exec xa = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
+        launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.w_gh4(), Lv.nghc4, Lv.ng, Lv.sweeps,
+                        Lv.go_ptr != nullptr, xb, xa);
+    }
 }
 
 TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
@@ -295,7 +315,7 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
                            tail_args(H, l, 0).nstage <= kTailStageInts, Exec(s));
         return;
     }
-    for (int i = 0; i < H->p.nu1; ++i) smooth_level<T>(H, l, s);
+    smooth_level<T>(H, l, s, H->p.nu1);
     launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), -1, prof_exec(H, s, LSMG_KERNEL_DEFECT, l));
     launch_band<T>(d, Lv.w_band(), Lv.nbandc, Exec(s));
     const Level &C = H->L[l + 1];
@@ -305,7 +325,7 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
     const int reps = l + 1 == H->nlev - 1 ? 1 : H->p.cycle_gamma;
     for (int i = 0; i < reps; ++i) vcycle_rec<T>(H, l + 1, s);
     launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), prof_exec(H, s, LSMG_KERNEL_PROLONG, l));
-    for (int i = 0; i < H->p.nu2; ++i) smooth_level<T>(H, l, s);
+    smooth_level<T>(H, l, s, H->p.nu2);
 }
 
 // full multigrid from a zero correction on level 0: the right-hand side
@@ -477,6 +497,10 @@ lsmg_status build_level_arrays(lsmg_hierarchy *H, int l, const double *phi, uint
     LSMGCHK(H->zalloc(&Lv.x_c, Lv.ssize));
     LSMGCHK(H->zalloc(&Lv.r_s, Lv.ssize));
     LSMGCHK(H->zalloc(&Lv.r_c, Lv.ssize));
+    if (dim == 2) {
+        LSMGCHK(H->zalloc(&Lv.x2_s, Lv.ssize));
+        LSMGCHK(H->zalloc(&Lv.x2_c, Lv.ssize));
+    }
     return LSMG_OK;
 }
 
@@ -525,6 +549,37 @@ lsmg_status build_band(lsmg_hierarchy *H, int l, const double *phi, uint8_t *fla
     return LSMG_OK;
 }
 
+// tiles of the fused 2-D sweep: kRbRows rows x 64 positions holding an inside or
+// ghost node of either colour
+lsmg_status build_tiles(lsmg_hierarchy *H, int l)
+{
+    Level &Lv = H->L[l];
+    std::vector<uint8_t> type((size_t)Lv.ssize);
+    HIPCHK(hipMemcpyAsync(type.data(), Lv.type, type.size(), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    std::vector<int4> tiles;
+    for (long long y0 = 0; y0 < Lv.rows; y0 += kRbRows)
+        for (int p0 = 0; p0 < Lv.Wp; p0 += kWave) {
+            bool any = false;
+            for (int c = 0; c < 2 && !any; ++c)
+                for (long long y = y0; y < y0 + kRbRows && y < Lv.rows && !any; ++y)
+                    for (int p = p0; p < p0 + kWave && p < Lv.Wp; ++p) {
+                        const uint8_t t = type[(size_t)(c * Lv.cs + y * Lv.Wp + p)];
+                        if (t == kIn || t == kGhost) {
+                            any = true;
+                            break;
+                        }
+                    }
+            if (any) tiles.push_back(make_int4(l << 2, (int)y0, p0, 0));
+        }
+    Lv.ntile = (int)tiles.size();
+    if (tiles.empty()) return LSMG_OK;
+    LSMGCHK(H->alloc(&Lv.tiles, Lv.ntile));
+    HIPCHK(hipMemcpyAsync(Lv.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    return LSMG_OK;
+}
+
 lsmg_status build_items(lsmg_hierarchy *H, int l)
 {
     Level &Lv = H->L[l];
@@ -560,6 +615,7 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
                               H->stream));
     HIPCHK(hipStreamSynchronize(H->stream));
     if (seg[0]) (void)hipFree(seg[0]);
+    if (H->dim == 2) LSMGCHK(build_tiles(H, l));
     return LSMG_OK;
 }
 
@@ -575,6 +631,10 @@ lsmg_status build_f32(lsmg_hierarchy *H)
         LSMGCHK(H->zalloc(&Lv.x_c32, Lv.ssize));
         LSMGCHK(H->zalloc(&Lv.r_s32, Lv.ssize));
         LSMGCHK(H->zalloc(&Lv.r_c32, Lv.ssize));
+        if (H->dim == 2) {
+            LSMGCHK(H->zalloc(&Lv.x2_s32, Lv.ssize));
+            LSMGCHK(H->zalloc(&Lv.x2_c32, Lv.ssize));
+        }
         LSMGCHK(H->alloc(&Lv.g_w32, (long long)Lv.ng * H->nst));
         LSMGCHK(H->zalloc(&Lv.g_buf0_32, Lv.ng));
         LSMGCHK(H->zalloc(&Lv.g_buf1_32, Lv.ng));
@@ -595,7 +655,8 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
 {
     Level &Lv = H->L[l];
     for (void *p : {(void *)Lv.go_ptr, (void *)Lv.go_col, (void *)Lv.go_a, (void *)Lv.go_b, (void *)Lv.go_a32,
-                    (void *)Lv.go_b32, (void *)Lv.gc_ptr, (void *)Lv.gc_idx, (void *)Lv.gc_w, (void *)Lv.gc_w32}) {
+                    (void *)Lv.go_b32, (void *)Lv.gc_ptr, (void *)Lv.gc_idx, (void *)Lv.gc_w, (void *)Lv.gc_w32,
+                    (void *)Lv.go_sidx}) {
         if (!p) continue;
         (void)hipFree(p);
         for (auto &q : H->ghost_ops)
@@ -604,7 +665,7 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     Lv.go_ptr = Lv.go_col = nullptr;
     Lv.go_a = Lv.go_b = nullptr;
     Lv.go_a32 = Lv.go_b32 = nullptr;
-    Lv.gc_ptr = Lv.gc_idx = nullptr;
+    Lv.gc_ptr = Lv.gc_idx = Lv.go_sidx = nullptr;
     Lv.gc_w = nullptr;
     Lv.gc_w32 = nullptr;
     Lv.go_bytes = 0;
@@ -679,9 +740,15 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     LSMGCHK(up((void **)&Lv.go_b32, vb32.data(), sizeof(float) * nnz));
     if (H->dim == 2) {
         // C = B W_GI: the inside-node part of the b-terms, over storage indices
-        std::vector<int> st((size_t)ng * nst);
+        std::vector<int> st((size_t)ng * nst), gidx(ng);
         HIPCHK(hipMemcpyAsync(st.data(), Lv.g_st, sizeof(int) * st.size(), hipMemcpyDeviceToHost, H->stream));
+        HIPCHK(hipMemcpyAsync(gidx.data(), Lv.g_idx, sizeof(int) * ng, hipMemcpyDeviceToHost, H->stream));
         HIPCHK(hipStreamSynchronize(H->stream));
+        // per entry, the storage index of its ghost: the b-part's right-hand side is read
+        // without going through g_idx
+        std::vector<int> sx(nnz);
+        for (size_t e = 0; e < nnz; ++e) sx[e] = gidx[col[e]];
+        LSMGCHK(up((void **)&Lv.go_sidx, sx.data(), sizeof(int) * nnz));
         std::vector<int> cptr(ng + 1, 0), cidx;
         std::vector<double> cw;
         std::vector<std::pair<int, double>> rowv;
@@ -742,11 +809,11 @@ void make_descs(lsmg_hierarchy *H)
         D.rows = Lv.rows; D.cs = Lv.cs; D.lo = H->lo; D.h = Lv.h;
         D.type = Lv.type; D.ext = Lv.ext; D.cmap = Lv.cmap;
         D.s = Lv.s; D.c = Lv.c; D.rhs_s = Lv.rhs_s; D.rhs_c = Lv.rhs_c; D.x_s = Lv.x_s; D.x_c = Lv.x_c;
-        D.r_s = Lv.r_s; D.r_c = Lv.r_c;
+        D.r_s = Lv.r_s; D.r_c = Lv.r_c; D.x2_s = Lv.x2_s; D.x2_c = Lv.x2_c;
         D.g_idx = Lv.g_idx; D.g_ijk = Lv.g_ijk; D.g_st = Lv.g_st; D.g_stg = Lv.g_stg; D.g_w = Lv.g_w;
         D.g_buf0 = Lv.g_buf0; D.g_buf1 = Lv.g_buf1;
         D.go_ptr = Lv.go_ptr; D.go_col = Lv.go_col; D.go_a = Lv.go_a; D.go_b = Lv.go_b;
-        D.gc_ptr = Lv.gc_ptr; D.gc_idx = Lv.gc_idx; D.gc_w = Lv.gc_w;
+        D.gc_ptr = Lv.gc_ptr; D.gc_idx = Lv.gc_idx; D.gc_w = Lv.gc_w; D.go_sidx = Lv.go_sidx;
         D.b_idx = Lv.b_idx; D.b_cnt = Lv.b_cnt; D.b_src = Lv.b_src; D.b_wt = Lv.b_wt;
         D.norms = H->d_norms; D.norm_stride = kNormSlots;
         if (l == 0) {
@@ -760,11 +827,11 @@ void make_descs(lsmg_hierarchy *H)
         E.rows = D.rows; E.cs = D.cs; E.lo = D.lo; E.h = D.h;
         E.type = D.type; E.ext = D.ext; E.cmap = D.cmap;
         E.s = Lv.s32; E.c = Lv.c32; E.rhs_s = Lv.rhs_s32; E.rhs_c = Lv.rhs_c32; E.x_s = Lv.x_s32; E.x_c = Lv.x_c32;
-        E.r_s = Lv.r_s32; E.r_c = Lv.r_c32;
+        E.r_s = Lv.r_s32; E.r_c = Lv.r_c32; E.x2_s = Lv.x2_s32; E.x2_c = Lv.x2_c32;
         E.g_idx = D.g_idx; E.g_ijk = D.g_ijk; E.g_st = D.g_st; E.g_stg = D.g_stg; E.g_w = Lv.g_w32;
         E.g_buf0 = Lv.g_buf0_32; E.g_buf1 = Lv.g_buf1_32;
         E.go_ptr = Lv.go_ptr; E.go_col = Lv.go_col; E.go_a = Lv.go_a32; E.go_b = Lv.go_b32;
-        E.gc_ptr = Lv.gc_ptr; E.gc_idx = Lv.gc_idx; E.gc_w = Lv.gc_w32;
+        E.gc_ptr = Lv.gc_ptr; E.gc_idx = Lv.gc_idx; E.gc_w = Lv.gc_w32; E.go_sidx = Lv.go_sidx;
         E.b_idx = D.b_idx; E.b_cnt = D.b_cnt; E.b_src = D.b_src; E.b_wt = Lv.b_wt32;
         E.norms = D.norms; E.norm_stride = D.norm_stride;
     }
@@ -1036,6 +1103,7 @@ void lsmg_default_params(lsmg_params *p)
     p->bc = 0;
     p->cycle_gamma = 1;
     p->fmg = 0;
+    p->fused_sweep = 1;
 }
 
 const char *lsmg_last_error(void) { return g_err.c_str(); }
@@ -1148,7 +1216,9 @@ lsmg_status lsmg_estimate_bytes(const lsmg_grid *grid, const lsmg_params *params
         const long long rows = grid->dim == 2 ? nl : (long long)nl * nl;
         const size_t ss = (size_t)(2 * rows * Wp);
         if (l == 0) ss0 = ss;
-        full += ss * (2 + 4 + 8 * sizeof(double) + (params->precision == 1 ? 8 * sizeof(float) : 0));
+        // 2-D: a second copy of the corrections for the fused sweeps
+        const size_t nv = grid->dim == 2 ? 10 : 8;
+        full += ss * (2 + 4 + nv * sizeof(double) + (params->precision == 1 ? nv * sizeof(float) : 0));
         if (nl <= params->coarsest_n || (nl - 1) % 2) break;
         nl = (nl - 1) / 2 + 1;
     }
@@ -1403,7 +1473,7 @@ lsmg_status lsmg_smooth(lsmg_hierarchy *h, int level, const double *d_rhs, doubl
     const Level &Lv = h->L[level];
     scatter<double>(h, level, d_rhs, Lv.rhs_s, Lv.rhs_c);
     scatter<double>(h, level, d_x, Lv.x_s, Lv.x_c);
-    for (int i = 0; i < nsweeps; ++i) smooth_level<double>(h, level, h->stream);
+    smooth_level<double>(h, level, h->stream, nsweeps);
     gather<double>(h, level, Lv.x_s, Lv.x_c, d_x);
     return LSMG_OK;
 }

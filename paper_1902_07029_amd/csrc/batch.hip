@@ -277,7 +277,7 @@ void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s)
                                 bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
         launch_smooth_colour<T>(B->dim, d, items(B, S.seg1g), S.seg1g.n, 1,
                                 bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
-        launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n,
+        launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 0,
                               bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n));
         return;
     }
@@ -389,7 +389,7 @@ void tune_launch(lsmg_batch *B, const BSize &S, int cls, const Exec &x)
         break;
     case kTGhost:
         if (B->dim == 2) {
-            launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, x);
+            launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 0, x);
             break;
         }
         launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, items(B, S.gh4), S.gh4.n, 0, B->p.ghost_sweeps, true, x,

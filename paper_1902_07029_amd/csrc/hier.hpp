@@ -47,6 +47,10 @@ struct Level {
     float *s32 = nullptr, *c32 = nullptr, *rhs_s32 = nullptr, *rhs_c32 = nullptr, *x_s32 = nullptr, *x_c32 = nullptr,
           *r_s32 = nullptr, *r_c32 = nullptr, *g_w32 = nullptr, *g_buf0_32 = nullptr, *g_buf1_32 = nullptr,
           *b_wt32 = nullptr;
+    double *x2_s = nullptr, *x2_c = nullptr;    // 2-D: second copy of the corrections
+    float *x2_s32 = nullptr, *x2_c32 = nullptr;
+    int4 *tiles = nullptr;                      // 2-D: tiles of the fused sweep (rows x 64 positions)
+    int ntile = 0;
     int sweeps = 0;                             // ghost relaxations per smoothing step
     size_t go_bytes = 0;                        // device bytes of the composed ghost relaxation
     int *in_ijk = nullptr;                      // packed coordinates of inside nodes, colour 0 then 1
@@ -55,6 +59,7 @@ struct Level {
     double *go_a = nullptr, *go_b = nullptr;
     float *go_a32 = nullptr, *go_b32 = nullptr;
     int *gc_ptr = nullptr, *gc_idx = nullptr;   // 2-D: the folded b-part (C = B W_GI)
+    int *go_sidx = nullptr;                     // 2-D: storage index of each entry's ghost
     double *gc_w = nullptr;
     float *gc_w32 = nullptr;
     // [seg colour 0 | seg colour 1 | ghost chunks of 64 | band chunks | ghost chunks of 4 (3-D)]

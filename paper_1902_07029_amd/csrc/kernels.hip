@@ -139,9 +139,21 @@ __device__ __forceinline__ void ghost_b_elem(const LevelDesc<T> *D, int q)
 {
     const int ng = D->ng;
     const long long g = D->g_idx[q];
+    // every stencil entry names a valid node (zero-weight entries the ghost itself), so all
+    // gathers are issued unconditionally and the ghost entries are dropped afterwards
+    int st[NST];
+    bool gh[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+        st[k] = D->g_st[k * ng + q];
+        gh[k] = D->g_stg[k * ng + q] >= 0;
+    }
     T val[NST];
 #pragma unroll
-    for (int k = 0; k < NST; ++k) val[k] = D->g_stg[k * ng + q] >= 0 ? T(0) : D->x_s[D->g_st[k * ng + q]];
+    for (int k = 0; k < NST; ++k) {
+        const T xv = D->x_s[st[k]];
+        val[k] = gh[k] ? T(0) : xv;
+    }
     T v = 0;
 #pragma unroll
     for (int k = 0; k < NST; ++k) v += D->g_w[k * ng + q] * val[k];
@@ -251,21 +263,24 @@ __device__ __forceinline__ void band_elem(const LevelDesc<T> *D, int b)
     if (cnt == 0) return;
     const int nb = D->nb;
     T v = 0;
-    // sources fetched eight at a time, summed in order
+    // sources fetched eight at a time (past the count: the last source again, not
+    // summed), summed in order
     for (int j0 = 0; j0 < cnt; j0 += 8) {
         int src[8];
         T wt[8], r[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const bool ok = j0 + u < cnt;
-            src[u] = ok ? D->b_src[(j0 + u) * nb + b] : 0;
-            wt[u] = ok ? D->b_wt[(j0 + u) * nb + b] : T(0);
+            const int ju = min(j0 + u, cnt - 1);
+            src[u] = D->b_src[ju * nb + b];
+            wt[u] = D->b_wt[ju * nb + b];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) r[u] = D->r_s[src[u]];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (j0 + u < cnt) v += wt[u] * r[u];
+        for (int u = 0; u < 8; ++u) {
+            const T t = v + wt[u] * r[u];
+            v = j0 + u < cnt ? t : v;
+        }
     }
     D->r_s[D->b_idx[b]] = v;
 }
@@ -274,9 +289,8 @@ __device__ __forceinline__ void band_elem(const LevelDesc<T> *D, int b)
 // weighting; inside rows read inside fine defects, boundary rows read ghost and
 // reached band defects, c-rows use full weighting renormalised over active fine
 // nodes.  Also clears the coarse correction.
-template <typename T, int DIM>
-__device__ __forceinline__ void restrict_node(const LevelDesc<T> *C, long long cidx, int ci, int cj, int ck,
-                                              bool coarse_inside)
+template <typename T, int DIM, bool INSIDE>
+__device__ __forceinline__ void restrict_node(const LevelDesc<T> *C, long long cidx, int ci, int cj, int ck)
 {
     const LevelDesc<T> *F = C - 1;
     constexpr int NST = DIM == 2 ? 9 : 27;
@@ -293,12 +307,15 @@ __device__ __forceinline__ void restrict_node(const LevelDesc<T> *C, long long c
         const bool inb = id0 >= 0 && id0 < fn && id1 >= 0 && id1 < fn && (DIM == 2 || (id2 >= 0 && id2 < fn));
         const long long q = inb ? sidx(fn, fWp, fcs, id0, id1, id2) : fcentre;
         const uint8_t t = F->type[q];
-        const uint8_t e = F->ext[q];
+        // boundary rows (INSIDE false) also need the extension flag; it is combined
+        // without short-circuit so that its load is issued with the type's
+        const uint8_t e = INSIDE ? 0 : F->ext[q];
         rs[kk] = F->r_s[q];
         rc[kk] = F->r_c[q];
-        bool excl = coarse_inside ? (t != kIn) : (t == kIn || (t == kOut && !e));
+        const bool tin = t == kIn, tout = t == kOut, ext = e != 0;
+        const bool excl = INSIDE ? !tin : (tin | (tout & !ext));
         ex[kk] = inb ? (uint8_t)excl : (uint8_t)1;
-        act[kk] = inb && t != kOut;
+        act[kk] = inb & !tout;
     }
     T vs, vc;
     restrict_vals<T, DIM>(ex, act, rs, rc, vs, vc);
@@ -314,7 +331,8 @@ __device__ __forceinline__ void restrict_elem(const LevelDesc<T> *C, int4 w, int
     long long cidx;
     int ci, cj, ck;
     if (!node_of<T, DIM>(C, w, lane, cidx, ci, cj, ck)) return;
-    restrict_node<T, DIM>(C, cidx, ci, cj, ck, item_kind(w) < 2);
+    if (item_kind(w) < 2) restrict_node<T, DIM, true>(C, cidx, ci, cj, ck);
+    else restrict_node<T, DIM, false>(C, cidx, ci, cj, ck);
 }
 
 // bilinear (trilinear) prolongation onto one fine node (section 3.5.3), over
@@ -324,9 +342,15 @@ __device__ __forceinline__ void prolong_node(const LevelDesc<T> *F, long long id
 {
     const LevelDesc<T> *C = F + 1;
     const int fi[3] = {i, j, k};
-    T ws = 0, es = 0, ec = 0;
+    constexpr int NC = 1 << DIM;
+    // the corners of the fine node's coarse cell; on an axis where the fine
+    // coordinate is even only the corners with bit 0 exist, and the others (not
+    // summed) re-read that corner, so that every load is issued at once
+    long long cq[NC];
+    T wq[NC];
+    bool use[NC];
 #pragma unroll
-    for (int corner = 0; corner < (1 << DIM); ++corner) {
+    for (int corner = 0; corner < NC; ++corner) {
         int id[3] = {0, 0, 0};
         T wk = 1;
         bool skip = false;
@@ -334,22 +358,37 @@ __device__ __forceinline__ void prolong_node(const LevelDesc<T> *F, long long id
         for (int a = 0; a < DIM; ++a) {
             const int bit = (corner >> a) & 1;
             if ((fi[a] & 1) == 0) {
-                if (bit) skip = true;
+                skip |= bit != 0;
                 id[a] = fi[a] >> 1;
             } else {
                 id[a] = (fi[a] >> 1) + bit;
                 wk *= T(0.5);
             }
         }
-        if (skip) continue;
-        // the corrections are read with the node type (one round trip); an inactive
-        // corner adds +0, which leaves the sums unchanged (they are never -0)
-        const long long q = sidx(C->n, C->Wp, C->cs, id[0], id[1], id[2]);
-        const bool on = C->type[q] != kOut;
-        const T xs = C->x_s[q], xc = C->x_c[q];
-        ws += on ? wk : T(0);
-        es += on ? wk * xs : T(0);
-        ec += on ? wk * xc : T(0);
+        cq[corner] = sidx(C->n, C->Wp, C->cs, id[0], id[1], id[2]);
+        wq[corner] = wk;
+        use[corner] = !skip;
+    }
+    // the corrections are read with the node type (one round trip); an inactive
+    // corner adds +0, which leaves the sums unchanged (they are never -0)
+    bool on[NC];
+    T xs[NC], xc[NC];
+#pragma unroll
+    for (int corner = 0; corner < NC; ++corner) {
+        on[corner] = C->type[cq[corner]] != kOut;
+        xs[corner] = C->x_s[cq[corner]];
+        xc[corner] = C->x_c[cq[corner]];
+    }
+    T ws = 0, es = 0, ec = 0;
+#pragma unroll
+    for (int corner = 0; corner < NC; ++corner) {
+        const T wk = wq[corner];
+        const T ws1 = ws + (on[corner] ? wk : T(0));
+        const T es1 = es + (on[corner] ? wk * xs[corner] : T(0));
+        const T ec1 = ec + (on[corner] ? wk * xc[corner] : T(0));
+        ws = use[corner] ? ws1 : ws;
+        es = use[corner] ? es1 : es;
+        ec = use[corner] ? ec1 : ec;
     }
     if (ws > T(0)) {
         F->x_s[idx] += es / ws;
@@ -455,6 +494,124 @@ __global__ __launch_bounds__(kMaxBlock) void k_smooth_colour(const LevelDesc<T> 
     smooth_elem<T, DIM>(D, w, lane, colour);
 }
 
+// ---------------------------------------------------------------------------
+// fused red-black sweep (2-D): one workgroup per tile of kRbRows rows x 64
+// positions, both colours, reading the corrections from one copy (x) and
+// writing every active node of the tile to the other (x2), flip 1 the reverse.
+// The red half-sweep is computed on the tile and a one-node halo around it
+// (rows y0 - 1 .. y0 + kRbRows, positions p0 - 1 .. p0 + 64) from the black
+// corrections of the read copy, which no workgroup of the launch writes; the
+// black half-sweep reads every red neighbour (s, c and the new correction) from
+// LDS.  A halo red node is computed with the same arithmetic as in the tile that
+// owns it, so a sweep gives the bits of one launch per colour.  Ghosts of the
+// tile are copied to the write copy unchanged.  Blocks after the tiles take the
+// ghost items (the snapshot of the ghosts' delta s for the folded ghost map).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kRbThreads) void k_smooth_rb(const LevelDesc<T> *__restrict__ descs,
+                                                          const int4 *__restrict__ tiles, int ntile,
+                                                          const int4 *__restrict__ gh, int ngh, int flip, LSMG_ACT)
+{
+    __shared__ T ls[kRbSlots], lc[kRbSlots], lxs[kRbSlots], lxc[kRbSlots];
+    const int b = logical_block();
+    const int tid = threadIdx.x;
+    if (b >= ntile) {
+        const int it = (b - ntile) * kRbWaves + __builtin_amdgcn_readfirstlane(tid >> 6);
+        if (it >= ngh) return;
+        const int4 w = gh[it];
+        if (act && !act[item_desc(w)]) return;
+        const LevelDesc<T> *D = descs + item_desc(w);
+        const gptr<T> XS = flip ? D->x2_s : D->x_s;
+        const int q = w.z + (tid & (kWave - 1));
+        if (q < w.w) D->g_buf1[q] = XS[D->g_idx[q]];
+        return;
+    }
+    const int4 w = tiles[b];
+    if (act && !act[item_desc(w)]) return;
+    const LevelDesc<T> *D = descs + item_desc(w);
+    const gptr<T> XS = flip ? D->x2_s : D->x_s, XC = flip ? D->x2_c : D->x_c;
+    const gptr<T> YS = flip ? D->x_s : D->x2_s, YC = flip ? D->x_c : D->x2_c;
+    const int n = D->n, Wp = D->Wp;
+    const long long cs = D->cs;
+    const int y0 = w.y, p0 = w.z;
+    // threads below 64 kRbRows own a black node (row y0 + tid / 64, position
+    // p0 + tid % 64), whose values are fetched before the red half-sweep
+    const int by = y0 + (tid >> 6), bp = p0 + (tid & (kWave - 1));
+    const int bi = 2 * bp + ((1 + by) & 1);
+    const bool bvalid = tid < kWave * kRbRows && by < n && bi < n;
+    const long long bidx = bvalid ? cs + (long long)by * Wp + bp : 0;
+    const uint8_t bt = D->type[bidx];
+    const T bs = D->s[bidx], bc = D->c[bidx], brs = D->rhs_s[bidx], brc = D->rhs_c[bidx];
+    const T bxs = XS[bidx], bxc = XC[bidx];
+    for (int t = tid; t < kRbSlots; t += kRbThreads) {
+        const int rr = t / kRbCols, pc = t - rr * kRbCols;
+        const int y = y0 - 1 + rr, p = p0 - 1 + pc;
+        const int i = 2 * p + (y & 1);
+        const bool valid = y >= 0 && y < n && p >= 0 && i < n;
+        // inside nodes never lie on the box edge, so only interior slots need neighbours
+        const bool interior = valid && y > 0 && y < n - 1 && i > 0 && i < n - 1;
+        const long long idx = valid ? (long long)y * Wp + p : 0;
+        long long nb[4];
+        if (interior) {
+            neighbours<2>(n, Wp, cs, 0, y, i, p, nb);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) nb[e] = idx;
+        }
+        const uint8_t ty = D->type[idx];
+        const T sr = D->s[idx], cr = D->c[idx], rhs_s = D->rhs_s[idx], rhs_c = D->rhs_c[idx];
+        const T xs0 = XS[idx], xc0 = XC[idx];
+        T se[4], ce[4], xse[4], xce[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            se[e] = D->s[nb[e]];
+            ce[e] = D->c[nb[e]];
+            xse[e] = XS[nb[e]];
+            xce[e] = XC[nb[e]];
+        }
+        // solved on every slot and kept on inside nodes only: the neighbour loads
+        // then never wait for the type
+        const InsideRow<T> R = inside_row_vals<T, 2>(D, sr, cr, se, ce, xse, xce);
+        T nxs, nxc;
+        block_solve<T>(R, rhs_s, rhs_c, nxs, nxc);
+        const bool in = interior && ty == kIn;
+        const T xs = in ? nxs : xs0, xc = in ? nxc : xc0;
+        if (valid && ty != kOut && rr >= 1 && rr <= kRbRows && pc >= 1 && pc <= kWave) {
+            YS[idx] = xs;
+            YC[idx] = xc;
+        }
+        ls[t] = sr;
+        lc[t] = cr;
+        lxs[t] = xs;
+        lxc[t] = xc;
+    }
+    __syncthreads();
+    if (!bvalid || bt == kOut) return;
+    if (bt != kIn) {
+        YS[bidx] = bxs;
+        YC[bidx] = bxc;
+        return;
+    }
+    // red neighbours x-, x+, y-, y+ (LDS slots of the row above, this row and the row below)
+    const int r0 = (tid >> 6) + 1, c0 = (tid & (kWave - 1)) + 1;
+    const int sl[4] = {r0 * kRbCols + ((bi - 1) >> 1) - p0 + 1, r0 * kRbCols + ((bi + 1) >> 1) - p0 + 1,
+                       (r0 - 1) * kRbCols + c0, (r0 + 1) * kRbCols + c0};
+    T se[4], ce[4], xse[4], xce[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        se[e] = ls[sl[e]];
+        ce[e] = lc[sl[e]];
+        xse[e] = lxs[sl[e]];
+        xce[e] = lxc[sl[e]];
+    }
+    const InsideRow<T> R = inside_row_vals<T, 2>(D, bs, bc, se, ce, xse, xce);
+    T xs, xc;
+    block_solve<T>(R, brs, brc, xs, xc);
+    YS[bidx] = xs;
+    YC[bidx] = xc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kMaxBlock) void k_ghost_load(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, LSMG_ACT)
 {
@@ -500,41 +657,132 @@ __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply(const LevelDesc<T> *_
 }
 
 // the same with 16 lanes per row (items of 4 ghosts: one row per 16-lane group),
-// for the long composed rows; in 2-D the rows carry the folded b-part
+// for the long composed rows; FOLD: the rows carry the folded b-part (2-D).  A
+// lane takes the entries e0 + sub, e0 + sub + 16, ... of its row.  The entries
+// of kApplyChunk strides are fetched (indices, then values) before they are
+// summed, in the same order; the first chunk of both parts and the ghost's own
+// values are fetched together, so that a row of up to 16 kApplyChunk entries
+// per part costs two dependent round trips after the row pointers.
+constexpr int kApplyChunk = 4;
+
+template <typename T, bool FOLD>
+struct ApplyChunk {
+    int col[kApplyChunk], six[kApplyChunk];
+    T a[kApplyChunk], b[kApplyChunk];
+    T u[kApplyChunk], r[kApplyChunk];
+    // entries past the row end re-read the row's last entry and are not summed
+    __device__ __forceinline__ void fetch_index(const LevelDesc<T> *D, int e, int e1)
+    {
+#pragma unroll
+        for (int k = 0; k < kApplyChunk; ++k) {
+            const int ek = min(e + 16 * k, e1 - 1);
+            col[k] = D->go_col[ek];
+            six[k] = FOLD ? D->go_sidx[ek] : 0;
+            a[k] = D->go_a[ek];
+            b[k] = D->go_b[ek];
+        }
+    }
+    __device__ __forceinline__ void fetch_values(const LevelDesc<T> *D)
+    {
+#pragma unroll
+        for (int k = 0; k < kApplyChunk; ++k) {
+            u[k] = D->g_buf1[col[k]];
+            r[k] = FOLD ? D->rhs_s[six[k]] : D->g_buf0[col[k]];
+        }
+    }
+    __device__ __forceinline__ T sum(T v, int e, int e1) const
+    {
+#pragma unroll
+        for (int k = 0; k < kApplyChunk; ++k) {
+            const T t = v + (a[k] * u[k] + b[k] * r[k]);
+            v = e + 16 * k < e1 ? t : v;
+        }
+        return v;
+    }
+};
+
 template <typename T>
+struct FoldChunk {
+    int ix[kApplyChunk];
+    T w[kApplyChunk], x[kApplyChunk];
+    __device__ __forceinline__ void fetch_index(const LevelDesc<T> *D, int f, int f1)
+    {
+#pragma unroll
+        for (int k = 0; k < kApplyChunk; ++k) {
+            const int fk = min(f + 16 * k, f1 - 1);
+            ix[k] = D->gc_idx[fk];
+            w[k] = D->gc_w[fk];
+        }
+    }
+    __device__ __forceinline__ void fetch_values(gptr<T> XS)
+    {
+#pragma unroll
+        for (int k = 0; k < kApplyChunk; ++k) x[k] = XS[ix[k]];
+    }
+    __device__ __forceinline__ T sum(T v, int f, int f1) const
+    {
+#pragma unroll
+        for (int k = 0; k < kApplyChunk; ++k) {
+            const T t = v - w[k] * x[k];
+            v = f + 16 * k < f1 ? t : v;
+        }
+        return v;
+    }
+};
+
+template <typename T, bool FOLD>
 __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply_grouped(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS,
-                                                                   LSMG_ACT)
+                                                                   int alt, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<T> *D = descs + item_desc(w);
+    // alt: the corrections live in the second copy (after a fused 2-D sweep)
+    const gptr<T> XS = alt ? D->x2_s : D->x_s, XC = alt ? D->x2_c : D->x_c;
     const int sub = lane & 15, grp = lane >> 4;
+    constexpr int kStride = 16 * kApplyChunk;
     for (int q0 = w.z; q0 < w.w; q0 += 4) {
         const int q = q0 + grp;
-        T v = 0;
-        if (q < w.w) {
-            const int e0 = D->go_ptr[q], e1 = D->go_ptr[q + 1];
-            if (D->gc_ptr) {
-                for (int e = e0 + sub; e < e1; e += 16) {
-                    const int c = D->go_col[e];
-                    v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->rhs_s[D->g_idx[c]];
+        const bool on = q < w.w;
+        T v = 0, sg = 0, cg = 0, xcg = 0, rcg = 0;
+        long long g = 0;
+        if (on) {
+            g = D->g_idx[q];
+            int e = D->go_ptr[q] + sub, f = FOLD ? D->gc_ptr[q] + sub : 0;
+            const int e1 = D->go_ptr[q + 1], f1 = FOLD ? D->gc_ptr[q + 1] : 0;
+            sg = D->s[g];
+            cg = D->c[g];
+            xcg = XC[g];
+            rcg = D->rhs_c[g];
+            ApplyChunk<T, FOLD> A;
+            FoldChunk<T> F;
+            const bool has_e = e < e1, has_f = FOLD && f < f1;
+            if (has_e) A.fetch_index(D, e, e1);
+            if (has_f) F.fetch_index(D, f, f1);
+            if (has_e) A.fetch_values(D);
+            if (has_f) F.fetch_values(XS);
+            if (has_e) {
+                v = A.sum(v, e, e1);
+                for (e += kStride; e < e1; e += kStride) {
+                    A.fetch_index(D, e, e1);
+                    A.fetch_values(D);
+                    v = A.sum(v, e, e1);
                 }
-                const int f0 = D->gc_ptr[q], f1 = D->gc_ptr[q + 1];
-                for (int f = f0 + sub; f < f1; f += 16) v -= D->gc_w[f] * D->x_s[D->gc_idx[f]];
-            } else {
-                for (int e = e0 + sub; e < e1; e += 16) {
-                    const int c = D->go_col[e];
-                    v += D->go_a[e] * D->g_buf1[c] + D->go_b[e] * D->g_buf0[c];
+            }
+            if (has_f) {
+                v = F.sum(v, f, f1);
+                for (f += kStride; f < f1; f += kStride) {
+                    F.fetch_index(D, f, f1);
+                    F.fetch_values(XS);
+                    v = F.sum(v, f, f1);
                 }
             }
         }
         for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
-        if (q < w.w && sub == 0) {
-            const long long g = D->g_idx[q];
-            D->x_s[g] = v;
+        if (on && sub == 0) {
+            XS[g] = v;
             T cs_d, cc_d;
-            c_row<T>(D, g, cs_d, cc_d);
-            const T xc = D->x_c[g];
-            D->x_c[g] = ghost_c_update<T>(cs_d, cc_d, D->rhs_c[g], v, xc);
+            c_row_vals<T>(D, sg, cg, cs_d, cc_d);
+            XC[g] = ghost_c_update<T>(cs_d, cc_d, rcg, v, xcg);
         }
     }
 }
@@ -854,7 +1102,8 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
                 long long idx;
                 int i, j, k;
                 tail_node<T, STAGE>(C, TC, S.si, t, idx, i, j, k);
-                restrict_node<T, DIM>(C, idx, i, j, k, t < ninc);
+                if (t < ninc) restrict_node<T, DIM, true>(C, idx, i, j, k);
+                else restrict_node<T, DIM, false>(C, idx, i, j, k);
             }
             __syncthreads();
             done &= ~(1u << l);
@@ -1323,6 +1572,17 @@ void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw,
     LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_smooth_colour<T, DIM>>(nw, x, d, w, nw, colour));
 }
 
+// one fused 2-D sweep over the tiles, then the ghost items (kRbWaves per block)
+template <typename T>
+void launch_smooth_rb(const LevelDesc<T> *d, const int4 *tiles, int ntile, const int4 *gh, int ngh, int flip,
+                      const Exec &x)
+{
+    if (ntile <= 0 && ngh <= 0) return;
+    const dim3 g(ntile + (ngh + kRbWaves - 1) / kRbWaves), b(kRbThreads);
+    if (x.ev0) hipExtLaunchKernelGGL(k_smooth_rb<T>, g, b, 0, x.s, x.ev0, x.ev1, 0, d, tiles, ntile, gh, ngh, flip, x.act);
+    else k_smooth_rb<T><<<g, b, 0, x.s>>>(d, tiles, ntile, gh, ngh, flip, x.act);
+}
+
 // the ghost relaxation of one smoothing step: the composed map (two launches,
 // xb and xa; in 3-D the map is applied over w4, items of 4 ghosts), or the sweeps
 // one by one (timed as a whole with xb's events)
@@ -1333,7 +1593,7 @@ void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int n
     if (nw <= 0) return;
     if (composed) {
         LSMG_DISPATCH_DIM(dim, (void)DIM; item_launch<k_ghost_b<T, NST>>(nw, xb, d, w, nw));
-        if (dim == 3) item_launch<k_ghost_apply_grouped<T>>(nw4, xa, d, w4, nw4);
+        if (dim == 3) item_launch<k_ghost_apply_grouped<T, false>>(nw4, xa, d, w4, nw4, 0);
         else item_launch<k_ghost_apply<T>>(nw, xa, d, w, nw);
         return;
     }
@@ -1352,13 +1612,14 @@ void launch_ghost(int dim, const LevelDesc<T> *d, int desc, const int4 *w, int n
     if (e1) (void)hipEventRecord(e1, x.s);
 }
 
-// the composed ghost map alone, 16 lanes per row over items of 4 ghosts
+// the folded composed ghost map alone (2-D), 16 lanes per row over items of 4
+// ghosts, on the corrections' first copy (alt 0) or second (alt 1)
 template <typename T>
-void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w4, int nw4, const Exec &x)
+void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w4, int nw4, int alt, const Exec &x)
 {
     (void)dim;
     if (nw4 <= 0) return;
-    item_launch<k_ghost_apply_grouped<T>>(nw4, x, d, w4, nw4);
+    item_launch<k_ghost_apply_grouped<T, true>>(nw4, x, d, w4, nw4, alt);
 }
 
 template <typename T>
@@ -1543,7 +1804,8 @@ void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, 
     template void launch_ghost<T>(int, const LevelDesc<T> *, int, const int4 *, int, const int4 *, int, int, int, bool, \
                                   const Exec &, const Exec &); \
     template void launch_defect<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
-    template void launch_ghost_apply<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
+    template void launch_ghost_apply<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
+    template void launch_smooth_rb<T>(const LevelDesc<T> *, const int4 *, int, const int4 *, int, int, const Exec &); \
     template void launch_apply_J<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \
     template void launch_band<T>(const LevelDesc<T> *, const int4 *, int, const Exec &); \
     template void launch_restrict<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \

@@ -78,6 +78,7 @@ struct LevelDesc {
     gptr<T> rhs_s, rhs_c;
     gptr<T> x_s, x_c;
     gptr<T> r_s, r_c;
+    gptr<T> x2_s, x2_c;          // 2-D: second copy of the corrections (fused sweeps alternate)
     // ghost table (structure of arrays, entry k of ghost q at k * ng + q)
     gptr<const int> g_idx;        // storage index of ghost q
     gptr<const int> g_ijk;        // packed grid coordinates i | j << 11 | k << 22
@@ -95,6 +96,7 @@ struct LevelDesc {
     // with C = B W_GI composed over inside storage indices (null in 3-D)
     gptr<const int> gc_ptr, gc_idx;
     gptr<const T> gc_w;
+    gptr<const int> go_sidx;      // 2-D: g_idx[go_col[e]], the storage index of entry e's ghost
     // band of inactive nodes used by the boundary-defect restriction
     gptr<const int> b_idx;        // storage index of band node b
     gptr<const int> b_cnt;        // number of ghost sources

@@ -12,6 +12,13 @@ namespace lsmg {
 // ghost sets up to this size are relaxed by one workgroup per smoothing step
 constexpr int kGhostFusedMax = 256;
 // levels with at most this many active nodes run inside the coarse-tail kernel
+// tiles of the fused 2-D sweep: kRbRows rows x 64 positions; the red half-sweep
+// covers the tile and a one-node halo (kRbSlots nodes, one per thread)
+constexpr int kRbRows = 4;
+constexpr int kRbCols = 64 + 2;
+constexpr int kRbSlots = (kRbRows + 2) * kRbCols;
+constexpr int kRbThreads = (kRbSlots + 63) / 64 * 64;
+constexpr int kRbWaves = kRbThreads / 64;
 constexpr int kTailMaxNodes = 1024;
 constexpr int kMaxLevels = 16;
 // the coarse tail copies its levels' node lists into LDS when they fit in this many ints
@@ -104,7 +111,12 @@ struct TailLdsSize {
 template <typename T> void launch_tail_lds(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks,
                                            const TailLdsSize &sz, const Exec &x);
 constexpr size_t kTailLdsMax = 158 * 1024;   // of the 160 KiB of a gfx950 CU
-template <typename T> void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
+template <typename T> void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int alt,
+                                             const Exec &x);
+// both colours of a 2-D sweep in one launch over tiles of rows (corrections read from
+// one copy, written to the other; flip selects which), with the ghost items after
+template <typename T> void launch_smooth_rb(const LevelDesc<T> *d, const int4 *tiles, int ntile, const int4 *gh,
+                                           int ngh, int flip, const Exec &x);
 template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x);
 template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
