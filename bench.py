@@ -342,7 +342,7 @@ def run_single(args):
     c2g0 = H.compact_to_grid(0).cpu().numpy()
     b0, b1 = smoother_bytes(c2g0, ni, ng, w["n"], w["dim"], P)
     eff = H.params
-    if w["dim"] == 2 and eff.fused_sweep and eff.ghost_c_new:
+    if H.sweep_fused(0, prec):
         bf = fused_sweep_bytes(c2g0, ni, ng, w["n"], P)
         pairs = eff.nu1 // 2 + eff.nu2 // 2
         single = eff.nu1 % 2 + eff.nu2 % 2
@@ -396,7 +396,7 @@ def run_single(args):
             "unknowns": unknowns, "inside": ni, "ghost": ng, "levels": H.nlev,
             "cycle": f"{'VW'[H.params.cycle_gamma - 1]}({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps "
                      f"({H.params.ghost_sweeps_coarse} where d dt/h^2 < {H.params.sweeps_lambda})",
-            "fused_sweep": bool(w["dim"] == 2 and H.params.fused_sweep),
+            "fused_sweep_levels": [l for l in range(H.nlev) if H.sweep_fused(l, prec)],
             "build_ms": round(build_ms, 1),
         },
         "vcycles": cycles,
@@ -428,7 +428,8 @@ def run_batch(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Hs = [lsmg.Hierarchy(torch.from_numpy(phi).cuda(), 2, d["n"],
-                         params=lsmg.default_params(coarsest_n=d["coarsest"], precision=prec))
+                         params=lsmg.default_params(coarsest_n=d["coarsest"], precision=prec,
+                                                    fused_sweep=args.fused))
           for phi, d in zip(phis, doms)]
     B = lsmg.Batch(Hs)
     torch.cuda.synchronize()
@@ -479,16 +480,24 @@ def run_batch(args):
     torch.cuda.synchronize()
     launches, prof_ms = B.profile_stop()
     P = 8 if prec == 0 else 4
+    fused = B.sweep_fused(nmax, prec) and Hs[0].params.nu1 % 2 == 0 and Hs[0].params.nu2 % 2 == 0
     byts = 0.0
     for H, d, inf in zip(Hs, doms, infos):
         if d["n"] == nmax:
-            b0, b1 = smoother_bytes(H.compact_to_grid(0).cpu().numpy(), inf["ni"], inf["ng"], d["n"], 2, P)
-            byts += 0.5 * (b0 + b1)
+            c2g0 = H.compact_to_grid(0).cpu().numpy()
+            if fused:
+                byts += fused_sweep_bytes(c2g0, inf["ni"], inf["ng"], d["n"], P)
+            else:
+                b0, b1 = smoother_bytes(c2g0, inf["ni"], inf["ng"], d["n"], 2, P)
+                byts += 0.5 * (b0 + b1)
+    kname = (f"k_smooth_rb (all {nmax}^2 levels of the batch, both colours of a sweep)" if fused
+             else f"k_smooth_colour (all {nmax}^2 levels of the batch, one colour)")
     avg_s = prof_ms * 1e-3 / max(launches, 1)
     achieved = byts / avg_s / 1e9 if launches else 0.0
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic("smooth_colour", "batch64", prec),
-                    kernel=f"k_smooth_colour (all {nmax}^2 levels of the batch, one colour)", launches=launches,
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=load_traffic("smooth_rb" if fused else "smooth_colour", "batch64", prec),
+                    kernel=kname, launches=launches,
                     avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(byts))
     # the plain FP64 path, domain after domain, same steps
     seq = None

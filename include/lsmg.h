@@ -92,7 +92,7 @@ typedef struct {
     int fused_sweep;       /* 2-D: 1 runs both colours of a smoothing sweep in one launch over
                             * tiles of rows, the red half-sweep recomputed on a one-node halo
                             * (same bits as one launch per colour); 0 one launch per colour.
-                            * Batches use one launch per colour */
+                            * A batch fuses its sweeps when every member has fused_sweep = 1 */
 } lsmg_params;
 
 typedef struct lsmg_hierarchy lsmg_hierarchy;
@@ -185,6 +185,14 @@ lsmg_status lsmg_extrapolate(const double *d_phi, const lsmg_grid *grid, double 
  * environment variable LSMG_TAIL_LDS=0 was set when h was built (the tail then
  * reads its levels from HBM; the results are the same bits). */
 lsmg_status lsmg_tail_in_lds(const lsmg_hierarchy *h, int precision, int *in_lds);
+
+/* Whether smoothing on `level` runs fused sweeps (fused_sweep, 2-D, pairs of
+ * steps) for the given precision: *fused = 1 where the level's active nodes
+ * times the value size are at most 1 MiB (launch latency dominates there; on
+ * larger levels the fused sweep's halo and whole-tile reads cost more than the
+ * launch it saves), else 0.  An odd step of a smoothing block always runs one
+ * launch per colour. */
+lsmg_status lsmg_sweep_fused(const lsmg_hierarchy *h, int level, int precision, int *fused);
 
 /* Parameters in effect (host out), with automatic choices resolved. */
 lsmg_status lsmg_get_params(const lsmg_hierarchy *h, lsmg_params *params);
@@ -391,6 +399,11 @@ lsmg_status lsmg_batch_set_autotune(lsmg_batch *b, int enable);
  * written (host arrays sizes[cap], ipb[6 * cap]); *count gets the number of
  * sizes. */
 lsmg_status lsmg_batch_tuning(const lsmg_batch *b, int cap, int *count, int *sizes, int *ipb);
+
+/* The same as lsmg_sweep_fused for the batch's launches at grid size n (the
+ * active nodes summed over the member levels of that size outside the coarse
+ * tails); *fused = 0 for a size the batch does not have. */
+lsmg_status lsmg_batch_sweep_fused(const lsmg_batch *b, int n, int precision, int *fused);
 
 /* Launch timing inside a batch, as lsmg_profile_start / lsmg_profile_stop:
  * every launch of kernel class `kernel` (LSMG_KERNEL_*) at grid size n (for

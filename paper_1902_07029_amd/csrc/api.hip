@@ -229,10 +229,11 @@ void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s, int count)
     const Level &Lv = H->L[l];
     const LevelDesc<T> *d = descs<T>(H);
     if (Lv.gc_ptr) {
-        // 2-D, folded ghost map.  Pairs of steps with fused sweeps: the first reads
-        // the corrections' first copy and writes the second, the folded map then
-        // works on the second, and the next step returns to the first
-        if (H->p.fused_sweep && Lv.tiles) {
+        // 2-D, folded ghost map.  Pairs of steps with fused sweeps (on levels small
+        // enough for launch latency to dominate): the first reads the corrections'
+        // first copy and writes the second, the folded map then works on the
+        // second, and the next step returns to the first
+        if (H->p.fused_sweep && Lv.tiles && fuse_sweep(Lv.na, sizeof(T))) {
             for (; count >= 2; count -= 2) {
                 for (int flip = 0; flip < 2; ++flip) {
                     launch_smooth_rb<T>(d, Lv.tiles, Lv.ntile, Lv.w_gh(), Lv.nghc, flip,
@@ -1176,6 +1177,16 @@ lsmg_status lsmg_tail_in_lds(const lsmg_hierarchy *h, int precision, int *in_lds
 {
     if (!h || !in_lds || (precision != 0 && precision != 1)) return fail(LSMG_EINVAL, "bad argument");
     *in_lds = precision == 0 ? tail_in_lds<double>(h) : tail_in_lds<float>(h);
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_sweep_fused(const lsmg_hierarchy *h, int level, int precision, int *fused)
+{
+    LSMGCHK(level_ok(h, level));
+    if (!fused || (precision != 0 && precision != 1)) return fail(LSMG_EINVAL, "bad argument");
+    const Level &Lv = h->L[level];
+    *fused = h->p.fused_sweep && Lv.tiles && Lv.gc_ptr &&
+             fuse_sweep(Lv.na, precision == 0 ? sizeof(double) : sizeof(float));
     return LSMG_OK;
 }
 

@@ -44,6 +44,8 @@ struct BSize {
     BList seg[2], gh, act, band;     // member levels of this size outside the coarse tails
     BList gh4;                       // their ghosts in items of 4 (the composed map)
     BList seg1g;                     // 2-D: colour-1 segments, each member's followed by its ghost items
+    BList tiles;                     // 2-D: tiles of the fused sweep
+    long long na = 0;                // active nodes of the member levels outside the coarse tails
     BList rcoarse;                   // their next coarser levels (restriction targets)
     BList icoarse;                   // next coarser levels of every member level of this size (injection)
     int ipb[kTClasses];
@@ -80,6 +82,7 @@ struct lsmg_batch {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     bool use_graphs = true;
     int autotune = 1, tuned = 0;
+    bool fused = false;         // 2-D, every member with fused sweeps
     double dt = 0.0;
     std::vector<const lsmg_state *> last_states;
     std::vector<const double *> last_sb;
@@ -267,27 +270,44 @@ double bnorm(const lsmg_batch *B, int k, int norm)
 // ---------------------------------------------------------------------------
 // V-cycle over all members
 // ---------------------------------------------------------------------------
+// `count` smoothing steps of every member level of size S.n (as in the single-
+// hierarchy driver: where the launch covers few nodes, pairs of fused 2-D sweeps
+// alternating between the copies of the corrections, the rest one launch per colour)
 template <typename T>
-void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s)
+void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s, int count)
 {
     const LevelDesc<T> *d = bdescs<T>(B);
     if (B->dim == 2) {
+        if (B->fused && fuse_sweep(S.na, sizeof(T))) {
+            for (; count >= 2; count -= 2) {
+                for (int flip = 0; flip < 2; ++flip) {
+                    launch_smooth_rb<T>(d, items(B, S.tiles), S.tiles.n, items(B, S.gh), S.gh.n, flip,
+                                        bexec_t(B, s, 0, LSMG_KERNEL_SMOOTH, S.n));
+                    launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 1 - flip,
+                                          bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n));
+                }
+            }
+        }
         // folded ghost relaxation: the black launch snapshots the ghosts, one apply launch
-        launch_smooth_colour<T>(B->dim, d, items(B, S.seg[0]), S.seg[0].n, 0,
-                                bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
-        launch_smooth_colour<T>(B->dim, d, items(B, S.seg1g), S.seg1g.n, 1,
-                                bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
-        launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 0,
-                              bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n));
+        for (; count > 0; --count) {
+            launch_smooth_colour<T>(B->dim, d, items(B, S.seg[0]), S.seg[0].n, 0,
+                                    bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
+            launch_smooth_colour<T>(B->dim, d, items(B, S.seg1g), S.seg1g.n, 1,
+                                    bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
+            launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 0,
+                                  bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n));
+        }
         return;
     }
-    for (int colour = 0; colour < 2; ++colour)
-        launch_smooth_colour<T>(B->dim, d, items(B, S.seg[colour]), S.seg[colour].n, colour,
-                                bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
-    const Exec xb = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
-    const Exec xa = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
-    launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, items(B, S.gh4), S.gh4.n, 0, B->p.ghost_sweeps, true, xb,
-                    xa);
+    for (; count > 0; --count) {
+        for (int colour = 0; colour < 2; ++colour)
+            launch_smooth_colour<T>(B->dim, d, items(B, S.seg[colour]), S.seg[colour].n, colour,
+                                    bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
+        const Exec xb = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
+        const Exec xa = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
+        launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, items(B, S.gh4), S.gh4.n, 0, B->p.ghost_sweeps, true,
+                        xb, xa);
+    }
 }
 
 template <typename T>
@@ -298,7 +318,7 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
     for (int z = 0; z < nz; ++z) {
         const BSize &S = B->sizes[z];
         if (S.act.n == 0) continue;
-        for (int i = 0; i < B->p.nu1; ++i) b_smooth<T>(B, S, s);
+        b_smooth<T>(B, S, s, B->p.nu1);
         launch_defect<T>(B->dim, d, items(B, S.act), S.act.n, -1,
                          bexec_t(B, s, S.ipb[kTDefect], LSMG_KERNEL_DEFECT, S.n));
         launch_band<T>(d, items(B, S.band), S.band.n, bexec(B, s, S.ipb[kTBand]));
@@ -314,7 +334,7 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
         if (S.act.n == 0) continue;
         launch_prolong<T>(B->dim, d, items(B, S.act), S.act.n,
                           bexec_t(B, s, S.ipb[kTProlong], LSMG_KERNEL_PROLONG, S.n));
-        for (int i = 0; i < B->p.nu2; ++i) b_smooth<T>(B, S, s);
+        b_smooth<T>(B, S, s, B->p.nu2);
     }
 }
 
@@ -486,7 +506,7 @@ lsmg_status build_lists(lsmg_batch *B)
     const int nk = B->ndom;
     for (size_t z = 0; z < ns.size(); ++z) {
         BSize &S = B->sizes[z];
-        std::vector<Job> seg0, seg1, seg1g, gh, gh4, act, band, rco, ico;
+        std::vector<Job> seg0, seg1, seg1g, gh, gh4, act, band, rco, ico, til;
         for (int k = 0; k < nk; ++k) {
             const lsmg_hierarchy *H = B->mem[k];
             for (int l = 0; l < H->nlev; ++l) {
@@ -501,6 +521,8 @@ lsmg_status build_lists(lsmg_batch *B)
                 seg0.push_back({Lv.w_seg(0), Lv.nseg[0], ds});
                 seg1.push_back({Lv.w_seg(1), Lv.nseg[1], ds});
                 seg1g.push_back({Lv.w_seg(1), Lv.nseg[1] + Lv.nghc, ds});
+                if (Lv.tiles) til.push_back({Lv.tiles, Lv.ntile, ds});
+                S.na += Lv.na;
                 gh.push_back({Lv.w_gh(), Lv.nghc, ds});
                 gh4.push_back({Lv.w_gh4(), Lv.nghc4, ds});
                 act.push_back({Lv.w_act(), Lv.nw_act(), ds});
@@ -512,6 +534,7 @@ lsmg_status build_lists(lsmg_batch *B)
         add(S.seg[0], seg0);
         add(S.seg[1], seg1);
         add(S.seg1g, seg1g);
+        add(S.tiles, til);
         add(S.gh, gh);
         add(S.gh4, gh4);
         add(S.act, act);
@@ -646,6 +669,8 @@ lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, void *s
     if (!B) return fail(LSMG_EOOM, "host allocation");
     B->dim = members[0]->dim;
     B->p = members[0]->p;
+    B->fused = B->dim == 2;
+    for (int k = 0; k < count; ++k) B->fused = B->fused && members[k]->p.fused_sweep;
     B->ndom = count;
     B->stream = (hipStream_t)stream;
     B->mem.assign(members, members + count);
@@ -665,6 +690,16 @@ void lsmg_batch_destroy(lsmg_batch *b)
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
     delete b;
+}
+
+lsmg_status lsmg_batch_sweep_fused(const lsmg_batch *b, int n, int precision, int *fused)
+{
+    if (!b || !fused || (precision != 0 && precision != 1)) return fail(LSMG_EINVAL, "bad argument");
+    *fused = 0;
+    for (const BSize &S : b->sizes)
+        if (S.n == n)
+            *fused = b->fused && S.tiles.n > 0 && fuse_sweep(S.na, precision == 0 ? sizeof(double) : sizeof(float));
+    return LSMG_OK;
 }
 
 lsmg_status lsmg_batch_set_autotune(lsmg_batch *b, int enable)

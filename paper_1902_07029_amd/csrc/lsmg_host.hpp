@@ -19,6 +19,14 @@ constexpr int kRbCols = 64 + 2;
 constexpr int kRbSlots = (kRbRows + 2) * kRbCols;
 constexpr int kRbThreads = (kRbSlots + 63) / 64 * 64;
 constexpr int kRbWaves = kRbThreads / 64;
+// the fused sweep recomputes the red halo and reads every node of its tiles, which
+// costs bandwidth but saves a launch: it is used where a sweep's launch moves
+// little data (latency-bound), i.e. active nodes x sizeof(T) up to this many bytes
+constexpr long long kFusedMaxBytes = 1 << 20;
+inline bool fuse_sweep(long long active_nodes, size_t value_bytes)
+{
+    return active_nodes * (long long)value_bytes <= kFusedMaxBytes;
+}
 constexpr int kTailMaxNodes = 1024;
 constexpr int kMaxLevels = 16;
 // the coarse tail copies its levels' node lists into LDS when they fit in this many ints

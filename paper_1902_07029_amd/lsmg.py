@@ -77,6 +77,8 @@ def load():
         "lsmg_levelset_from_mask": (_i, [_vp, _vp, _i, _vp, _vp]),
         "lsmg_extrapolate": (_i, [_vp, _vp, _vp, _i, _vp]),
         "lsmg_tail_in_lds": (_i, [_vp, _i, _vp]),
+        "lsmg_sweep_fused": (_i, [_vp, _i, _i, _vp]),
+        "lsmg_batch_sweep_fused": (_i, [_vp, _i, _i, _vp]),
         "lsmg_ghost_table": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "lsmg_state_create": (_i, [_vp, ctypes.POINTER(_vp)]),
         "lsmg_state_destroy": (None, [_vp]),
@@ -254,6 +256,11 @@ class Hierarchy:
     def tail_in_lds(self, precision=0):
         v = _i()
         _check(load().lsmg_tail_in_lds(self._h, precision, ctypes.byref(v)), "lsmg_tail_in_lds")
+        return bool(v.value)
+
+    def sweep_fused(self, level, precision=0):
+        v = _i()
+        _check(load().lsmg_sweep_fused(self._h, level, precision, ctypes.byref(v)), "lsmg_sweep_fused")
         return bool(v.value)
 
     def ghost_table(self, l):
@@ -455,6 +462,11 @@ class Batch:
         ipb = (_i * max(6 * m, 1))()
         _check(load().lsmg_batch_tuning(self._b, m, ctypes.byref(cnt), sizes, ipb), "lsmg_batch_tuning")
         return {sizes[z]: {c: ipb[6 * z + i] for i, c in enumerate(TUNE_CLASSES)} for z in range(m)}
+
+    def sweep_fused(self, n, precision=0):
+        v = _i()
+        _check(load().lsmg_batch_sweep_fused(self._b, n, precision, ctypes.byref(v)), "lsmg_batch_sweep_fused")
+        return bool(v.value)
 
     def profile_start(self, kernel, n):
         _check(load().lsmg_batch_profile_start(self._b, kernel, n), "lsmg_batch_profile_start")

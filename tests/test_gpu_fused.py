@@ -5,7 +5,8 @@ arithmetic to the same values, so smoothing sweeps, cycles and whole steps must 
 bit for bit.  Covered: odd sweep counts (the last step per colour), V- and W-cycles,
 Dirichlet and Neumann rows, FP64 and mixed precision, grids whose rows are not a
 multiple of the 64-position tile width, and a disc reaching the nodes next to the box
-edge (tiles on the edge rows and positions)."""
+edge (tiles on the edge rows and positions).  Where a launch moves more than 1 MiB
+of node values the fused sweep is not used (lsmg_sweep_fused)."""
 import numpy as np
 import pytest
 import torch
@@ -112,3 +113,54 @@ def test_fused_sweep_switch_by_set_params():
     sts[0].step(1e-4)
     sts[1].step(1e-4)
     assert torch.equal(sts[0].get(), sts[1].get())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_sweep_batch_bitwise(precision):
+    # a batch of stars of three grid sizes with fused sweeps against the same batch with
+    # one launch per colour
+    doms = [dict(n=129, a=0.45, b=0.1, k=4, p=0.3), dict(n=257, a=0.5, b=0.15, k=5, p=0.0),
+            dict(n=65, a=0.55, b=0.08, k=3, p=1.0), dict(n=257, a=0.38, b=0.18, k=7, p=2.5)]
+    out = []
+    for fused in (0, 1):
+        Hs, sts = [], []
+        for d in doms:
+            p = lsmg.default_params(coarsest_n=9, precision=precision, fused_sweep=fused)
+            H = lsmg.Hierarchy(torch.from_numpy(I.star(d["n"], d["a"], d["b"], d["k"], d["p"])), 2, d["n"], params=p)
+            st = lsmg.State(H)
+            s, c = I.initial_state(d["n"], 2)
+            st.set_grid(cuda(s), cuda(c))
+            Hs.append(H)
+            sts.append(st)
+        B = lsmg.Batch(Hs)
+        stats = []
+        for _ in range(2):
+            status, st_ = B.step(sts, 1e-4)
+            assert all(x == lsmg.OK for x in status)
+            stats.append([(x["newton_iters"], x["vcycles"]) for x in st_])
+        out.append(([st.get() for st in sts], stats))
+    say(f"fused batch prec {precision}: (newton, cycles) {out[1][1]}")
+    for a, b in zip(out[0][0], out[1][0]):
+        assert torch.equal(a, b)
+    assert out[0][1] == out[1][1]
+
+
+@pytest.mark.gpu
+def test_sweep_fused_rule():
+    # fused where active nodes x value size <= 1 MiB: the 1025^2 star level (217 k active
+    # nodes) runs one launch per colour in FP64 and fused in FP32; coarser levels fused
+    p = lsmg.default_params(coarsest_n=9, precision=1)
+    H = lsmg.Hierarchy(torch.from_numpy(I.star(1025)), 2, 1025, params=p)
+    na = H.level_info(0)["na"]
+    assert na * 8 > (1 << 20) >= na * 4
+    assert not H.sweep_fused(0, 0) and H.sweep_fused(0, 1)
+    assert all(H.sweep_fused(l, 0) for l in range(1, H.nlev))
+    q = lsmg.default_params(coarsest_n=9, fused_sweep=0)
+    Hu = lsmg.Hierarchy(torch.from_numpy(I.star(257)), 2, 257, params=q)
+    assert not any(Hu.sweep_fused(l, 0) for l in range(Hu.nlev))
+    T = lsmg.Hierarchy(torch.from_numpy(I.torus(33)), 3, 33, params=lsmg.default_params(coarsest_n=9))
+    assert not T.sweep_fused(0, 0)
+    B = lsmg.Batch([H, lsmg.Hierarchy(torch.from_numpy(I.star(257)), 2, 257, params=p)])
+    assert not B.sweep_fused(1025, 0) and B.sweep_fused(1025, 1) and B.sweep_fused(257, 0)
+    assert not B.sweep_fused(1000, 0)
