@@ -164,11 +164,13 @@ def oracle_params(H):
 
 # ---------------------------------------------------------------- profiling helpers
 
-SMOOTH_KERNELS = ("k_smooth_rb", "k_smooth_colour")
+SMOOTH_KERNELS = ("k_smooth_colour", "k_smooth_rb")
 
 
 def _smooth_kernel(rows):
-    """The smoother of a profile: the fused 2-D sweep where it ran, else the per-colour one."""
+    """The finest level's smoother in a profile: the per-colour kernel where it ran
+    (fused sweeps are used on the smaller levels only, or where the finest level
+    itself is small), else the fused 2-D sweep."""
     for k in SMOOTH_KERNELS:
         if any(k in r["Kernel_Name"] for r in rows):
             return k
@@ -225,16 +227,20 @@ def trace_summary(directory):
         print(f"{int(r['Calls']):7d} {t / 1e6:9.3f} {100 * t / total:5.1f}% {float(r['AverageNs']) / 1e3:8.2f}  "
               f"{_short(r['Name'])}")
     trace = _csv_rows(directory, "kernel_trace.csv")
+    for kern in SMOOTH_KERNELS:
+        sm = [r for r in trace if kern in r["Kernel_Name"]]
+        if not sm:
+            continue
+        by = {}
+        for r in sm:
+            g = int(r["Grid_Size_X"]) if "Grid_Size_X" in r else int(r["Grid_Size"])
+            by.setdefault(g, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        print(f"\n{kern} by grid size (threads), from the kernel trace:")
+        for g in sorted(by, reverse=True):
+            v = by[g]
+            print(f"  grid {g:9d}  launches {len(v):6d}  avg {sum(v) / len(v) / 1e3:8.2f} us")
     kern = _smooth_kernel(trace)
-    sm = [r for r in trace if kern in r["Kernel_Name"]]
-    by = {}
-    for r in sm:
-        g = int(r["Grid_Size_X"]) if "Grid_Size_X" in r else int(r["Grid_Size"])
-        by.setdefault(g, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    print(f"\n{kern} by grid size (threads), from the kernel trace:")
-    for g in sorted(by, reverse=True):
-        v = by[g]
-        print(f"  grid {g:9d}  launches {len(v):6d}  avg {sum(v) / len(v) / 1e3:8.2f} us")
+    print(f"finest-level smoother: {kern}")
     fin = _finest(trace, "Grid_Size_X" if "Grid_Size_X" in trace[0] else "Grid_Size")
     d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in fin]
     print(f"finest level: {len(d)} launches, average {sum(d) / len(d) / 1e3:.2f} us")
