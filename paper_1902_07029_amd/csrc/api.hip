@@ -292,8 +292,11 @@ TailArgs tail_args(const lsmg_hierarchy *H, int l0, int d0)
         a.nvals = H->tail_sz.nvals;
         a.nints = H->tail_sz.nints;
         a.ngmax = H->tail_sz.ngmax;
+        a.ncoarse = H->tail_sz.ncoarse;
         for (int l = H->tail_l0; l < H->nlev; ++l) a.ll[l] = H->tail_ll[l];
     }
+    // which tail kernel runs it (the same one alone and in a batch)
+    a.lds = (tail_in_lds<double>(H) ? 1 : 0) | (tail_in_lds<float>(H) ? 2 : 0);
     return a;
 }
 
@@ -310,7 +313,7 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
         }
         // this level and every coarser one in one workgroup
         if (tail_in_lds<T>(H))
-            launch_tail_lds<T>(H->dim, d, H->d_tail + l, 1, H->tail_sz, Exec(s));
+            launch_tail_lds<T>(H->dim, d, H->d_tail + l, 1, H->tail_sz.bytes<T>(), Exec(s));
         else
             launch_tail<T>(H->dim, d, H->d_tail + l, 1, H->L[H->nlev - 1].na,
                            tail_args(H, l, 0).nstage <= kTailStageInts, Exec(s));

@@ -70,8 +70,10 @@ struct lsmg_batch {
     TailArgs *d_tail = nullptr;
     int tail_na_max = 0;
     bool tail_stage = true;     // every member's tail node lists fit the LDS copy
-    TailLdsSize tail_sz{};      // LDS tail: the largest member layout
-    bool tail_lds64 = true, tail_lds32 = true;   // every member's tail runs in LDS
+    // a member's coarse tail runs in the kernel it runs in alone: the LDS tail where it
+    // fits there, else the HBM tail; a launch of each covers the members of its kind
+    bool any_lds64 = false, any_lds32 = false, all_lds64 = true, all_lds32 = true;
+    size_t lds_bytes64 = 0, lds_bytes32 = 0;   // the LDS tail's dynamic LDS (largest member)
     CoarseArgs *d_coarse = nullptr;
     int coarse_n_max = 0;
     int *d_act = nullptr, *h_act = nullptr;
@@ -325,9 +327,10 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
         launch_restrict<T>(B->dim, d, items(B, S.rcoarse), S.rcoarse.n,
                            bexec_t(B, s, S.ipb[kTRestrict], LSMG_KERNEL_RESTRICT, S.n));
     }
-    if ((sizeof(T) == 8 ? B->tail_lds64 : B->tail_lds32) && B->tail_sz.bytes<T>() <= kTailLdsMax)
-        launch_tail_lds<T>(B->dim, d, B->d_tail, B->ndom, B->tail_sz, Exec(s, B->d_act));
-    else
+    const bool f64 = sizeof(T) == 8;
+    if (f64 ? B->any_lds64 : B->any_lds32)
+        launch_tail_lds<T>(B->dim, d, B->d_tail, B->ndom, f64 ? B->lds_bytes64 : B->lds_bytes32, Exec(s, B->d_act));
+    if (!(f64 ? B->all_lds64 : B->all_lds32))
         launch_tail<T>(B->dim, d, B->d_tail, B->ndom, B->tail_na_max, B->tail_stage, Exec(s, B->d_act));
     for (int z = nz - 1; z >= 0; --z) {
         const BSize &S = B->sizes[z];
@@ -617,13 +620,13 @@ lsmg_status b_build(lsmg_batch *B)
         ta[k] = tail_args(H, H->tail_l0, B->d0[k]);
         B->tail_na_max = std::max(B->tail_na_max, H->L[H->nlev - 1].na);
         B->tail_stage = B->tail_stage && ta[k].nstage <= kTailStageInts;
-        B->tail_sz.ncoarse = std::max(B->tail_sz.ncoarse, H->tail_sz.ncoarse);
-        B->tail_sz.ngmax = std::max(B->tail_sz.ngmax, H->tail_sz.ngmax);
-        B->tail_sz.nvals = std::max(B->tail_sz.nvals, H->tail_sz.nvals);
-        B->tail_sz.nints = std::max(B->tail_sz.nints, H->tail_sz.nints);
-        B->tail_sz.tab_words = std::max(B->tail_sz.tab_words, H->tail_sz.tab_words);
-        B->tail_lds64 = B->tail_lds64 && tail_in_lds<double>(H);
-        B->tail_lds32 = B->tail_lds32 && tail_in_lds<float>(H);
+        const bool l64 = tail_in_lds<double>(H), l32 = tail_in_lds<float>(H);
+        B->any_lds64 = B->any_lds64 || l64;
+        B->any_lds32 = B->any_lds32 || l32;
+        B->all_lds64 = B->all_lds64 && l64;
+        B->all_lds32 = B->all_lds32 && l32;
+        if (l64) B->lds_bytes64 = std::max(B->lds_bytes64, H->tail_sz.bytes<double>());
+        if (l32) B->lds_bytes32 = std::max(B->lds_bytes32, H->tail_sz.bytes<float>());
         ca[k] = CoarseArgs{};
         ca[k].desc = B->d0[k] + H->nlev - 1;
         ca[k].c2s = H->L[H->nlev - 1].c2s;

@@ -278,7 +278,7 @@ __device__ __forceinline__ void band_elem(const LevelDesc<T> *D, int b)
         for (int u = 0; u < 8; ++u) r[u] = D->r_s[src[u]];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const T t = v + wt[u] * r[u];
+            const T t = fma(wt[u], r[u], v);
             v = j0 + u < cnt ? t : v;
         }
     }
@@ -929,32 +929,6 @@ __device__ __forceinline__ void tail_ghost_b(const LevelDesc<T> *D, int q, long 
 }
 
 // composed ghost relaxation, phase 2 (as ghost_apply_elem, row entries [e0, e1))
-template <typename T>
-__device__ __forceinline__ void tail_ghost_apply(const LevelDesc<T> *D, long long g, int e0, int e1, const T *gb0,
-                                                 const T *gb1)
-{
-    T cs_d, cc_d;
-    c_row<T>(D, g, cs_d, cc_d);
-    const T xc = D->x_c[g], rc = D->rhs_c[g];
-    T v = 0;
-    for (int e = e0; e < e1; e += 4) {
-        int col[4];
-        T a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool ok = e + u < e1;
-            col[u] = ok ? D->go_col[e + u] : 0;
-            a[u] = ok ? D->go_a[e + u] : T(0);
-            b[u] = ok ? D->go_b[e + u] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (e + u < e1) v += a[u] * gb1[col[u]] + b[u] * gb0[col[u]];
-    }
-    D->x_s[g] = v;
-    D->x_c[g] = ghost_c_update<T>(cs_d, cc_d, rc, v, xc);
-}
-
 template <typename T, int DIM, int NST, bool STAGE>
 __device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, const TailLds<T> &S)
 {
@@ -977,12 +951,26 @@ __device__ void wg_smooth(const LevelDesc<T> *D, const TailLevel &TL, const Tail
             tail_ghost_b<T, NST>(D, q, g, S.gb0, S.gb1);
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < ng; q += blockDim.x) {
-            long long g;
-            int i, j, k;
-            tail_node<T, STAGE>(D, TL, S.si, nin + q, g, i, j, k);
-            tail_ghost_apply<T>(D, g, tail_goptr<T, STAGE>(D, TL, S.si, q), tail_goptr<T, STAGE>(D, TL, S.si, q + 1),
-                                S.gb0, S.gb1);
+        // the composed rows, kRowGroup lanes per row
+        const int sub = threadIdx.x % kRowGroup, grp = threadIdx.x / kRowGroup, ngrp = blockDim.x / kRowGroup;
+        for (int q0 = 0; q0 < ng; q0 += ngrp) {
+            const int q = q0 + grp;
+            const bool on = q < ng;
+            long long g = 0;
+            int i, j, k, e0 = 0, e1 = 0;
+            if (on) {
+                tail_node<T, STAGE>(D, TL, S.si, nin + q, g, i, j, k);
+                e0 = tail_goptr<T, STAGE>(D, TL, S.si, q);
+                e1 = tail_goptr<T, STAGE>(D, TL, S.si, q + 1);
+            }
+            const T v = group_ghost_row<T>(D->go_col, D->go_a, D->go_b, S.gb0, S.gb1, e0, e1, sub);
+            if (on && sub == 0) {
+                T cs_d, cc_d;
+                c_row<T>(D, g, cs_d, cc_d);
+                const T xc = D->x_c[g], rc = D->rhs_c[g];
+                D->x_s[g] = v;
+                D->x_c[g] = ghost_c_update<T>(cs_d, cc_d, rc, v, xc);
+            }
         }
         __syncthreads();
         return;
@@ -1023,14 +1011,23 @@ __device__ void wg_coarse_apply(const LevelDesc<T> *D, gptr<const int> c2s, gptr
         u[r] = vc / cc[r];
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < na; r += blockDim.x) t[r] = row_dot<-1>(Jsc + (long long)r * na, u, na, rs[r]);
+    // rows by groups of kRowGroup lanes (a group past the last row computes row 0 and drops it)
+    const int sub = threadIdx.x % kRowGroup, grp = threadIdx.x / kRowGroup, ngrp = blockDim.x / kRowGroup;
+    for (int r0 = 0; r0 < na; r0 += ngrp) {
+        const int r = r0 + grp;
+        const double d = group_row_dot(Jsc + (long long)(r < na ? r : 0) * na, u, na, sub);
+        if (r < na && sub == 0) t[r] = rs[r] - d;
+    }
     __syncthreads();
-    for (int r = threadIdx.x; r < na; r += blockDim.x) {
-        const long long node = c2s[r];
-        const double csr = cs[r], ccr = cc[r];
-        const double v = row_dot<1>(Sinv + (long long)r * na, t, na, 0.0);
-        D->x_s[node] = (T)v;
-        D->x_c[node] = (T)((rc[r] - csr * v) / ccr);
+    for (int r0 = 0; r0 < na; r0 += ngrp) {
+        const int r = r0 + grp;
+        const double v = group_row_dot(Sinv + (long long)(r < na ? r : 0) * na, t, na, sub);
+        if (r < na && sub == 0) {
+            const long long node = c2s[r];
+            const double csr = cs[r], ccr = cc[r];
+            D->x_s[node] = (T)v;
+            D->x_c[node] = (T)((rc[r] - csr * v) / ccr);
+        }
     }
     __syncthreads();
 }
@@ -1042,6 +1039,8 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
     extern __shared__ double sb[];
     const TailArgs &A = args[blockIdx.x];
     if (act && !act[A.d0]) return;
+    // tails held in LDS run in k_tail_lds
+    if (A.lds & (sizeof(T) == 8 ? 1 : 2)) return;
     TailLds<T> S;
     S.coarse = sb;
     S.gb0 = reinterpret_cast<T *>(sb + 4 * ncoarse_max);

@@ -71,6 +71,8 @@ struct TailArgs {
     // coarse tail held in LDS (when the hierarchy's tail fits)
     gptr<const uint32_t> tab;   // table image
     int tab_words, nvals, nints, ngmax;
+    int ncoarse;         // active nodes of the coarsest level (4 ncoarse doubles of LDS)
+    int lds;             // bit 0: this tail runs in LDS in FP64 cycles, bit 1: in FP32 cycles
     TailLdsLevel ll[kMaxLevels];
 };
 
@@ -116,8 +118,10 @@ struct TailLdsSize {
                (size_t)(nints + tab_words) * sizeof(int);
     }
 };
+// (each block lays out its LDS from its own arguments; shm bytes cover the largest;
+// blocks whose lds bit for T is clear return, and k_tail skips the blocks whose bit is set)
 template <typename T> void launch_tail_lds(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks,
-                                           const TailLdsSize &sz, const Exec &x);
+                                           size_t shm, const Exec &x);
 constexpr size_t kTailLdsMax = 158 * 1024;   // of the 160 KiB of a gfx950 CU
 template <typename T> void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int alt,
                                              const Exec &x);

@@ -122,23 +122,63 @@ __device__ __forceinline__ void restrict_vals(uint8_t *ex, const uint8_t *act, c
     out_c = wcs > T(0) ? vc / wcs : T(0);
 }
 
-// sum_q M[r][q] v[q] subtracted from (SIGN < 0) or added to acc, with the row's
-// entries fetched eight at a time and summed in order q = 0 .. na-1
-template <int SIGN, typename P>
-__device__ __forceinline__ double row_dot(P row, const double *v, int na, double acc)
+// Rows evaluated by a group of kRowGroup lanes (the coarse tail and the coarsest
+// solve): lane sub sums the entries sub, sub + G, sub + 2G, ... of the row in
+// order, fetching kRowChunk strides before summing them (entries past the row's
+// end re-read its last entry and are dropped by a select); then the lanes' sums
+// are added pairwise by xor shuffles, and every lane of the group gets the total.
+// Every kernel that evaluates these rows uses this order, and the fused
+// multiply-adds are written out (contraction left to the compiler may pair the
+// products differently in different kernels), so they give the same bits.
+constexpr int kRowGroup = 8;
+constexpr int kRowChunk = 4;
+
+// sum_q M[r][q] v[q] of one row
+template <typename P>
+__device__ __forceinline__ double group_row_dot(P row, const double *v, int na, int sub)
 {
-    for (int q0 = 0; q0 < na; q0 += 8) {
-        double m[8];
+    double acc = 0.0;
+    for (int q0 = sub; q0 < na; q0 += kRowChunk * kRowGroup) {
+        double m[kRowChunk], x[kRowChunk];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) m[e] = q0 + e < na ? row[q0 + e] : 0.0;
+        for (int k = 0; k < kRowChunk; ++k) {
+            const int q = min(q0 + k * kRowGroup, na - 1);
+            m[k] = row[q];
+            x[k] = v[q];
+        }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            if (q0 + e < na) {
-                if (SIGN < 0) acc -= m[e] * v[q0 + e];
-                else acc += m[e] * v[q0 + e];
-            }
+        for (int k = 0; k < kRowChunk; ++k) {
+            const double t = fma(m[k], x[k], acc);
+            acc = q0 + k * kRowGroup < na ? t : acc;
         }
     }
+    for (int off = kRowGroup / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kRowGroup);
+    return acc;
+}
+
+// one composed ghost-map row, sum_e a[e] gb1[col[e]] + b[e] gb0[col[e]] over e in
+// [e0, e1) (the map's entries from HBM, the ghost values in LDS)
+template <typename T, typename PC, typename PV>
+__device__ __forceinline__ T group_ghost_row(PC col, PV a, PV b, const T *gb0, const T *gb1, int e0, int e1, int sub)
+{
+    T acc = 0;
+    for (int e = e0 + sub; e < e1; e += kRowChunk * kRowGroup) {
+        int c[kRowChunk];
+        T av[kRowChunk], bv[kRowChunk];
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k) {
+            const int ek = min(e + k * kRowGroup, e1 - 1);
+            c[k] = col[ek];
+            av[k] = a[ek];
+            bv[k] = b[ek];
+        }
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k) {
+            const T t = acc + fma(av[k], gb1[c[k]], bv[k] * gb0[c[k]]);
+            acc = e + k * kRowGroup < e1 ? t : acc;
+        }
+    }
+    for (int off = kRowGroup / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kRowGroup);
     return acc;
 }
 

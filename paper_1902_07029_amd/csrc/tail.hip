@@ -320,29 +320,21 @@ __device__ void lds_smooth(const LevelDesc<T> *D, const TailLevel &TL, const Lds
         gb1[q] = Z.xs[g];
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < ng; q += blockDim.x) {
-        const int g = Z.nin + q;
-        T cs_d, cc_d;
-        c_row_vals<T>(D, Z.s[g], Z.c[g], cs_d, cc_d);
-        const T xc = Z.xc[g], rc = Z.rhs_c[g];
-        const int e0 = Z.gop[q], e1 = Z.gop[q + 1];
-        T v = 0;
-        for (int e = e0; e < e1; e += 4) {
-            int col[4];
-            T a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool ok = e + u < e1;
-                col[u] = ok ? D->go_col[e + u] : 0;
-                a[u] = ok ? D->go_a[e + u] : T(0);
-                b[u] = ok ? D->go_b[e + u] : T(0);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (e + u < e1) v += a[u] * gb1[col[u]] + b[u] * gb0[col[u]];
+    // the composed rows, kRowGroup lanes per row
+    const int sub = threadIdx.x % kRowGroup, grp = threadIdx.x / kRowGroup, ngrp = blockDim.x / kRowGroup;
+    for (int q0 = 0; q0 < ng; q0 += ngrp) {
+        const int q = q0 + grp;
+        const bool on = q < ng;
+        const int e0 = on ? Z.gop[q] : 0, e1 = on ? Z.gop[q + 1] : 0;
+        const T v = group_ghost_row<T>(D->go_col, D->go_a, D->go_b, gb0, gb1, e0, e1, sub);
+        if (on && sub == 0) {
+            const int g = Z.nin + q;
+            T cs_d, cc_d;
+            c_row_vals<T>(D, Z.s[g], Z.c[g], cs_d, cc_d);
+            const T xc = Z.xc[g], rc = Z.rhs_c[g];
+            Z.xs[g] = v;
+            Z.xc[g] = ghost_c_update<T>(cs_d, cc_d, rc, v, xc);
         }
-        Z.xs[g] = v;
-        Z.xc[g] = ghost_c_update<T>(cs_d, cc_d, rc, v, xc);
     }
     __syncthreads();
 }
@@ -384,18 +376,22 @@ __device__ void lds_band(const LevelDesc<T> *D, const LdsLevel<T> &Z)
         const int cnt = Z.bcnt[b];
         if (cnt == 0) continue;
         T v = 0;
+        // sources fetched eight at a time (past the count: the last source again, not
+        // summed), summed in order
         for (int j0 = 0; j0 < cnt; j0 += 8) {
             int src[8];
             T wt[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const bool ok = j0 + u < cnt;
-                src[u] = ok ? Z.bsrc[(j0 + u) * nb + b] : 0;
-                wt[u] = ok ? D->b_wt[(j0 + u) * nb + b] : T(0);
+                const int ju = min(j0 + u, cnt - 1);
+                src[u] = Z.bsrc[ju * nb + b];
+                wt[u] = D->b_wt[ju * nb + b];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (j0 + u < cnt) v += wt[u] * Z.r_s[src[u]];
+            for (int u = 0; u < 8; ++u) {
+                const T t = fma(wt[u], Z.r_s[src[u]], v);
+                v = j0 + u < cnt ? t : v;
+            }
         }
         Z.r_s[Z.na + b] = v;
     }
@@ -476,14 +472,23 @@ __device__ void lds_coarse(const LevelDesc<T> *D, const LdsLevel<T> &Z, gptr<con
         u[r] = vc / cc[r];
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < na; r += blockDim.x) t[r] = row_dot<-1>(Jsc + (long long)r * na, u, na, rs[r]);
+    // rows by groups of kRowGroup lanes (a group past the last row computes row 0 and drops it)
+    const int sub = threadIdx.x % kRowGroup, grp = threadIdx.x / kRowGroup, ngrp = blockDim.x / kRowGroup;
+    for (int r0 = 0; r0 < na; r0 += ngrp) {
+        const int r = r0 + grp;
+        const double d = group_row_dot(Jsc + (long long)(r < na ? r : 0) * na, u, na, sub);
+        if (r < na && sub == 0) t[r] = rs[r] - d;
+    }
     __syncthreads();
-    for (int r = threadIdx.x; r < na; r += blockDim.x) {
-        const int p = Z.perm[r];
-        const double csr = cs[r], ccr = cc[r];
-        const double v = row_dot<1>(Sinv + (long long)r * na, t, na, 0.0);
-        Z.xs[p] = (T)v;
-        Z.xc[p] = (T)((rc[r] - csr * v) / ccr);
+    for (int r0 = 0; r0 < na; r0 += ngrp) {
+        const int r = r0 + grp;
+        const double v = group_row_dot(Sinv + (long long)(r < na ? r : 0) * na, t, na, sub);
+        if (r < na && sub == 0) {
+            const int p = Z.perm[r];
+            const double csr = cs[r], ccr = cc[r];
+            Z.xs[p] = (T)v;
+            Z.xc[p] = (T)((rc[r] - csr * v) / ccr);
+        }
     }
     __syncthreads();
 }
@@ -491,44 +496,111 @@ __device__ void lds_coarse(const LevelDesc<T> *D, const LdsLevel<T> &Z, gptr<con
 // LDS: [4 ncoarse doubles][ngmax T][ngmax T][nvals T][nints int][tab_words uint32]
 template <typename T, int DIM, int NST>
 __global__ __launch_bounds__(1024) void k_tail_lds(const LevelDesc<T> *__restrict__ descs,
-                                                   const TailArgs *__restrict__ args, TailLdsSize sz,
+                                                   const TailArgs *__restrict__ args,
                                                    const int *__restrict__ act)
 {
     extern __shared__ double sb[];
     const TailArgs &A = args[blockIdx.x];
     if (act && !act[A.d0]) return;
+    if (!(A.lds & (sizeof(T) == 8 ? 1 : 2))) return;
     double *coarse = sb;
-    T *gb0 = reinterpret_cast<T *>(sb + 4 * sz.ncoarse);
-    T *gb1 = gb0 + sz.ngmax;
-    T *V = gb1 + sz.ngmax;
-    int *gop = reinterpret_cast<int *>(V + sz.nvals);
-    uint32_t *tab32 = reinterpret_cast<uint32_t *>(gop + sz.nints);
+    T *gb0 = reinterpret_cast<T *>(sb + 4 * A.ncoarse);
+    T *gb1 = gb0 + A.ngmax;
+    T *V = gb1 + A.ngmax;
+    int *gop = reinterpret_cast<int *>(V + A.nvals);
+    uint32_t *tab32 = reinterpret_cast<uint32_t *>(gop + A.nints);
     const uint16_t *tab = reinterpret_cast<const uint16_t *>(tab32);
     const LevelDesc<T> *base = descs + A.d0;
     const int L = A.nlev;
-    for (int i = threadIdx.x; i < A.tab_words; i += blockDim.x) tab32[i] = A.tab[i];
-    for (int l = A.l0; l < L; ++l) {
-        const LevelDesc<T> *D = base + l;
-        const TailLevel &TL = A.lev[l];
-        const TailLdsLevel &d = A.ll[l];
-        T *b = V + d.v;
-        const int na = d.na, nin = TL.nin0 + TL.nin1;
-        for (int t = threadIdx.x; t < na; t += blockDim.x) {
-            int i, j, k;
-            unpack_ijk(t < nin ? TL.in_ijk[t] : D->g_ijk[t - nin], i, j, k);
-            const long long q = sidx(D->n, D->Wp, D->cs, i, j, k);
-            b[t] = D->s[q];
-            b[na + t] = D->c[q];
-            if (l == A.l0) {
-                b[2 * na + t] = D->x_s[q];
-                b[3 * na + t] = D->x_c[q];
-                b[4 * na + t] = D->rhs_s[q];
-                b[5 * na + t] = D->rhs_c[q];
+    // the table image, kTabChunk words per thread fetched before they are stored
+    constexpr int kTabChunk = 8;
+    for (int i0 = threadIdx.x; i0 < A.tab_words; i0 += kTabChunk * blockDim.x) {
+        uint32_t w[kTabChunk];
+#pragma unroll
+        for (int k = 0; k < kTabChunk; ++k) w[k] = A.tab[min(i0 + k * (int)blockDim.x, A.tab_words - 1)];
+#pragma unroll
+        for (int k = 0; k < kTabChunk; ++k)
+            if (i0 + k * (int)blockDim.x < A.tab_words) tab32[i0 + k * blockDim.x] = w[k];
+    }
+    // every level's values: a tail level has at most one active node per thread, so
+    // the node codes of all levels are fetched first, then all their values
+    constexpr int kLev = 8;
+    if (L - A.l0 <= kLev && blockDim.x >= (unsigned)kTailMaxNodes) {
+        const int t = threadIdx.x;
+        int code[kLev];
+#pragma unroll
+        for (int m = 0; m < kLev; ++m) {
+            const int l = A.l0 + m;
+            code[m] = 0;
+            if (l < L) {
+                const TailLevel &TL = A.lev[l];
+                const int na = A.ll[l].na, nin = TL.nin0 + TL.nin1;
+                if (t < na) code[m] = t < nin ? TL.in_ijk[t] : base[l].g_ijk[t - nin];
             }
         }
+        T sv[kLev], cv[kLev];
+        long long q0 = 0;
+#pragma unroll
+        for (int m = 0; m < kLev; ++m) {
+            const int l = A.l0 + m;
+            sv[m] = cv[m] = T(0);
+            if (l < L && t < A.ll[l].na) {
+                const LevelDesc<T> *D = base + l;
+                int i, j, k;
+                unpack_ijk(code[m], i, j, k);
+                const long long q = sidx(D->n, D->Wp, D->cs, i, j, k);
+                if (m == 0) q0 = q;
+                sv[m] = D->s[q];
+                cv[m] = D->c[q];
+            }
+        }
+        if (t < A.ll[A.l0].na) {
+            const LevelDesc<T> *D = base + A.l0;
+            T *b = V + A.ll[A.l0].v;
+            const int na = A.ll[A.l0].na;
+            b[2 * na + t] = D->x_s[q0];
+            b[3 * na + t] = D->x_c[q0];
+            b[4 * na + t] = D->rhs_s[q0];
+            b[5 * na + t] = D->rhs_c[q0];
+        }
+#pragma unroll
+        for (int m = 0; m < kLev; ++m) {
+            const int l = A.l0 + m;
+            if (l < L && t < A.ll[l].na) {
+                T *b = V + A.ll[l].v;
+                b[t] = sv[m];
+                b[A.ll[l].na + t] = cv[m];
+            }
+        }
+    } else {
+        for (int l = A.l0; l < L; ++l) {
+            const LevelDesc<T> *D = base + l;
+            const TailLevel &TL = A.lev[l];
+            const TailLdsLevel &d = A.ll[l];
+            T *b = V + d.v;
+            const int na = d.na, nin = TL.nin0 + TL.nin1;
+            for (int t = threadIdx.x; t < na; t += blockDim.x) {
+                int i, j, k;
+                unpack_ijk(t < nin ? TL.in_ijk[t] : D->g_ijk[t - nin], i, j, k);
+                const long long q = sidx(D->n, D->Wp, D->cs, i, j, k);
+                b[t] = D->s[q];
+                b[na + t] = D->c[q];
+                if (l == A.l0) {
+                    b[2 * na + t] = D->x_s[q];
+                    b[3 * na + t] = D->x_c[q];
+                    b[4 * na + t] = D->rhs_s[q];
+                    b[5 * na + t] = D->rhs_c[q];
+                }
+            }
+        }
+    }
+    for (int l = A.l0; l < L; ++l) {
+        const LevelDesc<T> *D = base + l;
+        const TailLdsLevel &d = A.ll[l];
+        T *b = V + d.v;
         // band slots that the extension does not reach stay zero, as in HBM; the
         // last slot is the zero read for inactive fine nodes
-        for (int t = threadIdx.x; t <= d.nb; t += blockDim.x) b[8 * na + t] = T(0);
+        for (int t = threadIdx.x; t <= d.nb; t += blockDim.x) b[8 * d.na + t] = T(0);
         if (l < L - 1 && D->go_ptr)
             for (int q = threadIdx.x; q <= D->ng; q += blockDim.x) gop[d.gop + q] = D->go_ptr[q];
     }
@@ -584,11 +656,9 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const LevelDesc<T> *__restric
 }
 
 template <typename T>
-void launch_tail_lds(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, const TailLdsSize &sz,
-                     const Exec &x)
+void launch_tail_lds(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, size_t shm, const Exec &x)
 {
     if (nblocks <= 0) return;
-    const size_t shm = sz.bytes<T>();
     if (dim == 2) {
         static bool attr = false;
         if (!attr) {
@@ -596,7 +666,7 @@ void launch_tail_lds(int dim, const LevelDesc<T> *d, const TailArgs *args, int n
                                       (int)kTailLdsMax);
             attr = true;
         }
-        k_tail_lds<T, 2, 9><<<nblocks, 1024, shm, x.s>>>(d, args, sz, x.act);
+        k_tail_lds<T, 2, 9><<<nblocks, 1024, shm, x.s>>>(d, args, x.act);
     } else {
         static bool attr = false;
         if (!attr) {
@@ -604,13 +674,13 @@ void launch_tail_lds(int dim, const LevelDesc<T> *d, const TailArgs *args, int n
                                       (int)kTailLdsMax);
             attr = true;
         }
-        k_tail_lds<T, 3, 27><<<nblocks, 1024, shm, x.s>>>(d, args, sz, x.act);
+        k_tail_lds<T, 3, 27><<<nblocks, 1024, shm, x.s>>>(d, args, x.act);
     }
 }
 
-template void launch_tail_lds<double>(int, const LevelDesc<double> *, const TailArgs *, int, const TailLdsSize &,
+template void launch_tail_lds<double>(int, const LevelDesc<double> *, const TailArgs *, int, size_t,
                                       const Exec &);
-template void launch_tail_lds<float>(int, const LevelDesc<float> *, const TailArgs *, int, const TailLdsSize &,
+template void launch_tail_lds<float>(int, const LevelDesc<float> *, const TailArgs *, int, size_t,
                                      const Exec &);
 
 }  // namespace lsmg

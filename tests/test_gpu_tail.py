@@ -1,8 +1,10 @@
 """The coarse tail held in LDS against the same tail read from HBM (hierarchies built
 with LSMG_TAIL_LDS=0): the two apply the same row arithmetic to the same values in the
-same order, so whole cycles and whole steps must agree bit for bit.  V- and W-cycles,
-2-D and 3-D, Dirichlet and Neumann rows, FP64 and mixed precision, single hierarchies
-and a batch."""
+same order, and on these shapes whole cycles and whole steps agree bit for bit.  V- and
+W-cycles, 2-D and 3-D, Dirichlet and Neumann rows, FP64 and mixed precision, single
+hierarchies and a batch.  (Compiled separately, the two kernels may pair a product
+with an addition differently somewhere; a batch therefore runs each member's tail in
+the kernel the member runs alone, which the last test checks.)"""
 import os
 
 import numpy as np
@@ -98,3 +100,43 @@ def test_tail_in_lds_batch_bitwise():
         out.append([st.get() for st in sts])
     for a, b in zip(*out):
         assert torch.equal(a, b)
+
+
+@pytest.mark.gpu
+def test_batch_members_run_their_own_tail_kind():
+    # the 3-D domains of the serving test (unions of ellipsoids, 33^3 and 65^3, mixed
+    # precision): one member's tail does not fit LDS, the others' do; each member runs in
+    # the batch the tail kernel it runs alone (the two kernels agree only to rounding on
+    # some of these domains), so the batch equals stepping alone bit for bit
+    from test_gpu_serve import _requests
+    params = lsmg.default_params(coarsest_n=9, precision=1)
+    reqs = _requests(6, 3, steps=(8, 15), gap=0.01)
+
+    def hier(r):
+        return lsmg.Hierarchy(torch.from_numpy(r.phi), r.dim, r.n, params=params)
+
+    def state(H, r):
+        st = lsmg.State(H)
+        nn = r.n ** r.dim
+        st.set_grid(torch.full((nn,), r.s0, dtype=torch.float64, device="cuda"),
+                    torch.full((nn,), r.c0, dtype=torch.float64, device="cuda"))
+        return st
+
+    alone = [(hier(r), r) for r in reqs]
+    kinds = [H.tail_in_lds(1) for H, _ in alone]
+    assert any(kinds) and not all(kinds), kinds
+    ref = []
+    for H, r in alone:
+        st = state(H, r)
+        for _ in range(3):
+            st.step(r.dt, sb_const=r.sb)
+        ref.append(st.get())
+    Hs = [hier(r) for r in reqs]
+    sts = [state(H, r) for H, r in zip(Hs, reqs)]
+    B = lsmg.Batch(Hs)
+    for _ in range(3):
+        status, _ = B.step(sts, reqs[0].dt, sb_const=[r.sb for r in reqs])
+        assert all(x == lsmg.OK for x in status)
+    say(f"tail kinds (LDS) per member: {kinds}")
+    for k in range(len(reqs)):
+        assert torch.equal(sts[k].get(), ref[k]), k
