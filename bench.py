@@ -120,6 +120,23 @@ def load_traffic(kernel, workload, precision):
     return None
 
 
+def host_cpu():
+    """The host's CPU model and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    return {"model": model, "cores_available": ncpu}
+
+
 def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label, max_steps=200, bc=0,
                  box=(-1.0, 1.0), c0=1.0):
     """The oracle (serial, one core) on the first steps of a domain of the workload,
@@ -149,10 +166,51 @@ def cpu_baseline(phi, dim, n, coarsest, dt, params, budget_s, gpu_states, label,
         if time.perf_counter() - t0 > budget_s and steps >= len(gpu_states):
             break
     el = time.perf_counter() - t0
-    return dict(value=2 * na * cycles / el, unit="unknowns*cycles/s", cores=1, kind="oracle",
+    return dict(value=2 * na * cycles / el, unit="unknowns*cycles/s", cores=1, kind="oracle", host=host_cpu(),
                 sample=f"first {steps} Crank-Nicolson steps of {label} ({cycles} V-cycles, {el:.1f} s, "
                        f"serial C, one host core)"), \
         dict(steps_checked=min(steps, len(gpu_states)), max_rel_err=worst, domain=label)
+
+
+def _oracle_worker(job):
+    """One host process of the all-cores baseline: the oracle stepping one domain for
+    about budget seconds (module-level for the spawn start method)."""
+    phi, dim, n, coarsest, dt, params, budget = job
+    import oracle
+    O = oracle.Hierarchy(phi, dim, n, coarsest_n=coarsest, params=params)
+    info = O.level_info(0)
+    s0, c0 = I.initial_state(n, dim)
+    W = O.to_compact(0, s0, c0)
+    sb = np.ones(info["ng"])
+    cycles = steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget:
+        rc, W, st = O.newton_cn_step(W, dt, sb)
+        if rc != 0:
+            raise RuntimeError(f"oracle step failed with {rc}")
+        cycles += st["vcycles"]
+        steps += 1
+    return 2 * info["na"] * cycles, time.perf_counter() - t0, steps, cycles
+
+
+def cpu_baseline_pool(jobs_in, budget_s, label):
+    """The oracle on every host core at once: one process per domain (the first
+    domains of the workload), each for about budget_s seconds; the throughputs add."""
+    import multiprocessing
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    workers = max(1, min(16, ncpu, len(jobs_in)))
+    jobs = [j + (budget_s,) for j in jobs_in[:workers]]
+    with multiprocessing.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    value = sum(u / el for u, el, _, _ in res)
+    steps = sum(r[2] for r in res)
+    cycles = sum(r[3] for r in res)
+    return dict(value=value, unit="unknowns*cycles/s", cores=workers, kind="oracle", host=host_cpu(),
+                sample=f"{workers} host processes at once, one domain each ({label}), "
+                       f"{steps} Crank-Nicolson steps and {cycles} V-cycles in about {budget_s:.0f} s each")
 
 
 def oracle_params(H):
@@ -539,6 +597,13 @@ def run_batch(args):
                                  f"batch member {k} (star {dk['n']}^2)", max_steps=len(traj[k]))
             parity["small"].append(pk)
         parity["max_rel_err_all"] = max([parity["max_rel_err"]] + [q["max_rel_err"] for q in parity["small"]])
+    # all host cores at once (one oracle process per domain)
+    cpu_all = None
+    if not args.no_cpu_baseline:
+        op = oracle_params(Hs[0])
+        jobs = [(phis[k], 2, doms[k]["n"], doms[k]["coarsest"], dt, op) for k in range(len(doms))]
+        cpu_all = cpu_baseline_pool(jobs, args.cpu_budget, "the batch's first domains, grids "
+                                    + "/".join(str(doms[k]["n"]) for k in range(min(16, len(doms)))))
     lat_ms = np.array(lat) * 1e3
     sizes = {}
     for d in doms:
@@ -568,6 +633,7 @@ def run_batch(args):
         "speedup_vs_fp64_sequential": (value / seq["value"]) if seq else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
         "parity": parity,
     }
 
