@@ -660,7 +660,9 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     Level &Lv = H->L[l];
     for (void *p : {(void *)Lv.go_ptr, (void *)Lv.go_col, (void *)Lv.go_a, (void *)Lv.go_b, (void *)Lv.go_a32,
                     (void *)Lv.go_b32, (void *)Lv.gc_ptr, (void *)Lv.gc_idx, (void *)Lv.gc_w, (void *)Lv.gc_w32,
-                    (void *)Lv.go_sidx}) {
+                    (void *)Lv.go_sidx, (void *)Lv.ell_col, (void *)Lv.ell_six, (void *)Lv.ellf_idx,
+                    (void *)Lv.ell_a, (void *)Lv.ell_b, (void *)Lv.ellf_w, (void *)Lv.ell_a32, (void *)Lv.ell_b32,
+                    (void *)Lv.ellf_w32}) {
         if (!p) continue;
         (void)hipFree(p);
         for (auto &q : H->ghost_ops)
@@ -670,6 +672,10 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     Lv.go_a = Lv.go_b = nullptr;
     Lv.go_a32 = Lv.go_b32 = nullptr;
     Lv.gc_ptr = Lv.gc_idx = Lv.go_sidx = nullptr;
+    Lv.ell_we = Lv.ell_wf = 0;
+    Lv.ell_col = Lv.ell_six = Lv.ellf_idx = nullptr;
+    Lv.ell_a = Lv.ell_b = Lv.ellf_w = nullptr;
+    Lv.ell_a32 = Lv.ell_b32 = Lv.ellf_w32 = nullptr;
     Lv.gc_w = nullptr;
     Lv.gc_w32 = nullptr;
     Lv.go_bytes = 0;
@@ -786,6 +792,48 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
         LSMGCHK(up((void **)&Lv.gc_idx, cidx.data(), sizeof(int) * cn));
         LSMGCHK(up((void **)&Lv.gc_w, cw.data(), sizeof(double) * cn));
         LSMGCHK(up((void **)&Lv.gc_w32, cw32.data(), sizeof(float) * cn));
+        // the same rows padded to fixed widths (multiples of 16: the 16 lanes of a row),
+        // where every row fits in 64 entries per part (one chunk of the apply kernel)
+        int we = 16, wf = 16;
+        for (int q = 0; q < ng; ++q) {
+            we = std::max(we, (ptr[q + 1] - ptr[q] + 15) / 16 * 16);
+            wf = std::max(wf, (cptr[q + 1] - cptr[q] + 15) / 16 * 16);
+        }
+        if (we > 64 || wf > 64) we = wf = 0;
+        if (we > 0) {
+        std::vector<int> ecol((size_t)ng * we), esix((size_t)ng * we), fidx((size_t)ng * wf);
+        std::vector<double> ea((size_t)ng * we, 0.0), eb((size_t)ng * we, 0.0), fw((size_t)ng * wf, 0.0);
+        for (int q = 0; q < ng; ++q) {
+            for (int k = 0; k < we; ++k) {
+                const int e = ptr[q] + k;
+                const bool in = e < ptr[q + 1];
+                ecol[(size_t)q * we + k] = in ? col[e] : q;
+                esix[(size_t)q * we + k] = in ? sx[e] : gidx[q];
+                if (in) {
+                    ea[(size_t)q * we + k] = va[e];
+                    eb[(size_t)q * we + k] = vb[e];
+                }
+            }
+            for (int k = 0; k < wf; ++k) {
+                const int f = cptr[q] + k;
+                const bool in = f < cptr[q + 1];
+                fidx[(size_t)q * wf + k] = in ? cidx[f] : gidx[q];
+                if (in) fw[(size_t)q * wf + k] = cw[f];
+            }
+        }
+        std::vector<float> ea32(ea.begin(), ea.end()), eb32(eb.begin(), eb.end()), fw32(fw.begin(), fw.end());
+        Lv.ell_we = we;
+        Lv.ell_wf = wf;
+        LSMGCHK(up((void **)&Lv.ell_col, ecol.data(), sizeof(int) * ecol.size()));
+        LSMGCHK(up((void **)&Lv.ell_six, esix.data(), sizeof(int) * esix.size()));
+        LSMGCHK(up((void **)&Lv.ellf_idx, fidx.data(), sizeof(int) * fidx.size()));
+        LSMGCHK(up((void **)&Lv.ell_a, ea.data(), sizeof(double) * ea.size()));
+        LSMGCHK(up((void **)&Lv.ell_b, eb.data(), sizeof(double) * eb.size()));
+        LSMGCHK(up((void **)&Lv.ellf_w, fw.data(), sizeof(double) * fw.size()));
+        LSMGCHK(up((void **)&Lv.ell_a32, ea32.data(), sizeof(float) * ea32.size()));
+        LSMGCHK(up((void **)&Lv.ell_b32, eb32.data(), sizeof(float) * eb32.size()));
+        LSMGCHK(up((void **)&Lv.ellf_w32, fw32.data(), sizeof(float) * fw32.size()));
+        }
     }
     HIPCHK(hipStreamSynchronize(H->stream));
     return LSMG_OK;
@@ -818,6 +866,8 @@ void make_descs(lsmg_hierarchy *H)
         D.g_buf0 = Lv.g_buf0; D.g_buf1 = Lv.g_buf1;
         D.go_ptr = Lv.go_ptr; D.go_col = Lv.go_col; D.go_a = Lv.go_a; D.go_b = Lv.go_b;
         D.gc_ptr = Lv.gc_ptr; D.gc_idx = Lv.gc_idx; D.gc_w = Lv.gc_w; D.go_sidx = Lv.go_sidx;
+        D.ell_we = Lv.ell_we; D.ell_wf = Lv.ell_wf; D.ell_col = Lv.ell_col; D.ell_six = Lv.ell_six;
+        D.ellf_idx = Lv.ellf_idx; D.ell_a = Lv.ell_a; D.ell_b = Lv.ell_b; D.ellf_w = Lv.ellf_w;
         D.b_idx = Lv.b_idx; D.b_cnt = Lv.b_cnt; D.b_src = Lv.b_src; D.b_wt = Lv.b_wt;
         D.norms = H->d_norms; D.norm_stride = kNormSlots;
         if (l == 0) {
@@ -836,6 +886,8 @@ void make_descs(lsmg_hierarchy *H)
         E.g_buf0 = Lv.g_buf0_32; E.g_buf1 = Lv.g_buf1_32;
         E.go_ptr = Lv.go_ptr; E.go_col = Lv.go_col; E.go_a = Lv.go_a32; E.go_b = Lv.go_b32;
         E.gc_ptr = Lv.gc_ptr; E.gc_idx = Lv.gc_idx; E.gc_w = Lv.gc_w32; E.go_sidx = Lv.go_sidx;
+        E.ell_we = Lv.ell_we; E.ell_wf = Lv.ell_wf; E.ell_col = Lv.ell_col; E.ell_six = Lv.ell_six;
+        E.ellf_idx = Lv.ellf_idx; E.ell_a = Lv.ell_a32; E.ell_b = Lv.ell_b32; E.ellf_w = Lv.ellf_w32;
         E.b_idx = D.b_idx; E.b_cnt = D.b_cnt; E.b_src = D.b_src; E.b_wt = Lv.b_wt32;
         E.norms = D.norms; E.norm_stride = D.norm_stride;
     }

@@ -60,6 +60,12 @@ struct Level {
     float *go_a32 = nullptr, *go_b32 = nullptr;
     int *gc_ptr = nullptr, *gc_idx = nullptr;   // 2-D: the folded b-part (C = B W_GI)
     int *go_sidx = nullptr;                     // 2-D: storage index of each entry's ghost
+    // 2-D: the folded rows again, padded to a fixed width per level (ELL): entry k of
+    // ghost q at q * we + k (b-part) and q * wf + k (C-part); padding has zero weights
+    int ell_we = 0, ell_wf = 0;
+    int *ell_col = nullptr, *ell_six = nullptr, *ellf_idx = nullptr;
+    double *ell_a = nullptr, *ell_b = nullptr, *ellf_w = nullptr;
+    float *ell_a32 = nullptr, *ell_b32 = nullptr, *ellf_w32 = nullptr;
     double *gc_w = nullptr;
     float *gc_w32 = nullptr;
     // [seg colour 0 | seg colour 1 | ghost chunks of 64 | band chunks | ghost chunks of 4 (3-D)]

@@ -745,7 +745,51 @@ __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply_grouped(const LevelDe
         const bool on = q < w.w;
         T v = 0, sg = 0, cg = 0, xcg = 0, rcg = 0;
         long long g = 0;
-        if (on) {
+        const int ne = FOLD ? D->ell_we >> 4 : 0, nf = FOLD ? D->ell_wf >> 4 : 0;
+        if (FOLD && on && ne >= 1 && ne <= kApplyChunk && nf <= kApplyChunk) {
+            // the padded rows (each part within one chunk): no row pointers to wait for;
+            // lane sub takes the entries sub, sub + 16, ... of each part, in order (b-part,
+            // then C-part), and the padding adds exact zeros
+            const long long eb = (long long)q * D->ell_we + sub, fb = (long long)q * D->ell_wf + sub;
+            {
+                // one chunk per part: the row's entries and the ghost's index in one round
+                // trip, then every value in a second
+                int col[kApplyChunk], six[kApplyChunk], ix[kApplyChunk];
+                T a[kApplyChunk], b[kApplyChunk], cw[kApplyChunk];
+#pragma unroll
+                for (int k = 0; k < kApplyChunk; ++k) {
+                    const long long ek = eb + 16 * min(k, ne - 1), fk = fb + 16 * min(k, nf - 1);
+                    col[k] = D->ell_col[ek];
+                    six[k] = D->ell_six[ek];
+                    a[k] = D->ell_a[ek];
+                    b[k] = D->ell_b[ek];
+                    ix[k] = D->ellf_idx[fk];
+                    cw[k] = D->ellf_w[fk];
+                }
+                g = D->g_idx[q];
+                sg = D->s[g];
+                cg = D->c[g];
+                xcg = XC[g];
+                rcg = D->rhs_c[g];
+                T u[kApplyChunk], r[kApplyChunk], xv[kApplyChunk];
+#pragma unroll
+                for (int k = 0; k < kApplyChunk; ++k) {
+                    u[k] = D->g_buf1[col[k]];
+                    r[k] = D->rhs_s[six[k]];
+                    xv[k] = XS[ix[k]];
+                }
+#pragma unroll
+                for (int k = 0; k < kApplyChunk; ++k) {
+                    const T t = v + (a[k] * u[k] + b[k] * r[k]);
+                    v = k < ne ? t : v;
+                }
+#pragma unroll
+                for (int k = 0; k < kApplyChunk; ++k) {
+                    const T t = v - cw[k] * xv[k];
+                    v = k < nf ? t : v;
+                }
+            }
+        } else if (on) {
             g = D->g_idx[q];
             int e = D->go_ptr[q] + sub, f = FOLD ? D->gc_ptr[q] + sub : 0;
             const int e1 = D->go_ptr[q + 1], f1 = FOLD ? D->gc_ptr[q + 1] : 0;

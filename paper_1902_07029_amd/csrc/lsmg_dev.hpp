@@ -97,6 +97,11 @@ struct LevelDesc {
     gptr<const int> gc_ptr, gc_idx;
     gptr<const T> gc_w;
     gptr<const int> go_sidx;      // 2-D: g_idx[go_col[e]], the storage index of entry e's ghost
+    // 2-D: the folded rows padded to widths ell_we / ell_wf (entry k of ghost q at
+    // q * width + k; padding: zero weights on the ghost itself), read without row pointers
+    int ell_we, ell_wf;
+    gptr<const int> ell_col, ell_six, ellf_idx;
+    gptr<const T> ell_a, ell_b, ellf_w;
     // band of inactive nodes used by the boundary-defect restriction
     gptr<const int> b_idx;        // storage index of band node b
     gptr<const int> b_cnt;        // number of ghost sources
