@@ -416,32 +416,54 @@ __device__ __forceinline__ void inject_elem(const LevelDesc<T> *C, int4 w, int l
     if (!node_of<T, DIM>(C, w, lane, cidx, ci[0], ci[1], ci[2])) return;
     const int fn = F->n;
     const int fc[3] = {2 * ci[0], 2 * ci[1], 2 * ci[2]};
-    const long long fq = sidx(fn, F->Wp, F->cs, fc[0], fc[1], fc[2]);
-    if (F->type[fq] != kOut) {
+    if (item_kind(w) < 2) {
+        // a coarse inside node's fine centre has the same level-set value: inside
+        const long long fq = sidx(fn, F->Wp, F->cs, fc[0], fc[1], fc[2]);
         C->s[cidx] = F->s[fq];
         C->c[cidx] = F->c[fq];
         return;
     }
-    T ws = 0, vs = 0, vc = 0;
     constexpr int NST = DIM == 2 ? 9 : 27;
+    constexpr int CEN = DIM == 2 ? 4 : 13;
+    // the whole fine neighbourhood is read at once (out-of-box entries read the
+    // centre and are dropped), then combined in order with selects
+    uint8_t t[NST];
+    T sv[NST], cv[NST];
+    bool inb[NST];
+#pragma unroll
     for (int kk = 0; kk < NST; ++kk) {
         const int d[3] = {kk % 3 - 1, (kk / 3) % 3 - 1, DIM == 3 ? kk / 9 - 1 : 0};
         int id[3];
-        T wk = 1;
         bool in = true;
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            id[a] = fc[a] + d[a];
-            if (a < DIM) {
-                wk *= d[a] == 0 ? T(0.5) : T(0.25);
-                if (id[a] < 0 || id[a] >= fn) in = false;
-            }
+            id[a] = fc[a] + (a < DIM ? d[a] : 0);
+            if (a < DIM && (id[a] < 0 || id[a] >= fn)) in = false;
         }
-        if (!in) continue;
-        const long long q = sidx(fn, F->Wp, F->cs, id[0], id[1], id[2]);
-        if (F->type[q] == kOut) continue;
-        ws += wk;
-        vs += wk * F->s[q];
-        vc += wk * F->c[q];
+        const long long q = in ? sidx(fn, F->Wp, F->cs, id[0], id[1], id[2])
+                               : sidx(fn, F->Wp, F->cs, fc[0], fc[1], fc[2]);
+        inb[kk] = in;
+        t[kk] = F->type[q];
+        sv[kk] = F->s[q];
+        cv[kk] = F->c[q];
+    }
+    if (t[CEN] != kOut) {
+        C->s[cidx] = sv[CEN];
+        C->c[cidx] = cv[CEN];
+        return;
+    }
+    T ws = 0, vs = 0, vc = 0;
+#pragma unroll
+    for (int kk = 0; kk < NST; ++kk) {
+        const int d[3] = {kk % 3 - 1, (kk / 3) % 3 - 1, DIM == 3 ? kk / 9 - 1 : 0};
+        T wk = 1;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) wk *= d[a] == 0 ? T(0.5) : T(0.25);
+        const bool use = inb[kk] && t[kk] != kOut;
+        const T ws1 = ws + wk, vs1 = vs + wk * sv[kk], vc1 = vc + wk * cv[kk];
+        ws = use ? ws1 : ws;
+        vs = use ? vs1 : vs;
+        vc = use ? vc1 : vc;
     }
     C->s[cidx] = vs / ws;
     C->c[cidx] = vc / ws;
