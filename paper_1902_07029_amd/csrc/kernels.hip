@@ -1602,6 +1602,227 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
     if (tid == 0) *CA.status = s_bad ? 1 : 0;
 }
 
+// One DPP step of a wavefront argmax: each lane takes the (value, index, payload)
+// of the lane the control names when that value is larger or equal with a smaller
+// index (lanes of rows the mask leaves out compare with themselves).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void argmax_dpp_step(double &a, int &i, double &pay)
+{
+    const long long ab = __double_as_longlong(a), pb = __double_as_longlong(pay);
+    const int alo = __builtin_amdgcn_update_dpp((int)ab, (int)ab, CTRL, ROWS, 0xf, false);
+    const int ahi = __builtin_amdgcn_update_dpp((int)(ab >> 32), (int)(ab >> 32), CTRL, ROWS, 0xf, false);
+    const int plo = __builtin_amdgcn_update_dpp((int)pb, (int)pb, CTRL, ROWS, 0xf, false);
+    const int phi = __builtin_amdgcn_update_dpp((int)(pb >> 32), (int)(pb >> 32), CTRL, ROWS, 0xf, false);
+    const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWS, 0xf, false);
+    const double oa = __longlong_as_double(((long long)ahi << 32) | (unsigned)alo);
+    const double op = __longlong_as_double(((long long)phi << 32) | (unsigned)plo);
+    const bool take = oa > a || (oa == a && oi < i);
+    a = take ? oa : a;
+    i = take ? oi : i;
+    pay = take ? op : pay;
+}
+
+// Wavefront argmax of a with ties to the smaller index, payload carried along, in
+// every lane: pairs within quads, half rows and rows, then the two row broadcasts
+// (rows 1 and 3 take row 0 and row 2, rows 2 and 3 take lane 31), which leave the
+// result in lane 63.  The combine is associative and commutative, so the result is
+// the one of any other reduction order.  Called with every lane active.
+__device__ __forceinline__ void wave_argmax(double &a, int &i, double &pay)
+{
+    argmax_dpp_step<0xB1, 0xf>(a, i, pay);    // quad_perm [1, 0, 3, 2]
+    argmax_dpp_step<0x4E, 0xf>(a, i, pay);    // quad_perm [2, 3, 0, 1]
+    argmax_dpp_step<0x141, 0xf>(a, i, pay);   // row_half_mirror
+    argmax_dpp_step<0x140, 0xf>(a, i, pay);   // row_mirror
+    argmax_dpp_step<0x142, 0xa>(a, i, pay);   // row_bcast:15
+    argmax_dpp_step<0x143, 0xc>(a, i, pay);   // row_bcast:31
+    const long long ab = __double_as_longlong(a), pb = __double_as_longlong(pay);
+    const int alo = __builtin_amdgcn_readlane((int)ab, 63), ahi = __builtin_amdgcn_readlane((int)(ab >> 32), 63);
+    const int plo = __builtin_amdgcn_readlane((int)pb, 63), phi = __builtin_amdgcn_readlane((int)(pb >> 32), 63);
+    i = __builtin_amdgcn_readlane(i, 63);
+    a = __longlong_as_double(((long long)ahi << 32) | (unsigned)alo);
+    pay = __longlong_as_double(((long long)phi << 32) | (unsigned)plo);
+}
+
+// The same factorisation for operators of at most kSmallCoarseN unknowns, with
+// one barrier per pivot instead of five: S and J^sc are assembled in LDS, and the
+// elimination writes each step's matrix into the other of two LDS copies.  Every
+// wavefront finds the pivot of the step by itself (the same search and tie rule,
+// so all agree), and every thread computes its entries of the next copy from the
+// previous one: the pivot row scaled by the reciprocal pivot, every other row less
+// its factor times that row, with the interchange of the pivot row and row kc
+// folded into which source row is read.  Each entry gets the value of the in-place
+// elimination above, bit for bit.  The interchanges are composed into one column
+// permutation that is applied while the inverse is written out.
+constexpr int kSmallCoarseN = 96;
+constexpr int kSmallEpt = (kSmallCoarseN * kSmallCoarseN + 1023) / 1024;
+
+// Gauss-Jordan steps of the small-operator factorisation with EPT entries of the
+// matrix per thread (entry tid + u blockDim); step kc reads copy kc & 1 of the two
+// in lds and writes the other.  Returns the number of steps done: N, or the step
+// whose pivot was not positive (the matrix is then left as it was before it).
+template <int EPT>
+__device__ __forceinline__ int small_eliminate(double *lds, int N, int *piv)
+{
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1), NN = N * N;
+    int ei[EPT], ec[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * nt;
+        ei[u] = e < NN ? e / N : -1;
+        ec[u] = e < NN ? e - ei[u] * N : 0;
+    }
+    for (int kc = 0; kc < N; ++kc) {
+        double *P = lds + (kc & 1) * NN, *Q = lds + ((kc & 1) ^ 1) * NN;
+        // pivot: largest |P[i][kc]|, i >= kc, first index on ties
+        double best = -1.0, bval = 0.0;
+        int bi = N;
+        for (int i2 = kc + lane; i2 < N; i2 += kWave) {
+            const double v = P[i2 * N + kc];
+            if (fabs(v) > best) {
+                best = fabs(v);
+                bval = v;
+                bi = i2;
+            }
+        }
+        wave_argmax(best, bi, bval);
+        if (!(best > 0.0) || bi >= N) return kc;
+        const int pr = bi;
+        if (tid == 0) piv[kc] = pr;
+        const double inv = 1.0 / bval;
+        // every load of the step is issued before the first new entry is stored
+        double nv[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int i = ei[u] < 0 ? 0 : ei[u], c = ec[u];
+            const int src = i == pr ? kc : i;
+            const double prc = P[pr * N + c], f = P[src * N + kc], a = P[src * N + c];
+            const double pk = (c == kc ? 1.0 : prc) * inv;
+            nv[u] = i == kc ? pk : (c == kc ? 0.0 : a) - f * pk;
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u)
+            if (ei[u] >= 0) Q[ei[u] * N + ec[u]] = nv[u];
+        __syncthreads();
+    }
+    return N;
+}
+
+template <int DIM, int NST>
+__global__ __launch_bounds__(1024) void k_coarse_invert_small(const LevelDesc<double> *__restrict__ descs,
+                                                              const CoarseArgs *__restrict__ args, LSMG_ACT)
+{
+    extern __shared__ double lds[];
+    __shared__ double csl[kSmallCoarseN], ccl[kSmallCoarseN];
+    __shared__ int piv[kSmallCoarseN], col[kSmallCoarseN];
+    const CoarseArgs &CA = args[blockIdx.x];
+    if (act && !act[CA.desc]) return;
+    const LevelDesc<double> *D = descs + CA.desc;
+    const int *__restrict__ c2s = CA.c2s;
+    double *__restrict__ Ainv = CA.Ainv;
+    const int na = D->na, ni = D->ni, N = na, NN = na * na;
+    double *Jsc = Ainv + (long long)NN, *csv = Ainv + 2LL * NN, *ccv = csv + na;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
+    double *P = lds, *Q = lds + NN;   // S in P, J^sc in Q; then the elimination's two copies
+    for (int e = tid; e < 2 * NN; e += nt) lds[e] = 0.0;
+    if (tid < na) {
+        double a, b;
+        c_row<double>(D, c2s[tid], a, b);
+        csv[tid] = a;
+        ccv[tid] = b;
+        csl[tid] = a;
+        ccl[tid] = b;
+    }
+    __syncthreads();
+    // s-rows (section 3.4): every value of a row is loaded before its entries are added
+    if (tid < ni) {
+        const int r = tid;
+        const long long idx = c2s[r];
+        const long long colour = idx / D->cs;
+        const long long rem = idx - colour * D->cs;
+        const long long row = rem / D->Wp;
+        const int p = (int)(rem - row * D->Wp);
+        int i, j, k;
+        node_coords<DIM>(D->n, (int)colour, row, p, i, j, k);
+        long long nb[2 * DIM];
+        neighbours<DIM>(D->n, D->Wp, D->cs, (int)colour, row, i, p, nb);
+        double se[2 * DIM], ce[2 * DIM];
+        int q[2 * DIM];
+#pragma unroll
+        for (int e = 0; e < 2 * DIM; ++e) {
+            se[e] = D->s[nb[e]];
+            ce[e] = D->c[nb[e]];
+            q[e] = D->cmap[nb[e]];
+        }
+        const double sr = D->s[idx], cr = D->c[idx];
+        const double al = D->alpha, be = D->beta, kap = D->kap;
+        const double phr = al * cr + be;
+        double *Rs = P + r * N, *Rsc = Q + r * N;
+        double sum_ss = 0.0, sum_sc = 0.0;
+#pragma unroll
+        for (int e = 0; e < 2 * DIM; ++e) {
+            const double a_ss = (al * ce[e] + be) + phr, a_sc = sr - se[e];
+            sum_ss += a_ss;
+            sum_sc += a_sc;
+            Rs[q[e]] += -kap * a_ss;
+            Rsc[q[e]] += kap * al * a_sc;
+        }
+        Rs[r] += phr * D->dt_inv + D->ks_half * phr * cr + kap * sum_ss;
+        Rsc[r] += al * sr * D->dt_inv + D->ks_half * (al * sr * cr + phr * sr) + kap * al * sum_sc;
+    } else if (tid < na) {
+        const int r = tid, g = r - ni, ng = D->ng;
+        double w[NST];
+        int cm[NST];
+#pragma unroll
+        for (int kk = 0; kk < NST; ++kk) {
+            w[kk] = D->g_w[kk * ng + g];
+            cm[kk] = D->cmap[D->g_st[kk * ng + g]];
+        }
+        double *Rs = P + r * N;
+#pragma unroll
+        for (int kk = 0; kk < NST; ++kk)
+            if (w[kk] != 0.0) Rs[cm[kk]] += w[kk];
+    }
+    __syncthreads();
+    // S = J^ss - J^sc diag(J^cs / J^cc); J^sc goes out
+    for (int e = tid; e < NN; e += nt) {
+        const int c = e % N;
+        P[e] -= Q[e] * (csl[c] / ccl[c]);
+        Jsc[e] = Q[e];
+    }
+    __syncthreads();
+    // entries per thread: a compile-time count, so that every load of a step is in flight at once
+    int steps;
+    switch ((NN + nt - 1) / nt) {
+    case 1: steps = small_eliminate<1>(lds, N, piv); break;
+    case 2: steps = small_eliminate<2>(lds, N, piv); break;
+    case 3: steps = small_eliminate<3>(lds, N, piv); break;
+    case 4: steps = small_eliminate<4>(lds, N, piv); break;
+    case 5: steps = small_eliminate<5>(lds, N, piv); break;
+    case 6: steps = small_eliminate<6>(lds, N, piv); break;
+    case 7: steps = small_eliminate<7>(lds, N, piv); break;
+    case 8: steps = small_eliminate<8>(lds, N, piv); break;
+    default: steps = small_eliminate<kSmallEpt>(lds, N, piv); break;
+    }
+    const bool bad = steps < N;
+    P = lds + (steps & 1) * NN;
+    // the row interchanges, undone as column interchanges last first, as one permutation
+    if (tid == 0) {
+        for (int c = 0; c < N; ++c) col[c] = c;
+        if (!bad)
+            for (int kc = N - 1; kc >= 0; --kc) {
+                const int pr = piv[kc], t = col[kc];
+                col[kc] = col[pr];
+                col[pr] = t;
+            }
+    }
+    __syncthreads();
+    for (int e = tid; e < NN; e += nt) {
+        const int r = e / N, c = e - r * N;
+        Ainv[e] = P[r * N + col[c]];
+    }
+    if (tid == 0) *CA.status = bad ? 1 : 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_coarse_apply(const LevelDesc<T> *__restrict__ descs, int lev,
                                                        const int *__restrict__ c2s, const double *__restrict__ Ainv)
@@ -1838,13 +2059,28 @@ void launch_grid_to_split(const int64_t *c2g, int na, const double *gs, const do
 }
 
 // dynamic LDS for the coarsest matrix: 147 KiB of the 160 KiB of a gfx950 CU
-// (the kernel's own shared arrays take 12 KiB)
+// (the kernels' own shared arrays take at most 12 KiB); operators of at most
+// kSmallCoarseN unknowns take the one-barrier-per-pivot kernel with two copies
 constexpr size_t kCoarseLdsMax = 147 * 1024;
+static_assert(2 * kSmallCoarseN * kSmallCoarseN * sizeof(double) <= kCoarseLdsMax, "two copies of S fit");
 
 void launch_coarse_factor(int dim, const LevelDesc<double> *d, const CoarseArgs *args, int nblocks, int n_max,
                           const Exec &x)
 {
     if (nblocks <= 0) return;
+    if (n_max <= kSmallCoarseN) {
+        const size_t two = (size_t)2 * n_max * n_max * sizeof(double);
+        LSMG_DISPATCH_DIM(dim, {
+            static bool attr_set = false;
+            if (two > 64 * 1024 && !attr_set) {
+                (void)hipFuncSetAttribute((const void *)k_coarse_invert_small<DIM, NST>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLdsMax);
+                attr_set = true;
+            }
+            k_coarse_invert_small<DIM, NST><<<nblocks, 1024, two, x.s>>>(d, args, x.act);
+        });
+        return;
+    }
     const size_t bytes = (size_t)n_max * n_max * sizeof(double);
     const int use_lds = bytes <= kCoarseLdsMax;
     LSMG_DISPATCH_DIM(dim, {

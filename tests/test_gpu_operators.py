@@ -4,6 +4,7 @@ coarse linearisation point, the coarsest solve and a whole V-cycle, on every lev
 import numpy as np
 import pytest
 
+import lsmg_inputs as I
 from _gpu import cuda, host, pair, random_state, rel, say
 
 CASES = [("disk", 65, 5), ("star", 257, 9), ("torus", 33, 9)]
@@ -84,3 +85,26 @@ def test_vcycle(kind, n, coarsest):
         # the defect of a nearly converged iterate is a difference of terms of the size of
         # rhs: its rounding is a few ulps of |rhs|, whatever the size of the defect itself
         assert abs(rg - ro) <= 1e-8 * ro + 1e-12 * np.max(np.abs(rhs)), q
+
+
+# coarsest operators on either side of the sizes where the factorisation changes
+# kernel: up to 96 unknowns two LDS copies with one barrier per pivot, up to 138 one
+# LDS copy, beyond that the matrix in HBM (radius: a disc of that radius instead)
+COARSE_CASES = [("star", 129, 17, None, 88), ("disk", 129, 33, 0.28, 97), ("disk", 129, 33, None, 165),
+                ("torus", 33, 17, None, 480)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind,n,coarsest,radius,na", COARSE_CASES)
+def test_coarse_solve_sizes(kind, n, coarsest, radius, na):
+    say(f"coarse solve {kind} n={n} coarsest={coarsest} na={na}")
+    H, O = pair(kind, n, coarsest, phi=I.disk(n, r=radius) if radius else None)
+    lc = O.nlev - 1
+    assert O.level_info(lc)["na"] == na
+    rng = np.random.default_rng(3)
+    W = random_state(O, 0, rng)
+    H.set_linearization(cuda(W), 1e-3)
+    O.set_linearization(W, 1e-3)
+    for _ in range(2):
+        rhs = rng.standard_normal(2 * na)
+        assert rel(host(H.coarse_solve(cuda(rhs))), O.coarse_solve(rhs)) <= 1e-11
