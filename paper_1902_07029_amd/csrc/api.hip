@@ -239,7 +239,7 @@ void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s, int count)
                     launch_smooth_rb<T>(d, Lv.tiles, Lv.ntile, Lv.w_gh(), Lv.nghc, flip,
                                         prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
                     launch_ghost_apply<T>(H->dim, d, Lv.w_gh4(), Lv.nghc4, 1 - flip,
-                                          prof_exec(H, s, LSMG_KERNEL_GHOST, l));
+                                          with_tail(prof_exec(H, s, LSMG_KERNEL_GHOST, l), Lv.nghc4));
                 }
             }
         }
@@ -248,8 +248,9 @@ void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s, int count)
         for (; count > 0; --count) {
             launch_smooth_colour<T>(H->dim, d, Lv.w_seg(0), Lv.nseg[0], 0, prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
             launch_smooth_colour<T>(H->dim, d, Lv.w_seg(1), Lv.nseg[1] + Lv.nghc, 1,
-                                    prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
-            launch_ghost_apply<T>(H->dim, d, Lv.w_gh4(), Lv.nghc4, 0, prof_exec(H, s, LSMG_KERNEL_GHOST, l));
+                                    with_tail(prof_exec(H, s, LSMG_KERNEL_SMOOTH, l), Lv.nghc));
+            launch_ghost_apply<T>(H->dim, d, Lv.w_gh4(), Lv.nghc4, 0,
+                                  with_tail(prof_exec(H, s, LSMG_KERNEL_GHOST, l), Lv.nghc4));
         }
         return;
     }
@@ -258,7 +259,7 @@ void smooth_level(lsmg_hierarchy *H, int l, hipStream_t s, int count)
             launch_smooth_colour<T>(H->dim, d, Lv.w_seg(colour), Lv.nseg[colour], colour,
                                     prof_exec(H, s, LSMG_KERNEL_SMOOTH, l));
         const Exec xb = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
-        const Exec xa = prof_exec(H, s, LSMG_KERNEL_GHOST, l);
+        const Exec xa = with_tail(prof_exec(H, s, LSMG_KERNEL_GHOST, l), Lv.nghc4);
         launch_ghost<T>(H->dim, d, l, Lv.w_gh(), Lv.nghc, Lv.w_gh4(), Lv.nghc4, Lv.ng, Lv.sweeps,
                         Lv.go_ptr != nullptr, xb, xa);
     }
@@ -320,15 +321,15 @@ void vcycle_rec(lsmg_hierarchy *H, int l, hipStream_t s)
         return;
     }
     smooth_level<T>(H, l, s, H->p.nu1);
-    launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), -1, prof_exec(H, s, LSMG_KERNEL_DEFECT, l));
+    launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), -1, with_tail(prof_exec(H, s, LSMG_KERNEL_DEFECT, l), Lv.nghc));
     launch_band<T>(d, Lv.w_band(), Lv.nbandc, Exec(s));
     const Level &C = H->L[l + 1];
-    launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), prof_exec(H, s, LSMG_KERNEL_RESTRICT, l + 1));
+    launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), with_tail(prof_exec(H, s, LSMG_KERNEL_RESTRICT, l + 1), C.nghc));
     // W-cycle: a second cycle on the next level from the first one's result; the
     // coarsest solve is exact, so it is not repeated
     const int reps = l + 1 == H->nlev - 1 ? 1 : H->p.cycle_gamma;
     for (int i = 0; i < reps; ++i) vcycle_rec<T>(H, l + 1, s);
-    launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), prof_exec(H, s, LSMG_KERNEL_PROLONG, l));
+    launch_prolong<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), with_tail(prof_exec(H, s, LSMG_KERNEL_PROLONG, l), Lv.nghc));
     smooth_level<T>(H, l, s, H->p.nu2);
 }
 
@@ -344,13 +345,13 @@ void fmg_enqueue(lsmg_hierarchy *H, hipStream_t s)
     const int L = H->nlev;
     for (int l = 0; l + 1 < L; ++l) {
         const Level &Lv = H->L[l], &C = H->L[l + 1];
-        launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), -1, Exec(s));
+        launch_defect<T>(H->dim, d, Lv.w_act(), Lv.nw_act(), -1, with_tail(Exec(s), Lv.nghc));
         launch_band<T>(d, Lv.w_band(), Lv.nbandc, Exec(s));
-        launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), Exec(s));
+        launch_restrict<T>(H->dim, d, C.w_act(), C.nw_act(), with_tail(Exec(s), C.nghc));
     }
     vcycle_rec<T>(H, L - 1, s);
     for (int l = L - 2; l >= 0; --l) {
-        launch_prolong<T>(H->dim, d, H->L[l].w_act(), H->L[l].nw_act(), Exec(s));
+        launch_prolong<T>(H->dim, d, H->L[l].w_act(), H->L[l].nw_act(), with_tail(Exec(s), H->L[l].nghc));
         vcycle_rec<T>(H, l, s);
     }
 }
@@ -367,12 +368,12 @@ void cycle_enqueue(lsmg_hierarchy *H, bool mixed, hipStream_t s, bool fmg = fals
         if (fmg) fmg_enqueue<double>(H, s);
         else vcycle_rec<double>(H, 0, s);
     } else {
-        launch_to_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), 1, s);
+        launch_to_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), 1, with_tail(Exec(s), L0.nghc));
         if (fmg) fmg_enqueue<float>(H, s);
         else vcycle_rec<float>(H, 0, s);
-        launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), s);
+        launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), with_tail(Exec(s), L0.nghc));
     }
-    launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), 1, s);
+    launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), 1, with_tail(Exec(s), L0.nghc));
 }
 
 void invalidate_graphs(lsmg_hierarchy *H)
@@ -425,12 +426,12 @@ lsmg_status linearize(lsmg_hierarchy *H, bool factor = true)
 {
     for (int l = 1; l < H->nlev; ++l) {
         const Level &C = H->L[l];
-        launch_inject<double>(H->dim, H->d64, C.w_act(), C.nw_act(), H->stream);
+        launch_inject<double>(H->dim, H->d64, C.w_act(), C.nw_act(), with_tail(Exec(H->stream), C.nghc));
     }
     if (H->have32)
         for (int l = 0; l < H->nlev; ++l) {
             const Level &Lv = H->L[l];
-            launch_to_f32(H->dim, H->d64, H->d32, Lv.w_act(), Lv.nw_act(), 0, H->stream);
+            launch_to_f32(H->dim, H->d64, H->d32, Lv.w_act(), Lv.nw_act(), 0, with_tail(Exec(H->stream), Lv.nghc));
         }
     if (factor) launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, H->stream);
     H->lin_set = true;
@@ -1043,7 +1044,7 @@ void gather(lsmg_hierarchy *H, int l, const T *a, const T *b, double *v)
 void zero_active_x(lsmg_hierarchy *H, int l)
 {
     const Level &Lv = H->L[l];
-    launch_zero_x<double>(H->dim, H->d64, Lv.w_act(), Lv.nw_act(), H->stream);
+    launch_zero_x<double>(H->dim, H->d64, Lv.w_act(), Lv.nw_act(), with_tail(Exec(H->stream), Lv.nghc));
 }
 
 // linear solve J dW = F on level 0 (rhs already in rhs_s / rhs_c) by V-cycles from zero;
@@ -1057,7 +1058,7 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
     const bool mixed = H->p.precision == 1;
     if (mixed) {
         // r = F - J 0 in FP64
-        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), -1, H->stream);
+        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), -1, with_tail(Exec(H->stream), L0.nghc));
     }
     hipGraphExec_t ge = nullptr, gf = nullptr;
     // events recorded inside a graph cannot be timed: while launch timing is on,
@@ -1431,9 +1432,9 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
     const Level &L0 = h->L[0];
     hipStream_t s = h->stream;
     // explicit half, and the first iterate W^{(n+1,0)} = W^n
-    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), s);
+    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), with_tail(Exec(s), L0.nghc));
     zero_norms(h, 0, 4);
-    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, s);
+    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, with_tail(Exec(s), L0.nghc));
     LSMGCHK(read_norms(h, 1));
     double nF = norm_value(h, 0);
     lsmg_status rc = LSMG_ENOCONV;
@@ -1449,8 +1450,8 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
         LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho,
                              h->p.fmg == 2 || (h->p.fmg == 1 && it == 1), true));
         zero_norms(h, 0, 4);
-        launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), s);
-        launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, s);
+        launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), with_tail(Exec(s), L0.nghc));
+        launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, with_tail(Exec(s), L0.nghc));
         LSMGCHK(read_norms(h, 4));
         nF = norm_value(h, 0);
         const double nD = norm_value(h, 2), nW = norm_value(h, 3);
@@ -1474,7 +1475,7 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
         stats->dw_rel = dwrel;
     }
     if (rc == LSMG_OK) {
-        launch_commit(h->dim, h->d64, L0.w_act(), L0.nw_act(), s);
+        launch_commit(h->dim, h->d64, L0.w_act(), L0.nw_act(), with_tail(Exec(s), L0.nghc));
         HIPCHK(hipStreamSynchronize(s));
     }
     h->lin_set = false;
@@ -1490,10 +1491,10 @@ lsmg_status lsmg_residual(lsmg_hierarchy *h, const double *d_W, const double *d_
     scatter<double>(h, 0, d_Wn, h->tmp_s, h->tmp_c);
     LSMGCHK(set_step(h, h->tmp_s, h->tmp_c, d_sb, sb_const, d_fn, d_fnp1));
     // the explicit half also sets the iterate to W^n; W replaces it afterwards
-    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), h->stream);
+    launch_explicit_half(h->dim, h->d64, L0.w_act(), L0.nw_act(), with_tail(Exec(h->stream), L0.nghc));
     scatter<double>(h, 0, d_W, L0.s, L0.c);
     zero_norms(h, 0, 1);
-    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, h->stream);
+    launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, with_tail(Exec(h->stream), L0.nghc));
     gather<double>(h, 0, L0.rhs_s, L0.rhs_c, d_F);
     h->lin_set = false;
     if (res_inf) {

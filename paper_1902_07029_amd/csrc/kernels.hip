@@ -369,8 +369,9 @@ __device__ __forceinline__ void prolong_node(const LevelDesc<T> *F, long long id
         wq[corner] = wk;
         use[corner] = !skip;
     }
-    // the corrections are read with the node type (one round trip); an inactive
-    // corner adds +0, which leaves the sums unchanged (they are never -0)
+    // the corrections are read with the node type and the fine node's own
+    // correction (one round trip); an inactive corner adds +0, which leaves the
+    // sums unchanged (they are never -0)
     bool on[NC];
     T xs[NC], xc[NC];
 #pragma unroll
@@ -379,6 +380,7 @@ __device__ __forceinline__ void prolong_node(const LevelDesc<T> *F, long long id
         xs[corner] = C->x_s[cq[corner]];
         xc[corner] = C->x_c[cq[corner]];
     }
+    const T fxs = F->x_s[idx], fxc = F->x_c[idx];
     T ws = 0, es = 0, ec = 0;
 #pragma unroll
     for (int corner = 0; corner < NC; ++corner) {
@@ -391,8 +393,8 @@ __device__ __forceinline__ void prolong_node(const LevelDesc<T> *F, long long id
         ec = use[corner] ? ec1 : ec;
     }
     if (ws > T(0)) {
-        F->x_s[idx] += es / ws;
-        F->x_c[idx] += ec / ws;
+        F->x_s[idx] = fxs + es / ws;
+        F->x_c[idx] = fxc + ec / ws;
     }
 }
 
@@ -476,21 +478,27 @@ __device__ __forceinline__ void inject_elem(const LevelDesc<T> *C, int4 w, int l
 // The logical block number gives XCD x a contiguous range of work items, so the
 // rows above and below an item (its y and z neighbours) are mostly processed by
 // the same XCD and found in its L2.
-__device__ __forceinline__ int logical_block()
+__device__ __forceinline__ int logical_block(int tb = 0)
 {
     const int nb = gridDim.x, b = blockIdx.x;
     const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
-    return x * q + (x < r ? x : r) + i;
+    // the last tb logical blocks are dealt to the XCDs in turn and run first on
+    // each; the others form one contiguous chunk per XCD
+    const int tq = tb >> 3, tr = tb & 7, tx = tq + (x < tr ? 1 : 0);
+    const int lead = x * q + (x < r ? x : r) - (x * tq + (x < tr ? x : tr)) + (i - tx);
+    return i < tx ? nb - tb + b : lead;   // a select: no branch ahead of the item's loads
 }
 
-// Every item kernel ends with `act`, per-descriptor flags (null: all active);
+// Every item kernel ends with `ntb`, the number of blocks that hold trailing
+// items only (logical_block deals them to the XCDs in turn; the launcher counts
+// them from Exec::tail), and `act`, per-descriptor flags (null: all active);
 // the items of a descriptor whose flag is 0 are skipped.  A wavefront returns
 // as a whole, so the wavefront reductions that follow never see part of one.
 // The item number is made wavefront-uniform explicitly (readfirstlane of the
 // wavefront index), so the item, its descriptor and the descriptor's pointers
 // are read with scalar loads and every data load of a lane can be issued at once.
 #define LSMG_ITEM_PROLOGUE                                                                   \
-    const int it = logical_block() * (int)(blockDim.x >> 6) +                               \
+    const int it = logical_block(ntb) * (int)(blockDim.x >> 6) +                            \
                    __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));                  \
     if (it >= nwork) return;                                                                \
     const int4 w = work[it];                                                                \
@@ -498,7 +506,7 @@ __device__ __forceinline__ int logical_block()
     const int lane = threadIdx.x & 63;
 
 #define LSMG_ITEMS const int4 *__restrict__ work, int nwork
-#define LSMG_ACT const int *__restrict__ act
+#define LSMG_ACT int ntb, const int *__restrict__ act
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kMaxBlock) void k_smooth_colour(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS,
@@ -1650,9 +1658,9 @@ __device__ __forceinline__ void wave_argmax(double &a, int &i, double &pay)
 // so all agree), and every thread computes its entries of the next copy from the
 // previous one: the pivot row scaled by the reciprocal pivot, every other row less
 // its factor times that row, with the interchange of the pivot row and row kc
-// folded into which source row is read.  Each entry gets the value of the in-place
-// elimination above, bit for bit.  The interchanges are composed into one column
-// permutation that is applied while the inverse is written out.
+// folded into which source row is read.  Each entry is computed by the same
+// operations as in the in-place elimination above.  The interchanges are composed
+// into one column permutation that is applied while the inverse is written out.
 constexpr int kSmallCoarseN = 96;
 constexpr int kSmallEpt = (kSmallCoarseN * kSmallCoarseN + 1023) / 1024;
 
@@ -1843,8 +1851,11 @@ static void item_launch(int nw, const Exec &x, Args... args)
 {
     const int ipb = x.ipb >= 1 && x.ipb <= kMaxItemsPerBlock ? x.ipb : kItemsPerBlock;
     const dim3 g(grid_of(nw, ipb)), b(kWave * ipb);
-    if (x.ev0) hipExtLaunchKernelGGL(KERN, g, b, 0, x.s, x.ev0, x.ev1, 0, args..., x.act);
-    else KERN<<<g, b, 0, x.s>>>(args..., x.act);
+    // blocks that hold trailing items only (see logical_block)
+    const int tail = x.tail < 0 ? 0 : (x.tail > nw ? nw : x.tail);
+    const int tb = (int)g.x - (int)grid_of(nw - tail, ipb);
+    if (x.ev0) hipExtLaunchKernelGGL(KERN, g, b, 0, x.s, x.ev0, x.ev1, 0, args..., tb, x.act);
+    else KERN<<<g, b, 0, x.s>>>(args..., tb, x.act);
 }
 
 #define LSMG_DISPATCH_DIM(dim, ...) \
@@ -1865,8 +1876,8 @@ void launch_smooth_rb(const LevelDesc<T> *d, const int4 *tiles, int ntile, const
 {
     if (ntile <= 0 && ngh <= 0) return;
     const dim3 g(ntile + (ngh + kRbWaves - 1) / kRbWaves), b(kRbThreads);
-    if (x.ev0) hipExtLaunchKernelGGL(k_smooth_rb<T>, g, b, 0, x.s, x.ev0, x.ev1, 0, d, tiles, ntile, gh, ngh, flip, x.act);
-    else k_smooth_rb<T><<<g, b, 0, x.s>>>(d, tiles, ntile, gh, ngh, flip, x.act);
+    if (x.ev0) hipExtLaunchKernelGGL(k_smooth_rb<T>, g, b, 0, x.s, x.ev0, x.ev1, 0, d, tiles, ntile, gh, ngh, flip, 0, x.act);
+    else k_smooth_rb<T><<<g, b, 0, x.s>>>(d, tiles, ntile, gh, ngh, flip, 0, x.act);
 }
 
 // the ghost relaxation of one smoothing step: the composed map (two launches,
@@ -1965,9 +1976,9 @@ void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nbloc
     const size_t shm = (size_t)4 * ncoarse_max * sizeof(double) + 2 * kTailMaxNodes * sizeof(T) +
                        (stage ? kTailStageInts * sizeof(int) : 0);
     if (stage)
-        LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST, true><<<nblocks, 1024, shm, x.s>>>(d, args, ncoarse_max, x.act));
+        LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST, true><<<nblocks, 1024, shm, x.s>>>(d, args, ncoarse_max, 0, x.act));
     else
-        LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST, false><<<nblocks, 1024, shm, x.s>>>(d, args, ncoarse_max, x.act));
+        LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST, false><<<nblocks, 1024, shm, x.s>>>(d, args, ncoarse_max, 0, x.act));
 }
 
 void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x)
@@ -2077,7 +2088,7 @@ void launch_coarse_factor(int dim, const LevelDesc<double> *d, const CoarseArgs 
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLdsMax);
                 attr_set = true;
             }
-            k_coarse_invert_small<DIM, NST><<<nblocks, 1024, two, x.s>>>(d, args, x.act);
+            k_coarse_invert_small<DIM, NST><<<nblocks, 1024, two, x.s>>>(d, args, 0, x.act);
         });
         return;
     }
@@ -2090,7 +2101,7 @@ void launch_coarse_factor(int dim, const LevelDesc<double> *d, const CoarseArgs 
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLdsMax);
             attr_set = true;
         }
-        k_coarse_invert<DIM, NST><<<nblocks, 1024, use_lds ? bytes : 0, x.s>>>(d, args, use_lds, x.act);
+        k_coarse_invert<DIM, NST><<<nblocks, 1024, use_lds ? bytes : 0, x.s>>>(d, args, use_lds, 0, x.act);
     });
 }
 

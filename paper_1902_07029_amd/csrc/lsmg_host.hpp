@@ -97,10 +97,20 @@ struct Exec {
     hipStream_t s = nullptr;
     const int *act = nullptr;
     int ipb = kItemsPerBlock;
+    // trailing items of the list (a level's ghost chunks) that are dealt to the
+    // XCDs in turn and started first; the leading items go to the XCDs in
+    // contiguous chunks
+    int tail = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     Exec(hipStream_t s_ = nullptr) : s(s_) {}
     Exec(hipStream_t s_, const int *a, int ipb_ = kItemsPerBlock) : s(s_), act(a), ipb(ipb_) {}
 };
+
+inline Exec with_tail(Exec x, int tail)
+{
+    x.tail = tail;
+    return x;
+}
 
 // ---- V-cycle and Newton kernels (kernels.hip) ----
 template <typename T> void launch_smooth_colour(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int colour, const Exec &x);
