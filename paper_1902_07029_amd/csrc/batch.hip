@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <vector>
 
@@ -37,13 +38,14 @@ enum { kFCycle = 0, kFStart = 1, kFLin = 2, kFUpdate = 3, kFCommit = 4, kFlagRow
 
 struct BList {
     int off = 0, n = 0;   // range in the batch's item pool
+    int tail = 0;         // trailing ghost items, dealt to the XCDs in turn (Exec::tail)
 };
 
 struct BSize {
     int n = 0;                       // nodes per axis
     BList seg[2], gh, act, band;     // member levels of this size outside the coarse tails
     BList gh4;                       // their ghosts in items of 4 (the composed map)
-    BList seg1g;                     // 2-D: colour-1 segments, each member's followed by its ghost items
+    BList seg1g;                     // colour-1 segments of the members, then all their ghost items
     BList tiles;                     // 2-D: tiles of the fused sweep
     long long na = 0;                // active nodes of the member levels outside the coarse tails
     BList rcoarse;                   // their next coarser levels (restriction targets)
@@ -286,7 +288,7 @@ void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s, int count)
                     launch_smooth_rb<T>(d, items(B, S.tiles), S.tiles.n, items(B, S.gh), S.gh.n, flip,
                                         bexec_t(B, s, 0, LSMG_KERNEL_SMOOTH, S.n));
                     launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 1 - flip,
-                                          bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n));
+                                          with_tail(bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n), S.gh4.tail));
                 }
             }
         }
@@ -295,9 +297,9 @@ void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s, int count)
             launch_smooth_colour<T>(B->dim, d, items(B, S.seg[0]), S.seg[0].n, 0,
                                     bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
             launch_smooth_colour<T>(B->dim, d, items(B, S.seg1g), S.seg1g.n, 1,
-                                    bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
+                                    with_tail(bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n), S.seg1g.tail));
             launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 0,
-                                  bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n));
+                                  with_tail(bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n), S.gh4.tail));
         }
         return;
     }
@@ -306,7 +308,7 @@ void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s, int count)
             launch_smooth_colour<T>(B->dim, d, items(B, S.seg[colour]), S.seg[colour].n, colour,
                                     bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
         const Exec xb = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
-        const Exec xa = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
+        const Exec xa = with_tail(bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n), S.gh4.tail);
         launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, items(B, S.gh4), S.gh4.n, 0, B->p.ghost_sweeps, true,
                         xb, xa);
     }
@@ -322,10 +324,10 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
         if (S.act.n == 0) continue;
         b_smooth<T>(B, S, s, B->p.nu1);
         launch_defect<T>(B->dim, d, items(B, S.act), S.act.n, -1,
-                         bexec_t(B, s, S.ipb[kTDefect], LSMG_KERNEL_DEFECT, S.n));
+                         with_tail(bexec_t(B, s, S.ipb[kTDefect], LSMG_KERNEL_DEFECT, S.n), S.act.tail));
         launch_band<T>(d, items(B, S.band), S.band.n, bexec(B, s, S.ipb[kTBand]));
         launch_restrict<T>(B->dim, d, items(B, S.rcoarse), S.rcoarse.n,
-                           bexec_t(B, s, S.ipb[kTRestrict], LSMG_KERNEL_RESTRICT, S.n));
+                           with_tail(bexec_t(B, s, S.ipb[kTRestrict], LSMG_KERNEL_RESTRICT, S.n), S.rcoarse.tail));
     }
     const bool f64 = sizeof(T) == 8;
     if (f64 ? B->any_lds64 : B->any_lds32)
@@ -336,7 +338,7 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
         const BSize &S = B->sizes[z];
         if (S.act.n == 0) continue;
         launch_prolong<T>(B->dim, d, items(B, S.act), S.act.n,
-                          bexec_t(B, s, S.ipb[kTProlong], LSMG_KERNEL_PROLONG, S.n));
+                          with_tail(bexec_t(B, s, S.ipb[kTProlong], LSMG_KERNEL_PROLONG, S.n), S.act.tail));
         b_smooth<T>(B, S, s, B->p.nu2);
     }
 }
@@ -351,11 +353,11 @@ void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s)
     if (!mixed) {
         b_vcycle<double>(B, s);
     } else {
-        launch_to_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, 1, x0);
+        launch_to_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, 1, with_tail(x0, B->lev0.tail));
         b_vcycle<float>(B, s);
-        launch_add_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, x0);
+        launch_add_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
     }
-    launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 1, x0);
+    launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 1, with_tail(x0, B->lev0.tail));
     launch_norm_reduce(B->d_norms, B->norm_stride, B->ndom, 1, 1, B->d_nred, s);
 }
 
@@ -412,20 +414,20 @@ void tune_launch(lsmg_batch *B, const BSize &S, int cls, const Exec &x)
         break;
     case kTGhost:
         if (B->dim == 2) {
-            launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 0, x);
+            launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 0, with_tail(x, S.gh4.tail));
             break;
         }
         launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, items(B, S.gh4), S.gh4.n, 0, B->p.ghost_sweeps, true, x,
-                        Exec(x.s, x.act, x.ipb));
+                        with_tail(Exec(x.s, x.act, x.ipb), S.gh4.tail));
         break;
     case kTDefect:
-        launch_defect<T>(B->dim, d, items(B, S.act), S.act.n, -1, x);
+        launch_defect<T>(B->dim, d, items(B, S.act), S.act.n, -1, with_tail(x, S.act.tail));
         break;
     case kTRestrict:
-        launch_restrict<T>(B->dim, d, items(B, S.rcoarse), S.rcoarse.n, x);
+        launch_restrict<T>(B->dim, d, items(B, S.rcoarse), S.rcoarse.n, with_tail(x, S.rcoarse.tail));
         break;
     case kTProlong:
-        launch_prolong<T>(B->dim, d, items(B, S.act), S.act.n, x);
+        launch_prolong<T>(B->dim, d, items(B, S.act), S.act.n, with_tail(x, S.act.tail));
         break;
     default:
         launch_band<T>(d, items(B, S.band), S.band.n, x);
@@ -499,6 +501,7 @@ lsmg_status build_lists(lsmg_batch *B)
     auto add = [&](BList &L, const std::vector<Job> &js) {
         L.off = total;
         L.n = 0;
+        L.tail = 0;
         for (const Job &j : js) {
             if (j.cnt <= 0) continue;
             jobs.push_back(j);
@@ -506,10 +509,30 @@ lsmg_status build_lists(lsmg_batch *B)
             total += j.cnt;
         }
     };
+    // leading job lists, then trailing ones (ghost items) counted in L.tail
+    auto add_tail = [&](BList &L, std::initializer_list<const std::vector<Job> *> lead, const std::vector<Job> &trail) {
+        L.off = total;
+        L.n = 0;
+        for (const std::vector<Job> *js : lead)
+            for (const Job &j : *js) {
+                if (j.cnt <= 0) continue;
+                jobs.push_back(j);
+                L.n += j.cnt;
+                total += j.cnt;
+            }
+        L.tail = 0;
+        for (const Job &j : trail) {
+            if (j.cnt <= 0) continue;
+            jobs.push_back(j);
+            L.n += j.cnt;
+            L.tail += j.cnt;
+            total += j.cnt;
+        }
+    };
     const int nk = B->ndom;
     for (size_t z = 0; z < ns.size(); ++z) {
         BSize &S = B->sizes[z];
-        std::vector<Job> seg0, seg1, seg1g, gh, gh4, act, band, rco, ico, til;
+        std::vector<Job> seg0, seg1, gh, gh4, band, til, rco, rco_gh, ico, ico_gh;
         for (int k = 0; k < nk; ++k) {
             const lsmg_hierarchy *H = B->mem[k];
             for (int l = 0; l < H->nlev; ++l) {
@@ -518,41 +541,48 @@ lsmg_status build_lists(lsmg_batch *B)
                 const int ds = B->d0[k];
                 if (l + 1 < H->nlev) {
                     const Level &C = H->L[l + 1];
-                    ico.push_back({C.w_act(), C.nw_act(), ds});
+                    ico.push_back({C.w_seg(0), C.nseg[0] + C.nseg[1], ds});
+                    ico_gh.push_back({C.w_gh(), C.nghc, ds});
                 }
                 if (l >= H->tail_l0) continue;
                 seg0.push_back({Lv.w_seg(0), Lv.nseg[0], ds});
                 seg1.push_back({Lv.w_seg(1), Lv.nseg[1], ds});
-                seg1g.push_back({Lv.w_seg(1), Lv.nseg[1] + Lv.nghc, ds});
                 if (Lv.tiles) til.push_back({Lv.tiles, Lv.ntile, ds});
                 S.na += Lv.na;
                 gh.push_back({Lv.w_gh(), Lv.nghc, ds});
                 gh4.push_back({Lv.w_gh4(), Lv.nghc4, ds});
-                act.push_back({Lv.w_act(), Lv.nw_act(), ds});
                 band.push_back({Lv.w_band(), Lv.nbandc, ds});
                 const Level &C = H->L[l + 1];
-                rco.push_back({C.w_act(), C.nw_act(), ds});
+                rco.push_back({C.w_seg(0), C.nseg[0] + C.nseg[1], ds});
+                rco_gh.push_back({C.w_gh(), C.nghc, ds});
             }
         }
         add(S.seg[0], seg0);
         add(S.seg[1], seg1);
-        add(S.seg1g, seg1g);
+        // the members' row segments first, then all their ghost items
+        add_tail(S.seg1g, {&seg1}, gh);
         add(S.tiles, til);
         add(S.gh, gh);
-        add(S.gh4, gh4);
-        add(S.act, act);
+        add_tail(S.gh4, {}, gh4);
+        add_tail(S.act, {&seg0, &seg1}, gh);
         add(S.band, band);
-        add(S.rcoarse, rco);
-        add(S.icoarse, ico);
+        add_tail(S.rcoarse, {&rco}, rco_gh);
+        add_tail(S.icoarse, {&ico}, ico_gh);
     }
-    std::vector<Job> l0, al;
+    std::vector<Job> l0, l0_gh, al, al_gh;
     for (int k = 0; k < nk; ++k) {
         const lsmg_hierarchy *H = B->mem[k];
-        l0.push_back({H->L[0].w_act(), H->L[0].nw_act(), B->d0[k]});
-        for (int l = 0; l < H->nlev; ++l) al.push_back({H->L[l].w_act(), H->L[l].nw_act(), B->d0[k]});
+        const Level &L0 = H->L[0];
+        l0.push_back({L0.w_seg(0), L0.nseg[0] + L0.nseg[1], B->d0[k]});
+        l0_gh.push_back({L0.w_gh(), L0.nghc, B->d0[k]});
+        for (int l = 0; l < H->nlev; ++l) {
+            const Level &Lv = H->L[l];
+            al.push_back({Lv.w_seg(0), Lv.nseg[0] + Lv.nseg[1], B->d0[k]});
+            al_gh.push_back({Lv.w_gh(), Lv.nghc, B->d0[k]});
+        }
     }
-    add(B->lev0, l0);
-    add(B->all, al);
+    add_tail(B->lev0, {&l0}, l0_gh);
+    add_tail(B->all, {&al}, al_gh);
     B->npool = total;
     LSMGCHK(B->alloc(&B->pool, total));
     // one launch copies every block; the job table is freed after the copy
@@ -769,9 +799,9 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
     std::vector<double> nF(nk, 0.0), rho_last(nk, 0.0), logsum(nk, 0.0), dwrel(nk, 0.0), rprev(nk, 0.0);
     LSMGCHK(set_flags(B, on));
     // explicit half, first iterate and F(W^n)
-    launch_explicit_half(B->dim, B->d64, items(B, B->lev0), B->lev0.n, x0);
+    launch_explicit_half(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
     zero_bnorms(B, 0, 4, s);
-    launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, x0);
+    launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, with_tail(x0, B->lev0.tail));
     LSMGCHK(read_bnorms(B, 0, 1));
     for (int k = 0; k < nk; ++k) nF[k] = bnorm(B, k, 0);
     for (int it = 1; it <= B->p.newton_max; ++it) {
@@ -789,8 +819,9 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
         if (nact == 0) break;
         LSMGCHK(set_flags(B, on));
         // linearisation: coarse (s, c) level by level, FP32 copies, coarsest inverses
-        for (const BSize &S : B->sizes) launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, x0);
-        if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, x0);
+        for (const BSize &S : B->sizes)
+            launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, with_tail(x0, S.icoarse.tail));
+        if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, with_tail(x0, B->all.tail));
         launch_coarse_factor(B->dim, B->d64, B->d_coarse, nk, B->coarse_n_max, x0);
         HIPCHK(hipMemcpyAsync(B->h_cstatus, B->d_cstatus, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -805,8 +836,8 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
             else LSMGCHK(b_autotune<double>(B, 3));
         }
         // linear solves J dW = F from dW = 0
-        launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, x0);
-        if (mixed) launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, x0);
+        launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
+        if (mixed) launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, with_tail(x0, B->lev0.tail));
         hipGraphExec_t ge = nullptr;
         // timed launches run direct: events inside a graph cannot be timed
         if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &ge));
@@ -841,8 +872,8 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
         // Newton update and the new residual
         LSMGCHK(set_flags(B, on));
         zero_bnorms(B, 0, 4, s);
-        launch_newton_update(B->dim, B->d64, items(B, B->lev0), B->lev0.n, x0);
-        launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, x0);
+        launch_newton_update(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
+        launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, with_tail(x0, B->lev0.tail));
         LSMGCHK(read_bnorms(B, 0, 4));
         for (int k = 0; k < nk; ++k) {
             if (!on[k]) continue;
@@ -866,7 +897,7 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
         if (!ok[k] && first_bad == LSMG_OK) first_bad = rc[k];
     }
     LSMGCHK(set_flags(B, ok));
-    launch_commit(B->dim, B->d64, items(B, B->lev0), B->lev0.n, x0);
+    launch_commit(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
     HIPCHK(hipStreamSynchronize(s));
     for (int k = 0; k < nk; ++k) {
         if (status) status[k] = rc[k];
@@ -970,12 +1001,13 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
             has_u |= fu[k];
         }
         if (has_s) {
-            launch_explicit_half(B->dim, B->d64, items(B, B->lev0), B->lev0.n, xs);
-            launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, xs);
+            launch_explicit_half(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xs, B->lev0.tail));
+            launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, with_tail(xs, B->lev0.tail));
         }
         if (has_l) {
-            for (const BSize &S : B->sizes) launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, xl);
-            if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, xl);
+            for (const BSize &S : B->sizes)
+                launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, with_tail(xl, S.icoarse.tail));
+            if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, with_tail(xl, B->all.tail));
             launch_coarse_factor(B->dim, B->d64, B->d_coarse, nk, B->coarse_n_max, xl);
             if (B->autotune && !B->tuned) {
                 // workgroup sizes, timed on the members being linearised (flag row 0 set to
@@ -988,8 +1020,8 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
                 else LSMGCHK(b_autotune<double>(B, 3));
                 LSMGCHK(set_flag_rows(B, rows));
             }
-            launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, xl);
-            if (mixed) launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, xl);
+            launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xl, B->lev0.tail));
+            if (mixed) launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, with_tail(xl, B->lev0.tail));
         }
         if (has_c) {
             hipGraphExec_t ge = nullptr;
@@ -998,8 +1030,8 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
             else b_cycle_enqueue(B, mixed, s);
         }
         if (has_u) {
-            launch_newton_update(B->dim, B->d64, items(B, B->lev0), B->lev0.n, xu);
-            launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, xu);
+            launch_newton_update(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xu, B->lev0.tail));
+            launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, with_tail(xu, B->lev0.tail));
         }
         launch_norm_reduce(B->d_norms, B->norm_stride, nk, 0, 4, B->d_nred, s);
         HIPCHK(hipMemcpyAsync(B->h_nred, B->d_nred, sizeof(unsigned long long) * 4 * nk, hipMemcpyDeviceToHost, s));
@@ -1075,7 +1107,7 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
             std::vector<std::vector<char>> crow(kFlagRows, std::vector<char>(nk, 0));
             crow[kFCommit] = commit;
             LSMGCHK(set_flag_rows(B, crow));
-            launch_commit(B->dim, B->d64, items(B, B->lev0), B->lev0.n, xm);
+            launch_commit(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xm, B->lev0.tail));
             HIPCHK(hipStreamSynchronize(s));
         }
     }
