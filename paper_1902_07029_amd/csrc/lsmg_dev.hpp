@@ -187,11 +187,37 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 // number, which keeps the atomics on any one address few.
 constexpr int kNormSlots = 256;
 
+// one DPP step of a wavefront max: each lane takes the larger of its value and
+// the value of the lane the control names (lanes of rows the mask leaves out
+// compare with themselves)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long max_dpp_u64(unsigned long long v)
+{
+    const int lo = __builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(v >> 32), (int)(v >> 32), CTRL, ROWS, 0xf, false);
+    const unsigned long long o = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    return o > v ? o : v;
+}
+
+// the wavefront max by VALU data-parallel moves (no LDS traffic): pairs within
+// quads, half rows and rows, then the two row broadcasts; the result is in lane 63.
+// Called with every lane active.
+__device__ __forceinline__ unsigned long long wave_max_u64_last(unsigned long long v)
+{
+    v = max_dpp_u64<0xB1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    v = max_dpp_u64<0x4E, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+    v = max_dpp_u64<0x141, 0xf>(v);   // row_half_mirror
+    v = max_dpp_u64<0x140, 0xf>(v);   // row_mirror
+    v = max_dpp_u64<0x142, 0xa>(v);   // row_bcast:15
+    v = max_dpp_u64<0x143, 0xc>(v);   // row_bcast:31
+    return v;
+}
+
 __device__ __forceinline__ void norm_accumulate(unsigned long long *slot, unsigned long long bits)
 {
-    bits = wave_max_u64(bits);
+    bits = wave_max_u64_last(bits);
     const int wslot = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kNormSlots - 1);
-    if ((threadIdx.x & (kWave - 1)) == 0 && bits != 0ull) atomicMax(slot + wslot, bits);
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1 && bits != 0ull) atomicMax(slot + wslot, bits);
 }
 
 // norm k of the domain that owns descriptor D
