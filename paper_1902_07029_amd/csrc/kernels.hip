@@ -760,6 +760,37 @@ struct FoldChunk {
     }
 };
 
+// Sum over each row of 16 lanes by DPP row rotations (VALU moves, no LDS).
+// After a rotation by 8 a lane's value depends only on its lane number mod 8, so
+// the next rotation by 4 pairs it with lane l ^ 4, and so on: every lane adds
+// the same pairs, in the same order, as an xor butterfly over 8, 4, 2, 1, and the
+// row's first lane ends with its sum ((v0 + v8) + (v4 + v12)) + ...  Called with
+// every lane active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <typename T>
+__device__ __forceinline__ T row16_sum_lane0(T v)
+{
+    v += dpp_mov<0x128>(v);   // row_ror:8
+    v += dpp_mov<0x124>(v);   // row_ror:4
+    v += dpp_mov<0x122>(v);   // row_ror:2
+    v += dpp_mov<0x121>(v);   // row_ror:1
+    return v;
+}
+
 template <typename T, bool FOLD>
 __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply_grouped(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS,
                                                                    int alt, LSMG_ACT)
@@ -851,7 +882,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_ghost_apply_grouped(const LevelDe
                 }
             }
         }
-        for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+        v = row16_sum_lane0(v);
         if (on && sub == 0) {
             XS[g] = v;
             T cs_d, cc_d;
