@@ -96,6 +96,24 @@ def test_batch_autotune_changes_nothing():
 
 
 @pytest.mark.gpu
+def test_batch_autotune_changes_nothing_3d():
+    # 3-D members: every list ends with the members' ghost items, which are dealt to
+    # the XCDs in turn; other workgroup sizes put them in other blocks
+    members = [_hier(3, d, 1) for d in ELL3]
+    plain = [_hier(3, d, 1) for d in ELL3]
+    s1 = [_state(H, d, 3) for H, d in zip(members, ELL3)]
+    s2 = [_state(H, d, 3) for H, d in zip(plain, ELL3)]
+    B1 = lsmg.Batch(members, autotune=True)
+    B2 = lsmg.Batch(plain, autotune=False)
+    for _ in range(2):
+        B1.step(s1, 1e-4)
+        B2.step(s2, 1e-4)
+        for m in range(len(ELL3)):
+            assert torch.equal(s1[m].get(), s2[m].get())
+    say(f"tuned workgroup sizes (3-D): {B1.tuning()}")
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batch_vs_oracle(precision):
     domains = [STARS2[2], STARS2[0]]
