@@ -368,12 +368,14 @@ void cycle_enqueue(lsmg_hierarchy *H, bool mixed, hipStream_t s, bool fmg = fals
         if (fmg) fmg_enqueue<double>(H, s);
         else vcycle_rec<double>(H, 0, s);
     } else {
-        launch_to_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), 1, with_tail(Exec(s), L0.nghc));
+        // the FP32 right-hand side and zero correction were written by the FP64
+        // defect that precedes every cycle
         if (fmg) fmg_enqueue<float>(H, s);
         else vcycle_rec<float>(H, 0, s);
         launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), with_tail(Exec(s), L0.nghc));
     }
-    launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), 1, with_tail(Exec(s), L0.nghc));
+    launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), 1, with_tail(Exec(s), L0.nghc),
+                          mixed ? H->d32 : nullptr);
 }
 
 void invalidate_graphs(lsmg_hierarchy *H)
@@ -1058,7 +1060,7 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
     const bool mixed = H->p.precision == 1;
     if (mixed) {
         // r = F - J 0 in FP64
-        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), -1, with_tail(Exec(H->stream), L0.nghc));
+        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), -1, with_tail(Exec(H->stream), L0.nghc), H->d32);
     }
     hipGraphExec_t ge = nullptr, gf = nullptr;
     // events recorded inside a graph cannot be timed: while launch timing is on,

@@ -353,11 +353,13 @@ void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s)
     if (!mixed) {
         b_vcycle<double>(B, s);
     } else {
-        launch_to_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, 1, with_tail(x0, B->lev0.tail));
+        // the FP32 right-hand side and zero correction were written by the FP64
+        // defect that precedes every cycle
         b_vcycle<float>(B, s);
         launch_add_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
     }
-    launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 1, with_tail(x0, B->lev0.tail));
+    launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 1, with_tail(x0, B->lev0.tail),
+                          mixed ? B->d32 : nullptr);
     launch_norm_reduce(B->d_norms, B->norm_stride, B->ndom, 1, 1, B->d_nred, s);
 }
 
@@ -837,7 +839,8 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
         }
         // linear solves J dW = F from dW = 0
         launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
-        if (mixed) launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, with_tail(x0, B->lev0.tail));
+        if (mixed)
+            launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, with_tail(x0, B->lev0.tail), B->d32);
         hipGraphExec_t ge = nullptr;
         // timed launches run direct: events inside a graph cannot be timed
         if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &ge));
@@ -1021,7 +1024,9 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
                 LSMGCHK(set_flag_rows(B, rows));
             }
             launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xl, B->lev0.tail));
-            if (mixed) launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, with_tail(xl, B->lev0.tail));
+            if (mixed)
+                launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, with_tail(xl, B->lev0.tail),
+                                      B->d32);
         }
         if (has_c) {
             hipGraphExec_t ge = nullptr;

@@ -179,8 +179,19 @@ __device__ __forceinline__ void ghost_apply_elem(const LevelDesc<T> *D, int q)
 }
 
 // defect r = rhs - J x on one active row pair (section 3.5.2); returns |r| bits
+// (a mixed-precision cycle's FP32 right-hand side: E, when given, takes the
+// defect rounded to FP32 and a zero FP32 correction at the same node)
+__device__ __forceinline__ void defect_to_f32(const LevelDesc<float> *E, long long idx, double rs, double rc)
+{
+    E->rhs_s[idx] = (float)rs;
+    E->rhs_c[idx] = (float)rc;
+    E->x_s[idx] = 0.0f;
+    E->x_c[idx] = 0.0f;
+}
+
 template <typename T, int DIM>
-__device__ __forceinline__ unsigned long long defect_inside(const LevelDesc<T> *D, long long idx, int i, int j, int k)
+__device__ __forceinline__ unsigned long long defect_inside(const LevelDesc<T> *D, long long idx, int i, int j, int k,
+                                                            const LevelDesc<float> *E)
 {
     long long nb[2 * DIM];
     neighbours<DIM>(D->n, D->Wp, D->cs, (i + j + k) & 1, (long long)j + (long long)D->n * k, i, i >> 1, nb);
@@ -189,12 +200,13 @@ __device__ __forceinline__ unsigned long long defect_inside(const LevelDesc<T> *
     inside_defect_vals<T>(R, D->rhs_s[idx], D->rhs_c[idx], D->x_s[idx], D->x_c[idx], rs, rc);
     D->r_s[idx] = rs;
     D->r_c[idx] = rc;
+    if (E) defect_to_f32(E, idx, (double)rs, (double)rc);
     const unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
     return a > b ? a : b;
 }
 
 template <typename T, int NST>
-__device__ __forceinline__ unsigned long long defect_ghost(const LevelDesc<T> *D, int q)
+__device__ __forceinline__ unsigned long long defect_ghost(const LevelDesc<T> *D, int q, const LevelDesc<float> *E)
 {
     const int ng = D->ng;
     const long long idx = D->g_idx[q];
@@ -210,21 +222,23 @@ __device__ __forceinline__ unsigned long long defect_ghost(const LevelDesc<T> *D
     const T rc = D->rhs_c[idx] - (cs_d * D->x_s[idx] + cc_d * D->x_c[idx]);
     D->r_s[idx] = rs;
     D->r_c[idx] = rc;
+    if (E) defect_to_f32(E, idx, (double)rs, (double)rc);
     const unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
     return a > b ? a : b;
 }
 
 template <typename T, int DIM, int NST>
-__device__ __forceinline__ unsigned long long defect_elem(const LevelDesc<T> *D, int4 w, int lane)
+__device__ __forceinline__ unsigned long long defect_elem(const LevelDesc<T> *D, int4 w, int lane,
+                                                          const LevelDesc<float> *E)
 {
     if (item_kind(w) == 2) {
         const int q = w.z + lane;
-        return q < w.w ? defect_ghost<T, NST>(D, q) : 0ull;
+        return q < w.w ? defect_ghost<T, NST>(D, q, E) : 0ull;
     }
     long long idx;
     int i, j, k;
     if (!node_of<T, DIM>(D, w, lane, idx, i, j, k)) return 0ull;
-    return defect_inside<T, DIM>(D, idx, i, j, k);
+    return defect_inside<T, DIM>(D, idx, i, j, k, E);
 }
 
 // y = J x on one active row pair (into r)
@@ -914,11 +928,11 @@ __global__ __launch_bounds__(1024) void k_ghost_fused(const LevelDesc<T> *__rest
 // defect on the items' rows; norm_k >= 0 also accumulates |r|_inf into that norm
 template <typename T, int DIM, int NST>
 __global__ __launch_bounds__(kMaxBlock) void k_defect(const LevelDesc<T> *__restrict__ descs, LSMG_ITEMS, int norm_k,
-                                                      LSMG_ACT)
+                                                      const LevelDesc<float> *__restrict__ rhs32, LSMG_ACT)
 {
     LSMG_ITEM_PROLOGUE
     const LevelDesc<T> *D = descs + item_desc(w);
-    const unsigned long long bits = defect_elem<T, DIM, NST>(D, w, lane);
+    const unsigned long long bits = defect_elem<T, DIM, NST>(D, w, lane, rhs32 ? rhs32 + item_desc(w) : nullptr);
     if (norm_k >= 0) norm_accumulate(D, norm_k, bits);
 }
 
@@ -1191,9 +1205,9 @@ __global__ __launch_bounds__(1024) void k_tail(const LevelDesc<T> *__restrict__ 
                     long long idx;
                     int i, j, k;
                     tail_node<T, STAGE>(D, TL, S.si, t, idx, i, j, k);
-                    (void)defect_inside<T, DIM>(D, idx, i, j, k);
+                    (void)defect_inside<T, DIM>(D, idx, i, j, k, nullptr);
                 } else {
-                    (void)defect_ghost<T, NST>(D, t - nin);
+                    (void)defect_ghost<T, NST>(D, t - nin, nullptr);
                 }
             }
             __syncthreads();
@@ -1951,10 +1965,11 @@ void launch_ghost_apply(int dim, const LevelDesc<T> *d, const int4 *w4, int nw4,
 }
 
 template <typename T>
-void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x)
+void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x,
+                   const LevelDesc<float> *rhs32)
 {
     if (nw <= 0) return;
-    LSMG_DISPATCH_DIM(dim, item_launch<k_defect<T, DIM, NST>>(nw, x, d, w, nw, norm_k));
+    LSMG_DISPATCH_DIM(dim, item_launch<k_defect<T, DIM, NST>>(nw, x, d, w, nw, norm_k, rhs32));
 }
 
 template <typename T>
@@ -2146,7 +2161,8 @@ void launch_coarse_apply(const LevelDesc<T> *d, int lev, int N, const int *c2s, 
     template void launch_smooth_colour<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
     template void launch_ghost<T>(int, const LevelDesc<T> *, int, const int4 *, int, const int4 *, int, int, int, bool, \
                                   const Exec &, const Exec &); \
-    template void launch_defect<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
+    template void launch_defect<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &,              \
+                                   const LevelDesc<float> *);                                                   \
     template void launch_ghost_apply<T>(int, const LevelDesc<T> *, const int4 *, int, int, const Exec &); \
     template void launch_smooth_rb<T>(const LevelDesc<T> *, const int4 *, int, const int4 *, int, int, const Exec &); \
     template void launch_apply_J<T>(int, const LevelDesc<T> *, const int4 *, int, const Exec &); \

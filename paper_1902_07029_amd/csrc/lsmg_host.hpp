@@ -139,7 +139,10 @@ template <typename T> void launch_ghost_apply(int dim, const LevelDesc<T> *d, co
 // one copy, written to the other; flip selects which), with the ghost items after
 template <typename T> void launch_smooth_rb(const LevelDesc<T> *d, const int4 *tiles, int ntile, const int4 *gh,
                                            int ngh, int flip, const Exec &x);
-template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x);
+// rhs32: when given (the FP64 defect of a mixed-precision solve), the defect rounded
+// to FP32 also goes to the FP32 right-hand side, with a zero FP32 correction
+template <typename T> void launch_defect(int dim, const LevelDesc<T> *d, const int4 *w, int nw, int norm_k, const Exec &x,
+                                         const LevelDesc<float> *rhs32 = nullptr);
 template <typename T> void launch_apply_J(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_band(const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_restrict(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
