@@ -141,6 +141,50 @@ def mms_sources(x, y, t, a=MODEL["a"], d=MODEL["d"], m_s=MODEL["m_s"], m_c=MODEL
     return f1, f2
 
 
+def sphere(n, r=0.6, centre=(0.0, 0.0, 0.0)):
+    """Signed distance to a sphere: the 3-D domain of the manufactured-solution tests."""
+    x, y, z = grid_points(n, 3)
+    return np.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2) - r
+
+
+def s_exact3(x, y, z, t):
+    """The section 4.1 solution for s with a cos z factor: the 3-D manufactured solution."""
+    return 2.0 + np.sin(x) * np.cos(y) * np.cos(z) * np.sin(t + SQ2)
+
+
+def s_exact3_grad(x, y, z, t):
+    st = np.sin(t + SQ2)
+    return (np.cos(x) * np.cos(y) * np.cos(z) * st, -np.sin(x) * np.sin(y) * np.cos(z) * st,
+            -np.sin(x) * np.cos(y) * np.sin(z) * st)
+
+
+def c_exact3(x, y, z, t):
+    return 3.0 + np.sin(0.5 * x) * np.cos(3.0 * y) * np.cos(z) * np.sin(2.0 * t + SQ3)
+
+
+def mms_sources3(x, y, z, t, a=MODEL["a"], d=MODEL["d"], m_s=MODEL["m_s"], m_c=MODEL["m_c"],
+                 alpha=MODEL["alpha"], beta=MODEL["beta"]):
+    """f1, f2 of the forced model (as mms_sources) for s_exact3, c_exact3."""
+    st = np.sin(t + SQ2)
+    u = np.sin(x) * np.cos(y) * np.cos(z)
+    s = 2.0 + u * st
+    s_t = u * np.cos(t + SQ2)
+    s_x, s_y, s_z = s_exact3_grad(x, y, z, t)
+    lap_s = -3.0 * u * st
+    ct = np.sin(2.0 * t + SQ3)
+    v = np.sin(0.5 * x) * np.cos(3.0 * y) * np.cos(z)
+    c = 3.0 + v * ct
+    c_t = 2.0 * v * np.cos(2.0 * t + SQ3)
+    c_x = 0.5 * np.cos(0.5 * x) * np.cos(3.0 * y) * np.cos(z) * ct
+    c_y = -3.0 * np.sin(0.5 * x) * np.sin(3.0 * y) * np.cos(z) * ct
+    c_z = -np.sin(0.5 * x) * np.cos(3.0 * y) * np.sin(z) * ct
+    por = alpha * c + beta
+    f1 = (alpha * c_t * s + por * s_t + (a / m_c) * por * s * c
+          - d * (alpha * (c_x * s_x + c_y * s_y + c_z * s_z) + por * lap_s))
+    f2 = c_t + (a / m_s) * por * s * c
+    return f1, f2
+
+
 # ----------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------
