@@ -17,7 +17,10 @@
  *   caller (for example torch tensors' data_ptr()).  The library never frees
  *   them and never keeps them beyond the call.  Pointers marked "host" are
  *   ordinary CPU memory.
- * - The library owns every internal buffer of a hierarchy and of a state.
+ * - The library owns every internal buffer of a hierarchy, of its states and of
+ *   a batch.  Their device memory comes from the caller's allocator given at
+ *   creation (lsmg_allocator, for example a framework's caching allocator), or
+ *   from hipMalloc when none is given.
  * - All GPU work of a hierarchy is enqueued on the HIP stream given to
  *   lsmg_build_hierarchy (NULL = the null stream).  Entry points that return
  *   a scalar through a host pointer synchronise that stream before returning;
@@ -107,6 +110,19 @@ typedef struct {
     double dw_rel;      /* last |dW|_inf / |W|_inf */
 } lsmg_step_stats;
 
+/* Device memory for the library's internal buffers.  alloc returns `bytes`
+ * bytes of device global memory (aligned to at least 256 bytes) on the
+ * device that is current, or NULL on failure; free returns a pointer that
+ * alloc gave.  The library calls free only after the stream the buffer was
+ * used on has been synchronised, so a stream-ordered caching allocator may
+ * hand the block out again at once.  Both are called from the thread that
+ * calls the library, never concurrently for one hierarchy or batch. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} lsmg_allocator;
+
 /* Default parameters: the model data of eq. (dataeq), tau_s = 0.9 (section
  * 3.5.1), V(2,2), automatic ghost sweeps (0, 0, 0), 3 band layers, ghost_c_new = 1,
  * coarsest 5, FP64, newton_tol 1e-10, newton_max 20, lin_rtol 1e-3,
@@ -129,13 +145,17 @@ void lsmg_default_params(lsmg_params *p);
  * bilinear gradient -> one-sided differences along the inward axes, each taken
  * only where its nonzero weights sit on active nodes and the ghost's own
  * weight meets eq. CFLcondN.
+ * allocator: host, may be NULL (then hipMalloc / hipFree).  Copied: the
+ *   hierarchy, its states and their temporaries take every device buffer from
+ *   it until lsmg_destroy_hierarchy / lsmg_state_destroy hand them back.
  * stream: a hipStream_t (NULL for the null stream); every later call of this
  *   hierarchy runs on it.
  * Errors: LSMG_EINVAL (bad grid or parameters), LSMG_EGEOM (an inside node on
- *   the box edge, or a Neumann ghost with no admissible row), LSMG_EOOM,
- *   LSMG_EHIP.  *out is NULL on error. */
+ *   the box edge, or a Neumann ghost with no admissible row), LSMG_EOOM (also
+ *   when the allocator returns NULL), LSMG_EHIP.  *out is NULL on error. */
 lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid,
-                                 const lsmg_params *params, void *stream, lsmg_hierarchy **out);
+                                 const lsmg_params *params, const lsmg_allocator *allocator, void *stream,
+                                 lsmg_hierarchy **out);
 void lsmg_destroy_hierarchy(lsmg_hierarchy *h);
 
 /* Set the time step ahead of the first step: the level descriptors and the
@@ -286,7 +306,15 @@ lsmg_status lsmg_restrict(lsmg_hierarchy *h, int level, const double *d_r, doubl
  * (section 3.5.3). */
 lsmg_status lsmg_prolong_add(lsmg_hierarchy *h, int level, const double *d_e_coarse, double *d_x);
 
-/* Direct solve on the coarsest level (dense LU with partial pivoting, FP64). */
+/* Exact solve on the coarsest level (section 3.5; the coarsest grid is solved
+ * directly), FP64.  The operator's c-block is diagonal on that level, so the
+ * library eliminates it: S = J^ss - J^sc diag(J^cs / J^cc) (Na x Na, Na the
+ * active nodes) is inverted once per linearisation by Gauss-Jordan elimination
+ * with partial pivoting, and each call applies
+ *   x_s = S^-1 (r_s - J^sc (r_c / J^cc)),   x_c = (r_c - J^cs x_s) / J^cc.
+ * d_rhs, d_x: device, 2 Na doubles, [s-block | c-block] of the coarsest level.
+ * Needs a linearisation (lsmg_set_linearization or a running step);
+ * LSMG_ENONFINITE when S is singular or not finite. */
 lsmg_status lsmg_coarse_solve(lsmg_hierarchy *h, const double *d_rhs, double *d_x);
 
 /* One V(nu1, nu2) cycle on `level` with initial guess d_x (in/out);
@@ -344,10 +372,12 @@ typedef struct lsmg_batch lsmg_batch;
  * must outlive the batch; while a batch call runs, a member must not be used
  * on its own.  All batch work runs on `stream` (NULL = null stream); building
  * synchronises it.  The batch holds the members' concatenated level
- * descriptors and work lists, per-member norm slots and flags.
+ * descriptors and work lists, per-member norm slots and flags, in device
+ * memory from `allocator` (host, may be NULL: hipMalloc / hipFree).
  * Errors: EINVAL (NULL, duplicates, mismatched members), ENOTIMPL
  * (ghost_c_new = 0), EOOM, EHIP. */
-lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, void *stream, lsmg_batch **out);
+lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, const lsmg_allocator *allocator,
+                              void *stream, lsmg_batch **out);
 void lsmg_batch_destroy(lsmg_batch *b);
 
 /* One Crank-Nicolson step with time step dt for every member k: states[k]

@@ -474,7 +474,7 @@ lsmg_status build_level_arrays(lsmg_hierarchy *H, int l, const double *phi, uint
     if (ng > 0) compact_flags(fgh, nn, Lv.c2g + ni, scratch, nscratch, H->stream);
     launch_c2s(dim, Lv.c2g, Lv.na, Lv.n, Lv.Wp, Lv.cs, Lv.c2s, Lv.cmap, H->stream);
     LSMGCHK(H->alloc(&Lv.in_ijk, ni));
-    if (build_inside_lists(dim, Lv.c2g, ni, Lv.n, Lv.in_ijk, Lv.nin, scratch, nscratch, H->stream) != 0)
+    if (build_inside_lists(dim, Lv.c2g, ni, Lv.n, Lv.in_ijk, Lv.nin, scratch, nscratch, H->mem, H->stream) != 0)
         return fail(LSMG_EHIP, "inside-node lists failed on level %d", l);
     // ghost geometry
     const int nst = H->nst;
@@ -527,12 +527,13 @@ lsmg_status build_band(lsmg_hierarchy *H, int l, const double *phi, uint8_t *fla
     int64_t *band = nullptr;
     int *bandid = nullptr, *up_s = nullptr, *up_b = nullptr, *blayer = nullptr;
     double *up_w = nullptr;
-    HIPCHK(hipMalloc(&band, sizeof(int64_t) * nb));
-    HIPCHK(hipMalloc(&bandid, sizeof(int) * nn));
-    HIPCHK(hipMalloc(&up_s, sizeof(int) * nb * dim));
-    HIPCHK(hipMalloc(&up_b, sizeof(int) * nb * dim));
-    HIPCHK(hipMalloc(&up_w, sizeof(double) * nb * dim));
-    HIPCHK(hipMalloc(&blayer, sizeof(int) * nb));
+    DevTemps tmp(H->mem, H->stream);
+    LSMGCHK(tmp.get(&band, nb));
+    LSMGCHK(tmp.get(&bandid, nn));
+    LSMGCHK(tmp.get(&up_s, (long long)nb * dim));
+    LSMGCHK(tmp.get(&up_b, (long long)nb * dim));
+    LSMGCHK(tmp.get(&up_w, (long long)nb * dim));
+    LSMGCHK(tmp.get(&blayer, nb));
     compact_flags(flag, nn, band, scratch, nscratch, H->stream);
     launch_fill<int>(bandid, nn, -1, H->stream);
     launch_fill_bandid(band, nb, bandid, H->stream);
@@ -547,12 +548,6 @@ lsmg_status build_band(lsmg_hierarchy *H, int l, const double *phi, uint8_t *fla
         launch_band_layer(dim, layer, nb, F.bmax, up_s, up_b, up_w, blayer, F.b_cnt, F.b_src, F.b_wt, H->stream);
     launch_band_ext(nb, F.b_idx, blayer, F.ext, H->stream);
     HIPCHK(hipStreamSynchronize(H->stream));
-    (void)hipFree(band);
-    (void)hipFree(bandid);
-    (void)hipFree(up_s);
-    (void)hipFree(up_b);
-    (void)hipFree(up_w);
-    (void)hipFree(blayer);
     return LSMG_OK;
 }
 
@@ -592,7 +587,12 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
     Level &Lv = H->L[l];
     int4 *seg[2] = {nullptr, nullptr};
     int cnt[2] = {0, 0};
-    build_segments(H->dim, Lv.type, Lv.n, Lv.Wp, Lv.rows, Lv.cs, l, seg, cnt, H->stream);
+    build_segments(H->dim, Lv.type, Lv.n, Lv.Wp, Lv.rows, Lv.cs, l, seg, cnt, H->mem, H->stream);
+    struct SegFree {
+        const DevMem &m;
+        int4 *p;
+        ~SegFree() { m.put(p); }
+    } seg_free{H->mem, seg[0]};
     if (Lv.ni > 0 && cnt[0] + cnt[1] == 0) return fail(LSMG_EHIP, "segment construction failed on level %d", l);
     Lv.nseg[0] = cnt[0];
     Lv.nseg[1] = cnt[1];
@@ -621,7 +621,6 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
         HIPCHK(hipMemcpyAsync(Lv.items + cnt[0] + cnt[1], hv.data(), sizeof(int4) * hv.size(), hipMemcpyHostToDevice,
                               H->stream));
     HIPCHK(hipStreamSynchronize(H->stream));
-    if (seg[0]) (void)hipFree(seg[0]);
     if (H->dim == 2) LSMGCHK(build_tiles(H, l));
     return LSMG_OK;
 }
@@ -667,7 +666,9 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
                     (void *)Lv.ell_a, (void *)Lv.ell_b, (void *)Lv.ellf_w, (void *)Lv.ell_a32, (void *)Lv.ell_b32,
                     (void *)Lv.ellf_w32}) {
         if (!p) continue;
-        (void)hipFree(p);
+        // the tables may be in use by work still queued on the stream
+        HIPCHK(hipStreamSynchronize(H->stream));
+        H->mem.put(p);
         for (auto &q : H->ghost_ops)
             if (q == p) q = nullptr;
     }
@@ -739,7 +740,8 @@ lsmg_status build_ghost_ops(lsmg_hierarchy *H, int l)
     const size_t nnz = col.size();
     std::vector<float> va32(va.begin(), va.end()), vb32(vb.begin(), vb.end());
     auto up = [&](void **dst, const void *src, size_t bytes) -> lsmg_status {
-        if (hipMalloc(dst, bytes ? bytes : 1) != hipSuccess) return fail(LSMG_EOOM, "ghost operator allocation");
+        *dst = H->mem.get(bytes);
+        if (!*dst) return fail(LSMG_EOOM, "ghost operator allocation");
         H->ghost_ops.push_back(*dst);
         Lv.go_bytes += bytes ? bytes : 1;
         if (bytes) HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, H->stream));
@@ -934,39 +936,31 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
     int *err = nullptr;
     const long long nscr = compact_scratch_size(nn0) + 1;
     lsmg_status st = LSMG_OK;
-    auto cleanup = [&]() {
-        for (double *p : phis) (void)hipFree(p);
-        (void)hipFree(fin);
-        (void)hipFree(fgh);
-        (void)hipFree(scratch);
-        (void)hipFree(err);
-    };
-    if (hipMalloc(&fin, nn0) != hipSuccess || hipMalloc(&fgh, nn0) != hipSuccess ||
-        hipMalloc(&scratch, sizeof(int64_t) * nscr) != hipSuccess || hipMalloc(&err, sizeof(int)) != hipSuccess) {
-        cleanup();
-        return fail(LSMG_EOOM, "build temporaries");
-    }
-    (void)hipMemsetAsync(err, 0, sizeof(int), H->stream);
-    for (int l = 0; l < nlev && st == LSMG_OK; ++l) {
-        const Level &Lv = H->L[l];
-        const long long nn = (long long)Lv.n * Lv.n * (dim == 3 ? Lv.n : 1);
-        if (hipMalloc(&phis[l], sizeof(double) * nn) != hipSuccess) {
-            st = fail(LSMG_EOOM, "level-set copy");
-            break;
-        }
-        if (l == 0)
-            (void)hipMemcpyAsync(phis[0], d_phi, sizeof(double) * nn, hipMemcpyDeviceToDevice, H->stream);
-        else
-            launch_inject_phi(dim, phis[l - 1], H->L[l - 1].n, phis[l], Lv.n, H->stream);
-        st = build_level_arrays(H, l, phis[l], fin, fgh, scratch, (int)nscr, err);
-    }
-    for (int l = 0; l + 1 < nlev && st == LSMG_OK; ++l) st = build_band(H, l, phis[l], fin, scratch, (int)nscr);
     int herr = 0;
-    if (st == LSMG_OK) {
-        (void)hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, H->stream);
-        if (hipStreamSynchronize(H->stream) != hipSuccess) st = fail(LSMG_EHIP, "build synchronisation failed");
+    {  // the temporaries of the level construction, handed back at the end of the block
+        DevTemps tmp(H->mem, H->stream);
+        LSMGCHK(tmp.get(&fin, nn0));
+        LSMGCHK(tmp.get(&fgh, nn0));
+        LSMGCHK(tmp.get(&scratch, nscr));
+        LSMGCHK(tmp.get(&err, 1));
+        (void)hipMemsetAsync(err, 0, sizeof(int), H->stream);
+        for (int l = 0; l < nlev && st == LSMG_OK; ++l) {
+            const Level &Lv = H->L[l];
+            const long long nn = (long long)Lv.n * Lv.n * (dim == 3 ? Lv.n : 1);
+            st = tmp.get(&phis[l], nn);
+            if (st != LSMG_OK) break;
+            if (l == 0)
+                (void)hipMemcpyAsync(phis[0], d_phi, sizeof(double) * nn, hipMemcpyDeviceToDevice, H->stream);
+            else
+                launch_inject_phi(dim, phis[l - 1], H->L[l - 1].n, phis[l], Lv.n, H->stream);
+            st = build_level_arrays(H, l, phis[l], fin, fgh, scratch, (int)nscr, err);
+        }
+        for (int l = 0; l + 1 < nlev && st == LSMG_OK; ++l) st = build_band(H, l, phis[l], fin, scratch, (int)nscr);
+        if (st == LSMG_OK) {
+            (void)hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, H->stream);
+            if (hipStreamSynchronize(H->stream) != hipSuccess) st = fail(LSMG_EHIP, "build synchronisation failed");
+        }
     }
-    cleanup();
     if (st != LSMG_OK) return st;
     if (herr & 1) return fail(LSMG_EGEOM, "an inside node lies on the box edge");
     if (herr & 2) return fail(LSMG_EGEOM, "a ghost has no admissible Neumann row");
@@ -1168,7 +1162,7 @@ void lsmg_default_params(lsmg_params *p)
 const char *lsmg_last_error(void) { return g_err.c_str(); }
 
 lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid, const lsmg_params *params,
-                                 void *stream, lsmg_hierarchy **out)
+                                 const lsmg_allocator *allocator, void *stream, lsmg_hierarchy **out)
 {
     if (!out) return fail(LSMG_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1183,6 +1177,15 @@ lsmg_status lsmg_build_hierarchy(const double *d_levelset, const lsmg_grid *grid
     if (H->p.ghost_sweeps_coarse == 0) H->p.ghost_sweeps_coarse = grid->dim == 2 ? 20 : 30;
     if (H->p.sweeps_lambda == 0.0) H->p.sweeps_lambda = grid->dim == 2 ? 0.3 : 0.1;
     H->stream = (hipStream_t)stream;
+    if (allocator) {
+        if (!allocator->alloc || !allocator->free) {
+            delete H;
+            return fail(LSMG_EINVAL, "allocator needs both alloc and free");
+        }
+        H->mem.alloc_fn = allocator->alloc;
+        H->mem.free_fn = allocator->free;
+        H->mem.ctx = allocator->ctx;
+    }
     // LSMG_GRAPHS=0 replays the V-cycle as direct launches instead of a captured graph
     if (const char *e = std::getenv("LSMG_GRAPHS")) H->use_graphs = std::atoi(e) != 0;
     // LSMG_TAIL_LDS=0 runs the coarse tail from HBM instead of LDS
@@ -1370,8 +1373,9 @@ lsmg_status lsmg_state_create(lsmg_hierarchy *h, lsmg_state **out)
     if (!st) return fail(LSMG_EOOM, "host allocation");
     st->h = h;
     const Level &L0 = h->L[0];
-    if (hipMalloc(&st->s, sizeof(double) * L0.ssize) != hipSuccess ||
-        hipMalloc(&st->c, sizeof(double) * L0.ssize) != hipSuccess) {
+    st->s = (double *)h->mem.get(sizeof(double) * L0.ssize);
+    st->c = (double *)h->mem.get(sizeof(double) * L0.ssize);
+    if (!st->s || !st->c) {
         delete st;
         return fail(LSMG_EOOM, "state allocation");
     }

@@ -91,6 +91,7 @@ struct lsmg_batch {
     std::vector<const lsmg_state *> last_states;
     std::vector<const double *> last_sb;
     std::vector<double> last_sbc;
+    DevMem dmem;  // device memory: the caller's allocator or hipMalloc
     std::vector<void *> allocs;
     std::vector<hipEvent_t> evpool;
     // launch timing of one kernel class at one grid size
@@ -106,7 +107,7 @@ struct lsmg_batch {
         if (cap) (void)hipStreamDestroy(cap);
         for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
         for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
-        for (void *q : allocs) (void)hipFree(q);
+        for (void *q : allocs) dmem.put(q);
         if (h_act) (void)hipHostFree(h_act);
         if (h_cstatus) (void)hipHostFree(h_cstatus);
         if (h_nred) (void)hipHostFree(h_nred);
@@ -116,9 +117,8 @@ struct lsmg_batch {
     {
         *ptr = nullptr;
         if (count <= 0) count = 1;
-        void *q = nullptr;
-        if (hipMalloc(&q, sizeof(T) * (size_t)count) != hipSuccess)
-            return fail(LSMG_EOOM, "batch allocation of %lld bytes failed", (long long)(sizeof(T) * count));
+        void *q = dmem.get(sizeof(T) * (size_t)count);
+        if (!q) return fail(LSMG_EOOM, "batch allocation of %lld bytes failed", (long long)(sizeof(T) * count));
         allocs.push_back(q);
         *ptr = (T *)q;
         return LSMG_OK;
@@ -600,11 +600,11 @@ lsmg_status build_lists(lsmg_batch *B)
     }
     if (!hj.empty()) {
         ItemCopy *dj = nullptr;
-        HIPCHK(hipMalloc(&dj, sizeof(ItemCopy) * hj.size()));
+        DevTemps tmp(B->dmem, B->stream);
+        LSMGCHK(tmp.get(&dj, (long long)hj.size()));
         HIPCHK(hipMemcpyAsync(dj, hj.data(), sizeof(ItemCopy) * hj.size(), hipMemcpyHostToDevice, B->stream));
         launch_copy_items(dj, (int)hj.size(), B->pool, B->stream);
         HIPCHK(hipStreamSynchronize(B->stream));
-        (void)hipFree(dj);
     }
     return LSMG_OK;
 }
@@ -683,7 +683,8 @@ lsmg_status b_build(lsmg_batch *B)
 // ===========================================================================
 extern "C" {
 
-lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, void *stream, lsmg_batch **out)
+lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, const lsmg_allocator *allocator,
+                              void *stream, lsmg_batch **out)
 {
     if (!out) return fail(LSMG_EINVAL, "out is NULL");
     *out = nullptr;
@@ -702,6 +703,15 @@ lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, void *s
     }
     lsmg_batch *B = new (std::nothrow) lsmg_batch();
     if (!B) return fail(LSMG_EOOM, "host allocation");
+    if (allocator) {
+        if (!allocator->alloc || !allocator->free) {
+            delete B;
+            return fail(LSMG_EINVAL, "allocator needs both alloc and free");
+        }
+        B->dmem.alloc_fn = allocator->alloc;
+        B->dmem.free_fn = allocator->free;
+        B->dmem.ctx = allocator->ctx;
+    }
     B->dim = members[0]->dim;
     B->p = members[0]->p;
     B->fused = B->dim == 2;

@@ -223,14 +223,17 @@ __global__ void k_pack_ijk(const int64_t *__restrict__ c2g, const int64_t *__res
 }
 
 int build_inside_lists(int dim, const int64_t *c2g, int ni, int n, int *out, int *count, int64_t *scratch,
-                       int nscratch, hipStream_t s)
+                       int nscratch, const DevMem &mem, hipStream_t s)
 {
     count[0] = count[1] = 0;
     if (ni <= 0) return 0;
-    uint8_t *flags = nullptr;
-    int64_t *sel = nullptr;
-    if (hipMalloc(&flags, ni) != hipSuccess) return -1;
-    if (hipMalloc(&sel, sizeof(int64_t) * ni) != hipSuccess) { (void)hipFree(flags); return -1; }
+    uint8_t *flags = (uint8_t *)mem.get(ni);
+    int64_t *sel = (int64_t *)mem.get(sizeof(int64_t) * ni);
+    if (!flags || !sel) {
+        mem.put(flags);
+        mem.put(sel);
+        return -1;
+    }
     int off = 0;
     for (int colour = 0; colour < 2; ++colour) {
         k_colour_flags<<<(ni + 255) / 256, 256, 0, s>>>(c2g, ni, n, dim, colour, flags);
@@ -241,20 +244,20 @@ int build_inside_lists(int dim, const int64_t *c2g, int ni, int n, int *out, int
         off += c;
     }
     (void)hipStreamSynchronize(s);
-    (void)hipFree(flags);
-    (void)hipFree(sel);
+    mem.put(flags);
+    mem.put(sel);
     return off < 0 ? -1 : 0;
 }
 
 void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows, long long cs, int desc,
-                    int4 **out_items, int *out_count, hipStream_t s)
+                    int4 **out_items, int *out_count, const DevMem &mem, hipStream_t s)
 {
     (void)dim;
     (void)n;
-    int64_t *cnt = nullptr;
     out_items[0] = out_items[1] = nullptr;
     out_count[0] = out_count[1] = 0;
-    if (hipMalloc(&cnt, sizeof(int64_t) * (2 * rows + 1)) != hipSuccess) return;
+    int64_t *cnt = (int64_t *)mem.get(sizeof(int64_t) * (2 * rows + 1));
+    if (!cnt) return;
     const unsigned nb = (unsigned)((2 * rows + 255) / 256);
     k_seg_count<<<nb, 256, 0, s>>>(type, rows, Wp, cs, cnt);
     // per-colour totals come from the exclusive scan at rows and 2 rows
@@ -264,8 +267,8 @@ void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows,
     (void)hipMemcpyAsync(&h[1], cnt + 2 * rows, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);
     const long long total = h[1];
-    int4 *items = nullptr;
-    if (total > 0 && hipMalloc(&items, sizeof(int4) * total) == hipSuccess) {
+    int4 *items = total > 0 ? (int4 *)mem.get(sizeof(int4) * total) : nullptr;
+    if (items) {
         k_seg_emit<<<nb, 256, 0, s>>>(type, rows, Wp, cs, cnt, desc, items);
         (void)hipStreamSynchronize(s);
         out_items[0] = items;
@@ -273,7 +276,8 @@ void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows,
         out_count[0] = (int)h[0];
         out_count[1] = (int)(total - h[0]);
     }
-    (void)hipFree(cnt);
+    (void)hipStreamSynchronize(s);
+    mem.put(cnt);
 }
 
 // ---------------------------------------------------------------------------

@@ -128,6 +128,7 @@ struct lsmg_hierarchy {
                  *step_sb = nullptr;
     double step_sb_const = 0.0;
     int *h_status = nullptr;
+    DevMem mem;              // device memory: the caller's allocator or hipMalloc
     std::vector<void *> allocs;
     size_t alloc_bytes = 0;  // device bytes held through alloc()
     // launch timing of one kernel class on one level (HIP events on the stream)
@@ -156,9 +157,9 @@ struct lsmg_hierarchy {
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (cap) (void)hipStreamDestroy(cap);
-        for (void *p : ghost_ops) (void)hipFree(p);
+        for (void *p : ghost_ops) mem.put(p);
         for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
-        for (void *p : allocs) (void)hipFree(p);
+        for (void *p : allocs) mem.put(p);
         if (h_norms) (void)hipHostFree(h_norms);
         if (h_status) (void)hipHostFree(h_status);
     }
@@ -167,9 +168,8 @@ struct lsmg_hierarchy {
     {
         *ptr = nullptr;
         if (count <= 0) count = 1;
-        void *p = nullptr;
-        if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess)
-            return fail(LSMG_EOOM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
+        void *p = mem.get(sizeof(T) * (size_t)count);
+        if (!p) return fail(LSMG_EOOM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
         allocs.push_back(p);
         alloc_bytes += sizeof(T) * (size_t)count;
         *ptr = (T *)p;
@@ -184,13 +184,39 @@ struct lsmg_hierarchy {
     }
 };
 
+// temporaries of one call, taken from a hierarchy's or batch's device memory
+// and handed back on every exit path, after their stream has been synchronised
+struct DevTemps {
+    const lsmg::DevMem &m;
+    hipStream_t s;
+    std::vector<void *> p;
+    DevTemps(const lsmg::DevMem &mm, hipStream_t ss) : m(mm), s(ss) {}
+    template <typename T>
+    lsmg_status get(T **out, long long count)
+    {
+        void *q = m.get(sizeof(T) * (size_t)(count > 0 ? count : 1));
+        *out = (T *)q;
+        if (!q) return lsmg::fail(LSMG_EOOM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
+        p.push_back(q);
+        return LSMG_OK;
+    }
+    ~DevTemps()
+    {
+        if (p.empty()) return;
+        (void)hipStreamSynchronize(s);
+        for (void *q : p) m.put(q);
+    }
+};
+
 struct lsmg_state {
     lsmg_hierarchy *h = nullptr;
     double *s = nullptr, *c = nullptr;
     ~lsmg_state()
     {
-        (void)hipFree(s);
-        (void)hipFree(c);
+        if (h) {
+            h->mem.put(s);
+            h->mem.put(c);
+        }
     }
 };
 

@@ -9,6 +9,29 @@
 
 namespace lsmg {
 
+// Device memory of a hierarchy or batch: the caller's allocator where one was
+// given at creation (callbacks with a context), else hipMalloc / hipFree.
+// put() is called only after the stream the block was used on has been
+// synchronised.
+struct DevMem {
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+    void *get(size_t bytes) const
+    {
+        if (bytes == 0) bytes = 1;
+        if (alloc_fn) return alloc_fn(bytes, ctx);
+        void *p = nullptr;
+        return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+    }
+    void put(void *p) const
+    {
+        if (!p) return;
+        if (free_fn) free_fn(p, ctx);
+        else (void)hipFree(p);
+    }
+};
+
 // ghost sets up to this size are relaxed by one workgroup per smoothing step
 constexpr int kGhostFusedMax = 256;
 // levels with at most this many active nodes run inside the coarse-tail kernel
@@ -194,10 +217,10 @@ long long compact_scratch_size(long long N);
 void launch_c2s(int dim, const int64_t *c2g, int na, int n, int Wp, long long cs, int *c2s, int *cmap, hipStream_t s);
 // inside-segment work items of a level: returns the item count per colour (synchronises)
 void build_segments(int dim, const uint8_t *type_split, int n, int Wp, long long rows, long long cs, int desc,
-                    int4 **out_items, int *out_count, hipStream_t s);
+                    int4 **out_items, int *out_count, const DevMem &mem, hipStream_t s);
 // packed coordinates of the inside nodes of each colour (out: ni ints, colour 0 then 1)
 int build_inside_lists(int dim, const int64_t *c2g, int ni, int n, int *out, int *count, int64_t *scratch,
-                       int nscratch, hipStream_t s);
+                       int nscratch, const DevMem &mem, hipStream_t s);
 void launch_ghost_geometry(int dim, int level, int bc, const double *phi, const uint8_t *type_split,
                            const int64_t *c2g_ghost, const int *cmap, int ni, int ng, int n, int Wp, long long cs,
                            double lo, double h, int *g_idx, int *g_ijk, int *g_st, int *g_stg, int *g_stc, double *g_w,

@@ -51,6 +51,44 @@ _vp = ctypes.c_void_p
 _d = ctypes.c_double
 _i = ctypes.c_int
 
+_ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp)
+_FREE_FN = ctypes.CFUNCTYPE(None, _vp, _vp)
+
+
+class Allocator(ctypes.Structure):
+    """lsmg_allocator: device memory callbacks for the library's internal buffers."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", _vp)]
+
+
+# one torch-backed allocator per stream; kept for the life of the process because
+# hierarchies and batches hold its callbacks until they are destroyed
+_TORCH_ALLOCATORS = {}
+
+
+def torch_allocator(stream=None):
+    """An lsmg_allocator backed by torch's caching allocator on `stream` (default:
+    the current stream): the library's buffers then count in
+    torch.cuda.memory_allocated() and share torch's pool."""
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    key = (stream.device.index, stream.cuda_stream)
+    if key in _TORCH_ALLOCATORS:
+        return _TORCH_ALLOCATORS[key]
+    dev = stream.device.index
+
+    def _alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+        except Exception:      # out of memory: the library reports LSMG_EOOM
+            return None
+
+    def _free(ptr, _ctx):
+        if ptr:
+            torch.cuda.caching_allocator_delete(ptr)
+
+    a = Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
+    _TORCH_ALLOCATORS[key] = a
+    return a
+
 
 def load():
     """Load liblsmg.so; raises if it has not been built."""
@@ -64,7 +102,8 @@ def load():
     sigs = {
         "lsmg_default_params": (None, [ctypes.POINTER(Params)]),
         "lsmg_last_error": (ctypes.c_char_p, []),
-        "lsmg_build_hierarchy": (_i, [_vp, ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]),
+        "lsmg_build_hierarchy": (_i, [_vp, ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.POINTER(Allocator),
+                                      _vp, ctypes.POINTER(_vp)]),
         "lsmg_destroy_hierarchy": (None, [_vp]),
         "lsmg_set_params": (_i, [_vp, ctypes.POINTER(Params)]),
         "lsmg_set_dt": (_i, [_vp, _d]),
@@ -102,7 +141,7 @@ def load():
         "lsmg_memory_bytes": (_i, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "lsmg_estimate_bytes": (_i, [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t),
                                      ctypes.POINTER(ctypes.c_size_t)]),
-        "lsmg_batch_create": (_i, [ctypes.POINTER(_vp), _i, _vp, ctypes.POINTER(_vp)]),
+        "lsmg_batch_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(Allocator), _vp, ctypes.POINTER(_vp)]),
         "lsmg_batch_destroy": (None, [_vp]),
         "lsmg_batch_step": (_i, [_vp, ctypes.POINTER(_vp), _d, ctypes.POINTER(_vp), ctypes.POINTER(_d),
                                  ctypes.POINTER(_i), ctypes.POINTER(StepStats)]),
@@ -188,10 +227,20 @@ def estimate_bytes(dim, n, params, lo=-1.0, hi=1.0):
     return hb.value, sb.value
 
 
-class Hierarchy:
-    """A domain's grid hierarchy on the current CUDA device and stream."""
+def _allocator_arg(allocator, stream):
+    if allocator == "torch":
+        return ctypes.byref(torch_allocator(stream))
+    if allocator is None:
+        return None
+    return ctypes.byref(allocator)
 
-    def __init__(self, phi, dim, n, lo=-1.0, hi=1.0, params=None, stream=None):
+
+class Hierarchy:
+    """A domain's grid hierarchy on the current CUDA device and stream.  allocator:
+    "torch" (default) takes the library's buffers from torch's caching allocator,
+    None from hipMalloc, or an Allocator instance."""
+
+    def __init__(self, phi, dim, n, lo=-1.0, hi=1.0, params=None, stream=None, allocator="torch"):
         lib = load()
         self.params = params if params is not None else default_params()
         self.dim, self.n, self.lo, self.hi = dim, n, lo, hi
@@ -200,7 +249,9 @@ class Hierarchy:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         grid = Grid(dim, n, lo, hi)
         h = _vp()
+        self._alloc = allocator
         _check(lib.lsmg_build_hierarchy(_f64(phi), ctypes.byref(grid), ctypes.byref(self.params),
+                                        _allocator_arg(allocator, self.stream),
                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                "lsmg_build_hierarchy")
         self._h = h
@@ -395,14 +446,16 @@ class Batch:
     The members (Hierarchy objects) must outlive the batch; they are kept
     referenced here."""
 
-    def __init__(self, hierarchies, stream=None, autotune=True):
+    def __init__(self, hierarchies, stream=None, autotune=True, allocator="torch"):
         lib = load()
         self.members = list(hierarchies)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         arr = (_vp * len(self.members))(*[h._h for h in self.members])
         b = _vp()
-        _check(lib.lsmg_batch_create(arr, len(self.members), ctypes.c_void_p(self.stream.cuda_stream),
-                                     ctypes.byref(b)), "lsmg_batch_create")
+        self._alloc = allocator
+        _check(lib.lsmg_batch_create(arr, len(self.members), _allocator_arg(allocator, self.stream),
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(b)),
+               "lsmg_batch_create")
         self._b = b
         if not autotune:
             _check(lib.lsmg_batch_set_autotune(b, 0), "lsmg_batch_set_autotune")
