@@ -136,9 +136,13 @@ void lsmg_default_params(lsmg_params *p);
  * (inside / ghost / inactive), the compact ordering, ghost geometry (normal by
  * central differences, eq. nij; upwind stencil ST; boundary point B by
  * bisection; the biquadratic/triquadratic weights of eq. JssD, with a lower-
- * order fallback where ST reaches an inactive node, and the constant rule
- * (w = 1 on the ghost) where the ghost's own weight would be negative or B
- * lies outside the stencil) and the tables of the boundary-aware restriction.
+ * order fallback where ST reaches an inactive node; where no order is
+ * admissible, the ghost's own weight would be negative or B lies outside the
+ * stencil: in 2-D the axis rule (B on the grid line to the inside axis
+ * neighbour that gives the ghost the largest weight, found by bisection of the
+ * quadratic interpolant of phi on that line, and the row the quadratic
+ * interpolation along it), in 3-D the constant rule w = 1 on the ghost) and the
+ * tables of the boundary-aware restriction.
  * With params->bc = 1 the boundary rows are Neumann rows (section 3.6): the
  * derivative at B of the interpolant of s on ST along the unit gradient of the
  * interpolant of phi at B (eqs. Neumanntilde, JccN), with the fallbacks
@@ -230,14 +234,17 @@ lsmg_status lsmg_compact_to_grid(lsmg_hierarchy *h, int level, int64_t *d_out);
 
 /* Ghost table of a level (all device, Ng rows; nst = 3^dim):
  * d_st: Ng*nst int32 compact indices of the stencil ST (k = (k_x, k_y[, k_z]) in
- *   {0,1,2}^dim, x fastest, node G - h (m_x k_x, ...)), -1 where inactive;
+ *   {0,1,2}^dim, x fastest, node G - h (m_x k_x, ...), m = SIGN(normal) except
+ *   on the line of an axis-rule row, where G - m_a e_a is the inside
+ *   neighbour), -1 where inactive;
  * d_w: Ng*nst weights of the boundary row (eq. JssD); d_B: Ng*dim boundary
  * points; d_normal: Ng*dim unit normals by central differences (eq. nij);
  * d_row_normal: Ng*dim normal of the boundary row (d_normal for Dirichlet
  * rows; for Neumann rows the unit gradient of the interpolated level set at
  * B, eq. Neumanntilde); d_order: Ng int32 (2 quadratic, 1 linear, 0 constant
- * or, for Neumann rows, one-sided); d_bfallback: Ng int32 (1 when B came from
- * the first-order projection instead of bisection).  Any pointer may be NULL. */
+ * or, for Neumann rows, one-sided); d_bfallback: Ng int32 (0 when B came from
+ * bisection along the normal, 1 from the first-order projection, 2 from the
+ * axis rule).  Any pointer may be NULL. */
 lsmg_status lsmg_ghost_table(lsmg_hierarchy *h, int level, int32_t *d_st, double *d_w, double *d_B,
                              double *d_normal, double *d_row_normal, int32_t *d_order, int32_t *d_bfallback);
 

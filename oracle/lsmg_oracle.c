@@ -53,7 +53,7 @@ typedef struct {
     double *nrow;    /* ng * dim normal of the boundary row: nrm (Dirichlet), or the unit
                         gradient of the interpolated level set at B (Neumann, eq. Neumanntilde) */
     int *order;      /* 2 biquadratic, 1 bilinear, 0 constant (Neumann: one-sided) */
-    int *bfall;      /* 1 if B came from the first-order projection */
+    int *bfall;      /* B from: 0 bisection along the normal, 1 the first-order projection, 2 the axis rule */
     /* band of inactive nodes around coarse ghost centres (for the BC defect) */
     int nb;
     long *band;      /* grid indices */
@@ -297,6 +297,69 @@ static int neumann_row(const or_hier *H, const OLevel *L, const int *m, const lo
     return OR_OK;
 }
 
+/* READING (axis rule, 2-D): where the row of eq. BCs would take the constant
+ * rule (a negative self-weight, B outside the stencil, or no admissible order),
+ * the boundary point is taken on a grid line instead.  Among the axis
+ * neighbours G + sgn e_a that are inside (axes in order, sgn = -1 then +1), the
+ * one whose line gives the ghost the largest self-weight is chosen: on that line
+ * the stencil is oriented so that G - m_a e_a is the neighbour (m_a = -sgn), B
+ * is the zero of the quadratic interpolant of phi through G, G - m_a e_a and
+ * G - 2 m_a e_a (linear through the first two where the third leaves the box),
+ * found by bisection of t in (0, 1], and theta = t on that axis, 1 on the
+ * other.  The row is the quadratic interpolation along the line (linear where
+ * G - 2 m_a e_a is inactive): second order, with self-weight t (1 + t) / 2 (or
+ * t) in (0, 1].  Returns 0 if G has no inside axis neighbour. */
+static int axis_row(const or_hier *H, const OLevel *L, long g, const int *gi, int *m, long *st, char *oob,
+                    double *Bp, double *th, double *w, int *order)
+{
+    int dim = H->dim, n = L->n, nst = H->nst;
+    int best = -1, bsgn = 0;
+    double bw = -1.0, bt = 0.0;
+    for (int a = 0; a < dim; ++a)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            int n1[3] = {gi[0], gi[1], gi[2]}, n2[3] = {gi[0], gi[1], gi[2]};
+            n1[a] += sgn;
+            n2[a] += 2 * sgn;
+            if (!in_box(n1, n, dim) || !(L->phi[ravel(n1, n, dim)] < 0.0)) continue;
+            int q2 = in_box(n2, n, dim);
+            double f0 = L->phi[g], f1 = L->phi[ravel(n1, n, dim)], f2 = q2 ? L->phi[ravel(n2, n, dim)] : 0.0;
+            double lo = 0.0, hi = 1.0;
+            for (int it = 0; it < 200; ++it) {
+                double t = 0.5 * (lo + hi);
+                if (t <= lo || t >= hi) break;
+                double v = q2 ? lag2(0, t) * f0 + lag2(1, t) * f1 + lag2(2, t) * f2 : t * f0 + (1.0 - t) * f1;
+                if (v < 0.0) lo = t; else hi = t;
+            }
+            double wg = (q2 && L->type[ravel(n2, n, dim)] != 0) ? lag2(0, hi) : lag1(0, hi);
+            if (wg > bw) { bw = wg; best = a; bsgn = sgn; bt = hi; }
+        }
+    if (best < 0) return 0;
+    m[best] = -bsgn;
+    for (int k = 0; k < nst; ++k) {
+        int kk = k, idx[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) { idx[a] = gi[a] - m[a] * (kk % 3); kk /= 3; }
+        oob[k] = !in_box(idx, n, dim);
+        st[k] = oob[k] ? g : ravel(idx, n, dim);
+    }
+    for (int a = 0; a < dim; ++a) { Bp[a] = xcoord(H, L, gi[a]); th[a] = 1.0; }
+    th[best] = bt;
+    Bp[best] = xcoord(H, L, gi[best]) - m[best] * L->h * (1.0 - bt);
+    *order = 2;
+    for (int k = 0; k < nst; ++k) {
+        int kk = k; double wk = 1.0;
+        for (int a = 0; a < dim; ++a) { wk *= lag2(kk % 3, th[a]); kk /= 3; }
+        w[k] = wk;
+    }
+    for (int k = 0; k < nst; ++k) if (w[k] != 0.0 && (oob[k] || L->type[st[k]] == 0)) *order = 1;
+    if (*order == 1)
+        for (int k = 0; k < nst; ++k) {
+            int kk = k; double wk = 1.0;
+            for (int a = 0; a < dim; ++a) { wk *= lag1(kk % 3, th[a]); kk /= 3; }
+            w[k] = wk;
+        }
+    return 1;
+}
+
 static int build_level_geometry(or_hier *H, int l)
 {
     OLevel *L = &H->L[l];
@@ -437,10 +500,15 @@ static int build_level_geometry(or_hier *H, int l)
         }
         /* READING: a ghost whose own weight w[0] is negative (theta outside
          * [0, 1] on an axis, outside the paper's analysis) cannot meet eq.
-         * CFLcond with 0 < tau < 1; its row takes the constant rule */
+         * CFLcond with 0 < tau < 1: in 2-D its row takes the axis rule above,
+         * in 3-D (and in 2-D without an inside axis neighbour) the constant rule */
         if (w[0] < 0.0) order = 0;
-        if (order == 0)
+        if (order == 0 && dim == 2 && axis_row(H, L, g, gi, m, st, oob, Bp, th, w, &order)) {
+            for (int a = 0; a < dim; ++a) L->B[q * dim + a] = Bp[a];
+            L->bfall[q] = 2;
+        } else if (order == 0) {
             for (int k = 0; k < nst; ++k) w[k] = (k == 0) ? 1.0 : 0.0;
+        }
         L->order[q] = order;
     }
     return OR_OK;

@@ -285,8 +285,10 @@ void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows,
 // the box edge), upwind stencil ST, boundary point B by full-precision
 // bisection of the biquadratic (triquadratic) interpolant of phi on the
 // segment P = G - 2 h n -> G, the tensor weights of eq. (JssD) and the order
-// fallback (quadratic -> linear -> constant) where a nonzero weight falls on
-// an inactive or out-of-box node.
+// fallback (quadratic -> linear) where a nonzero weight falls on an inactive or
+// out-of-box node; where no order is admissible, the ghost's own weight would be
+// negative or B lies outside the stencil, the axis rule in 2-D and the constant
+// rule in 3-D.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double lag2(int k, double t)
 {
@@ -417,6 +419,100 @@ __device__ double phi_interp(const double *phi, const long long *stl, const int 
     return v;
 }
 
+// axis rule (2-D), taken where the row would otherwise take the constant rule:
+// among the inside axis neighbours G + sgn e_a (axes in order, sgn = -1 then
+// +1), the line giving the ghost the largest self-weight; on it the stencil is
+// oriented so that G - m_a e_a is that neighbour, B is the zero of the quadratic
+// interpolant of phi through G and the next two nodes of the line (linear
+// through two where the third leaves the box), bisected in t in (0, 1], and
+// theta = t on the axis, 1 on the other.  The weights are those of the 1-D
+// quadratic (linear where the third node is inactive).  Same operations in
+// the same order as the CPU reference.  Returns false if G has no inside axis
+// neighbour.
+template <int DIM>
+__device__ bool axis_row(const double *phi, const uint8_t *type, long long g, const int *gi, int n, int Wp,
+                         long long cs, double lo, double h, int *m, long long *stl, long long *sts, bool *oob,
+                         double *Bp, double *th, double *w, int &order)
+{
+    constexpr int NST = DIM == 2 ? 9 : 27;
+    int best = -1, bsgn = 0;
+    double bw = -1.0, bt = 0.0;
+    long long sa = 1;
+    for (int a = 0; a < DIM; ++a, sa *= n)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const int k1 = gi[a] + sgn, k2 = gi[a] + 2 * sgn;
+            if (k1 < 0 || k1 >= n || !(phi[g + sgn * sa] < 0.0)) continue;
+            const bool q2 = k2 >= 0 && k2 < n;
+            const double f0 = phi[g], f1 = phi[g + sgn * sa], f2 = q2 ? phi[g + 2 * sgn * sa] : 0.0;
+            double tlo = 0.0, thi = 1.0;
+            for (int it = 0; it < 200; ++it) {
+                const double t = 0.5 * (tlo + thi);
+                if (t <= tlo || t >= thi) break;
+                const double v = q2 ? lag2(0, t) * f0 + lag2(1, t) * f1 + lag2(2, t) * f2 : t * f0 + (1.0 - t) * f1;
+                if (v < 0.0) tlo = t;
+                else thi = t;
+            }
+            bool act2 = false;
+            if (q2) {
+                int id[3] = {gi[0], gi[1], gi[2]};
+                id[a] = k2;
+                act2 = type[sidx(n, Wp, cs, id[0], id[1], id[2])] != kOut;
+            }
+            const double wg = act2 ? lag2(0, thi) : lag1(0, thi);
+            if (wg > bw) {
+                bw = wg;
+                best = a;
+                bsgn = sgn;
+                bt = thi;
+            }
+        }
+    if (best < 0) return false;
+    m[best] = -bsgn;
+    const long long g0 = stl[0];
+    const long long gs = sts[0];
+    for (int k = 0; k < NST; ++k) {
+        int kk = k, id[3] = {0, 0, 0};
+        bool o = false;
+        for (int a = 0; a < DIM; ++a) {
+            id[a] = gi[a] - m[a] * (kk % 3);
+            kk /= 3;
+            if (id[a] < 0 || id[a] >= n) o = true;
+        }
+        oob[k] = o;
+        stl[k] = o ? g0 : (long long)id[0] + (long long)n * ((long long)id[1] + (long long)n * id[2]);
+        sts[k] = o ? gs : sidx(n, Wp, cs, id[0], id[1], id[2]);
+    }
+    for (int a = 0; a < DIM; ++a) {
+        Bp[a] = lo + (double)gi[a] * h;
+        th[a] = 1.0;
+    }
+    th[best] = bt;
+    Bp[best] = (lo + (double)gi[best] * h) - (double)m[best] * h * (1.0 - bt);
+    order = 2;
+    for (int k = 0; k < NST; ++k) {
+        int kk = k;
+        double wk = 1.0;
+        for (int a = 0; a < DIM; ++a) {
+            wk *= lag2(kk % 3, th[a]);
+            kk /= 3;
+        }
+        w[k] = wk;
+    }
+    for (int k = 0; k < NST; ++k)
+        if (w[k] != 0.0 && (oob[k] || type[sts[k]] == kOut)) order = 1;
+    if (order == 1)
+        for (int k = 0; k < NST; ++k) {
+            int kk = k;
+            double wk = 1.0;
+            for (int a = 0; a < DIM; ++a) {
+                wk *= lag1(kk % 3, th[a]);
+                kk /= 3;
+            }
+            w[k] = wk;
+        }
+    return true;
+}
+
 template <int DIM>
 __global__ void k_ghost_geometry(int level, int bc, const double *__restrict__ phi, const uint8_t *__restrict__ type,
                                  const int64_t *__restrict__ c2g_gh, const int *__restrict__ cmap, int ni, int ng, int n,
@@ -535,9 +631,13 @@ __global__ void k_ghost_geometry(int level, int bc, const double *__restrict__ p
     }
     if (bc != 1) {
         // a negative weight of the ghost itself (theta outside [0, 1] on an axis)
-        // cannot meet eq. CFLcond with 0 < tau < 1: the row takes the constant rule
+        // cannot meet eq. CFLcond with 0 < tau < 1: in 2-D the row takes the axis
+        // rule, in 3-D (and without an inside axis neighbour) the constant rule
         if (!bad && w[0] < 0.0) order = 0;
-        if (order == 0)
+        if (order == 0 && DIM == 2 &&
+            axis_row<DIM>(phi, type, g, gi, n, Wp, cs, lo, h, m, stl, sts, oob, Bp, th, w, order))
+            bfall = 2;
+        else if (order == 0)
             for (int k = 0; k < NST; ++k) w[k] = k == 0 ? 1.0 : 0.0;
     }
     g_idx[q] = (int)gs;

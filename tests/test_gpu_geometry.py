@@ -11,7 +11,7 @@ CASES = [("disk", 65, 5), ("star", 257, 9), ("star", 1025, 9), ("torus", 65, 9),
 
 
 # stars of the 64-domain batch (seed 0) whose concave corners give ghosts with a negative
-# biquadratic self-weight (constant rule) and order fallbacks
+# biquadratic self-weight (axis rule) and order fallbacks
 BATCH_MEMBERS = [36, 47]
 
 

@@ -188,38 +188,65 @@ def _lag2(k, t):
     return {0: t * (1 + t) / 2, 1: (1 - t) * (1 + t), 2: t * (t - 1) / 2}[k]
 
 
-def test_negative_ghost_weight_takes_constant_rule(oracle_mod):
+def test_negative_ghost_weight_takes_axis_row(oracle_mod):
     # Reading of eq. (CFLcond) outside theta in [0, 1]: where the biquadratic weight of the ghost
-    # itself is negative (possible only if theta leaves [0, 1] on an axis), the row takes the
-    # constant rule w = 1 on the ghost; everywhere else the biquadratic weights stand.
-    # The domain is a star of the 64-domain batch (seed 0, member 36) whose concave corners
-    # produce such ghosts on the 129^2 grid.
+    # itself would be negative (possible only if theta leaves [0, 1] on an axis), the 2-D row is
+    # taken on a grid line to an inside axis neighbour: B is the zero of the 1-D quadratic
+    # interpolant of phi through G and its next two nodes on that line, and the row is that 1-D
+    # interpolation, checked here from the level set and B alone.  Everywhere else the biquadratic
+    # weights stand.  The domain is a star of the 64-domain batch (seed 0, member 36) whose concave
+    # corners produce such ghosts on the 129^2 grid.
     d = I.batch_domains(64, 0)[36]
     n = d["n"]
-    H = oracle_mod.Hierarchy(I.star(n, **d["shape"]), 2, n, coarsest_n=9)
+    phi = I.star(n, **d["shape"])
+    H = oracle_mod.Hierarchy(phi, 2, n, coarsest_n=9)
     info = H.level_info(0)
     gt = H.ghost_table(0)
     c2g = H.compact_to_grid(0)
     x, y = I.grid_points(n, 2)
     h = info["h"]
+    P = np.stack([x, y], axis=1)
     flipped = 0
     for q in range(info["ng"]):
         g = c2g[info["ni"] + q]
         m = np.where(gt["normal"][q] >= 0, 1, -1)
-        G = np.array([x[g], y[g]])
+        G = P[g]
         th = m * (gt["B"][q] - (G - m * h)) / h
         wq = np.array([_lag2(k % 3, th[0]) * _lag2(k // 3, th[1]) for k in range(9)])
-        if wq[0] < 0:
+        if gt["bfallback"][q] == 2:
             flipped += 1
-            assert gt["order"][q] == 0
-            assert np.array_equal(gt["w"][q], np.eye(9)[0])
+            assert gt["order"][q] == 2
+            # B on a grid line through G: one coordinate moved, by at most h, towards an inside node
+            dB = gt["B"][q] - G
+            a = int(np.argmax(np.abs(dB)))
+            assert dB[1 - a] == 0.0 and 0 < abs(dB[a]) <= h
+            step = int(np.sign(dB[a]))
+            gi = np.array([g % n, g // n])
+            line = [gi.copy() for _ in range(3)]
+            for k in range(3):
+                line[k][a] += k * step
+            f = [phi[v[0] + n * v[1]] for v in line]
+            assert f[1] < 0.0
+            t = 1.0 - abs(dB[a]) / h
+            assert abs(_lag2(0, t) * f[0] + _lag2(1, t) * f[1] + _lag2(2, t) * f[2]) < 1e-12
+            # the row: 1-D quadratic weights at t on G, its inside neighbour and the next node
+            nodes = c2g[gt["st"][q]]
+            expect = {line[k][0] + n * line[k][1]: _lag2(k, t) for k in range(3)}
+            got = {}
+            for node, wk in zip(nodes, gt["w"][q]):
+                if wk != 0.0:
+                    got[node] = got.get(node, 0.0) + wk
+            assert set(got) <= set(expect)
+            for node, wk in expect.items():
+                assert abs(got.get(node, 0.0) - wk) < 1e-14
+            assert 0.0 < gt["w"][q][0] <= 1.0
         elif gt["order"][q] == 2:
+            assert wq[0] >= 0.0
             assert np.max(np.abs(gt["w"][q] - wq)) < 1e-13
     assert flipped == 4
     for l in range(H.nlev):
         g2 = H.ghost_table(l)
         li = H.level_info(l)
-        cg = H.compact_to_grid(l)
         for q in range(li["ng"]):
             own = g2["w"][q][g2["st"][q] == li["ni"] + q].sum()
             assert own >= 0.0 and abs(1 - 0.9 * own) < 1

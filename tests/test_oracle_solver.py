@@ -164,7 +164,7 @@ def test_multigrid_convergence_factor(oracle_mod):
 @pytest.mark.parametrize("member", [36, 47, 14])
 def test_batch_star_domains_converge(oracle_mod, member):
     # 129^2 stars of the 64-domain batch (seed 0) with thin arms and concave corners: with the
-    # constant rule for negative ghost weights and the extra ghost relaxations on mass-dominated
+    # axis rows for negative ghost weights and the extra ghost relaxations on mass-dominated
     # levels, Newton converges in the same few iterations as on the smooth domains and the
     # V-cycle factor stays well below 1
     d = I.batch_domains(64, 0)[member]
@@ -177,3 +177,45 @@ def test_batch_star_domains_converge(oracle_mod, member):
         assert rc == 0
         assert st["newton_iters"] <= 5
         assert np.median(st["rho"][1:st["vcycles"]]) < 0.5
+
+
+def _mms_star_run(oracle_mod, shape, n, T):
+    H = oracle_mod.Hierarchy(I.star(n, **shape), 2, n, coarsest_n=9, params=dict(SOLVER))
+    info = H.level_info(0)
+    na, ni, h = info["na"], info["ni"], info["h"]
+    dt = h
+    x, y = I.grid_points(n, 2)
+    g = H.compact_to_grid(0)
+    xa, ya = x[g], y[g]
+    gt = H.ghost_table(0)
+    B = gt["B"]
+    W = np.concatenate([I.s_exact(xa, ya, 0.0), I.c_exact(xa, ya, 0.0)])
+
+    def forcing(t):
+        return np.concatenate(I.mms_sources(xa, ya, t))
+
+    steps = int(round(T / dt))
+    for k in range(steps):
+        t0, t1 = k * dt, (k + 1) * dt
+        rc, W, _ = H.newton_cn_step(W, dt, I.s_exact(B[:, 0], B[:, 1], t1), forcing(t0), forcing(t1))
+        assert rc == 0
+    t = steps * dt
+    sx, cx = I.s_exact(xa[:ni], ya[:ni], t), I.c_exact(xa[:ni], ya[:ni], t)
+    es, ec = np.abs(W[:ni] - sx), np.abs(W[na:na + ni] - cx)
+    return (np.array([es.max() / np.abs(sx).max(), ec.max() / np.abs(cx).max(),
+                      es.sum() / np.abs(sx).sum(), ec.sum() / np.abs(cx).sum()]),
+            int(np.sum(gt["bfallback"] == 2)))
+
+
+def test_manufactured_solution_second_order_on_thin_armed_star(oracle_mod):
+    # member 36 of the 64-star batch (seed 0): on the 129^2 grid four ghosts at its concave
+    # corners would take a negative biquadratic self-weight; their axis rows keep the scheme
+    # second order there (with the constant rule s_G = s_b the 129^2 error was 1.7e-3, four
+    # orders above the trend; measured now 6.0e-7, 1.5e-7, 3.8e-8, orders 1.98-2.01)
+    shape = I.batch_domains(64, 0)[36]["shape"]
+    runs = [_mms_star_run(oracle_mod, shape, n, 0.25) for n in (129, 257, 513)]
+    errs = np.array([e for e, _ in runs])
+    assert runs[0][1] == 4
+    orders = np.log2(errs[:-1] / errs[1:])
+    assert np.all(orders > 1.9), orders
+    assert np.all(errs[0] < 2e-6), errs[0]
