@@ -188,6 +188,18 @@ lsmg_status lsmg_set_params(lsmg_hierarchy *h, const lsmg_params *params);
  * function (section 2). */
 lsmg_status lsmg_reinitialize(double *d_phi, const lsmg_grid *grid, int iterations, void *stream);
 
+/* lsmg_reinitialize for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, bit for bit, with the
+ * working arrays in a fixed device array of the library (52.4 MB per device,
+ * held until the process ends) instead of hipMalloc'd ones.  No allocating
+ * call is made.  Grids of at most 2^21 nodes (1025^2 in 2-D, 127^3 in 3-D);
+ * larger ones return LSMG_EINVAL before any GPU work.  Every call on a device
+ * uses that device's one array: calls that overlap on one device (several
+ * streams or host threads) race and must be serialised by the caller.
+ * Synchronises `stream` before returning. */
+lsmg_status lsmg_reinitialize_noalloc(double *d_phi, const lsmg_grid *grid, int iterations, void *stream);
+
 /* A level set from a mask (section 2, images): phi = -1 where d_mask != 0
  * (n^dim bytes), +1 elsewhere, then `iterations` explicit heat steps phi +=
  * (1 / (2 dim)) * (sum of the second differences).  d_phi: n^dim doubles out. */

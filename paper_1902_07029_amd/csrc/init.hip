@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -229,6 +230,51 @@ struct Scratch {
     }
 };
 
+// re-initialisation on caller streams and buffers: phi0, D and the second
+// copy of phi (n^dim doubles each), then the near-interface flags (n^dim bytes)
+void reinit_run(const Grid3 &G, double *d_phi, int iterations, hipStream_t s, double *phi0, double *tmp, double *D,
+                uint8_t *near)
+{
+    (void)hipMemcpyAsync(phi0, d_phi, sizeof(double) * G.nn, hipMemcpyDeviceToDevice, s);
+    k_reinit_prep<<<blocks_of(G.nn), 256, 0, s>>>(G, phi0, near, D);
+    double *cur = d_phi, *nxt = tmp;
+    for (int it = 0; it < iterations; ++it) {
+        k_reinit_step<<<blocks_of(G.nn), 256, 0, s>>>(G, phi0, near, D, cur, nxt);
+        std::swap(cur, nxt);
+    }
+    if (cur != d_phi) (void)hipMemcpyAsync(d_phi, cur, sizeof(double) * G.nn, hipMemcpyDeviceToDevice, s);
+}
+
+// Scratch of the allocation-free re-initialisation: one array per device,
+// sized for grids of up to kNoAllocNodes nodes (1025^2 in 2-D, 127^3 in 3-D),
+// 25 bytes per node (three doubles and a flag), 52.4 MB in all.  Each device
+// holds its copy until the process ends.
+constexpr long long kNoAllocNodes = 1LL << 21;
+constexpr size_t kNoAllocBytes = (size_t)kNoAllocNodes * (3 * sizeof(double) + 1);
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// the device address of `scratch` on each device, looked up once per device
+// with that device current (the array's host-side name is not a device address)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+lsmg_status scratch_ptr(void **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LSMG_EINVAL, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LSMG_EHIP, "no device address for the re-initialisation scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LSMG_OK;
+}
+
 }  // namespace
 }  // namespace lsmg
 
@@ -249,14 +295,30 @@ lsmg_status lsmg_reinitialize(double *d_phi, const lsmg_grid *grid, int iteratio
     LSMGCHK(S.get(&tmp, G.nn));
     LSMGCHK(S.get(&D, G.nn));
     LSMGCHK(S.get(&near, G.nn));
-    HIPCHK(hipMemcpyAsync(phi0, d_phi, sizeof(double) * G.nn, hipMemcpyDeviceToDevice, s));
-    k_reinit_prep<<<blocks_of(G.nn), 256, 0, s>>>(G, phi0, near, D);
-    double *cur = d_phi, *nxt = tmp;
-    for (int it = 0; it < iterations; ++it) {
-        k_reinit_step<<<blocks_of(G.nn), 256, 0, s>>>(G, phi0, near, D, cur, nxt);
-        std::swap(cur, nxt);
-    }
-    if (cur != d_phi) HIPCHK(hipMemcpyAsync(d_phi, cur, sizeof(double) * G.nn, hipMemcpyDeviceToDevice, s));
+    reinit_run(G, d_phi, iterations, s, phi0, tmp, D, near);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return LSMG_OK;
+}
+
+lsmg_status lsmg_reinitialize_noalloc(double *d_phi, const lsmg_grid *grid, int iterations, void *stream)
+{
+    Grid3 G;
+    LSMGCHK(grid3(grid, G));
+    if (G.nn > kNoAllocNodes)
+        return fail(LSMG_EINVAL, "grid of %lld nodes exceeds the %lld nodes of the allocation-free scratch",
+                    G.nn, kNoAllocNodes);
+    if (!d_phi || iterations < 0) return fail(LSMG_EINVAL, "bad argument");
+    void *p = nullptr;
+    LSMGCHK(scratch_ptr(&p));
+    // the regions are laid out for the largest grid, so their offsets never move
+    unsigned char *base = (unsigned char *)p;
+    double *phi0 = (double *)base;
+    double *tmp = phi0 + kNoAllocNodes;
+    double *D = tmp + kNoAllocNodes;
+    uint8_t *near = (uint8_t *)(D + kNoAllocNodes);
+    hipStream_t s = (hipStream_t)stream;
+    reinit_run(G, d_phi, iterations, s, phi0, tmp, D, near);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     return LSMG_OK;

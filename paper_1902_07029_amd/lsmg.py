@@ -113,6 +113,7 @@ def load():
                                  ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "lsmg_compact_to_grid": (_i, [_vp, _i, _vp]),
         "lsmg_reinitialize": (_i, [_vp, _vp, _i, _vp]),
+        "lsmg_reinitialize_noalloc": (_i, [_vp, _vp, _i, _vp]),
         "lsmg_levelset_from_mask": (_i, [_vp, _vp, _i, _vp, _vp]),
         "lsmg_extrapolate": (_i, [_vp, _vp, _vp, _i, _vp]),
         "lsmg_tail_in_lds": (_i, [_vp, _i, _vp]),
@@ -198,6 +199,15 @@ def reinitialize(phi, dim, n, iterations, lo=-1.0, hi=1.0, stream=None):
     """Level set phi (CUDA float64, n^dim) re-initialised towards the signed distance, in place."""
     grid = Grid(dim, n, lo, hi)
     _check(load().lsmg_reinitialize(_ptr(phi), ctypes.byref(grid), iterations, _stream(stream)), "lsmg_reinitialize")
+    return phi
+
+
+def reinitialize_noalloc(phi, dim, n, iterations, lo=-1.0, hi=1.0, stream=None):
+    """reinitialize() without any device allocation: the library's fixed scratch
+    array (grids of up to 2^21 nodes; calls overlapping on one device race)."""
+    grid = Grid(dim, n, lo, hi)
+    _check(load().lsmg_reinitialize_noalloc(_ptr(phi), ctypes.byref(grid), iterations, _stream(stream)),
+           "lsmg_reinitialize_noalloc")
     return phi
 
 
