@@ -1,15 +1,17 @@
 """Benchmark of the level-set multigrid Crank-Nicolson step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star1025|torus257|disk65|batch64|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch64|star1025|torus257|disk65|serve|...]
                     [--precision 0|1] [--no-cpu-baseline] [--no-sequential]
                     [--requests R] [--load X] [--budget-gb G]
 
-Workloads: star1025 (default, FP64), torus257 and disk65 are single domains;
-batch64 is 64 star domains of grid sizes 129^2 .. 1025^2 stepped together in
-mixed precision (one launch per kernel and grid size), reported beside the same
-domains stepped one after another with the plain FP64 path; serve is a seeded
-Poisson stream of 3-D simulations continuously batched under a memory budget,
-with p50/p99 step latency, against the same requests run one after another.
+Workloads: batch64 (default) is 64 star domains of grid sizes 129^2 .. 1025^2
+(10.8 M unknowns) stepped together, one launch per kernel and grid size, in
+mixed precision (the headline value) and in FP64, beside the same domains
+stepped one after another with the plain FP64 path; the oracle checks one
+member of each grid size over every step run.  star1025 (FP64 by default),
+torus257 and disk65 are single domains; serve is a seeded Poisson stream of
+3-D simulations continuously batched under a memory budget, with p50/p99 step
+latency, against the same requests run one after another.
 
 Profiling helpers (they print text, not the benchmark line):
     python bench.py --copy-probe MIB          one plain device copy kernel over MIB MiB, 5 times
@@ -478,28 +480,47 @@ def run_single(args):
     }
 
 
+# Algorithmic HBM bytes per finest active node per V-cycle (the byte model of the
+# kernels: four smoothing sweeps, the defect with the restriction, the
+# prolongation and the cycle-end defect with its norm, with the coarse levels'
+# share of 1/3 in 2-D and 1/7 in 3-D): 63 values of P bytes in 2-D, 55 in 3-D.
+# The mixed cycle moves FP32 values and adds the FP64 refinement (defect and
+# update, about 70 bytes per node).
+def vcycle_bytes_per_node(dim, mixed):
+    per = 63 if dim == 2 else 55
+    return per * 4 + 70 if mixed else per * 8
+
+
 def run_batch(args):
-    """64 star domains of uneven grid sizes (129^2 .. 1025^2) stepped together in
-    mixed precision, against the same domains stepped one after another with the
-    plain FP64 path."""
+    """64 star domains of uneven grid sizes (129^2 .. 1025^2) stepped together, in
+    mixed precision (the headline) and in FP64, against the same domains stepped one
+    after another with the plain FP64 path.  For each precision: a parity pass of
+    warmup + timed steps whose states of one member per grid size go to the oracle,
+    then the timed run from the same initial states (checked to end bitwise where the
+    parity pass ended), then a kernel timing pass."""
     import torch
     from paper_1902_07029_amd import lsmg
 
     doms = I.batch_domains(64, seed=0)
-    prec = args.precision if args.precision is not None else 1
     dt = doms[0]["dt"]
     phis = [I.star(d["n"], **d["shape"]) for d in doms]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Hs = [lsmg.Hierarchy(torch.from_numpy(phi).cuda(), 2, d["n"],
-                         params=lsmg.default_params(coarsest_n=d["coarsest"], precision=prec,
-                                                    fused_sweep=args.fused))
-          for phi, d in zip(phis, doms)]
-    B = lsmg.Batch(Hs)
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - t0) * 1e3
-    infos = [H.level_info(0) for H in Hs]
-    unk = np.array([2 * inf["na"] for inf in infos], dtype=np.float64)
+    sizes_all = sorted({d["n"] for d in doms})
+    # parity members: the first domain of each grid size
+    sample = [next(k for k, d in enumerate(doms) if d["n"] == n) for n in sizes_all]
+    big = sample[-1]
+    nsteps = args.warmup + args.steps
+    precs = [1, 0] if args.precision is None else [args.precision]
+
+    def build(prec):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Hs = [lsmg.Hierarchy(torch.from_numpy(phi).cuda(), 2, d["n"],
+                             params=lsmg.default_params(coarsest_n=d["coarsest"], precision=prec,
+                                                        fused_sweep=args.fused))
+              for phi, d in zip(phis, doms)]
+        B = lsmg.Batch(Hs)
+        torch.cuda.synchronize()
+        return Hs, B, (time.perf_counter() - t0) * 1e3
 
     def fresh_states(hs):
         out = []
@@ -510,60 +531,84 @@ def run_batch(args):
             out.append(st)
         return out
 
-    states = fresh_states(Hs)
-    # members for the oracle: the two smallest domains (parity) and the first of the
-    # largest grid size (timed CPU baseline, parity on its first steps too)
-    sample = sorted(range(len(doms)), key=lambda k: infos[k]["na"])[:2]
-    big = next(k for k, d in enumerate(doms) if d["n"] == max(dd["n"] for dd in doms))
-    sample.append(big)
-    traj = {k: [] for k in sample}
-    for _ in range(args.warmup):
-        B.step(states, dt)
-        for k in sample:
-            traj[k].append(states[k].get().cpu().numpy())
-    lat = []
-    cyc = np.zeros(len(doms))
-    newton = 0
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        _, stats = B.step(states, dt)
-        lat.append(time.perf_counter() - ts)
-        for k, stt in enumerate(stats):
-            cyc[k] += stt["vcycles"]
-            newton += stt["newton_iters"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    value = float(np.dot(unk, cyc)) / elapsed
-    # kernel timing pass: the smoother launches at the largest grid size
-    nmax = max(d["n"] for d in doms)
-    B.profile_start(lsmg.KERNEL_SMOOTH, nmax)
-    for _ in range(args.steps):
-        B.step(states, dt)
-    torch.cuda.synchronize()
-    launches, prof_ms = B.profile_stop()
-    P = 8 if prec == 0 else 4
-    fused = B.sweep_fused(nmax, prec) and Hs[0].params.nu1 % 2 == 0 and Hs[0].params.nu2 % 2 == 0
-    byts = 0.0
-    for H, d, inf in zip(Hs, doms, infos):
-        if d["n"] == nmax:
-            c2g0 = H.compact_to_grid(0).cpu().numpy()
-            if fused:
-                byts += fused_sweep_bytes(c2g0, inf["ni"], inf["ng"], d["n"], P)
-            else:
-                b0, b1 = smoother_bytes(c2g0, inf["ni"], inf["ng"], d["n"], 2, P)
-                byts += 0.5 * (b0 + b1)
-    kname = (f"k_smooth_rb (all {nmax}^2 levels of the batch, both colours of a sweep)" if fused
-             else f"k_smooth_colour (all {nmax}^2 levels of the batch, one colour)")
-    avg_s = prof_ms * 1e-3 / max(launches, 1)
-    achieved = byts / avg_s / 1e9 if launches else 0.0
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+    runs = {}
+    infos = None
+    for prec in precs:
+        Hs, B, build_ms = build(prec)
+        opar = oracle_params(Hs[0])      # the members share their (resolved) parameters
+        infos = [H.level_info(0) for H in Hs]
+        na = np.array([inf["na"] for inf in infos], dtype=np.float64)
+        # parity pass (the autotuner runs in its first step)
+        states = fresh_states(Hs)
+        traj = {k: [] for k in sample}
+        for _ in range(nsteps):
+            B.step(states, dt)
+            for k in sample:
+                traj[k].append(states[k].get().cpu().numpy())
+        # timed run from the same initial states
+        states = fresh_states(Hs)
+        for _ in range(args.warmup):
+            B.step(states, dt)
+        lat = []
+        cyc = np.zeros(len(doms))
+        newton = 0
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            _, stats = B.step(states, dt)
+            lat.append(time.perf_counter() - ts)
+            for k, stt in enumerate(stats):
+                cyc[k] += stt["vcycles"]
+                newton += stt["newton_iters"]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        same = all(np.array_equal(states[k].get().cpu().numpy(), traj[k][-1]) for k in sample)
+        # kernel timing pass: the smoother launches at the largest grid size
+        nmax = max(sizes_all)
+        B.profile_start(lsmg.KERNEL_SMOOTH, nmax)
+        for _ in range(args.steps):
+            B.step(states, dt)
+        torch.cuda.synchronize()
+        launches, prof_ms = B.profile_stop()
+        P = 8 if prec == 0 else 4
+        fused = B.sweep_fused(nmax, prec) and Hs[0].params.nu1 % 2 == 0 and Hs[0].params.nu2 % 2 == 0
+        byts = 0.0
+        for H, d, inf in zip(Hs, doms, infos):
+            if d["n"] == nmax:
+                c2g0 = H.compact_to_grid(0).cpu().numpy()
+                if fused:
+                    byts += fused_sweep_bytes(c2g0, inf["ni"], inf["ng"], d["n"], P)
+                else:
+                    b0, b1 = smoother_bytes(c2g0, inf["ni"], inf["ng"], d["n"], 2, P)
+                    byts += 0.5 * (b0 + b1)
+        kname = (f"k_smooth_rb (all {nmax}^2 levels of the batch, both colours of a sweep)" if fused
+                 else f"k_smooth_colour (all {nmax}^2 levels of the batch, one colour)")
+        avg_s = prof_ms * 1e-3 / max(launches, 1)
+        achieved = byts / avg_s / 1e9 if launches else 0.0
+        kern = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=load_traffic("smooth_rb" if fused else "smooth_colour", "batch64", prec),
-                    kernel=kname, launches=launches,
-                    avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(byts))
-    # the plain FP64 path, domain after domain, same steps
+                    kernel=kname, launches=launches, avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(byts))
+        bpn = vcycle_bytes_per_node(2, prec == 1)
+        vbytes = float(np.dot(na, cyc)) * bpn
+        vcyc = dict(bound="hbm", achieved=round(vbytes / elapsed / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(vbytes / elapsed / 1e9 / HBM_PEAK_GBS, 4), bytes_per_node_cycle=bpn,
+                    node_cycles=int(np.dot(na, cyc)),
+                    model="algorithmic bytes per finest active node per V-cycle x nodes x cycles executed "
+                          "/ timed wall time (all kernels, launch gaps and host work included)")
+        lat_ms = np.array(lat) * 1e3
+        runs[prec] = dict(value=float(np.dot(2 * na, cyc)) / elapsed, ms_per_step=elapsed * 1e3 / args.steps,
+                          vcycles=int(cyc.sum()), newton_iters=newton,
+                          solution_throughput=float(2 * na.sum()) * args.steps / elapsed,
+                          p50_step_ms=float(np.percentile(lat_ms, 50)), p99_step_ms=float(np.percentile(lat_ms, 99)),
+                          kernel_roofline=kern, vcycle_roofline=vcyc, build_ms=round(build_ms, 1),
+                          tuning={str(k): v for k, v in B.tuning().items()}, timed_equals_parity_pass=same,
+                          traj=traj)
+        del states, B, Hs
+        torch.cuda.synchronize()
+    unk = np.array([2 * inf["na"] for inf in infos], dtype=np.float64)
+    # the plain FP64 path, domain after domain
     seq = None
     if not args.no_sequential:
         H64 = [lsmg.Hierarchy(torch.from_numpy(phi).cuda(), 2, d["n"],
@@ -584,58 +629,97 @@ def run_batch(args):
         seq = dict(value=float(np.dot(unk, cyc64)) / el64, steps=nseq, ms_per_round=el64 * 1e3 / nseq,
                    solution_throughput=float(unk.sum()) * nseq / el64)
         del st64, H64
+    # the oracle over the same steps of the parity members; its time on the largest
+    # member is the one-core baseline
     cpu = parity = None
     if not args.no_cpu_baseline:
-        d = doms[big]
-        cpu, parity = cpu_baseline(phis[big], 2, d["n"], d["coarsest"], dt, oracle_params(Hs[big]),
-                                   args.cpu_budget, traj[big],
-                                   f"batch member {big} (star {d['n']}^2, stepped inside the 64-domain batch)")
-        parity = dict(parity, small=[])
-        for k in sample[:2]:
-            dk = doms[k]
-            _, pk = cpu_baseline(phis[k], 2, dk["n"], dk["coarsest"], dt, oracle_params(Hs[k]), 0.0, traj[k],
-                                 f"batch member {k} (star {dk['n']}^2)", max_steps=len(traj[k]))
-            parity["small"].append(pk)
-        parity["max_rel_err_all"] = max([parity["max_rel_err"]] + [q["max_rel_err"] for q in parity["small"]])
-    # all host cores at once (one oracle process per domain)
+        import oracle
+        par = []
+        worst = {p: 0.0 for p in precs}
+        for k in sample:
+            d = doms[k]
+            O = oracle.Hierarchy(phis[k], 2, d["n"], coarsest_n=d["coarsest"], params=opar)
+            info = O.level_info(0)
+            nak = info["na"]
+            s0, c0 = I.initial_state(d["n"], 2)
+            W = O.to_compact(0, s0, c0)
+            sb = np.ones(info["ng"])
+            errs = {p: [] for p in precs}
+            ocyc = 0
+            t0 = time.perf_counter()
+            for j in range(nsteps):
+                rc, W, stt = O.newton_cn_step(W, dt, sb)
+                if rc != 0:
+                    raise RuntimeError(f"oracle step failed with {rc} on member {k}")
+                ocyc += stt["vcycles"]
+                for p in precs:
+                    G = runs[p]["traj"][k][j]
+                    errs[p].append(max(float(np.max(np.abs(G[blk] - W[blk])) / np.max(np.abs(W[blk])))
+                                       for blk in (slice(0, nak), slice(nak, 2 * nak))))
+            el = time.perf_counter() - t0
+            for p in precs:
+                worst[p] = max(worst[p], max(errs[p]))
+            par.append(dict(member=k, n=d["n"], steps=nsteps,
+                            max_rel_err={("mixed" if p else "fp64"): max(errs[p]) for p in precs}))
+            if k == big:
+                cpu = dict(value=2 * nak * ocyc / el, unit="unknowns*cycles/s", cores=1, kind="oracle",
+                           host=host_cpu(),
+                           sample=f"batch member {k} (star {d['n']}^2): {nsteps} Crank-Nicolson steps, {ocyc} V-cycles "
+                                  f"in {el:.1f} s, serial C, one host core")
+        parity = dict(steps_checked=nsteps, timed_steps=args.steps, tolerance=1e-10,
+                      max_rel_err={("mixed" if p else "fp64"): worst[p] for p in precs},
+                      timed_run_equals_checked_run={("mixed" if p else "fp64"): runs[p]["timed_equals_parity_pass"]
+                                                    for p in precs},
+                      members=par)
     cpu_all = None
     if not args.no_cpu_baseline:
-        op = oracle_params(Hs[0])
-        jobs = [(phis[k], 2, doms[k]["n"], doms[k]["coarsest"], dt, op) for k in range(len(doms))]
+        jobs = [(phis[k], 2, doms[k]["n"], doms[k]["coarsest"], dt, opar) for k in range(len(doms))]
         cpu_all = cpu_baseline_pool(jobs, args.cpu_budget, "the batch's first domains, grids "
                                     + "/".join(str(doms[k]["n"]) for k in range(min(16, len(doms)))))
-    lat_ms = np.array(lat) * 1e3
+    head = runs[precs[0]]
     sizes = {}
     for d in doms:
         sizes[str(d["n"])] = sizes.get(str(d["n"]), 0) + 1
-    return {
+
+    def summary(r):
+        return {k: v for k, v in r.items() if k != "traj"}
+
+    out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "unknowns*cycles/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == 0 else "f32+f64",
+        "dtype": "f64" if precs[0] == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"batch64_{'fp64' if prec == 0 else 'mixed'}", "domains": len(doms),
-                   "grid_sizes": sizes, "dt": dt, "coarsest": 9, "unknowns": int(unk.sum()),
-                   "build_ms": round(build_ms, 1), "tuning": {str(k): v for k, v in B.tuning().items()}},
-        "vcycles": int(cyc.sum()),
-        "newton_iters": newton,
-        "solution_throughput": float(unk.sum()) * args.steps / elapsed,
-        "p50_step_ms": float(np.percentile(lat_ms, 50)),
-        "p99_step_ms": float(np.percentile(lat_ms, 99)),
-        "fp64_sequential": seq,
-        "speedup_vs_fp64_sequential": (value / seq["value"]) if seq else None,
-        "roofline": roofline,
+        "config": {"workload": "batch64" + ("" if args.precision is None else ("_fp64" if precs[0] == 0 else "_mixed")),
+                   "precision": "mixed" if precs[0] == 1 else "fp64", "domains": len(doms), "grid_sizes": sizes,
+                   "dt": dt, "coarsest": 9, "unknowns": int(unk.sum()), "cycle": "V(2,2) red-black"},
+        "vcycles": head["vcycles"],
+        "newton_iters": head["newton_iters"],
+        "solution_throughput": head["solution_throughput"],
+        "p50_step_ms": head["p50_step_ms"],
+        "p99_step_ms": head["p99_step_ms"],
+        "roofline": head["kernel_roofline"],
+        "vcycle_roofline": head["vcycle_roofline"],
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "parity": parity,
+        "fp64_sequential": seq,
+        "speedup_vs_fp64_sequential": (head["value"] / seq["value"]) if seq else None,
     }
+    if len(precs) == 2:
+        out["mixed_batched"] = summary(runs[1])
+        out["fp64_batched"] = summary(runs[0])
+        out["speedup_mixed_vs_fp64_batched"] = runs[1]["value"] / runs[0]["value"]
+    else:
+        out["run"] = summary(head)
+    return out
 
 
 def run_serve(args):
@@ -790,8 +874,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="star1025", choices=sorted(WORKLOADS) + ["batch64", "serve", "prepare1025"],
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batch64", choices=sorted(WORKLOADS) + ["batch64", "serve", "prepare1025"],
                     help="paper3: the paper's Test 3 with its W(2,1) cycle (section 4.2)")
     ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
     ap.add_argument("--load", type=float, default=2.0,
@@ -799,7 +883,7 @@ def main():
     ap.add_argument("--seq-steps", type=int, default=6, help="serve: steps timed per request on the FP64 path")
     ap.add_argument("--budget-gb", type=float, default=None, help="serve: memory budget (default 80%% of free)")
     ap.add_argument("--precision", type=int, default=None, choices=(0, 1),
-                    help="0 = FP64, 1 = mixed (default: FP64, batch64: mixed)")
+                    help="0 = FP64, 1 = mixed (default: single domains FP64; batch64 both, mixed the headline)")
     ap.add_argument("--bc", default="dirichlet", choices=("dirichlet", "neumann"),
                     help="star1025 / torus257 / disk65: boundary condition for s (section 3.6 for Neumann)")
     ap.add_argument("--fmg", type=int, default=0, choices=(0, 1, 2),
