@@ -237,6 +237,42 @@ def estimate_bytes(dim, n, params, lo=-1.0, hi=1.0):
     return hb.value, sb.value
 
 
+class _Ordered:
+    """Orders a library call that runs on `stream` with the caller's current stream:
+    the library's stream first waits for the work queued on the current stream (the
+    tensors passed in were written there), and the current stream then waits for the
+    call's work (its outputs are read there).  Nothing to do when they are the same
+    stream."""
+
+    def __init__(self, stream):
+        self.s = stream
+
+    def __enter__(self):
+        self.cur = torch.cuda.current_stream(self.s.device)
+        if self.cur != self.s:
+            self.s.wait_stream(self.cur)
+        return self
+
+    def __exit__(self, *exc):
+        if self.cur != self.s:
+            self.cur.wait_stream(self.s)
+        return False
+
+
+def _ordered(stream_of):
+    def deco(fn):
+        def wrapped(self, *a, **k):
+            with _Ordered(stream_of(self)):
+                return fn(self, *a, **k)
+        wrapped.__name__, wrapped.__doc__ = fn.__name__, fn.__doc__
+        return wrapped
+    return deco
+
+
+_own_stream = _ordered(lambda self: self.stream)
+_hier_stream = _ordered(lambda self: self.hier.stream)
+
+
 def _allocator_arg(allocator, stream):
     if allocator == "torch":
         return ctypes.byref(torch_allocator(stream))
@@ -307,8 +343,11 @@ class Hierarchy:
         return dict(n=n.value, h=h.value, ni=ni.value, ng=ng.value, na=ni.value + ng.value, nb=nb.value)
 
     def _vec(self, l):
-        return torch.zeros(2 * self.level_info(l)["na"], dtype=torch.float64, device="cuda")
+        # an output the library writes in full (no fill kernel, which would race with a
+        # library stream that has already been ordered after the current one)
+        return torch.empty(2 * self.level_info(l)["na"], dtype=torch.float64, device="cuda")
 
+    @_own_stream
     def compact_to_grid(self, l):
         out = torch.empty(self.level_info(l)["na"], dtype=torch.int64, device="cuda")
         _check(load().lsmg_compact_to_grid(self._h, l, _ptr(out)), "lsmg_compact_to_grid")
@@ -324,6 +363,7 @@ class Hierarchy:
         _check(load().lsmg_sweep_fused(self._h, level, precision, ctypes.byref(v)), "lsmg_sweep_fused")
         return bool(v.value)
 
+    @_own_stream
     def ghost_table(self, l):
         info = self.level_info(l)
         ng, nst, dim = info["ng"], 3 ** self.dim, self.dim
@@ -338,6 +378,7 @@ class Hierarchy:
                                        _ptr(bf)), "lsmg_ghost_table")
         return dict(st=st, w=w, B=B, normal=nrm, row_normal=nrow, order=order, bfallback=bf)
 
+    @_own_stream
     def residual(self, W, Wn, dt, sb=None, sb_const=1.0, fn=None, fnp1=None):
         F = torch.empty_like(W)
         nrm = _d()
@@ -345,40 +386,48 @@ class Hierarchy:
                                     _f64(F), ctypes.byref(nrm)), "lsmg_residual")
         return F, nrm.value
 
+    @_own_stream
     def set_linearization(self, W, dt):
         _check(load().lsmg_set_linearization(self._h, _f64(W), dt), "lsmg_set_linearization")
 
+    @_own_stream
     def level_state(self, l):
         out = self._vec(l)
         _check(load().lsmg_level_state(self._h, l, _f64(out)), "lsmg_level_state")
         return out
 
+    @_own_stream
     def apply_J(self, l, x):
         y = torch.empty_like(x)
         _check(load().lsmg_apply_J(self._h, l, _f64(x), _f64(y)), "lsmg_apply_J")
         return y
 
+    @_own_stream
     def smooth(self, l, rhs, x, nsweeps=1):
         x = x.clone()
         _check(load().lsmg_smooth(self._h, l, _f64(rhs), _f64(x), nsweeps), "lsmg_smooth")
         return x
 
+    @_own_stream
     def defect(self, l, rhs, x):
         r = torch.empty_like(x)
         nrm = _d()
         _check(load().lsmg_defect(self._h, l, _f64(rhs), _f64(x), _f64(r), ctypes.byref(nrm)), "lsmg_defect")
         return r, nrm.value
 
+    @_own_stream
     def restrict(self, l, r):
         rc = self._vec(l + 1)
         _check(load().lsmg_restrict(self._h, l, _f64(r), _f64(rc)), "lsmg_restrict")
         return rc
 
+    @_own_stream
     def prolong_add(self, l, ec, x):
         x = x.clone()
         _check(load().lsmg_prolong_add(self._h, l, _f64(ec), _f64(x)), "lsmg_prolong_add")
         return x
 
+    @_own_stream
     def coarse_solve(self, rhs):
         x = torch.empty_like(rhs)
         _check(load().lsmg_coarse_solve(self._h, _f64(rhs), _f64(x)), "lsmg_coarse_solve")
@@ -392,6 +441,7 @@ class Hierarchy:
         _check(load().lsmg_profile_stop(self._h, ctypes.byref(n), ctypes.byref(ms)), "lsmg_profile_stop")
         return n.value, ms.value
 
+    @_own_stream
     def vcycle(self, l, rhs, x):
         x = x.clone()
         nrm = _d()
@@ -419,17 +469,21 @@ class State:
         except Exception:
             pass
 
+    @_hier_stream
     def set(self, W):
         _check(load().lsmg_state_set(self._s, _f64(W)), "lsmg_state_set")
 
+    @_hier_stream
     def get(self):
         W = self.hier._vec(0)
         _check(load().lsmg_state_get(self._s, _f64(W)), "lsmg_state_get")
         return W
 
+    @_hier_stream
     def set_grid(self, s, c):
         _check(load().lsmg_state_set_grid(self._s, _f64(s), _f64(c)), "lsmg_state_set_grid")
 
+    @_hier_stream
     def get_grid(self):
         nn = self.hier.n ** self.hier.dim
         s = torch.empty(nn, dtype=torch.float64, device="cuda")
@@ -437,6 +491,7 @@ class State:
         _check(load().lsmg_state_get_grid(self._s, _f64(s), _f64(c)), "lsmg_state_get_grid")
         return s, c
 
+    @_hier_stream
     def step(self, dt, sb=None, sb_const=1.0, fn=None, fnp1=None, check=True):
         """One Crank-Nicolson step; returns (status, stats dict)."""
         st = StepStats()
@@ -481,6 +536,7 @@ class Batch:
         except Exception:
             pass
 
+    @_own_stream
     def step(self, states, dt, sb=None, sb_const=None, check=True):
         """One Crank-Nicolson step of every member; returns (status list, stats list)."""
         n = len(self.members)
@@ -499,6 +555,7 @@ class Batch:
             _check(rc, "lsmg_batch_step")
         return [status[k] for k in range(n)], [stats[k].as_dict() for k in range(n)]
 
+    @_own_stream
     def advance(self, states, dt, remaining, sb_const=None, max_ticks=1 << 30):
         """Ticks at V-cycle granularity until some member ends a step; returns a list of
         (member, status, stats, step_ms) for the members whose step ended, and the ticks run."""

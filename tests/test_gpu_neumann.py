@@ -87,22 +87,24 @@ def test_neumann_manufactured_solution_steps():
     info = O.level_info(0)
     na, h = info["na"], info["h"]
     x, y = I.grid_points(n, 2)
-    g = O.compact_to_grid(0)
-    gt = O.ghost_table(0)
-    B, nr = gt["B"], gt["row_normal"]
+    # each side takes its own compact order, boundary points and row normals
+    g, gg = O.compact_to_grid(0), host(H.compact_to_grid(0))
+    gt, ggt = O.ghost_table(0), {k: host(v) for k, v in H.ghost_table(0).items()}
     W = np.concatenate([I.s_exact(x[g], y[g], 0.0), I.c_exact(x[g], y[g], 0.0)])
     st = lsmg.State(H)
-    st.set(cuda(W))
+    st.set(cuda(np.concatenate([I.s_exact(x[gg], y[gg], 0.0), I.c_exact(x[gg], y[gg], 0.0)])))
 
-    def forcing(t):
-        return np.concatenate(I.mms_sources(x[g], y[g], t))
+    def forcing(t, idx):
+        return np.concatenate(I.mms_sources(x[idx], y[idx], t))
+
+    def data(t, tab):
+        gx, gy = I.s_exact_grad(tab["B"][:, 0], tab["B"][:, 1], t)
+        return gx * tab["row_normal"][:, 0] + gy * tab["row_normal"][:, 1]
 
     for k in range(4):
         t0, t1 = k * h, (k + 1) * h
-        gx, gy = I.s_exact_grad(B[:, 0], B[:, 1], t1)
-        sb = gx * nr[:, 0] + gy * nr[:, 1]
-        st.step(h, sb=cuda(sb), fn=cuda(forcing(t0)), fnp1=cuda(forcing(t1)))
-        rc, W, _ = O.newton_cn_step(W, h, sb, forcing(t0), forcing(t1))
+        st.step(h, sb=cuda(data(t1, ggt)), fn=cuda(forcing(t0, gg)), fnp1=cuda(forcing(t1, gg)))
+        rc, W, _ = O.newton_cn_step(W, h, data(t1, gt), forcing(t0, g), forcing(t1, g))
         assert rc == 0
         G = host(st.get())
         es, ec = rel(G[:na], W[:na]), rel(G[na:], W[na:])

@@ -67,3 +67,27 @@ def test_admission_respects_budget():
     assert rep["max_members"] <= 2
     for f in rep["finished"]:
         assert f["bytes"] <= f["est_bytes"], (f["bytes"], f["est_bytes"])
+
+
+@pytest.mark.gpu
+def test_failing_request_is_evicted_others_unchanged():
+    # one request starts from a non-finite state (forced from the host): its first step
+    # fails with LSMG_ENONFINITE and it leaves the batch; the others finish with the
+    # bits they have when run alone
+    params = lsmg.default_params(coarsest_n=9, precision=1)
+    reqs = _requests(4, 7, steps=(5, 9), gap=0.0)
+    bad = reqs[1]
+    bad.s0 = float("nan")
+    rep = Server(params, keep_states=True).run(reqs)
+    by_id = {f["id"]: f for f in rep["finished"]}
+    say(f"served {len(reqs)} requests, one failing: statuses "
+        f"{[by_id[r.id]['status'] for r in reqs]}, up to {rep['max_members']} members at once")
+    assert by_id[bad.id]["status"] == lsmg.ENONFINITE and by_id[bad.id]["steps"] == 0
+    assert rep["completed"] == len(reqs) - 1
+    assert rep["max_members"] >= 2
+    for r in reqs:
+        if r is bad:
+            continue
+        f = by_id[r.id]
+        assert f["status"] == lsmg.OK and f["steps"] == r.steps
+        assert np.array_equal(f["state"], _alone(r, params)), r.id

@@ -51,7 +51,7 @@ def test_star_257(precision):
 @pytest.mark.gpu
 @pytest.mark.parametrize("member,precision", [(36, 0), (47, 1)])
 def test_batch_star_members(member, precision):
-    # thin-armed 129^2 stars of the 64-domain batch: constant-rule ghosts and the extra
+    # thin-armed 129^2 stars of the 64-domain batch: axis-rule ghosts and the extra
     # ghost relaxations on mass-dominated levels
     d = I.batch_domains(64, 0)[member]
     _run("star", d["n"], 9, 1e-4, 3, precision, phi=I.star(d["n"], **d["shape"]))
@@ -83,21 +83,21 @@ def test_manufactured_solution_steps():
     na = info["na"]
     h = info["h"]
     x, y = I.grid_points(n, 2)
-    g = O.compact_to_grid(0)
-    B = O.ghost_table(0)["B"]
+    # each side takes its own compact order and boundary points
+    g, gg = O.compact_to_grid(0), host(H.compact_to_grid(0))
+    B, Bg = O.ghost_table(0)["B"], host(H.ghost_table(0)["B"])
     W = np.concatenate([I.s_exact(x[g], y[g], 0.0), I.c_exact(x[g], y[g], 0.0)])
     st = lsmg.State(H)
-    st.set(cuda(W))
+    st.set(cuda(np.concatenate([I.s_exact(x[gg], y[gg], 0.0), I.c_exact(x[gg], y[gg], 0.0)])))
 
-    def forcing(t):
-        f1, f2 = I.mms_sources(x[g], y[g], t)
+    def forcing(t, idx):
+        f1, f2 = I.mms_sources(x[idx], y[idx], t)
         return np.concatenate([f1, f2])
 
     for k in range(4):
         t0, t1 = k * h, (k + 1) * h
-        sb = I.s_exact(B[:, 0], B[:, 1], t1)
-        st.step(h, sb=cuda(sb), fn=cuda(forcing(t0)), fnp1=cuda(forcing(t1)))
-        rc, W, _ = O.newton_cn_step(W, h, sb, forcing(t0), forcing(t1))
+        st.step(h, sb=cuda(I.s_exact(Bg[:, 0], Bg[:, 1], t1)), fn=cuda(forcing(t0, gg)), fnp1=cuda(forcing(t1, gg)))
+        rc, W, _ = O.newton_cn_step(W, h, I.s_exact(B[:, 0], B[:, 1], t1), forcing(t0, g), forcing(t1, g))
         G = host(st.get())
         assert rel(G[:na], W[:na]) <= TOL and rel(G[na:], W[na:]) <= TOL
 
