@@ -571,6 +571,7 @@ def run_batch(args):
             B.step(states, dt)
         torch.cuda.synchronize()
         launches, prof_ms = B.profile_stop()
+        tuning = {str(k): v for k, v in B.tuning().items()}
         P = 8 if prec == 0 else 4
         fused = B.sweep_fused(nmax, prec) and Hs[0].params.nu1 % 2 == 0 and Hs[0].params.nu2 % 2 == 0
         byts = 0.0
@@ -598,14 +599,43 @@ def run_batch(args):
                     model="algorithmic bytes per finest active node per V-cycle x nodes x cycles executed "
                           "/ timed wall time (all kernels, launch gaps and host work included)")
         lat_ms = np.array(lat) * 1e3
+        # the same members as `groups` batches on their own streams, stepped concurrently
+        grouped = None
+        B = None
+        if args.groups > 1:
+            G = lsmg.BatchGroup(Hs, groups=args.groups)
+            gst = fresh_states(Hs)
+            for _ in range(args.warmup):
+                G.step(gst, dt)
+            gcyc = np.zeros(len(doms))
+            glat = []
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            for _ in range(args.steps):
+                ts = time.perf_counter()
+                _, stats = G.step(gst, dt)
+                glat.append(time.perf_counter() - ts)
+                for k, stt in enumerate(stats):
+                    gcyc[k] += stt["vcycles"]
+            torch.cuda.synchronize()
+            gel = time.perf_counter() - tg
+            gsame = all(np.array_equal(gst[k].get().cpu().numpy(), traj[k][-1]) for k in sample)
+            glat_ms = np.array(glat) * 1e3
+            grouped = dict(groups=len(G.parts), domains_per_group=[len(p) for p in G.parts],
+                           value=float(np.dot(2 * na, gcyc)) / gel, ms_per_step=gel * 1e3 / args.steps,
+                           p50_step_ms=float(np.percentile(glat_ms, 50)), p99_step_ms=float(np.percentile(glat_ms, 99)),
+                           vcycle_roofline_frac=round(float(np.dot(na, gcyc)) * bpn / gel / 1e9 / HBM_PEAK_GBS, 4),
+                           timed_run_equals_checked_run=gsame)
+            G.close()
+            del G, gst
         runs[prec] = dict(value=float(np.dot(2 * na, cyc)) / elapsed, ms_per_step=elapsed * 1e3 / args.steps,
                           vcycles=int(cyc.sum()), newton_iters=newton,
                           solution_throughput=float(2 * na.sum()) * args.steps / elapsed,
                           p50_step_ms=float(np.percentile(lat_ms, 50)), p99_step_ms=float(np.percentile(lat_ms, 99)),
                           kernel_roofline=kern, vcycle_roofline=vcyc, build_ms=round(build_ms, 1),
-                          tuning={str(k): v for k, v in B.tuning().items()}, timed_equals_parity_pass=same,
+                          tuning=tuning, timed_equals_parity_pass=same, concurrent_batches=grouped,
                           traj=traj)
-        del states, B, Hs
+        del states, Hs
         torch.cuda.synchronize()
     unk = np.array([2 * inf["na"] for inf in infos], dtype=np.float64)
     # the plain FP64 path, domain after domain
@@ -710,6 +740,7 @@ def run_batch(args):
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "parity": parity,
+        "concurrent_batches": head["concurrent_batches"],
         "fp64_sequential": seq,
         "speedup_vs_fp64_sequential": (head["value"] / seq["value"]) if seq else None,
     }
@@ -762,8 +793,58 @@ def run_serve(args):
     reqs = [Request(r["id"], r["arrival"], 3, r["n"], r["steps"], r["dt"], phi) for r, phi in zip(stream, phis)]
     params = lsmg.default_params(coarsest_n=9, precision=prec)
     budget = int(args.budget_gb * (1 << 30)) if args.budget_gb else None
-    server = Server(params, budget_bytes=budget)
+    # the served results of the requests whose whole oracle trajectories are stored
+    checked = [rid for rid in (12, 17) if rid < len(reqs)]
+    server = Server(params, budget_bytes=budget, keep_states=set(checked))
     rep = server.run(reqs)
+    parity = None
+    if checked:
+        par = []
+        for f in rep["finished"]:
+            if f.get("id") not in checked or "state" not in f:
+                continue
+            g = np.load(os.path.join(ROOT, "tests", "golden", f"trajectory_serve_r{f['id']}.npz"))
+            na, idx = int(g["na"]), g["idx"]
+            W = f["state"]
+            err = 0.0
+            for b, blk in enumerate((slice(0, na), slice(na, 2 * na))):
+                ref = g["norms"][-1, b]
+                err = max(err, float(np.max(np.abs(W[blk][idx] - g["vals"][-1, b])) / ref),
+                          abs(float(np.max(np.abs(W[blk]))) - ref) / ref)
+            par.append(dict(request=f["id"], n=f["n"], steps=f["steps"], status=f["status"], max_rel_err=err,
+                            against="stored oracle trajectory, 512 sampled nodes and the norms over all"))
+        parity = dict(tolerance=1e-10, requests=par, max_rel_err=max((q["max_rel_err"] for q in par), default=None))
+    # one core of the host running the oracle on the first steps of request 12 (129^3)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        r = base[12] if len(base) > 12 else base[0]
+        # the solver parameters as the library resolves them in 3-D, read from a small hierarchy
+        opar = oracle_params(lsmg.Hierarchy(torch.from_numpy(I.sphere(17)).cuda(), 3, 17, params=params))
+        O = oracle.Hierarchy(phis[r["id"]], 3, r["n"], coarsest_n=9, params=opar)
+        info = O.level_info(0)
+        s0, c0 = I.initial_state(r["n"], 3)
+        W = O.to_compact(0, s0, c0)
+        sb = np.ones(info["ng"])
+        cyc = k = 0
+        t1 = time.perf_counter()
+        while k < r["steps"] and time.perf_counter() - t1 < min(args.cpu_budget, 20.0):
+            rc, W, stt = O.newton_cn_step(W, r["dt"], sb)
+            cyc += stt["vcycles"]
+            k += 1
+        el = time.perf_counter() - t1
+        cpu = dict(value=2 * info["na"] * cyc / el, unit="unknowns*cycles/s", cores=1, kind="oracle", host=host_cpu(),
+                   sample=f"request {r['id']} ({r['n']}^3, {len(r['centres'])} ellipsoids): first {k} steps, "
+                          f"{cyc} V-cycles in {el:.1f} s, serial C, one host core")
+    # whole-cycle bytes over the served work: algorithmic bytes per finest active node per
+    # V-cycle (3-D, this precision) x node-cycles, over the makespan and over the busy time
+    bpn = vcycle_bytes_per_node(3, prec == 1)
+    vbytes = rep["unknowns_cycles"] / 2 * bpn
+    roofline = dict(bound="hbm", kind="whole V-cycle over the served work (byte model, all kernels and gaps)",
+                    achieved=round(vbytes / rep["makespan_s"] / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(vbytes / rep["makespan_s"] / 1e9 / HBM_PEAK_GBS, 4),
+                    frac_busy=round(vbytes / max(rep["busy_s"], 1e-9) / 1e9 / HBM_PEAK_GBS, 4),
+                    bytes_per_node_cycle=bpn, traffic=None)
     sizes = {}
     for r in base:
         sizes[str(r["n"])] = sizes.get(str(r["n"]), 0) + 1
@@ -799,9 +880,9 @@ def run_serve(args):
         "fp64_sequential": dict(value=seq_value, time_s=seq_time, steps_measured_per_request=args.seq_steps),
         "speedup_vs_fp64_sequential": rep["throughput"] / seq_value,
         "est_vs_actual_bytes": max(f["bytes"] / f["est_bytes"] for f in rep["finished"] if "bytes" in f),
-        "roofline": None,
-        "cpu_baseline": None,
-        "parity": None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
     }
 
 
@@ -893,6 +974,9 @@ def main():
                     help="2-D: both colours of a smoothing sweep in one launch (1) or one launch per colour (0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true", help="batch64: skip the sequential FP64 comparison")
+    ap.add_argument("--groups", type=int, default=4,
+                    help="batch64: also step the domains as this many concurrent batches on their own streams "
+                         "(1 = off)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--parity-steps", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, metavar="MIB")

@@ -180,7 +180,9 @@ __device__ __forceinline__ void ghost_apply_elem(const LevelDesc<T> *D, int q)
 
 // defect r = rhs - J x on one active row pair (section 3.5.2); returns |r| bits
 // (a mixed-precision cycle's FP32 right-hand side: E, when given, takes the
-// defect rounded to FP32 and a zero FP32 correction at the same node)
+// defect rounded to FP32 and a zero FP32 correction at the same node; the FP64
+// defect itself is then not stored, since no later kernel of a mixed-precision
+// solve reads it, only its norm)
 __device__ __forceinline__ void defect_to_f32(const LevelDesc<float> *E, long long idx, double rs, double rc)
 {
     E->rhs_s[idx] = (float)rs;
@@ -198,9 +200,12 @@ __device__ __forceinline__ unsigned long long defect_inside(const LevelDesc<T> *
     const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
     T rs, rc;
     inside_defect_vals<T>(R, D->rhs_s[idx], D->rhs_c[idx], D->x_s[idx], D->x_c[idx], rs, rc);
-    D->r_s[idx] = rs;
-    D->r_c[idx] = rc;
-    if (E) defect_to_f32(E, idx, (double)rs, (double)rc);
+    if (E) {
+        defect_to_f32(E, idx, (double)rs, (double)rc);
+    } else {
+        D->r_s[idx] = rs;
+        D->r_c[idx] = rc;
+    }
     const unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
     return a > b ? a : b;
 }
@@ -220,9 +225,12 @@ __device__ __forceinline__ unsigned long long defect_ghost(const LevelDesc<T> *D
     c_row<T>(D, idx, cs_d, cc_d);
     const T rs = D->rhs_s[idx] - v;
     const T rc = D->rhs_c[idx] - (cs_d * D->x_s[idx] + cc_d * D->x_c[idx]);
-    D->r_s[idx] = rs;
-    D->r_c[idx] = rc;
-    if (E) defect_to_f32(E, idx, (double)rs, (double)rc);
+    if (E) {
+        defect_to_f32(E, idx, (double)rs, (double)rc);
+    } else {
+        D->r_s[idx] = rs;
+        D->r_c[idx] = rc;
+    }
     const unsigned long long a = abs_bits((double)rs), b = abs_bits((double)rc);
     return a > b ? a : b;
 }

@@ -595,3 +595,59 @@ class Batch:
         n, ms = _i(), _d()
         _check(load().lsmg_batch_profile_stop(self._b, ctypes.byref(n), ctypes.byref(ms)), "lsmg_batch_profile_stop")
         return n.value, ms.value
+
+
+class BatchGroup:
+    """Members split into `groups` batches, each on its own stream and stepped from its
+    own host thread, so that the batches' launch chains overlap on the device and one
+    batch's host round trips hide behind the others' kernels.  Members are dealt
+    largest first to the group with the fewest active nodes so far.  A member's results
+    are those of its batch, which are bitwise those of the member alone."""
+
+    def __init__(self, hierarchies, groups=4, autotune=True, allocator="torch"):
+        import concurrent.futures
+        self.members = list(hierarchies)
+        groups = max(1, min(int(groups), len(self.members)))
+        na = [h.level_info(0)["na"] for h in self.members]
+        load_ = [0] * groups
+        self.parts = [[] for _ in range(groups)]
+        for k in sorted(range(len(self.members)), key=lambda k: -na[k]):
+            g = min(range(groups), key=lambda g: load_[g])
+            self.parts[g].append(k)
+            load_[g] += na[k]
+        self.parts = [sorted(p) for p in self.parts if p]
+        self.streams = [torch.cuda.Stream() for _ in self.parts]
+        self.batches = [Batch([self.members[k] for k in p], stream=s, autotune=autotune, allocator=allocator)
+                        for p, s in zip(self.parts, self.streams)]
+        self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=len(self.parts))
+
+    def close(self):
+        for b in getattr(self, "batches", []):
+            b.close()
+        if getattr(self, "_pool", None):
+            self._pool.shutdown(wait=True)
+            self._pool = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, states, dt, check=True):
+        """One Crank-Nicolson step of every member (states in member order); returns
+        (status list, stats list) in member order."""
+        n = len(self.members)
+        assert len(states) == n
+
+        def run(g):
+            with torch.cuda.stream(self.streams[g]):
+                return self.batches[g].step([states[k] for k in self.parts[g]], dt, check=check)
+
+        futs = [self._pool.submit(run, g) for g in range(len(self.parts))]
+        status, stats = [None] * n, [None] * n
+        for g, f in enumerate(futs):
+            sg, tg = f.result()
+            for j, k in enumerate(self.parts[g]):
+                status[k], stats[k] = sg[j], tg[j]
+        return status, stats

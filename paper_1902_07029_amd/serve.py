@@ -54,7 +54,8 @@ class _Member:
 class Server:
     """params: lsmg parameters shared by every simulation (coarsest_n, precision, ...);
     budget_bytes: device memory the resident simulations may hold (default 80 % of
-    the free memory); max_members: batch slots."""
+    the free memory); max_members: batch slots; keep_states: True to return every
+    finished simulation's final state, or a set of request ids."""
 
     def __init__(self, params, budget_bytes=None, max_members=64, autotune=False, keep_states=False,
                  max_ticks=8):
@@ -189,7 +190,7 @@ class Server:
                                arrival=m.req.arrival, admitted=m.t_admit, ready=m.t_ready, finished=t_end,
                                unknowns=m.unknowns, cycles=m.cycles, newton=m.newton, bytes=m.bytes,
                                est_bytes=m.est, lat_ms=m.lat)
-                    if self.keep_states:
+                    if self.keep_states is True or (self.keep_states and m.req.id in self.keep_states):
                         rec["state"] = m.st.get().cpu().numpy()
                     finished.append(rec)
                     used -= m.bytes
