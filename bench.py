@@ -974,7 +974,7 @@ def main():
                     help="2-D: both colours of a smoothing sweep in one launch (1) or one launch per colour (0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true", help="batch64: skip the sequential FP64 comparison")
-    ap.add_argument("--groups", type=int, default=4,
+    ap.add_argument("--groups", type=int, default=3,
                     help="batch64: also step the domains as this many concurrent batches on their own streams "
                          "(1 = off)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
