@@ -398,7 +398,7 @@ def run_single(args):
     torch.cuda.synchronize()
     prof_elapsed = time.perf_counter() - prof_t0
     launches, prof_ms = H.profile_stop()
-    if launches == 0:
+    if launches == 0 and not H.tail_whole():
         raise RuntimeError("no timed launches of the dominant kernel")
 
     # roofline of the dominant kernel, the finest-level smoother: in 2-D pairs of
@@ -419,14 +419,20 @@ def run_single(args):
     else:
         bytes_per_launch = 0.5 * (b0 + b1)
         kname, tkey = "k_smooth_colour (finest level, one colour)", "smooth_colour"
-    avg_s = prof_ms * 1e-3 / launches
-    achieved = bytes_per_launch / avg_s / 1e9
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=load_traffic(tkey, args.workload, prec),
-                    kernel=kname, launches=launches,
-                    avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(bytes_per_launch),
-                    timing_pass_ms_per_step=round(prof_elapsed * 1e3 / args.steps, 3))
+    if launches:
+        avg_s = prof_ms * 1e-3 / launches
+        achieved = bytes_per_launch / avg_s / 1e9
+        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4),
+                        traffic=load_traffic(tkey, args.workload, prec),
+                        kernel=kname, launches=launches,
+                        avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(bytes_per_launch),
+                        timing_pass_ms_per_step=round(prof_elapsed * 1e3 / args.steps, 3))
+    else:
+        # every level fits the one-workgroup coarse tail: there is no smoother launch
+        # to time, and a single workgroup is latency-bound by construction
+        roofline = dict(bound="latency", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s", frac=None, traffic=None,
+                        kernel="coarse tail (the whole hierarchy runs in one workgroup)", launches=0)
 
     cpu = parity = None
     if not args.no_cpu_baseline:

@@ -363,6 +363,11 @@ class Hierarchy:
         _check(load().lsmg_sweep_fused(self._h, level, precision, ctypes.byref(v)), "lsmg_sweep_fused")
         return bool(v.value)
 
+    def tail_whole(self):
+        """True when every level runs in the one-workgroup coarse tail (the finest level
+        has at most 1024 active nodes)."""
+        return self.level_info(0)["na"] <= 1024
+
     @_own_stream
     def ghost_table(self, l):
         info = self.level_info(l)
