@@ -625,6 +625,7 @@ class BatchGroup:
         self.batches = [Batch([self.members[k] for k in p], stream=s, autotune=autotune, allocator=allocator)
                         for p, s in zip(self.parts, self.streams)]
         self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=len(self.parts))
+        self._first_done = False
 
     def close(self):
         for b in getattr(self, "batches", []):
@@ -649,10 +650,16 @@ class BatchGroup:
             with torch.cuda.stream(self.streams[g]):
                 return self.batches[g].step([states[k] for k in self.parts[g]], dt, check=check)
 
-        futs = [self._pool.submit(run, g) for g in range(len(self.parts))]
         status, stats = [None] * n, [None] * n
-        for g, f in enumerate(futs):
-            sg, tg = f.result()
+        if not self._first_done:
+            # each batch times its launch shapes in its first step (the autotuner): the
+            # batches take that step one after another, so no batch times its kernels
+            # while another's run beside them
+            results = [run(g) for g in range(len(self.parts))]
+            self._first_done = True
+        else:
+            results = [f.result() for f in [self._pool.submit(run, g) for g in range(len(self.parts))]]
+        for g, (sg, tg) in enumerate(results):
             for j, k in enumerate(self.parts[g]):
                 status[k], stats[k] = sg[j], tg[j]
         return status, stats
