@@ -306,6 +306,38 @@ def trace_summary(directory):
     print(f"finest level: {len(d)} launches, average {sum(d) / len(d) / 1e3:.2f} us")
 
 
+def trace_step(directory, k):
+    """Kernels of one Crank-Nicolson step of a kernel trace: the dispatches from the
+    k-th explicit-half launch (0-based; each step starts with one) to the next, with
+    the step's span and the share of it during which the GPU ran a kernel."""
+    rows = _csv_rows(directory, "kernel_trace.csv")
+    for r in rows:
+        r["_s"], r["_e"] = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+    rows.sort(key=lambda r: r["_s"])
+    starts = [i for i, r in enumerate(rows) if "k_explicit_half" in r["Kernel_Name"]]
+    if k + 1 >= len(starts):
+        raise SystemExit(f"the trace holds {len(starts)} step starts")
+    seg = rows[starts[k]:starts[k + 1]]
+    span = seg[-1]["_e"] - seg[0]["_s"]
+    busy, last = 0, seg[0]["_s"]
+    for r in seg:
+        b = max(r["_s"], last)
+        if r["_e"] > b:
+            busy += r["_e"] - b
+        last = max(last, r["_e"])
+    by = {}
+    for r in seg:
+        key = _short(r["Kernel_Name"])
+        c = by.setdefault(key, [0, 0])
+        c[0] += 1
+        c[1] += r["_e"] - r["_s"]
+    print(f"step {k}: {len(seg)} dispatches, span {span / 1e3:.1f} us, GPU busy {busy / 1e3:.1f} us "
+          f"({100.0 * busy / span:.0f} %)")
+    print(f"{'calls':>7} {'total us':>10} {'avg us':>8}  kernel")
+    for key, (c, t) in sorted(by.items(), key=lambda kv: -kv[1][1]):
+        print(f"{c:7d} {t / 1e3:10.1f} {t / c / 1e3:8.2f}  {key}")
+
+
 def _pmc_per_dispatch(directory, counter, finest):
     rows = [r for r in _csv_rows(directory, "counter_collection.csv") if r["Counter_Name"] == counter]
     if finest:
@@ -987,11 +1019,17 @@ def main():
     ap.add_argument("--parity-steps", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, metavar="MIB")
     ap.add_argument("--trace-summary", metavar="DIR")
+    ap.add_argument("--trace-step", type=int, metavar="K",
+                    help="with --trace-summary: also the kernels of the K-th step of the trace (0-based)")
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
     ap.add_argument("--copy-mib", type=int, default=512)
     args = ap.parse_args()
     if args.trace_summary:
-        return trace_summary(args.trace_summary)
+        trace_summary(args.trace_summary)
+        if args.trace_step is not None:
+            print()
+            trace_step(args.trace_summary, args.trace_step)
+        return None
     if args.traffic:
         return traffic(*args.traffic, args.workload, args.precision or 0, args.copy_mib)
     if args.copy_probe:
