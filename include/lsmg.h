@@ -265,7 +265,7 @@ lsmg_status lsmg_ghost_table(lsmg_hierarchy *h, int level, int32_t *d_st, double
 /* A state holds W = (s, c) on the finest active nodes (FP64, device). */
 lsmg_status lsmg_state_create(lsmg_hierarchy *h, lsmg_state **out);
 void lsmg_state_destroy(lsmg_state *st);
-/* d_W: device compact vector of level 0 (2 Na doubles). */
+/* d_W: device compact vector of level 0 (2 Na doubles; may be NULL when Na = 0). */
 lsmg_status lsmg_state_set(lsmg_state *st, const double *d_W);
 lsmg_status lsmg_state_get(const lsmg_state *st, double *d_W);
 /* Grid form: d_s, d_c device n^dim doubles; set reads active nodes only,

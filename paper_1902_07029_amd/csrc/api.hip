@@ -1397,14 +1397,18 @@ void lsmg_state_destroy(lsmg_state *st)
 
 lsmg_status lsmg_state_set(lsmg_state *st, const double *d_W)
 {
-    if (!st || !d_W) return fail(LSMG_EINVAL, "NULL argument");
+    if (!st) return fail(LSMG_EINVAL, "NULL argument");
+    if (st->h->L[0].na == 0) return LSMG_OK;  // an empty domain: the vector has no entries
+    if (!d_W) return fail(LSMG_EINVAL, "NULL argument");
     scatter<double>(st->h, 0, d_W, st->s, st->c);
     return LSMG_OK;
 }
 
 lsmg_status lsmg_state_get(const lsmg_state *st, double *d_W)
 {
-    if (!st || !d_W) return fail(LSMG_EINVAL, "NULL argument");
+    if (!st) return fail(LSMG_EINVAL, "NULL argument");
+    if (st->h->L[0].na == 0) return LSMG_OK;  // an empty domain: the vector has no entries
+    if (!d_W) return fail(LSMG_EINVAL, "NULL argument");
     gather<double>(st->h, 0, st->s, st->c, d_W);
     return LSMG_OK;
 }
