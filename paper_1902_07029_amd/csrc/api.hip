@@ -984,9 +984,23 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
         LSMGCHK(H->alloc(&H->lu, na_c * na_c));
         LSMGCHK(H->alloc(&H->ainv, 2 * na_c * na_c + 2 * na_c));
     }
-    H->tail_l0 = nlev - 1;
-    while (H->tail_l0 > 0 && H->L[H->tail_l0 - 1].na <= kTailMaxNodes) --H->tail_l0;
+    // the coarse tail: the levels with one active node per thread of its workgroup,
+    // and the next finer ones of up to kTailMaxNodes nodes where the tail of the
+    // working precision still fits in LDS (a level of that size run alone is a chain
+    // of latency-bound launches)
+    int l1 = nlev - 1;
+    while (l1 > 0 && H->L[l1 - 1].na <= kTailNodes1) --l1;
+    int l2 = l1;
+    while (l2 > 0 && H->L[l2 - 1].na <= kTailMaxNodes) --l2;
+    H->tail_l0 = l2;
     LSMGCHK(build_tail_tables(H));
+    if (l2 < l1) {
+        const size_t bytes = H->p.precision == 1 ? H->tail_sz.bytes<float>() : H->tail_sz.bytes<double>();
+        if (!H->tail_lds || bytes > kTailLdsMax) {
+            H->tail_l0 = l1;
+            LSMGCHK(build_tail_tables(H));
+        }
+    }
     LSMGCHK(H->alloc(&H->piv, H->luN));
     LSMGCHK(H->zalloc(&H->lu_status, 1));
     LSMGCHK(H->zalloc(&H->d_norms, 4 * kNormSlots));
@@ -1049,13 +1063,12 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
                          bool fmg_first, bool factor_first)
 {
     const Level &L0 = H->L[0];
-    zero_active_x(H, 0);
     double rprev = nF;
     const bool mixed = H->p.precision == 1;
-    if (mixed) {
-        // r = F - J 0 in FP64
-        launch_defect<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), -1, with_tail(Exec(H->stream), L0.nghc), H->d32);
-    }
+    if (mixed)   // x = 0; the FP32 cycle's right-hand side is r = F - J 0 = F
+        launch_start_mixed(H->dim, H->d64, L0.w_act(), L0.nw_act(), with_tail(Exec(H->stream), L0.nghc), H->d32);
+    else
+        zero_active_x(H, 0);
     hipGraphExec_t ge = nullptr, gf = nullptr;
     // events recorded inside a graph cannot be timed: while launch timing is on,
     // cycles run as direct launches

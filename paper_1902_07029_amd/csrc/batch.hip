@@ -848,9 +848,10 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
             else LSMGCHK(b_autotune<double>(B, 3));
         }
         // linear solves J dW = F from dW = 0
-        launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
         if (mixed)
-            launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, with_tail(x0, B->lev0.tail), B->d32);
+            launch_start_mixed(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail), B->d32);
+        else
+            launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
         hipGraphExec_t ge = nullptr;
         // timed launches run direct: events inside a graph cannot be timed
         if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &ge));
@@ -1033,10 +1034,10 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
                 else LSMGCHK(b_autotune<double>(B, 3));
                 LSMGCHK(set_flag_rows(B, rows));
             }
-            launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xl, B->lev0.tail));
             if (mixed)
-                launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, -1, with_tail(xl, B->lev0.tail),
-                                      B->d32);
+                launch_start_mixed(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xl, B->lev0.tail), B->d32);
+            else
+                launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xl, B->lev0.tail));
         }
         if (has_c) {
             hipGraphExec_t ge = nullptr;

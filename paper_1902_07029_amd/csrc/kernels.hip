@@ -993,6 +993,24 @@ __global__ __launch_bounds__(kMaxBlock) void k_zero_x(const LevelDesc<T> *__rest
     D->x_c[idx] = T(0);
 }
 
+// start of a mixed-precision linear solve on the items' nodes: the FP64 correction
+// is zero, so the first defect F - J 0 is F itself; it goes to the FP32 right-hand
+// side with a zero FP32 correction (the effect of the defect from x = 0, without
+// reading the rows)
+template <int DIM>
+__global__ __launch_bounds__(kMaxBlock) void k_start_mixed(const LevelDesc<double> *__restrict__ descs, LSMG_ITEMS,
+                                                           const LevelDesc<float> *__restrict__ rhs32, LSMG_ACT)
+{
+    LSMG_ITEM_PROLOGUE
+    const LevelDesc<double> *D = descs + item_desc(w);
+    long long idx;
+    int i, j, k;
+    if (!node_of<double, DIM>(D, w, lane, idx, i, j, k)) return;
+    D->x_s[idx] = 0.0;
+    D->x_c[idx] = 0.0;
+    defect_to_f32(rhs32 + item_desc(w), idx, D->rhs_s[idx], D->rhs_c[idx]);
+}
+
 // ---------------------------------------------------------------------------
 // coarse tail: levels l0 .. L-1 of a V-cycle in one workgroup, walking packed
 // node lists (one node per thread and pass) with barriers between phases.
@@ -2022,6 +2040,13 @@ void launch_zero_x(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const 
     LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_zero_x<T, DIM>>(nw, x, d, w, nw));
 }
 
+void launch_start_mixed(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x,
+                        const LevelDesc<float> *d32)
+{
+    if (nw <= 0) return;
+    LSMG_DISPATCH_DIM(dim, (void)NST; item_launch<k_start_mixed<DIM>>(nw, x, d, w, nw, d32));
+}
+
 template <typename T>
 void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nblocks, int ncoarse_max, bool stage,
                  const Exec &x)
@@ -2029,6 +2054,18 @@ void launch_tail(int dim, const LevelDesc<T> *d, const TailArgs *args, int nbloc
     if (nblocks <= 0) return;
     const size_t shm = (size_t)4 * ncoarse_max * sizeof(double) + 2 * kTailMaxNodes * sizeof(T) +
                        (stage ? kTailStageInts * sizeof(int) : 0);
+    // above 64 KiB of dynamic LDS the kernel has to be allowed it
+    static bool attr[2][2] = {{false, false}, {false, false}};
+    bool &done = attr[dim == 3][stage];
+    if (!done) {
+        if (stage)
+            LSMG_DISPATCH_DIM(dim, (void)hipFuncSetAttribute((const void *)k_tail<T, DIM, NST, true>,
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailLdsMax));
+        else
+            LSMG_DISPATCH_DIM(dim, (void)hipFuncSetAttribute((const void *)k_tail<T, DIM, NST, false>,
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailLdsMax));
+        done = true;
+    }
     if (stage)
         LSMG_DISPATCH_DIM(dim, k_tail<T, DIM, NST, true><<<nblocks, 1024, shm, x.s>>>(d, args, ncoarse_max, 0, x.act));
     else

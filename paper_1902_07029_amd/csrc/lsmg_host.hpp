@@ -50,7 +50,10 @@ inline bool fuse_sweep(long long active_nodes, size_t value_bytes)
 {
     return active_nodes * (long long)value_bytes <= kFusedMaxBytes;
 }
-constexpr int kTailMaxNodes = 1024;
+// the coarse tail: levels of at most kTailNodes1 active nodes (one per thread of
+// its workgroup), and those of up to kTailMaxNodes where the tail still fits in LDS
+constexpr int kTailNodes1 = 1024;
+constexpr int kTailMaxNodes = 2048;
 constexpr int kMaxLevels = 16;
 // the coarse tail copies its levels' node lists into LDS when they fit in this many ints
 constexpr int kTailStageInts = 6144;
@@ -172,6 +175,10 @@ template <typename T> void launch_restrict(int dim, const LevelDesc<T> *d, const
 template <typename T> void launch_prolong(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_inject(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
 template <typename T> void launch_zero_x(int dim, const LevelDesc<T> *d, const int4 *w, int nw, const Exec &x);
+// x = 0 in FP64, and the FP32 right-hand side and correction of a mixed-precision solve's
+// first cycle (its defect from x = 0), on the items' nodes
+void launch_start_mixed(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x,
+                        const LevelDesc<float> *d32);
 void launch_explicit_half(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x);
 void launch_residual(int dim, const LevelDesc<double> *d, const int4 *w, int nw, int norm_k, const Exec &x);
 void launch_newton_update(int dim, const LevelDesc<double> *d, const int4 *w, int nw, const Exec &x);

@@ -1,7 +1,7 @@
 // Coarse tail of the V- or W-cycle held in LDS (gfx950, one 1024-thread
 // workgroup per hierarchy).
 //
-// The levels with at most kTailMaxNodes active nodes run in one workgroup with
+// The coarsest levels (up to kTailMaxNodes active nodes) run in one workgroup with
 // a barrier between phases (smoothing colours, ghost relaxation, defect, band,
 // restriction, coarsest solve, prolongation).  Reading them from HBM makes each
 // phase cost a few dependent memory round trips.  Here every value of those
@@ -522,10 +522,12 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const LevelDesc<T> *__restric
         for (int k = 0; k < kTabChunk; ++k)
             if (i0 + k * (int)blockDim.x < A.tab_words) tab32[i0 + k * blockDim.x] = w[k];
     }
-    // every level's values: a tail level has at most one active node per thread, so
-    // the node codes of all levels are fetched first, then all their values
+    // every level's values: where each tail level has at most one active node per
+    // thread, the node codes of all levels are fetched first, then all their values
     constexpr int kLev = 8;
-    if (L - A.l0 <= kLev && blockDim.x >= (unsigned)kTailMaxNodes) {
+    bool one_per_thread = L - A.l0 <= kLev;
+    for (int l = A.l0; l < L; ++l) one_per_thread = one_per_thread && A.ll[l].na <= (int)blockDim.x;
+    if (one_per_thread) {
         const int t = threadIdx.x;
         int code[kLev];
 #pragma unroll
