@@ -84,6 +84,15 @@ struct lsmg_batch {
     unsigned long long *d_norms = nullptr, *d_nred = nullptr, *h_nred = nullptr;
     long long norm_stride = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // linear solves in chunks of cycles with the stopping tests on the device:
+    // per-member control, the norms of a chunk's cycles, (d0, nlev) per member,
+    // the cycles each member's last solve took, and the cycle graph with the
+    // device-side tests (one per precision; a chunk replays it)
+    LinCtl *d_lctl = nullptr, *h_lctl = nullptr;
+    double *d_hist = nullptr, *h_hist = nullptr;
+    int2 *d_dlev = nullptr;
+    std::vector<int> last_cycles;
+    hipGraphExec_t gctl[2] = {nullptr, nullptr};
     bool use_graphs = true;
     int autotune = 1, tuned = 0;
     bool fused = false;         // 2-D, every member with fused sweeps
@@ -102,8 +111,10 @@ struct lsmg_batch {
     long long prof_acc_n = 0;
     ~lsmg_batch()
     {
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i) {
             if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+            if (gctl[i]) (void)hipGraphExecDestroy(gctl[i]);
+        }
         if (cap) (void)hipStreamDestroy(cap);
         for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
         for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
@@ -111,6 +122,8 @@ struct lsmg_batch {
         if (h_act) (void)hipHostFree(h_act);
         if (h_cstatus) (void)hipHostFree(h_cstatus);
         if (h_nred) (void)hipHostFree(h_nred);
+        if (h_lctl) (void)hipHostFree(h_lctl);
+        if (h_hist) (void)hipHostFree(h_hist);
     }
     template <typename T>
     lsmg_status alloc(T **ptr, long long count)
@@ -346,7 +359,7 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
 // one linear-solve iteration for every active member (see the single-hierarchy
 // driver): V-cycle, or FP32 V-cycle on the FP64 defect; then the FP64 defect
 // with its norm in slot 1
-void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s)
+void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s, bool ctl = false)
 {
     zero_bnorms(B, 1, 1, s);
     const Exec x0(s, B->d_act);
@@ -360,7 +373,10 @@ void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s)
     }
     launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 1, with_tail(x0, B->lev0.tail),
                           mixed ? B->d32 : nullptr);
-    launch_norm_reduce(B->d_norms, B->norm_stride, B->ndom, 1, 1, B->d_nred, s);
+    if (!ctl)
+        launch_norm_reduce(B->d_norms, B->norm_stride, B->ndom, 1, 1, B->d_nred, s);
+    else
+        launch_norm_ctl(B->d_norms, B->norm_stride, B->ndom, B->d_nred, B->d_lctl, B->d_dlev, B->d_act, B->d_hist, s);
 }
 
 void b_invalidate(lsmg_batch *B)
@@ -368,23 +384,28 @@ void b_invalidate(lsmg_batch *B)
     for (int i = 0; i < 2; ++i) {
         if (B->gexec[i]) (void)hipGraphExecDestroy(B->gexec[i]);
         B->gexec[i] = nullptr;
+        if (B->gctl[i]) (void)hipGraphExecDestroy(B->gctl[i]);
+        B->gctl[i] = nullptr;
     }
 }
 
-lsmg_status b_graph(lsmg_batch *B, bool mixed, hipGraphExec_t *out)
+// the captured cycle, with the plain norm reduction or (ctl) the device-side
+// stopping tests
+lsmg_status b_graph(lsmg_batch *B, bool mixed, hipGraphExec_t *out, bool ctl = false)
 {
     const int gi = mixed ? 1 : 0;
-    if (!B->gexec[gi]) {
+    hipGraphExec_t &ge = ctl ? B->gctl[gi] : B->gexec[gi];
+    if (!ge) {
         if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-        b_cycle_enqueue(B, mixed, B->cap);
+        b_cycle_enqueue(B, mixed, B->cap, ctl);
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamEndCapture(B->cap, &g));
-        hipError_t e = hipGraphInstantiate(&B->gexec[gi], g, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail(LSMG_EHIP, "batch graph instantiation failed: %s", hipGetErrorString(e));
     }
-    *out = B->gexec[gi];
+    *out = ge;
     return LSMG_OK;
 }
 
@@ -644,6 +665,19 @@ lsmg_status b_build(lsmg_batch *B)
     HIPCHK(hipHostMalloc(&B->h_nred, sizeof(unsigned long long) * 4 * nk, hipHostMallocDefault));
     HIPCHK(hipHostMalloc(&B->h_act, sizeof(int) * kFlagRows * nd, hipHostMallocDefault));
     HIPCHK(hipHostMalloc(&B->h_cstatus, sizeof(int) * nk, hipHostMallocDefault));
+    {
+        const int cmax = std::max(B->p.cycles_max, 1);
+        LSMGCHK(B->alloc(&B->d_lctl, nk));
+        LSMGCHK(B->alloc(&B->d_hist, (long long)cmax * nk));
+        LSMGCHK(B->alloc(&B->d_dlev, nk));
+        HIPCHK(hipHostMalloc(&B->h_lctl, sizeof(LinCtl) * nk, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(&B->h_hist, sizeof(double) * (size_t)cmax * nk, hipHostMallocDefault));
+        std::vector<int2> dl(nk);
+        for (int k = 0; k < nk; ++k) dl[k] = make_int2(B->d0[k], B->mem[k]->nlev);
+        HIPCHK(hipMemcpyAsync(B->d_dlev, dl.data(), sizeof(int2) * nk, hipMemcpyHostToDevice, B->stream));
+        HIPCHK(hipStreamSynchronize(B->stream));
+        B->last_cycles.assign(nk, 0);
+    }
     // coarse tails and coarsest operators, one workgroup per member
     std::vector<TailArgs> ta(nk);
     std::vector<CoarseArgs> ca(nk);
@@ -835,13 +869,20 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
             launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, with_tail(x0, S.icoarse.tail));
         if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, with_tail(x0, B->all.tail));
         launch_coarse_factor(B->dim, B->d64, B->d_coarse, nk, B->coarse_n_max, x0);
+        // the factorisations' status comes back with the first chunk's norms; a member
+        // whose coarsest operator is singular or not finite leaves the step then (its
+        // cycles until that point touch only its own arrays, and are not counted)
         HIPCHK(hipMemcpyAsync(B->h_cstatus, B->d_cstatus, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int k = 0; k < nk; ++k)
-            if (on[k] && B->h_cstatus[k] != 0) {
-                rc[k] = LSMG_ENONFINITE;
-                on[k] = 0;
-            }
+        bool status_read = false;
+        auto take_status = [&]() {
+            for (int k = 0; k < nk; ++k)
+                if (on[k] && B->h_cstatus[k] != 0) {
+                    rc[k] = LSMG_ENONFINITE;
+                    on[k] = 0;
+                    lin[k] = 0;
+                }
+            status_read = true;
+        };
         LSMGCHK(set_flags(B, on));
         if (B->autotune && !B->tuned) {
             if (mixed) LSMGCHK(b_autotune<float>(B, 3));
@@ -852,37 +893,70 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
             launch_start_mixed(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail), B->d32);
         else
             launch_zero_x<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
-        hipGraphExec_t ge = nullptr;
-        // timed launches run direct: events inside a graph cannot be timed
-        if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &ge));
         for (int k = 0; k < nk; ++k) {
             lin[k] = on[k];
             rprev[k] = nF[k];
         }
-        for (int q = 0; q < B->p.cycles_max; ++q) {
-            int nlin = 0;
+        // cycles in chunks: each member's stopping tests (|r| <= lin_rtol |F|, a
+        // non-finite |r|) run on the device after every cycle of a chunk (the captured
+        // cycle replayed back to back), and the norms come back once per chunk.  A chunk
+        // ends one cycle before the longest of the solving members' previous solves would
+        // (later chunks: one cycle each), so it rarely holds a cycle no member needs; the
+        // host replays the same tests on
+        // the norms, so members run exactly the cycles they would with a round trip
+        // after each
+        std::vector<int> solve_cycles(nk, 0);
+        int q = 0;
+        while (q < B->p.cycles_max) {
+            int nlin = 0, kc = 1;
             for (int k = 0; k < nk; ++k) {
                 if (lin[k] && rprev[k] <= B->p.lin_rtol * nF[k]) lin[k] = 0;
-                nlin += lin[k];
+                if (!lin[k]) continue;
+                ++nlin;
+                kc = std::max(kc, B->last_cycles[k] - 1 - solve_cycles[k]);
             }
             if (nlin == 0) break;
+            kc = std::min(kc, B->p.cycles_max - q);
+            for (int k = 0; k < nk; ++k) B->h_lctl[k] = LinCtl{B->p.lin_rtol * nF[k], rprev[k], lin[k] ? 1 : 0, 0};
+            HIPCHK(hipMemcpyAsync(B->d_lctl, B->h_lctl, sizeof(LinCtl) * nk, hipMemcpyHostToDevice, s));
             LSMGCHK(set_flags(B, lin));
-            if (ge) HIPCHK(hipGraphLaunch(ge, s));
-            else b_cycle_enqueue(B, mixed, s);
-            HIPCHK(hipMemcpyAsync(B->h_nred, B->d_nred, sizeof(unsigned long long) * 4 * nk, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (!ge) b_prof_collect(B);
-            for (int k = 0; k < nk; ++k) {
-                if (!lin[k]) continue;
-                const double rq = bnorm(B, k, 1);
-                ++cycles[k];
-                rho_last[k] = rprev[k] > 0.0 ? rq / rprev[k] : 0.0;
-                if (rho_last[k] > 0.0) logsum[k] += std::log(rho_last[k]);
-                ++nrho[k];
-                rprev[k] = rq;
-                if (!std::isfinite(rq)) lin[k] = 0;
+            hipGraphExec_t gc = nullptr;
+            // timed launches run direct: events inside a graph cannot be timed
+            if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &gc, true));
+            for (int j = 0; j < kc; ++j) {
+                if (gc) HIPCHK(hipGraphLaunch(gc, s));
+                else b_cycle_enqueue(B, mixed, s, true);
             }
+            B->act_last.clear();   // the chunk cleared the flags of the members that stopped
+            HIPCHK(hipMemcpyAsync(B->h_hist, B->d_hist, sizeof(double) * (size_t)kc * nk, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (!gc) b_prof_collect(B);
+            if (!status_read) take_status();
+            for (int j = 0; j < kc; ++j)
+                for (int k = 0; k < nk; ++k) {
+                    if (!lin[k]) continue;
+                    if (j > 0 && rprev[k] <= B->p.lin_rtol * nF[k]) {
+                        lin[k] = 0;
+                        continue;
+                    }
+                    // a member records the norms of its cycles from the chunk's first on
+                    const double rq = B->h_hist[(size_t)j * nk + k];
+                    ++cycles[k];
+                    ++solve_cycles[k];
+                    rho_last[k] = rprev[k] > 0.0 ? rq / rprev[k] : 0.0;
+                    if (rho_last[k] > 0.0) logsum[k] += std::log(rho_last[k]);
+                    ++nrho[k];
+                    rprev[k] = rq;
+                    if (!std::isfinite(rq)) lin[k] = 0;
+                }
+            q += kc;
         }
+        if (!status_read) {
+            HIPCHK(hipStreamSynchronize(s));
+            take_status();
+        }
+        for (int k = 0; k < nk; ++k)
+            if (solve_cycles[k] > 0) B->last_cycles[k] = solve_cycles[k];
         // Newton update and the new residual
         LSMGCHK(set_flags(B, on));
         zero_bnorms(B, 0, 4, s);

@@ -1526,6 +1526,40 @@ __global__ __launch_bounds__(kNormSlots) void k_norm_reduce(const unsigned long 
     }
 }
 
+// norm 1 (a cycle's FP64 defect) reduced per domain as in k_norm_reduce, then the
+// domain's linear-solve control for cycles run without a host round trip: a
+// domain still solving records the norm as the next of its chunk, and stops on a
+// non-finite norm or once the norm is at most its tolerance (the tests the host
+// makes between cycles); a domain that stops clears the cycle flags of its levels
+__global__ __launch_bounds__(kNormSlots) void k_norm_ctl(const unsigned long long *__restrict__ base, long long stride,
+                                                         unsigned long long *__restrict__ out, LinCtl *__restrict__ ctl,
+                                                         const int2 *__restrict__ dlev, int *__restrict__ act,
+                                                         double *__restrict__ hist, int ndom)
+{
+    __shared__ unsigned long long part[kNormSlots / kWave];
+    const int dom = blockIdx.x;
+    unsigned long long v = base[stride + (long long)dom * kNormSlots + threadIdx.x];
+    v = wave_max_u64(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    unsigned long long m = 0;
+    for (int i = 0; i < kNormSlots / kWave; ++i) m = part[i] > m ? part[i] : m;
+    out[dom * 4 + 1] = m;
+    LinCtl c = ctl[dom];
+    if (!c.lin) return;
+    const double rq = __longlong_as_double((long long)m);
+    hist[(long long)c.n * ndom + dom] = rq;
+    ++c.n;
+    c.rprev = rq;
+    c.lin = (isfinite(rq) && !(rq <= c.tol)) ? 1 : 0;
+    ctl[dom] = c;
+    if (!c.lin) {
+        const int2 dl = dlev[dom];
+        for (int l = 0; l < dl.y; ++l) act[dl.x + l] = 0;
+    }
+}
+
 // concatenation of work lists: job b copies cnt items from src to dst + off,
 // adding dshift to each item's descriptor index
 __global__ void k_copy_items(const ItemCopy *__restrict__ jobs, int4 *__restrict__ dst)
@@ -2138,6 +2172,13 @@ void launch_norm_reduce(const unsigned long long *base, long long stride, int nd
 {
     if (ndom <= 0) return;
     k_norm_reduce<<<ndom, kNormSlots, 0, s>>>(base, stride, first, count, out);
+}
+
+void launch_norm_ctl(const unsigned long long *base, long long stride, int ndom, unsigned long long *out, LinCtl *ctl,
+                     const int2 *dlev, int *act, double *hist, hipStream_t s)
+{
+    if (ndom <= 0) return;
+    k_norm_ctl<<<ndom, kNormSlots, 0, s>>>(base, stride, out, ctl, dlev, act, hist, ndom);
 }
 
 void launch_copy_items(const ItemCopy *jobs, int njobs, int4 *dst, hipStream_t s)

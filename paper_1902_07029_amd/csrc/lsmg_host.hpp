@@ -193,6 +193,18 @@ template <typename T> void launch_fill(T *p, long long n, T v, hipStream_t s);
 void launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 void launch_norm_reduce(const unsigned long long *base, long long stride, int ndom, int first, int count,
                         unsigned long long *out, hipStream_t s);
+// linear-solve control of one domain of a batch whose cycles run in chunks on the
+// device: tol = lin_rtol |F|, the last defect norm, whether it still solves, and
+// how many norms it has recorded in the chunk
+struct LinCtl {
+    double tol, rprev;
+    int lin, n;
+};
+// norm 1 reduced per domain (as launch_norm_reduce), then each solving domain's
+// control: the norm stored at hist[n * ndom + dom], n counted up; a domain that
+// stops clears the flags act[d0 .. d0 + nlev) of its levels (dlev[dom] = (d0, nlev))
+void launch_norm_ctl(const unsigned long long *base, long long stride, int ndom, unsigned long long *out, LinCtl *ctl,
+                     const int2 *dlev, int *act, double *hist, hipStream_t s);
 void launch_copy_items(const ItemCopy *jobs, int njobs, int4 *dst, hipStream_t s);
 void launch_compact_to_grid(const int64_t *c2g, int na, const double *a, const double *b, const int *c2s, double *gs,
                             double *gc, hipStream_t s);
