@@ -361,7 +361,9 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
 // with its norm in slot 1
 void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s, bool ctl = false)
 {
-    zero_bnorms(B, 1, 1, s);
+    // (with the device-side tests the norm slots are left zero by the previous
+    // cycle, and cleared before a chunk)
+    if (!ctl) zero_bnorms(B, 1, 1, s);
     const Exec x0(s, B->d_act);
     if (!mixed) {
         b_vcycle<double>(B, s);
@@ -920,6 +922,7 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
             for (int k = 0; k < nk; ++k) B->h_lctl[k] = LinCtl{B->p.lin_rtol * nF[k], rprev[k], lin[k] ? 1 : 0, 0};
             HIPCHK(hipMemcpyAsync(B->d_lctl, B->h_lctl, sizeof(LinCtl) * nk, hipMemcpyHostToDevice, s));
             LSMGCHK(set_flags(B, lin));
+            zero_bnorms(B, 1, 1, s);
             hipGraphExec_t gc = nullptr;
             // timed launches run direct: events inside a graph cannot be timed
             if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &gc, true));

@@ -1530,15 +1530,18 @@ __global__ __launch_bounds__(kNormSlots) void k_norm_reduce(const unsigned long 
 // domain's linear-solve control for cycles run without a host round trip: a
 // domain still solving records the norm as the next of its chunk, and stops on a
 // non-finite norm or once the norm is at most its tolerance (the tests the host
-// makes between cycles); a domain that stops clears the cycle flags of its levels
-__global__ __launch_bounds__(kNormSlots) void k_norm_ctl(const unsigned long long *__restrict__ base, long long stride,
+// makes between cycles); a domain that stops clears the cycle flags of its levels.
+// The slots are cleared after they are read, for the next cycle's defect
+__global__ __launch_bounds__(kNormSlots) void k_norm_ctl(unsigned long long *__restrict__ base, long long stride,
                                                          unsigned long long *__restrict__ out, LinCtl *__restrict__ ctl,
                                                          const int2 *__restrict__ dlev, int *__restrict__ act,
                                                          double *__restrict__ hist, int ndom)
 {
     __shared__ unsigned long long part[kNormSlots / kWave];
     const int dom = blockIdx.x;
-    unsigned long long v = base[stride + (long long)dom * kNormSlots + threadIdx.x];
+    const long long slot = stride + (long long)dom * kNormSlots + threadIdx.x;
+    unsigned long long v = base[slot];
+    base[slot] = 0ull;
     v = wave_max_u64(v);
     if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -2174,7 +2177,7 @@ void launch_norm_reduce(const unsigned long long *base, long long stride, int nd
     k_norm_reduce<<<ndom, kNormSlots, 0, s>>>(base, stride, first, count, out);
 }
 
-void launch_norm_ctl(const unsigned long long *base, long long stride, int ndom, unsigned long long *out, LinCtl *ctl,
+void launch_norm_ctl(unsigned long long *base, long long stride, int ndom, unsigned long long *out, LinCtl *ctl,
                      const int2 *dlev, int *act, double *hist, hipStream_t s)
 {
     if (ndom <= 0) return;

@@ -202,8 +202,9 @@ struct LinCtl {
 };
 // norm 1 reduced per domain (as launch_norm_reduce), then each solving domain's
 // control: the norm stored at hist[n * ndom + dom], n counted up; a domain that
-// stops clears the flags act[d0 .. d0 + nlev) of its levels (dlev[dom] = (d0, nlev))
-void launch_norm_ctl(const unsigned long long *base, long long stride, int ndom, unsigned long long *out, LinCtl *ctl,
+// stops clears the flags act[d0 .. d0 + nlev) of its levels (dlev[dom] = (d0, nlev)).
+// Norm 1's slots are left zero
+void launch_norm_ctl(unsigned long long *base, long long stride, int ndom, unsigned long long *out, LinCtl *ctl,
                      const int2 *dlev, int *act, double *hist, hipStream_t s);
 void launch_copy_items(const ItemCopy *jobs, int njobs, int4 *dst, hipStream_t s);
 void launch_compact_to_grid(const int64_t *c2g, int na, const double *a, const double *b, const int *c2s, double *gs,

@@ -12,7 +12,9 @@ level set, its own boundary points):
   together in mixed precision, all 50 steps, the oracle live;
 * configuration 5: served requests to completion in mixed precision, request 12
   (129^3) and request 17 (257^3) of the seeded stream, against stored oracle
-  trajectories."""
+  trajectories; and requests on the domains as stated, the plain (creased) minimum
+  of their ellipsoids, where the V-cycles converge on it (request 18 at 65^3 and
+  request 19 at 129^3), stepped beside the live oracle."""
 import os
 
 import numpy as np
@@ -143,3 +145,30 @@ def test_batch_one_member_per_size_all_steps():
             assert e <= TOL, (j, pick[m], e)
         if j % 10 == 9:
             say(f"batch members {pick} step {j + 1}/{steps}: worst err {worst:.2e}")
+
+
+@pytest.mark.parametrize("rid", [18, 19])
+def test_plain_union_request_against_oracle(rid):
+    import oracle
+    r = _request(rid)
+    n, dt = r["n"], r["dt"]
+    phi = I.ellipsoids(n, r["centres"], r["semi"], smooth=0.0)
+    H = lsmg.Hierarchy(torch.from_numpy(phi), 3, n, params=lsmg.default_params(coarsest_n=9, precision=1))
+    O = oracle.Hierarchy(phi, 3, n, coarsest_n=9, params=oracle_params(H.params))
+    info = O.level_info(0)
+    na = info["na"]
+    assert H.level_info(0)["na"] == na
+    st = _state(H, n, 3)
+    s0, c0 = I.initial_state(n, 3)
+    W = O.to_compact(0, s0, c0)
+    sb = np.ones(info["ng"])
+    for k in range(3):
+        rc, gs = st.step(dt)
+        assert rc == 0
+        orc, W, os_ = O.newton_cn_step(W, dt, sb)
+        assert orc == 0
+        G = host(st.get())
+        e = max(rel(G[:na], W[:na]), rel(G[na:], W[na:]))
+        say(f"plain union, request {rid} ({n}^3) step {k + 1}: err {e:.2e} "
+            f"newton {gs['newton_iters']}/{os_['newton_iters']} cycles {gs['vcycles']}/{os_['vcycles']}")
+        assert e <= TOL, (k, e)
