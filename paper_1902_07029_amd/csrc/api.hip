@@ -594,6 +594,35 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
         ~SegFree() { m.put(p); }
     } seg_free{H->mem, seg[0]};
     if (Lv.ni > 0 && cnt[0] + cnt[1] == 0) return fail(LSMG_EHIP, "segment construction failed on level %d", l);
+    // 3-D: pairs of consecutive segments of at most 32 positions share an item (a
+    // row crosses a 3-D domain in short runs, which would leave most lanes idle)
+    std::vector<int4> packed;
+    if (H->dim == 3 && cnt[0] + cnt[1] > 0 && Lv.Wp <= 1024) {
+        std::vector<int4> hs((size_t)(cnt[0] + cnt[1]));
+        HIPCHK(hipMemcpyAsync(hs.data(), seg[0], sizeof(int4) * hs.size(), hipMemcpyDeviceToHost, H->stream));
+        HIPCHK(hipStreamSynchronize(H->stream));
+        int pc[2] = {0, 0};
+        for (int c = 0, off = 0; c < 2; off += cnt[c], ++c) {
+            const int end = off + cnt[c];
+            for (int t = off; t < end; ++pc[c]) {
+                const int4 a = hs[(size_t)t];
+                const int la = a.w - a.z;
+                if (la <= 32 && t + 1 < end && hs[(size_t)t + 1].w - hs[(size_t)t + 1].z <= 32) {
+                    const int4 b = hs[(size_t)t + 1];
+                    const unsigned lb = (unsigned)(b.w - b.z);
+                    const unsigned u = 0x80000000u | (unsigned)a.z | ((unsigned)b.z << 10) | ((unsigned)(la - 1) << 20) |
+                                       (lb << 25);
+                    packed.push_back(make_int4(a.x, a.y, b.y, (int)u));
+                    t += 2;
+                } else {
+                    packed.push_back(a);
+                    ++t;
+                }
+            }
+        }
+        cnt[0] = pc[0];
+        cnt[1] = pc[1];
+    }
     Lv.nseg[0] = cnt[0];
     Lv.nseg[1] = cnt[1];
     Lv.nghc = (Lv.ng + kWave - 1) / kWave;
@@ -602,7 +631,9 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
     Lv.nghc4 = (Lv.ng + 3) / 4;
     const int total = cnt[0] + cnt[1] + Lv.nghc + Lv.nbandc + Lv.nghc4;
     LSMGCHK(H->alloc(&Lv.items, total));
-    if (cnt[0] + cnt[1] > 0)
+    if (!packed.empty())
+        HIPCHK(hipMemcpyAsync(Lv.items, packed.data(), sizeof(int4) * packed.size(), hipMemcpyHostToDevice, H->stream));
+    else if (cnt[0] + cnt[1] > 0)
         HIPCHK(hipMemcpyAsync(Lv.items, seg[0], sizeof(int4) * (cnt[0] + cnt[1]), hipMemcpyDeviceToDevice, H->stream));
     std::vector<int4> hv;
     for (int c = 0; c < Lv.nghc; ++c) {

@@ -51,10 +51,10 @@ __device__ __forceinline__ bool node_of(const LevelDesc<T> *D, int4 w, int lane,
 {
     const int kind = item_kind(w);
     if (kind < 2) {
-        const int p = w.z + lane;
-        if (p >= w.w) return false;
-        idx = kind * D->cs + (long long)w.y * D->Wp + p;   // segments hold inside nodes only
-        node_coords<DIM>(D->n, kind, w.y, p, i, j, k);
+        int row, p;
+        if (!seg_lane(w, lane, row, p)) return false;
+        idx = kind * D->cs + (long long)row * D->Wp + p;   // segments hold inside nodes only
+        node_coords<DIM>(D->n, kind, row, p, i, j, k);
     } else {
         const int q = w.z + lane;
         if (q >= w.w) return false;
@@ -86,11 +86,11 @@ __device__ __forceinline__ void smooth_node(const LevelDesc<T> *D, long long idx
 template <typename T, int DIM>
 __device__ __forceinline__ void smooth_elem(const LevelDesc<T> *D, int4 w, int lane, int colour)
 {
-    const int p = w.z + lane;
-    if (p >= w.w) return;
-    const long long idx = colour * D->cs + (long long)w.y * D->Wp + p;
+    int row, p;
+    if (!seg_lane(w, lane, row, p)) return;
+    const long long idx = colour * D->cs + (long long)row * D->Wp + p;
     int i, j, k;
-    node_coords<DIM>(D->n, colour, w.y, p, i, j, k);
+    node_coords<DIM>(D->n, colour, row, p, i, j, k);
     smooth_node<T, DIM>(D, idx, i, j, k, colour);
 }
 

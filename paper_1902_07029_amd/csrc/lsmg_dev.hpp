@@ -121,6 +121,27 @@ struct LevelDesc {
 __device__ __forceinline__ int item_desc(int4 w) { return w.x >> 2; }
 __device__ __forceinline__ int item_kind(int4 w) { return w.x & 3; }
 
+// row and position of lane `lane` of a segment item (kinds 0 and 1), false past
+// its end.  A plain segment holds positions [w.z, w.w) of row w.y.  A packed item
+// (w.w < 0; 3-D levels, whose rows cross the domain in short runs) holds two
+// segments of at most 32 positions: lanes 0-31 on row w.y, lanes 32-63 on row w.z,
+// with w.w = first positions (bits 0-9 and 10-19), length - 1 of the first (bits
+// 20-24) and length of the second (bits 25-30)
+__device__ __forceinline__ bool seg_lane(int4 w, int lane, int &row, int &p)
+{
+    if (w.w >= 0) {
+        p = w.z + lane;
+        row = w.y;
+        return p < w.w;
+    }
+    const unsigned u = (unsigned)w.w;
+    const int hi = lane >> 5, l = lane & 31;
+    const int len = hi ? (int)((u >> 25) & 63u) : (int)((u >> 20) & 31u) + 1;
+    p = (int)((hi ? (u >> 10) : u) & 1023u) + l;
+    row = hi ? w.z : w.y;
+    return l < len;
+}
+
 // grid coordinates of the node at (colour, row, position)
 template <int DIM>
 __device__ __forceinline__ void node_coords(int n, int colour, long long row, int p, int &i, int &j, int &k)
