@@ -903,10 +903,9 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
         // non-finite |r|) run on the device after every cycle of a chunk (the captured
         // cycle replayed back to back), and the norms come back once per chunk.  A chunk
         // ends one cycle before the longest of the solving members' previous solves would
-        // (later chunks: one cycle each), so it rarely holds a cycle no member needs; the
-        // host replays the same tests on
-        // the norms, so members run exactly the cycles they would with a round trip
-        // after each
+        // (later chunks: one cycle each), so it rarely holds a cycle no member needs.  The
+        // host replays the same tests on the norms, so members run exactly the cycles
+        // they would with a round trip after each
         std::vector<int> solve_cycles(nk, 0);
         int q = 0;
         while (q < B->p.cycles_max) {
