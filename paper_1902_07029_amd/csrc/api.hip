@@ -587,42 +587,41 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
     Level &Lv = H->L[l];
     int4 *seg[2] = {nullptr, nullptr};
     int cnt[2] = {0, 0};
-    build_segments(H->dim, Lv.type, Lv.n, Lv.Wp, Lv.rows, Lv.cs, l, seg, cnt, H->mem, H->stream);
+    // 3-D: items of two bricks of one colour (consecutive along x) holding an inside
+    // node, with the bits of their inside nodes, so that a wavefront reads whole
+    // 128-byte lines of the brick layout; bricks in storage order
+    std::vector<int4> bricks;
+    if (H->dim == 3) {
+        const int half = (Lv.n + 1) / 2, np = Lv.Wp / 8;
+        if (half > 1024 || np > 1024) return fail(LSMG_EINVAL, "3-D grids hold at most 2047 nodes per axis");
+        std::vector<uint8_t> ty((size_t)Lv.ssize);
+        HIPCHK(hipMemcpyAsync(ty.data(), Lv.type, ty.size(), hipMemcpyDeviceToHost, H->stream));
+        HIPCHK(hipStreamSynchronize(H->stream));
+        for (int c = 0; c < 2; ++c)
+            for (int kb = 0; kb < half; ++kb)
+                for (int jb = 0; jb < half; ++jb)
+                    for (int pb = 0; pb < np; pb += 2) {
+                        unsigned m[2] = {0u, 0u};
+                        for (int h = 0; h < 2 && pb + h < np; ++h) {
+                            const size_t base = (size_t)(c * Lv.cs + ((((long long)kb * half + jb) * np + pb + h) << 5));
+                            for (int in = 0; in < 32; ++in)
+                                if (ty[base + in] == kIn) m[h] |= 1u << in;
+                        }
+                        if (m[0] | m[1]) {
+                            bricks.push_back(make_int4((l << 2) | c, pb | (jb << 10) | (kb << 20), (int)m[0], (int)m[1]));
+                            ++cnt[c];
+                        }
+                    }
+        if (Lv.ni > 0 && cnt[0] + cnt[1] == 0) return fail(LSMG_EHIP, "brick lists empty on level %d", l);
+    } else {
+        build_segments(H->dim, Lv.type, Lv.n, Lv.Wp, Lv.rows, Lv.cs, l, seg, cnt, H->mem, H->stream);
+        if (Lv.ni > 0 && cnt[0] + cnt[1] == 0) return fail(LSMG_EHIP, "segment construction failed on level %d", l);
+    }
     struct SegFree {
         const DevMem &m;
         int4 *p;
         ~SegFree() { m.put(p); }
     } seg_free{H->mem, seg[0]};
-    if (Lv.ni > 0 && cnt[0] + cnt[1] == 0) return fail(LSMG_EHIP, "segment construction failed on level %d", l);
-    // 3-D: pairs of consecutive segments of at most 32 positions share an item (a
-    // row crosses a 3-D domain in short runs, which would leave most lanes idle)
-    std::vector<int4> packed;
-    if (H->dim == 3 && cnt[0] + cnt[1] > 0 && Lv.Wp <= 1024) {
-        std::vector<int4> hs((size_t)(cnt[0] + cnt[1]));
-        HIPCHK(hipMemcpyAsync(hs.data(), seg[0], sizeof(int4) * hs.size(), hipMemcpyDeviceToHost, H->stream));
-        HIPCHK(hipStreamSynchronize(H->stream));
-        int pc[2] = {0, 0};
-        for (int c = 0, off = 0; c < 2; off += cnt[c], ++c) {
-            const int end = off + cnt[c];
-            for (int t = off; t < end; ++pc[c]) {
-                const int4 a = hs[(size_t)t];
-                const int la = a.w - a.z;
-                if (la <= 32 && t + 1 < end && hs[(size_t)t + 1].w - hs[(size_t)t + 1].z <= 32) {
-                    const int4 b = hs[(size_t)t + 1];
-                    const unsigned lb = (unsigned)(b.w - b.z);
-                    const unsigned u = 0x80000000u | (unsigned)a.z | ((unsigned)b.z << 10) | ((unsigned)(la - 1) << 20) |
-                                       (lb << 25);
-                    packed.push_back(make_int4(a.x, a.y, b.y, (int)u));
-                    t += 2;
-                } else {
-                    packed.push_back(a);
-                    ++t;
-                }
-            }
-        }
-        cnt[0] = pc[0];
-        cnt[1] = pc[1];
-    }
     Lv.nseg[0] = cnt[0];
     Lv.nseg[1] = cnt[1];
     Lv.nghc = (Lv.ng + kWave - 1) / kWave;
@@ -631,8 +630,8 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
     Lv.nghc4 = (Lv.ng + 3) / 4;
     const int total = cnt[0] + cnt[1] + Lv.nghc + Lv.nbandc + Lv.nghc4;
     LSMGCHK(H->alloc(&Lv.items, total));
-    if (!packed.empty())
-        HIPCHK(hipMemcpyAsync(Lv.items, packed.data(), sizeof(int4) * packed.size(), hipMemcpyHostToDevice, H->stream));
+    if (!bricks.empty())
+        HIPCHK(hipMemcpyAsync(Lv.items, bricks.data(), sizeof(int4) * bricks.size(), hipMemcpyHostToDevice, H->stream));
     else if (cnt[0] + cnt[1] > 0)
         HIPCHK(hipMemcpyAsync(Lv.items, seg[0], sizeof(int4) * (cnt[0] + cnt[1]), hipMemcpyDeviceToDevice, H->stream));
     std::vector<int4> hv;
@@ -952,9 +951,17 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
         Level &Lv = H->L[l];
         Lv.n = nl;
         Lv.h = (g->hi - g->lo) / (nl - 1);
-        Lv.Wp = ((nl + 1) / 2 + 15) / 16 * 16;
         Lv.rows = dim == 2 ? nl : (long long)nl * nl;
-        Lv.cs = Lv.rows * Lv.Wp;
+        if (dim == 2) {
+            // rows of positions padded to 128 bytes of doubles
+            Lv.Wp = ((nl + 1) / 2 + 15) / 16 * 16;
+            Lv.cs = Lv.rows * Lv.Wp;
+        } else {
+            // bricks of 8 positions x 2 rows x 2 planes
+            const long long half = (nl + 1) / 2;
+            Lv.Wp = (int)((half + 7) / 8 * 8);
+            Lv.cs = 4 * half * half * Lv.Wp;
+        }
         Lv.ssize = 2 * Lv.cs;
         if (Lv.ssize > 0x7fffffffLL) return fail(LSMG_EINVAL, "grid too large for 32-bit storage indices");
         nl = (nl - 1) / 2 + 1;
@@ -1328,9 +1335,9 @@ lsmg_status lsmg_estimate_bytes(const lsmg_grid *grid, const lsmg_params *params
     size_t full = 0, ss0 = 0;
     int nl = grid->n;
     for (int l = 0; l < 16; ++l) {
-        const long long Wp = ((nl + 1) / 2 + 15) / 16 * 16;
-        const long long rows = grid->dim == 2 ? nl : (long long)nl * nl;
-        const size_t ss = (size_t)(2 * rows * Wp);
+        const long long half = (nl + 1) / 2;
+        const size_t ss = grid->dim == 2 ? (size_t)(2 * (long long)nl * ((half + 15) / 16 * 16))
+                                         : (size_t)(2 * 4 * half * half * ((half + 7) / 8 * 8));
         if (l == 0) ss0 = ss;
         // 2-D: a second copy of the corrections for the fused sweeps
         const size_t nv = grid->dim == 2 ? 10 : 8;

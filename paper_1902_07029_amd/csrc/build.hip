@@ -56,7 +56,7 @@ __global__ void k_classify(int dim, const double *__restrict__ phi, int n, int W
         }
     }
     const uint8_t t = inside ? kIn : (ghost ? kGhost : kOut);
-    type[sidx(n, Wp, cs, id[0], id[1], id[2])] = t;
+    type[sidx(dim, n, Wp, cs, id[0], id[1], id[2])] = t;
     fin[g] = inside;
     fgh[g] = ghost;
 }
@@ -153,7 +153,7 @@ __global__ void k_c2s(int dim, const int64_t *__restrict__ c2g, int na, int n, i
     if (r >= na) return;
     const long long g = c2g[r];
     const int i = (int)(g % n), j = (int)((g / n) % n), k = dim == 3 ? (int)(g / ((long long)n * n)) : 0;
-    const long long q = sidx(n, Wp, cs, i, j, k);
+    const long long q = sidx(dim, n, Wp, cs, i, j, k);
     c2s[r] = (int)q;
     cmap[q] = r;
 }
@@ -163,13 +163,31 @@ __global__ void k_c2s(int dim, const int64_t *__restrict__ c2g, int na, int n, i
 // consecutive inside positions, cut into pieces of at most 64, so a segment
 // holds inside nodes only
 // ---------------------------------------------------------------------------
-__global__ void k_seg_count(const uint8_t *__restrict__ type, long long rows, int Wp, long long cs,
+// type of position p of a row of one colour
+struct RowType {
+    const uint8_t *type;
+    int dim, n, Wp, j, k, colour;
+    long long cs, base;
+    __device__ RowType(const uint8_t *t, int dim_, int n_, int Wp_, long long cs_, int colour_, long long row)
+        : type(t), dim(dim_), n(n_), Wp(Wp_), colour(colour_), cs(cs_)
+    {
+        k = dim == 3 ? (int)(row / n) : 0;
+        j = (int)(row - (long long)k * n);
+        base = colour * cs + row * Wp;
+    }
+    __device__ uint8_t operator[](int p) const
+    {
+        return dim == 3 ? type[sidx3(n, Wp, cs, colour, p, j, k)] : type[base + p];
+    }
+};
+
+__global__ void k_seg_count(const uint8_t *__restrict__ type, int dim, int n, long long rows, int Wp, long long cs,
                             int64_t *__restrict__ cnt)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * rows) return;
     const long long colour = t / rows, row = t - colour * rows;
-    const uint8_t *rp = type + colour * cs + row * Wp;
+    const RowType rp(type, dim, n, Wp, cs, (int)colour, row);
     long long c = 0;
     int p = 0;
     while (p < Wp) {
@@ -182,13 +200,13 @@ __global__ void k_seg_count(const uint8_t *__restrict__ type, long long rows, in
     cnt[t] = c;
 }
 
-__global__ void k_seg_emit(const uint8_t *__restrict__ type, long long rows, int Wp, long long cs,
+__global__ void k_seg_emit(const uint8_t *__restrict__ type, int dim, int n, long long rows, int Wp, long long cs,
                            const int64_t *__restrict__ offs, int desc, int4 *__restrict__ items)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * rows) return;
     const long long colour = t / rows, row = t - colour * rows;
-    const uint8_t *rp = type + colour * cs + row * Wp;
+    const RowType rp(type, dim, n, Wp, cs, (int)colour, row);
     long long o = offs[t];
     int p = 0;
     while (p < Wp) {
@@ -252,14 +270,12 @@ int build_inside_lists(int dim, const int64_t *c2g, int ni, int n, int *out, int
 void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows, long long cs, int desc,
                     int4 **out_items, int *out_count, const DevMem &mem, hipStream_t s)
 {
-    (void)dim;
-    (void)n;
     out_items[0] = out_items[1] = nullptr;
     out_count[0] = out_count[1] = 0;
     int64_t *cnt = (int64_t *)mem.get(sizeof(int64_t) * (2 * rows + 1));
     if (!cnt) return;
     const unsigned nb = (unsigned)((2 * rows + 255) / 256);
-    k_seg_count<<<nb, 256, 0, s>>>(type, rows, Wp, cs, cnt);
+    k_seg_count<<<nb, 256, 0, s>>>(type, dim, n, rows, Wp, cs, cnt);
     // per-colour totals come from the exclusive scan at rows and 2 rows
     k_scan_single<<<1, 1024, 0, s>>>(cnt, 2 * rows);
     int64_t h[2] = {0, 0};
@@ -269,7 +285,7 @@ void build_segments(int dim, const uint8_t *type, int n, int Wp, long long rows,
     const long long total = h[1];
     int4 *items = total > 0 ? (int4 *)mem.get(sizeof(int4) * total) : nullptr;
     if (items) {
-        k_seg_emit<<<nb, 256, 0, s>>>(type, rows, Wp, cs, cnt, desc, items);
+        k_seg_emit<<<nb, 256, 0, s>>>(type, dim, n, rows, Wp, cs, cnt, desc, items);
         (void)hipStreamSynchronize(s);
         out_items[0] = items;
         out_items[1] = items + h[0];
@@ -456,7 +472,7 @@ __device__ bool axis_row(const double *phi, const uint8_t *type, long long g, co
             if (q2) {
                 int id[3] = {gi[0], gi[1], gi[2]};
                 id[a] = k2;
-                act2 = type[sidx(n, Wp, cs, id[0], id[1], id[2])] != kOut;
+                act2 = type[sidx(DIM, n, Wp, cs, id[0], id[1], id[2])] != kOut;
             }
             const double wg = act2 ? lag2(0, thi) : lag1(0, thi);
             if (wg > bw) {
@@ -480,7 +496,7 @@ __device__ bool axis_row(const double *phi, const uint8_t *type, long long g, co
         }
         oob[k] = o;
         stl[k] = o ? g0 : (long long)id[0] + (long long)n * ((long long)id[1] + (long long)n * id[2]);
-        sts[k] = o ? gs : sidx(n, Wp, cs, id[0], id[1], id[2]);
+        sts[k] = o ? gs : sidx(DIM, n, Wp, cs, id[0], id[1], id[2]);
     }
     for (int a = 0; a < DIM; ++a) {
         Bp[a] = lo + (double)gi[a] * h;
@@ -550,7 +566,7 @@ __global__ void k_ghost_geometry(int level, int bc, const double *__restrict__ p
     long long sts[NST];
     bool oob[NST];
     bool any_oob = false;
-    const long long gs = sidx(n, Wp, cs, gi[0], gi[1], gi[2]);
+    const long long gs = sidx(DIM, n, Wp, cs, gi[0], gi[1], gi[2]);
     for (int k = 0; k < NST; ++k) {
         int kk = k, id[3] = {0, 0, 0};
         bool o = false;
@@ -562,7 +578,7 @@ __global__ void k_ghost_geometry(int level, int bc, const double *__restrict__ p
         oob[k] = o;
         any_oob |= o;
         stl[k] = o ? g : (long long)id[0] + (long long)n * ((long long)id[1] + (long long)n * id[2]);
-        sts[k] = o ? gs : sidx(n, Wp, cs, id[0], id[1], id[2]);
+        sts[k] = o ? gs : sidx(DIM, n, Wp, cs, id[0], id[1], id[2]);
     }
     // boundary point
     double Bp[3] = {G[0], G[1], G[2]};
@@ -682,7 +698,7 @@ __global__ void k_band_mark(int dim, const int64_t *__restrict__ c2g_cg, int ngc
             if (id[a] < 0 || id[a] >= nf) in = false;
         }
         if (!in) continue;
-        if (ftype[sidx(nf, fWp, fcs, id[0], id[1], id[2])] == kOut)
+        if (ftype[sidx(dim, nf, fWp, fcs, id[0], id[1], id[2])] == kOut)
             flag[(long long)id[0] + (long long)nf * ((long long)id[1] + (long long)nf * id[2])] = 1;
     }
 }
@@ -715,7 +731,7 @@ __global__ void k_band_geometry(int dim, const double *__restrict__ phi, const i
     double len2 = 0.0;
     for (int a = 0; a < dim; ++a) len2 += nt[a] * nt[a];
     const double len = sqrt(len2);
-    b_idx[b] = (int)sidx(n, Wp, cs, gi[0], gi[1], gi[2]);
+    b_idx[b] = (int)sidx(dim, n, Wp, cs, gi[0], gi[1], gi[2]);
     sa = 1;
     for (int a = 0; a < dim; ++a) {
         const double na = len > 0.0 ? nt[a] / len : 0.0;
@@ -727,7 +743,7 @@ __global__ void k_band_geometry(int dim, const double *__restrict__ phi, const i
         up_w[a * nb + b] = 0.0;
         if (up[a] >= 0 && up[a] < n) {
             const long long gu = g - ma * sa;
-            const long long su = sidx(n, Wp, cs, up[0], up[1], up[2]);
+            const long long su = sidx(dim, n, Wp, cs, up[0], up[1], up[2]);
             const int bid = bandid[gu];
             if (type[su] == kGhost || bid >= 0) {
                 up_s[a * nb + b] = (int)su;

@@ -51,10 +51,12 @@ __device__ __forceinline__ bool node_of(const LevelDesc<T> *D, int4 w, int lane,
 {
     const int kind = item_kind(w);
     if (kind < 2) {
+        // segments (2-D) and bricks (3-D) hold inside nodes only
+        if (DIM == 3) return brick_lane(D->n, D->Wp, D->cs, kind, w, lane, idx, i, j, k);
         int row, p;
         if (!seg_lane(w, lane, row, p)) return false;
-        idx = kind * D->cs + (long long)row * D->Wp + p;   // segments hold inside nodes only
         node_coords<DIM>(D->n, kind, row, p, i, j, k);
+        idx = sidx_at<DIM>(D->n, D->Wp, D->cs, kind, p, j, k);
     } else {
         const int q = w.z + lane;
         if (q >= w.w) return false;
@@ -75,7 +77,7 @@ template <typename T, int DIM>
 __device__ __forceinline__ void smooth_node(const LevelDesc<T> *D, long long idx, int i, int j, int k, int colour)
 {
     long long nb[2 * DIM];
-    neighbours<DIM>(D->n, D->Wp, D->cs, colour, (long long)j + (long long)D->n * k, i, i >> 1, nb);
+    neighbours<DIM>(D->n, D->Wp, D->cs, colour, i, j, k, nb);
     const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
     T xs, xc;
     block_solve<T>(R, D->rhs_s[idx], D->rhs_c[idx], xs, xc);
@@ -86,11 +88,16 @@ __device__ __forceinline__ void smooth_node(const LevelDesc<T> *D, long long idx
 template <typename T, int DIM>
 __device__ __forceinline__ void smooth_elem(const LevelDesc<T> *D, int4 w, int lane, int colour)
 {
-    int row, p;
-    if (!seg_lane(w, lane, row, p)) return;
-    const long long idx = colour * D->cs + (long long)row * D->Wp + p;
+    long long idx;
     int i, j, k;
-    node_coords<DIM>(D->n, colour, row, p, i, j, k);
+    if (DIM == 3) {
+        if (!brick_lane(D->n, D->Wp, D->cs, colour, w, lane, idx, i, j, k)) return;
+    } else {
+        int row, p;
+        if (!seg_lane(w, lane, row, p)) return;
+        node_coords<DIM>(D->n, colour, row, p, i, j, k);
+        idx = sidx_at<DIM>(D->n, D->Wp, D->cs, colour, p, j, k);
+    }
     smooth_node<T, DIM>(D, idx, i, j, k, colour);
 }
 
@@ -196,7 +203,7 @@ __device__ __forceinline__ unsigned long long defect_inside(const LevelDesc<T> *
                                                             const LevelDesc<float> *E)
 {
     long long nb[2 * DIM];
-    neighbours<DIM>(D->n, D->Wp, D->cs, (i + j + k) & 1, (long long)j + (long long)D->n * k, i, i >> 1, nb);
+    neighbours<DIM>(D->n, D->Wp, D->cs, (i + j + k) & 1, i, j, k, nb);
     const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
     T rs, rc;
     inside_defect_vals<T>(R, D->rhs_s[idx], D->rhs_c[idx], D->x_s[idx], D->x_c[idx], rs, rc);
@@ -258,7 +265,7 @@ __device__ __forceinline__ void apply_J_elem(const LevelDesc<T> *D, int4 w, int 
     if (!node_of<T, DIM>(D, w, lane, idx, i, j, k)) return;
     if (item_kind(w) < 2) {
         long long nb[2 * DIM];
-        neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), (long long)j + (long long)D->n * k, i, i >> 1, nb);
+        neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), i, j, k, nb);
         const InsideRow<T> R = inside_row<T, DIM>(D, idx, nb);
         const T xs = D->x_s[idx], xc = D->x_c[idx];
         D->r_s[idx] = R.ss_d * xs + R.sc_d * xc + R.off_s;
@@ -319,7 +326,7 @@ __device__ __forceinline__ void restrict_node(const LevelDesc<T> *C, long long c
     const int fn = F->n, fWp = F->Wp;
     const long long fcs = F->cs;
     const int fc0 = 2 * ci, fc1 = 2 * cj, fc2 = 2 * ck;
-    const long long fcentre = sidx(fn, fWp, fcs, fc0, fc1, fc2);
+    const long long fcentre = sidx(DIM, fn, fWp, fcs, fc0, fc1, fc2);
     // gather the 3^d fine neighbourhood (out-of-box entries read the centre with type "excluded")
     uint8_t ex[NST], act[NST];
     T rs[NST], rc[NST];
@@ -327,7 +334,7 @@ __device__ __forceinline__ void restrict_node(const LevelDesc<T> *C, long long c
     for (int kk = 0; kk < NST; ++kk) {
         const int id0 = fc0 + kk % 3 - 1, id1 = fc1 + (kk / 3) % 3 - 1, id2 = DIM == 3 ? fc2 + kk / 9 - 1 : 0;
         const bool inb = id0 >= 0 && id0 < fn && id1 >= 0 && id1 < fn && (DIM == 2 || (id2 >= 0 && id2 < fn));
-        const long long q = inb ? sidx(fn, fWp, fcs, id0, id1, id2) : fcentre;
+        const long long q = inb ? sidx(DIM, fn, fWp, fcs, id0, id1, id2) : fcentre;
         const uint8_t t = F->type[q];
         // boundary rows (INSIDE false) also need the extension flag; it is combined
         // without short-circuit so that its load is issued with the type's
@@ -387,7 +394,7 @@ __device__ __forceinline__ void prolong_node(const LevelDesc<T> *F, long long id
                 wk *= T(0.5);
             }
         }
-        cq[corner] = sidx(C->n, C->Wp, C->cs, id[0], id[1], id[2]);
+        cq[corner] = sidx(DIM, C->n, C->Wp, C->cs, id[0], id[1], id[2]);
         wq[corner] = wk;
         use[corner] = !skip;
     }
@@ -442,7 +449,7 @@ __device__ __forceinline__ void inject_elem(const LevelDesc<T> *C, int4 w, int l
     const int fc[3] = {2 * ci[0], 2 * ci[1], 2 * ci[2]};
     if (item_kind(w) < 2) {
         // a coarse inside node's fine centre has the same level-set value: inside
-        const long long fq = sidx(fn, F->Wp, F->cs, fc[0], fc[1], fc[2]);
+        const long long fq = sidx(DIM, fn, F->Wp, F->cs, fc[0], fc[1], fc[2]);
         C->s[cidx] = F->s[fq];
         C->c[cidx] = F->c[fq];
         return;
@@ -464,8 +471,8 @@ __device__ __forceinline__ void inject_elem(const LevelDesc<T> *C, int4 w, int l
             id[a] = fc[a] + (a < DIM ? d[a] : 0);
             if (a < DIM && (id[a] < 0 || id[a] >= fn)) in = false;
         }
-        const long long q = in ? sidx(fn, F->Wp, F->cs, id[0], id[1], id[2])
-                               : sidx(fn, F->Wp, F->cs, fc[0], fc[1], fc[2]);
+        const long long q = in ? sidx(DIM, fn, F->Wp, F->cs, id[0], id[1], id[2])
+                               : sidx(DIM, fn, F->Wp, F->cs, fc[0], fc[1], fc[2]);
         inb[kk] = in;
         t[kk] = F->type[q];
         sv[kk] = F->s[q];
@@ -606,7 +613,7 @@ __global__ __launch_bounds__(kRbThreads) void k_smooth_rb(const LevelDesc<T> *__
         const long long idx = valid ? (long long)y * Wp + p : 0;
         long long nb[4];
         if (interior) {
-            neighbours<2>(n, Wp, cs, 0, y, i, p, nb);
+            neighbours<2>(n, Wp, cs, 0, i, y, 0, nb);
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) nb[e] = idx;
@@ -1046,7 +1053,7 @@ __device__ __forceinline__ void tail_node(const LevelDesc<T> *D, const TailLevel
                                           long long &idx, int &i, int &j, int &k)
 {
     unpack_ijk(tail_ijk<T, STAGE>(D, TL, si, t), i, j, k);
-    idx = sidx(D->n, D->Wp, D->cs, i, j, k);
+    idx = sidx(D->dim, D->n, D->Wp, D->cs, i, j, k);
 }
 
 template <typename T, bool STAGE>
@@ -1314,7 +1321,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_explicit_half(const LevelDesc<dou
     const int na = D->na;
     if (item_kind(w) < 2) {
         long long nb[2 * DIM];
-        neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), (long long)j + (long long)D->n * k, i, i >> 1, nb);
+        neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), i, j, k, nb);
         double bsv = (D->alpha * cn[idx] + D->beta) * sn[idx] * D->dt_inv + 0.5 * Ls_h<DIM>(D, sn, cn, idx, nb);
         if (D->fn) bsv += 0.5 * (D->fn[r] + D->fnp1[r]);
         D->bs[idx] = bsv;
@@ -1344,7 +1351,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_residual(const LevelDesc<double> 
         double fs;
         if (item_kind(w) < 2) {
             long long nb[2 * DIM];
-            neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), (long long)j + (long long)D->n * k, i, i >> 1, nb);
+            neighbours<DIM>(D->n, D->Wp, D->cs, item_kind(w), i, j, k, nb);
             fs = (D->alpha * c[idx] + D->beta) * s[idx] * D->dt_inv - 0.5 * Ls_h<DIM>(D, s, c, idx, nb) - D->bs[idx];
         } else {
             const int q = w.z + lane;
@@ -1618,14 +1625,10 @@ __global__ __launch_bounds__(1024) void k_coarse_invert(const LevelDesc<double> 
         const long long idx = c2s[r];
         double *Rs = M + r * N, *Rsc = Jsc + (long long)r * N;
         if (r < ni) {
-            const long long colour = idx / D->cs;
-            const long long rem = idx - colour * D->cs;
-            const long long row = rem / D->Wp;
-            const int p = (int)(rem - row * D->Wp);
             int i, j, k;
-            node_coords<DIM>(D->n, (int)colour, row, p, i, j, k);
+            sidx_node<DIM>(D->n, D->Wp, D->cs, idx, i, j, k);
             long long nb[2 * DIM];
-            neighbours<DIM>(D->n, D->Wp, D->cs, (int)colour, row, i, p, nb);
+            neighbours<DIM>(D->n, D->Wp, D->cs, (i + j + k) & 1, i, j, k, nb);
             const double sr = D->s[idx], cr = D->c[idx];
             const double al = D->alpha, be = D->beta, kap = D->kap;
             const double phr = al * cr + be;
@@ -1853,14 +1856,10 @@ __global__ __launch_bounds__(1024) void k_coarse_invert_small(const LevelDesc<do
     if (tid < ni) {
         const int r = tid;
         const long long idx = c2s[r];
-        const long long colour = idx / D->cs;
-        const long long rem = idx - colour * D->cs;
-        const long long row = rem / D->Wp;
-        const int p = (int)(rem - row * D->Wp);
         int i, j, k;
-        node_coords<DIM>(D->n, (int)colour, row, p, i, j, k);
+        sidx_node<DIM>(D->n, D->Wp, D->cs, idx, i, j, k);
         long long nb[2 * DIM];
-        neighbours<DIM>(D->n, D->Wp, D->cs, (int)colour, row, i, p, nb);
+        neighbours<DIM>(D->n, D->Wp, D->cs, (i + j + k) & 1, i, j, k, nb);
         double se[2 * DIM], ce[2 * DIM];
         int q[2 * DIM];
 #pragma unroll

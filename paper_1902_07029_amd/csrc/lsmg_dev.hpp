@@ -2,16 +2,23 @@
 //
 // Storage of a level: every per-node array is a full grid held in red/black
 // split form.  Node (i, j[, k]) has colour c = (i + j + k) & 1, row
-// r = j + n k and position p = i >> 1; its storage index is
-//     c * cs + r * Wp + p,   cs = rows * Wp,  rows = n^(dim-1),
-// with Wp >= (n + 1) / 2 rounded up to 16 doubles (128 bytes).  A red or black
-// half-sweep therefore reads and writes contiguous memory, and the four (six)
-// axis neighbours of a node are the other colour in the same row (x) or at the
-// same position in the rows above and below (y, z).
+// r = j + n k and position p = i >> 1.
+//   2-D: its storage index is c * cs + r * Wp + p, cs = n * Wp, with Wp >=
+//   (n + 1) / 2 rounded up to 16 doubles (128 bytes).  A red or black half-sweep
+//   reads and writes contiguous memory, and the four axis neighbours of a node
+//   are the other colour in the same row (x) or at the same position in the rows
+//   above and below (y).
+//   3-D: each colour is stored in bricks of 8 positions x 2 rows (y) x 2 planes
+//   (z), 32 consecutive values (one 128-byte line in FP32, two in FP64), bricks
+//   in (position, y, z) order: a run of inside nodes along a row then shares its
+//   lines with the runs of the next row and plane instead of ending in partial
+//   lines of its own (a row crosses a 3-D domain in short runs).  Wp is the
+//   position count rounded up to 8, and cs = 4 ((n + 1) / 2)^2 Wp.
 //
 // Work is described by lists of int4 work items, one 64-lane wavefront per
 // item: x = (descriptor index << 2) | kind, then
-//   kind 0 / 1: inside nodes of colour 0 / 1 in row y, positions [z, w);
+//   kind 0 / 1: inside nodes of colour 0 / 1: in 2-D row y, positions [z, w);
+//   in 3-D two consecutive bricks of the colour (see brick_lane);
 //   kind 2: ghosts [z, w) of the level's ghost list;
 //   kind 3: band nodes [z, w) of the level's boundary band.
 // Descriptors of one hierarchy are contiguous by level (finest first), so the
@@ -121,25 +128,34 @@ struct LevelDesc {
 __device__ __forceinline__ int item_desc(int4 w) { return w.x >> 2; }
 __device__ __forceinline__ int item_kind(int4 w) { return w.x & 3; }
 
-// row and position of lane `lane` of a segment item (kinds 0 and 1), false past
-// its end.  A plain segment holds positions [w.z, w.w) of row w.y.  A packed item
-// (w.w < 0; 3-D levels, whose rows cross the domain in short runs) holds two
-// segments of at most 32 positions: lanes 0-31 on row w.y, lanes 32-63 on row w.z,
-// with w.w = first positions (bits 0-9 and 10-19), length - 1 of the first (bits
-// 20-24) and length of the second (bits 25-30)
+// row and position of lane `lane` of a 2-D segment item (kinds 0 and 1): positions
+// [w.z, w.w) of row w.y; false past its end
 __device__ __forceinline__ bool seg_lane(int4 w, int lane, int &row, int &p)
 {
-    if (w.w >= 0) {
-        p = w.z + lane;
-        row = w.y;
-        return p < w.w;
-    }
-    const unsigned u = (unsigned)w.w;
-    const int hi = lane >> 5, l = lane & 31;
-    const int len = hi ? (int)((u >> 25) & 63u) : (int)((u >> 20) & 31u) + 1;
-    p = (int)((hi ? (u >> 10) : u) & 1023u) + l;
-    row = hi ? w.z : w.y;
-    return l < len;
+    p = w.z + lane;
+    row = w.y;
+    return p < w.w;
+}
+
+// node of lane `lane` of a 3-D brick item (kinds 0 and 1 = colour): two bricks
+// of the colour, consecutive along x, lanes 0-31 the first and 32-63 the second,
+// lane l & 31 its value (l & 7) + 8 ((l >> 3) & 1) + 16 (l >> 4) at position
+// 8 pb + (l & 7), y index 2 jb + ((l >> 3) & 1), z index 2 kb + (l >> 4).
+// w.y = pb | jb << 10 | kb << 20 of the first brick; w.z, w.w: the bits of the
+// inside nodes of each brick (false for the other lanes)
+__host__ __device__ __forceinline__ bool brick_lane(int n, int Wp, long long cs, int colour, int4 w, int lane, long long &idx,
+                                           int &i, int &j, int &k)
+{
+    const int hi = lane >> 5, in = lane & 31;
+    const unsigned mask = (unsigned)(hi ? w.w : w.z);
+    const int pb = (w.y & 1023) + hi, jb = (w.y >> 10) & 1023, kb = (w.y >> 20) & 1023;
+    const long long brick = ((long long)kb * ((n + 1) >> 1) + jb) * (Wp >> 3) + pb;
+    idx = colour * cs + (brick << 5) + in;
+    const int p = pb * 8 + (in & 7);
+    j = jb * 2 + ((in >> 3) & 1);
+    k = kb * 2 + (in >> 4);
+    i = 2 * p + ((colour + j + k) & 1);
+    return (mask >> in) & 1u;
 }
 
 // grid coordinates of the node at (colour, row, position)
@@ -164,27 +180,71 @@ __device__ __forceinline__ void unpack_ijk(int v, int &i, int &j, int &k)
     k = (v >> 22) & 1023;
 }
 
-__device__ __forceinline__ long long sidx(int n, int Wp, long long cs, int i, int j, int k)
+// 3-D storage index of (colour, position p, y index j, z index k)
+__host__ __device__ __forceinline__ long long sidx3(int n, int Wp, long long cs, int colour, int p, int j, int k)
 {
-    const int colour = (i + j + k) & 1;
-    return colour * cs + ((long long)j + (long long)n * k) * Wp + (i >> 1);
+    const long long brick = ((long long)(k >> 1) * ((n + 1) >> 1) + (j >> 1)) * (Wp >> 3) + (p >> 3);
+    return colour * cs + (brick << 5) + ((((k & 1) << 1) | (j & 1)) << 3) + (p & 7);
 }
 
-// storage indices of the axis neighbours of node (i, row) with colour `colour`,
-// ordered x-, x+, y-, y+[, z-, z+]
+// storage index of node (colour, p, j, k) on a level of dimension DIM
 template <int DIM>
-__device__ __forceinline__ void neighbours(int n, int Wp, long long cs, int colour, long long row, int i, int p,
-                                           long long *nb)
+__host__ __device__ __forceinline__ long long sidx_at(int n, int Wp, long long cs, int colour, int p, int j, int k)
 {
-    const long long ob = (colour ^ 1) * cs + row * Wp;
+    if (DIM == 3) return sidx3(n, Wp, cs, colour, p, j, k);
+    return colour * cs + (long long)j * Wp + p;
+}
+
+// storage index of grid node (i, j, k) (k = 0 in 2-D)
+__host__ __device__ __forceinline__ long long sidx(int dim, int n, int Wp, long long cs, int i, int j, int k)
+{
+    const int colour = (i + j + k) & 1;
+    return dim == 3 ? sidx3(n, Wp, cs, colour, i >> 1, j, k) : colour * cs + (long long)j * Wp + (i >> 1);
+}
+
+// grid node (i, j, k) of storage index idx
+template <int DIM>
+__host__ __device__ __forceinline__ void sidx_node(int n, int Wp, long long cs, long long idx, int &i, int &j, int &k)
+{
+    const int colour = (int)(idx / cs);
+    const long long rem = idx - colour * cs;
+    int p;
+    if (DIM == 3) {
+        const long long brick = rem >> 5;
+        const int in = (int)(rem & 31), np = Wp >> 3, nj = (n + 1) >> 1;
+        const long long jk = brick / np;
+        p = (int)(brick - jk * np) * 8 + (in & 7);
+        const int kb = (int)(jk / nj);
+        j = (int)(jk - (long long)kb * nj) * 2 + ((in >> 3) & 1);
+        k = kb * 2 + (in >> 4);
+    } else {
+        j = (int)(rem / Wp);
+        p = (int)(rem - (long long)j * Wp);
+        k = 0;
+    }
+    i = 2 * p + ((colour + j + k) & 1);
+}
+
+// storage indices of the axis neighbours of node (i, j, k) of colour `colour`
+// (an inside node: never on the box edge), ordered x-, x+, y-, y+[, z-, z+]
+template <int DIM>
+__device__ __forceinline__ void neighbours(int n, int Wp, long long cs, int colour, int i, int j, int k, long long *nb)
+{
+    const int o = colour ^ 1, p = i >> 1;
+    if (DIM == 3) {
+        nb[0] = sidx3(n, Wp, cs, o, (i - 1) >> 1, j, k);
+        nb[1] = sidx3(n, Wp, cs, o, (i + 1) >> 1, j, k);
+        nb[2] = sidx3(n, Wp, cs, o, p, j - 1, k);
+        nb[3] = sidx3(n, Wp, cs, o, p, j + 1, k);
+        nb[4] = sidx3(n, Wp, cs, o, p, j, k - 1);
+        nb[5] = sidx3(n, Wp, cs, o, p, j, k + 1);
+        return;
+    }
+    const long long ob = o * cs + (long long)j * Wp;
     nb[0] = ob + ((i - 1) >> 1);
     nb[1] = ob + ((i + 1) >> 1);
     nb[2] = ob - Wp + p;
     nb[3] = ob + Wp + p;
-    if (DIM == 3) {
-        nb[4] = ob - (long long)n * Wp + p;
-        nb[5] = ob + (long long)n * Wp + p;
-    }
 }
 
 // max of non-negative doubles as ordered bit patterns; NaN (any payload, sign

@@ -54,10 +54,9 @@ void unpack(int v, int &i, int &j, int &k)
     k = (v >> 22) & 1023;
 }
 
-long long sidx_h(const Level &L, int i, int j, int k)
+long long sidx_h(int dim, const Level &L, int i, int j, int k)
 {
-    const int colour = (i + j + k) & 1;
-    return colour * L.cs + ((long long)j + (long long)L.n * k) * L.Wp + (i >> 1);
+    return sidx(dim, L.n, L.Wp, L.cs, i, j, k);
 }
 
 }  // namespace
@@ -89,7 +88,7 @@ lsmg_status build_tail_tables(lsmg_hierarchy *H)
         for (int t = 0; t < Lv.na; ++t) {
             int i, j, k;
             unpack(h.ijk[t], i, j, k);
-            h.inv[(size_t)sidx_h(Lv, i, j, k)] = t;
+            h.inv[(size_t)sidx_h(dim, Lv, i, j, k)] = t;
         }
         h.binv.assign((size_t)Lv.ssize, -1);
         for (int b = 0; b < Lv.nb; ++b) h.binv[(size_t)h.bidx[b]] = b;
@@ -117,12 +116,11 @@ lsmg_status build_tail_tables(lsmg_hierarchy *H)
             for (int t = 0; t < nin; ++t) {
                 int i, j, k;
                 unpack(h.ijk[t], i, j, k);
-                const int colour = (i + j + k) & 1;
-                const long long row = (long long)j + (long long)Lv.n * k;
-                const long long ob = (colour ^ 1) * Lv.cs + row * Lv.Wp;
-                const int p = i >> 1;
-                long long nb[6] = {ob + ((i - 1) >> 1), ob + ((i + 1) >> 1), ob - Lv.Wp + p, ob + Lv.Wp + p,
-                                   ob - (long long)Lv.n * Lv.Wp + p, ob + (long long)Lv.n * Lv.Wp + p};
+                // axis neighbours: inside nodes never lie on the box edge
+                const long long nb[6] = {sidx_h(dim, Lv, i - 1, j, k), sidx_h(dim, Lv, i + 1, j, k),
+                                         sidx_h(dim, Lv, i, j - 1, k), sidx_h(dim, Lv, i, j + 1, k),
+                                         dim == 3 ? sidx_h(dim, Lv, i, j, k - 1) : 0,
+                                         dim == 3 ? sidx_h(dim, Lv, i, j, k + 1) : 0};
                 for (int e = 0; e < 2 * dim; ++e) {
                     const int v = h.inv[(size_t)nb[e]];
                     if (!fits(v)) return LSMG_OK;
@@ -175,7 +173,7 @@ lsmg_status build_tail_tables(lsmg_hierarchy *H)
                         tab.push_back(kSkip);
                         continue;
                     }
-                    const long long q = sidx_h(Cv, id[0], id[1], id[2]);
+                    const long long q = sidx_h(dim, Cv, id[0], id[1], id[2]);
                     if (hc.type[(size_t)q] == kOut) {
                         tab.push_back(kOff);
                         continue;
@@ -191,13 +189,13 @@ lsmg_status build_tail_tables(lsmg_hierarchy *H)
             for (int tc = 0; tc < Cv.na; ++tc) {
                 int c[3];
                 unpack(hc.ijk[tc], c[0], c[1], c[2]);
-                const long long fcentre = sidx_h(Lv, 2 * c[0], 2 * c[1], 2 * c[2]);
+                const long long fcentre = sidx_h(dim, Lv, 2 * c[0], 2 * c[1], 2 * c[2]);
                 for (int kk = 0; kk < nst; ++kk) {
                     const int id0 = 2 * c[0] + kk % 3 - 1, id1 = 2 * c[1] + (kk / 3) % 3 - 1,
                               id2 = dim == 3 ? 2 * c[2] + kk / 9 - 1 : 0;
                     const bool inb = id0 >= 0 && id0 < Lv.n && id1 >= 0 && id1 < Lv.n &&
                                      (dim == 2 || (id2 >= 0 && id2 < Lv.n));
-                    const long long q = inb ? sidx_h(Lv, id0, id1, id2) : fcentre;
+                    const long long q = inb ? sidx_h(dim, Lv, id0, id1, id2) : fcentre;
                     const uint8_t ty = h.type[(size_t)q], ex = h.ext[(size_t)q];
                     int slot;
                     if (ty != kOut) slot = h.inv[(size_t)q];
@@ -550,7 +548,7 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const LevelDesc<T> *__restric
                 const LevelDesc<T> *D = base + l;
                 int i, j, k;
                 unpack_ijk(code[m], i, j, k);
-                const long long q = sidx(D->n, D->Wp, D->cs, i, j, k);
+                const long long q = sidx(DIM, D->n, D->Wp, D->cs, i, j, k);
                 if (m == 0) q0 = q;
                 sv[m] = D->s[q];
                 cv[m] = D->c[q];
@@ -584,7 +582,7 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const LevelDesc<T> *__restric
             for (int t = threadIdx.x; t < na; t += blockDim.x) {
                 int i, j, k;
                 unpack_ijk(t < nin ? TL.in_ijk[t] : D->g_ijk[t - nin], i, j, k);
-                const long long q = sidx(D->n, D->Wp, D->cs, i, j, k);
+                const long long q = sidx(DIM, D->n, D->Wp, D->cs, i, j, k);
                 b[t] = D->s[q];
                 b[na + t] = D->c[q];
                 if (l == A.l0) {
@@ -650,7 +648,7 @@ __global__ __launch_bounds__(1024) void k_tail_lds(const LevelDesc<T> *__restric
         for (int t = threadIdx.x; t < na; t += blockDim.x) {
             int i, j, k;
             unpack_ijk(t < nin ? TL.in_ijk[t] : D->g_ijk[t - nin], i, j, k);
-            const long long q = sidx(D->n, D->Wp, D->cs, i, j, k);
+            const long long q = sidx(DIM, D->n, D->Wp, D->cs, i, j, k);
             D->x_s[q] = b[2 * na + t];
             D->x_c[q] = b[3 * na + t];
         }
