@@ -592,18 +592,18 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
     // 128-byte lines of the brick layout; bricks in storage order
     std::vector<int4> bricks;
     if (H->dim == 3) {
-        const int half = (Lv.n + 1) / 2, np = Lv.Wp / 8;
-        if (half > 1024 || np > 1024) return fail(LSMG_EINVAL, "3-D grids hold at most 2047 nodes per axis");
+        const int np = brick_np(Lv.Wp), nj = brick_nj(Lv.n), nk = brick_nk(Lv.n);
+        if (np > 1024 || nj > 1024 || nk > 1024) return fail(LSMG_EINVAL, "3-D grids hold at most 2047 nodes per axis");
         std::vector<uint8_t> ty((size_t)Lv.ssize);
         HIPCHK(hipMemcpyAsync(ty.data(), Lv.type, ty.size(), hipMemcpyDeviceToHost, H->stream));
         HIPCHK(hipStreamSynchronize(H->stream));
         for (int c = 0; c < 2; ++c)
-            for (int kb = 0; kb < half; ++kb)
-                for (int jb = 0; jb < half; ++jb)
+            for (int kb = 0; kb < nk; ++kb)
+                for (int jb = 0; jb < nj; ++jb)
                     for (int pb = 0; pb < np; pb += 2) {
                         unsigned m[2] = {0u, 0u};
                         for (int h = 0; h < 2 && pb + h < np; ++h) {
-                            const size_t base = (size_t)(c * Lv.cs + ((((long long)kb * half + jb) * np + pb + h) << 5));
+                            const size_t base = (size_t)(c * Lv.cs + ((((long long)kb * nj + jb) * np + pb + h) << 5));
                             for (int in = 0; in < 32; ++in)
                                 if (ty[base + in] == kIn) m[h] |= 1u << in;
                         }
@@ -957,10 +957,10 @@ lsmg_status build(lsmg_hierarchy *H, const double *d_phi, const lsmg_grid *g)
             Lv.Wp = ((nl + 1) / 2 + 15) / 16 * 16;
             Lv.cs = Lv.rows * Lv.Wp;
         } else {
-            // bricks of 8 positions x 2 rows x 2 planes
+            // bricks of 32 values (positions x rows x planes)
             const long long half = (nl + 1) / 2;
-            Lv.Wp = (int)((half + 7) / 8 * 8);
-            Lv.cs = 4 * half * half * Lv.Wp;
+            Lv.Wp = (int)((half + (1 << kBP) - 1) >> kBP << kBP);
+            Lv.cs = 32LL * brick_np(Lv.Wp) * brick_nj(nl) * brick_nk(nl);
         }
         Lv.ssize = 2 * Lv.cs;
         if (Lv.ssize > 0x7fffffffLL) return fail(LSMG_EINVAL, "grid too large for 32-bit storage indices");
@@ -1336,8 +1336,10 @@ lsmg_status lsmg_estimate_bytes(const lsmg_grid *grid, const lsmg_params *params
     int nl = grid->n;
     for (int l = 0; l < 16; ++l) {
         const long long half = (nl + 1) / 2;
-        const size_t ss = grid->dim == 2 ? (size_t)(2 * (long long)nl * ((half + 15) / 16 * 16))
-                                         : (size_t)(2 * 4 * half * half * ((half + 7) / 8 * 8));
+        const size_t ss = grid->dim == 2
+                              ? (size_t)(2 * (long long)nl * ((half + 15) / 16 * 16))
+                              : (size_t)(2 * 32LL * brick_np((int)((half + (1 << kBP) - 1) >> kBP << kBP)) *
+                                         brick_nj(nl) * brick_nk(nl));
         if (l == 0) ss0 = ss;
         // 2-D: a second copy of the corrections for the fused sweeps
         const size_t nv = grid->dim == 2 ? 10 : 8;

@@ -8,12 +8,13 @@
 //   reads and writes contiguous memory, and the four axis neighbours of a node
 //   are the other colour in the same row (x) or at the same position in the rows
 //   above and below (y).
-//   3-D: each colour is stored in bricks of 8 positions x 2 rows (y) x 2 planes
-//   (z), 32 consecutive values (one 128-byte line in FP32, two in FP64), bricks
-//   in (position, y, z) order: a run of inside nodes along a row then shares its
-//   lines with the runs of the next row and plane instead of ending in partial
-//   lines of its own (a row crosses a 3-D domain in short runs).  Wp is the
-//   position count rounded up to 8, and cs = 4 ((n + 1) / 2)^2 Wp.
+//   3-D: each colour is stored in bricks of 32 consecutive values (one 128-byte
+//   line in FP32, two in FP64) covering 2^kBP positions x 2^kBJ rows (y) x 2^kBK
+//   planes (z), bricks in (position, y, z) order: a run of inside nodes along a
+//   row then shares its lines with the runs of the next rows and planes instead
+//   of ending in partial lines of its own (a row crosses a 3-D domain in short
+//   runs).  Wp is the position count rounded up to 2^kBP, and cs = 32 x the
+//   number of bricks of a colour.
 //
 // Work is described by lists of int4 work items, one 64-lane wavefront per
 // item: x = (descriptor index << 2) | kind, then
@@ -30,6 +31,14 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+// 3-D brick shape (log2 of positions and of rows per brick; planes take the rest of 32)
+#ifndef LSMG_BRICK_P
+#define LSMG_BRICK_P 2
+#endif
+#ifndef LSMG_BRICK_J
+#define LSMG_BRICK_J 2
+#endif
 
 namespace lsmg {
 
@@ -137,23 +146,32 @@ __device__ __forceinline__ bool seg_lane(int4 w, int lane, int &row, int &p)
     return p < w.w;
 }
 
+// 3-D brick shape: 2^kBP positions x 2^kBJ rows (y) x 2^kBK planes (z) of one
+// colour, 32 values
+constexpr int kBP = LSMG_BRICK_P, kBJ = LSMG_BRICK_J, kBK = 5 - LSMG_BRICK_P - LSMG_BRICK_J;
+
+// bricks per row of positions, per plane of rows and per grid of planes
+__host__ __device__ __forceinline__ int brick_np(int Wp) { return Wp >> kBP; }
+__host__ __device__ __forceinline__ int brick_nj(int n) { return (n + (1 << kBJ) - 1) >> kBJ; }
+__host__ __device__ __forceinline__ int brick_nk(int n) { return (n + (1 << kBK) - 1) >> kBK; }
+
 // node of lane `lane` of a 3-D brick item (kinds 0 and 1 = colour): two bricks
-// of the colour, consecutive along x, lanes 0-31 the first and 32-63 the second,
-// lane l & 31 its value (l & 7) + 8 ((l >> 3) & 1) + 16 (l >> 4) at position
-// 8 pb + (l & 7), y index 2 jb + ((l >> 3) & 1), z index 2 kb + (l >> 4).
-// w.y = pb | jb << 10 | kb << 20 of the first brick; w.z, w.w: the bits of the
-// inside nodes of each brick (false for the other lanes)
-__host__ __device__ __forceinline__ bool brick_lane(int n, int Wp, long long cs, int colour, int4 w, int lane, long long &idx,
-                                           int &i, int &j, int &k)
+// of the colour, consecutive along x, lanes 0-31 the first and 32-63 the second;
+// value v = l & 31 of a brick lies at position (v mod 2^kBP), y offset
+// (v >> kBP) mod 2^kBJ and z offset v >> (kBP + kBJ) within it.  w.y = pb | jb << 10
+// | kb << 20 of the first brick; w.z, w.w: the bits of the inside nodes of each
+// brick (false for the other lanes)
+__host__ __device__ __forceinline__ bool brick_lane(int n, int Wp, long long cs, int colour, int4 w, int lane,
+                                                    long long &idx, int &i, int &j, int &k)
 {
     const int hi = lane >> 5, in = lane & 31;
     const unsigned mask = (unsigned)(hi ? w.w : w.z);
     const int pb = (w.y & 1023) + hi, jb = (w.y >> 10) & 1023, kb = (w.y >> 20) & 1023;
-    const long long brick = ((long long)kb * ((n + 1) >> 1) + jb) * (Wp >> 3) + pb;
+    const long long brick = ((long long)kb * brick_nj(n) + jb) * brick_np(Wp) + pb;
     idx = colour * cs + (brick << 5) + in;
-    const int p = pb * 8 + (in & 7);
-    j = jb * 2 + ((in >> 3) & 1);
-    k = kb * 2 + (in >> 4);
+    const int p = (pb << kBP) + (in & ((1 << kBP) - 1));
+    j = (jb << kBJ) + ((in >> kBP) & ((1 << kBJ) - 1));
+    k = (kb << kBK) + (in >> (kBP + kBJ));
     i = 2 * p + ((colour + j + k) & 1);
     return (mask >> in) & 1u;
 }
@@ -183,8 +201,9 @@ __device__ __forceinline__ void unpack_ijk(int v, int &i, int &j, int &k)
 // 3-D storage index of (colour, position p, y index j, z index k)
 __host__ __device__ __forceinline__ long long sidx3(int n, int Wp, long long cs, int colour, int p, int j, int k)
 {
-    const long long brick = ((long long)(k >> 1) * ((n + 1) >> 1) + (j >> 1)) * (Wp >> 3) + (p >> 3);
-    return colour * cs + (brick << 5) + ((((k & 1) << 1) | (j & 1)) << 3) + (p & 7);
+    const long long brick = ((long long)(k >> kBK) * brick_nj(n) + (j >> kBJ)) * brick_np(Wp) + (p >> kBP);
+    const int in = ((((k & ((1 << kBK) - 1)) << kBJ) | (j & ((1 << kBJ) - 1))) << kBP) | (p & ((1 << kBP) - 1));
+    return colour * cs + (brick << 5) + in;
 }
 
 // storage index of node (colour, p, j, k) on a level of dimension DIM
@@ -211,12 +230,12 @@ __host__ __device__ __forceinline__ void sidx_node(int n, int Wp, long long cs, 
     int p;
     if (DIM == 3) {
         const long long brick = rem >> 5;
-        const int in = (int)(rem & 31), np = Wp >> 3, nj = (n + 1) >> 1;
+        const int in = (int)(rem & 31), np = brick_np(Wp), nj = brick_nj(n);
         const long long jk = brick / np;
-        p = (int)(brick - jk * np) * 8 + (in & 7);
+        p = ((int)(brick - jk * np) << kBP) + (in & ((1 << kBP) - 1));
         const int kb = (int)(jk / nj);
-        j = (int)(jk - (long long)kb * nj) * 2 + ((in >> 3) & 1);
-        k = kb * 2 + (in >> 4);
+        j = ((int)(jk - (long long)kb * nj) << kBJ) + ((in >> kBP) & ((1 << kBJ) - 1));
+        k = (kb << kBK) + (in >> (kBP + kBJ));
     } else {
         j = (int)(rem / Wp);
         p = (int)(rem - (long long)j * Wp);
