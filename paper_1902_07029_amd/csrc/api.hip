@@ -589,7 +589,12 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
     int cnt[2] = {0, 0};
     // 3-D: items of two bricks of one colour (consecutive along x) holding an inside
     // node, with the bits of their inside nodes, so that a wavefront reads whole
-    // 128-byte lines of the brick layout; bricks in storage order
+    // 128-byte lines of the brick layout.  Items in Morton (Z) order of the pair's
+    // (x, y, z) brick coordinates: a launch deals each XCD a contiguous eighth of
+    // the list (logical_block), which is then a compact piece of the domain, and
+    // the lines of the other colour that two XCDs both fetch are those along the
+    // pieces' faces.  (In storage order the eighths are thin z slabs of the domain,
+    // whose large faces made the torus's finest FP32 sweep fetch 1.4x its bytes.)
     std::vector<int4> bricks;
     if (H->dim == 3) {
         const int np = brick_np(Lv.Wp), nj = brick_nj(Lv.n), nk = brick_nk(Lv.n);
@@ -597,7 +602,13 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
         std::vector<uint8_t> ty((size_t)Lv.ssize);
         HIPCHK(hipMemcpyAsync(ty.data(), Lv.type, ty.size(), hipMemcpyDeviceToHost, H->stream));
         HIPCHK(hipStreamSynchronize(H->stream));
-        for (int c = 0; c < 2; ++c)
+        auto spread3 = [](unsigned v) {
+            unsigned long long r = 0;
+            for (int b = 0; b < 10; ++b) r |= (unsigned long long)((v >> b) & 1u) << (3 * b);
+            return r;
+        };
+        for (int c = 0; c < 2; ++c) {
+            std::vector<std::pair<unsigned long long, int4>> keyed;
             for (int kb = 0; kb < nk; ++kb)
                 for (int jb = 0; jb < nj; ++jb)
                     for (int pb = 0; pb < np; pb += 2) {
@@ -608,10 +619,19 @@ lsmg_status build_items(lsmg_hierarchy *H, int l)
                                 if (ty[base + in] == kIn) m[h] |= 1u << in;
                         }
                         if (m[0] | m[1]) {
-                            bricks.push_back(make_int4((l << 2) | c, pb | (jb << 10) | (kb << 20), (int)m[0], (int)m[1]));
-                            ++cnt[c];
+                            const unsigned long long key =
+                                spread3((unsigned)(pb >> 1)) | spread3((unsigned)jb) << 1 | spread3((unsigned)kb) << 2;
+                            keyed.push_back({key, make_int4((l << 2) | c, pb | (jb << 10) | (kb << 20), (int)m[0],
+                                                            (int)m[1])});
                         }
                     }
+            std::sort(keyed.begin(), keyed.end(),
+                      [](const std::pair<unsigned long long, int4> &a, const std::pair<unsigned long long, int4> &b) {
+                          return a.first < b.first;
+                      });
+            for (const auto &e : keyed) bricks.push_back(e.second);
+            cnt[c] = (int)keyed.size();
+        }
         if (Lv.ni > 0 && cnt[0] + cnt[1] == 0) return fail(LSMG_EHIP, "brick lists empty on level %d", l);
     } else {
         build_segments(H->dim, Lv.type, Lv.n, Lv.Wp, Lv.rows, Lv.cs, l, seg, cnt, H->mem, H->stream);
