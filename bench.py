@@ -602,33 +602,45 @@ def run_batch(args):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         same = all(np.array_equal(states[k].get().cpu().numpy(), traj[k][-1]) for k in sample)
-        # kernel timing pass: the smoother launches at the largest grid size
+        # kernel timing pass: the smoother launches at the largest grid size.  A launch
+        # covers the members of that size that are still solving, so each member is
+        # credited with its own bytes for each cycle it ran: per cycle, nu1 + nu2
+        # smoothing steps of its finest level (one launch per colour, or one fused launch)
         nmax = max(sizes_all)
+        cyc_t = np.zeros(len(doms), dtype=np.int64)
         B.profile_start(lsmg.KERNEL_SMOOTH, nmax)
         for _ in range(args.steps):
-            B.step(states, dt)
+            _, stt = B.step(states, dt)
+            for k, sk in enumerate(stt):
+                cyc_t[k] += sk["vcycles"]
         torch.cuda.synchronize()
         launches, prof_ms = B.profile_stop()
         tuning = {str(k): v for k, v in B.tuning().items()}
         P = 8 if prec == 0 else 4
+        nsm = Hs[0].params.nu1 + Hs[0].params.nu2
         fused = B.sweep_fused(nmax, prec) and Hs[0].params.nu1 % 2 == 0 and Hs[0].params.nu2 % 2 == 0
-        byts = 0.0
-        for H, d, inf in zip(Hs, doms, infos):
+        byts_full = byts_run = 0.0
+        for k, (H, d, inf) in enumerate(zip(Hs, doms, infos)):
             if d["n"] == nmax:
                 c2g0 = H.compact_to_grid(0).cpu().numpy()
                 if fused:
-                    byts += fused_sweep_bytes(c2g0, inf["ni"], inf["ng"], d["n"], P)
+                    per_step = fused_sweep_bytes(c2g0, inf["ni"], inf["ng"], d["n"], P)
+                    byts_full += per_step
                 else:
                     b0, b1 = smoother_bytes(c2g0, inf["ni"], inf["ng"], d["n"], 2, P)
-                    byts += 0.5 * (b0 + b1)
-        kname = (f"k_smooth_rb (all {nmax}^2 levels of the batch, both colours of a sweep)" if fused
-                 else f"k_smooth_colour (all {nmax}^2 levels of the batch, one colour)")
+                    per_step = b0 + b1
+                    byts_full += 0.5 * (b0 + b1)
+                byts_run += float(cyc_t[k]) * nsm * per_step
+        kname = (f"k_smooth_rb (the {nmax}^2 levels of the batch still solving, both colours of a sweep)" if fused
+                 else f"k_smooth_colour (the {nmax}^2 levels of the batch still solving, one colour)")
         avg_s = prof_ms * 1e-3 / max(launches, 1)
+        byts = byts_run / max(launches, 1)
         achieved = byts / avg_s / 1e9 if launches else 0.0
         kern = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=load_traffic("smooth_rb" if fused else "smooth_colour", "batch64", prec),
-                    kernel=kname, launches=launches, avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(byts))
+                    kernel=kname, launches=launches, avg_us=round(avg_s * 1e6, 2), bytes_per_launch=int(byts),
+                    bytes_all_members=int(byts_full))
         bpn = vcycle_bytes_per_node(2, prec == 1)
         vbytes = float(np.dot(na, cyc)) * bpn
         vcyc = dict(bound="hbm", achieved=round(vbytes / elapsed / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",

@@ -66,6 +66,7 @@ struct lsmg_batch {
     LevelDesc<double> *d64 = nullptr;
     LevelDesc<float> *d32 = nullptr;
     std::vector<BSize> sizes;       // descending n
+    std::vector<int> zfin;          // per member: the size class of its finest level
     BList lev0, all;
     int4 *pool = nullptr;
     int npool = 0;
@@ -83,7 +84,7 @@ struct lsmg_batch {
     int *d_cstatus = nullptr, *h_cstatus = nullptr;
     unsigned long long *d_norms = nullptr, *d_nred = nullptr, *h_nred = nullptr;
     long long norm_stride = 0;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::vector<hipGraphExec_t> gexec[2];   // per precision, by first size class (b_vcycle)
     // linear solves in chunks of cycles with the stopping tests on the device:
     // per-member control, the norms of a chunk's cycles, (d0, nlev) per member,
     // the cycles each member's last solve took, and the cycle graph with the
@@ -92,7 +93,7 @@ struct lsmg_batch {
     double *d_hist = nullptr, *h_hist = nullptr;
     int2 *d_dlev = nullptr;
     std::vector<int> last_cycles;
-    hipGraphExec_t gctl[2] = {nullptr, nullptr};
+    std::vector<hipGraphExec_t> gctl[2];
     bool use_graphs = true;
     int autotune = 1, tuned = 0;
     bool fused = false;         // 2-D, every member with fused sweeps
@@ -112,8 +113,10 @@ struct lsmg_batch {
     ~lsmg_batch()
     {
         for (int i = 0; i < 2; ++i) {
-            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
-            if (gctl[i]) (void)hipGraphExecDestroy(gctl[i]);
+            for (hipGraphExec_t g : gexec[i])
+                if (g) (void)hipGraphExecDestroy(g);
+            for (hipGraphExec_t g : gctl[i])
+                if (g) (void)hipGraphExecDestroy(g);
         }
         if (cap) (void)hipStreamDestroy(cap);
         for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
@@ -327,12 +330,16 @@ void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s, int count)
     }
 }
 
+// The size classes from z0 on: a member's levels lie in the classes of its finest
+// size and below, so when the cycle's active members all have their finest level in
+// class z0 or a smaller one, the classes before z0 hold no active level and their
+// launches (every item skipped by its flag) are left out.
 template <typename T>
-void b_vcycle(lsmg_batch *B, hipStream_t s)
+void b_vcycle(lsmg_batch *B, hipStream_t s, int z0 = 0)
 {
     const LevelDesc<T> *d = bdescs<T>(B);
     const int nz = (int)B->sizes.size();
-    for (int z = 0; z < nz; ++z) {
+    for (int z = z0; z < nz; ++z) {
         const BSize &S = B->sizes[z];
         if (S.act.n == 0) continue;
         b_smooth<T>(B, S, s, B->p.nu1);
@@ -347,7 +354,7 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
         launch_tail_lds<T>(B->dim, d, B->d_tail, B->ndom, f64 ? B->lds_bytes64 : B->lds_bytes32, Exec(s, B->d_act));
     if (!(f64 ? B->all_lds64 : B->all_lds32))
         launch_tail<T>(B->dim, d, B->d_tail, B->ndom, B->tail_na_max, B->tail_stage, Exec(s, B->d_act));
-    for (int z = nz - 1; z >= 0; --z) {
+    for (int z = nz - 1; z >= z0; --z) {
         const BSize &S = B->sizes[z];
         if (S.act.n == 0) continue;
         launch_prolong<T>(B->dim, d, items(B, S.act), S.act.n,
@@ -359,18 +366,18 @@ void b_vcycle(lsmg_batch *B, hipStream_t s)
 // one linear-solve iteration for every active member (see the single-hierarchy
 // driver): V-cycle, or FP32 V-cycle on the FP64 defect; then the FP64 defect
 // with its norm in slot 1
-void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s, bool ctl = false)
+void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s, bool ctl = false, int z0 = 0)
 {
     // (with the device-side tests the norm slots are left zero by the previous
     // cycle, and cleared before a chunk)
     if (!ctl) zero_bnorms(B, 1, 1, s);
     const Exec x0(s, B->d_act);
     if (!mixed) {
-        b_vcycle<double>(B, s);
+        b_vcycle<double>(B, s, z0);
     } else {
         // the FP32 right-hand side and zero correction were written by the FP64
         // defect that precedes every cycle
-        b_vcycle<float>(B, s);
+        b_vcycle<float>(B, s, z0);
         launch_add_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
     }
     launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 1, with_tail(x0, B->lev0.tail),
@@ -384,23 +391,29 @@ void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s, bool ctl = false)
 void b_invalidate(lsmg_batch *B)
 {
     for (int i = 0; i < 2; ++i) {
-        if (B->gexec[i]) (void)hipGraphExecDestroy(B->gexec[i]);
-        B->gexec[i] = nullptr;
-        if (B->gctl[i]) (void)hipGraphExecDestroy(B->gctl[i]);
-        B->gctl[i] = nullptr;
+        for (hipGraphExec_t &g : B->gexec[i]) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+        for (hipGraphExec_t &g : B->gctl[i]) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     }
 }
 
-// the captured cycle, with the plain norm reduction or (ctl) the device-side
-// stopping tests
-lsmg_status b_graph(lsmg_batch *B, bool mixed, hipGraphExec_t *out, bool ctl = false)
+// the captured cycle from size class z0 on, with the plain norm reduction or (ctl)
+// the device-side stopping tests
+lsmg_status b_graph(lsmg_batch *B, bool mixed, hipGraphExec_t *out, bool ctl = false, int z0 = 0)
 {
     const int gi = mixed ? 1 : 0;
-    hipGraphExec_t &ge = ctl ? B->gctl[gi] : B->gexec[gi];
+    std::vector<hipGraphExec_t> &gv = ctl ? B->gctl[gi] : B->gexec[gi];
+    if (gv.size() < B->sizes.size() + 1) gv.resize(B->sizes.size() + 1, nullptr);
+    hipGraphExec_t &ge = gv[z0];
     if (!ge) {
         if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-        b_cycle_enqueue(B, mixed, B->cap, ctl);
+        b_cycle_enqueue(B, mixed, B->cap, ctl, z0);
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamEndCapture(B->cap, &g));
         hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -521,6 +534,8 @@ lsmg_status build_lists(lsmg_batch *B)
         B->sizes[z].n = ns[z];
         for (int c = 0; c < kTClasses; ++c) B->sizes[z].ipb[c] = kItemsPerBlock;
     }
+    B->zfin.resize(B->mem.size());
+    for (size_t k = 0; k < B->mem.size(); ++k) B->zfin[k] = zi[B->mem[k]->L[0].n];
     std::vector<Job> jobs;
     int total = 0;
     auto add = [&](BList &L, const std::vector<Job> &js) {
@@ -866,9 +881,15 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
         }
         if (nact == 0) break;
         LSMGCHK(set_flags(B, on));
-        // linearisation: coarse (s, c) level by level, FP32 copies, coarsest inverses
-        for (const BSize &S : B->sizes)
+        // linearisation: coarse (s, c) level by level (from the first size class that
+        // holds a level of an iterating member), FP32 copies, coarsest inverses
+        int zl = (int)B->sizes.size();
+        for (int k = 0; k < nk; ++k)
+            if (on[k]) zl = std::min(zl, B->zfin[k]);
+        for (int z = zl; z < (int)B->sizes.size(); ++z) {
+            const BSize &S = B->sizes[z];
             launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, with_tail(x0, S.icoarse.tail));
+        }
         if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, with_tail(x0, B->all.tail));
         launch_coarse_factor(B->dim, B->d64, B->d_coarse, nk, B->coarse_n_max, x0);
         // the factorisations' status comes back with the first chunk's norms; a member
@@ -922,12 +943,17 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
             HIPCHK(hipMemcpyAsync(B->d_lctl, B->h_lctl, sizeof(LinCtl) * nk, hipMemcpyHostToDevice, s));
             LSMGCHK(set_flags(B, lin));
             zero_bnorms(B, 1, 1, s);
+            // the first size class holding a level of a solving member (members only
+            // leave during a chunk)
+            int z0 = (int)B->sizes.size();
+            for (int k = 0; k < nk; ++k)
+                if (lin[k]) z0 = std::min(z0, B->zfin[k]);
             hipGraphExec_t gc = nullptr;
             // timed launches run direct: events inside a graph cannot be timed
-            if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &gc, true));
+            if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &gc, true, z0));
             for (int j = 0; j < kc; ++j) {
                 if (gc) HIPCHK(hipGraphLaunch(gc, s));
-                else b_cycle_enqueue(B, mixed, s, true);
+                else b_cycle_enqueue(B, mixed, s, true, z0);
             }
             B->act_last.clear();   // the chunk cleared the flags of the members that stopped
             HIPCHK(hipMemcpyAsync(B->h_hist, B->d_hist, sizeof(double) * (size_t)kc * nk, hipMemcpyDeviceToHost, s));
