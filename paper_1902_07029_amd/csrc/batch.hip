@@ -1120,9 +1120,17 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
             launch_explicit_half(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xs, B->lev0.tail));
             launch_residual(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 0, with_tail(xs, B->lev0.tail));
         }
+        // the first size classes holding a level of a member being linearised, or cycled
+        int zl = (int)B->sizes.size(), zc = zl;
+        for (int k = 0; k < nk; ++k) {
+            if (fl[k]) zl = std::min(zl, B->zfin[k]);
+            if (fc[k]) zc = std::min(zc, B->zfin[k]);
+        }
         if (has_l) {
-            for (const BSize &S : B->sizes)
+            for (int z = zl; z < (int)B->sizes.size(); ++z) {
+                const BSize &S = B->sizes[z];
                 launch_inject<double>(B->dim, B->d64, items(B, S.icoarse), S.icoarse.n, with_tail(xl, S.icoarse.tail));
+            }
             if (mixed) launch_to_f32(B->dim, B->d64, B->d32, items(B, B->all), B->all.n, 0, with_tail(xl, B->all.tail));
             launch_coarse_factor(B->dim, B->d64, B->d_coarse, nk, B->coarse_n_max, xl);
             if (B->autotune && !B->tuned) {
@@ -1143,9 +1151,9 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
         }
         if (has_c) {
             hipGraphExec_t ge = nullptr;
-            if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &ge));
+            if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &ge, false, zc));
             if (ge) HIPCHK(hipGraphLaunch(ge, s));
-            else b_cycle_enqueue(B, mixed, s);
+            else b_cycle_enqueue(B, mixed, s, false, zc);
         }
         if (has_u) {
             launch_newton_update(B->dim, B->d64, items(B, B->lev0), B->lev0.n, with_tail(xu, B->lev0.tail));
