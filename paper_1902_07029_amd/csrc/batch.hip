@@ -477,29 +477,37 @@ template <typename T>
 lsmg_status b_autotune(lsmg_batch *B, int reps)
 {
     static const int cand[4] = {1, 2, 4, 8};
-    LSMGCHK(ensure_events(B, (size_t)2 * reps));
+    constexpr int nc = 4;
+    LSMGCHK(ensure_events(B, (size_t)2 * reps * nc));
     for (BSize &S : B->sizes) {
         if (S.act.n == 0) continue;
         for (int cls = 0; cls < kTClasses; ++cls) {
-            double best = 1e300;
-            int best_ipb = kItemsPerBlock;
-            for (int ci = 0; ci < 4; ++ci) {
-                // one untimed launch, then reps timed ones
-                tune_launch<T>(B, S, cls, bexec(B, B->stream, cand[ci]));
-                for (int r = 0; r < reps; ++r) {
+            // one untimed launch per candidate, then `reps` rounds that time every
+            // candidate in turn (so that a drift of the clock or of the caches during
+            // tuning does not favour one of them); each candidate scores its median
+            for (int ci = 0; ci < nc; ++ci) tune_launch<T>(B, S, cls, bexec(B, B->stream, cand[ci]));
+            for (int r = 0; r < reps; ++r)
+                for (int ci = 0; ci < nc; ++ci) {
                     Exec x = bexec(B, B->stream, cand[ci]);
-                    x.ev0 = B->evpool[2 * r];
-                    x.ev1 = B->evpool[2 * r + 1];
+                    x.ev0 = B->evpool[2 * (r * nc + ci)];
+                    x.ev1 = B->evpool[2 * (r * nc + ci) + 1];
                     tune_launch<T>(B, S, cls, x);
                 }
-                HIPCHK(hipStreamSynchronize(B->stream));
-                double tot = 0.0;
+            HIPCHK(hipStreamSynchronize(B->stream));
+            double best = 1e300;
+            int best_ipb = kItemsPerBlock;
+            for (int ci = 0; ci < nc; ++ci) {
+                std::vector<double> t(reps, 1e300);
                 for (int r = 0; r < reps; ++r) {
                     float ms = 0.0f;
-                    if (hipEventElapsedTime(&ms, B->evpool[2 * r], B->evpool[2 * r + 1]) == hipSuccess) tot += ms;
+                    if (hipEventElapsedTime(&ms, B->evpool[2 * (r * nc + ci)], B->evpool[2 * (r * nc + ci) + 1]) ==
+                        hipSuccess)
+                        t[r] = ms;
                 }
-                if (tot < best) {
-                    best = tot;
+                std::sort(t.begin(), t.end());
+                const double med = t[reps / 2];
+                if (med < best) {
+                    best = med;
                     best_ipb = cand[ci];
                 }
             }
@@ -908,8 +916,8 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
         };
         LSMGCHK(set_flags(B, on));
         if (B->autotune && !B->tuned) {
-            if (mixed) LSMGCHK(b_autotune<float>(B, 3));
-            else LSMGCHK(b_autotune<double>(B, 3));
+            if (mixed) LSMGCHK(b_autotune<float>(B, 5));
+            else LSMGCHK(b_autotune<double>(B, 5));
         }
         // linear solves J dW = F from dW = 0
         if (mixed)
@@ -1140,8 +1148,8 @@ lsmg_status lsmg_batch_advance(lsmg_batch *b, lsmg_state *const *states, double 
                 std::vector<std::vector<char>> trow = rows;
                 trow[kFCycle] = fl;
                 LSMGCHK(set_flag_rows(B, trow));
-                if (mixed) LSMGCHK(b_autotune<float>(B, 3));
-                else LSMGCHK(b_autotune<double>(B, 3));
+                if (mixed) LSMGCHK(b_autotune<float>(B, 5));
+                else LSMGCHK(b_autotune<double>(B, 5));
                 LSMGCHK(set_flag_rows(B, rows));
             }
             if (mixed)
