@@ -39,7 +39,6 @@ enum { kFCycle = 0, kFStart = 1, kFLin = 2, kFUpdate = 3, kFCommit = 4, kFlagRow
 struct BList {
     int off = 0, n = 0;   // range in the batch's item pool
     int tail = 0;         // trailing ghost items, dealt to the XCDs in turn (Exec::tail)
-    std::vector<int> cum; // member-major lists: items of the first p members (in the batch's order)
 };
 
 struct BSize {
@@ -68,14 +67,6 @@ struct lsmg_batch {
     LevelDesc<float> *d32 = nullptr;
     std::vector<BSize> sizes;       // descending n
     std::vector<int> zfin;          // per member: the size class of its finest level
-    // 2-D batches list their items member by member (mm), the members in `order`
-    // (after the first step: most V-cycles first), so that the members still solving
-    // late in a linear solve are a short prefix of every list; a cycle then covers the
-    // first P members only (P = ndom: all).  3-D batches keep each list's ghost items
-    // at its end, dealt to the XCDs first (Exec::tail), and P = ndom.
-    bool mm = false, ordered = false;
-    std::vector<int> order, pos;
-    int P = 0;
     BList lev0, all;
     int4 *pool = nullptr;
     int npool = 0;
@@ -93,7 +84,7 @@ struct lsmg_batch {
     int *d_cstatus = nullptr, *h_cstatus = nullptr;
     unsigned long long *d_norms = nullptr, *d_nred = nullptr, *h_nred = nullptr;
     long long norm_stride = 0;
-    std::map<int, hipGraphExec_t> gexec[2];   // per precision, by first size class and member prefix
+    std::vector<hipGraphExec_t> gexec[2];   // per precision, by first size class (b_vcycle)
     // linear solves in chunks of cycles with the stopping tests on the device:
     // per-member control, the norms of a chunk's cycles, (d0, nlev) per member,
     // the cycles each member's last solve took, and the cycle graph with the
@@ -102,7 +93,7 @@ struct lsmg_batch {
     double *d_hist = nullptr, *h_hist = nullptr;
     int2 *d_dlev = nullptr;
     std::vector<int> last_cycles;
-    std::map<int, hipGraphExec_t> gctl[2];
+    std::vector<hipGraphExec_t> gctl[2];
     bool use_graphs = true;
     int autotune = 1, tuned = 0;
     bool fused = false;         // 2-D, every member with fused sweeps
@@ -122,10 +113,10 @@ struct lsmg_batch {
     ~lsmg_batch()
     {
         for (int i = 0; i < 2; ++i) {
-            for (auto &e : gexec[i])
-                if (e.second) (void)hipGraphExecDestroy(e.second);
-            for (auto &e : gctl[i])
-                if (e.second) (void)hipGraphExecDestroy(e.second);
+            for (hipGraphExec_t g : gexec[i])
+                if (g) (void)hipGraphExecDestroy(g);
+            for (hipGraphExec_t g : gctl[i])
+                if (g) (void)hipGraphExecDestroy(g);
         }
         if (cap) (void)hipStreamDestroy(cap);
         for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
@@ -160,8 +151,6 @@ template <>
 const LevelDesc<float> *bdescs<float>(const lsmg_batch *B) { return B->d32; }
 
 inline const int4 *items(const lsmg_batch *B, const BList &l) { return B->pool + l.off; }
-// the items of a list that a cycle covers: those of the first P members in member-major lists
-inline int bn(const lsmg_batch *B, const BList &l) { return (!l.cum.empty() && B->P < B->ndom) ? l.cum[B->P] : l.n; }
 
 Exec bexec(const lsmg_batch *B, hipStream_t s, int ipb) { return Exec(s, B->d_act, ipb); }
 
@@ -312,31 +301,31 @@ void b_smooth(lsmg_batch *B, const BSize &S, hipStream_t s, int count)
         if (B->fused && fuse_sweep(S.na, sizeof(T))) {
             for (; count >= 2; count -= 2) {
                 for (int flip = 0; flip < 2; ++flip) {
-                    launch_smooth_rb<T>(d, items(B, S.tiles), bn(B, S.tiles), items(B, S.gh), bn(B, S.gh), flip,
+                    launch_smooth_rb<T>(d, items(B, S.tiles), S.tiles.n, items(B, S.gh), S.gh.n, flip,
                                         bexec_t(B, s, 0, LSMG_KERNEL_SMOOTH, S.n));
-                    launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), bn(B, S.gh4), 1 - flip,
+                    launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 1 - flip,
                                           with_tail(bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n), S.gh4.tail));
                 }
             }
         }
         // folded ghost relaxation: the black launch snapshots the ghosts, one apply launch
         for (; count > 0; --count) {
-            launch_smooth_colour<T>(B->dim, d, items(B, S.seg[0]), bn(B, S.seg[0]), 0,
+            launch_smooth_colour<T>(B->dim, d, items(B, S.seg[0]), S.seg[0].n, 0,
                                     bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
-            launch_smooth_colour<T>(B->dim, d, items(B, S.seg1g), bn(B, S.seg1g), 1,
+            launch_smooth_colour<T>(B->dim, d, items(B, S.seg1g), S.seg1g.n, 1,
                                     with_tail(bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n), S.seg1g.tail));
-            launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), bn(B, S.gh4), 0,
+            launch_ghost_apply<T>(B->dim, d, items(B, S.gh4), S.gh4.n, 0,
                                   with_tail(bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n), S.gh4.tail));
         }
         return;
     }
     for (; count > 0; --count) {
         for (int colour = 0; colour < 2; ++colour)
-            launch_smooth_colour<T>(B->dim, d, items(B, S.seg[colour]), bn(B, S.seg[colour]), colour,
+            launch_smooth_colour<T>(B->dim, d, items(B, S.seg[colour]), S.seg[colour].n, colour,
                                     bexec_t(B, s, S.ipb[kTSmooth], LSMG_KERNEL_SMOOTH, S.n));
         const Exec xb = bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n);
         const Exec xa = with_tail(bexec_t(B, s, S.ipb[kTGhost], LSMG_KERNEL_GHOST, S.n), S.gh4.tail);
-        launch_ghost<T>(B->dim, d, 0, items(B, S.gh), bn(B, S.gh), items(B, S.gh4), bn(B, S.gh4), 0, B->p.ghost_sweeps, true,
+        launch_ghost<T>(B->dim, d, 0, items(B, S.gh), S.gh.n, items(B, S.gh4), S.gh4.n, 0, B->p.ghost_sweeps, true,
                         xb, xa);
     }
 }
@@ -352,12 +341,12 @@ void b_vcycle(lsmg_batch *B, hipStream_t s, int z0 = 0)
     const int nz = (int)B->sizes.size();
     for (int z = z0; z < nz; ++z) {
         const BSize &S = B->sizes[z];
-        if (bn(B, S.act) == 0) continue;
+        if (S.act.n == 0) continue;
         b_smooth<T>(B, S, s, B->p.nu1);
-        launch_defect<T>(B->dim, d, items(B, S.act), bn(B, S.act), -1,
+        launch_defect<T>(B->dim, d, items(B, S.act), S.act.n, -1,
                          with_tail(bexec_t(B, s, S.ipb[kTDefect], LSMG_KERNEL_DEFECT, S.n), S.act.tail));
-        launch_band<T>(d, items(B, S.band), bn(B, S.band), bexec(B, s, S.ipb[kTBand]));
-        launch_restrict<T>(B->dim, d, items(B, S.rcoarse), bn(B, S.rcoarse),
+        launch_band<T>(d, items(B, S.band), S.band.n, bexec(B, s, S.ipb[kTBand]));
+        launch_restrict<T>(B->dim, d, items(B, S.rcoarse), S.rcoarse.n,
                            with_tail(bexec_t(B, s, S.ipb[kTRestrict], LSMG_KERNEL_RESTRICT, S.n), S.rcoarse.tail));
     }
     const bool f64 = sizeof(T) == 8;
@@ -367,8 +356,8 @@ void b_vcycle(lsmg_batch *B, hipStream_t s, int z0 = 0)
         launch_tail<T>(B->dim, d, B->d_tail, B->ndom, B->tail_na_max, B->tail_stage, Exec(s, B->d_act));
     for (int z = nz - 1; z >= z0; --z) {
         const BSize &S = B->sizes[z];
-        if (bn(B, S.act) == 0) continue;
-        launch_prolong<T>(B->dim, d, items(B, S.act), bn(B, S.act),
+        if (S.act.n == 0) continue;
+        launch_prolong<T>(B->dim, d, items(B, S.act), S.act.n,
                           with_tail(bexec_t(B, s, S.ipb[kTProlong], LSMG_KERNEL_PROLONG, S.n), S.act.tail));
         b_smooth<T>(B, S, s, B->p.nu2);
     }
@@ -389,9 +378,9 @@ void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s, bool ctl = false,
         // the FP32 right-hand side and zero correction were written by the FP64
         // defect that precedes every cycle
         b_vcycle<float>(B, s, z0);
-        launch_add_f32(B->dim, B->d64, B->d32, items(B, B->lev0), bn(B, B->lev0), with_tail(x0, B->lev0.tail));
+        launch_add_f32(B->dim, B->d64, B->d32, items(B, B->lev0), B->lev0.n, with_tail(x0, B->lev0.tail));
     }
-    launch_defect<double>(B->dim, B->d64, items(B, B->lev0), bn(B, B->lev0), 1, with_tail(x0, B->lev0.tail),
+    launch_defect<double>(B->dim, B->d64, items(B, B->lev0), B->lev0.n, 1, with_tail(x0, B->lev0.tail),
                           mixed ? B->d32 : nullptr);
     if (!ctl)
         launch_norm_reduce(B->d_norms, B->norm_stride, B->ndom, 1, 1, B->d_nred, s);
@@ -402,21 +391,25 @@ void b_cycle_enqueue(lsmg_batch *B, bool mixed, hipStream_t s, bool ctl = false,
 void b_invalidate(lsmg_batch *B)
 {
     for (int i = 0; i < 2; ++i) {
-        for (auto &e : B->gexec[i])
-            if (e.second) (void)hipGraphExecDestroy(e.second);
-        B->gexec[i].clear();
-        for (auto &e : B->gctl[i])
-            if (e.second) (void)hipGraphExecDestroy(e.second);
-        B->gctl[i].clear();
+        for (hipGraphExec_t &g : B->gexec[i]) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+        for (hipGraphExec_t &g : B->gctl[i]) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     }
 }
 
-// the captured cycle from size class z0 on, over the first B->P members, with the
-// plain norm reduction or (ctl) the device-side stopping tests
+// the captured cycle from size class z0 on, with the plain norm reduction or (ctl)
+// the device-side stopping tests
 lsmg_status b_graph(lsmg_batch *B, bool mixed, hipGraphExec_t *out, bool ctl = false, int z0 = 0)
 {
     const int gi = mixed ? 1 : 0;
-    hipGraphExec_t &ge = (ctl ? B->gctl[gi] : B->gexec[gi])[z0 * 4096 + B->P];
+    std::vector<hipGraphExec_t> &gv = ctl ? B->gctl[gi] : B->gexec[gi];
+    if (gv.size() < B->sizes.size() + 1) gv.resize(B->sizes.size() + 1, nullptr);
+    hipGraphExec_t &ge = gv[z0];
     if (!ge) {
         if (!B->cap) HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
@@ -553,50 +546,41 @@ lsmg_status build_lists(lsmg_batch *B)
     for (size_t k = 0; k < B->mem.size(); ++k) B->zfin[k] = zi[B->mem[k]->L[0].n];
     std::vector<Job> jobs;
     int total = 0;
-    const int nk = B->ndom;
-    // jobs per member (a member has at most one level of a size, but every level in
-    // the all-levels list); a list is made of parts, the last `ntrail` of them its
-    // ghost items.  Member-major lists take each member's parts together, in the
-    // batch's member order, and count the items of every member prefix; the others
-    // take each part for all members in turn, the trailing parts last (Exec::tail).
-    using PerMember = std::vector<std::vector<Job>>;
-    auto add_parts = [&](BList &L, std::initializer_list<const PerMember *> parts, int ntrail) {
+    auto add = [&](BList &L, const std::vector<Job> &js) {
         L.off = total;
         L.n = 0;
         L.tail = 0;
-        L.cum.clear();
-        if (B->mm) {
-            L.cum.assign(nk + 1, 0);
-            for (int i = 0; i < nk; ++i) {
-                const int k = B->order[i];
-                for (const PerMember *pm : parts)
-                    for (const Job &j : (*pm)[k]) {
-                        if (j.cnt <= 0) continue;
-                        jobs.push_back(j);
-                        L.n += j.cnt;
-                        total += j.cnt;
-                    }
-                L.cum[i + 1] = L.n;
-            }
-            return;
-        }
-        const int np = (int)parts.size();
-        int pi = 0;
-        for (const PerMember *pm : parts) {
-            const bool trail = pi++ >= np - ntrail;
-            for (int k = 0; k < nk; ++k)
-                for (const Job &j : (*pm)[k]) {
-                    if (j.cnt <= 0) continue;
-                    jobs.push_back(j);
-                    L.n += j.cnt;
-                    total += j.cnt;
-                    if (trail) L.tail += j.cnt;
-                }
+        for (const Job &j : js) {
+            if (j.cnt <= 0) continue;
+            jobs.push_back(j);
+            L.n += j.cnt;
+            total += j.cnt;
         }
     };
+    // leading job lists, then trailing ones (ghost items) counted in L.tail
+    auto add_tail = [&](BList &L, std::initializer_list<const std::vector<Job> *> lead, const std::vector<Job> &trail) {
+        L.off = total;
+        L.n = 0;
+        for (const std::vector<Job> *js : lead)
+            for (const Job &j : *js) {
+                if (j.cnt <= 0) continue;
+                jobs.push_back(j);
+                L.n += j.cnt;
+                total += j.cnt;
+            }
+        L.tail = 0;
+        for (const Job &j : trail) {
+            if (j.cnt <= 0) continue;
+            jobs.push_back(j);
+            L.n += j.cnt;
+            L.tail += j.cnt;
+            total += j.cnt;
+        }
+    };
+    const int nk = B->ndom;
     for (size_t z = 0; z < ns.size(); ++z) {
         BSize &S = B->sizes[z];
-        PerMember seg0(nk), seg1(nk), gh(nk), gh4(nk), band(nk), til(nk), rco(nk), rco_gh(nk), ico(nk), ico_gh(nk);
+        std::vector<Job> seg0, seg1, gh, gh4, band, til, rco, rco_gh, ico, ico_gh;
         for (int k = 0; k < nk; ++k) {
             const lsmg_hierarchy *H = B->mem[k];
             for (int l = 0; l < H->nlev; ++l) {
@@ -605,51 +589,50 @@ lsmg_status build_lists(lsmg_batch *B)
                 const int ds = B->d0[k];
                 if (l + 1 < H->nlev) {
                     const Level &C = H->L[l + 1];
-                    ico[k].push_back({C.w_seg(0), C.nseg[0] + C.nseg[1], ds});
-                    ico_gh[k].push_back({C.w_gh(), C.nghc, ds});
+                    ico.push_back({C.w_seg(0), C.nseg[0] + C.nseg[1], ds});
+                    ico_gh.push_back({C.w_gh(), C.nghc, ds});
                 }
                 if (l >= H->tail_l0) continue;
-                seg0[k].push_back({Lv.w_seg(0), Lv.nseg[0], ds});
-                seg1[k].push_back({Lv.w_seg(1), Lv.nseg[1], ds});
-                if (Lv.tiles) til[k].push_back({Lv.tiles, Lv.ntile, ds});
+                seg0.push_back({Lv.w_seg(0), Lv.nseg[0], ds});
+                seg1.push_back({Lv.w_seg(1), Lv.nseg[1], ds});
+                if (Lv.tiles) til.push_back({Lv.tiles, Lv.ntile, ds});
                 S.na += Lv.na;
-                gh[k].push_back({Lv.w_gh(), Lv.nghc, ds});
-                gh4[k].push_back({Lv.w_gh4(), Lv.nghc4, ds});
-                band[k].push_back({Lv.w_band(), Lv.nbandc, ds});
+                gh.push_back({Lv.w_gh(), Lv.nghc, ds});
+                gh4.push_back({Lv.w_gh4(), Lv.nghc4, ds});
+                band.push_back({Lv.w_band(), Lv.nbandc, ds});
                 const Level &C = H->L[l + 1];
-                rco[k].push_back({C.w_seg(0), C.nseg[0] + C.nseg[1], ds});
-                rco_gh[k].push_back({C.w_gh(), C.nghc, ds});
+                rco.push_back({C.w_seg(0), C.nseg[0] + C.nseg[1], ds});
+                rco_gh.push_back({C.w_gh(), C.nghc, ds});
             }
         }
-        add_parts(S.seg[0], {&seg0}, 0);
-        add_parts(S.seg[1], {&seg1}, 0);
-        // the members' row segments, then their ghost items
-        add_parts(S.seg1g, {&seg1, &gh}, 1);
-        add_parts(S.tiles, {&til}, 0);
-        add_parts(S.gh, {&gh}, 0);
-        add_parts(S.gh4, {&gh4}, 1);
-        add_parts(S.act, {&seg0, &seg1, &gh}, 1);
-        add_parts(S.band, {&band}, 0);
-        add_parts(S.rcoarse, {&rco, &rco_gh}, 1);
-        add_parts(S.icoarse, {&ico, &ico_gh}, 1);
+        add(S.seg[0], seg0);
+        add(S.seg[1], seg1);
+        // the members' row segments first, then all their ghost items
+        add_tail(S.seg1g, {&seg1}, gh);
+        add(S.tiles, til);
+        add(S.gh, gh);
+        add_tail(S.gh4, {}, gh4);
+        add_tail(S.act, {&seg0, &seg1}, gh);
+        add(S.band, band);
+        add_tail(S.rcoarse, {&rco}, rco_gh);
+        add_tail(S.icoarse, {&ico}, ico_gh);
     }
-    PerMember l0(nk), l0_gh(nk), al(nk), al_gh(nk);
+    std::vector<Job> l0, l0_gh, al, al_gh;
     for (int k = 0; k < nk; ++k) {
         const lsmg_hierarchy *H = B->mem[k];
         const Level &L0 = H->L[0];
-        l0[k].push_back({L0.w_seg(0), L0.nseg[0] + L0.nseg[1], B->d0[k]});
-        l0_gh[k].push_back({L0.w_gh(), L0.nghc, B->d0[k]});
+        l0.push_back({L0.w_seg(0), L0.nseg[0] + L0.nseg[1], B->d0[k]});
+        l0_gh.push_back({L0.w_gh(), L0.nghc, B->d0[k]});
         for (int l = 0; l < H->nlev; ++l) {
             const Level &Lv = H->L[l];
-            al[k].push_back({Lv.w_seg(0), Lv.nseg[0] + Lv.nseg[1], B->d0[k]});
-            al_gh[k].push_back({Lv.w_gh(), Lv.nghc, B->d0[k]});
+            al.push_back({Lv.w_seg(0), Lv.nseg[0] + Lv.nseg[1], B->d0[k]});
+            al_gh.push_back({Lv.w_gh(), Lv.nghc, B->d0[k]});
         }
     }
-    add_parts(B->lev0, {&l0, &l0_gh}, 1);
-    add_parts(B->all, {&al, &al_gh}, 1);
-    // a rebuild in another member order holds the same items: the pool is reused
-    if (!B->pool || B->npool != total) LSMGCHK(B->alloc(&B->pool, total));
+    add_tail(B->lev0, {&l0}, l0_gh);
+    add_tail(B->all, {&al}, al_gh);
     B->npool = total;
+    LSMGCHK(B->alloc(&B->pool, total));
     // one launch copies every block; the job table is freed after the copy
     std::vector<ItemCopy> hj(jobs.size());
     int off = 0;
@@ -747,38 +730,8 @@ lsmg_status b_build(lsmg_batch *B)
     LSMGCHK(B->alloc(&B->d_coarse, nk));
     HIPCHK(hipMemcpyAsync(B->d_tail, ta.data(), sizeof(TailArgs) * nk, hipMemcpyHostToDevice, B->stream));
     HIPCHK(hipMemcpyAsync(B->d_coarse, ca.data(), sizeof(CoarseArgs) * nk, hipMemcpyHostToDevice, B->stream));
-    B->mm = B->dim == 2;
-    B->order.resize(nk);
-    B->pos.resize(nk);
-    for (int k = 0; k < nk; ++k) B->order[k] = B->pos[k] = k;
-    B->P = nk;
     LSMGCHK(build_lists(B));
     LSMGCHK(refresh_descs(B, nullptr, nullptr, nullptr));
-    return LSMG_OK;
-}
-
-// member-major batches: after the first step, order the members by the V-cycles they
-// ran in it (most first; the slow members stay slow from step to step) and rebuild
-// the lists in that order, keeping the tuned launch shapes
-lsmg_status b_reorder(lsmg_batch *B, const std::vector<int> &cycles)
-{
-    B->ordered = true;
-    const int nk = B->ndom;
-    std::vector<int> ord(nk);
-    for (int k = 0; k < nk; ++k) ord[k] = k;
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cycles[a] > cycles[b]; });
-    if (ord == B->order) return LSMG_OK;
-    std::map<int, std::vector<int>> ipb;
-    for (const BSize &S : B->sizes) ipb[S.n].assign(S.ipb, S.ipb + kTClasses);
-    HIPCHK(hipStreamSynchronize(B->stream));
-    B->order = ord;
-    for (int i = 0; i < nk; ++i) B->pos[ord[i]] = i;
-    LSMGCHK(build_lists(B));
-    for (BSize &S : B->sizes) {
-        auto it = ipb.find(S.n);
-        if (it != ipb.end()) std::copy(it->second.begin(), it->second.end(), S.ipb);
-    }
-    b_invalidate(B);
     return LSMG_OK;
 }
 
@@ -1000,14 +953,9 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
             zero_bnorms(B, 1, 1, s);
             // the first size class holding a level of a solving member (members only
             // leave during a chunk)
-            int z0 = (int)B->sizes.size(), pm = 0;
+            int z0 = (int)B->sizes.size();
             for (int k = 0; k < nk; ++k)
-                if (lin[k]) {
-                    z0 = std::min(z0, B->zfin[k]);
-                    pm = std::max(pm, B->pos[k] + 1);
-                }
-            // and the members up to the last one solving, in the batch's order
-            B->P = B->mm ? pm : nk;
+                if (lin[k]) z0 = std::min(z0, B->zfin[k]);
             hipGraphExec_t gc = nullptr;
             // timed launches run direct: events inside a graph cannot be timed
             if (B->use_graphs && B->prof_kernel < 0) LSMGCHK(b_graph(B, mixed, &gc, true, z0));
@@ -1015,7 +963,6 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
                 if (gc) HIPCHK(hipGraphLaunch(gc, s));
                 else b_cycle_enqueue(B, mixed, s, true, z0);
             }
-            B->P = nk;
             B->act_last.clear();   // the chunk cleared the flags of the members that stopped
             HIPCHK(hipMemcpyAsync(B->h_hist, B->d_hist, sizeof(double) * (size_t)kc * nk, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -1088,7 +1035,6 @@ lsmg_status lsmg_batch_step(lsmg_batch *b, lsmg_state *const *states, double dt,
         }
         B->mem[k]->lin_set = false;
     }
-    if (B->mm && !B->ordered) LSMGCHK(b_reorder(B, cycles));
     if (first_bad != LSMG_OK) {
         for (int k = 0; k < nk; ++k)
             if (rc[k] != LSMG_OK) {
