@@ -976,7 +976,8 @@ def run_prepare(args):
     achieved = bytes_per_iter * iters / (per_call * 1e-3) / 1e9
     cpu = None
     if not args.no_cpu_baseline:
-        phi_np = phi_mask.cpu().numpy()
+        # the oracle's own level set of the same mask (no input from the GPU path)
+        phi_np = oracle.levelset_from_mask(I.necklace_mask(n).astype(np.uint8), dim, n, 8)
         k = 0
         t1 = time.perf_counter()
         while time.perf_counter() - t1 < min(args.cpu_budget, 10.0):
