@@ -57,7 +57,7 @@ def _load():
                              ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     lib.or_free.argtypes = [vp]
     lib.or_free.restype = None
-    lib.or_set_params.argtypes = [vp] + [ctypes.c_double] * 7 + [ctypes.c_int] * 6 + [ctypes.c_double] + [ctypes.c_int] * 3
+    lib.or_set_params.argtypes = [vp] + [ctypes.c_double] * 7 + [ctypes.c_int] * 6 + [ctypes.c_double] + [ctypes.c_int] * 4
     lib.or_num_levels.argtypes = [vp]
     lib.or_level_info.argtypes = [vp, ctypes.c_int, _I, _D, _I, _I, _I]
     lib.or_compact_to_grid.argtypes = [vp, ctypes.c_int, _L]
@@ -79,6 +79,7 @@ def _load():
                                       ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                       ctypes.POINTER(_Stats), _D, ctypes.c_int]
     lib.or_lu_solve_dense.argtypes = [_D, _D, ctypes.c_int]
+    lib.or_krylov_solve.argtypes = [vp, _D, _D, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     lib.or_reinitialize.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _D]
     lib.or_levelset_from_mask.argtypes = [ctypes.POINTER(ctypes.c_ubyte), ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
     lib.or_extrapolate.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int, _D]
@@ -156,7 +157,8 @@ class Hierarchy:
         self.nlev = lib.or_num_levels(h)
         self.params = dict(a=1e4, d=0.1, m_s=64.06, m_c=100.09, alpha=0.01, beta=0.1,
                            tau_s=0.9, nu1=2, nu2=2, ghost_c_new=1, band_steps=3,
-                           ghost_sweeps=1, ghost_sweeps_coarse=None, sweeps_lambda=0.3, gamma=1, lex=0, fmg=0)
+                           ghost_sweeps=1, ghost_sweeps_coarse=None, sweeps_lambda=0.3, gamma=1, lex=0, fmg=0,
+                           krylov_m=0)
         if params:
             self.set_params(**params)
 
@@ -175,7 +177,7 @@ class Hierarchy:
                                      int(p["ghost_sweeps"] if p["ghost_sweeps_coarse"] is None
                                          else p["ghost_sweeps_coarse"]),
                                      float(p["sweeps_lambda"]), int(p["gamma"]), int(p["lex"]),
-                                     int(p["fmg"])), "set_params")
+                                     int(p["fmg"]), int(p["krylov_m"])), "set_params")
 
     # --- geometry ---------------------------------------------------------
     def level_info(self, l):
@@ -271,6 +273,15 @@ class Hierarchy:
         rhs = _f64(rhs); x = _f64(x).copy(); res = ctypes.c_double()
         _check(_load().or_vcycle(self._h, l, _dp(rhs), _dp(x), ctypes.byref(res)), "vcycle")
         return x, res.value
+
+    def krylov_solve(self, F, m=30, rtol=1e-3, cycles_max=30):
+        """Flexible GMRES(m) on level 0 at the current linearisation point, preconditioned
+        by one V-cycle: returns (x, V-cycles taken)."""
+        F = _f64(F); x = np.zeros_like(F)
+        rc = _load().or_krylov_solve(self._h, _dp(F), _dp(x), int(m), float(rtol), int(cycles_max))
+        if rc < 0:
+            raise OracleError(rc, "krylov_solve")
+        return x, rc
 
     def assemble_dense(self, l):
         N = 2 * self.level_info(l)["na"]

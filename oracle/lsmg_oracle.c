@@ -75,6 +75,8 @@ typedef struct {
                           collective Gauss-Seidel, §3.5.1); 0: red-black */
     int fmg;           /* full multigrid as the first iteration of the linear solves:
                           0 never, 1 in the first Newton iteration of a step, 2 in every one */
+    int krylov_m;      /* 0: the linear solves iterate V-cycles (the paper); m > 0: flexible
+                          GMRES(m) preconditioned by one V-cycle (not in the paper) */
 } OPar;
 
 typedef struct or_hier {
@@ -598,7 +600,7 @@ int or_build(const double *phi, int dim, int n, double lo, double hi, int coarse
     H->p.alpha = 0.01; H->p.beta = 0.1; H->p.tau_s = 0.9;
     H->p.nu1 = 2; H->p.nu2 = 2; H->p.ghost_c_new = 1; H->p.band_steps = 3; H->p.ghost_sweeps = 1;
     H->p.ghost_sweeps_coarse = 1; H->p.sweeps_lambda = 0.3;
-    H->p.gamma = 1; H->p.lex = 0; H->p.fmg = 0;
+    H->p.gamma = 1; H->p.lex = 0; H->p.fmg = 0; H->p.krylov_m = 0;
     nl = n;
     for (int l = 0; l < nlev; ++l) {
         OLevel *L = &H->L[l];
@@ -651,10 +653,13 @@ void or_free(or_hier *H)
 
 int or_set_params(or_hier *H, double a, double d, double m_s, double m_c, double alpha, double beta,
                   double tau_s, int nu1, int nu2, int ghost_c_new, int band_steps, int ghost_sweeps,
-                  int ghost_sweeps_coarse, double sweeps_lambda, int gamma, int lex, int fmg)
+                  int ghost_sweeps_coarse, double sweeps_lambda, int gamma, int lex, int fmg,
+                  int krylov_m)
 {
-    if (gamma < 1 || gamma > 2 || lex < 0 || lex > 1 || fmg < 0 || fmg > 2) return OR_EINVAL;
+    if (gamma < 1 || gamma > 2 || lex < 0 || lex > 1 || fmg < 0 || fmg > 2 || krylov_m < 0 || krylov_m > 200)
+        return OR_EINVAL;
     H->p.fmg = fmg;
+    H->p.krylov_m = krylov_m;
     H->p.gamma = gamma;
     H->p.lex = lex;
     H->p.ghost_sweeps = ghost_sweeps;
@@ -1485,6 +1490,123 @@ typedef struct {
  * the defect drops below lin_rtol * ||F||_inf or cycles_max cycles ran
  * (READING: the paper gives no inner tolerance).  rho_hist (optional,
  * capacity rho_cap) receives the convergence factor of every cycle. */
+/* ------------------------------------------------------------------ */
+/* Krylov acceleration of the linear solves (krylov_m > 0)             */
+/* ------------------------------------------------------------------ */
+
+static double dot(const double *a, const double *b, int N)
+{
+    double t = 0.0;
+    for (int r = 0; r < N; ++r) t += a[r] * b[r];
+    return t;
+}
+
+/* z = one V-cycle on level 0 from a zero correction with right-hand side v
+ * (compact vectors) */
+static void precondition(or_hier *H, const double *v, double *z)
+{
+    OLevel *L = &H->L[0];
+    for (long g = 0; g < L->nn; ++g) { L->rhs_s[g] = L->rhs_c[g] = L->x_s[g] = L->x_c[g] = 0.0; }
+    to_grid(L, v, L->rhs_s, L->rhs_c);
+    vcycle_rec(H, 0);
+    from_grid(L, L->x_s, L->x_c, z);
+}
+
+/* Flexible GMRES(m) for J x = F on level 0 (Saad's flexible variant: the
+ * preconditioned vectors Z_j = M(V_j) are kept, so the preconditioner need not
+ * be a fixed linear map), M one V-cycle from zero.  The new direction is made
+ * orthogonal to V_0..V_j by classical Gram-Schmidt applied twice (all inner
+ * products of a pass taken before the pass subtracts them); the small
+ * least-squares problem is reduced by Givens rotations, whose last rotated
+ * entry |g_{j+1}| is the 2-norm of the defect F - J x_j.  The solve starts
+ * from x = 0, stops when that norm is at most rtol |F|_2 or after cycles_max
+ * V-cycles, and restarts from its current x every m iterations.  x: N values
+ * on exit; cycles, rho: V-cycles taken and the last ratio of consecutive
+ * defect norms (the caller's statistics). */
+static void krylov_solve(or_hier *H, const double *F, double *x, int m, double rtol, int cycles_max,
+                         int *cycles, double *rho_last, double *logsum, int *nrho, double *rho_hist,
+                         int rho_cap)
+{
+    const int N = 2 * H->L[0].na;
+    double *V = dalloc((long)(m + 1) * N), *Z = dalloc((long)m * N), *w = dalloc(N), *r = dalloc(N);
+    double *Hh = dalloc((long)(m + 1) * m), *cs = dalloc(m), *sn = dalloc(m), *g = dalloc(m + 1),
+           *y = dalloc(m), *hp = dalloc(m + 1);
+    for (int i = 0; i < N; ++i) { x[i] = 0.0; r[i] = F[i]; }
+    const double target = rtol * sqrt(dot(F, F, N));
+    double beta = sqrt(dot(r, r, N));
+    int used = 0;
+    while (beta > target && used < cycles_max) {
+        for (int i = 0; i < N; ++i) V[i] = r[i] / beta;
+        for (long e = 0; e < (long)(m + 1) * m; ++e) Hh[e] = 0.0;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        double prev = beta;
+        int k = 0;
+        for (int j = 0; j < m && used < cycles_max; ++j) {
+            precondition(H, V + (long)j * N, Z + (long)j * N);
+            ++used;
+            or_apply_J(H, 0, Z + (long)j * N, w);
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i <= j; ++i) hp[i] = dot(w, V + (long)i * N, N);
+                for (int i = 0; i <= j; ++i) {
+                    Hh[(long)i * m + j] += hp[i];
+                    for (int q = 0; q < N; ++q) w[q] -= hp[i] * V[(long)i * N + q];
+                }
+            }
+            const double hn = sqrt(dot(w, w, N));
+            Hh[(long)(j + 1) * m + j] = hn;
+            for (int q = 0; q < N; ++q) V[(long)(j + 1) * N + q] = hn > 0.0 ? w[q] / hn : 0.0;
+            /* the earlier rotations on column j, then the one that zeroes its last entry */
+            for (int i = 0; i < j; ++i) {
+                const double a = Hh[(long)i * m + j], b = Hh[(long)(i + 1) * m + j];
+                Hh[(long)i * m + j] = cs[i] * a + sn[i] * b;
+                Hh[(long)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = Hh[(long)j * m + j], b = Hh[(long)(j + 1) * m + j];
+            const double d = sqrt(a * a + b * b);
+            cs[j] = d > 0.0 ? a / d : 1.0;
+            sn[j] = d > 0.0 ? b / d : 0.0;
+            Hh[(long)j * m + j] = d;
+            Hh[(long)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            const double res = fabs(g[j + 1]);
+            *rho_last = prev > 0.0 ? res / prev : 0.0;
+            if (*rho_last > 0.0) *logsum += log(*rho_last);
+            if (rho_hist && *nrho < rho_cap) rho_hist[*nrho] = *rho_last;
+            ++*nrho;
+            prev = res;
+            if (res <= target || hn == 0.0 || !(res == res)) break;
+        }
+        /* x += Z y with R y = g, R the rotated k x k upper triangle */
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int q = i + 1; q < k; ++q) t -= Hh[(long)i * m + q] * y[q];
+            y[i] = t / Hh[(long)i * m + i];
+        }
+        for (int i = 0; i < k; ++i)
+            for (int q = 0; q < N; ++q) x[q] += y[i] * Z[(long)i * N + q];
+        or_apply_J(H, 0, x, w);
+        for (int q = 0; q < N; ++q) r[q] = F[q] - w[q];
+        beta = sqrt(dot(r, r, N));
+        if (!(beta == beta)) break;
+    }
+    *cycles += used;
+    free(V); free(Z); free(w); free(r); free(Hh); free(cs); free(sn); free(g); free(y); free(hp);
+}
+
+/* the Krylov solve alone, for its tests: x (compact) from F at the current
+ * linearisation point; returns the V-cycles taken */
+int or_krylov_solve(or_hier *H, const double *F, double *x, int m, double rtol, int cycles_max)
+{
+    if (!H->lin_set || m < 1 || m > 200 || cycles_max < 0) return OR_EINVAL;
+    int cycles = 0, nrho = 0;
+    double rho = 0.0, logsum = 0.0;
+    krylov_solve(H, F, x, m, rtol, cycles_max, &cycles, &rho, &logsum, &nrho, NULL, 0);
+    return cycles;
+}
+
 int or_newton_cn_step(or_hier *H, double *W, double dt, const double *sb, const double *fn,
                       const double *fnp1, double newton_tol, int newton_max, double lin_rtol,
                       int cycles_max, or_stats *st, double *rho_hist, int rho_cap)
@@ -1502,6 +1624,11 @@ int or_newton_cn_step(or_hier *H, double *W, double dt, const double *sb, const 
     for (it = 1; it <= newton_max; ++it) {
         if (!(nF == nF) || isinf(nF)) { rc = OR_ENONFINITE; break; }
         if (or_set_linearization(H, Wk, dt) != OR_OK) { rc = OR_ENONFINITE; break; }
+        if (H->p.krylov_m > 0) {
+            krylov_solve(H, Fv, Dx, H->p.krylov_m, lin_rtol, cycles_max, &cycles, &rho_last, &logsum, &nrho,
+                         rho_hist, rho_cap);
+            goto update;
+        }
         /* J dW = F by V-cycles from dW = 0 */
         for (long g = 0; g < L->nn; ++g) { L->rhs_s[g] = L->rhs_c[g] = L->x_s[g] = L->x_c[g] = 0.0; }
         to_grid(L, Fv, L->rhs_s, L->rhs_c);
@@ -1520,6 +1647,7 @@ int or_newton_cn_step(or_hier *H, double *W, double dt, const double *sb, const 
             if (!(rq == rq) || isinf(rq)) break;
         }
         from_grid(L, L->x_s, L->x_c, Dx);
+    update:;
         double nW = 0.0, nD = 0.0;
         for (int r = 0; r < N; ++r) {
             double a = fabs(Wk[r]), b = fabs(Dx[r]);
