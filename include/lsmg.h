@@ -96,6 +96,16 @@ typedef struct {
                             * tiles of rows, the red half-sweep recomputed on a one-node halo
                             * (same bits as one launch per colour); 0 one launch per colour.
                             * A batch fuses its sweeps when every member has fused_sweep = 1 */
+    int krylov_m;          /* 0: the linear solve of each Newton iteration iterates V-cycles
+                            * (section 3.5); m in 1..200: flexible GMRES(m) on the same system,
+                            * right-preconditioned by one V-cycle from a zero correction (the FP32
+                            * cycle in mixed precision), restarted from the true defect every m
+                            * iterations, stopping when the 2-norm of the defect is at most
+                            * lin_rtol times that of F or after cycles_max cycles; fmg is not used.
+                            * Not in the paper: it removes the few slow modes that ghost rows with a
+                            * tiny self-weight leave to the cycles.  Single hierarchies only (a batch
+                            * refuses members with krylov_m > 0, LSMG_ENOTIMPL); its vectors take
+                            * (2m + 4) 2 Na doubles of device memory, allocated at the first solve */
 } lsmg_params;
 
 typedef struct lsmg_hierarchy lsmg_hierarchy;

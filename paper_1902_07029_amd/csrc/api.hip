@@ -49,7 +49,7 @@ lsmg_status check_params(const lsmg_params *p)
         p->band_steps > 3 || p->coarsest_n < 3 || p->newton_max < 1 || p->cycles_max < 1 ||
         !(p->lin_rtol > 0.0) || !(p->newton_tol > 0.0) || (p->precision != 0 && p->precision != 1) ||
         (p->bc != 0 && p->bc != 1) || p->cycle_gamma < 1 || p->cycle_gamma > 2 || p->fmg < 0 || p->fmg > 2 ||
-        (p->fused_sweep != 0 && p->fused_sweep != 1))
+        (p->fused_sweep != 0 && p->fused_sweep != 1) || p->krylov_m < 0 || p->krylov_m > 200)
         return fail(LSMG_EINVAL, "invalid solver parameters");
     return LSMG_OK;
 }
@@ -1167,6 +1167,146 @@ lsmg_status linear_solve(lsmg_hierarchy *H, double nF, int *cycles, double *rho_
     return LSMG_OK;
 }
 
+// Flexible GMRES(m) for the Newton system J dW = F on level 0 (krylov_m = m > 0),
+// right-preconditioned by one V-cycle from zero (the FP32 cycle in mixed
+// precision, which is why the preconditioned vectors Z_j are kept: Saad's
+// flexible variant).  The vectors are compact (2 Na values) and enter the cycle
+// and the operator through the level-0 storage arrays.  Each new direction is
+// made orthogonal to V_0..V_j by classical Gram-Schmidt applied twice, on the
+// device (inner products summed in a fixed order); its coefficients and norm
+// come back to the host once per iteration for the Givens rotations of the
+// small least-squares problem, whose last rotated entry is the 2-norm of the
+// defect.  From x = 0, until that norm is at most lin_rtol |F|_2 or cycles_max
+// cycles have run, restarting from the true defect every m iterations.  F is in
+// the level-0 right-hand side on entry; the correction is left in the level-0
+// correction arrays, as after linear_solve.
+lsmg_status krylov_solve(lsmg_hierarchy *H, int *cycles, double *rho_last, double *logsum, int *nrho,
+                         bool factor_first)
+{
+    const Level &L0 = H->L[0];
+    const int m = H->p.krylov_m;
+    const long long N = 2LL * L0.na;
+    const bool mixed = H->p.precision == 1;
+    hipStream_t s = H->stream;
+    if (factor_first) {
+        launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, s);
+        LSMGCHK(check_factor(H));
+    }
+    if (N == 0) return LSMG_OK;
+    if (H->km < m) {
+        // buffers for a larger m replace the earlier ones, which are kept until the
+        // hierarchy is destroyed
+        LSMGCHK(H->alloc(&H->kv, (long long)(m + 1) * N));
+        LSMGCHK(H->alloc(&H->kz, (long long)m * N));
+        LSMGCHK(H->alloc(&H->kf, N));
+        LSMGCHK(H->alloc(&H->kx, N));
+        LSMGCHK(H->alloc(&H->kw, N));
+        LSMGCHK(H->alloc(&H->kpart, (long long)(m + 1) * kKvBlocks));
+        LSMGCHK(H->alloc(&H->kres, 2LL * (m + 1) + 1));
+        LSMGCHK(H->alloc(&H->kcoef, m));
+        H->km = m;
+    }
+    double *V = H->kv, *Z = H->kz, *Fv = H->kf, *X = H->kx, *Wv = H->kw;
+    auto vec = [&](double *b, int i) { return b + (size_t)i * N; };
+    std::vector<double> hres(2 * (m + 1) + 1), Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto read = [&](int count) -> lsmg_status {
+        HIPCHK(hipMemcpyAsync(hres.data(), H->kres, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return LSMG_OK;
+    };
+    gather<double>(H, 0, L0.rhs_s, L0.rhs_c, Fv);
+    launch_kv_div(X, X, N, 0.0, s);
+    launch_kv_dots(Fv, Fv, N, 1, H->kpart, H->kres, s);
+    LSMGCHK(read(1));
+    const double target = H->p.lin_rtol * std::sqrt(hres[0]);
+    double beta = std::sqrt(hres[0]);
+    const double *r = Fv;   // the defect of x = 0
+    int used = 0;
+    while (beta > target && used < H->p.cycles_max) {
+        launch_kv_div(vec(V, 0), r, N, beta, s);
+        std::fill(Hh.begin(), Hh.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        double prev = beta;
+        int k = 0;
+        for (int j = 0; j < m && used < H->p.cycles_max; ++j) {
+            const size_t mark0 = H->prof_used;
+            // Z_j = M V_j: one cycle on the level-0 arrays from a zero correction
+            scatter<double>(H, 0, vec(V, j), L0.rhs_s, L0.rhs_c);
+            if (mixed) {
+                launch_start_mixed(H->dim, H->d64, L0.w_act(), L0.nw_act(), with_tail(Exec(s), L0.nghc), H->d32);
+                vcycle_rec<float>(H, 0, s);
+                launch_add_f32(H->dim, H->d64, H->d32, L0.w_act(), L0.nw_act(), with_tail(Exec(s), L0.nghc));
+            } else {
+                zero_active_x(H, 0);
+                vcycle_rec<double>(H, 0, s);
+            }
+            ++used;
+            gather<double>(H, 0, L0.x_s, L0.x_c, vec(Z, j));
+            // J Z_j (the operator reads the level-0 correction, which holds Z_j)
+            launch_apply_J<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), Exec(s));
+            double *w = vec(V, j + 1);
+            gather<double>(H, 0, L0.r_s, L0.r_c, w);
+            launch_kv_dots(w, V, N, j + 1, H->kpart, H->kres, s);
+            launch_kv_update(w, V, N, j + 1, H->kres, -1.0, s);
+            launch_kv_dots(w, V, N, j + 1, H->kpart, H->kres + (m + 1), s);
+            launch_kv_update(w, V, N, j + 1, H->kres + (m + 1), -1.0, s);
+            launch_kv_dots(w, w, N, 1, H->kpart, H->kres + 2 * (m + 1), s);
+            LSMGCHK(read(2 * (m + 1) + 1));
+            if (H->prof_kernel >= 0) {
+                prof_collect(H, mark0, H->prof_used);
+                H->prof_used = mark0;
+            }
+            for (int i = 0; i <= j; ++i) Hh[(size_t)i * m + j] = (0.0 + hres[i]) + hres[m + 1 + i];
+            const double hn = std::sqrt(hres[2 * (m + 1)]);
+            Hh[(size_t)(j + 1) * m + j] = hn;
+            launch_kv_div(w, w, N, hn, s);
+            // the earlier rotations on column j, then the one that zeroes its last entry
+            for (int i = 0; i < j; ++i) {
+                const double a = Hh[(size_t)i * m + j], b = Hh[(size_t)(i + 1) * m + j];
+                Hh[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                Hh[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = Hh[(size_t)j * m + j], b = Hh[(size_t)(j + 1) * m + j];
+            const double d = std::sqrt(a * a + b * b);
+            cs[j] = d > 0.0 ? a / d : 1.0;
+            sn[j] = d > 0.0 ? b / d : 0.0;
+            Hh[(size_t)j * m + j] = d;
+            Hh[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            const double res = std::fabs(g[j + 1]);
+            *rho_last = prev > 0.0 ? res / prev : 0.0;
+            if (*rho_last > 0.0) *logsum += std::log(*rho_last);
+            ++*nrho;
+            prev = res;
+            if (res <= target || hn == 0.0 || !std::isfinite(res)) break;
+        }
+        // x += Z y, R y = g with R the rotated k x k upper triangle
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int q = i + 1; q < k; ++q) t -= Hh[(size_t)i * m + q] * y[q];
+            y[i] = t / Hh[(size_t)i * m + i];
+        }
+        HIPCHK(hipMemcpyAsync(H->kcoef, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        launch_kv_update(X, Z, N, k, H->kcoef, 1.0, s);
+        // the true defect F - J x
+        scatter<double>(H, 0, X, L0.x_s, L0.x_c);
+        launch_apply_J<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), Exec(s));
+        gather<double>(H, 0, L0.r_s, L0.r_c, Wv);
+        launch_kv_rsub(Wv, Fv, N, s);
+        launch_kv_dots(Wv, Wv, N, 1, H->kpart, H->kres, s);
+        LSMGCHK(read(1));
+        beta = std::sqrt(hres[0]);
+        r = Wv;
+        if (!std::isfinite(beta)) break;
+    }
+    scatter<double>(H, 0, X, L0.x_s, L0.x_c);
+    *cycles += used;
+    return LSMG_OK;
+}
+
 // names the Crank-Nicolson step's arrays in the level-0 descriptor (pushed
 // only when they change)
 lsmg_status set_step(lsmg_hierarchy *H, const double *sn, const double *cn, const double *sb, double sb_const,
@@ -1228,6 +1368,7 @@ void lsmg_default_params(lsmg_params *p)
     p->cycle_gamma = 1;
     p->fmg = 0;
     p->fused_sweep = 1;
+    p->krylov_m = 0;
 }
 
 const char *lsmg_last_error(void) { return g_err.c_str(); }
@@ -1530,8 +1671,11 @@ lsmg_status lsmg_newton_cn_step(lsmg_hierarchy *h, lsmg_state *st, double dt, co
         }
         // the coarsest factorisation runs inside the first cycle, and is checked with its norms
         LSMGCHK(linearize(h, false));
-        LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho,
-                             h->p.fmg == 2 || (h->p.fmg == 1 && it == 1), true));
+        if (h->p.krylov_m > 0)
+            LSMGCHK(krylov_solve(h, &cycles, &rho_last, &logsum, &nrho, true));
+        else
+            LSMGCHK(linear_solve(h, nF, &cycles, &rho_last, &logsum, &nrho,
+                                 h->p.fmg == 2 || (h->p.fmg == 1 && it == 1), true));
         zero_norms(h, 0, 4);
         launch_newton_update(h->dim, h->d64, L0.w_act(), L0.nw_act(), with_tail(Exec(s), L0.nghc));
         launch_residual(h->dim, h->d64, L0.w_act(), L0.nw_act(), 0, with_tail(Exec(s), L0.nghc));

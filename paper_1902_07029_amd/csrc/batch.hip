@@ -758,6 +758,8 @@ lsmg_status lsmg_batch_create(lsmg_hierarchy *const *members, int count, const l
             return fail(LSMG_ENOTIMPL, "batches run V-cycles (cycle_gamma = 1) without full multigrid (fmg = 0)");
         if (!members[k]->p.ghost_c_new)
             return fail(LSMG_ENOTIMPL, "batches use the composed ghost relaxation (ghost_c_new = 1)");
+        if (members[k]->p.krylov_m != 0)
+            return fail(LSMG_ENOTIMPL, "batches iterate V-cycles (krylov_m = 0)");
         if (members[k]->p.precision == 1 && !members[k]->have32) return fail(LSMG_EINVAL, "member %d has no FP32 copy", k);
     }
     lsmg_batch *B = new (std::nothrow) lsmg_batch();

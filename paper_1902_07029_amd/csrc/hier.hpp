@@ -128,6 +128,13 @@ struct lsmg_hierarchy {
                  *step_sb = nullptr;
     double step_sb_const = 0.0;
     int *h_status = nullptr;
+    // Krylov solve (krylov_m > 0): m + 1 basis vectors, m preconditioned vectors, F,
+    // the iterate and a work vector (compact, 2 Na each), inner-product partial sums
+    // and results, and the least-squares coefficients; allocated at the first solve
+    // for its m (km)
+    int km = 0;
+    double *kv = nullptr, *kz = nullptr, *kf = nullptr, *kx = nullptr, *kw = nullptr, *kpart = nullptr,
+           *kres = nullptr, *kcoef = nullptr;
     DevMem mem;              // device memory: the caller's allocator or hipMalloc
     std::vector<void *> allocs;
     size_t alloc_bytes = 0;  // device bytes held through alloc()

@@ -2169,6 +2169,106 @@ void launch_fill(T *p, long long n, T v, hipStream_t s)
 
 void launch_zero_u64(unsigned long long *p, int n, hipStream_t s) { k_zero_u64<<<1, 256, 0, s>>>(p, n); }
 
+// ---------------------------------------------------------------------------
+// vectors of the Krylov solve (compact level-0 vectors of N values).  Inner
+// products are summed in a fixed order, so that a result does not depend on
+// timing: block b sums, for each thread, the elements b * kKvThreads + t +
+// k * kKvBlocks * kKvThreads in order of k, then the block's threads by a fixed
+// tree; a second kernel sums the blocks' partial sums the same way.
+// ---------------------------------------------------------------------------
+constexpr int kKvThreads = 256;
+
+__device__ __forceinline__ double block_tree_sum(double *sh, double t)
+{
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int st = kKvThreads / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// part[i * kKvBlocks + b] = block b's share of <w, v_i>, v_i = vb + i N, i < nv
+__global__ __launch_bounds__(kKvThreads) void k_kv_dots(const double *__restrict__ w, const double *__restrict__ vb,
+                                                        long long N, int nv, double *__restrict__ part)
+{
+    __shared__ double sh[kKvThreads];
+    const long long stride = (long long)kKvBlocks * kKvThreads;
+    for (int i = 0; i < nv; ++i) {
+        const double *v = vb + (long long)i * N;
+        double t = 0.0;
+        for (long long q = (long long)blockIdx.x * kKvThreads + threadIdx.x; q < N; q += stride)
+            t = fma(w[q], v[q], t);
+        const double r = block_tree_sum(sh, t);
+        if (threadIdx.x == 0) part[(long long)i * kKvBlocks + blockIdx.x] = r;
+    }
+}
+
+// out[i] = sum of the kKvBlocks partial sums of vector i (block i)
+__global__ __launch_bounds__(kKvThreads) void k_kv_final(const double *__restrict__ part, double *__restrict__ out)
+{
+    __shared__ double sh[kKvThreads];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < kKvBlocks; b += kKvThreads) t += part[(long long)blockIdx.x * kKvBlocks + b];
+    const double r = block_tree_sum(sh, t);
+    if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
+// w += sign sum_{i < nv} coef[i] v_i, the terms taken in order of i
+__global__ void k_kv_update(double *__restrict__ w, const double *__restrict__ vb, long long N, int nv,
+                            const double *__restrict__ coef, double sign)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    double t = w[q];
+    for (int i = 0; i < nv; ++i) t += sign * (coef[i] * vb[(long long)i * N + q]);
+    w[q] = t;
+}
+
+// y = x / a (a != 0), or y = 0 (a == 0, x not read)
+__global__ void k_kv_div(double *__restrict__ y, const double *__restrict__ x, long long N, double a)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    y[q] = a != 0.0 ? x[q] / a : 0.0;
+}
+
+// y = x - y
+__global__ void k_kv_rsub(double *__restrict__ y, const double *__restrict__ x, long long N)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    y[q] = x[q] - y[q];
+}
+
+void launch_kv_dots(const double *w, const double *vb, long long N, int nv, double *part, double *out, hipStream_t s)
+{
+    if (nv <= 0) return;
+    k_kv_dots<<<kKvBlocks, kKvThreads, 0, s>>>(w, vb, N, nv, part);
+    k_kv_final<<<nv, kKvThreads, 0, s>>>(part, out);
+}
+
+void launch_kv_update(double *w, const double *vb, long long N, int nv, const double *coef, double sign, hipStream_t s)
+{
+    if (N <= 0 || nv <= 0) return;
+    k_kv_update<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(w, vb, N, nv, coef, sign);
+}
+
+void launch_kv_div(double *y, const double *x, long long N, double a, hipStream_t s)
+{
+    if (N <= 0) return;
+    k_kv_div<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(y, x, N, a);
+}
+
+void launch_kv_rsub(double *y, const double *x, long long N, hipStream_t s)
+{
+    if (N <= 0) return;
+    k_kv_rsub<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(y, x, N);
+}
+
 void launch_norm_reduce(const unsigned long long *base, long long stride, int ndom, int first, int count,
                         unsigned long long *out, hipStream_t s)
 {

@@ -191,6 +191,14 @@ template <typename T> void launch_gather_compact(const int *c2s, int na, const T
 template <typename T> void launch_scatter_compact(const int *c2s, int na, const double *v, T *a, T *b, hipStream_t s);
 template <typename T> void launch_fill(T *p, long long n, T v, hipStream_t s);
 void launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+// vectors of the Krylov solve: inner products <w, v_i> (i < nv, v_i = vb + i N) into
+// out[0..nv) through part (kKvBlocks per vector), summed in a fixed order;
+// w += sign sum coef[i] v_i; y = x / a (y = 0 for a = 0); y = x - y
+constexpr int kKvBlocks = 512;
+void launch_kv_dots(const double *w, const double *vb, long long N, int nv, double *part, double *out, hipStream_t s);
+void launch_kv_update(double *w, const double *vb, long long N, int nv, const double *coef, double sign, hipStream_t s);
+void launch_kv_div(double *y, const double *x, long long N, double a, hipStream_t s);
+void launch_kv_rsub(double *y, const double *x, long long N, hipStream_t s);
 void launch_norm_reduce(const unsigned long long *base, long long stride, int ndom, int first, int count,
                         unsigned long long *out, hipStream_t s);
 // linear-solve control of one domain of a batch whose cycles run in chunks on the

@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("precision", ctypes.c_int), ("newton_tol", ctypes.c_double),
                 ("newton_max", ctypes.c_int), ("lin_rtol", ctypes.c_double), ("cycles_max", ctypes.c_int),
                 ("sweeps_lambda", ctypes.c_double), ("bc", ctypes.c_int), ("cycle_gamma", ctypes.c_int),
-                ("fmg", ctypes.c_int), ("fused_sweep", ctypes.c_int)]
+                ("fmg", ctypes.c_int), ("fused_sweep", ctypes.c_int),
+                ("krylov_m", ctypes.c_int)]
 
 
 class StepStats(ctypes.Structure):

@@ -17,7 +17,7 @@ def oracle_params(p):
     return dict(a=p.a, d=p.d, m_s=p.m_s, m_c=p.m_c, alpha=p.alpha, beta=p.beta, tau_s=p.tau_s, nu1=p.nu1,
                 nu2=p.nu2, ghost_c_new=p.ghost_c_new, band_steps=p.band_steps, ghost_sweeps=p.ghost_sweeps,
                 ghost_sweeps_coarse=p.ghost_sweeps_coarse, sweeps_lambda=p.sweeps_lambda, gamma=p.cycle_gamma,
-                fmg=p.fmg)
+                fmg=p.fmg, krylov_m=p.krylov_m)
 
 
 def pair(kind, n, coarsest, phi=None, **params):
