@@ -51,10 +51,19 @@ WORKLOADS = {
     # s_B = 1, dt = h, N = 256, W(2,1), 8 x 8 coarsest grid; box [-pi/2, pi/2]^2
     "paper3": dict(kind="paper_circle", dim=2, n=257, coarsest=9, dt=None, steps=20, box=I.PAPER_BOX, c0=10.0,
                    params=dict(nu1=2, nu2=1, cycle_gamma=2)),
+    # single requests of the served stream (seed 0) stepped alone: request 22 (257^3, four
+    # ellipsoids, smoothed union; its slow ghost modes set the serving p99) and request 10
+    # (65^3, three ellipsoids) on its plain, creased union
+    "request22": dict(kind="request", id=22, smooth=0.02, dim=3, n=257, coarsest=9, dt=1e-4, steps=160),
+    "request10_creased": dict(kind="request", id=10, smooth=0.0, dim=3, n=65, coarsest=9, dt=1e-4, steps=20),
 }
 
 
 def levelset(w):
+    if w["kind"] == "request":
+        r = [q for q in I.serving_requests(24, seed=0) if q["id"] == w["id"]][0]
+        assert r["n"] == w["n"] and r["dt"] == w["dt"]
+        return I.ellipsoids(r["n"], r["centres"], r["semi"], smooth=w["smooth"])
     return {"star": I.star, "torus": I.torus, "disk": I.disk, "paper_circle": I.paper_circle}[w["kind"]](w["n"])
 
 
@@ -219,7 +228,7 @@ def oracle_params(H):
     eff = H.params
     return {k: getattr(eff, k) for k in ("a", "d", "m_s", "m_c", "alpha", "beta", "tau_s", "nu1", "nu2",
                                          "ghost_c_new", "band_steps", "ghost_sweeps", "ghost_sweeps_coarse",
-                                         "sweeps_lambda")} | {"gamma": eff.cycle_gamma, "fmg": eff.fmg}
+                                         "sweeps_lambda", "krylov_m")} | {"gamma": eff.cycle_gamma, "fmg": eff.fmg}
 
 
 # ---------------------------------------------------------------- profiling helpers
@@ -382,7 +391,7 @@ def run_single(args):
     prec = args.precision if args.precision is not None else 0
     bc = 1 if args.bc == "neumann" else 0
     params = lsmg.default_params(coarsest_n=w["coarsest"], precision=prec, bc=bc, fmg=args.fmg,
-                                 fused_sweep=args.fused, **w.get("params", {}))
+                                 fused_sweep=args.fused, krylov_m=args.krylov, **w.get("params", {}))
     phi_np = levelset(w)
     lo, hi = box_of(w)
     dt = dt_of(w)
@@ -493,7 +502,7 @@ def run_single(args):
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}_{'fp64' if prec == 0 else 'mixed'}" + ("_neumann" if bc else "")
-                        + (f"_fmg{args.fmg}" if args.fmg else ""),
+                        + (f"_fmg{args.fmg}" if args.fmg else "") + (f"_krylov{args.krylov}" if args.krylov else ""),
             "boundary": "neumann ds/dn = 1" if bc else "dirichlet s = 1",
             "domain": w["kind"], "dim": w["dim"], "n": w["n"], "dt": dt, "coarsest": w["coarsest"],
             "box": [lo, hi], "c0": w.get("c0", 1.0),
@@ -501,6 +510,8 @@ def run_single(args):
             "cycle": f"{'VW'[H.params.cycle_gamma - 1]}({H.params.nu1},{H.params.nu2}) red-black, {H.params.ghost_sweeps} ghost sweeps "
                      f"({H.params.ghost_sweeps_coarse} where d dt/h^2 < {H.params.sweeps_lambda})",
             "fused_sweep_levels": [l for l in range(H.nlev) if H.sweep_fused(l, prec)],
+            "linear_solve": (f"flexible GMRES({args.krylov}) preconditioned by one V-cycle" if args.krylov
+                             else "V-cycles"),
             "build_ms": round(build_ms, 1),
         },
         "vcycles": cycles,
@@ -1021,6 +1032,9 @@ def main():
     ap.add_argument("--fmg", type=int, default=0, choices=(0, 1, 2),
                     help="single domains: full multigrid as the first iteration of the first (1) or every (2) "
                          "linear solve of a step")
+    ap.add_argument("--krylov", type=int, default=0,
+                    help="single domains: the linear solves by flexible GMRES(M) preconditioned by one V-cycle "
+                         "(0: plain V-cycles)")
     ap.add_argument("--fused", type=int, default=1, choices=(0, 1),
                     help="2-D: both colours of a smoothing sweep in one launch (1) or one launch per colour (0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -70,3 +70,17 @@ def test_copy_probe_scale(tmp_path):
     lines = ["Counter_Name,Counter_Value"] + ["FETCH_SIZE,262144"] * 3 + ["FETCH_SIZE,12"]
     (d / "run_counter_collection.csv").write_text("\n".join(lines) + "\n")
     assert bench._pmc_copy(str(tmp_path / "copy"), "FETCH_SIZE", 512) == 2.0
+
+
+def test_request_workloads_are_the_served_requests():
+    # the single-request workloads step requests of the served stream (seed 0) alone,
+    # request 10 on its plain (creased) union
+    import lsmg_inputs as I
+    reqs = {r["id"]: r for r in I.serving_requests(24, seed=0)}
+    for name, smooth in (("request22", 0.02), ("request10_creased", 0.0)):
+        w = bench.WORKLOADS[name]
+        r = reqs[w["id"]]
+        assert (w["n"], w["dt"], w["smooth"]) == (r["n"], r["dt"], smooth)
+        if w["n"] <= 65:
+            phi = bench.levelset(w)
+            assert np.array_equal(phi, I.ellipsoids(r["n"], r["centres"], r["semi"], smooth=smooth))
