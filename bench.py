@@ -856,7 +856,7 @@ def run_serve(args):
     budget = int(args.budget_gb * (1 << 30)) if args.budget_gb else None
     # the served results of the requests whose whole oracle trajectories are stored
     checked = [rid for rid in (12, 17) if rid < len(reqs)]
-    server = Server(params, budget_bytes=budget, keep_states=set(checked))
+    server = Server(params, budget_bytes=budget, keep_states=set(checked), krylov_m=args.krylov)
     rep = server.run(reqs)
     parity = None
     if checked:
@@ -922,11 +922,16 @@ def run_serve(args):
         "vs_baseline": None,
         "dtype": "f64" if prec == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"serve{args.requests}_{'fp64' if prec == 0 else 'mixed'}",
+        "config": {"workload": f"serve{args.requests}_{'fp64' if prec == 0 else 'mixed'}"
+                               + (f"_krylov{args.krylov}" if args.krylov else ""),
                    "requests": len(reqs), "grid_sizes": sizes, "arrival_rate_per_s": rate, "load": args.load,
                    "budget_bytes": server.budget, "dt": 1e-4, "coarsest": 9},
         "p50_step_ms": rep["p50_step_ms"],
         "p99_step_ms": rep["p99_step_ms"],
+        # requests whose first step took more than 60 V-cycles and that then ran alone
+        # with Krylov solves (--krylov M; their steps are not in busy_s, which counts
+        # the batch's advance calls)
+        "krylov_lane": dict(m=args.krylov, requests=rep["krylov_lane"]) if args.krylov else None,
         "completed": rep["completed"],
         "makespan_s": rep["makespan_s"],
         "ticks": rep["ticks"],
@@ -1033,7 +1038,8 @@ def main():
                     help="single domains: full multigrid as the first iteration of the first (1) or every (2) "
                          "linear solve of a step")
     ap.add_argument("--krylov", type=int, default=0,
-                    help="single domains: the linear solves by flexible GMRES(M) preconditioned by one V-cycle "
+                    help="single domains: the linear solves by flexible GMRES(M) preconditioned by one V-cycle; "
+                         "serve: the Krylov lane for requests whose first step needs more than 60 V-cycles "
                          "(0: plain V-cycles)")
     ap.add_argument("--fused", type=int, default=1, choices=(0, 1),
                     help="2-D: both colours of a smoothing sweep in one launch (1) or one launch per colour (0)")

@@ -91,3 +91,64 @@ def test_failing_request_is_evicted_others_unchanged():
         f = by_id[r.id]
         assert f["status"] == lsmg.OK and f["steps"] == r.steps
         assert np.array_equal(f["state"], _alone(r, params)), r.id
+
+
+def _alone_with_lane(req, params, krylov_m, krylov_cycles):
+    # the lane's rule applied to one simulation on its own: after a first step of more
+    # than krylov_cycles V-cycles, the remaining steps use Krylov solves
+    H = lsmg.Hierarchy(torch.from_numpy(req.phi), req.dim, req.n, params=params)
+    st = lsmg.State(H)
+    nn = req.n ** req.dim
+    st.set_grid(torch.full((nn,), req.s0, dtype=torch.float64, device="cuda"),
+                torch.full((nn,), req.c0, dtype=torch.float64, device="cuda"))
+    lane = False
+    for k in range(req.steps):
+        _, stats = st.step(req.dt, sb_const=req.sb)
+        if k == 0 and stats["vcycles"] > krylov_cycles:
+            p = type(params).from_buffer_copy(params)
+            p.krylov_m = krylov_m
+            H.set_params(p)
+            lane = True
+    return st.get().cpu().numpy(), lane
+
+
+@pytest.mark.gpu
+def test_slow_request_moves_to_the_krylov_lane():
+    # request 10 of the served stream on its plain (creased) union needs about 212
+    # V-cycles in its first step: it leaves the batch after that step and finishes with
+    # Krylov solves beside two ordinary requests.  Every result equals the same
+    # simulation run alone under the same rule, and the slow one is within 1e-10 of the
+    # oracle stepping it the same way.
+    import oracle
+    from _gpu import oracle_params, rel
+    params = lsmg.default_params(coarsest_n=9, precision=1)
+    r10 = [q for q in I.serving_requests(24, seed=0) if q["id"] == 10][0]
+    n = r10["n"]
+    slow = Request(100, 0.0, 3, n, 3, r10["dt"], I.ellipsoids(n, r10["centres"], r10["semi"], smooth=0.0))
+    reqs = [slow] + _requests(2, 11, sizes=(33,), steps=(4, 6), gap=0.0)
+    rep = Server(params, keep_states=True, krylov_m=30, krylov_cycles=60).run(reqs)
+    assert rep["completed"] == len(reqs), rep["errors"]
+    say(f"Krylov lane: {rep['krylov_lane']}, p99 {rep['p99_step_ms']:.2f} ms, up to {rep['max_members']} in the batch")
+    assert rep["krylov_lane"] == [100]
+    by_id = {f["id"]: f for f in rep["finished"]}
+    for r in reqs:
+        state, lane = _alone_with_lane(r, params, 30, 60)
+        assert lane == (r.id == 100)
+        assert np.array_equal(by_id[r.id]["state"], state), r.id
+    # the effective parameters (automatic ghost sweep counts resolved) of a hierarchy of the domain
+    eff = lsmg.Hierarchy(torch.from_numpy(slow.phi), 3, n, params=params).params
+    O = oracle.Hierarchy(slow.phi, 3, n, coarsest_n=9, params=oracle_params(eff))
+    info = O.level_info(0)
+    s0, c0 = I.initial_state(n, 3)
+    W = O.to_compact(0, s0, c0)
+    sb = np.ones(info["ng"])
+    for k in range(slow.steps):
+        if k == 1:
+            O.set_params(krylov_m=30)
+        rc, W, _ = O.newton_cn_step(W, slow.dt, sb)
+        assert rc == 0
+    G = by_id[100]["state"]
+    na = info["na"]
+    e = max(rel(G[:na], W[:na]), rel(G[na:], W[na:]))
+    say(f"request 10 through the lane against the oracle: {e:.2e}")
+    assert e <= 1e-10
