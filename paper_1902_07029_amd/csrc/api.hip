@@ -1188,11 +1188,13 @@ lsmg_status krylov_solve(lsmg_hierarchy *H, int *cycles, double *rho_last, doubl
     const long long N = 2LL * L0.na;
     const bool mixed = H->p.precision == 1;
     hipStream_t s = H->stream;
-    if (factor_first) {
-        launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, s);
-        LSMGCHK(check_factor(H));
+    if (N == 0) {
+        if (factor_first) {
+            launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, s);
+            LSMGCHK(check_factor(H));
+        }
+        return LSMG_OK;
     }
-    if (N == 0) return LSMG_OK;
     if (H->km < m) {
         // buffers for a larger m replace the earlier ones, which are kept until the
         // hierarchy is destroyed
@@ -1222,6 +1224,26 @@ lsmg_status krylov_solve(lsmg_hierarchy *H, int *cycles, double *rho_last, doubl
     double beta = std::sqrt(hres[0]);
     const double *r = Fv;   // the defect of x = 0
     int used = 0;
+    // the coarsest factorisation runs on a side stream beside the first cycle's fine
+    // levels, which joins it before its coarse tail; its status is read with the first
+    // inner products (or at once, when no cycle runs)
+    bool factor_pending = false;
+    if (factor_first) {
+        if (beta > target && H->p.cycles_max > 0 && H->prof_kernel < 0) {
+            if (!H->side) HIPCHK(hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking));
+            if (!H->ev_fork) HIPCHK(hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+            if (!H->ev_join) HIPCHK(hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(H->ev_fork, s));
+            HIPCHK(hipStreamWaitEvent(H->side, H->ev_fork, 0));
+            launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, Exec(H->side));
+            HIPCHK(hipEventRecord(H->ev_join, H->side));
+            H->join_pending = true;
+            factor_pending = true;
+        } else {
+            launch_coarse_factor(H->dim, H->d64, H->d_coarse, 1, H->L[H->nlev - 1].na, s);
+            LSMGCHK(check_factor(H));
+        }
+    }
     while (beta > target && used < H->p.cycles_max) {
         launch_kv_div(vec(V, 0), r, N, beta, s);
         std::fill(Hh.begin(), Hh.end(), 0.0);
@@ -1242,6 +1264,11 @@ lsmg_status krylov_solve(lsmg_hierarchy *H, int *cycles, double *rho_last, doubl
                 vcycle_rec<double>(H, 0, s);
             }
             ++used;
+            if (H->join_pending) {
+                // (a cycle that did not reach the coarse tail) the factorisation joins here
+                HIPCHK(hipStreamWaitEvent(s, H->ev_join, 0));
+                H->join_pending = false;
+            }
             gather<double>(H, 0, L0.x_s, L0.x_c, vec(Z, j));
             // J Z_j (the operator reads the level-0 correction, which holds Z_j)
             launch_apply_J<double>(H->dim, H->d64, L0.w_act(), L0.nw_act(), Exec(s));
@@ -1252,7 +1279,13 @@ lsmg_status krylov_solve(lsmg_hierarchy *H, int *cycles, double *rho_last, doubl
             launch_kv_dots(w, V, N, j + 1, H->kpart, H->kres + (m + 1), s);
             launch_kv_update(w, V, N, j + 1, H->kres + (m + 1), -1.0, s);
             launch_kv_dots(w, w, N, 1, H->kpart, H->kres + 2 * (m + 1), s);
+            if (factor_pending)
+                HIPCHK(hipMemcpyAsync(H->h_status, H->lu_status, sizeof(int), hipMemcpyDeviceToHost, s));
             LSMGCHK(read(2 * (m + 1) + 1));
+            if (factor_pending) {
+                factor_pending = false;
+                if (*H->h_status != 0) return fail(LSMG_ENONFINITE, "coarsest operator is singular or not finite");
+            }
             if (H->prof_kernel >= 0) {
                 prof_collect(H, mark0, H->prof_used);
                 H->prof_used = mark0;
