@@ -1522,7 +1522,8 @@ static void precondition(or_hier *H, const double *v, double *z)
  * from x = 0, stops when that norm is at most rtol |F|_2 or after cycles_max
  * V-cycles, and restarts from its current x every m iterations.  x: N values
  * on exit; cycles, rho: V-cycles taken and the last ratio of consecutive
- * defect norms (the caller's statistics). */
+ * defect norms (the caller's statistics).  Pinned against a sparse direct
+ * solve of the assembled Jacobian, with and without restarts. */
 static void krylov_solve(or_hier *H, const double *F, double *x, int m, double rtol, int cycles_max,
                          int *cycles, double *rho_last, double *logsum, int *nrho, double *rho_hist,
                          int rho_cap)
