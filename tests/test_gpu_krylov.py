@@ -1,7 +1,8 @@
 """The Krylov option of the linear solves (krylov_m > 0: flexible GMRES preconditioned by
 one V-cycle) on the GPU against the oracle's, step by step: the same status and, when
 both converge, ||x_gpu - x_oracle||_inf / ||x_oracle||_inf <= 1e-10 for s and for c,
-in FP64 and in mixed precision, in 2-D and 3-D, with restarts, and on a creased union
+in FP64 and in mixed precision, in 2-D and 3-D, with restarts, under the paper's
+W-cycle, with Neumann rows, and on a creased union
 of ellipsoids where plain cycles need ten times as many cycles.  Batches refuse
 members with the option."""
 import numpy as np
@@ -39,13 +40,15 @@ def _steps(H, O, n, dim, dt, steps, label):
     return counts
 
 
-@pytest.mark.parametrize("kind,n,coarsest,precision,m", [
-    ("disk", 65, 5, 0, 30), ("star", 129, 9, 1, 30), ("star", 129, 9, 0, 3), ("torus", 33, 9, 0, 20),
-    ("torus", 65, 9, 1, 4)])
-def test_krylov_steps_match_oracle(kind, n, coarsest, precision, m):
-    label = f"krylov m={m} {kind} {n} precision {precision}"
+@pytest.mark.parametrize("kind,n,coarsest,precision,m,extra", [
+    ("disk", 65, 5, 0, 30, {}), ("star", 129, 9, 1, 30, {}), ("star", 129, 9, 0, 3, {}), ("torus", 33, 9, 0, 20, {}),
+    ("torus", 65, 9, 1, 4, {}), ("star", 65, 9, 1, 10, dict(cycle_gamma=2)), ("disk", 65, 5, 0, 20, dict(bc=1)),
+    ("torus", 33, 9, 1, 20, dict(bc=1))])
+def test_krylov_steps_match_oracle(kind, n, coarsest, precision, m, extra):
+    # also with the paper's W-cycle as the preconditioner, and with Neumann rows
+    label = f"krylov m={m} {kind} {n} precision {precision} {extra}"
     say(label)
-    H, O = pair(kind, n, coarsest, precision=precision, krylov_m=m)
+    H, O = pair(kind, n, coarsest, precision=precision, krylov_m=m, **extra)
     _steps(H, O, n, 2 if kind != "torus" else 3, 1e-4, 3, label)
 
 
